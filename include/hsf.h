@@ -1,0 +1,225 @@
+/*
+ * hsf.h -- C ABI of libhsf, joint-cut hybrid Schroedinger-Feynman (HSF)
+ * simulation on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Joint Cutting for Hybrid Schroedinger-Feynman Simulation of Quantum
+ * Circuits, arXiv:2502.06959):
+ *   - the qubits are split at a cut between qubit l and l+1: side b holds
+ *     qubits 0..l, side a holds l+1..n-1 (Sec. IV-A);
+ *   - gates that cross the cut are grouped by the caller into blocks, and
+ *     every block is multiplied into one operator and split by an
+ *     operator-Schmidt decomposition A = sum_m s_m X_m (x) Y_m (Sec. II-B,
+ *     Sec. III-A, Sec. IV-A);
+ *   - a path picks one term per block; there are prod_k r_k paths (Sec. III);
+ *   - per path the two half-register states are simulated independently and
+ *     the output is the sum over paths of their Kronecker products (Sec. II-B).
+ *
+ * Index conventions (Sec. II-A): amplitude index i = sum_q i_q 2^q.  A gate's
+ * matrix is written with its first qubit q[0] as the most significant bit.
+ * Half-state index of side a: i_a = i >> n_b; of side b: i_b = i & (2^n_b - 1),
+ * so psi[i_a * 2^n_b + i_b] = sum_p psiA[p][i_a] * psiB[p][i_b], i.e. the
+ * row-major matrix C = PsiA^T PsiB is the state.
+ *
+ * Ownership: a plan owns its host tables and the small device buffers it
+ * uploads (gate matrices, Schmidt factors, pass programs; uploaded on first
+ * use on each device).  The caller owns every large buffer: half-states,
+ * outputs, bitstrings, gradients and workspaces, all device pointers.
+ *
+ * Errors: every call returns a status; on a non-OK status nothing was
+ * launched, the outputs are untouched, and hsf_last_error() returns a
+ * thread-local message.  Launch failures map to HSF_E_DEVICE; faults inside
+ * a kernel surface when the caller synchronises the stream.  No C++
+ * exception crosses this interface.  All work is enqueued on the caller's
+ * stream; no call synchronises it except where stated.
+ */
+#ifndef HSF_H
+#define HSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hsf_stream_t; /* a hipStream_t; NULL = default stream */
+typedef struct hsf_plan_s* hsf_plan_t;
+
+typedef enum {
+    HSF_OK = 0,
+    HSF_E_ARG = 1,              /* bad argument (null pointer, range, size)          */
+    HSF_E_CUT = 2,              /* cut outside 0..n-2                                */
+    HSF_E_BLOCK_UNCOVERED = 3,  /* a crossing gate lies in no block                  */
+    HSF_E_BLOCK_OVERLAP = 4,    /* two block hulls share a gate                      */
+    HSF_E_BLOCK_CYCLE = 5,      /* contracted circuit has a cycle                    */
+    HSF_E_BLOCK_TOO_LARGE = 6,  /* block hull wider than max_side_qubits on a side   */
+    HSF_E_RANK_AMBIGUOUS = 7,   /* a singular-value ratio lies in (1e-13, 1e-7]      */
+    HSF_E_PATHS_OVERFLOW = 8,   /* more than 2^62 paths                              */
+    HSF_E_DEVICE = 9,           /* HIP error (allocation, launch, copy)              */
+    HSF_E_UNSUPPORTED = 10      /* valid request this build does not implement       */
+} hsf_status;
+
+typedef enum {
+    HSF_GATE_U = 0,   /* explicit 2^nq x 2^nq matrix (nq = 1..3)                     */
+    HSF_GATE_H, HSF_GATE_X, HSF_GATE_Y, HSF_GATE_Z, HSF_GATE_S, HSF_GATE_SDG,
+    HSF_GATE_T, HSF_GATE_TDG,
+    HSF_GATE_RX,      /* exp(-i t X / 2)                                             */
+    HSF_GATE_RY,      /* exp(-i t Y / 2)                                             */
+    HSF_GATE_RZ,      /* exp(-i t Z / 2)                                             */
+    HSF_GATE_PHASE,   /* diag(1, e^{it})                                             */
+    HSF_GATE_CX,      /* q[0] control, q[1] target                                   */
+    HSF_GATE_CZ,
+    HSF_GATE_CP,      /* diag(1, 1, 1, e^{it})                                       */
+    HSF_GATE_RZZ,     /* exp(-i t Z(x)Z / 2)                                         */
+    HSF_GATE_SWAP,
+    HSF_GATE_ISWAP
+} hsf_gate_kind;
+
+typedef enum { HSF_C64 = 0, HSF_C128 = 1 } hsf_dtype;
+
+/* Path-sum arithmetic for hsf_amplitudes_full / _bitstrings.                  */
+typedef enum {
+    HSF_SUM_F32 = 0,     /* c64 in, FP32 MFMA with FP32 accumulation, c64 out      */
+    HSF_SUM_BF16X3 = 1,  /* c64 in, split-BF16 x3 MFMA, FP32 accumulation, c64 out */
+    HSF_SUM_F64 = 2,     /* c64 or c128 in, FP64 MFMA, c128 out (reference mode)   */
+    HSF_SUM_C128 = 3     /* alias of HSF_SUM_F64 for c128 plans                    */
+} hsf_sum_mode;
+
+typedef struct {
+    int32_t kind;            /* hsf_gate_kind                                      */
+    int32_t nq;              /* number of qubits (1..3)                            */
+    int32_t q[4];            /* qubits; q[0] is the matrix's most significant bit  */
+    double param;            /* angle for RX/RY/RZ/PHASE/CP/RZZ                    */
+    int32_t param_id;        /* gradient slot of `param`, -1 if none               */
+    int32_t reserved;
+    const double* matrix;    /* HSF_GATE_U: 2^nq x 2^nq row-major complex128,
+                                interleaved (re, im); copied by hsf_plan          */
+} hsf_gate;
+
+typedef struct {
+    int32_t n_qubits;        /* 2..62                                              */
+    int32_t reserved;
+    int64_t n_gates;
+    const hsf_gate* gates;   /* host array, list order = circuit order             */
+} hsf_circuit;
+
+typedef struct {
+    double rank_tol;         /* s_m counted if s_m > rank_tol * s_0 (default 1e-10) */
+    int32_t max_side_qubits; /* hull qubits allowed per side (default 4, max 4)      */
+    int32_t dtype;           /* hsf_dtype of the half-states (default HSF_C64)      */
+    int32_t tile_qubits;     /* qubits per LDS tile (0 = largest that fits)         */
+    int32_t fuse;            /* 1 = fuse gates on the host (default), 0 = off       */
+} hsf_plan_options;
+
+/* ---------------------------------------------------------------- plan ---- */
+
+/* Build a plan (host only; no device call).  Sec. IV-A (partition, reshape,
+ * SVD), Sec. III-A (joint cutting of blocks), Sec. III (path count).
+ *   circuit         host circuit; copied.
+ *   cut             last qubit of side b (Table II's "cut pos."), 0..n-2.
+ *   block_gate_ids  gate ids of all blocks back to back; block k is
+ *   block_offsets   ids[offsets[k] .. offsets[k+1]), offsets has n_blocks+1
+ *                   entries.  Each block is closed to its hull (all gates
+ *                   between two of its gates along shared qubits).  Every
+ *                   crossing gate must be in some hull.
+ *   opts            NULL for defaults.
+ *   out             receives the plan; destroy with hsf_plan_destroy.
+ * Blocks are renumbered in the order of a topological sort of the circuit
+ * with blocks contracted (ready node with smallest gate id first), and path
+ * p has digit m_k = (p / R_k) mod r_k, R_k = prod_{k'>k} r_k'.            */
+hsf_status hsf_plan(const hsf_circuit* circuit, int32_t cut, const int64_t* block_gate_ids,
+                    const int64_t* block_offsets, int32_t n_blocks,
+                    const hsf_plan_options* opts, hsf_plan_t* out);
+void hsf_plan_destroy(hsf_plan_t plan);
+
+/* Dimensions: n, cut, n_a = n - cut - 1, n_b = cut + 1, K blocks, P paths.  */
+hsf_status hsf_plan_dims(hsf_plan_t plan, int32_t* n, int32_t* cut, int32_t* n_a,
+                         int32_t* n_b, int32_t* n_blocks, int64_t* n_paths);
+int64_t hsf_num_paths(hsf_plan_t plan);
+
+/* Block k (plan order): rank r_k, digit stride R_k, side-a and side-b
+ * supports (ascending qubits, at most 4 each), hull size and the caller's
+ * index of the block.                                                         */
+hsf_status hsf_block_info(hsf_plan_t plan, int32_t k, int32_t* rank, int64_t* stride,
+                          int32_t* n_sa, int32_t sa[4], int32_t* n_sb, int32_t sb[4],
+                          int64_t* hull_len, int32_t* caller_index);
+/* Hull gate ids of block k, ascending (hull_len entries).                    */
+hsf_status hsf_block_hull(hsf_plan_t plan, int32_t k, int64_t* ids);
+/* Schmidt data of block k (Sec. IV-A): all singular values (4^min(|sa|,|sb|)
+ * entries, descending) and the folded factors sqrt(s_m) X_m (side a) and
+ * sqrt(s_m) Y_m (side b), m < r_k, each row-major 2^|s| x 2^|s| complex128
+ * interleaved, ascending qubit = ascending significance.  Any pointer may be
+ * NULL.                                                                       */
+hsf_status hsf_block_factors(hsf_plan_t plan, int32_t k, double* sigma, double* xa, double* yb);
+/* Digits m_k(p) of path p (K entries).                                       */
+hsf_status hsf_path_digits(hsf_plan_t plan, int64_t p, int32_t* digits);
+/* Gate-program statistics of side 0 = a, 1 = b: ops before fusion, ops after
+ * fusion, LDS passes per path chunk, qubits per tile.                          */
+hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical,
+                          int64_t* ops_fused, int32_t* passes, int32_t* tile_qubits);
+
+/* --------------------------------------------------------------- paths ---- */
+
+/* Device workspace in bytes for `op` over `n_paths` paths:
+ *   op 0 = hsf_run_paths, 1 = hsf_amplitudes_full, 2 = hsf_backward.         */
+size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t mode);
+
+/* Per-path half-states for paths [p_begin, p_end) (Sec. II-B): row j of
+ * psiA (ld ldA elements) receives side a's state for path p_begin + j,
+ * 2^n_a amplitudes; psiB likewise with 2^n_b.  Either side may be NULL to
+ * skip it.  Element type is the plan's dtype (c64 = 2 x float, c128 =
+ * 2 x double).  Rows are overwritten; nothing is read.                      */
+hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* psiA,
+                         int64_t ldA, void* psiB, int64_t ldB, void* ws, size_t ws_bytes,
+                         hsf_stream_t stream);
+
+/* Path sum (Sec. II-B), output rows [row_begin, row_end) of C = PsiA^T PsiB:
+ * out[(r - row_begin) * ldo + c] = sum_{j < n_paths} psiA[j][r] psiB[j][c],
+ * c < 2^n_b.  Input type: the plan's dtype.  Output type: c64 for HSF_SUM_F32
+ * and HSF_SUM_BF16X3, c128 for HSF_SUM_F64 / HSF_SUM_C128.  accumulate = 1
+ * adds into `out` (path chunks, resume).  ws: hsf_workspace_size(plan, 1,
+ * n_paths, mode) bytes (only HSF_SUM_BF16X3 uses it).                        */
+hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA,
+                               const void* psiB, int64_t ldB, int64_t n_paths,
+                               int64_t row_begin, int64_t row_end, void* out, int64_t ldo,
+                               int32_t mode, int32_t accumulate, void* ws, size_t ws_bytes,
+                               hsf_stream_t stream);
+
+/* Amplitudes of chosen basis states (Sec. V computes a subset):
+ * out[j] = sum_{p < n_paths} psiA[p][x_j >> n_b] psiB[p][x_j & (2^n_b - 1)],
+ * accumulated in FP64; `out` is c128 (2 doubles per entry).  x: device
+ * array of n_x indices < 2^n.  accumulate = 1 adds into `out`.               */
+hsf_status hsf_amplitudes_bitstrings(hsf_plan_t plan, const void* psiA, int64_t ldA,
+                                     const void* psiB, int64_t ldB, int64_t n_paths,
+                                     const uint64_t* x, int64_t n_x, void* out,
+                                     int32_t accumulate, hsf_stream_t stream);
+
+/* ------------------------------------------------------------- checks ---- */
+
+/* FP64-accumulated sums over n complex entries of type dtype: out[0] =
+ * sum |a_i|^2 and, if b != NULL, out[1] = sum |a_i - b_i|^2 (b of the same
+ * type; b may be c64 or c128 per b_dtype).  out: 2 device doubles.
+ * Deterministic (fixed reduction order).  ws: at least 4096 doubles.          */
+hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dtype, int64_t n,
+                     double* out, void* ws, size_t ws_bytes, hsf_stream_t stream);
+
+/* ------------------------------------------------------------ gradient ---- */
+
+/* Gradient of L = sum_j |psi(x_j)|^2 over the n_x basis states x (device),
+ * with respect to every parameter id of the circuit's RX/RY/RZ/RZZ/PHASE/CP
+ * gates.  grad: device doubles, one per parameter id (0..max id), overwritten.
+ * Recomputes half-states per path chunk; ws: hsf_workspace_size(plan, 2,
+ * chunk, 0) bytes for a chunk of `chunk` paths.                               */
+hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* grad,
+                        int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes,
+                        hsf_stream_t stream);
+
+/* Thread-local message for the last non-OK status on this thread.            */
+const char* hsf_last_error(void);
+/* Library version string.                                                    */
+const char* hsf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSF_H */

@@ -1,0 +1,14 @@
+"""Joint-cut hybrid Schroedinger-Feynman simulation on AMD Instinct MI355X.
+
+The work happens in libhsf (HIP kernels for gfx950 plus a C++ planner behind
+the C ABI of include/hsf.h).  This package marshals arguments: circuits go in
+as host structs, device buffers are torch tensors, and the stream is torch's
+current stream.  Functions keep the C names (hsf_plan, hsf_run_paths, ...);
+`Plan` bundles them.
+"""
+from .hsf import (Plan, hsf_amplitudes_bitstrings, hsf_amplitudes_full, hsf_backward, hsf_norm2, hsf_plan,
+                  hsf_run_paths, hsf_workspace_size)
+from ._lib import HsfError
+
+__all__ = ["Plan", "HsfError", "hsf_plan", "hsf_run_paths", "hsf_amplitudes_full", "hsf_amplitudes_bitstrings",
+           "hsf_norm2", "hsf_backward", "hsf_workspace_size"]

@@ -1,0 +1,95 @@
+"""ctypes declarations of libhsf's C ABI (include/hsf.h).  Argument
+marshalling only: every step of the simulation runs inside the library."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsf.so")
+
+c_int32, c_int64, c_double, c_void_p, c_size_t = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                                   ctypes.c_void_p, ctypes.c_size_t)
+P = ctypes.POINTER
+
+STATUS = {0: "HSF_OK", 1: "HSF_E_ARG", 2: "HSF_E_CUT", 3: "HSF_E_BLOCK_UNCOVERED", 4: "HSF_E_BLOCK_OVERLAP",
+          5: "HSF_E_BLOCK_CYCLE", 6: "HSF_E_BLOCK_TOO_LARGE", 7: "HSF_E_RANK_AMBIGUOUS",
+          8: "HSF_E_PATHS_OVERFLOW", 9: "HSF_E_DEVICE", 10: "HSF_E_UNSUPPORTED"}
+
+GATE_KIND = {"U": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8, "RX": 9, "RY": 10,
+             "RZ": 11, "PHASE": 12, "CX": 13, "CZ": 14, "CP": 15, "RZZ": 16, "SWAP": 17, "ISWAP": 18}
+
+HSF_C64, HSF_C128 = 0, 1
+SUM_MODE = {"f32": 0, "bf16x3": 1, "f64": 2, "c128": 3}
+
+
+class HsfGate(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("nq", c_int32), ("q", c_int32 * 4), ("param", c_double),
+                ("param_id", c_int32), ("reserved", c_int32), ("matrix", c_void_p)]
+
+
+class HsfCircuit(ctypes.Structure):
+    _fields_ = [("n_qubits", c_int32), ("reserved", c_int32), ("n_gates", c_int64), ("gates", P(HsfGate))]
+
+
+class HsfPlanOptions(ctypes.Structure):
+    _fields_ = [("rank_tol", c_double), ("max_side_qubits", c_int32), ("dtype", c_int32),
+                ("tile_qubits", c_int32), ("fuse", c_int32)]
+
+
+class HsfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.code = STATUS.get(status, str(status))
+
+
+_lib = None
+
+SIGNATURES = {
+    "hsf_plan": (c_int32, [P(HsfCircuit), c_int32, P(c_int64), P(c_int64), c_int32, P(HsfPlanOptions),
+                           P(c_void_p)]),
+    "hsf_plan_destroy": (None, [c_void_p]),
+    "hsf_plan_dims": (c_int32, [c_void_p, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int32),
+                                P(c_int64)]),
+    "hsf_num_paths": (c_int64, [c_void_p]),
+    "hsf_block_info": (c_int32, [c_void_p, c_int32, P(c_int32), P(c_int64), P(c_int32), P(c_int32),
+                                 P(c_int32), P(c_int32), P(c_int64), P(c_int32)]),
+    "hsf_block_hull": (c_int32, [c_void_p, c_int32, P(c_int64)]),
+    "hsf_block_factors": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "hsf_path_digits": (c_int32, [c_void_p, c_int64, P(c_int32)]),
+    "hsf_side_stats": (c_int32, [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int32), P(c_int32)]),
+    "hsf_workspace_size": (c_size_t, [c_void_p, c_int32, c_int64, c_int32]),
+    "hsf_run_paths": (c_int32, [c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                c_size_t, c_void_p]),
+    "hsf_amplitudes_full": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64, c_int64,
+                                      c_void_p, c_int64, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
+    "hsf_amplitudes_bitstrings": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p,
+                                            c_int64, c_void_p, c_int32, c_void_p]),
+    "hsf_norm2": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_size_t,
+                            c_void_p]),
+    "hsf_backward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_size_t,
+                               c_void_p]),
+    "hsf_last_error": (ctypes.c_char_p, []),
+    "hsf_version": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded libhsf.  Raises if the library has not been built: there is
+    no fallback implementation."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_06959_amd.build` "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != 0:
+        raise HsfError(status, lib().hsf_last_error().decode())

@@ -1,0 +1,233 @@
+// extern "C" entry points of libhsf: argument checks, status codes and the
+// thread-local error message.  The work itself is in plan.cpp (host) and in
+// the HIP sources (device).
+#include <cstring>
+#include <string>
+
+#include "device.h"
+#include "internal.h"
+
+namespace hsf {
+
+thread_local std::string g_last_error;
+
+hsf_status fail(hsf_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+}  // namespace hsf
+
+using namespace hsf;
+
+#define HSF_GUARD_BEGIN try {
+#define HSF_GUARD_END                                                      \
+    }                                                                      \
+    catch (const std::bad_alloc&) {                                        \
+        return fail(HSF_E_ARG, "host allocation failed");                  \
+    }                                                                      \
+    catch (const std::exception& e) {                                      \
+        return fail(HSF_E_ARG, std::string("internal error: ") + e.what()); \
+    }
+
+extern "C" {
+
+const char* hsf_last_error(void) { return g_last_error.c_str(); }
+const char* hsf_version(void) { return "libhsf 0.1 (gfx950)"; }
+
+hsf_status hsf_plan(const hsf_circuit* circuit, int32_t cut, const int64_t* block_gate_ids,
+                    const int64_t* block_offsets, int32_t n_blocks, const hsf_plan_options* opts,
+                    hsf_plan_t* out) {
+    HSF_GUARD_BEGIN
+    if (!out) return fail(HSF_E_ARG, "null output pointer");
+    *out = nullptr;
+    Plan* p = nullptr;
+    hsf_status s = build_plan(circuit, cut, block_gate_ids, block_offsets, n_blocks, opts, &p);
+    if (s != HSF_OK) return s;
+    *out = reinterpret_cast<hsf_plan_t>(p);
+    return HSF_OK;
+    HSF_GUARD_END
+}
+
+void hsf_plan_destroy(hsf_plan_t plan) {
+    if (!plan) return;
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    release_device(*p);
+    delete p;
+}
+
+static Plan* P_(hsf_plan_t h) { return reinterpret_cast<Plan*>(h); }
+
+hsf_status hsf_plan_dims(hsf_plan_t plan, int32_t* n, int32_t* cut, int32_t* n_a, int32_t* n_b,
+                         int32_t* n_blocks, int64_t* n_paths) {
+    if (!plan) return fail(HSF_E_ARG, "null plan");
+    const Plan* p = P_(plan);
+    if (n) *n = p->n;
+    if (cut) *cut = p->cut;
+    if (n_a) *n_a = p->na;
+    if (n_b) *n_b = p->nb;
+    if (n_blocks) *n_blocks = (int32_t)p->blocks.size();
+    if (n_paths) *n_paths = p->P;
+    return HSF_OK;
+}
+
+int64_t hsf_num_paths(hsf_plan_t plan) { return plan ? P_(plan)->P : -1; }
+
+hsf_status hsf_block_info(hsf_plan_t plan, int32_t k, int32_t* rank, int64_t* stride, int32_t* n_sa,
+                          int32_t sa[4], int32_t* n_sb, int32_t sb[4], int64_t* hull_len,
+                          int32_t* caller_index) {
+    if (!plan) return fail(HSF_E_ARG, "null plan");
+    const Plan* p = P_(plan);
+    if (k < 0 || k >= (int32_t)p->blocks.size()) return fail(HSF_E_ARG, "block index out of range");
+    const Block& b = p->blocks[k];
+    if (rank) *rank = b.rank;
+    if (stride) *stride = b.stride;
+    if (n_sa) *n_sa = (int32_t)b.sa.size();
+    if (n_sb) *n_sb = (int32_t)b.sb.size();
+    if (sa)
+        for (size_t i = 0; i < b.sa.size(); ++i) sa[i] = b.sa[i];
+    if (sb)
+        for (size_t i = 0; i < b.sb.size(); ++i) sb[i] = b.sb[i];
+    if (hull_len) *hull_len = (int64_t)b.hull.size();
+    if (caller_index) *caller_index = b.caller_index;
+    return HSF_OK;
+}
+
+hsf_status hsf_block_hull(hsf_plan_t plan, int32_t k, int64_t* ids) {
+    if (!plan || !ids) return fail(HSF_E_ARG, "null argument");
+    const Plan* p = P_(plan);
+    if (k < 0 || k >= (int32_t)p->blocks.size()) return fail(HSF_E_ARG, "block index out of range");
+    std::memcpy(ids, p->blocks[k].hull.data(), p->blocks[k].hull.size() * sizeof(int64_t));
+    return HSF_OK;
+}
+
+hsf_status hsf_block_factors(hsf_plan_t plan, int32_t k, double* sigma, double* xa, double* yb) {
+    if (!plan) return fail(HSF_E_ARG, "null plan");
+    const Plan* p = P_(plan);
+    if (k < 0 || k >= (int32_t)p->blocks.size()) return fail(HSF_E_ARG, "block index out of range");
+    const Block& b = p->blocks[k];
+    if (sigma) std::memcpy(sigma, b.sigma.data(), b.sigma.size() * sizeof(double));
+    if (xa) std::memcpy(xa, b.xa.data(), b.xa.size() * sizeof(cd));
+    if (yb) std::memcpy(yb, b.yb.data(), b.yb.size() * sizeof(cd));
+    return HSF_OK;
+}
+
+hsf_status hsf_path_digits(hsf_plan_t plan, int64_t path, int32_t* digits) {
+    if (!plan || !digits) return fail(HSF_E_ARG, "null argument");
+    const Plan* p = P_(plan);
+    if (path < 0 || path >= p->P) return fail(HSF_E_ARG, "path index out of range");
+    for (size_t k = 0; k < p->blocks.size(); ++k)
+        digits[k] = (int32_t)((path / p->blocks[k].stride) % p->blocks[k].rank);
+    return HSF_OK;
+}
+
+hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical, int64_t* ops_fused,
+                          int32_t* passes, int32_t* tile_qubits) {
+    if (!plan) return fail(HSF_E_ARG, "null plan");
+    if (side != 0 && side != 1) return fail(HSF_E_ARG, "side must be 0 (a) or 1 (b)");
+    const SideProgram& s = P_(plan)->side[side];
+    if (ops_logical) *ops_logical = s.ops_logical;
+    if (ops_fused) *ops_fused = (int64_t)s.ops.size();
+    if (passes) *passes = (int32_t)s.passes.size();
+    if (tile_qubits) *tile_qubits = s.tile_bits;
+    return HSF_OK;
+}
+
+size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t mode) {
+    if (!plan || n_paths < 0) return 0;
+    const Plan* p = P_(plan);
+    if (op == 1 && mode == HSF_SUM_BF16X3) return bf16x3_workspace(p->na, p->nb, n_paths);
+    if (op == 2) return backward_workspace(*p, n_paths);
+    return 0;
+}
+
+hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* psiA, int64_t ldA,
+                         void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    if (!plan) return fail(HSF_E_ARG, "null plan");
+    Plan* p = P_(plan);
+    if (p_begin < 0 || p_end > p->P || p_begin > p_end) return fail(HSF_E_ARG, "path range outside [0, P)");
+    if (psiA && ldA < (int64_t(1) << p->na)) return fail(HSF_E_ARG, "ldA smaller than 2^n_a");
+    if (psiB && ldB < (int64_t(1) << p->nb)) return fail(HSF_E_ARG, "ldB smaller than 2^n_b");
+    if (p_begin == p_end) return HSF_OK;
+    DeviceCopy* d = nullptr;
+    hsf_status s = ensure_device(*p, &d);
+    if (s != HSF_OK) return s;
+    (void)ws;
+    (void)ws_bytes;
+    if (psiA) {
+        s = run_side(*p, *d, 0, p_begin, p_end - p_begin, psiA, ldA, (hipStream_t)stream);
+        if (s != HSF_OK) return s;
+    }
+    if (psiB) {
+        s = run_side(*p, *d, 1, p_begin, p_end - p_begin, psiB, ldB, (hipStream_t)stream);
+        if (s != HSF_OK) return s;
+    }
+    return HSF_OK;
+    HSF_GUARD_END
+}
+
+hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA, const void* psiB,
+                               int64_t ldB, int64_t n_paths, int64_t row_begin, int64_t row_end,
+                               void* out, int64_t ldo, int32_t mode, int32_t accumulate, void* ws,
+                               size_t ws_bytes, hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    if (!plan || !psiA || !psiB || !out) return fail(HSF_E_ARG, "null argument");
+    const Plan* p = P_(plan);
+    const int64_t M = int64_t(1) << p->na, N = int64_t(1) << p->nb;
+    if (n_paths < 0) return fail(HSF_E_ARG, "negative path count");
+    if (row_begin < 0 || row_end > M || row_begin > row_end) return fail(HSF_E_ARG, "row range outside [0, 2^n_a)");
+    if (ldA < M || ldB < N || ldo < N) return fail(HSF_E_ARG, "leading dimension too small");
+    if (mode < HSF_SUM_F32 || mode > HSF_SUM_C128) return fail(HSF_E_ARG, "unknown path-sum mode");
+    if (p->dtype == HSF_C128 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3))
+        return fail(HSF_E_ARG, "c128 half-states need HSF_SUM_F64 or HSF_SUM_C128");
+    if (mode == HSF_SUM_BF16X3 && ws_bytes < bf16x3_workspace(p->na, p->nb, n_paths))
+        return fail(HSF_E_ARG, "workspace too small for HSF_SUM_BF16X3");
+    if (row_begin == row_end) return HSF_OK;
+    return path_sum(p->dtype, mode, psiA, ldA, psiB, ldB, n_paths, row_begin, row_end - row_begin, N,
+                    out, ldo, accumulate, ws, (hipStream_t)stream);
+    HSF_GUARD_END
+}
+
+hsf_status hsf_amplitudes_bitstrings(hsf_plan_t plan, const void* psiA, int64_t ldA, const void* psiB,
+                                     int64_t ldB, int64_t n_paths, const uint64_t* x, int64_t n_x,
+                                     void* out, int32_t accumulate, hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    if (!plan || !psiA || !psiB || !out || (n_x > 0 && !x)) return fail(HSF_E_ARG, "null argument");
+    const Plan* p = P_(plan);
+    if (n_paths < 0 || n_x < 0) return fail(HSF_E_ARG, "negative size");
+    if (ldA < (int64_t(1) << p->na) || ldB < (int64_t(1) << p->nb)) return fail(HSF_E_ARG, "leading dimension too small");
+    if (n_x == 0) return HSF_OK;
+    return gather_dot(p->dtype, psiA, ldA, psiB, ldB, n_paths, p->nb, p->n, x, n_x, out, accumulate,
+                      (hipStream_t)stream);
+    HSF_GUARD_END
+}
+
+hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dtype, int64_t n, double* out,
+                     void* ws, size_t ws_bytes, hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    if (!a || !out || !ws) return fail(HSF_E_ARG, "null argument");
+    if ((a_dtype != HSF_C64 && a_dtype != HSF_C128) || (b && b_dtype != HSF_C64 && b_dtype != HSF_C128))
+        return fail(HSF_E_ARG, "dtype must be HSF_C64 or HSF_C128");
+    if (n < 0) return fail(HSF_E_ARG, "negative size");
+    if (ws_bytes < kNormWsDoubles * sizeof(double)) return fail(HSF_E_ARG, "workspace too small");
+    return norm2(a, a_dtype, b, b_dtype, n, out, (double*)ws, (hipStream_t)stream);
+    HSF_GUARD_END
+}
+
+hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* grad, int64_t n_params,
+                        int64_t chunk, void* ws, size_t ws_bytes, hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    if (!plan || !grad || (n_x > 0 && !x)) return fail(HSF_E_ARG, "null argument");
+    Plan* p = P_(plan);
+    if (n_params < p->n_params) return fail(HSF_E_ARG, "grad has fewer slots than the circuit's parameter ids");
+    if (chunk <= 0) return fail(HSF_E_ARG, "chunk must be positive");
+    if (ws_bytes < backward_workspace(*p, chunk)) return fail(HSF_E_ARG, "workspace too small");
+    DeviceCopy* d = nullptr;
+    hsf_status s = ensure_device(*p, &d);
+    if (s != HSF_OK) return s;
+    return backward(*p, *d, x, n_x, grad, n_params, chunk, ws, ws_bytes, (hipStream_t)stream);
+    HSF_GUARD_END
+}
+
+}  // extern "C"

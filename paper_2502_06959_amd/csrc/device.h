@@ -1,0 +1,39 @@
+// Device-side launchers of libhsf (implemented in the .hip sources).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace hsf {
+
+constexpr size_t kNormWsDoubles = 8192;
+
+// Runs one side's program for paths [p_begin, p_begin + n_paths) into psi.
+hsf_status run_side(Plan& p, DeviceCopy& d, int side, int64_t p_begin, int64_t n_paths, void* psi,
+                    int64_t ld, hipStream_t stream);
+
+size_t bf16x3_workspace(int na, int nb, int64_t n_paths);
+
+// out[r * ldo + c] (+)= sum_k A[k * ldA + row0 + r] * B[k * ldB + c], r < M, c < N.
+hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void* B, int64_t ldB,
+                    int64_t K, int64_t row0, int64_t M, int64_t N, void* out, int64_t ldo,
+                    int accumulate, void* ws, hipStream_t stream);
+
+hsf_status gather_dot(int dtype, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K,
+                      int nb, int n, const uint64_t* x, int64_t nx, void* out, int accumulate,
+                      hipStream_t stream);
+
+hsf_status norm2(const void* a, int adt, const void* b, int bdt, int64_t n, double* out, double* ws,
+                 hipStream_t stream);
+
+size_t backward_workspace(const Plan& p, int64_t chunk);
+hsf_status backward(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, double* grad,
+                    int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes, hipStream_t stream);
+
+inline hsf_status hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return HSF_OK;
+    return fail(HSF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace hsf

@@ -1,0 +1,128 @@
+// Internal data structures of libhsf (host side).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hsf.h"
+
+namespace hsf {
+
+using cd = std::complex<double>;
+
+constexpr int kMaxSideQubits = 4;     // widest block support per side
+constexpr int kMaxOpQubits = 4;       // widest dense op in a side program
+constexpr int kMaxTileBits = 24;
+
+hsf_status fail(hsf_status s, const std::string& msg);   // records the thread-local message
+
+struct Gate {
+    int kind = 0;
+    int nq = 0;
+    int q[4] = {0, 0, 0, 0};
+    double param = 0.0;
+    int param_id = -1;
+    std::vector<cd> m;     // 2^nq x 2^nq, row-major, q[0] most significant
+    bool diag = false;     // matrix is exactly diagonal
+};
+
+// Builds the matrix of a gate from its definition; false if the kind is unknown.
+bool gate_matrix(int kind, int nq, double param, const double* explicit_m, std::vector<cd>& out);
+
+// Singular value decomposition A = W diag(s) Vh of a row-major m x n complex
+// matrix by one-sided (Hestenes) Jacobi rotations in FP64.  W is m x r
+// (column-major: W[j * m + i]), Vh is r x n row-major, r = min(m, n), s is
+// descending.  Columns of W for zero singular values are left zero.
+void jacobi_svd(int m, int n, const std::vector<cd>& A, std::vector<cd>& W,
+                std::vector<double>& s, std::vector<cd>& Vh);
+
+struct Block {
+    int caller_index = 0;
+    std::vector<int64_t> hull;       // gate ids, ascending
+    std::vector<int> sa, sb;         // supports, ascending qubits
+    std::vector<double> sigma;       // all singular values, descending
+    int rank = 0;
+    int64_t stride = 1;              // R_k
+    std::vector<cd> xa;              // rank x (dA x dA), sqrt(s) folded
+    std::vector<cd> yb;              // rank x (dB x dB)
+};
+
+// One op of a side program on side-local qubits (q[0] = most significant
+// bit of the op's matrix index).
+struct SideOp {
+    enum Kind { DENSE = 0, DIAG = 1, SLOT = 2 };
+    int kind = DENSE;
+    int k = 0;
+    int q[kMaxOpQubits] = {0, 0, 0, 0};
+    std::vector<cd> m;       // DENSE: d x d; DIAG: d entries; SLOT: rank x d x d
+    int block = -1;          // SLOT: plan block index
+    int rank = 1;
+    int64_t stride = 1;
+    int64_t logical = 1;     // circuit gates represented by this op
+};
+
+// Device op (plain data, read by the sweep kernels).
+enum DevOpType : int32_t { DOP_DENSE1 = 0, DOP_DENSE2 = 1, DOP_DENSEK = 2, DOP_DIAG = 3, DOP_SLOT = 4 };
+struct DevOp {
+    int32_t type;
+    int32_t k;
+    int32_t bit[4];      // tile bit of q[i]; for DIAG a qubit outside the tile is -1 - q
+    int32_t mat;         // offset (complex elements) into the matrix pool
+    int32_t rank;        // SLOT: number of factor matrices
+    int64_t stride;      // SLOT: digit stride R_k
+};
+
+struct Pass {
+    int32_t n_local = 0;               // tile bits L
+    int32_t init_zero = 0;             // start from |0...0> instead of reading
+    int32_t op_begin = 0, op_end = 0;  // DevOp range
+    int32_t local_q[kMaxTileBits] = {};   // side-local qubit of tile bit i (ascending)
+    int32_t n_nonlocal = 0;
+    int32_t nonlocal_q[kMaxTileBits] = {};
+};
+
+struct SideProgram {
+    int nq = 0;
+    std::vector<SideOp> ops;          // after fusion
+    int64_t ops_logical = 0;
+    int tile_bits = 0;
+    std::vector<Pass> passes;
+    std::vector<DevOp> devops;
+    std::vector<cd> pool;             // matrices referenced by devops
+};
+
+struct DeviceCopy {
+    int device = -1;
+    void* ops[2] = {nullptr, nullptr};      // DevOp arrays per side
+    void* pool[2] = {nullptr, nullptr};     // float2 or double2 pools per side
+};
+
+struct Plan {
+    int n = 0, cut = 0, na = 0, nb = 0;
+    int dtype = HSF_C64;
+    double rank_tol = 1e-10;
+    int max_side = kMaxSideQubits;
+    int fuse = 1;
+    int tile_req = 0;
+    std::vector<Gate> gates;
+    std::vector<Block> blocks;
+    int64_t P = 1;
+    SideProgram side[2];              // 0 = side a (upper), 1 = side b (lower)
+    std::vector<DeviceCopy> dev;
+    int64_t n_params = 0;
+};
+
+hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, const int64_t* offs,
+                      int32_t n_blocks, const hsf_plan_options* opts, Plan** out);
+
+// Side-program construction and pass scheduling (plan.cpp).
+void schedule_side(Plan& p, int side, int tile_bits);
+
+// Device side (sweep.hip / pathsum.hip).
+hsf_status ensure_device(Plan& p, DeviceCopy** out);
+void release_device(Plan& p);
+int max_tile_bits(int dtype);
+
+}  // namespace hsf

@@ -1,0 +1,338 @@
+// Path sum (Sec. II-B: Kronecker products of the two half-states, summed over
+// paths).  With side a as rows and side b as columns the full state is the
+// complex product C = PsiA^T PsiB (PsiA is paths x 2^n_a, PsiB paths x 2^n_b),
+// so the sum is a dense contraction over the path index and runs on MFMA:
+// real and imaginary parts are separate MFMA operands, accumulated in FP32
+// (or FP64), and the epilogue writes interleaved complex output.  Also here:
+// amplitudes of chosen bitstrings and FP64-accumulated norms.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.h"
+
+namespace hsf {
+
+namespace {
+
+using f32x16 = float __attribute__((ext_vector_type(16)));
+using f64x4 = double __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- FP32 ----
+// Workgroup: 4 waves in a 2 x 2 grid, each wave 64 x 64 complex outputs made
+// of 2 x 2 blocks of the 32x32x2 FP32 MFMA; per block four products:
+// Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.  Operands stream straight from
+// global memory: for one path index the 32 lanes of a half-wave read 32
+// consecutive complex entries (256 contiguous bytes).
+constexpr int F32_TILE = 128;
+
+__global__ __launch_bounds__(256) void pathsum_f32(const float2* __restrict__ A, int64_t ldA,
+                                                   const float2* __restrict__ B, int64_t ldB, int64_t K,
+                                                   int64_t M, int64_t N, float2* __restrict__ out,
+                                                   int64_t ldo, int accumulate) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 31, lk = lane >> 5;
+    const int64_t m0 = (int64_t)blockIdx.y * F32_TILE + (w >> 1) * 64;
+    const int64_t n0 = (int64_t)blockIdx.x * F32_TILE + (w & 1) * 64;
+    f32x16 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cr[a][b] = (f32x16)0.0f;
+            ci[a][b] = (f32x16)0.0f;
+        }
+    bool mok[2], nok[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        mok[a] = m0 + a * 32 + li < M;
+        nok[a] = n0 + a * 32 + li < N;
+    }
+    auto load = [&](int64_t k, float2 (&av)[2], float2 (&bv)[2]) {
+        const bool kok = k < K;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            av[a] = (kok && mok[a]) ? A[k * ldA + m0 + a * 32 + li] : make_float2(0.f, 0.f);
+            bv[a] = (kok && nok[a]) ? B[k * ldB + n0 + a * 32 + li] : make_float2(0.f, 0.f);
+        }
+    };
+    float2 av[2], bv[2];
+    load(lk, av, bv);
+    for (int64_t k0 = 0; k0 < K; k0 += 2) {
+        float2 an[2], bn[2];
+        load(k0 + 2 + lk, an, bn);   // prefetch the next path pair
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                cr[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+                cr[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].y, -bv[b].y, cr[a][b], 0, 0, 0);
+                ci[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+                ci[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
+            }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            av[a] = an[a];
+            bv[a] = bn[a];
+        }
+    }
+    // accumulator r of a 32x32 block: row (r/4)*8 + (lane/32)*4 + r%4, column lane%32
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t col = n0 + b * 32 + li;
+            if (col >= N) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = m0 + a * 32 + (r >> 2) * 8 + lk * 4 + (r & 3);
+                if (row >= M) continue;
+                float2 v = make_float2(cr[a][b][r], ci[a][b][r]);
+                float2* o = out + row * ldo + col;
+                if (accumulate) {
+                    const float2 old = *o;
+                    v.x += old.x;
+                    v.y += old.y;
+                }
+                *o = v;
+            }
+        }
+}
+
+// ---------------------------------------------------------------- FP64 ----
+// Same structure on the 16x16x4 FP64 MFMA: wave 32 x 32 outputs (2 x 2
+// blocks), workgroup 64 x 64.  Inputs are c128, or c64 widened on load.
+constexpr int F64_TILE = 64;
+
+template <typename VIN>
+__device__ __forceinline__ double2 widen(VIN v) {
+    return make_double2((double)v.x, (double)v.y);
+}
+
+template <typename VIN>
+__global__ __launch_bounds__(256) void pathsum_f64(const VIN* __restrict__ A, int64_t ldA,
+                                                   const VIN* __restrict__ B, int64_t ldB, int64_t K,
+                                                   int64_t M, int64_t N, double2* __restrict__ out,
+                                                   int64_t ldo, int accumulate) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * F64_TILE + (w >> 1) * 32;
+    const int64_t n0 = (int64_t)blockIdx.x * F64_TILE + (w & 1) * 32;
+    f64x4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cr[a][b] = (f64x4)0.0;
+            ci[a][b] = (f64x4)0.0;
+        }
+    bool mok[2], nok[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        mok[a] = m0 + a * 16 + li < M;
+        nok[a] = n0 + a * 16 + li < N;
+    }
+    for (int64_t k0 = 0; k0 < K; k0 += 4) {
+        const int64_t k = k0 + lk;
+        const bool kok = k < K;
+        double2 av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            av[a] = (kok && mok[a]) ? widen(A[k * ldA + m0 + a * 16 + li]) : make_double2(0.0, 0.0);
+            bv[a] = (kok && nok[a]) ? widen(B[k * ldB + n0 + a * 16 + li]) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+                cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, -bv[b].y, cr[a][b], 0, 0, 0);
+                ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+                ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
+            }
+    }
+    // accumulator r of a 16x16 FP64 block: row lane/16 + 4*r, column lane%16
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t col = n0 + b * 16 + li;
+            if (col >= N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + a * 16 + lk + 4 * r;
+                if (row >= M) continue;
+                double2 v = make_double2(cr[a][b][r], ci[a][b][r]);
+                double2* o = out + row * ldo + col;
+                if (accumulate) {
+                    const double2 old = *o;
+                    v.x += old.x;
+                    v.y += old.y;
+                }
+                *o = v;
+            }
+        }
+}
+
+// ------------------------------------------------------------ gather-dot ----
+// One wave per requested basis state; lanes stride over paths, FP64
+// accumulation, fixed-order butterfly reduction (deterministic).
+template <typename VIN>
+__global__ __launch_bounds__(256) void gather_dot_kernel(const VIN* __restrict__ A, int64_t ldA,
+                                                         const VIN* __restrict__ B, int64_t ldB, int64_t K,
+                                                         int nb, int n, const uint64_t* __restrict__ x, int64_t nx,
+                                                         double2* __restrict__ out, int accumulate) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (j >= nx) return;
+    // index bits at or above n are ignored, so every read stays inside the half-states
+    const uint64_t xj = x[j] & ((n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1));
+    const int64_t ia = (int64_t)(xj >> nb);
+    const int64_t ib = (int64_t)(xj & ((uint64_t(1) << nb) - 1));
+    double re = 0.0, im = 0.0;
+    for (int64_t p = lane; p < K; p += 64) {
+        const double2 a = widen(A[p * ldA + ia]);
+        const double2 b = widen(B[p * ldB + ib]);
+        re += a.x * b.x - a.y * b.y;
+        im += a.x * b.y + a.y * b.x;
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        re += __shfl_xor(re, s, 64);
+        im += __shfl_xor(im, s, 64);
+    }
+    if (lane == 0) {
+        if (accumulate) {
+            re += out[j].x;
+            im += out[j].y;
+        }
+        out[j] = make_double2(re, im);
+    }
+}
+
+// ------------------------------------------------------------------ norms ----
+constexpr int NORM_BLOCKS = 4096;
+
+template <typename VA, typename VB, bool HAS_B>
+__global__ __launch_bounds__(256) void norm_partial(const VA* __restrict__ a, const VB* __restrict__ b, int64_t n,
+                                                    double* __restrict__ part) {
+    double s1 = 0.0, s2 = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double2 av = widen(a[i]);
+        s1 += av.x * av.x + av.y * av.y;
+        if constexpr (HAS_B) {
+            const double2 bv = widen(b[i]);
+            const double dx = av.x - bv.x, dy = av.y - bv.y;
+            s2 += dx * dx + dy * dy;
+        }
+    }
+    __shared__ double r1[256], r2[256];
+    r1[threadIdx.x] = s1;
+    r2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = r1[0];
+        part[2 * blockIdx.x + 1] = r2[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void norm_final(const double* __restrict__ part, int nblocks, double* __restrict__ out) {
+    __shared__ double r1[256], r2[256];
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += 256) {
+        s1 += part[2 * i];
+        s2 += part[2 * i + 1];
+    }
+    r1[threadIdx.x] = s1;
+    r2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = r1[0];
+        out[1] = r2[0];
+    }
+}
+
+template <typename VA, typename VB, bool HAS_B>
+hsf_status launch_norm(const void* a, const void* b, int64_t n, double* out, double* ws, hipStream_t st) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(NORM_BLOCKS, (n + 1023) / 1024));
+    hipLaunchKernelGGL((norm_partial<VA, VB, HAS_B>), dim3(blocks), dim3(256), 0, st, (const VA*)a,
+                       (const VB*)b, n, ws);
+    hipLaunchKernelGGL(norm_final, dim3(1), dim3(256), 0, st, (const double*)ws, blocks, out);
+    return hip_check(hipGetLastError(), "norm launch");
+}
+
+}  // namespace
+
+size_t bf16x3_workspace(int na, int nb, int64_t n_paths) {
+    // hi and lo BF16 planes of the real and imaginary parts of both operands
+    return (size_t)n_paths * ((size_t(1) << na) + (size_t(1) << nb)) * 4 * sizeof(uint16_t) + 256;
+}
+
+hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
+                           int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st);
+
+hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K,
+                    int64_t row0, int64_t M, int64_t N, void* out, int64_t ldo, int accumulate, void* ws,
+                    hipStream_t st) {
+    if (dtype == HSF_C64 && mode == HSF_SUM_F32) {
+        const dim3 grid((uint32_t)((N + F32_TILE - 1) / F32_TILE), (uint32_t)((M + F32_TILE - 1) / F32_TILE));
+        if (grid.y > 65535u) return fail(HSF_E_ARG, "too many output rows in one call (split the row range)");
+        hipLaunchKernelGGL(pathsum_f32, grid, dim3(256), 0, st, (const float2*)A + row0, ldA, (const float2*)B, ldB, K,
+                           M, N, (float2*)out, ldo, accumulate);
+        return hip_check(hipGetLastError(), "pathsum_f32 launch");
+    }
+    if (dtype == HSF_C64 && mode == HSF_SUM_BF16X3)
+        return path_sum_bf16x3((const float2*)A + row0, ldA, (const float2*)B, ldB, K, M, N, (float2*)out, ldo,
+                               accumulate, ws, st);
+    const dim3 grid((uint32_t)((N + F64_TILE - 1) / F64_TILE), (uint32_t)((M + F64_TILE - 1) / F64_TILE));
+    if (grid.y > 65535u) return fail(HSF_E_ARG, "too many output rows in one call (split the row range)");
+    if (dtype == HSF_C64)
+        hipLaunchKernelGGL(pathsum_f64<float2>, grid, dim3(256), 0, st, (const float2*)A + row0, ldA, (const float2*)B,
+                           ldB, K, M, N, (double2*)out, ldo, accumulate);
+    else
+        hipLaunchKernelGGL(pathsum_f64<double2>, grid, dim3(256), 0, st, (const double2*)A + row0, ldA,
+                           (const double2*)B, ldB, K, M, N, (double2*)out, ldo, accumulate);
+    return hip_check(hipGetLastError(), "pathsum_f64 launch");
+}
+
+hsf_status gather_dot(int dtype, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K, int nb, int n,
+                      const uint64_t* x, int64_t nx, void* out, int accumulate, hipStream_t st) {
+    const int waves = 4;
+    const dim3 grid((uint32_t)((nx + waves - 1) / waves));
+    if (dtype == HSF_C64)
+        hipLaunchKernelGGL(gather_dot_kernel<float2>, grid, dim3(64 * waves), 0, st, (const float2*)A, ldA,
+                           (const float2*)B, ldB, K, nb, n, x, nx, (double2*)out, accumulate);
+    else
+        hipLaunchKernelGGL(gather_dot_kernel<double2>, grid, dim3(64 * waves), 0, st, (const double2*)A, ldA,
+                           (const double2*)B, ldB, K, nb, n, x, nx, (double2*)out, accumulate);
+    return hip_check(hipGetLastError(), "gather_dot launch");
+}
+
+hsf_status norm2(const void* a, int adt, const void* b, int bdt, int64_t n, double* out, double* ws,
+                 hipStream_t st) {
+    if (!b) {
+        return adt == HSF_C64 ? launch_norm<float2, float2, false>(a, b, n, out, ws, st)
+                              : launch_norm<double2, double2, false>(a, b, n, out, ws, st);
+    }
+    if (adt == HSF_C64 && bdt == HSF_C64) return launch_norm<float2, float2, true>(a, b, n, out, ws, st);
+    if (adt == HSF_C64 && bdt == HSF_C128) return launch_norm<float2, double2, true>(a, b, n, out, ws, st);
+    if (adt == HSF_C128 && bdt == HSF_C64) return launch_norm<double2, float2, true>(a, b, n, out, ws, st);
+    return launch_norm<double2, double2, true>(a, b, n, out, ws, st);
+}
+
+}  // namespace hsf

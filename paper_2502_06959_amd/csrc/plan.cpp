@@ -1,0 +1,518 @@
+// Host planner: partition, block hulls, block operators, operator-Schmidt
+// decomposition, path table, side programs and their LDS pass schedule.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <queue>
+#include <set>
+#include <utility>
+
+#include "internal.h"
+
+namespace hsf {
+
+namespace {
+
+bool matrix_is_diag(const std::vector<cd>& m, int d) {
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            if (i != j && m[(size_t)i * d + j] != cd(0)) return false;
+    return true;
+}
+
+// U <- G U, where G acts on local bits lb[0..k) (lb[0] most significant) of
+// an nl-qubit register and U is a row-major 2^nl x 2^nl matrix.
+void left_multiply(std::vector<cd>& U, int nl, const int* lb, int k, const std::vector<cd>& g) {
+    const int d = 1 << nl, dk = 1 << k;
+    int mask = 0;
+    for (int i = 0; i < k; ++i) mask |= 1 << lb[i];
+    std::vector<cd> v(dk);
+    std::vector<int> idx(dk);
+    for (int base = 0; base < d; ++base) {
+        if (base & mask) continue;
+        for (int j = 0; j < dk; ++j) {
+            int x = base;
+            for (int i = 0; i < k; ++i)
+                if ((j >> (k - 1 - i)) & 1) x |= 1 << lb[i];
+            idx[j] = x;
+        }
+        for (int c = 0; c < d; ++c) {
+            for (int j = 0; j < dk; ++j) v[j] = U[(size_t)idx[j] * d + c];
+            for (int r = 0; r < dk; ++r) {
+                cd acc = 0;
+                for (int j = 0; j < dk; ++j) acc += g[(size_t)r * dk + j] * v[j];
+                U[(size_t)idx[r] * d + c] = acc;
+            }
+        }
+    }
+}
+
+// Gates reachable from the seed set along shared-qubit succession, forward
+// (later gates) or backward (earlier gates).
+std::vector<char> closure(const std::vector<Gate>& gs, int n, const std::vector<char>& seed, bool fwd) {
+    std::vector<char> in = seed;
+    std::vector<char> last(n, 0);
+    const int64_t G = (int64_t)gs.size();
+    for (int64_t t = 0; t < G; ++t) {
+        const int64_t i = fwd ? t : G - 1 - t;
+        bool r = in[i];
+        for (int j = 0; j < gs[i].nq && !r; ++j) r = last[gs[i].q[j]];
+        in[i] = r;
+        for (int j = 0; j < gs[i].nq; ++j) last[gs[i].q[j]] = r;
+    }
+    return in;
+}
+
+}  // namespace
+
+hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, const int64_t* offs,
+                      int32_t n_blocks, const hsf_plan_options* opts, Plan** out) {
+    if (!c || !out) return fail(HSF_E_ARG, "null circuit or output pointer");
+    if (c->n_qubits < 2 || c->n_qubits > 62) return fail(HSF_E_ARG, "n_qubits must be in 2..62");
+    if (c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) return fail(HSF_E_ARG, "bad gate array");
+    if (n_blocks < 0 || (n_blocks > 0 && (!ids || !offs))) return fail(HSF_E_ARG, "bad block arrays");
+    const int n = c->n_qubits;
+    if (cut < 0 || cut > n - 2) return fail(HSF_E_CUT, "cut must lie in 0..n-2");
+
+    Plan* p = new Plan();
+    std::unique_ptr<Plan> guard(p);
+    p->n = n;
+    p->cut = cut;
+    p->nb = cut + 1;
+    p->na = n - cut - 1;
+    if (opts) {
+        if (opts->rank_tol > 0) p->rank_tol = opts->rank_tol;
+        if (opts->max_side_qubits > 0) p->max_side = std::min(opts->max_side_qubits, kMaxSideQubits);
+        if (opts->dtype != HSF_C64 && opts->dtype != HSF_C128) return fail(HSF_E_ARG, "dtype must be HSF_C64 or HSF_C128");
+        p->dtype = opts->dtype;
+        p->tile_req = opts->tile_qubits;
+        p->fuse = opts->fuse;
+    }
+    if (p->tile_req < 0 || p->tile_req > max_tile_bits(p->dtype))
+        return fail(HSF_E_ARG, "tile_qubits out of range");
+
+    // ---- ingest gates
+    const int64_t G = c->n_gates;
+    p->gates.resize(G);
+    for (int64_t i = 0; i < G; ++i) {
+        const hsf_gate& in = c->gates[i];
+        Gate& g = p->gates[i];
+        g.kind = in.kind;
+        g.nq = in.nq;
+        g.param = in.param;
+        g.param_id = in.param_id;
+        if (in.nq < 1 || in.nq > 3) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": nq must be 1..3");
+        for (int j = 0; j < in.nq; ++j) {
+            if (in.q[j] < 0 || in.q[j] >= n) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": qubit out of range");
+            for (int l = 0; l < j; ++l)
+                if (in.q[l] == in.q[j]) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": repeated qubit");
+            g.q[j] = in.q[j];
+        }
+        const int want = (in.kind >= HSF_GATE_H && in.kind <= HSF_GATE_PHASE) ? 1
+                         : (in.kind >= HSF_GATE_CX && in.kind <= HSF_GATE_ISWAP) ? 2 : 0;
+        if (in.kind != HSF_GATE_U && want != in.nq)
+            return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": kind does not match nq");
+        if (in.kind == HSF_GATE_U && !in.matrix) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": U needs a matrix");
+        if (!gate_matrix(in.kind, in.nq, in.param, in.matrix, g.m))
+            return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": unknown kind");
+        g.diag = matrix_is_diag(g.m, 1 << in.nq);
+        if (g.param_id >= 0) p->n_params = std::max<int64_t>(p->n_params, g.param_id + 1);
+    }
+
+    // ---- sides: 0 = a (all qubits > cut), 1 = b (all <= cut), 2 = crossing
+    std::vector<int> side(G);
+    for (int64_t i = 0; i < G; ++i) {
+        int lo = 0;
+        for (int j = 0; j < p->gates[i].nq; ++j) lo += p->gates[i].q[j] <= cut;
+        side[i] = lo == 0 ? 0 : (lo == p->gates[i].nq ? 1 : 2);
+    }
+
+    // ---- block hulls
+    std::vector<int> owner(G, -1);
+    std::vector<std::vector<int64_t>> hulls(n_blocks);
+    for (int b = 0; b < n_blocks; ++b) {
+        const int64_t b0 = offs[b], b1 = offs[b + 1];
+        if (b1 <= b0) return fail(HSF_E_ARG, "block " + std::to_string(b) + " is empty");
+        std::vector<char> seed(G, 0);
+        for (int64_t t = b0; t < b1; ++t) {
+            if (ids[t] < 0 || ids[t] >= G) return fail(HSF_E_ARG, "block " + std::to_string(b) + ": gate id out of range");
+            seed[ids[t]] = 1;
+        }
+        std::vector<char> dn = closure(p->gates, n, seed, true);
+        std::vector<char> up = closure(p->gates, n, seed, false);
+        for (int64_t i = 0; i < G; ++i)
+            if (dn[i] && up[i]) {
+                if (owner[i] >= 0) return fail(HSF_E_BLOCK_OVERLAP, "blocks " + std::to_string(owner[i]) + " and " + std::to_string(b) + " share gate " + std::to_string(i));
+                owner[i] = b;
+                hulls[b].push_back(i);
+            }
+    }
+    for (int64_t i = 0; i < G; ++i)
+        if (side[i] == 2 && owner[i] < 0) return fail(HSF_E_BLOCK_UNCOVERED, "crossing gate " + std::to_string(i) + " is in no block");
+
+    // ---- contracted DAG, Kahn's algorithm (smallest original gate id first)
+    const int64_t NN = G + n_blocks;
+    auto node_of = [&](int64_t i) -> int64_t { return owner[i] >= 0 ? G + owner[i] : i; };
+    std::vector<int64_t> key(NN, -1);
+    for (int64_t i = 0; i < G; ++i) {
+        const int64_t nd = node_of(i);
+        if (key[nd] < 0) key[nd] = i;
+    }
+    std::vector<std::vector<int64_t>> succ(NN);
+    std::vector<int64_t> indeg(NN, 0);
+    {
+        std::set<std::pair<int64_t, int64_t>> seen;
+        std::vector<int64_t> last(n, -1);
+        for (int64_t i = 0; i < G; ++i) {
+            const int64_t nd = node_of(i);
+            for (int j = 0; j < p->gates[i].nq; ++j) {
+                const int q = p->gates[i].q[j];
+                if (last[q] >= 0 && last[q] != nd && seen.insert({last[q], nd}).second) {
+                    succ[last[q]].push_back(nd);
+                    indeg[nd]++;
+                }
+                last[q] = nd;
+            }
+        }
+    }
+    std::priority_queue<std::pair<int64_t, int64_t>, std::vector<std::pair<int64_t, int64_t>>, std::greater<>> ready;
+    int64_t live = 0;
+    for (int64_t nd = 0; nd < NN; ++nd)
+        if (key[nd] >= 0) {
+            ++live;
+            if (indeg[nd] == 0) ready.push({key[nd], nd});
+        }
+    std::vector<int64_t> order;
+    while (!ready.empty()) {
+        const int64_t nd = ready.top().second;
+        ready.pop();
+        order.push_back(nd);
+        for (int64_t s : succ[nd])
+            if (--indeg[s] == 0) ready.push({key[s], s});
+    }
+    if ((int64_t)order.size() != live) return fail(HSF_E_BLOCK_CYCLE, "blocks form a cycle in the contracted circuit");
+
+    // ---- blocks in plan order: operator, Schmidt decomposition, rank
+    std::vector<int> plan_index(n_blocks, -1);
+    for (int64_t nd : order) {
+        if (nd < G) continue;
+        const int b = (int)(nd - G);
+        plan_index[b] = (int)p->blocks.size();
+        Block blk;
+        blk.caller_index = b;
+        blk.hull = hulls[b];
+        std::set<int> qs;
+        for (int64_t gi : blk.hull)
+            for (int j = 0; j < p->gates[gi].nq; ++j) qs.insert(p->gates[gi].q[j]);
+        for (int q : qs) (q > cut ? blk.sa : blk.sb).push_back(q);
+        if ((int)blk.sa.size() > p->max_side || (int)blk.sb.size() > p->max_side)
+            return fail(HSF_E_BLOCK_TOO_LARGE, "block " + std::to_string(b) + " support " + std::to_string(blk.sa.size()) + "|" + std::to_string(blk.sb.size()));
+        const int ka = (int)blk.sa.size(), kb = (int)blk.sb.size(), nl = ka + kb;
+        const int da = 1 << ka, db = 1 << kb, d = 1 << nl;
+        int local[64];
+        for (int i = 0; i < kb; ++i) local[blk.sb[i]] = i;
+        for (int i = 0; i < ka; ++i) local[blk.sa[i]] = kb + i;
+        std::vector<cd> U((size_t)d * d, cd(0));
+        for (int i = 0; i < d; ++i) U[(size_t)i * d + i] = 1.0;
+        for (int64_t gi : blk.hull) {
+            const Gate& g = p->gates[gi];
+            int lb[4];
+            for (int j = 0; j < g.nq; ++j) lb[j] = local[g.q[j]];
+            left_multiply(U, nl, lb, g.nq, g.m);
+        }
+        // reshape: rows (i_b, j_b), columns (i_a, j_a)
+        const int rows = db * db, cols = da * da;
+        std::vector<cd> At((size_t)rows * cols);
+        for (int ia = 0; ia < da; ++ia)
+            for (int ib = 0; ib < db; ++ib)
+                for (int ja = 0; ja < da; ++ja)
+                    for (int jb = 0; jb < db; ++jb)
+                        At[(size_t)(ib * db + jb) * cols + (ia * da + ja)] = U[(size_t)(ia * db + ib) * d + (ja * db + jb)];
+        std::vector<cd> W, Vh;
+        jacobi_svd(rows, cols, At, W, blk.sigma, Vh);
+        const double s0 = blk.sigma.empty() ? 0.0 : blk.sigma[0];
+        if (!(s0 > 0)) return fail(HSF_E_RANK_AMBIGUOUS, "block " + std::to_string(b) + " operator is zero");
+        int r = 0;
+        for (double sv : blk.sigma) {
+            const double rel = sv / s0;
+            if (rel > p->rank_tol * 1e-3 && rel <= p->rank_tol * 1e3)
+                return fail(HSF_E_RANK_AMBIGUOUS, "block " + std::to_string(b) + ": singular value ratio " + std::to_string(rel) + " near the rank tolerance");
+            if (rel > p->rank_tol) ++r;
+        }
+        blk.rank = r;
+        blk.xa.resize((size_t)r * da * da);
+        blk.yb.resize((size_t)r * db * db);
+        for (int m = 0; m < r; ++m) {
+            const double rt = std::sqrt(blk.sigma[m]);
+            for (int e = 0; e < da * da; ++e) blk.xa[(size_t)m * da * da + e] = rt * Vh[(size_t)m * cols + e];
+            for (int e = 0; e < db * db; ++e) blk.yb[(size_t)m * db * db + e] = rt * W[(size_t)m * rows + e];
+        }
+        // a side with no qubit in the block carries a scalar: fold it into the other side
+        if (ka == 0)
+            for (int m = 0; m < r; ++m)
+                for (int e = 0; e < db * db; ++e) blk.yb[(size_t)m * db * db + e] *= blk.xa[m];
+        if (kb == 0)
+            for (int m = 0; m < r; ++m)
+                for (int e = 0; e < da * da; ++e) blk.xa[(size_t)m * da * da + e] *= blk.yb[m];
+        p->blocks.push_back(std::move(blk));
+    }
+
+    // ---- path table
+    p->P = 1;
+    for (const Block& b : p->blocks) {
+        if (p->P > (int64_t(1) << 62) / b.rank) return fail(HSF_E_PATHS_OVERFLOW, "more than 2^62 paths");
+        p->P *= b.rank;
+    }
+    {
+        int64_t R = 1;
+        for (int k = (int)p->blocks.size() - 1; k >= 0; --k) {
+            p->blocks[k].stride = R;
+            R *= p->blocks[k].rank;
+        }
+    }
+
+    // ---- side programs (topological order projected to each side)
+    for (int s = 0; s < 2; ++s) {
+        p->side[s].nq = s == 0 ? p->na : p->nb;
+        p->side[s].ops.clear();
+    }
+    for (int64_t nd : order) {
+        if (nd < G) {
+            const Gate& g = p->gates[nd];
+            const int s = side[nd];
+            const int off = s == 0 ? p->nb : 0;
+            SideOp op;
+            op.kind = g.diag ? SideOp::DIAG : SideOp::DENSE;
+            op.k = g.nq;
+            for (int j = 0; j < g.nq; ++j) op.q[j] = g.q[j] - off;
+            const int dd = 1 << g.nq;
+            if (g.diag) {
+                op.m.resize(dd);
+                for (int i = 0; i < dd; ++i) op.m[i] = g.m[(size_t)i * dd + i];
+            } else {
+                op.m = g.m;
+            }
+            p->side[s].ops.push_back(std::move(op));
+        } else {
+            const int k = plan_index[nd - G];
+            const Block& b = p->blocks[k];
+            for (int s = 0; s < 2; ++s) {
+                const std::vector<int>& sup = s == 0 ? b.sa : b.sb;
+                if (sup.empty()) continue;
+                const int off = s == 0 ? p->nb : 0;
+                SideOp op;
+                op.kind = SideOp::SLOT;
+                op.k = (int)sup.size();
+                // factor index: ascending qubit = ascending significance => q[0] is the top qubit
+                for (int j = 0; j < op.k; ++j) op.q[j] = sup[op.k - 1 - j] - off;
+                op.m = s == 0 ? b.xa : b.yb;
+                op.block = k;
+                op.rank = b.rank;
+                op.stride = b.stride;
+                p->side[s].ops.push_back(std::move(op));
+            }
+        }
+    }
+    for (int s = 0; s < 2; ++s) {
+        p->side[s].ops_logical = (int64_t)p->side[s].ops.size();
+        int tb = p->tile_req > 0 ? p->tile_req : max_tile_bits(p->dtype);
+        schedule_side(*p, s, std::min(tb, std::max(p->side[s].nq, 1)));
+    }
+    *out = guard.release();
+    return HSF_OK;
+}
+
+// ---------------------------------------------------------------- fusion --
+
+namespace {
+
+std::vector<cd> mat_mul(const std::vector<cd>& a, const std::vector<cd>& b, int d) {
+    std::vector<cd> c((size_t)d * d, cd(0));
+    for (int i = 0; i < d; ++i)
+        for (int k = 0; k < d; ++k)
+            for (int j = 0; j < d; ++j) c[(size_t)i * d + j] += a[(size_t)i * d + k] * b[(size_t)k * d + j];
+    return c;
+}
+
+std::vector<cd> as_dense1(const SideOp& o) {
+    if (o.kind == SideOp::DENSE) return o.m;
+    return {o.m[0], 0, 0, o.m[1]};
+}
+
+// Merge runs of one-qubit ops on the same qubit (exact in real arithmetic),
+// then fold diagonal ops into the diagonal op placed before them when their
+// union stays within kMaxOpQubits qubits and nothing in between touches them.
+void fuse_ops(std::vector<SideOp>& ops, int nq) {
+    std::vector<SideOp> out;
+    std::vector<int> pend(nq, -1);  // index in `out` of a one-qubit op still open on q
+    for (SideOp& o : ops) {
+        if (o.kind != SideOp::SLOT && o.k == 1 && pend[o.q[0]] >= 0) {
+            SideOp& t = out[pend[o.q[0]]];
+            if (t.kind == SideOp::DIAG && o.kind == SideOp::DIAG) {
+                t.m[0] *= o.m[0];
+                t.m[1] *= o.m[1];
+            } else {
+                t.m = mat_mul(as_dense1(o), as_dense1(t), 2);
+                t.kind = SideOp::DENSE;
+            }
+            t.logical += o.logical;
+            continue;
+        }
+        for (int j = 0; j < o.k; ++j) pend[o.q[j]] = -1;
+        out.push_back(std::move(o));
+        if (out.back().kind != SideOp::SLOT && out.back().k == 1) pend[out.back().q[0]] = (int)out.size() - 1;
+    }
+    // diagonal folding
+    std::vector<SideOp> res;
+    std::vector<int> last_touch(nq, -1);   // index in res of the last op touching q
+    for (SideOp& o : out) {
+        if (o.kind == SideOp::DIAG) {
+            // candidate: the latest diag op in res that no later op blocks
+            int cand = -1;
+            for (int j = 0; j < o.k; ++j) cand = std::max(cand, last_touch[o.q[j]]);
+            // the op at cand must be diagonal; walk back over diag ops not touching o
+            int tgt = -1;
+            if (cand >= 0 && res[cand].kind == SideOp::DIAG) tgt = cand;
+            if (cand < 0 && !res.empty()) {
+                // nothing touches o's qubits yet: fold into the last diag op if any
+                for (int i = (int)res.size() - 1; i >= 0; --i)
+                    if (res[i].kind == SideOp::DIAG) { tgt = i; break; }
+            }
+            if (tgt >= 0) {
+                SideOp& t = res[tgt];
+                // every op after tgt must not touch o's qubits (then o can move up to tgt)
+                bool ok = true;
+                for (int j = 0; j < o.k && ok; ++j)
+                    if (last_touch[o.q[j]] > tgt) ok = false;
+                // union of qubits
+                int uq[8], nu = 0;
+                for (int j = 0; j < t.k; ++j) uq[nu++] = t.q[j];
+                for (int j = 0; j < o.k; ++j) {
+                    bool have = false;
+                    for (int l = 0; l < nu; ++l) have |= uq[l] == o.q[j];
+                    if (!have) uq[nu++] = o.q[j];
+                }
+                if (ok && nu <= kMaxOpQubits) {
+                    std::vector<cd> m(1u << nu);
+                    for (int e = 0; e < (1 << nu); ++e) {
+                        int et = 0, eo = 0;
+                        for (int j = 0; j < t.k; ++j) {
+                            int pos = 0;
+                            while (uq[pos] != t.q[j]) ++pos;
+                            et |= ((e >> (nu - 1 - pos)) & 1) << (t.k - 1 - j);
+                        }
+                        for (int j = 0; j < o.k; ++j) {
+                            int pos = 0;
+                            while (uq[pos] != o.q[j]) ++pos;
+                            eo |= ((e >> (nu - 1 - pos)) & 1) << (o.k - 1 - j);
+                        }
+                        m[e] = t.m[et] * o.m[eo];
+                    }
+                    t.k = nu;
+                    for (int j = 0; j < nu; ++j) t.q[j] = uq[j];
+                    t.m = std::move(m);
+                    t.logical += o.logical;
+                    for (int j = 0; j < nu; ++j) last_touch[uq[j]] = std::max(last_touch[uq[j]], tgt);
+                    continue;
+                }
+            }
+        }
+        res.push_back(std::move(o));
+        for (int j = 0; j < res.back().k; ++j) last_touch[res.back().q[j]] = (int)res.size() - 1;
+    }
+    ops.swap(res);
+}
+
+}  // namespace
+
+// ------------------------------------------------------- pass scheduling --
+
+void schedule_side(Plan& p, int s, int L) {
+    SideProgram& sp = p.side[s];
+    if (p.fuse) fuse_ops(sp.ops, std::max(sp.nq, 1));
+    sp.passes.clear();
+    sp.devops.clear();
+    sp.pool.clear();
+    const int nq = sp.nq;
+    // a multi-pass tile needs room for the widest op beside the coalesced low qubits
+    L = std::max(std::min(nq, 8), std::min(L, nq));
+    sp.tile_bits = L;
+    const int nops = (int)sp.ops.size();
+    std::vector<char> done(nops, 0);
+    int remaining = nops;
+    const int low = L >= nq ? L : std::max(0, std::min(5, L - kMaxOpQubits));
+    bool first = true;
+    while (first || remaining > 0) {
+        Pass ps;
+        ps.init_zero = first ? 1 : 0;
+        std::vector<char> local(nq, 0);
+        int nloc = 0;
+        for (int q = 0; q < low; ++q) local[q] = 1, ++nloc;
+        if (L >= nq) {
+            for (int q = 0; q < nq; ++q) local[q] = 1;
+            nloc = nq;
+        } else {
+            // choose the qubits of the earliest pending non-diagonal ops
+            for (int i = 0; i < nops && nloc < L; ++i) {
+                if (done[i]) continue;
+                const SideOp& o = sp.ops[i];
+                if (o.kind != SideOp::DIAG) {
+                    int need = 0;
+                    for (int j = 0; j < o.k; ++j) need += !local[o.q[j]];
+                    if (nloc + need <= L)
+                        for (int j = 0; j < o.k; ++j)
+                            if (!local[o.q[j]]) local[o.q[j]] = 1, ++nloc;
+                }
+            }
+            for (int q = nq - 1; q >= 0 && nloc < L; --q)
+                if (!local[q]) local[q] = 1, ++nloc;
+        }
+        int t = 0, u = 0;
+        for (int q = 0; q < nq; ++q) {
+            if (local[q]) ps.local_q[t++] = q;
+            else ps.nonlocal_q[u++] = q;
+        }
+        ps.n_local = t;
+        ps.n_nonlocal = u;
+        ps.op_begin = (int)sp.devops.size();
+        std::vector<char> blocked(nq, 0);
+        for (int i = 0; i < nops; ++i) {
+            if (done[i]) continue;
+            const SideOp& o = sp.ops[i];
+            bool blk = false, fits = true;
+            for (int j = 0; j < o.k; ++j) {
+                blk |= (bool)blocked[o.q[j]];
+                fits &= (bool)local[o.q[j]];
+            }
+            if (!blk && (fits || o.kind == SideOp::DIAG)) {
+                done[i] = 1;
+                --remaining;
+                DevOp d{};
+                d.k = o.k;
+                for (int j = 0; j < o.k; ++j) {
+                    int pos = -1;
+                    for (int l = 0; l < ps.n_local; ++l)
+                        if (ps.local_q[l] == o.q[j]) pos = l;
+                    d.bit[j] = pos >= 0 ? pos : -1 - o.q[j];
+                }
+                d.mat = (int32_t)sp.pool.size();
+                d.rank = o.rank;
+                d.stride = o.stride;
+                if (o.kind == SideOp::DIAG) d.type = DOP_DIAG;
+                else if (o.kind == SideOp::SLOT) d.type = DOP_SLOT;
+                else d.type = o.k == 1 ? DOP_DENSE1 : (o.k == 2 ? DOP_DENSE2 : DOP_DENSEK);
+                sp.pool.insert(sp.pool.end(), o.m.begin(), o.m.end());
+                sp.devops.push_back(d);
+            } else {
+                for (int j = 0; j < o.k; ++j) blocked[o.q[j]] = 1;
+            }
+        }
+        ps.op_end = (int)sp.devops.size();
+        sp.passes.push_back(ps);
+        first = false;
+        if (sp.passes.size() > (size_t)4 * nops + 8) break;  // cannot happen: every pass applies an op
+    }
+}
+
+}  // namespace hsf

@@ -1,0 +1,208 @@
+"""Python binding of libhsf with the C names.  Device buffers are torch
+tensors (complex64 / complex128 / uint64 / float64 on a HIP device); work is
+enqueued on torch's current stream of the tensors' device."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DT = {"c64": L.HSF_C64, "c128": L.HSF_C128}
+_TORCH_DT = {L.HSF_C64: torch.complex64, L.HSF_C128: torch.complex128}
+
+
+def _stream(t=None):
+    dev = t.device if t is not None else torch.device("cuda", torch.cuda.current_device())
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _gate_struct(g):
+    s = L.HsfGate()
+    s.kind = L.GATE_KIND[g["kind"]]
+    s.nq = len(g["q"])
+    for i, q in enumerate(g["q"]):
+        s.q[i] = int(q)
+    s.param = float(g["param"]) if g.get("param") is not None else 0.0
+    s.param_id = int(g.get("param_id", -1))
+    m = None
+    if g.get("matrix") is not None:
+        m = np.ascontiguousarray(np.asarray(g["matrix"], dtype=np.complex128))
+        s.matrix = m.ctypes.data
+    return s, m
+
+
+def hsf_plan(circuit, cut=None, blocks=None, dtype="c64", rank_tol=1e-10, max_side_qubits=4, tile_qubits=0,
+             fuse=True):
+    """Plan for `circuit` (a dict with n, gates[, cut, blocks]); returns the
+    opaque handle (int).  Raises HsfError with the library's status."""
+    lib = L.lib()
+    cut = circuit["cut"] if cut is None else cut
+    blocks = circuit.get("blocks", []) if blocks is None else blocks
+    gates = circuit["gates"]
+    arr = (L.HsfGate * max(1, len(gates)))()
+    keep = []
+    for i, g in enumerate(gates):
+        s, m = _gate_struct(g)
+        arr[i] = s
+        keep.append(m)
+    c = L.HsfCircuit(n_qubits=int(circuit["n"]), reserved=0, n_gates=len(gates),
+                     gates=ctypes.cast(arr, ctypes.POINTER(L.HsfGate)))
+    ids = np.array([int(i) for b in blocks for i in b] or [0], dtype=np.int64)
+    offs = np.zeros(len(blocks) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(b) for b in blocks]) if blocks else []
+    opts = L.HsfPlanOptions(rank_tol=rank_tol, max_side_qubits=max_side_qubits, dtype=_DT[dtype],
+                            tile_qubits=tile_qubits, fuse=1 if fuse else 0)
+    h = ctypes.c_void_p()
+    L.check(lib.hsf_plan(ctypes.byref(c), int(cut), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                         offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(blocks), ctypes.byref(opts),
+                         ctypes.byref(h)))
+    del keep
+    return h.value
+
+
+def hsf_workspace_size(plan, op, n_paths, mode=0):
+    return int(L.lib().hsf_workspace_size(ctypes.c_void_p(plan), op, n_paths, mode))
+
+
+def hsf_run_paths(plan, p_begin, p_end, psiA, psiB, ws=None):
+    """Half-states of paths [p_begin, p_end) into rows of psiA / psiB."""
+    ref = psiA if psiA is not None else psiB
+    L.check(L.lib().hsf_run_paths(ctypes.c_void_p(plan), p_begin, p_end, _ptr(psiA),
+                                  psiA.stride(0) if psiA is not None else 0, _ptr(psiB),
+                                  psiB.stride(0) if psiB is not None else 0, _ptr(ws),
+                                  ws.numel() * ws.element_size() if ws is not None else 0, _stream(ref)))
+
+
+def hsf_amplitudes_full(plan, psiA, psiB, n_paths, row_begin, row_end, out, mode="f32", accumulate=False,
+                        ws=None):
+    L.check(L.lib().hsf_amplitudes_full(ctypes.c_void_p(plan), _ptr(psiA), psiA.stride(0), _ptr(psiB),
+                                        psiB.stride(0), n_paths, row_begin, row_end, _ptr(out), out.stride(0),
+                                        L.SUM_MODE[mode], 1 if accumulate else 0, _ptr(ws),
+                                        ws.numel() * ws.element_size() if ws is not None else 0,
+                                        _stream(psiA)))
+
+
+def hsf_amplitudes_bitstrings(plan, psiA, psiB, n_paths, x, out, accumulate=False):
+    L.check(L.lib().hsf_amplitudes_bitstrings(ctypes.c_void_p(plan), _ptr(psiA), psiA.stride(0), _ptr(psiB),
+                                              psiB.stride(0), n_paths, _ptr(x), x.numel(), _ptr(out),
+                                              1 if accumulate else 0, _stream(psiA)))
+
+
+def hsf_norm2(a, b=None):
+    """(sum |a|^2, sum |a - b|^2) accumulated in FP64 on the device."""
+    dev = a.device
+    out = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = torch.empty(8192, dtype=torch.float64, device=dev)
+    adt = L.HSF_C128 if a.dtype == torch.complex128 else L.HSF_C64
+    bdt = (L.HSF_C128 if b.dtype == torch.complex128 else L.HSF_C64) if b is not None else 0
+    if b is not None and b.numel() != a.numel():
+        raise ValueError("a and b differ in size")
+    L.check(L.lib().hsf_norm2(_ptr(a), adt, _ptr(b), bdt, a.numel(), _ptr(out), _ptr(ws), 8192 * 8, _stream(a)))
+    return out
+
+
+def hsf_backward(plan, x, grad, chunk, ws):
+    L.check(L.lib().hsf_backward(ctypes.c_void_p(plan), _ptr(x), x.numel(), _ptr(grad), grad.numel(), chunk,
+                                 _ptr(ws), ws.numel() * ws.element_size(), _stream(grad)))
+
+
+class Plan:
+    """A planned circuit.  `circuit` is a dict with keys n, gates, cut and
+    blocks (the format of circuitgen); dtype "c64" or "c128"."""
+
+    def __init__(self, circuit, cut=None, blocks=None, dtype=None, **opts):
+        dtype = dtype or circuit.get("meta", {}).get("dtype", "c64")
+        self.dtype = dtype
+        self.handle = hsf_plan(circuit, cut, blocks, dtype=dtype, **opts)
+        n, c, na, nb, k = (ctypes.c_int32() for _ in range(5))
+        p = ctypes.c_int64()
+        L.check(L.lib().hsf_plan_dims(ctypes.c_void_p(self.handle), *(ctypes.byref(v) for v in (n, c, na, nb, k)),
+                                      ctypes.byref(p)))
+        self.n, self.cut, self.na, self.nb, self.K, self.P = n.value, c.value, na.value, nb.value, k.value, p.value
+        self.torch_dtype = _TORCH_DT[_DT[dtype]]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib().hsf_plan_destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- tables ----
+    def block_info(self, k):
+        r, na_, nb_, ci = (ctypes.c_int32() for _ in range(4))
+        st, hl = ctypes.c_int64(), ctypes.c_int64()
+        sa, sb = (ctypes.c_int32 * 4)(), (ctypes.c_int32 * 4)()
+        L.check(L.lib().hsf_block_info(ctypes.c_void_p(self.handle), k, ctypes.byref(r), ctypes.byref(st),
+                                       ctypes.byref(na_), sa, ctypes.byref(nb_), sb, ctypes.byref(hl),
+                                       ctypes.byref(ci)))
+        hull = np.zeros(max(1, hl.value), dtype=np.int64)
+        L.check(L.lib().hsf_block_hull(ctypes.c_void_p(self.handle), k,
+                                       hull.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return {"rank": r.value, "stride": st.value, "sa": list(sa[:na_.value]), "sb": list(sb[:nb_.value]),
+                "hull": [int(v) for v in hull[:hl.value]], "caller_index": ci.value}
+
+    def block_factors(self, k):
+        info = self.block_info(k)
+        ka, kb, r = len(info["sa"]), len(info["sb"]), info["rank"]
+        sig = np.zeros(4 ** min(ka, kb), dtype=np.float64)
+        xa = np.zeros((r, 2 ** ka, 2 ** ka), dtype=np.complex128)
+        yb = np.zeros((r, 2 ** kb, 2 ** kb), dtype=np.complex128)
+        L.check(L.lib().hsf_block_factors(ctypes.c_void_p(self.handle), k, sig.ctypes.data, xa.ctypes.data,
+                                          yb.ctypes.data))
+        return sig, xa, yb
+
+    def digits(self, p):
+        d = (ctypes.c_int32 * max(1, self.K))()
+        L.check(L.lib().hsf_path_digits(ctypes.c_void_p(self.handle), int(p), d))
+        return list(d[:self.K])
+
+    def side_stats(self, side):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        c, d = ctypes.c_int32(), ctypes.c_int32()
+        L.check(L.lib().hsf_side_stats(ctypes.c_void_p(self.handle), side, ctypes.byref(a), ctypes.byref(b),
+                                       ctypes.byref(c), ctypes.byref(d)))
+        return {"ops_logical": a.value, "ops_fused": b.value, "passes": c.value, "tile_qubits": d.value}
+
+    # ------------------------------------------------------------ device ----
+    def alloc_halves(self, n_paths, device="cuda"):
+        A = torch.empty((n_paths, 1 << self.na), dtype=self.torch_dtype, device=device)
+        B = torch.empty((n_paths, 1 << self.nb), dtype=self.torch_dtype, device=device)
+        return A, B
+
+    def run_paths(self, p_begin=0, p_end=None, psiA=None, psiB=None):
+        p_end = self.P if p_end is None else p_end
+        if psiA is None and psiB is None:
+            psiA, psiB = self.alloc_halves(p_end - p_begin)
+        hsf_run_paths(self.handle, p_begin, p_end, psiA, psiB)
+        return psiA, psiB
+
+    def amplitudes_full(self, psiA, psiB, n_paths=None, rows=None, mode=None, out=None, accumulate=False,
+                        ws=None):
+        n_paths = psiA.shape[0] if n_paths is None else n_paths
+        r0, r1 = (0, 1 << self.na) if rows is None else rows
+        mode = mode or ("c128" if self.dtype == "c128" else "f32")
+        odt = torch.complex64 if mode in ("f32", "bf16x3") else torch.complex128
+        if out is None:
+            out = torch.empty((r1 - r0, 1 << self.nb), dtype=odt, device=psiA.device)
+        if mode == "bf16x3" and ws is None:
+            nbytes = hsf_workspace_size(self.handle, 1, n_paths, L.SUM_MODE[mode])
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=psiA.device)
+        hsf_amplitudes_full(self.handle, psiA, psiB, n_paths, r0, r1, out, mode, accumulate, ws)
+        return out
+
+    def amplitudes_bitstrings(self, psiA, psiB, x, n_paths=None, out=None, accumulate=False):
+        n_paths = psiA.shape[0] if n_paths is None else n_paths
+        if out is None:
+            out = torch.zeros(x.numel(), dtype=torch.complex128, device=psiA.device)
+        hsf_amplitudes_bitstrings(self.handle, psiA, psiB, n_paths, x, out, accumulate)
+        return out

@@ -1,0 +1,141 @@
+"""Host-side tests of libhsf through its C ABI (no GPU needed): the library
+loads and exports every declared symbol, the planner's integer path table
+equals the oracle's independent planner bit for bit, its Schmidt factors
+reproduce the oracle's block operators, and every error status is reachable.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import circuitgen as cg
+from oracle import hsf as ohsf
+from paper_2502_06959_amd import HsfError, Plan
+from paper_2502_06959_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_header_symbol():
+    hdr = open(os.path.join(ROOT, "include", "hsf.h")).read()
+    names = set(re.findall(r"\b(hsf_[a-z0-9_]+)\s*\(", hdr))
+    assert len(names) >= 15
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing
+    assert set(L.SIGNATURES) == names
+    assert L.lib().hsf_version().decode().startswith("libhsf")
+
+
+def _workloads():
+    out = [cg.bell(), cg.ghz(9), cg.qft_basis(8, 77), cg.cnot_cascade(3), cg.c1(), cg.c1b(), cg.c2(), cg.c2p(),
+           cg.c3(), cg.c4(), cg.qaoa_sbm(3, sizes=(6, 7), p_intra=0.5, p_inter=0.3)]
+    for s in range(40, 46):
+        out.append(cg.random_circuit(s, n=9, n_gates=40, group=2, p2=0.4))
+    out += cg.c5(count=6)
+    return out
+
+
+@pytest.mark.parametrize("c", _workloads(), ids=lambda c: c["name"])
+def test_path_table_bit_exact(c):
+    o = ohsf.plan(c)
+    p = Plan(c)
+    assert (p.n, p.cut, p.na, p.nb, p.K, p.P) == (o["n"], o["cut"], o["na"], o["nb"], len(o["ranks"]), o["P"])
+    for k in range(p.K):
+        bi = p.block_info(k)
+        ob = o["blocks"][k]
+        assert bi["rank"] == ob["rank"]
+        assert bi["stride"] == o["strides"][k]
+        assert bi["hull"] == ob["hull"]
+        assert bi["sa"] == ob["sa"] and bi["sb"] == ob["sb"]
+        assert bi["caller_index"] == ob["caller_index"]
+    rng = np.random.default_rng(0)
+    ps = range(p.P) if p.P <= 4096 else rng.integers(0, p.P, 512)
+    for q in ps:
+        assert p.digits(int(q)) == ohsf.digits(o, int(q))
+
+
+@pytest.mark.parametrize("maker", [cg.c1, cg.c1b, cg.c2p, cg.c3, cg.c4, cg.cnot_cascade],
+                         ids=lambda f: f.__name__)
+def test_factors_reproduce_block_operator(maker):
+    c = maker()
+    o = ohsf.plan(c)
+    p = Plan(c)
+    for k in range(p.K):
+        sig, xa, yb = p.block_factors(k)
+        ob = o["blocks"][k]
+        assert np.allclose(sig, ob["sigma"], atol=1e-12)
+        recon = sum(np.kron(xa[m], yb[m]) for m in range(len(xa)))
+        assert np.max(np.abs(recon - ob["U"])) < 1e-12
+
+
+def test_singleton_blocks_standard_cutting():
+    c = cg.c1b()
+    cross = [i for i, g in enumerate(c["gates"]) if cg.crossing(g, c["cut"])]
+    p = Plan(c, blocks=[[i] for i in cross])
+    assert p.P == 2 ** len(cross)
+
+
+def _code(fn):
+    with pytest.raises(HsfError) as e:
+        fn()
+    return e.value.code
+
+
+def test_error_statuses():
+    c = cg.c1()
+    assert _code(lambda: Plan(c, blocks=c["blocks"][:-1])) == "HSF_E_BLOCK_UNCOVERED"
+    assert _code(lambda: Plan(c, blocks=c["blocks"] + [c["blocks"][0]])) == "HSF_E_BLOCK_OVERLAP"
+    assert _code(lambda: Plan(c, cut=11)) == "HSF_E_CUT"
+    assert _code(lambda: Plan(c, cut=-1)) == "HSF_E_CUT"
+    big = cg.c1b()
+    assert _code(lambda: Plan(big, blocks=[[i for b in big["blocks"] for i in b]])) == "HSF_E_BLOCK_TOO_LARGE"
+    gs = [cg.gate("CZ", (1, 2)), cg.gate("CZ", (0, 3)), cg.gate("CZ", (1, 3)), cg.gate("CZ", (2, 0))]
+    cyc = cg.circuit("cyc", 4, gs, 1, [[0, 2], [1, 3]])
+    assert _code(lambda: Plan(cyc)) == "HSF_E_BLOCK_CYCLE"
+    near = np.eye(4, dtype=complex)
+    near[3, 3] = 1 + 1e-9          # diag(1,1,1,1+1e-9): Schmidt ratio ~ 2.5e-10
+    amb = cg.circuit("amb", 2, [cg.gate("U", (1, 0), matrix=near)], 0, [[0]])
+    assert _code(lambda: Plan(amb)) == "HSF_E_RANK_AMBIGUOUS"
+    # 32 blocks of rank 4 -> 2^64 paths
+    rng = np.random.default_rng(1)
+    many = []
+    for _ in range(33):
+        many.append(cg.gate("U", (1, 0), matrix=cg.haar_unitary(rng, 4)))
+    ov = cg.circuit("ov", 2, many, 0, [[i] for i in range(33)])
+    assert _code(lambda: Plan(ov)) == "HSF_E_PATHS_OVERFLOW"
+    bad = cg.circuit("bad", 3, [cg.gate("CZ", (0, 1))], 0, [[5]])
+    assert _code(lambda: Plan(bad)) == "HSF_E_ARG"
+
+
+def test_ambiguous_matches_oracle_rule():
+    near = np.eye(4, dtype=complex)
+    near[3, 3] = 1 + 1e-9
+    amb = cg.circuit("amb", 2, [cg.gate("U", (1, 0), matrix=near)], 0, [[0]])
+    with pytest.raises(ohsf.PlanError) as e:
+        ohsf.plan(amb)
+    assert e.value.code == "RANK_AMBIGUOUS"
+
+
+def test_null_and_range_arguments():
+    lib = L.lib()
+    assert lib.hsf_run_paths(None, 0, 1, None, 0, None, 0, None, 0, None) == 1
+    assert lib.hsf_num_paths(None) == -1
+    p = Plan(cg.c1())
+    assert lib.hsf_run_paths(ctypes.c_void_p(p.handle), 0, p.P + 1, None, 0, None, 0, None, 0, None) == 1
+    assert "path range" in lib.hsf_last_error().decode()
+    d = (ctypes.c_int32 * 8)()
+    assert lib.hsf_path_digits(ctypes.c_void_p(p.handle), p.P, d) == 1
+    assert lib.hsf_workspace_size(ctypes.c_void_p(p.handle), 1, 16, 1) > 0
+
+
+def test_multi_pass_schedule_shapes():
+    c = cg.c2p()
+    for tq in (8, 10, 12, 14):
+        p = Plan(c, tile_qubits=tq)
+        for s in (0, 1):
+            st = p.side_stats(s)
+            assert st["tile_qubits"] == tq
+            assert (st["passes"] == 1) == (tq >= 14)
