@@ -1,6 +1,7 @@
 // extern "C" entry points of libhsf: argument checks, status codes and the
 // thread-local error message.  The work itself is in plan.cpp (host) and in
 // the HIP sources (device).
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -125,11 +126,13 @@ hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical, i
                           int32_t* passes, int32_t* tile_qubits) {
     if (!plan) return fail(HSF_E_ARG, "null plan");
     if (side != 0 && side != 1) return fail(HSF_E_ARG, "side must be 0 (a) or 1 (b)");
-    const SideProgram& s = P_(plan)->side[side];
+    const Plan* p = P_(plan);
+    const SideProgram& s = p->side[side];
+    const size_t i = std::min<size_t>((size_t)pick_schedule(*p, p->P), s.sched.size() - 1);
     if (ops_logical) *ops_logical = s.ops_logical;
     if (ops_fused) *ops_fused = (int64_t)s.ops.size();
-    if (passes) *passes = (int32_t)s.passes.size();
-    if (tile_qubits) *tile_qubits = s.tile_bits;
+    if (passes) *passes = (int32_t)s.sched[i].passes.size();
+    if (tile_qubits) *tile_qubits = s.sched[i].tile_bits;
     return HSF_OK;
 }
 
@@ -155,15 +158,7 @@ hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* 
     if (s != HSF_OK) return s;
     (void)ws;
     (void)ws_bytes;
-    if (psiA) {
-        s = run_side(*p, *d, 0, p_begin, p_end - p_begin, psiA, ldA, (hipStream_t)stream);
-        if (s != HSF_OK) return s;
-    }
-    if (psiB) {
-        s = run_side(*p, *d, 1, p_begin, p_end - p_begin, psiB, ldB, (hipStream_t)stream);
-        if (s != HSF_OK) return s;
-    }
-    return HSF_OK;
+    return run_sides(*p, *d, p_begin, p_end - p_begin, psiA, ldA, psiB, ldB, (hipStream_t)stream);
     HSF_GUARD_END
 }
 

@@ -9,9 +9,10 @@ namespace hsf {
 
 constexpr size_t kNormWsDoubles = 8192;
 
-// Runs one side's program for paths [p_begin, p_begin + n_paths) into psi.
-hsf_status run_side(Plan& p, DeviceCopy& d, int side, int64_t p_begin, int64_t n_paths, void* psi,
-                    int64_t ld, hipStream_t stream);
+// Runs both sides' programs (a side with a null pointer is skipped) for
+// paths [p_begin, p_begin + n_paths), one launch per LDS pass.
+hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
+                     void* psiB, int64_t ldB, hipStream_t stream);
 
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths);
 

@@ -64,14 +64,36 @@ struct SideOp {
 };
 
 // Device op (plain data, read by the sweep kernels).
-enum DevOpType : int32_t { DOP_DENSE1 = 0, DOP_DENSE2 = 1, DOP_DENSEK = 2, DOP_DIAG = 3, DOP_SLOT = 4 };
+//   DOP_GROUP: every thread holds the 2^k amplitudes that differ in tile bits
+//     bit[0..k) (register position g <-> tile bit bit[g]) and applies the
+//     sub-ops subs[mat .. mat + rank) to them in order.
+//   DOP_DENSEK / DOP_SLOT: a dense 2^k x 2^k matrix on tile bits bit[0..k)
+//     (bit[0] = most significant); SLOT picks matrix (path / stride) % rank.
+enum DevOpType : int32_t { DOP_GROUP = 0, DOP_DENSEK = 2, DOP_SLOT = 4 };
 struct DevOp {
     int32_t type;
     int32_t k;
-    int32_t bit[4];      // tile bit of q[i]; for DIAG a qubit outside the tile is -1 - q
-    int32_t mat;         // offset (complex elements) into the matrix pool
-    int32_t rank;        // SLOT: number of factor matrices
+    int32_t bit[4];
+    int32_t mat;         // DENSEK/SLOT: pool offset (complex); GROUP: first sub-op
+    int32_t rank;        // SLOT: factor count; GROUP: sub-op count
     int64_t stride;      // SLOT: digit stride R_k
+};
+
+// Sub-op of a group.  D1: 2x2 matrix m on register position g.  SIGN/PHASE:
+// a diagonal; its qubits outside the group (nc of them, tile bit qb[i] >= 0
+// or -1 - q for a qubit outside the tile) form the combo index
+// c = sum_i bit_i 2^i, uniform over a thread's group; SIGN negates register
+// element j when bit j of the 16-bit mask (mask[c / 2] >> 16 (c % 2)) is set,
+// PHASE multiplies element j by pool[mat + c 2^k + j].
+enum SubOpType : int32_t { SUB_D1 = 0, SUB_SIGN = 1, SUB_PHASE = 2 };
+struct SubOp {
+    int32_t type;
+    int32_t g;
+    int32_t nc;
+    int32_t mat;
+    int32_t qb[4];
+    uint32_t mask[8];
+    double m[8];
 };
 
 struct Pass {
@@ -83,20 +105,32 @@ struct Pass {
     int32_t nonlocal_q[kMaxTileBits] = {};
 };
 
+// LDS pass schedule of one side for one tile size.
+struct Schedule {
+    int tile_bits = 0;
+    std::vector<Pass> passes;
+    std::vector<DevOp> devops;
+    std::vector<SubOp> subs;
+    std::vector<cd> pool;             // matrices referenced by devops / subs
+};
+
 struct SideProgram {
     int nq = 0;
     std::vector<SideOp> ops;          // after fusion
     int64_t ops_logical = 0;
-    int tile_bits = 0;
-    std::vector<Pass> passes;
-    std::vector<DevOp> devops;
-    std::vector<cd> pool;             // matrices referenced by devops
+    std::vector<Schedule> sched;      // one per candidate tile size, largest first
+};
+
+struct DeviceSchedule {
+    void* passes = nullptr;           // Pass[]
+    void* ops = nullptr;              // DevOp[]
+    void* subs = nullptr;             // SubOp[]
+    void* pool = nullptr;             // float2[] or double2[]
 };
 
 struct DeviceCopy {
     int device = -1;
-    void* ops[2] = {nullptr, nullptr};      // DevOp arrays per side
-    void* pool[2] = {nullptr, nullptr};     // float2 or double2 pools per side
+    std::vector<DeviceSchedule> side[2];
 };
 
 struct Plan {
@@ -117,8 +151,11 @@ struct Plan {
 hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, const int64_t* offs,
                       int32_t n_blocks, const hsf_plan_options* opts, Plan** out);
 
-// Side-program construction and pass scheduling (plan.cpp).
-void schedule_side(Plan& p, int side, int tile_bits);
+// Side-program fusion and pass scheduling (plan.cpp).
+void fuse_side(Plan& p, int side);
+Schedule schedule_side(const Plan& p, int side, int tile_bits);
+// Index of the schedule used for a launch over n_paths paths.
+int pick_schedule(const Plan& p, int64_t n_paths);
 
 // Device side (sweep.hip / pathsum.hip).
 hsf_status ensure_device(Plan& p, DeviceCopy** out);

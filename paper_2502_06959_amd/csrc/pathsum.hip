@@ -279,8 +279,10 @@ hsf_status launch_norm(const void* a, const void* b, int64_t n, double* out, dou
 }  // namespace
 
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths) {
-    // hi and lo BF16 planes of the real and imaginary parts of both operands
-    return (size_t)n_paths * ((size_t(1) << na) + (size_t(1) << nb)) * 4 * sizeof(uint16_t) + 256;
+    // hi and lo BF16 planes of the real and imaginary parts of both operands,
+    // paths padded to a multiple of 16
+    const size_t kp = (size_t)std::max<int64_t>(16, (n_paths + 15) / 16 * 16);
+    return kp * ((size_t(1) << na) + (size_t(1) << nb)) * 4 * sizeof(uint16_t) + 256;
 }
 
 hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,

@@ -316,8 +316,13 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
     }
     for (int s = 0; s < 2; ++s) {
         p->side[s].ops_logical = (int64_t)p->side[s].ops.size();
-        int tb = p->tile_req > 0 ? p->tile_req : max_tile_bits(p->dtype);
-        schedule_side(*p, s, std::min(tb, std::max(p->side[s].nq, 1)));
+        fuse_side(*p, s);
+        const int nq = std::max(p->side[s].nq, 1);
+        const int tmax = p->tile_req > 0 ? p->tile_req : max_tile_bits(p->dtype);
+        // candidate tile sizes, largest first (a requested size is the only one)
+        const int top = std::min(tmax, nq);
+        const int bottom = p->tile_req > 0 ? top : std::max(std::min(nq, 8), top - 3);
+        for (int L = top; L >= bottom; --L) p->side[s].sched.push_back(schedule_side(*p, s, L));
     }
     *out = guard.release();
     return HSF_OK;
@@ -428,16 +433,142 @@ void fuse_ops(std::vector<SideOp>& ops, int nq) {
 
 // ------------------------------------------------------- pass scheduling --
 
-void schedule_side(Plan& p, int s, int L) {
-    SideProgram& sp = p.side[s];
-    if (p.fuse) fuse_ops(sp.ops, std::max(sp.nq, 1));
-    sp.passes.clear();
-    sp.devops.clear();
-    sp.pool.clear();
+void fuse_side(Plan& p, int s) {
+    if (p.fuse) fuse_ops(p.side[s].ops, std::max(p.side[s].nq, 1));
+}
+
+namespace {
+
+// Turns the ops of one pass into device ops: runs of one-qubit gates (on at
+// most four tile bits) and diagonal gates (on any qubits) become one
+// register-resident group; wider dense ops and factor slots stand alone.
+void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::vector<int>& ids) {
+    const int L = ps.n_local;
+    const int KG = std::min(4, L);
+    auto tbit = [&](int q) -> int {
+        for (int l = 0; l < L; ++l)
+            if (ps.local_q[l] == q) return l;
+        return -1 - q;
+    };
+    auto pos_in = [](const std::vector<int>& v, int x) -> int {
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i] == x) return (int)i;
+        return -1;
+    };
+    std::vector<int> grp, gbits;
+    auto close = [&]() {
+        if (grp.empty()) return;
+        std::vector<int> bits = gbits;
+        for (int id : grp) {
+            const SideOp& o = sp.ops[id];
+            if (o.kind != SideOp::DIAG) continue;
+            for (int j = 0; j < o.k && (int)bits.size() < KG; ++j) {
+                const int b = tbit(o.q[j]);
+                if (b >= 0 && pos_in(bits, b) < 0) bits.push_back(b);
+            }
+        }
+        for (int b = 0; b < L && (int)bits.size() < KG; ++b)
+            if (pos_in(bits, b) < 0) bits.push_back(b);
+        DevOp d{};
+        d.type = DOP_GROUP;
+        d.k = KG;
+        for (int g = 0; g < KG; ++g) d.bit[g] = bits[g];
+        d.mat = (int32_t)sc.subs.size();
+        d.rank = (int32_t)grp.size();
+        for (int id : grp) {
+            const SideOp& o = sp.ops[id];
+            SubOp so{};
+            if (o.kind == SideOp::DENSE) {
+                so.type = SUB_D1;
+                so.g = pos_in(bits, tbit(o.q[0]));
+                for (int i = 0; i < 4; ++i) {
+                    so.m[2 * i] = o.m[i].real();
+                    so.m[2 * i + 1] = o.m[i].imag();
+                }
+            } else {
+                int regpos[4], cpos[4], nc = 0;
+                for (int j = 0; j < o.k; ++j) {
+                    const int b = tbit(o.q[j]);
+                    const int pp = b >= 0 ? pos_in(bits, b) : -1;
+                    regpos[j] = pp;
+                    cpos[j] = -1;
+                    if (pp < 0) {
+                        so.qb[nc] = b;
+                        cpos[j] = nc++;
+                    }
+                }
+                so.nc = nc;
+                const int D = 1 << KG;
+                std::vector<cd> T((size_t)(1 << nc) * D);
+                bool sign = true;
+                for (int c = 0; c < (1 << nc); ++c)
+                    for (int jj = 0; jj < D; ++jj) {
+                        int idx = 0;
+                        for (int j = 0; j < o.k; ++j) {
+                            const int bit = regpos[j] >= 0 ? (jj >> regpos[j]) & 1 : (c >> cpos[j]) & 1;
+                            idx |= bit << (o.k - 1 - j);
+                        }
+                        const cd v = o.m[idx];
+                        T[(size_t)c * D + jj] = v;
+                        if (!(v == cd(1.0) || v == cd(-1.0))) sign = false;
+                    }
+                if (sign) {
+                    so.type = SUB_SIGN;
+                    for (int c = 0; c < (1 << nc); ++c) {
+                        uint32_t m16 = 0;
+                        for (int jj = 0; jj < D; ++jj)
+                            if (T[(size_t)c * D + jj] == cd(-1.0)) m16 |= 1u << jj;
+                        so.mask[c >> 1] |= m16 << (16 * (c & 1));
+                    }
+                } else {
+                    so.type = SUB_PHASE;
+                    so.mat = (int32_t)sc.pool.size();
+                    sc.pool.insert(sc.pool.end(), T.begin(), T.end());
+                }
+            }
+            sc.subs.push_back(so);
+        }
+        sc.devops.push_back(d);
+        grp.clear();
+        gbits.clear();
+    };
+    for (int id : ids) {
+        const SideOp& o = sp.ops[id];
+        if (o.kind == SideOp::DENSE && o.k == 1) {
+            const int b = tbit(o.q[0]);
+            if (pos_in(gbits, b) < 0 && (int)gbits.size() >= KG) close();
+            if (pos_in(gbits, b) < 0) gbits.push_back(b);
+            grp.push_back(id);
+            if (grp.size() >= 24) close();
+        } else if (o.kind == SideOp::DIAG) {
+            grp.push_back(id);
+            if (grp.size() >= 24) close();
+        } else {
+            close();
+            DevOp d{};
+            d.type = o.kind == SideOp::SLOT ? DOP_SLOT : DOP_DENSEK;
+            d.k = o.k;
+            for (int j = 0; j < o.k; ++j) d.bit[j] = tbit(o.q[j]);
+            d.mat = (int32_t)sc.pool.size();
+            d.rank = o.rank;
+            d.stride = o.stride;
+            sc.pool.insert(sc.pool.end(), o.m.begin(), o.m.end());
+            sc.devops.push_back(d);
+        }
+    }
+    close();
+}
+
+}  // namespace
+
+Schedule schedule_side(const Plan& p, int s, int L) {
+    const SideProgram& sp = p.side[s];
+    Schedule sc;
     const int nq = sp.nq;
     // a multi-pass tile needs room for the widest op beside the coalesced low qubits
     L = std::max(std::min(nq, 8), std::min(L, nq));
-    sp.tile_bits = L;
+    L = std::max(L, 1);
+    sc.tile_bits = L;
     const int nops = (int)sp.ops.size();
     std::vector<char> done(nops, 0);
     int remaining = nops;
@@ -446,14 +577,14 @@ void schedule_side(Plan& p, int s, int L) {
     while (first || remaining > 0) {
         Pass ps;
         ps.init_zero = first ? 1 : 0;
-        std::vector<char> local(nq, 0);
+        std::vector<char> local(std::max(nq, 1), 0);
         int nloc = 0;
-        for (int q = 0; q < low; ++q) local[q] = 1, ++nloc;
         if (L >= nq) {
             for (int q = 0; q < nq; ++q) local[q] = 1;
             nloc = nq;
         } else {
-            // choose the qubits of the earliest pending non-diagonal ops
+            for (int q = 0; q < low; ++q) local[q] = 1, ++nloc;
+            // the qubits of the earliest pending non-diagonal ops
             for (int i = 0; i < nops && nloc < L; ++i) {
                 if (done[i]) continue;
                 const SideOp& o = sp.ops[i];
@@ -473,10 +604,10 @@ void schedule_side(Plan& p, int s, int L) {
             if (local[q]) ps.local_q[t++] = q;
             else ps.nonlocal_q[u++] = q;
         }
-        ps.n_local = t;
+        ps.n_local = std::max(t, 1);
         ps.n_nonlocal = u;
-        ps.op_begin = (int)sp.devops.size();
-        std::vector<char> blocked(nq, 0);
+        std::vector<int> ids;
+        std::vector<char> blocked(std::max(nq, 1), 0);
         for (int i = 0; i < nops; ++i) {
             if (done[i]) continue;
             const SideOp& o = sp.ops[i];
@@ -488,31 +619,36 @@ void schedule_side(Plan& p, int s, int L) {
             if (!blk && (fits || o.kind == SideOp::DIAG)) {
                 done[i] = 1;
                 --remaining;
-                DevOp d{};
-                d.k = o.k;
-                for (int j = 0; j < o.k; ++j) {
-                    int pos = -1;
-                    for (int l = 0; l < ps.n_local; ++l)
-                        if (ps.local_q[l] == o.q[j]) pos = l;
-                    d.bit[j] = pos >= 0 ? pos : -1 - o.q[j];
-                }
-                d.mat = (int32_t)sp.pool.size();
-                d.rank = o.rank;
-                d.stride = o.stride;
-                if (o.kind == SideOp::DIAG) d.type = DOP_DIAG;
-                else if (o.kind == SideOp::SLOT) d.type = DOP_SLOT;
-                else d.type = o.k == 1 ? DOP_DENSE1 : (o.k == 2 ? DOP_DENSE2 : DOP_DENSEK);
-                sp.pool.insert(sp.pool.end(), o.m.begin(), o.m.end());
-                sp.devops.push_back(d);
+                ids.push_back(i);
             } else {
                 for (int j = 0; j < o.k; ++j) blocked[o.q[j]] = 1;
             }
         }
-        ps.op_end = (int)sp.devops.size();
-        sp.passes.push_back(ps);
+        ps.op_begin = (int32_t)sc.devops.size();
+        emit_pass(sp, sc, ps, ids);
+        ps.op_end = (int32_t)sc.devops.size();
+        sc.passes.push_back(ps);
         first = false;
-        if (sp.passes.size() > (size_t)4 * nops + 8) break;  // cannot happen: every pass applies an op
+        if (sc.passes.size() > (size_t)4 * nops + 8) break;  // every pass applies an op; never reached
     }
+    return sc;
+}
+
+int pick_schedule(const Plan& p, int64_t n_paths) {
+    // smallest tile that still gives every compute unit a workgroup; more
+    // passes cost extra trips through HBM, so stop at the first that does
+    const int64_t target = 256;
+    const size_t n = std::max(p.side[0].sched.size(), p.side[1].sched.size());
+    for (size_t i = 0; i < n; ++i) {
+        int64_t wgs = 0;
+        for (int s = 0; s < 2; ++s) {
+            const auto& v = p.side[s].sched;
+            const Schedule& sc = v[std::min(i, v.size() - 1)];
+            wgs += n_paths << std::max(0, p.side[s].nq - sc.tile_bits);
+        }
+        if (wgs >= target) return (int)i;
+    }
+    return (int)n - 1;
 }
 
 }  // namespace hsf

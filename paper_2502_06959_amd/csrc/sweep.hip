@@ -1,10 +1,16 @@
 // Half-state gate sweeps (Sec. II-A applied to each path's subcircuit,
-// Sec. II-B): every launch covers all paths of a chunk.  A workgroup owns one
-// tile of one path's half-state in LDS -- 2^L amplitudes spanning L of the
-// side's qubits, the low qubits always among them so that tile rows are
-// contiguous in HBM -- and applies every op of the pass to it before writing
-// it back.  When the whole half-state fits (L = n_side) there is a single
-// pass that starts from |0...0> in LDS and only writes HBM once.
+// Sec. II-B).  One launch covers every path of a chunk on both sides.  A
+// workgroup owns one tile of one path's half-state in LDS -- 2^L amplitudes
+// spanning L of the side's qubits, the low qubits among them so that tile
+// rows are contiguous in HBM -- and applies every op of the pass before
+// writing the tile back.  When the whole half-state fits (L = n_side) there
+// is a single pass that starts from |0...0> in LDS and writes HBM once.
+//
+// Inside a pass, runs of one-qubit gates and diagonal gates are grouped: a
+// thread loads the 16 amplitudes that differ in four tile bits into
+// registers, applies the run there (one-qubit gates as 2x2 butterflies,
+// diagonal gates as sign masks or phase rows), and stores them back, so LDS
+// is touched once per group instead of once per gate.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,14 +42,15 @@ __device__ __forceinline__ V cfma(V a, V b, V c) {  // c + a*b
     return r;
 }
 
-struct PassArgs {
-    int32_t n_local;
-    int32_t init_zero;
-    int32_t op_begin, op_end;
-    int32_t n_nonlocal;
-    int32_t n_contig;            // local_q[i] == i for i < n_contig
-    int32_t local_q[kMaxTileBits];
-    int32_t nonlocal_q[kMaxTileBits];
+struct SideArgs {
+    const Pass* pass;        // device copy of the pass record
+    void* psi;
+    int64_t ld;
+    const DevOp* ops;
+    const SubOp* subs;
+    const void* pool;
+    uint32_t n_tiles;
+    uint32_t n_blocks;       // paths x tiles
 };
 
 // Inserts a zero bit at position b of i.
@@ -52,16 +59,28 @@ __device__ __forceinline__ uint32_t ins0(uint32_t i, int b) {
     return ((i >> b) << (b + 1)) | lo;
 }
 
+template <int K>
+__device__ __forceinline__ void sort_bits(const int32_t* bit, int (&sb)[K]) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) sb[i] = bit[i];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = i + 1; j < K; ++j)
+            if (sb[j] < sb[i]) {
+                const int t = sb[i];
+                sb[i] = sb[j];
+                sb[j] = t;
+            }
+}
+
+// Dense 2^K x 2^K matrix on tile bits bit[0..K) (bit[0] most significant).
 template <int K, typename V>
 __device__ __forceinline__ void apply_dense(V* tile, uint32_t E, const int32_t* bit, const V* __restrict__ m,
                                             int tid, int nt) {
     constexpr int D = 1 << K;
     int sb[K];
-    for (int i = 0; i < K; ++i) sb[i] = bit[i];
-    // ascending order for zero insertion
-    for (int i = 0; i < K; ++i)
-        for (int j = i + 1; j < K; ++j)
-            if (sb[j] < sb[i]) { int t = sb[i]; sb[i] = sb[j]; sb[j] = t; }
+    sort_bits<K>(bit, sb);
     uint32_t off[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -71,17 +90,6 @@ __device__ __forceinline__ void apply_dense(V* tile, uint32_t E, const int32_t* 
             if ((j >> (K - 1 - i)) & 1) o |= 1u << bit[i];
         off[j] = o;
     }
-    // K <= 2: matrix in registers; wider ops read it through the scalar cache
-    constexpr int DM = K <= 2 ? D * D : 1;
-    V mm[DM];
-    if constexpr (K <= 2) {
-#pragma unroll
-        for (int j = 0; j < D * D; ++j) mm[j] = m[j];
-    }
-    auto M_ = [&](int idx) -> V {
-        if constexpr (K <= 2) return mm[idx];
-        else return m[idx];
-    };
     const uint32_t groups = E >> K;
     for (uint32_t g = tid; g < groups; g += nt) {
         uint32_t base = g;
@@ -92,40 +100,130 @@ __device__ __forceinline__ void apply_dense(V* tile, uint32_t E, const int32_t* 
         for (int j = 0; j < D; ++j) v[j] = tile[base | off[j]];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-            V acc = cmul(M_(r * D), v[0]);
+            V acc = cmul(m[r * D], v[0]);
 #pragma unroll
-            for (int j = 1; j < D; ++j) acc = cfma(M_(r * D + j), v[j], acc);
+            for (int j = 1; j < D; ++j) acc = cfma(m[r * D + j], v[j], acc);
             tile[base | off[r]] = acc;
         }
     }
 }
 
+// 2x2 butterfly on register position G of a 2^K register group.
+template <int K, int G, typename V>
+__device__ __forceinline__ void d1g(V (&v)[1 << K], V m00, V m01, V m10, V m11) {
+    if constexpr (G < K) {
+#pragma unroll
+        for (int j = 0; j < (1 << K); ++j) {
+            if (j & (1 << G)) continue;
+            const V x0 = v[j], x1 = v[j | (1 << G)];
+            v[j] = cfma(m01, x1, cmul(m00, x0));
+            v[j | (1 << G)] = cfma(m11, x1, cmul(m10, x0));
+        }
+    }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E, const DevOp& op,
+                                            const SubOp* __restrict__ subs, const typename Cx<T>::v* __restrict__ pool,
+                                            uint64_t gbase, int tid, int nt) {
+    using V = typename Cx<T>::v;
+    constexpr int D = 1 << K;
+    int sb[K];
+    sort_bits<K>(op.bit, sb);
+    uint32_t off[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int g = 0; g < K; ++g)
+            if ((j >> g) & 1) o |= 1u << op.bit[g];
+        off[j] = o;
+    }
+    const int s0 = op.mat, ns = op.rank;
+    const uint32_t groups = E >> K;
+    for (uint32_t gi = tid; gi < groups; gi += nt) {
+        uint32_t base = gi;
+#pragma unroll
+        for (int i = 0; i < K; ++i) base = ins0(base, sb[i]);
+        V v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = tile[base | off[j]];
+        for (int s = s0; s < s0 + ns; ++s) {
+            const SubOp& so = subs[s];
+            const int ty = so.type;
+            if (ty == SUB_D1) {
+                V m00, m01, m10, m11;
+                m00.x = (T)so.m[0]; m00.y = (T)so.m[1];
+                m01.x = (T)so.m[2]; m01.y = (T)so.m[3];
+                m10.x = (T)so.m[4]; m10.y = (T)so.m[5];
+                m11.x = (T)so.m[6]; m11.y = (T)so.m[7];
+                switch (so.g) {
+                    case 0: d1g<K, 0>(v, m00, m01, m10, m11); break;
+                    case 1: d1g<K, 1>(v, m00, m01, m10, m11); break;
+                    case 2: d1g<K, 2>(v, m00, m01, m10, m11); break;
+                    default: d1g<K, 3>(v, m00, m01, m10, m11); break;
+                }
+            } else {
+                uint32_t c = 0;
+                for (int i = 0; i < so.nc; ++i) {
+                    const int b = so.qb[i];
+                    const uint32_t bit = b >= 0 ? (base >> b) & 1u : (uint32_t)((gbase >> (-1 - b)) & 1u);
+                    c |= bit << i;
+                }
+                if (ty == SUB_SIGN) {
+                    const uint32_t mask = (so.mask[c >> 1] >> ((c & 1u) * 16u)) & 0xffffu;
+#pragma unroll
+                    for (int j = 0; j < D; ++j)
+                        if ((mask >> j) & 1u) {
+                            v[j].x = -v[j].x;
+                            v[j].y = -v[j].y;
+                        }
+                } else {
+                    const V* row = pool + so.mat + (c << K);
+#pragma unroll
+                    for (int j = 0; j < D; ++j) v[j] = cmul(row[j], v[j]);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) tile[base | off[j]] = v[j];
+    }
+}
+
 template <typename T>
-__global__ __launch_bounds__(1024) void sweep_pass(PassArgs a, typename Cx<T>::v* __restrict__ psi, int64_t ld,
-                                                   int64_t p_begin, uint32_t n_tiles,
-                                                   const DevOp* __restrict__ ops,
-                                                   const typename Cx<T>::v* __restrict__ pool) {
+__global__ __launch_bounds__(1024) void sweep_pass(SideArgs s0, SideArgs s1, int64_t p_begin) {
     using V = typename Cx<T>::v;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* tile = reinterpret_cast<V*>(smem_raw);
-    const int L = a.n_local;
-    const uint32_t E = 1u << L;
-    const uint32_t pl = blockIdx.x / n_tiles;
-    const uint32_t t = blockIdx.x - pl * n_tiles;
+    const bool sd = blockIdx.x >= s0.n_blocks;
+    const Pass* __restrict__ ps = sd ? s1.pass : s0.pass;
+    const DevOp* __restrict__ ops = sd ? s1.ops : s0.ops;
+    const SubOp* __restrict__ subs = sd ? s1.subs : s0.subs;
+    const V* __restrict__ pool = reinterpret_cast<const V*>(sd ? s1.pool : s0.pool);
+    const int64_t ld = sd ? s1.ld : s0.ld;
+    const uint32_t n_tiles = sd ? s1.n_tiles : s0.n_tiles;
+    const uint32_t blk = sd ? blockIdx.x - s0.n_blocks : blockIdx.x;
+    const uint32_t pl = blk / n_tiles;
+    const uint32_t t = blk - pl * n_tiles;
     const int64_t path = p_begin + pl;
-    V* st = psi + (int64_t)pl * ld;
+    V* st = reinterpret_cast<V*>(sd ? s1.psi : s0.psi) + (int64_t)pl * ld;
     const int tid = threadIdx.x, nt = blockDim.x;
 
+    const int L = ps->n_local;
+    const uint32_t E = 1u << L;
     uint64_t base = 0;
-    for (int i = 0; i < a.n_nonlocal; ++i) base |= (uint64_t)((t >> i) & 1u) << a.nonlocal_q[i];
-    const uint32_t cmask = (1u << a.n_contig) - 1u;
+    const int nnl = ps->n_nonlocal;
+    for (int i = 0; i < nnl; ++i) base |= (uint64_t)((t >> i) & 1u) << ps->nonlocal_q[i];
+    int nc = 0;
+    while (nc < L && ps->local_q[nc] == nc) ++nc;
+    const uint32_t cmask = (1u << nc) - 1u;
     auto gidx = [&](uint32_t e) -> uint64_t {
         uint64_t g = base | (e & cmask);
-        for (int i = a.n_contig; i < L; ++i) g |= (uint64_t)((e >> i) & 1u) << a.local_q[i];
+        for (int i = nc; i < L; ++i) g |= (uint64_t)((e >> i) & 1u) << ps->local_q[i];
         return g;
     };
 
-    if (a.init_zero) {
+    if (ps->init_zero) {
         for (uint32_t e = tid; e < E; e += nt) {
             V z;
             z.x = (e == 0 && base == 0) ? T(1) : T(0);
@@ -137,50 +235,25 @@ __global__ __launch_bounds__(1024) void sweep_pass(PassArgs a, typename Cx<T>::v
     }
     __syncthreads();
 
-    for (int o = a.op_begin; o < a.op_end; ++o) {
+    const int o1 = ps->op_end;
+    for (int o = ps->op_begin; o < o1; ++o) {
         const DevOp& op = ops[o];
         const int type = op.type;
-        if (type == DOP_DENSE1) {
-            const int b = op.bit[0];
-            const V m00 = pool[op.mat], m01 = pool[op.mat + 1], m10 = pool[op.mat + 2], m11 = pool[op.mat + 3];
-            const uint32_t half = E >> 1;
-            for (uint32_t i = tid; i < half; i += nt) {
-                const uint32_t i0 = ins0(i, b), i1 = i0 | (1u << b);
-                const V x0 = tile[i0], x1 = tile[i1];
-                tile[i0] = cfma(m01, x1, cmul(m00, x0));
-                tile[i1] = cfma(m11, x1, cmul(m10, x0));
+        if (type == DOP_GROUP) {
+            switch (op.k) {
+                case 4: apply_group<4, T>(tile, E, op, subs, pool, base, tid, nt); break;
+                case 3: apply_group<3, T>(tile, E, op, subs, pool, base, tid, nt); break;
+                case 2: apply_group<2, T>(tile, E, op, subs, pool, base, tid, nt); break;
+                default: apply_group<1, T>(tile, E, op, subs, pool, base, tid, nt); break;
             }
-        } else if (type == DOP_DENSE2) {
-            apply_dense<2>(tile, E, op.bit, pool + op.mat, tid, nt);
-        } else if (type == DOP_DENSEK || type == DOP_SLOT) {
+        } else {
             int32_t mat = op.mat;
-            const int D2 = 1 << (2 * op.k);
-            if (type == DOP_SLOT) mat += (int32_t)((path / op.stride) % op.rank) * D2;
+            if (type == DOP_SLOT) mat += (int32_t)((path / op.stride) % op.rank) << (2 * op.k);
             switch (op.k) {
                 case 1: apply_dense<1>(tile, E, op.bit, pool + mat, tid, nt); break;
                 case 2: apply_dense<2>(tile, E, op.bit, pool + mat, tid, nt); break;
                 case 3: apply_dense<3>(tile, E, op.bit, pool + mat, tid, nt); break;
                 default: apply_dense<4>(tile, E, op.bit, pool + mat, tid, nt); break;
-            }
-        } else {  // DOP_DIAG
-            const int k = op.k;
-            uint32_t c0 = 0;
-            int lb[4], ls[4], nl = 0;
-            for (int i = 0; i < k; ++i) {
-                const int b = op.bit[i];
-                if (b >= 0) {
-                    lb[nl] = b;
-                    ls[nl] = k - 1 - i;
-                    ++nl;
-                } else {
-                    c0 |= (uint32_t)((base >> (-1 - b)) & 1u) << (k - 1 - i);
-                }
-            }
-            const V* dg = pool + op.mat;
-            for (uint32_t e = tid; e < E; e += nt) {
-                uint32_t idx = c0;
-                for (int i = 0; i < nl; ++i) idx |= ((e >> lb[i]) & 1u) << ls[i];
-                tile[e] = cmul(dg[idx], tile[e]);
             }
         }
         __syncthreads();
@@ -191,22 +264,25 @@ __global__ __launch_bounds__(1024) void sweep_pass(PassArgs a, typename Cx<T>::v
 
 std::mutex g_dev_mutex;
 
+hsf_status upload(const void* src, size_t bytes, void** dst) {
+    hsf_status s = hip_check(hipMalloc(dst, std::max<size_t>(bytes, 64)), "hipMalloc(plan tables)");
+    if (s != HSF_OK || bytes == 0) return s;
+    return hip_check(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(plan tables)");
+}
+
 template <typename T>
-hsf_status upload_side(const SideProgram& sp, void** ops, void** pool) {
+hsf_status upload_schedule(const Schedule& sc, DeviceSchedule& d) {
     using V = typename Cx<T>::v;
     hsf_status s;
-    const size_t no = std::max<size_t>(sp.devops.size(), 1);
-    if ((s = hip_check(hipMalloc(ops, no * sizeof(DevOp)), "hipMalloc(ops)")) != HSF_OK) return s;
-    if (!sp.devops.empty() &&
-        (s = hip_check(hipMemcpy(*ops, sp.devops.data(), sp.devops.size() * sizeof(DevOp), hipMemcpyHostToDevice), "hipMemcpy(ops)")) != HSF_OK)
-        return s;
-    std::vector<V> h(std::max<size_t>(sp.pool.size(), 1));
-    for (size_t i = 0; i < sp.pool.size(); ++i) {
-        h[i].x = (T)sp.pool[i].real();
-        h[i].y = (T)sp.pool[i].imag();
+    if ((s = upload(sc.passes.data(), sc.passes.size() * sizeof(Pass), &d.passes)) != HSF_OK) return s;
+    if ((s = upload(sc.devops.data(), sc.devops.size() * sizeof(DevOp), &d.ops)) != HSF_OK) return s;
+    if ((s = upload(sc.subs.data(), sc.subs.size() * sizeof(SubOp), &d.subs)) != HSF_OK) return s;
+    std::vector<V> h(sc.pool.size());
+    for (size_t i = 0; i < sc.pool.size(); ++i) {
+        h[i].x = (T)sc.pool[i].real();
+        h[i].y = (T)sc.pool[i].imag();
     }
-    if ((s = hip_check(hipMalloc(pool, h.size() * sizeof(V)), "hipMalloc(pool)")) != HSF_OK) return s;
-    return hip_check(hipMemcpy(*pool, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice), "hipMemcpy(pool)");
+    return upload(h.data(), h.size() * sizeof(V), &d.pool);
 }
 
 bool g_attr_done[2] = {false, false};
@@ -225,17 +301,18 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
             *out = &d;
             return HSF_OK;
         }
-    DeviceCopy d;
+    p.dev.emplace_back();
+    DeviceCopy& d = p.dev.back();
     d.device = dev;
     for (int side = 0; side < 2; ++side) {
-        s = p.dtype == HSF_C128 ? upload_side<double>(p.side[side], &d.ops[side], &d.pool[side])
-                                : upload_side<float>(p.side[side], &d.ops[side], &d.pool[side]);
-        if (s != HSF_OK) {
-            for (int j = 0; j < 2; ++j) {
-                if (d.ops[j]) (void)hipFree(d.ops[j]);
-                if (d.pool[j]) (void)hipFree(d.pool[j]);
+        for (const Schedule& sc : p.side[side].sched) {
+            d.side[side].emplace_back();
+            s = p.dtype == HSF_C128 ? upload_schedule<double>(sc, d.side[side].back())
+                                    : upload_schedule<float>(sc, d.side[side].back());
+            if (s != HSF_OK) {
+                release_device(p);
+                return s;
             }
-            return s;
         }
     }
     const int di = p.dtype == HSF_C128 ? 1 : 0;
@@ -248,8 +325,7 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
         if (s != HSF_OK) return s;
         g_attr_done[di] = true;
     }
-    p.dev.push_back(d);
-    *out = &p.dev.back();
+    *out = &d;
     return HSF_OK;
 }
 
@@ -258,51 +334,68 @@ void release_device(Plan& p) {
     if (p.dev.empty() || hipGetDevice(&cur) != hipSuccess) return;
     for (DeviceCopy& d : p.dev) {
         (void)hipSetDevice(d.device);
-        for (int j = 0; j < 2; ++j) {
-            if (d.ops[j]) (void)hipFree(d.ops[j]);
-            if (d.pool[j]) (void)hipFree(d.pool[j]);
-        }
+        for (int side = 0; side < 2; ++side)
+            for (DeviceSchedule& ds : d.side[side])
+                for (void* q : {ds.passes, ds.ops, ds.subs, ds.pool})
+                    if (q) (void)hipFree(q);
     }
     (void)hipSetDevice(cur);
     p.dev.clear();
 }
 
-hsf_status run_side(Plan& p, DeviceCopy& d, int side, int64_t p_begin, int64_t n_paths, void* psi, int64_t ld,
-                    hipStream_t stream) {
-    const SideProgram& sp = p.side[side];
+hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
+                     void* psiB, int64_t ldB, hipStream_t stream) {
     const bool dbl = p.dtype == HSF_C128;
     const size_t esz = dbl ? 16 : 8;
-    for (const Pass& ps : sp.passes) {
-        PassArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.n_local = ps.n_local;
-        a.init_zero = ps.init_zero;
-        a.op_begin = ps.op_begin;
-        a.op_end = ps.op_end;
-        a.n_nonlocal = ps.n_nonlocal;
-        int c = 0;
-        while (c < ps.n_local && ps.local_q[c] == c) ++c;
-        a.n_contig = c;
-        for (int i = 0; i < kMaxTileBits; ++i) {
-            a.local_q[i] = ps.local_q[i];
-            a.nonlocal_q[i] = ps.nonlocal_q[i];
+    const int pick = pick_schedule(p, n_paths);
+    void* psi[2] = {psiA, psiB};
+    const int64_t ld[2] = {ldA, ldB};
+    const Schedule* sc[2];
+    int si[2];
+    size_t npass = 0;
+    for (int s = 0; s < 2; ++s) {
+        si[s] = std::min<int>(pick, (int)p.side[s].sched.size() - 1);
+        sc[s] = &p.side[s].sched[si[s]];
+        if (psi[s]) npass = std::max(npass, sc[s]->passes.size());
+    }
+    // paths per launch bounded so the grid stays below 2^31 workgroups
+    int64_t tiles_max = 1;
+    for (int s = 0; s < 2; ++s)
+        if (psi[s]) tiles_max = std::max<int64_t>(tiles_max, int64_t(1) << sc[s]->passes[0].n_nonlocal);
+    const int64_t max_paths = std::max<int64_t>(1, (int64_t(1) << 29) / tiles_max);
+    for (size_t k = 0; k < npass; ++k) {
+        SideArgs a[2];
+        std::memset(a, 0, sizeof(a));
+        uint32_t emax = 1;
+        for (int s = 0; s < 2; ++s) {
+            if (!psi[s] || k >= sc[s]->passes.size()) continue;
+            const Pass& ps = sc[s]->passes[k];
+            const DeviceSchedule& ds = d.side[s][si[s]];
+            a[s].pass = reinterpret_cast<const Pass*>(ds.passes) + k;
+            a[s].ld = ld[s];
+            a[s].ops = (const DevOp*)ds.ops;
+            a[s].subs = (const SubOp*)ds.subs;
+            a[s].pool = ds.pool;
+            a[s].n_tiles = 1u << ps.n_nonlocal;
+            emax = std::max(emax, 1u << ps.n_local);
         }
-        const uint32_t n_tiles = 1u << ps.n_nonlocal;
-        const uint32_t E = 1u << ps.n_local;
-        const int threads = (int)std::min<uint32_t>(dbl ? 512u : 1024u, std::max<uint32_t>(64u, E / 2));
-        const size_t shmem = (size_t)E * esz;
-        const int64_t max_paths = std::max<int64_t>(1, (int64_t(1) << 30) / n_tiles);
+        const int threads = (int)std::min<uint32_t>(dbl ? 512u : 1024u, std::max<uint32_t>(64u, emax / 16));
+        const size_t shmem = (size_t)emax * esz;
         for (int64_t p0 = 0; p0 < n_paths; p0 += max_paths) {
             const int64_t np = std::min(max_paths, n_paths - p0);
-            const dim3 grid((uint32_t)(np * n_tiles));
+            SideArgs b[2] = {a[0], a[1]};
+            for (int s = 0; s < 2; ++s) {
+                if (!b[s].pass) continue;
+                b[s].psi = (unsigned char*)psi[s] + (size_t)(p0 * ld[s]) * esz;
+                b[s].n_blocks = (uint32_t)(np * b[s].n_tiles);
+            }
+            // a side with no pass this round contributes no workgroups
+            const uint32_t total = b[0].n_blocks + b[1].n_blocks;
+            if (total == 0) continue;
             if (dbl)
-                hipLaunchKernelGGL(sweep_pass<double>, grid, dim3(threads), shmem, stream, a,
-                                   (double2*)psi + p0 * ld, ld, p_begin + p0, n_tiles, (const DevOp*)d.ops[side],
-                                   (const double2*)d.pool[side]);
+                hipLaunchKernelGGL(sweep_pass<double>, dim3(total), dim3(threads), shmem, stream, b[0], b[1], p_begin + p0);
             else
-                hipLaunchKernelGGL(sweep_pass<float>, grid, dim3(threads), shmem, stream, a,
-                                   (float2*)psi + p0 * ld, ld, p_begin + p0, n_tiles, (const DevOp*)d.ops[side],
-                                   (const float2*)d.pool[side]);
+                hipLaunchKernelGGL(sweep_pass<float>, dim3(total), dim3(threads), shmem, stream, b[0], b[1], p_begin + p0);
             hsf_status s = hip_check(hipGetLastError(), "sweep_pass launch");
             if (s != HSF_OK) return s;
         }

@@ -1,0 +1,88 @@
+"""GPU parity of the path sum (Sec. II-B reconstruction, C = PsiA^T PsiB) in
+every arithmetic mode, on random half-states with ragged shapes, against the
+exact product in FP64 on the host (numpy).  Tolerances: FP32 and split-BF16
+x3 rel-L2 <= 1e-5 (the c64 amplitude bar), FP64 <= 1e-12."""
+import numpy as np
+import pytest
+import torch
+
+import circuitgen as cg
+from oracle import hsf as ohsf
+from paper_2502_06959_amd import Plan, hsf_norm2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _shape_plan(na, nb, dtype="c64"):
+    # a gate-free circuit: only its dimensions matter to the path sum
+    return Plan(cg.circuit("dims", na + nb, [], nb - 1, []), dtype=dtype)
+
+
+def _rand(rng, k, d, dtype):
+    x = (rng.standard_normal((k, d)) + 1j * rng.standard_normal((k, d))) / np.sqrt(2 * d * max(k, 1) ** 0.5)
+    return x.astype(dtype)
+
+
+CASES = [(1, 1, 1), (5, 3, 2), (6, 6, 3), (7, 8, 17), (9, 7, 33), (8, 8, 64), (10, 6, 100), (6, 10, 257),
+         (12, 12, 32), (3, 11, 7)]
+
+
+@pytest.mark.parametrize("na,nb,K", CASES)
+@pytest.mark.parametrize("mode", ["f32", "bf16x3", "f64"])
+def test_path_sum_modes(na, nb, K, mode):
+    rng = np.random.default_rng(na * 1000 + nb * 10 + K)
+    A = _rand(rng, K, 1 << na, np.complex64)
+    B = _rand(rng, K, 1 << nb, np.complex64)
+    ref = A.astype(np.complex128).T @ B.astype(np.complex128)
+    plan = _shape_plan(na, nb)
+    out = plan.amplitudes_full(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), n_paths=K, mode=mode)
+    torch.cuda.synchronize()
+    tol = 1e-12 if mode == "f64" else 1e-5
+    assert ohsf.rel_l2(out.cpu().numpy(), ref) < tol
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16x3", "f64"])
+def test_path_sum_row_range_ld_and_accumulate(mode):
+    rng = np.random.default_rng(3)
+    na, nb, K = 9, 8, 40
+    A = _rand(rng, K, 1 << na, np.complex64)
+    B = _rand(rng, K, 1 << nb, np.complex64)
+    ref = A.astype(np.complex128).T @ B.astype(np.complex128)
+    plan = _shape_plan(na, nb)
+    # padded leading dimensions
+    Ad = torch.zeros((K, (1 << na) + 24), dtype=torch.complex64, device="cuda")
+    Bd = torch.zeros((K, (1 << nb) + 8), dtype=torch.complex64, device="cuda")
+    Ad[:, :1 << na] = torch.from_numpy(A).cuda()
+    Bd[:, :1 << nb] = torch.from_numpy(B).cuda()
+    odt = torch.complex128 if mode == "f64" else torch.complex64
+    out = torch.zeros((300, (1 << nb) + 16), dtype=odt, device="cuda")
+    h = K // 2
+    plan.amplitudes_full(Ad[:h], Bd[:h], n_paths=h, rows=(100, 400), mode=mode, out=out)
+    plan.amplitudes_full(Ad[h:], Bd[h:], n_paths=K - h, rows=(100, 400), mode=mode, out=out, accumulate=True)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert ohsf.rel_l2(got[:, :1 << nb], ref[100:400]) < (1e-12 if mode == "f64" else 1e-5)
+    assert np.all(got[:, 1 << nb:] == 0)          # padding columns untouched
+
+
+def test_bf16x3_on_c2p_matches_fp64_mode():
+    """The chosen form on the benchmarked workload: split-BF16 x3 against the
+    FP64 path sum of the same half-states, over all 2^28 amplitudes."""
+    c = cg.c2p()
+    plan = Plan(c)
+    A, B = plan.run_paths()
+    rows = (0, 1 << 12)
+    o16 = plan.amplitudes_full(A, B, mode="bf16x3", rows=rows)
+    o64 = plan.amplitudes_full(A, B, mode="f64", rows=rows)
+    s = hsf_norm2(o16.reshape(-1), o64.reshape(-1)).cpu().numpy()
+    ref = hsf_norm2(o64.reshape(-1)).cpu().numpy()
+    assert np.sqrt(s[1] / ref[0]) < 1e-5
+    full = plan.amplitudes_full(A, B, mode="bf16x3")
+    nrm = hsf_norm2(full.reshape(-1)).cpu().numpy()[0]
+    assert abs(nrm - 1) < 1e-5
