@@ -14,12 +14,13 @@
 #include <algorithm>
 
 #include "device.h"
+#include "epilogue.h"
 
 namespace hsf {
 
 namespace {
 
-using f32x16 = float __attribute__((ext_vector_type(16)));
+using f32x16 = f32x16_t;
 using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
 using u16x8 = unsigned short __attribute__((ext_vector_type(8)));
 
@@ -63,14 +64,14 @@ __device__ __forceinline__ bf16x8 as_bf(u16x8 v) { return __builtin_bit_cast(bf1
 // (l % 32) and paths k0 + 8 (l / 32) .. +7.
 constexpr int BF_TILE = 128;
 
-__global__ __launch_bounds__(256) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
-                                                             const unsigned short* __restrict__ PB, int64_t N,
-                                                             int64_t Kp, float2* __restrict__ out, int64_t ldo,
-                                                             int accumulate) {
+__device__ __forceinline__ void bf16x3_tile(const unsigned short* __restrict__ PA, int64_t M,
+                                            const unsigned short* __restrict__ PB, int64_t N, int64_t Kp,
+                                            float2* __restrict__ out, int64_t ldo, int accumulate, int64_t row0,
+                                            int64_t col0) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 31, lk = lane >> 5;
-    const int64_t m0 = (int64_t)blockIdx.y * BF_TILE + (w >> 1) * 64;
-    const int64_t n0 = (int64_t)blockIdx.x * BF_TILE + (w & 1) * 64;
+    const int64_t m0 = row0 + (w >> 1) * 64;
+    const int64_t n0 = col0 + (w & 1) * 64;
     const int64_t pa = M * Kp, pb = N * Kp;
     f32x16 cr[2][2], ci[2][2];
 #pragma unroll
@@ -132,29 +133,21 @@ __global__ __launch_bounds__(256) void pathsum_bf16x3_kernel(const unsigned shor
             }
         }
     }
-    // accumulator r of a 32x32 block: row (r/4)*8 + (lane/32)*4 + r%4, column lane%32
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int64_t col = n0 + b * 32 + li;
-            if (col >= N) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + a * 32 + (r >> 2) * 8 + lk * 4 + (r & 3);
-                if (row >= M) continue;
-                float2 v = make_float2(cr[a][b][r], ci[a][b][r]);
-                float2* o = out + row * ldo + col;
-                if (accumulate) {
-                    const float2 old = *o;
-                    v.x += old.x;
-                    v.y += old.y;
-                }
-                *o = v;
-            }
-        }
+    store_tile_128(cr, ci, row0, col0, M, N, out, ldo, accumulate);
 }
 
+// Persistent: workgroup g handles tiles g, g + gridDim.x, ... (tile t covers
+// rows (t / tiles_n) * 128 and columns (t % tiles_n) * 128), so the stores of
+// one tile drain while the next tile loads and multiplies.
+__global__ __launch_bounds__(256) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
+                                                             const unsigned short* __restrict__ PB, int64_t N,
+                                                             int64_t Kp, float2* __restrict__ out, int64_t ldo,
+                                                             int accumulate, int64_t tiles_n, int64_t tiles) {
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
+        bf16x3_tile(PA, M, PB, N, Kp, out, ldo, accumulate, tm * BF_TILE, tn * BF_TILE);
+    }
+}
 }  // namespace
 
 hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
@@ -171,9 +164,10 @@ hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_
         hsf_status s = hip_check(hipGetLastError(), "split_planes launch");
         if (s != HSF_OK) return s;
     }
-    const dim3 grid((uint32_t)((N + BF_TILE - 1) / BF_TILE), (uint32_t)((M + BF_TILE - 1) / BF_TILE));
-    if (grid.y > 65535u) return fail(HSF_E_ARG, "too many output rows in one call (split the row range)");
-    hipLaunchKernelGGL(pathsum_bf16x3_kernel, grid, dim3(256), 0, st, PA, M, PB, N, Kp, out, ldo, accumulate);
+    const int64_t tn = (N + BF_TILE - 1) / BF_TILE, tiles = tn * ((M + BF_TILE - 1) / BF_TILE);
+    const int grid = persistent_grid((const void*)pathsum_bf16x3_kernel, 256, 0, tiles);
+    hipLaunchKernelGGL(pathsum_bf16x3_kernel, dim3(grid), dim3(256), 0, st, PA, M, PB, N, Kp, out, ldo, accumulate,
+                       tn, tiles);
     return hip_check(hipGetLastError(), "pathsum_bf16x3 launch");
 }
 

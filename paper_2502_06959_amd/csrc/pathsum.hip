@@ -10,12 +10,13 @@
 #include <algorithm>
 
 #include "device.h"
+#include "epilogue.h"
 
 namespace hsf {
 
 namespace {
 
-using f32x16 = float __attribute__((ext_vector_type(16)));
+using f32x16 = f32x16_t;
 using f64x4 = double __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- FP32 ----
@@ -26,14 +27,13 @@ using f64x4 = double __attribute__((ext_vector_type(4)));
 // consecutive complex entries (256 contiguous bytes).
 constexpr int F32_TILE = 128;
 
-__global__ __launch_bounds__(256) void pathsum_f32(const float2* __restrict__ A, int64_t ldA,
-                                                   const float2* __restrict__ B, int64_t ldB, int64_t K,
-                                                   int64_t M, int64_t N, float2* __restrict__ out,
-                                                   int64_t ldo, int accumulate) {
+__device__ __forceinline__ void f32_tile(const float2* __restrict__ A, int64_t ldA, const float2* __restrict__ B,
+                                         int64_t ldB, int64_t K, int64_t M, int64_t N, float2* __restrict__ out,
+                                         int64_t ldo, int accumulate, int64_t row0, int64_t col0) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 31, lk = lane >> 5;
-    const int64_t m0 = (int64_t)blockIdx.y * F32_TILE + (w >> 1) * 64;
-    const int64_t n0 = (int64_t)blockIdx.x * F32_TILE + (w & 1) * 64;
+    const int64_t m0 = row0 + (w >> 1) * 64;
+    const int64_t n0 = col0 + (w & 1) * 64;
     f32x16 cr[2][2], ci[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -76,27 +76,18 @@ __global__ __launch_bounds__(256) void pathsum_f32(const float2* __restrict__ A,
             bv[a] = bn[a];
         }
     }
-    // accumulator r of a 32x32 block: row (r/4)*8 + (lane/32)*4 + r%4, column lane%32
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int64_t col = n0 + b * 32 + li;
-            if (col >= N) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + a * 32 + (r >> 2) * 8 + lk * 4 + (r & 3);
-                if (row >= M) continue;
-                float2 v = make_float2(cr[a][b][r], ci[a][b][r]);
-                float2* o = out + row * ldo + col;
-                if (accumulate) {
-                    const float2 old = *o;
-                    v.x += old.x;
-                    v.y += old.y;
-                }
-                *o = v;
-            }
-        }
+    store_tile_128(cr, ci, row0, col0, M, N, out, ldo, accumulate);
+}
+
+// Persistent over 128 x 128 output tiles (see the split-BF16 kernel).
+__global__ __launch_bounds__(256) void pathsum_f32(const float2* __restrict__ A, int64_t ldA,
+                                                   const float2* __restrict__ B, int64_t ldB, int64_t K,
+                                                   int64_t M, int64_t N, float2* __restrict__ out, int64_t ldo,
+                                                   int accumulate, int64_t tiles_n, int64_t tiles) {
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
+        f32_tile(A, ldA, B, ldB, K, M, N, out, ldo, accumulate, tm * F32_TILE, tn * F32_TILE);
+    }
 }
 
 // ---------------------------------------------------------------- FP64 ----
@@ -278,6 +269,13 @@ hsf_status launch_norm(const void* a, const void* b, int64_t n, double* out, dou
 
 }  // namespace
 
+int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t tiles) {
+    int dev = 0, cus = 256, per = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, shmem) != hipSuccess || per < 1) per = 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per));
+}
+
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths) {
     // hi and lo BF16 planes of the real and imaginary parts of both operands,
     // paths padded to a multiple of 16
@@ -292,10 +290,10 @@ hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void*
                     int64_t row0, int64_t M, int64_t N, void* out, int64_t ldo, int accumulate, void* ws,
                     hipStream_t st) {
     if (dtype == HSF_C64 && mode == HSF_SUM_F32) {
-        const dim3 grid((uint32_t)((N + F32_TILE - 1) / F32_TILE), (uint32_t)((M + F32_TILE - 1) / F32_TILE));
-        if (grid.y > 65535u) return fail(HSF_E_ARG, "too many output rows in one call (split the row range)");
-        hipLaunchKernelGGL(pathsum_f32, grid, dim3(256), 0, st, (const float2*)A + row0, ldA, (const float2*)B, ldB, K,
-                           M, N, (float2*)out, ldo, accumulate);
+        const int64_t tn = (N + F32_TILE - 1) / F32_TILE, tiles = tn * ((M + F32_TILE - 1) / F32_TILE);
+        const int grid = persistent_grid((const void*)pathsum_f32, 256, 0, tiles);
+        hipLaunchKernelGGL(pathsum_f32, dim3(grid), dim3(256), 0, st, (const float2*)A + row0, ldA, (const float2*)B,
+                           ldB, K, M, N, (float2*)out, ldo, accumulate, tn, tiles);
         return hip_check(hipGetLastError(), "pathsum_f32 launch");
     }
     if (dtype == HSF_C64 && mode == HSF_SUM_BF16X3)

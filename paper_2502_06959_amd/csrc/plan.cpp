@@ -439,12 +439,15 @@ void fuse_side(Plan& p, int s) {
 
 namespace {
 
+// Tile bits held in registers by one thread of a group (2^kGroupBits amplitudes).
+constexpr int kGroupBits = 3;
+
 // Turns the ops of one pass into device ops: runs of one-qubit gates (on at
 // most four tile bits) and diagonal gates (on any qubits) become one
 // register-resident group; wider dense ops and factor slots stand alone.
 void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::vector<int>& ids) {
     const int L = ps.n_local;
-    const int KG = std::min(4, L);
+    const int KG = std::min(kGroupBits, L);
     auto tbit = [&](int q) -> int {
         for (int l = 0; l < L; ++l)
             if (ps.local_q[l] == q) return l;

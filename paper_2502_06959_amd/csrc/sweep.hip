@@ -42,16 +42,37 @@ __device__ __forceinline__ V cfma(V a, V b, V c) {  // c + a*b
     return r;
 }
 
+// Device form of a group sub-op, with the 2x2 matrix (or the sign masks) in
+// the arithmetic type so a record is 64 bytes (c64) or 96 bytes (c128).
+template <typename T>
+struct DSub {
+    int32_t type;
+    int32_t g;
+    int32_t nc;
+    int32_t mat;
+    int32_t qb[4];
+    union {
+        T m[8];
+        uint32_t mask[8];
+    };
+};
+
 struct SideArgs {
     const Pass* pass;        // device copy of the pass record
     void* psi;
     int64_t ld;
     const DevOp* ops;
-    const SubOp* subs;
+    const void* subs;        // DSub<T>[]
     const void* pool;
     uint32_t n_tiles;
     uint32_t n_blocks;       // paths x tiles
 };
+
+// LDS position of tile element e: the low four index bits are XORed with the
+// next four, so that the 16 lanes that vary the lowest free bits of a
+// register group land on 16 distinct 8-byte bank pairs whatever the group's
+// bits are (a bijection on [0, 2^L) for every L).
+__device__ __forceinline__ uint32_t swz(uint32_t e) { return e ^ ((e >> 4) & 15u); }
 
 // Inserts a zero bit at position b of i.
 __device__ __forceinline__ uint32_t ins0(uint32_t i, int b) {
@@ -76,7 +97,7 @@ __device__ __forceinline__ void sort_bits(const int32_t* bit, int (&sb)[K]) {
 
 // Dense 2^K x 2^K matrix on tile bits bit[0..K) (bit[0] most significant).
 template <int K, typename V>
-__device__ __forceinline__ void apply_dense(V* tile, uint32_t E, const int32_t* bit, const V* __restrict__ m,
+__device__ __forceinline__ void apply_dense(V* tile, uint32_t E, const int32_t* bit, const V* m,
                                             int tid, int nt) {
     constexpr int D = 1 << K;
     int sb[K];
@@ -97,13 +118,13 @@ __device__ __forceinline__ void apply_dense(V* tile, uint32_t E, const int32_t* 
         for (int i = 0; i < K; ++i) base = ins0(base, sb[i]);
         V v[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = tile[base | off[j]];
+        for (int j = 0; j < D; ++j) v[j] = tile[swz(base | off[j])];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             V acc = cmul(m[r * D], v[0]);
 #pragma unroll
             for (int j = 1; j < D; ++j) acc = cfma(m[r * D + j], v[j], acc);
-            tile[base | off[r]] = acc;
+            tile[swz(base | off[r])] = acc;
         }
     }
 }
@@ -124,7 +145,7 @@ __device__ __forceinline__ void d1g(V (&v)[1 << K], V m00, V m01, V m10, V m11) 
 
 template <int K, typename T>
 __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E, const DevOp& op,
-                                            const SubOp* __restrict__ subs, const typename Cx<T>::v* __restrict__ pool,
+                                            const DSub<T>* __restrict__ subs, const typename Cx<T>::v* __restrict__ pool,
                                             uint64_t gbase, int tid, int nt) {
     using V = typename Cx<T>::v;
     constexpr int D = 1 << K;
@@ -147,16 +168,20 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
         for (int i = 0; i < K; ++i) base = ins0(base, sb[i]);
         V v[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = tile[base | off[j]];
+        for (int j = 0; j < D; ++j) v[j] = tile[swz(base | off[j])];
+        // software pipeline: the next record's scalar loads are issued before
+        // the current record is applied
+        DSub<T> cur = subs[s0];
         for (int s = s0; s < s0 + ns; ++s) {
-            const SubOp& so = subs[s];
+            const DSub<T> so = cur;
+            if (s + 1 < s0 + ns) cur = subs[s + 1];
             const int ty = so.type;
             if (ty == SUB_D1) {
                 V m00, m01, m10, m11;
-                m00.x = (T)so.m[0]; m00.y = (T)so.m[1];
-                m01.x = (T)so.m[2]; m01.y = (T)so.m[3];
-                m10.x = (T)so.m[4]; m10.y = (T)so.m[5];
-                m11.x = (T)so.m[6]; m11.y = (T)so.m[7];
+                m00.x = so.m[0]; m00.y = so.m[1];
+                m01.x = so.m[2]; m01.y = so.m[3];
+                m10.x = so.m[4]; m10.y = so.m[5];
+                m11.x = so.m[6]; m11.y = so.m[7];
                 switch (so.g) {
                     case 0: d1g<K, 0>(v, m00, m01, m10, m11); break;
                     case 1: d1g<K, 1>(v, m00, m01, m10, m11); break;
@@ -165,13 +190,19 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
                 }
             } else {
                 uint32_t c = 0;
-                for (int i = 0; i < so.nc; ++i) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (i >= so.nc) break;
                     const int b = so.qb[i];
                     const uint32_t bit = b >= 0 ? (base >> b) & 1u : (uint32_t)((gbase >> (-1 - b)) & 1u);
                     c |= bit << i;
                 }
                 if (ty == SUB_SIGN) {
-                    const uint32_t mask = (so.mask[c >> 1] >> ((c & 1u) * 16u)) & 0xffffu;
+                    // the 16 combos' masks are uniform; pick this group's by c
+                    uint32_t w = so.mask[0];
+#pragma unroll
+                    for (int q = 1; q < 8; ++q) w = ((c >> 1) == (uint32_t)q) ? so.mask[q] : w;
+                    const uint32_t mask = (w >> ((c & 1u) * 16u)) & 0xffffu;
 #pragma unroll
                     for (int j = 0; j < D; ++j)
                         if ((mask >> j) & 1u) {
@@ -186,19 +217,24 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
             }
         }
 #pragma unroll
-        for (int j = 0; j < D; ++j) tile[base | off[j]] = v[j];
+        for (int j = 0; j < D; ++j) tile[swz(base | off[j])] = v[j];
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void sweep_pass(SideArgs s0, SideArgs s1, int64_t p_begin) {
+template <typename T> struct Threads;
+template <> struct Threads<float> { static constexpr int max = 512; };
+template <> struct Threads<double> { static constexpr int max = 512; };
+
+// KG: register-group width (4 for every tile of four or more bits).
+template <typename T, int KG>
+__global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideArgs s1, int64_t p_begin) {
     using V = typename Cx<T>::v;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* tile = reinterpret_cast<V*>(smem_raw);
     const bool sd = blockIdx.x >= s0.n_blocks;
     const Pass* __restrict__ ps = sd ? s1.pass : s0.pass;
     const DevOp* __restrict__ ops = sd ? s1.ops : s0.ops;
-    const SubOp* __restrict__ subs = sd ? s1.subs : s0.subs;
+    const DSub<T>* __restrict__ subs = reinterpret_cast<const DSub<T>*>(sd ? s1.subs : s0.subs);
     const V* __restrict__ pool = reinterpret_cast<const V*>(sd ? s1.pool : s0.pool);
     const int64_t ld = sd ? s1.ld : s0.ld;
     const uint32_t n_tiles = sd ? s1.n_tiles : s0.n_tiles;
@@ -211,6 +247,7 @@ __global__ __launch_bounds__(1024) void sweep_pass(SideArgs s0, SideArgs s1, int
 
     const int L = ps->n_local;
     const uint32_t E = 1u << L;
+    V* mstage = tile + E;       // 256-entry matrix staging area after the tile
     uint64_t base = 0;
     const int nnl = ps->n_nonlocal;
     for (int i = 0; i < nnl; ++i) base |= (uint64_t)((t >> i) & 1u) << ps->nonlocal_q[i];
@@ -228,10 +265,10 @@ __global__ __launch_bounds__(1024) void sweep_pass(SideArgs s0, SideArgs s1, int
             V z;
             z.x = (e == 0 && base == 0) ? T(1) : T(0);
             z.y = T(0);
-            tile[e] = z;
+            tile[swz(e)] = z;
         }
     } else {
-        for (uint32_t e = tid; e < E; e += nt) tile[e] = st[gidx(e)];
+        for (uint32_t e = tid; e < E; e += nt) tile[swz(e)] = st[gidx(e)];
     }
     __syncthreads();
 
@@ -240,26 +277,26 @@ __global__ __launch_bounds__(1024) void sweep_pass(SideArgs s0, SideArgs s1, int
         const DevOp& op = ops[o];
         const int type = op.type;
         if (type == DOP_GROUP) {
-            switch (op.k) {
-                case 4: apply_group<4, T>(tile, E, op, subs, pool, base, tid, nt); break;
-                case 3: apply_group<3, T>(tile, E, op, subs, pool, base, tid, nt); break;
-                case 2: apply_group<2, T>(tile, E, op, subs, pool, base, tid, nt); break;
-                default: apply_group<1, T>(tile, E, op, subs, pool, base, tid, nt); break;
-            }
+            apply_group<KG, T>(tile, E, op, subs, pool, base, tid, nt);
         } else {
+            // dense factor or wide gate: its matrix goes through LDS so the
+            // 4^k uniform entries are read as broadcasts, not held in registers
             int32_t mat = op.mat;
             if (type == DOP_SLOT) mat += (int32_t)((path / op.stride) % op.rank) << (2 * op.k);
+            const int dd = 1 << (2 * op.k);
+            for (int i = tid; i < dd; i += nt) mstage[i] = pool[mat + i];
+            __syncthreads();
             switch (op.k) {
-                case 1: apply_dense<1>(tile, E, op.bit, pool + mat, tid, nt); break;
-                case 2: apply_dense<2>(tile, E, op.bit, pool + mat, tid, nt); break;
-                case 3: apply_dense<3>(tile, E, op.bit, pool + mat, tid, nt); break;
-                default: apply_dense<4>(tile, E, op.bit, pool + mat, tid, nt); break;
+                case 1: apply_dense<1>(tile, E, op.bit, mstage, tid, nt); break;
+                case 2: apply_dense<2>(tile, E, op.bit, mstage, tid, nt); break;
+                case 3: apply_dense<3>(tile, E, op.bit, mstage, tid, nt); break;
+                default: apply_dense<4>(tile, E, op.bit, mstage, tid, nt); break;
             }
         }
         __syncthreads();
     }
 
-    for (uint32_t e = tid; e < E; e += nt) st[gidx(e)] = tile[e];
+    for (uint32_t e = tid; e < E; e += nt) st[gidx(e)] = tile[swz(e)];
 }
 
 std::mutex g_dev_mutex;
@@ -276,7 +313,22 @@ hsf_status upload_schedule(const Schedule& sc, DeviceSchedule& d) {
     hsf_status s;
     if ((s = upload(sc.passes.data(), sc.passes.size() * sizeof(Pass), &d.passes)) != HSF_OK) return s;
     if ((s = upload(sc.devops.data(), sc.devops.size() * sizeof(DevOp), &d.ops)) != HSF_OK) return s;
-    if ((s = upload(sc.subs.data(), sc.subs.size() * sizeof(SubOp), &d.subs)) != HSF_OK) return s;
+    std::vector<DSub<T>> hs(sc.subs.size());
+    for (size_t i = 0; i < sc.subs.size(); ++i) {
+        const SubOp& so = sc.subs[i];
+        DSub<T>& o = hs[i];
+        std::memset(&o, 0, sizeof(o));
+        o.type = so.type;
+        o.g = so.g;
+        o.nc = so.nc;
+        o.mat = so.mat;
+        for (int j = 0; j < 4; ++j) o.qb[j] = so.qb[j];
+        if (so.type == SUB_SIGN)
+            for (int j = 0; j < 8; ++j) o.mask[j] = so.mask[j];
+        else
+            for (int j = 0; j < 8; ++j) o.m[j] = (T)so.m[j];
+    }
+    if ((s = upload(hs.data(), hs.size() * sizeof(DSub<T>), &d.subs)) != HSF_OK) return s;
     std::vector<V> h(sc.pool.size());
     for (size_t i = 0; i < sc.pool.size(); ++i) {
         h[i].x = (T)sc.pool[i].real();
@@ -286,6 +338,9 @@ hsf_status upload_schedule(const Schedule& sc, DeviceSchedule& d) {
 }
 
 bool g_attr_done[2] = {false, false};
+
+// Tile bits per register group; must match the planner's group width.
+constexpr int kGroupBits = 3;
 
 }  // namespace
 
@@ -317,11 +372,11 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
     }
     const int di = p.dtype == HSF_C128 ? 1 : 0;
     if (!g_attr_done[di]) {
-        const size_t bytes = (size_t(1) << max_tile_bits(p.dtype)) * (p.dtype == HSF_C128 ? 16 : 8);
+        const size_t bytes = ((size_t(1) << max_tile_bits(p.dtype)) + 256) * (p.dtype == HSF_C128 ? 16 : 8);
         if (p.dtype == HSF_C128)
-            s = hip_check(hipFuncSetAttribute((const void*)sweep_pass<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes), "hipFuncSetAttribute");
+            s = hip_check(hipFuncSetAttribute((const void*)sweep_pass<double, kGroupBits>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes), "hipFuncSetAttribute");
         else
-            s = hip_check(hipFuncSetAttribute((const void*)sweep_pass<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes), "hipFuncSetAttribute");
+            s = hip_check(hipFuncSetAttribute((const void*)sweep_pass<float, kGroupBits>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes), "hipFuncSetAttribute");
         if (s != HSF_OK) return s;
         g_attr_done[di] = true;
     }
@@ -342,6 +397,28 @@ void release_device(Plan& p) {
     (void)hipSetDevice(cur);
     p.dev.clear();
 }
+
+namespace {
+
+template <typename T>
+hsf_status launch_pass_t(int kg, uint32_t total, int threads, size_t shmem, hipStream_t stream, const SideArgs& a,
+                         const SideArgs& b, int64_t p0) {
+    switch (kg) {
+        case 4: hipLaunchKernelGGL((sweep_pass<T, 4>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
+        case 3: hipLaunchKernelGGL((sweep_pass<T, 3>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
+        case 2: hipLaunchKernelGGL((sweep_pass<T, 2>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
+        default: hipLaunchKernelGGL((sweep_pass<T, 1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
+    }
+    return hip_check(hipGetLastError(), "sweep_pass launch");
+}
+
+hsf_status launch_pass(bool dbl, int kg, uint32_t total, int threads, size_t shmem, hipStream_t stream,
+                       const SideArgs& a, const SideArgs& b, int64_t p0) {
+    return dbl ? launch_pass_t<double>(kg, total, threads, shmem, stream, a, b, p0)
+               : launch_pass_t<float>(kg, total, threads, shmem, stream, a, b, p0);
+}
+
+}  // namespace
 
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
                      void* psiB, int64_t ldB, hipStream_t stream) {
@@ -374,13 +451,20 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
             a[s].pass = reinterpret_cast<const Pass*>(ds.passes) + k;
             a[s].ld = ld[s];
             a[s].ops = (const DevOp*)ds.ops;
-            a[s].subs = (const SubOp*)ds.subs;
+            a[s].subs = ds.subs;
             a[s].pool = ds.pool;
             a[s].n_tiles = 1u << ps.n_nonlocal;
             emax = std::max(emax, 1u << ps.n_local);
         }
-        const int threads = (int)std::min<uint32_t>(dbl ? 512u : 1024u, std::max<uint32_t>(64u, emax / 16));
-        const size_t shmem = (size_t)emax * esz;
+        // group width: every group of a pass uses min(kGroupBits, L) bits (L = that side's tile)
+        int kg = kGroupBits;
+        for (int s = 0; s < 2; ++s)
+            if (a[s].pass) kg = std::min(kg, std::min(kGroupBits, sc[s]->passes[k].n_local));
+        bool kg_mixed = false;
+        for (int s = 0; s < 2; ++s)
+            if (a[s].pass && std::min(kGroupBits, sc[s]->passes[k].n_local) != kg) kg_mixed = true;
+        const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, emax >> kg));
+        const size_t shmem = ((size_t)emax + 256) * esz;
         for (int64_t p0 = 0; p0 < n_paths; p0 += max_paths) {
             const int64_t np = std::min(max_paths, n_paths - p0);
             SideArgs b[2] = {a[0], a[1]};
@@ -392,12 +476,20 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
             // a side with no pass this round contributes no workgroups
             const uint32_t total = b[0].n_blocks + b[1].n_blocks;
             if (total == 0) continue;
-            if (dbl)
-                hipLaunchKernelGGL(sweep_pass<double>, dim3(total), dim3(threads), shmem, stream, b[0], b[1], p_begin + p0);
-            else
-                hipLaunchKernelGGL(sweep_pass<float>, dim3(total), dim3(threads), shmem, stream, b[0], b[1], p_begin + p0);
-            hsf_status s = hip_check(hipGetLastError(), "sweep_pass launch");
-            if (s != HSF_OK) return s;
+            // sides with different group widths (a side narrower than four qubits) go in separate launches
+            for (int part = 0; part < (kg_mixed ? 2 : 1); ++part) {
+                SideArgs c[2] = {b[0], b[1]};
+                int kgp = kg;
+                if (kg_mixed) {
+                    c[1 - part].n_blocks = 0;
+                    c[1 - part].pass = nullptr;
+                    if (!c[part].pass) continue;
+                    kgp = std::min(kGroupBits, sc[part]->passes[k].n_local);
+                }
+                const uint32_t tot = c[0].n_blocks + c[1].n_blocks;
+                hsf_status s = launch_pass(dbl, kgp, tot, threads, shmem, stream, c[0], c[1], p_begin + p0);
+                if (s != HSF_OK) return s;
+            }
         }
     }
     return HSF_OK;
