@@ -2,13 +2,16 @@
 per-path half-state sweeps of both sides for all paths, then the path sum
 into every output amplitude -- over a seeded synthetic circuit.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2p] [--mode f32|bf16x3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2p] [--mode bf16x3|f32]
+    python bench.py --calibrate-copy      # a plain 1 GiB device copy, for counter scaling
 
 Prints one JSON line.  `value` is logical path-gate updates per second of
 the whole step (paths x circuit ops of both sides, Schmidt-factor slots
-included, divided by the step time); the path-sum TFLOP/s, the per-kernel
-times, the roofline of the dominant kernel and the FP64 oracle's throughput
-on the host (bounded sample) ride along.
+included, divided by the step time) with the chosen path sum (split-BF16
+x3); the same step with the plain FP32 path sum ("plain c64 HSF") is timed
+beside it.  The path-sum TFLOP/s, the per-phase times, the roofline of the
+dominant phase and the FP64 oracle's throughput on the host (bounded sample)
+ride along.
 """
 import argparse
 import hashlib
@@ -96,10 +99,23 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2p", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="f32", choices=["f32", "bf16x3"])
+    ap.add_argument("--mode", default="bf16x3", choices=["f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP32 path sum")
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_each_way": n * 4}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the build targets a single MI355X; multi-GPU path sharding is "
               "described in the design notes but not run. Use --gpus 1.", file=sys.stderr)
@@ -121,34 +137,54 @@ def main():
     sa, sb = plan.side_stats(0), plan.side_stats(1)
     A, B = plan.alloc_halves(P)
     out = torch.empty((1 << na, 1 << nb), dtype=torch.complex64, device="cuda")
-    ws = None
-    if args.mode == "bf16x3":
-        from paper_2502_06959_amd import hsf_workspace_size
-        ws = torch.empty(hsf_workspace_size(plan.handle, 1, P, 1), dtype=torch.uint8, device="cuda")
 
-    def step(ev=None):
-        if ev:
-            ev[0].record()
-        plan.run_paths(0, P, A, B)
-        if ev:
-            ev[1].record()
-        plan.amplitudes_full(A, B, mode=args.mode, out=out, ws=ws)
-        if ev:
-            ev[2].record()
+    def run_mode(mode, steps, warmup):
+        ws = None
+        if mode == "bf16x3":
+            from paper_2502_06959_amd import hsf_workspace_size
+            ws = torch.empty(hsf_workspace_size(plan.handle, 1, P, 1), dtype=torch.uint8, device="cuda")
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sweep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    sum_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    ms_step = wall * 1e3 / args.steps
+        def step(ev=None):
+            if ev:
+                ev[0].record()
+            plan.run_paths(0, P, A, B)
+            if ev:
+                ev[1].record()
+            plan.amplitudes_full(A, B, mode=mode, out=out, ws=ws)
+            if ev:
+                ev[2].record()
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(evs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sweep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+        sum_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+        rel = None
+        if not args.no_check:
+            from oracle import hsf as ohsf
+            if "oracle" not in cache:
+                o = ohsf.plan(circuit)
+                cache["oracle"] = (ohsf.half_states(circuit, o, "A"), ohsf.half_states(circuit, o, "B"))
+            oa, ob = cache["oracle"]
+            rows = np.random.default_rng(7).choice(1 << na, 32, replace=False)
+            got = out[torch.from_numpy(rows).to("cuda")].cpu().numpy()
+            rel = ohsf.rel_l2(got, ohsf.amplitudes_rows(oa, ob, rows))
+        return wall * 1e3 / steps, sweep_ms, sum_ms, rel
+
+    cache = {}
+    plain = None
+    if not args.no_plain and args.mode != "f32":
+        p_ms, p_sw, p_sum, p_rel = run_mode("f32", args.steps, args.warmup)
+        plain = {"path_sum": "f32", "ms_per_step": p_ms, "breakdown_ms": {"sweeps": p_sw, "path_sum": p_sum},
+                 "rel_l2_sampled_rows": p_rel}
+    ms_step, sweep_ms, sum_ms, rel = run_mode(args.mode, args.steps, args.warmup)
 
     logical_updates = P * (sa["ops_logical"] + sb["ops_logical"])
     flops = 8.0 * (1 << na) * (1 << nb) * P
@@ -158,8 +194,10 @@ def main():
 
     # dominant kernel roofline
     if sum_ms >= sweep_ms:
-        src = _src_hash("pathsum.hip", "bf16x3.hip")
-        kern = "pathsum_f32" if args.mode == "f32" else "pathsum_bf16x3"
+        src = _src_hash("pathsum.hip", "bf16x3.hip", "epilogue.h")
+        # the timed path-sum call: one MFMA kernel (FP32), or the two split
+        # passes plus the MFMA kernel (split-BF16 x3)
+        kern = "pathsum_f32" if args.mode == "f32" else "split_planes x2 + pathsum_bf16x3_kernel"
         ach_tf = flops / (sum_ms * 1e-3) / 1e12
         if args.mode == "f32":
             bound, peak, unit, achieved = "mfma", MFMA_PEAK["f32"], "TFLOP/s", ach_tf
@@ -175,28 +213,21 @@ def main():
         traffic = _traffic_from_profiles(kern, src)
     else:
         src = _src_hash("sweep.hip")
-        kern = "sweep_pass<float>"
-        # every op of a single-pass sweep works on-chip; the bound is the VALU
-        # (non-packed FP32: 256 CU x 64 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s)
-        fl = P * 8.0 * 16 * ((1 << na) * sa["ops_fused"] + (1 << nb) * sb["ops_fused"]) / 2
+        kern = "sweep_pass<float> (all passes)"
+        # ops are applied on-chip; the bound is the VALU (non-packed FP32:
+        # 256 CU x 64 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s); a one-qubit
+        # gate costs 14 flop per amplitude
+        fl = P * 14.0 * ((1 << na) * sa["ops_fused"] + (1 << nb) * sb["ops_fused"])
         bound, peak, unit = "alu", 78.6, "TFLOP/s"
         achieved = fl / (sweep_ms * 1e-3) / 1e12
         traffic = _traffic_from_profiles(kern, src)
-
-    rel = None
-    if not args.no_check:
-        from oracle import hsf as ohsf
-        o = ohsf.plan(circuit)
-        oa, ob = ohsf.half_states(circuit, o, "A"), ohsf.half_states(circuit, o, "B")
-        rows = np.random.default_rng(7).choice(1 << na, 32, replace=False)
-        got = out[torch.from_numpy(rows).to("cuda")].cpu().numpy()
-        rel = ohsf.rel_l2(got, ohsf.amplitudes_rows(oa, ob, rows))
 
     res = {
         "metric": "path-gate updates/s (%HBM peak) + path-sum TFLOP/s; vs plain c64 HSF at rel-L2<=1e-5",
         "value": value, "unit": "path-gate updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64 (f32)", "data": "synthetic",
+        "vs_baseline": None, "dtype": "c64 (f32 sweeps, " + ("split-bf16x3" if args.mode == "bf16x3" else "f32") + " path sum)",
+        "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "paths": P, "n": plan.n, "cut": f"{nb}|{na}",
                    "path_sum": args.mode, "ops_logical": [sa["ops_logical"], sb["ops_logical"]],
                    "ops_fused": [sa["ops_fused"], sb["ops_fused"]], "passes": [sa["passes"], sb["passes"]]},
@@ -205,6 +236,8 @@ def main():
         "sweep_updates_per_s": logical_updates / (sweep_ms * 1e-3),
         "sweep_hbm_equiv_pct": 100.0 * logical_updates * 2 * 8 * (1 << max(na, nb)) / (sweep_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "rel_l2_sampled_rows": rel,
+        "plain_c64_hsf": None if plain is None else {**plain, "value": logical_updates / (plain["ms_per_step"] * 1e-3),
+                                                     "speedup_of_chosen": plain["ms_per_step"] / ms_step},
         "roofline": {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": traffic},
     }
