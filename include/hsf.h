@@ -161,7 +161,9 @@ hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical,
 /* --------------------------------------------------------------- paths ---- */
 
 /* Device workspace in bytes for `op` over `n_paths` paths:
- *   op 0 = hsf_run_paths, 1 = hsf_amplitudes_full, 2 = hsf_backward.         */
+ *   op 0 = hsf_run_paths (none), 1 = hsf_amplitudes_full with path-sum mode
+ *   `mode`, 2 = hsf_backward with chunks of `n_paths` paths and `mode` =
+ *   number of bitstrings n_x.                                                  */
 size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t mode);
 
 /* Per-path half-states for paths [p_begin, p_end) (Sec. II-B): row j of
@@ -205,11 +207,19 @@ hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dt
 
 /* ------------------------------------------------------------ gradient ---- */
 
-/* Gradient of L = sum_j |psi(x_j)|^2 over the n_x basis states x (device),
- * with respect to every parameter id of the circuit's RX/RY/RZ/RZZ/PHASE/CP
- * gates.  grad: device doubles, one per parameter id (0..max id), overwritten.
- * Recomputes half-states per path chunk; ws: hsf_workspace_size(plan, 2,
- * chunk, 0) bytes for a chunk of `chunk` paths.                               */
+/* Gradient of the probability mass L = sum_j |psi(x_j)|^2 of n_x basis
+ * states x (device array) with respect to every parameter id (0..n_params-1)
+ * of the circuit's rotation gates (RX, RY, RZ, RZZ; PHASE and CP outside
+ * blocks).  psi is the HSF state of Sec. II-B; d psi/d t follows from the
+ * chain rule through the per-path half-states.  Angles outside blocks use an
+ * adjoint sweep per path (state checkpointed in front of each Schmidt factor,
+ * which has no inverse); angles inside a block use the exact parameter-shift
+ * rule with the block re-factored (Sec. IV-A) at t +- pi/2.  grad: n_params
+ * device doubles, overwritten.  Paths are processed `chunk` at a time; ws:
+ * hsf_workspace_size(plan, 2, chunk, n_x) bytes.  Reductions run in a fixed
+ * order (bitwise reproducible).  Synchronises `stream` (host tables are
+ * staged through it), so it cannot be captured in a graph.  Returns
+ * HSF_E_UNSUPPORTED if a shifted block needs more Schmidt terms than the plan. */
 hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* grad,
                         int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes,
                         hsf_stream_t stream);

@@ -17,6 +17,8 @@ hsf_status fail(hsf_status s, const std::string& msg) {
     return s;
 }
 
+std::string g_last_error_copy() { return g_last_error; }
+
 }  // namespace hsf
 
 using namespace hsf;
@@ -140,7 +142,7 @@ size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t 
     if (!plan || n_paths < 0) return 0;
     const Plan* p = P_(plan);
     if (op == 1 && mode == HSF_SUM_BF16X3) return bf16x3_workspace(p->na, p->nb, n_paths);
-    if (op == 2) return backward_workspace(*p, n_paths);
+    if (op == 2) return backward_workspace(*p, n_paths, mode);
     return 0;
 }
 
@@ -217,7 +219,8 @@ hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double*
     Plan* p = P_(plan);
     if (n_params < p->n_params) return fail(HSF_E_ARG, "grad has fewer slots than the circuit's parameter ids");
     if (chunk <= 0) return fail(HSF_E_ARG, "chunk must be positive");
-    if (ws_bytes < backward_workspace(*p, chunk)) return fail(HSF_E_ARG, "workspace too small");
+    if (n_x < 0) return fail(HSF_E_ARG, "negative bitstring count");
+    if (ws_bytes < backward_workspace(*p, chunk, n_x)) return fail(HSF_E_ARG, "workspace too small");
     DeviceCopy* d = nullptr;
     hsf_status s = ensure_device(*p, &d);
     if (s != HSF_OK) return s;

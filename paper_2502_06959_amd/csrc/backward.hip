@@ -1,21 +1,759 @@
-// Adjoint gradient of a probability-mass loss (placeholder).
+// Gradient of L = sum_j |psi(x_j)|^2 with respect to rotation angles.
+//
+// psi(x) = sum_p a_p[x_a] b_p[x_b] (Sec. II-B), so for an angle t of a gate
+// outside every block, on side a,
+//   dL/dt = 2 Re sum_p ( w_p , da_p/dt ),  w_p[y] = sum_{j: x_j,a = y} conj(psi(x_j)) b_p[x_j,b]
+// with the bilinear pairing (u, v) = sum_y u[y] v[y] (side b symmetric).  With
+// a_p = V U(t) V' |0>, da_p/dt = V D U V' |0> for dU/dt = D U, and
+// (w, V D s) = (V^T w, D s): the adjoint lambda = V^T w is carried backwards
+// through the side program (lambda <- M^T lambda), the state s backwards by
+// the inverse of each gate (s <- M^dagger s).  Schmidt factors are not
+// invertible, so the forward pass keeps a checkpoint of the state in front of
+// every factor slot and the backward pass restores it there.
+//
+// Angles inside a block's hull change the block operator and with it the SVD;
+// they use the parameter-shift rule on the block: every gate here is
+// exp(-i t P / 2), so dL/dt = [L(t + pi/2) - L(t - pi/2)] / 2, each L a full
+// forward with that block re-factored.
+//
+// Every reduction runs in a fixed order (no atomics), so results are
+// bitwise reproducible.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "device.h"
 
 namespace hsf {
 
-size_t backward_workspace(const Plan& p, int64_t chunk) {
-    (void)p;
-    (void)chunk;
-    return 0;
+namespace {
+
+template <typename T> struct Cx;
+template <> struct Cx<float> { using v = float2; };
+template <> struct Cx<double> { using v = double2; };
+
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) {
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
 }
+
+__device__ __forceinline__ uint64_t ins0(uint64_t i, int b) {
+    const uint64_t lo = i & ((uint64_t(1) << b) - 1);
+    return ((i >> b) << (b + 1)) | lo;
+}
+
+struct Bits {
+    int32_t b[4];
+};
+
+template <int K>
+__device__ __forceinline__ void group_offsets(const Bits& bits, uint64_t g, uint64_t (&idx)[1 << K]) {
+    int sb[K];
+    for (int i = 0; i < K; ++i) sb[i] = bits.b[i];
+    for (int i = 0; i < K; ++i)
+        for (int j = i + 1; j < K; ++j)
+            if (sb[j] < sb[i]) {
+                const int t = sb[i];
+                sb[i] = sb[j];
+                sb[j] = t;
+            }
+    uint64_t base = g;
+    for (int i = 0; i < K; ++i) base = ins0(base, sb[i]);
+#pragma unroll
+    for (int j = 0; j < (1 << K); ++j) {
+        uint64_t o = base;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((j >> (K - 1 - i)) & 1) o |= uint64_t(1) << bits.b[i];
+        idx[j] = o;
+    }
+}
+
+// x <- M x on every row, M = mats + ((p_begin + row) / stride % rank) * D^2.
+// Grid: rows x blocks_per_row; a block works inside one row.
+template <int K, typename T>
+__global__ __launch_bounds__(256) void bw_apply(typename Cx<T>::v* __restrict__ x, int64_t ld, int nq, Bits bits,
+                                                const typename Cx<T>::v* __restrict__ mats, int rank, int64_t stride,
+                                                int64_t p_begin, uint32_t blocks_per_row) {
+    using V = typename Cx<T>::v;
+    constexpr int D = 1 << K;
+    __shared__ V m[D * D];
+    const uint32_t row = blockIdx.x / blocks_per_row;
+    const uint32_t blk = blockIdx.x - row * blocks_per_row;
+    const int sel = rank > 1 ? (int)(((p_begin + row) / stride) % rank) : 0;
+    for (int i = threadIdx.x; i < D * D; i += blockDim.x) m[i] = mats[sel * D * D + i];
+    __syncthreads();
+    const uint64_t groups = uint64_t(1) << (nq - K);
+    const uint64_t g = (uint64_t)blk * blockDim.x + threadIdx.x;
+    if (g >= groups) return;
+    V* r = x + (int64_t)row * ld;
+    uint64_t idx[D];
+    group_offsets<K>(bits, g, idx);
+    V v[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) v[j] = r[idx[j]];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        V acc;
+        acc.x = 0;
+        acc.y = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const V t = cmul(m[i * D + j], v[j]);
+            acc.x += t.x;
+            acc.y += t.y;
+        }
+        r[idx[i]] = acc;
+    }
+}
+
+// s <- Ms s and l <- Ml l on every row (one unitary gate undone; adjoint moved back).
+template <int K, typename T>
+__global__ __launch_bounds__(256) void bw_apply2(typename Cx<T>::v* __restrict__ s, typename Cx<T>::v* __restrict__ l,
+                                                 int64_t ld, int nq, Bits bits, const typename Cx<T>::v* __restrict__ ms,
+                                                 const typename Cx<T>::v* __restrict__ ml, uint32_t blocks_per_row) {
+    using V = typename Cx<T>::v;
+    constexpr int D = 1 << K;
+    __shared__ V m1[D * D], m2[D * D];
+    for (int i = threadIdx.x; i < D * D; i += blockDim.x) {
+        m1[i] = ms[i];
+        m2[i] = ml[i];
+    }
+    __syncthreads();
+    const uint32_t row = blockIdx.x / blocks_per_row;
+    const uint32_t blk = blockIdx.x - row * blocks_per_row;
+    const uint64_t groups = uint64_t(1) << (nq - K);
+    const uint64_t g = (uint64_t)blk * blockDim.x + threadIdx.x;
+    if (g >= groups) return;
+    uint64_t idx[D];
+    group_offsets<K>(bits, g, idx);
+    for (int w = 0; w < 2; ++w) {
+        V* r = (w ? l : s) + (int64_t)row * ld;
+        const V* m = w ? m2 : m1;
+        V v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = r[idx[j]];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            V acc;
+            acc.x = 0;
+            acc.y = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const V t = cmul(m[i * D + j], v[j]);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            r[idx[i]] = acc;
+        }
+    }
+}
+
+// partial[row] = sum_y l[y] (Dg s)[y]   (FP64; one block per row, fixed order)
+template <int K, typename T>
+__global__ __launch_bounds__(256) void bw_grad_dot(const typename Cx<T>::v* __restrict__ s,
+                                                   const typename Cx<T>::v* __restrict__ l, int64_t ld, int nq,
+                                                   Bits bits, const typename Cx<T>::v* __restrict__ dg,
+                                                   double2* __restrict__ partial) {
+    using V = typename Cx<T>::v;
+    constexpr int D = 1 << K;
+    __shared__ V m[D * D];
+    __shared__ double rr[256], ri[256];
+    for (int i = threadIdx.x; i < D * D; i += blockDim.x) m[i] = dg[i];
+    __syncthreads();
+    const int64_t row = blockIdx.x;
+    const V* sr = s + row * ld;
+    const V* lr = l + row * ld;
+    const uint64_t groups = uint64_t(1) << (nq - K);
+    double accr = 0.0, acci = 0.0;
+    for (uint64_t g = threadIdx.x; g < groups; g += blockDim.x) {
+        uint64_t idx[D];
+        group_offsets<K>(bits, g, idx);
+        V v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = sr[idx[j]];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double tr = 0.0, ti = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const V t = cmul(m[i * D + j], v[j]);
+                tr += (double)t.x;
+                ti += (double)t.y;
+            }
+            const V lv = lr[idx[i]];
+            accr += (double)lv.x * tr - (double)lv.y * ti;
+            acci += (double)lv.x * ti + (double)lv.y * tr;
+        }
+    }
+    rr[threadIdx.x] = accr;
+    ri[threadIdx.x] = acci;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            rr[threadIdx.x] += rr[threadIdx.x + w];
+            ri[threadIdx.x] += ri[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[row] = make_double2(rr[0], ri[0]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bw_fill(typename Cx<T>::v* __restrict__ x, int64_t ld, int64_t dim, int64_t rows,
+                                               int one_at_zero) {
+    const int64_t n = rows * dim;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / dim, c = i - r * dim;
+        typename Cx<T>::v z;
+        z.x = (one_at_zero && c == 0) ? T(1) : T(0);
+        z.y = T(0);
+        x[r * ld + c] = z;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bw_copy_rows(const typename Cx<T>::v* __restrict__ src, int64_t lds,
+                                                    typename Cx<T>::v* __restrict__ dst, int64_t ldd, int64_t dim,
+                                                    int64_t rows) {
+    const int64_t n = rows * dim;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / dim, c = i - r * dim;
+        dst[r * ldd + c] = src[r * lds + c];
+    }
+}
+
+// lam[row][gidx[g]] = sum_{t in [off[g], off[g+1])} conj(psi_x[jj[t]]) other[row][oidx[jj[t]]]
+template <typename T>
+__global__ __launch_bounds__(256) void bw_cotangent(const typename Cx<T>::v* __restrict__ other, int64_t ldo,
+                                                    typename Cx<T>::v* __restrict__ lam, int64_t ldl,
+                                                    const int64_t* __restrict__ off, const int64_t* __restrict__ jj,
+                                                    const int64_t* __restrict__ gidx, const int64_t* __restrict__ oidx,
+                                                    const double2* __restrict__ psi_x, int64_t ngroups,
+                                                    uint32_t blocks_per_row) {
+    const uint32_t row = blockIdx.x / blocks_per_row;
+    const int64_t g = (int64_t)(blockIdx.x - row * blocks_per_row) * blockDim.x + threadIdx.x;
+    if (g >= ngroups) return;
+    double sr = 0.0, si = 0.0;
+    for (int64_t t = off[g]; t < off[g + 1]; ++t) {
+        const int64_t j = jj[t];
+        const double2 c = psi_x[j];
+        const auto o = other[(int64_t)row * ldo + oidx[j]];
+        // conj(c) * o
+        sr += c.x * (double)o.x + c.y * (double)o.y;
+        si += c.x * (double)o.y - c.y * (double)o.x;
+    }
+    typename Cx<T>::v v;
+    v.x = (T)sr;
+    v.y = (T)si;
+    lam[(int64_t)row * ldl + gidx[g]] = v;
+}
+
+// grad[t] += sum over occurrences of t, over rows, of 2 Re partial[occ][row]
+__global__ void bw_reduce(const double2* __restrict__ partial, int64_t stride, int64_t rows,
+                          const int64_t* __restrict__ occ_off, const int64_t* __restrict__ occ, int64_t n_params,
+                          double* __restrict__ grad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_params) return;
+    double acc = 0.0;
+    for (int64_t i = occ_off[t]; i < occ_off[t + 1]; ++i) {
+        const double2* p = partial + occ[i] * stride;
+        for (int64_t r = 0; r < rows; ++r) acc += 2.0 * p[r].x;
+    }
+    grad[t] += acc;
+}
+
+__global__ void bw_zero_doubles(double* __restrict__ a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
+// out = sum_j |amp_j|^2 in a fixed order (one block)
+__global__ __launch_bounds__(256) void bw_loss(const double2* __restrict__ amp, int64_t n, double* __restrict__ out) {
+    __shared__ double r[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += amp[i].x * amp[i].x + amp[i].y * amp[i].y;
+    r[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = r[0];
+}
+
+__global__ void bw_shift_combine(const double* __restrict__ lp, const double* __restrict__ lm, double* __restrict__ grad,
+                                 int64_t t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) grad[t] += 0.5 * (*lp - *lm);
+}
+
+// ---------------------------------------------------------------- host ----
+
+struct Layout {
+    size_t vA, vB, lA, lB, ckA, ckB, psi_x, psi_s, loss, partial, tables, mats, pools, total;
+    int64_t dimA, dimB;
+    int ka, kb;            // checkpoints per side
+    int64_t n_occ;         // parametrised ops outside blocks, both sides
+    size_t table_elems, mat_elems, pool_elems;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t side_mat_elems(const SideProgram& sp) {
+    size_t e = 0;
+    for (const SideOp& o : sp.raw) {
+        const size_t d2 = (size_t)1 << (2 * o.k);
+        if (o.kind == SideOp::SLOT) e += 2 * o.rank * d2;      // factors and their transposes
+        else e += 3 * d2 + (o.param_id >= 0 ? d2 : 0);         // M, M^dagger, M^T (+ D)
+    }
+    return e;
+}
+
+Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
+    Layout L{};
+    const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
+    L.dimA = int64_t(1) << p.na;
+    L.dimB = int64_t(1) << p.nb;
+    L.ka = L.kb = 0;
+    for (const Block& b : p.blocks) {
+        L.ka += !b.sa.empty();
+        L.kb += !b.sb.empty();
+    }
+    L.n_occ = 0;
+    for (int s = 0; s < 2; ++s)
+        for (const SideOp& o : p.side[s].raw) L.n_occ += o.param_id >= 0;
+    L.table_elems = 2 * (size_t)(4 * nx + 1) + (size_t)(p.n_params + 1) + (size_t)L.n_occ;
+    L.mat_elems = side_mat_elems(p.side[0]) + side_mat_elems(p.side[1]);
+    L.pool_elems = 0;
+    for (int s = 0; s < 2; ++s)
+        for (const Schedule& sc : p.side[s].sched) L.pool_elems += std::max<size_t>(sc.pool.size(), 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.vA = take((size_t)chunk * L.dimA * esz);
+    L.vB = take((size_t)chunk * L.dimB * esz);
+    L.lA = take((size_t)chunk * L.dimA * esz);
+    L.lB = take((size_t)chunk * L.dimB * esz);
+    L.ckA = take((size_t)L.ka * chunk * L.dimA * esz);
+    L.ckB = take((size_t)L.kb * chunk * L.dimB * esz);
+    L.psi_x = take((size_t)nx * 16);
+    L.psi_s = take((size_t)nx * 16);
+    L.loss = take(4 * sizeof(double));
+    L.partial = take((size_t)std::max<int64_t>(L.n_occ, 1) * chunk * 16);
+    L.tables = take(L.table_elems * sizeof(int64_t));
+    L.mats = take(L.mat_elems * esz);
+    L.pools = take(L.pool_elems * esz);
+    L.total = o + 256;
+    return L;
+}
+
+template <typename T>
+void to_dev(const std::vector<cd>& h, std::vector<typename Cx<T>::v>& out) {
+    out.resize(h.size());
+    for (size_t i = 0; i < h.size(); ++i) {
+        out[i].x = (T)h[i].real();
+        out[i].y = (T)h[i].imag();
+    }
+}
+
+std::vector<cd> dense_of(const SideOp& o) {
+    const int d = 1 << o.k;
+    if (o.kind != SideOp::DIAG) return std::vector<cd>(o.m.begin(), o.m.begin() + (size_t)d * d);
+    std::vector<cd> m((size_t)d * d, cd(0));
+    for (int i = 0; i < d; ++i) m[(size_t)i * d + i] = o.m[i];
+    return m;
+}
+
+std::vector<cd> adjoint_of(const std::vector<cd>& m, int d) {
+    std::vector<cd> r((size_t)d * d);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) r[(size_t)i * d + j] = std::conj(m[(size_t)j * d + i]);
+    return r;
+}
+
+std::vector<cd> transpose_of(const std::vector<cd>& m, int d) {
+    std::vector<cd> r((size_t)d * d);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) r[(size_t)i * d + j] = m[(size_t)j * d + i];
+    return r;
+}
+
+// Offsets (in complex elements, inside the backward matrix area) of each raw op's matrices.
+struct OpMats {
+    size_t fwd, inv, tr, dg;
+};
+
+template <typename T>
+struct Runner {
+    using V = typename Cx<T>::v;
+    const Plan& p;
+    hipStream_t st;
+
+    template <typename F>
+    hsf_status dispatch_k(int k, F f) {
+        switch (k) {
+            case 1: return f(std::integral_constant<int, 1>());
+            case 2: return f(std::integral_constant<int, 2>());
+            case 3: return f(std::integral_constant<int, 3>());
+            default: return f(std::integral_constant<int, 4>());
+        }
+    }
+
+    static Bits bits_of(const SideOp& o) {
+        Bits b{};
+        for (int i = 0; i < o.k; ++i) b.b[i] = o.q[i];
+        return b;
+    }
+
+    hsf_status apply(V* x, int64_t ld, int64_t rows, int nq, const SideOp& o, const V* mats, int rank,
+                     int64_t stride, int64_t p_begin) {
+        const uint64_t groups = uint64_t(1) << (nq - o.k);
+        const uint32_t bpr = (uint32_t)((groups + 255) / 256);
+        return dispatch_k(o.k, [&](auto kk) {
+            constexpr int K = decltype(kk)::value;
+            hipLaunchKernelGGL((bw_apply<K, T>), dim3((uint32_t)(rows * bpr)), dim3(256), 0, st, x, ld, nq, bits_of(o),
+                               mats, rank, stride, p_begin, bpr);
+            return hip_check(hipGetLastError(), "bw_apply launch");
+        });
+    }
+
+    hsf_status apply2(V* s, V* l, int64_t ld, int64_t rows, int nq, const SideOp& o, const V* ms, const V* ml) {
+        const uint64_t groups = uint64_t(1) << (nq - o.k);
+        const uint32_t bpr = (uint32_t)((groups + 255) / 256);
+        return dispatch_k(o.k, [&](auto kk) {
+            constexpr int K = decltype(kk)::value;
+            hipLaunchKernelGGL((bw_apply2<K, T>), dim3((uint32_t)(rows * bpr)), dim3(256), 0, st, s, l, ld, nq,
+                               bits_of(o), ms, ml, bpr);
+            return hip_check(hipGetLastError(), "bw_apply2 launch");
+        });
+    }
+
+    hsf_status grad_dot(const V* s, const V* l, int64_t ld, int64_t rows, int nq, const SideOp& o, const V* dg,
+                        double2* partial) {
+        return dispatch_k(o.k, [&](auto kk) {
+            constexpr int K = decltype(kk)::value;
+            hipLaunchKernelGGL((bw_grad_dot<K, T>), dim3((uint32_t)rows), dim3(256), 0, st, s, l, ld, nq, bits_of(o),
+                               dg, partial);
+            return hip_check(hipGetLastError(), "bw_grad_dot launch");
+        });
+    }
+
+    hsf_status fill(V* x, int64_t ld, int64_t dim, int64_t rows, int one) {
+        const int64_t n = rows * dim;
+        const uint32_t g = (uint32_t)std::min<int64_t>(65536, (n + 255) / 256);
+        hipLaunchKernelGGL(bw_fill<T>, dim3(std::max(g, 1u)), dim3(256), 0, st, x, ld, dim, rows, one);
+        return hip_check(hipGetLastError(), "bw_fill launch");
+    }
+
+    hsf_status copy_rows(const V* src, int64_t lds, V* dst, int64_t ldd, int64_t dim, int64_t rows) {
+        const int64_t n = rows * dim;
+        const uint32_t g = (uint32_t)std::min<int64_t>(65536, (n + 255) / 256);
+        hipLaunchKernelGGL(bw_copy_rows<T>, dim3(std::max(g, 1u)), dim3(256), 0, st, src, lds, dst, ldd, dim, rows);
+        return hip_check(hipGetLastError(), "bw_copy_rows launch");
+    }
+};
+
+template <typename T>
+hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, double* grad, int64_t n_params,
+                      int64_t chunk, void* ws, size_t ws_bytes, hipStream_t st) {
+    using V = typename Cx<T>::v;
+    const Layout Lo = layout(p, chunk, nx);
+    if (ws_bytes < Lo.total) return fail(HSF_E_ARG, "workspace too small for hsf_backward");
+    unsigned char* base = reinterpret_cast<unsigned char*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    V* vS[2] = {(V*)(base + Lo.vA), (V*)(base + Lo.vB)};
+    V* lS[2] = {(V*)(base + Lo.lA), (V*)(base + Lo.lB)};
+    V* ck[2] = {(V*)(base + Lo.ckA), (V*)(base + Lo.ckB)};
+    double2* psi_x = (double2*)(base + Lo.psi_x);
+    double2* psi_s = (double2*)(base + Lo.psi_s);
+    double* lossb = (double*)(base + Lo.loss);
+    double2* partial = (double2*)(base + Lo.partial);
+    int64_t* tables = (int64_t*)(base + Lo.tables);
+    V* mats = (V*)(base + Lo.mats);
+    V* pools = (V*)(base + Lo.pools);
+    const int64_t dim[2] = {Lo.dimA, Lo.dimB};
+    const int nq[2] = {p.na, p.nb};
+    hsf_status s;
+
+    // ---- host tables: bitstring groups per side, parameter occurrences
+    std::vector<uint64_t> hx((size_t)std::max<int64_t>(nx, 1));
+    if (nx > 0) {
+        if ((s = hip_check(hipMemcpyAsync(hx.data(), x, nx * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy x")) != HSF_OK)
+            return s;
+        if ((s = hip_check(hipStreamSynchronize(st), "sync")) != HSF_OK) return s;
+    }
+    const uint64_t maskn = p.n >= 64 ? ~uint64_t(0) : ((uint64_t(1) << p.n) - 1);
+    const uint64_t maskb = (uint64_t(1) << p.nb) - 1;
+    std::vector<int64_t> ht(Lo.table_elems, 0);
+    int64_t ngroups[2] = {0, 0};
+    size_t toff[2][4];   // off, jj, gidx, oidx
+    {
+        size_t o = 0;
+        for (int side = 0; side < 2; ++side) {
+            std::vector<std::pair<int64_t, int64_t>> key(nx);   // (own index, j)
+            for (int64_t j = 0; j < nx; ++j) {
+                const uint64_t xj = hx[j] & maskn;
+                const int64_t own = side == 0 ? (int64_t)(xj >> p.nb) : (int64_t)(xj & maskb);
+                key[j] = {own, j};
+            }
+            std::sort(key.begin(), key.end());
+            toff[side][0] = o;
+            toff[side][1] = o + nx + 1;
+            toff[side][2] = o + 2 * nx + 1;
+            toff[side][3] = o + 3 * nx + 1;
+            int64_t ng = 0;
+            for (int64_t t = 0; t < nx; ++t) {
+                if (t == 0 || key[t].first != key[t - 1].first) {
+                    ht[toff[side][0] + ng] = t;
+                    ht[toff[side][2] + ng] = key[t].first;
+                    ++ng;
+                }
+                ht[toff[side][1] + t] = key[t].second;
+            }
+            ht[toff[side][0] + ng] = nx;
+            ngroups[side] = ng;
+            for (int64_t j = 0; j < nx; ++j) {
+                const uint64_t xj = hx[j] & maskn;
+                ht[toff[side][3] + j] = side == 0 ? (int64_t)(xj & maskb) : (int64_t)(xj >> p.nb);
+            }
+            o += 4 * (size_t)nx + 1;
+        }
+        // occurrences: param id -> raw-op occurrence numbers (side a first, program order)
+        const size_t occ_off = o, occ_list = o + (size_t)p.n_params + 1;
+        std::vector<std::vector<int64_t>> per(p.n_params);
+        int64_t occ = 0;
+        for (int side = 0; side < 2; ++side)
+            for (const SideOp& op : p.side[side].raw)
+                if (op.param_id >= 0) per[op.param_id].push_back(occ++);
+        int64_t w = 0;
+        for (int64_t t = 0; t < p.n_params; ++t) {
+            ht[occ_off + t] = w;
+            for (int64_t q : per[t]) ht[occ_list + w++] = q;
+        }
+        ht[occ_off + p.n_params] = w;
+        if ((s = hip_check(hipMemcpyAsync(tables, ht.data(), ht.size() * sizeof(int64_t), hipMemcpyHostToDevice, st),
+                           "upload tables")) != HSF_OK)
+            return s;
+    }
+    const int64_t* occ_off_d = tables + 2 * (4 * nx + 1);
+    const int64_t* occ_d = occ_off_d + p.n_params + 1;
+
+    // ---- matrices of the raw side programs
+    std::vector<std::vector<OpMats>> om(2);
+    std::vector<cd> hm;
+    hm.reserve(Lo.mat_elems);
+    for (int side = 0; side < 2; ++side)
+        for (const SideOp& o : p.side[side].raw) {
+            const int dd = 1 << o.k;
+            OpMats m{};
+            if (o.kind == SideOp::SLOT) {
+                m.fwd = hm.size();
+                hm.insert(hm.end(), o.m.begin(), o.m.end());
+                m.tr = hm.size();
+                for (int r = 0; r < o.rank; ++r) {
+                    std::vector<cd> f(o.m.begin() + (size_t)r * dd * dd, o.m.begin() + (size_t)(r + 1) * dd * dd);
+                    const std::vector<cd> t = transpose_of(f, dd);
+                    hm.insert(hm.end(), t.begin(), t.end());
+                }
+            } else {
+                const std::vector<cd> M = dense_of(o);
+                m.fwd = hm.size();
+                hm.insert(hm.end(), M.begin(), M.end());
+                m.inv = hm.size();
+                const std::vector<cd> a = adjoint_of(M, dd);
+                hm.insert(hm.end(), a.begin(), a.end());
+                m.tr = hm.size();
+                const std::vector<cd> t = transpose_of(M, dd);
+                hm.insert(hm.end(), t.begin(), t.end());
+                if (o.param_id >= 0) {
+                    m.dg = hm.size();
+                    hm.insert(hm.end(), o.dgen.begin(), o.dgen.end());
+                }
+            }
+            om[side].push_back(m);
+        }
+    std::vector<V> hmv;
+    to_dev<T>(hm, hmv);
+    if (!hmv.empty() &&
+        (s = hip_check(hipMemcpyAsync(mats, hmv.data(), hmv.size() * sizeof(V), hipMemcpyHostToDevice, st), "upload mats")) != HSF_OK)
+        return s;
+
+    Runner<T> R{p, st};
+    hipLaunchKernelGGL(bw_zero_doubles, dim3(std::max<uint32_t>(1, (uint32_t)((n_params + 255) / 256))), dim3(256), 0, st,
+                       grad, n_params);
+    if ((s = hip_check(hipGetLastError(), "zero grad")) != HSF_OK) return s;
+
+    // ---- psi(x_j) for every bitstring: tiled forward over all paths
+    for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
+        const int64_t np = std::min(chunk, p.P - p0);
+        if ((s = run_sides(p, d, p0, np, vS[0], dim[0], vS[1], dim[1], st)) != HSF_OK) return s;
+        if ((s = gather_dot(p.dtype, vS[0], dim[0], vS[1], dim[1], np, p.nb, p.n, x, nx, psi_x, p0 > 0 ? 1 : 0, st)) != HSF_OK)
+            return s;
+    }
+
+    // ---- adjoint over angles outside blocks
+    const int64_t* gt[2][4];
+    for (int side = 0; side < 2; ++side)
+        for (int i = 0; i < 4; ++i) gt[side][i] = tables + toff[side][i];
+    for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
+        const int64_t np = std::min(chunk, p.P - p0);
+        // forward, one op per launch, with a checkpoint in front of every factor slot
+        for (int side = 0; side < 2; ++side) {
+            if ((s = R.fill(vS[side], dim[side], dim[side], np, 1)) != HSF_OK) return s;
+            int kc = 0;
+            const auto& raw = p.side[side].raw;
+            for (size_t i = 0; i < raw.size(); ++i) {
+                const SideOp& o = raw[i];
+                if (o.kind == SideOp::SLOT) {
+                    V* c = ck[side] + (size_t)kc * chunk * dim[side];
+                    if ((s = R.copy_rows(vS[side], dim[side], c, dim[side], dim[side], np)) != HSF_OK) return s;
+                    ++kc;
+                    s = R.apply(vS[side], dim[side], np, nq[side], o, mats + om[side][i].fwd, o.rank, o.stride, p0);
+                } else {
+                    s = R.apply(vS[side], dim[side], np, nq[side], o, mats + om[side][i].fwd, 1, 1, p0);
+                }
+                if (s != HSF_OK) return s;
+            }
+        }
+        // cotangents: lambda_a from psi_x and side b, lambda_b from psi_x and side a
+        for (int side = 0; side < 2; ++side) {
+            if ((s = R.fill(lS[side], dim[side], dim[side], np, 0)) != HSF_OK) return s;
+            const int other = 1 - side;
+            const uint32_t bpr = (uint32_t)std::max<int64_t>(1, (ngroups[side] + 255) / 256);
+            if (ngroups[side] > 0) {
+                hipLaunchKernelGGL(bw_cotangent<T>, dim3((uint32_t)(np * bpr)), dim3(256), 0, st, vS[other], dim[other],
+                                   lS[side], dim[side], gt[side][0], gt[side][1], gt[side][2], gt[side][3],
+                                   (const double2*)psi_x, ngroups[side], bpr);
+                if ((s = hip_check(hipGetLastError(), "bw_cotangent launch")) != HSF_OK) return s;
+            }
+        }
+        // backward sweep
+        int64_t occ = 0;
+        for (int side = 0; side < 2; ++side) {
+            const auto& raw = p.side[side].raw;
+            int64_t occ_side = occ;
+            for (const SideOp& o : raw) occ += o.param_id >= 0;
+            int64_t oc = occ;                 // occurrences are numbered in program order
+            int kc = 0;
+            for (const SideOp& o : raw) kc += o.kind == SideOp::SLOT;
+            for (size_t ii = raw.size(); ii-- > 0;) {
+                const SideOp& o = raw[ii];
+                if (o.param_id >= 0) {
+                    --oc;
+                    if ((s = R.grad_dot(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].dg,
+                                        partial + oc * chunk)) != HSF_OK)
+                        return s;
+                }
+                if (o.kind == SideOp::SLOT) {
+                    --kc;
+                    V* c = ck[side] + (size_t)kc * chunk * dim[side];
+                    if ((s = R.copy_rows(c, dim[side], vS[side], dim[side], dim[side], np)) != HSF_OK) return s;
+                    if ((s = R.apply(lS[side], dim[side], np, nq[side], o, mats + om[side][ii].tr, o.rank, o.stride, p0)) != HSF_OK)
+                        return s;
+                } else {
+                    if ((s = R.apply2(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].inv,
+                                      mats + om[side][ii].tr)) != HSF_OK)
+                        return s;
+                }
+            }
+            (void)occ_side;
+        }
+        hipLaunchKernelGGL(bw_reduce, dim3(std::max<uint32_t>(1, (uint32_t)((p.n_params + 63) / 64))), dim3(64), 0, st,
+                           (const double2*)partial, chunk, np, occ_off_d, occ_d, p.n_params, grad);
+        if ((s = hip_check(hipGetLastError(), "bw_reduce launch")) != HSF_OK) return s;
+    }
+
+    // ---- angles inside blocks: parameter shift on the re-factored block
+    bool any = false;
+    for (const Block& b : p.blocks) any |= !b.params.empty();
+    if (any) {
+        // device pools of every schedule, to be patched per shifted block
+        std::vector<std::vector<size_t>> pool_at(2);
+        size_t o = 0;
+        std::vector<std::vector<V>> hpool;
+        for (int side = 0; side < 2; ++side)
+            for (const Schedule& sc : p.side[side].sched) {
+                pool_at[side].push_back(o);
+                o += std::max<size_t>(sc.pool.size(), 1);
+            }
+        DeviceCopy dd = d;
+        for (int side = 0; side < 2; ++side)
+            for (size_t i = 0; i < p.side[side].sched.size(); ++i) dd.side[side][i].pool = pools + pool_at[side][i];
+        const double half_pi = std::acos(0.0);
+        for (size_t k = 0; k < p.blocks.size(); ++k) {
+            const Block& b = p.blocks[k];
+            for (const auto& gp : b.params) {
+                const int64_t gid = gp.first;
+                const int t = gp.second;
+                if (t >= n_params) continue;
+                for (int sg = 0; sg < 2; ++sg) {
+                    std::vector<double> sig;
+                    std::vector<cd> xa, yb;
+                    int r = 0;
+                    const double ang = p.gates[gid].param + (sg == 0 ? half_pi : -half_pi);
+                    if ((s = factor_block(p, b, gid, ang, sig, xa, yb, r)) != HSF_OK) return s;
+                    if (r > b.rank)
+                        return fail(HSF_E_UNSUPPORTED, "a shifted block has a larger Schmidt rank than the plan's");
+                    // patched pools: factors of block k replaced (missing ranks zero)
+                    std::vector<cd> all;
+                    all.reserve(Lo.pool_elems);
+                    for (int side = 0; side < 2; ++side) {
+                        const std::vector<cd>& f = side == 0 ? xa : yb;
+                        const int kk = (int)(side == 0 ? b.sa.size() : b.sb.size());
+                        const size_t d2 = (size_t)1 << (2 * kk);
+                        for (const Schedule& sc : p.side[side].sched) {
+                            std::vector<cd> pl = sc.pool;
+                            for (const DevOp& op : sc.devops)
+                                if (op.type == DOP_SLOT && op.block == (int)k)
+                                    for (int m = 0; m < b.rank; ++m)
+                                        for (size_t e = 0; e < d2; ++e)
+                                            pl[op.mat + m * d2 + e] = m < r ? f[m * d2 + e] : cd(0);
+                            if (pl.empty()) pl.push_back(cd(0));
+                            all.insert(all.end(), pl.begin(), pl.end());
+                        }
+                    }
+                    std::vector<V> av;
+                    to_dev<T>(all, av);
+                    if ((s = hip_check(hipMemcpyAsync(pools, av.data(), av.size() * sizeof(V), hipMemcpyHostToDevice, st),
+                                       "upload shifted factors")) != HSF_OK)
+                        return s;
+                    for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
+                        const int64_t np = std::min(chunk, p.P - p0);
+                        if ((s = run_sides(p, dd, p0, np, vS[0], dim[0], vS[1], dim[1], st)) != HSF_OK) return s;
+                        if ((s = gather_dot(p.dtype, vS[0], dim[0], vS[1], dim[1], np, p.nb, p.n, x, nx, psi_s,
+                                            p0 > 0 ? 1 : 0, st)) != HSF_OK)
+                            return s;
+                    }
+                    hipLaunchKernelGGL(bw_loss, dim3(1), dim3(256), 0, st, (const double2*)psi_s, nx, lossb + sg);
+                    if ((s = hip_check(hipGetLastError(), "bw_loss launch")) != HSF_OK) return s;
+                    // the host copy of the pools must outlive the upload
+                    if ((s = hip_check(hipStreamSynchronize(st), "sync")) != HSF_OK) return s;
+                }
+                hipLaunchKernelGGL(bw_shift_combine, dim3(1), dim3(1), 0, st, lossb, lossb + 1, grad, (int64_t)t);
+                if ((s = hip_check(hipGetLastError(), "bw_shift_combine launch")) != HSF_OK) return s;
+            }
+        }
+    }
+    // host staging buffers above must outlive their async uploads
+    return hip_check(hipStreamSynchronize(st), "sync");
+}
+
+}  // namespace
+
+size_t backward_workspace(const Plan& p, int64_t chunk, int64_t nx) { return layout(p, chunk, nx).total; }
 
 hsf_status backward(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, double* grad, int64_t n_params,
                     int64_t chunk, void* ws, size_t ws_bytes, hipStream_t stream) {
-    (void)p; (void)d; (void)x; (void)nx; (void)grad; (void)n_params; (void)chunk; (void)ws; (void)ws_bytes;
-    (void)stream;
-    return fail(HSF_E_UNSUPPORTED, "hsf_backward not built yet");
+    if (p.dtype == HSF_C128) return backward_t<double>(p, d, x, nx, grad, n_params, chunk, ws, ws_bytes, stream);
+    return backward_t<float>(p, d, x, nx, grad, n_params, chunk, ws, ws_bytes, stream);
 }
 
 }  // namespace hsf

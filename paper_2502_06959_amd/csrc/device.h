@@ -28,7 +28,7 @@ hsf_status gather_dot(int dtype, const void* A, int64_t ldA, const void* B, int6
 hsf_status norm2(const void* a, int adt, const void* b, int bdt, int64_t n, double* out, double* ws,
                  hipStream_t stream);
 
-size_t backward_workspace(const Plan& p, int64_t chunk);
+size_t backward_workspace(const Plan& p, int64_t chunk, int64_t nx);
 hsf_status backward(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, double* grad,
                     int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes, hipStream_t stream);
 

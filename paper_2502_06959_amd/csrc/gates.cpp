@@ -63,4 +63,23 @@ bool gate_matrix(int kind, int nq, double t, const double* em, std::vector<cd>& 
     }
 }
 
+bool gate_generator(int kind, int nq, std::vector<cd>& d) {
+    // exp(-i t P / 2): dU/dt = (-i/2) P U;  diag(1, e^{it}): dU/dt = i |1><1| U
+    const cd h(0.0, -0.5), one_i(0.0, 1.0);
+    switch (kind) {
+        case HSF_GATE_RX: set(d, 2, {0, h, h, 0}); return nq == 1;
+        case HSF_GATE_RY: set(d, 2, {0, -h * cd(0, 1), h * cd(0, 1), 0}); return nq == 1;
+        case HSF_GATE_RZ: set(d, 2, {h, 0, 0, -h}); return nq == 1;
+        case HSF_GATE_PHASE: set(d, 2, {0, 0, 0, one_i}); return nq == 1;
+        case HSF_GATE_RZZ:
+            set(d, 4, {h, 0, 0, 0, 0, -h, 0, 0, 0, 0, -h, 0, 0, 0, 0, h});
+            return nq == 2;
+        case HSF_GATE_CP:
+            set(d, 4, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, one_i});
+            return nq == 2;
+        default:
+            return false;
+    }
+}
+
 }  // namespace hsf

@@ -17,6 +17,7 @@ constexpr int kMaxOpQubits = 4;       // widest dense op in a side program
 constexpr int kMaxTileBits = 24;
 
 hsf_status fail(hsf_status s, const std::string& msg);   // records the thread-local message
+std::string g_last_error_copy();                        // the current thread-local message
 
 struct Gate {
     int kind = 0;
@@ -40,6 +41,7 @@ void jacobi_svd(int m, int n, const std::vector<cd>& A, std::vector<cd>& W,
 
 struct Block {
     int caller_index = 0;
+    std::vector<std::pair<int64_t, int>> params;   // (gate id, param id) of rotations in the hull
     std::vector<int64_t> hull;       // gate ids, ascending
     std::vector<int> sa, sb;         // supports, ascending qubits
     std::vector<double> sigma;       // all singular values, descending
@@ -61,6 +63,8 @@ struct SideOp {
     int rank = 1;
     int64_t stride = 1;
     int64_t logical = 1;     // circuit gates represented by this op
+    int param_id = -1;       // rotation angle of a single gate (before fusion), -1 if none
+    std::vector<cd> dgen;    // D with dU/dparam = D U on the op's qubits (param_id >= 0)
 };
 
 // Device op (plain data, read by the sweep kernels).
@@ -77,6 +81,8 @@ struct DevOp {
     int32_t mat;         // DENSEK/SLOT: pool offset (complex); GROUP: first sub-op
     int32_t rank;        // SLOT: factor count; GROUP: sub-op count
     int64_t stride;      // SLOT: digit stride R_k
+    int32_t block;       // SLOT: plan block index
+    int32_t pad;
 };
 
 // Sub-op of a group.  D1: 2x2 matrix m on register position g.  SIGN/PHASE:
@@ -116,6 +122,7 @@ struct Schedule {
 
 struct SideProgram {
     int nq = 0;
+    std::vector<SideOp> raw;          // before fusion (one op per gate or slot)
     std::vector<SideOp> ops;          // after fusion
     int64_t ops_logical = 0;
     std::vector<Schedule> sched;      // one per candidate tile size, largest first
@@ -150,6 +157,15 @@ struct Plan {
 
 hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, const int64_t* offs,
                       int32_t n_blocks, const hsf_plan_options* opts, Plan** out);
+
+// Operator-Schmidt factors of block k with gate `gate_id` taking angle
+// `param` instead of its own (gate_id < 0: unchanged).  Fills sigma, the
+// folded factors (rank x d x d each) and the rank under the plan's tolerance.
+hsf_status factor_block(const Plan& p, const Block& b, int64_t gate_id, double param, std::vector<double>& sigma,
+                        std::vector<cd>& xa, std::vector<cd>& yb, int& rank);
+
+// dU/dparam = D U for a rotation gate (RX, RY, RZ, RZZ, PHASE, CP); false otherwise.
+bool gate_generator(int kind, int nq, std::vector<cd>& d);
 
 // Side-program fusion and pass scheduling (plan.cpp).
 void fuse_side(Plan& p, int side);

@@ -66,6 +66,64 @@ std::vector<char> closure(const std::vector<Gate>& gs, int n, const std::vector<
 
 }  // namespace
 
+hsf_status factor_block(const Plan& p, const Block& blk, int64_t gate_id, double param, std::vector<double>& sigma,
+                        std::vector<cd>& xa, std::vector<cd>& yb, int& rank) {
+    const int ka = (int)blk.sa.size(), kb = (int)blk.sb.size(), nl = ka + kb;
+    const int da = 1 << ka, db = 1 << kb, d = 1 << nl;
+    int local[64];
+    for (int i = 0; i < kb; ++i) local[blk.sb[i]] = i;
+    for (int i = 0; i < ka; ++i) local[blk.sa[i]] = kb + i;
+    std::vector<cd> U((size_t)d * d, cd(0));
+    for (int i = 0; i < d; ++i) U[(size_t)i * d + i] = 1.0;
+    std::vector<cd> alt;
+    for (int64_t gi : blk.hull) {
+        const Gate& g = p.gates[gi];
+        int lb[4];
+        for (int j = 0; j < g.nq; ++j) lb[j] = local[g.q[j]];
+        const std::vector<cd>* m = &g.m;
+        if (gi == gate_id) {
+            gate_matrix(g.kind, g.nq, param, nullptr, alt);
+            m = &alt;
+        }
+        left_multiply(U, nl, lb, g.nq, *m);
+    }
+    // reshape: rows (i_b, j_b), columns (i_a, j_a)
+    const int rows = db * db, cols = da * da;
+    std::vector<cd> At((size_t)rows * cols);
+    for (int ia = 0; ia < da; ++ia)
+        for (int ib = 0; ib < db; ++ib)
+            for (int ja = 0; ja < da; ++ja)
+                for (int jb = 0; jb < db; ++jb)
+                    At[(size_t)(ib * db + jb) * cols + (ia * da + ja)] = U[(size_t)(ia * db + ib) * d + (ja * db + jb)];
+    std::vector<cd> W, Vh;
+    jacobi_svd(rows, cols, At, W, sigma, Vh);
+    const double s0 = sigma.empty() ? 0.0 : sigma[0];
+    if (!(s0 > 0)) return fail(HSF_E_RANK_AMBIGUOUS, "operator is zero");
+    int r = 0;
+    for (double sv : sigma) {
+        const double rel = sv / s0;
+        if (rel > p.rank_tol * 1e-3 && rel <= p.rank_tol * 1e3)
+            return fail(HSF_E_RANK_AMBIGUOUS, "singular value ratio " + std::to_string(rel) + " near the rank tolerance");
+        if (rel > p.rank_tol) ++r;
+    }
+    rank = r;
+    xa.assign((size_t)r * da * da, cd(0));
+    yb.assign((size_t)r * db * db, cd(0));
+    for (int m = 0; m < r; ++m) {
+        const double rt = std::sqrt(sigma[m]);
+        for (int e = 0; e < da * da; ++e) xa[(size_t)m * da * da + e] = rt * Vh[(size_t)m * cols + e];
+        for (int e = 0; e < db * db; ++e) yb[(size_t)m * db * db + e] = rt * W[(size_t)m * rows + e];
+    }
+    // a side with no qubit in the block carries a scalar: fold it into the other side
+    if (ka == 0)
+        for (int m = 0; m < r; ++m)
+            for (int e = 0; e < db * db; ++e) yb[(size_t)m * db * db + e] *= xa[m];
+    if (kb == 0)
+        for (int m = 0; m < r; ++m)
+            for (int e = 0; e < da * da; ++e) xa[(size_t)m * da * da + e] *= yb[m];
+    return HSF_OK;
+}
+
 hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, const int64_t* offs,
                       int32_t n_blocks, const hsf_plan_options* opts, Plan** out) {
     if (!c || !out) return fail(HSF_E_ARG, "null circuit or output pointer");
@@ -208,53 +266,10 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
         for (int q : qs) (q > cut ? blk.sa : blk.sb).push_back(q);
         if ((int)blk.sa.size() > p->max_side || (int)blk.sb.size() > p->max_side)
             return fail(HSF_E_BLOCK_TOO_LARGE, "block " + std::to_string(b) + " support " + std::to_string(blk.sa.size()) + "|" + std::to_string(blk.sb.size()));
-        const int ka = (int)blk.sa.size(), kb = (int)blk.sb.size(), nl = ka + kb;
-        const int da = 1 << ka, db = 1 << kb, d = 1 << nl;
-        int local[64];
-        for (int i = 0; i < kb; ++i) local[blk.sb[i]] = i;
-        for (int i = 0; i < ka; ++i) local[blk.sa[i]] = kb + i;
-        std::vector<cd> U((size_t)d * d, cd(0));
-        for (int i = 0; i < d; ++i) U[(size_t)i * d + i] = 1.0;
-        for (int64_t gi : blk.hull) {
-            const Gate& g = p->gates[gi];
-            int lb[4];
-            for (int j = 0; j < g.nq; ++j) lb[j] = local[g.q[j]];
-            left_multiply(U, nl, lb, g.nq, g.m);
-        }
-        // reshape: rows (i_b, j_b), columns (i_a, j_a)
-        const int rows = db * db, cols = da * da;
-        std::vector<cd> At((size_t)rows * cols);
-        for (int ia = 0; ia < da; ++ia)
-            for (int ib = 0; ib < db; ++ib)
-                for (int ja = 0; ja < da; ++ja)
-                    for (int jb = 0; jb < db; ++jb)
-                        At[(size_t)(ib * db + jb) * cols + (ia * da + ja)] = U[(size_t)(ia * db + ib) * d + (ja * db + jb)];
-        std::vector<cd> W, Vh;
-        jacobi_svd(rows, cols, At, W, blk.sigma, Vh);
-        const double s0 = blk.sigma.empty() ? 0.0 : blk.sigma[0];
-        if (!(s0 > 0)) return fail(HSF_E_RANK_AMBIGUOUS, "block " + std::to_string(b) + " operator is zero");
-        int r = 0;
-        for (double sv : blk.sigma) {
-            const double rel = sv / s0;
-            if (rel > p->rank_tol * 1e-3 && rel <= p->rank_tol * 1e3)
-                return fail(HSF_E_RANK_AMBIGUOUS, "block " + std::to_string(b) + ": singular value ratio " + std::to_string(rel) + " near the rank tolerance");
-            if (rel > p->rank_tol) ++r;
-        }
-        blk.rank = r;
-        blk.xa.resize((size_t)r * da * da);
-        blk.yb.resize((size_t)r * db * db);
-        for (int m = 0; m < r; ++m) {
-            const double rt = std::sqrt(blk.sigma[m]);
-            for (int e = 0; e < da * da; ++e) blk.xa[(size_t)m * da * da + e] = rt * Vh[(size_t)m * cols + e];
-            for (int e = 0; e < db * db; ++e) blk.yb[(size_t)m * db * db + e] = rt * W[(size_t)m * rows + e];
-        }
-        // a side with no qubit in the block carries a scalar: fold it into the other side
-        if (ka == 0)
-            for (int m = 0; m < r; ++m)
-                for (int e = 0; e < db * db; ++e) blk.yb[(size_t)m * db * db + e] *= blk.xa[m];
-        if (kb == 0)
-            for (int m = 0; m < r; ++m)
-                for (int e = 0; e < da * da; ++e) blk.xa[(size_t)m * da * da + e] *= blk.yb[m];
+        for (int64_t gi : blk.hull)
+            if (p->gates[gi].param_id >= 0) blk.params.push_back({gi, p->gates[gi].param_id});
+        hsf_status fs = factor_block(*p, blk, -1, 0.0, blk.sigma, blk.xa, blk.yb, blk.rank);
+        if (fs != HSF_OK) return fail(fs, "block " + std::to_string(b) + ": " + hsf::g_last_error_copy());
         p->blocks.push_back(std::move(blk));
     }
 
@@ -293,6 +308,7 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
             } else {
                 op.m = g.m;
             }
+            if (g.param_id >= 0 && gate_generator(g.kind, g.nq, op.dgen)) op.param_id = g.param_id;
             p->side[s].ops.push_back(std::move(op));
         } else {
             const int k = plan_index[nd - G];
@@ -316,6 +332,7 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
     }
     for (int s = 0; s < 2; ++s) {
         p->side[s].ops_logical = (int64_t)p->side[s].ops.size();
+        p->side[s].raw = p->side[s].ops;
         fuse_side(*p, s);
         const int nq = std::max(p->side[s].nq, 1);
         const int tmax = p->tile_req > 0 ? p->tile_req : max_tile_bits(p->dtype);
@@ -474,6 +491,7 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
             if (pos_in(bits, b) < 0) bits.push_back(b);
         DevOp d{};
         d.type = DOP_GROUP;
+        d.block = -1;
         d.k = KG;
         for (int g = 0; g < KG; ++g) d.bit[g] = bits[g];
         d.mat = (int32_t)sc.subs.size();
@@ -555,6 +573,7 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
             d.mat = (int32_t)sc.pool.size();
             d.rank = o.rank;
             d.stride = o.stride;
+            d.block = o.block;
             sc.pool.insert(sc.pool.end(), o.m.begin(), o.m.end());
             sc.devops.push_back(d);
         }

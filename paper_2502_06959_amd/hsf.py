@@ -118,6 +118,7 @@ class Plan:
     def __init__(self, circuit, cut=None, blocks=None, dtype=None, **opts):
         dtype = dtype or circuit.get("meta", {}).get("dtype", "c64")
         self.dtype = dtype
+        self.n_params = 1 + max([g.get("param_id", -1) for g in circuit["gates"]] + [-1])
         self.handle = hsf_plan(circuit, cut, blocks, dtype=dtype, **opts)
         n, c, na, nb, k = (ctypes.c_int32() for _ in range(5))
         p = ctypes.c_int64()
@@ -206,3 +207,56 @@ class Plan:
             out = torch.zeros(x.numel(), dtype=torch.complex128, device=psiA.device)
         hsf_amplitudes_bitstrings(self.handle, psiA, psiB, n_paths, x, out, accumulate)
         return out
+
+    def backward(self, x, chunk=None, grad=None):
+        """d/dt of L = sum_j |psi(x_j)|^2 for every parameter id (float64
+        tensor of n_params entries).  x: device tensor of basis-state indices."""
+        chunk = min(self.P, 256) if chunk is None else chunk
+        nbytes = hsf_workspace_size(self.handle, 2, chunk, x.numel())
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        if grad is None:
+            grad = torch.zeros(max(self.n_params, 1), dtype=torch.float64, device=x.device)
+        hsf_backward(self.handle, x, grad, chunk, ws)
+        return grad[:self.n_params]
+
+    def loss(self, x, chunk=None):
+        """L = sum_j |psi(x_j)|^2 (forward only), as a float."""
+        chunk = min(self.P, 256) if chunk is None else chunk
+        A, B = self.alloc_halves(chunk, device=x.device)
+        amp = torch.zeros(x.numel(), dtype=torch.complex128, device=x.device)
+        for p0 in range(0, self.P, chunk):
+            p1 = min(self.P, p0 + chunk)
+            self.run_paths(p0, p1, A[:p1 - p0], B[:p1 - p0])
+            self.amplitudes_bitstrings(A, B, x, n_paths=p1 - p0, out=amp, accumulate=p0 > 0)
+        return float((amp.abs() ** 2).sum().item())
+
+
+def _with_params(circuit, theta):
+    gs = []
+    for g in circuit["gates"]:
+        if g.get("param_id", -1) >= 0:
+            g = dict(g)
+            g["param"] = float(theta[g["param_id"]])
+        gs.append(g)
+    c = dict(circuit)
+    c["gates"] = gs
+    return c
+
+
+class ProbabilityMass(torch.autograd.Function):
+    """L(theta) = sum_j |<x_j| U(theta) |0>|^2 through joint-cut HSF.
+
+    forward plans the circuit at the given angles and sums the bitstring
+    amplitudes over all paths; backward calls hsf_backward."""
+
+    @staticmethod
+    def forward(ctx, theta, circuit, x, dtype="c64", chunk=None):
+        th = theta.detach().double().cpu().numpy()
+        plan = Plan(_with_params(circuit, th), dtype=dtype)
+        ctx.plan, ctx.x, ctx.chunk = plan, x, chunk
+        return torch.tensor(plan.loss(x, chunk), dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gout):
+        g = ctx.plan.backward(ctx.x, ctx.chunk)
+        return (gout.to(g.device) * g).to(torch.float64).cpu(), None, None, None, None

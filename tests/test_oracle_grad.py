@@ -1,0 +1,51 @@
+"""Pins of the oracle's gradient routes to the definition of the derivative:
+the parameter-shift rule equals central finite differences, the full-state
+adjoint equals both, and the HSF loss equals the Schroedinger loss."""
+import numpy as np
+import pytest
+
+import circuitgen as cg
+from oracle import grad as OG
+
+
+def _small_c3(n=8, layers=6, seed=3):
+    return cg.c3(seed=seed, n=n, layers=layers)
+
+
+def _xs(n, count, seed):
+    return cg.c3_bitstrings(n=n, count=count, seed=seed)
+
+
+@pytest.mark.parametrize("n,layers", [(6, 3), (8, 6)])
+def test_shift_rule_equals_finite_differences(n, layers):
+    c = _small_c3(n, layers)
+    xs = _xs(n, 16, 5)
+    ids = sorted(OG.occurrences(c))[::3]
+    gs = OG.loss_grad_shift(c, xs, ids, use_hsf=False)
+    gf = OG.loss_grad_fd(c, xs, ids, h=1e-5, use_hsf=False)
+    ref = max(abs(v) for v in gs.values())
+    assert max(abs(gs[t] - gf[t]) for t in ids) < 1e-6 * max(ref, 1e-3)
+
+
+def test_adjoint_equals_shift_rule():
+    c = _small_c3(8, 6)
+    xs = _xs(8, 20, 6)
+    ga = OG.loss_grad_adjoint(c, xs)
+    gs = OG.loss_grad_shift(c, xs, use_hsf=False)
+    assert set(ga) == set(gs)
+    assert max(abs(ga[t] - gs[t]) for t in gs) < 1e-12
+
+
+def test_hsf_loss_equals_schroedinger_loss():
+    c = _small_c3(10, 6)
+    xs = _xs(10, 40, 7)
+    assert abs(OG.loss(c, xs, True) - OG.loss(c, xs, False)) < 1e-14
+
+
+def test_shared_parameter_sums_occurrences():
+    c = cg.qaoa_sbm(2, sizes=(3, 3), p_intra=0.7, p_inter=0.4)
+    xs = np.arange(64, dtype=np.uint64)[::3]
+    gs = OG.loss_grad_shift(c, xs, use_hsf=False)
+    gf = OG.loss_grad_fd(c, xs, h=1e-5, use_hsf=False)
+    for t in gs:
+        assert abs(gs[t] - gf[t]) < 1e-7
