@@ -224,6 +224,34 @@ hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double*
                         int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes,
                         hsf_stream_t stream);
 
+/* -------------------------------------------------------------- batches ---- */
+
+/* Many independent circuits run together (paths of different circuits are as
+ * independent as paths of one, Sec. II-B): every circuit's LDS pass k goes in
+ * one launch, the path sums of all circuits in one persistent MFMA launch
+ * over the union of their output tiles.  Plans must be complex64, with sides
+ * of at least 3 qubits, and must outlive the batch.                           */
+typedef struct hsf_batch_s* hsf_batch_t;
+hsf_status hsf_batch_create(const hsf_plan_t* plans, int32_t n_plans, hsf_batch_t* out);
+void hsf_batch_destroy(hsf_batch_t batch);
+/* Workspace bytes for hsf_batch_run with path-sum `mode` (F32 or BF16X3):
+ * every circuit's half-states (all paths), plus BF16 planes for BF16X3.      */
+size_t hsf_batch_workspace_size(hsf_batch_t batch, int32_t mode);
+/* Full state of every circuit: outs[i] is a device array of 2^n_i complex64
+ * amplitudes of circuit i (row-major, index i_a 2^n_b + i_b as for one plan).
+ * use_graph = 1 records the launch sequence in a HIP graph on the first call
+ * and replays it afterwards (the graph is rebuilt when `outs`, `mode`, the
+ * workspace address or the tuned policy change); small device tables are
+ * (re)built with synchronous copies when those change, outside any capture. */
+hsf_status hsf_batch_run(hsf_batch_t batch, void* const* outs, int32_t mode, int32_t use_graph, void* ws,
+                         size_t ws_bytes, hsf_stream_t stream);
+/* Autotuner: times the tile policies (0: largest tiles, fewest passes; 1:
+ * per-circuit tiles that fill the device alone; 2: one size smaller) with 3
+ * runs each on `stream`, keeps the fastest for later hsf_batch_run calls and
+ * returns it in *policy.  Synchronises `stream`.                             */
+hsf_status hsf_batch_tune(hsf_batch_t batch, void* const* outs, int32_t mode, void* ws, size_t ws_bytes,
+                          hsf_stream_t stream, int32_t* policy);
+
 /* Thread-local message for the last non-OK status on this thread.            */
 const char* hsf_last_error(void);
 /* Library version string.                                                    */

@@ -6,9 +6,9 @@ as host structs, device buffers are torch tensors, and the stream is torch's
 current stream.  Functions keep the C names (hsf_plan, hsf_run_paths, ...);
 `Plan` bundles them.
 """
-from .hsf import (Plan, ProbabilityMass, hsf_amplitudes_bitstrings, hsf_amplitudes_full, hsf_backward, hsf_norm2, hsf_plan,
+from .hsf import (Batch, Plan, ProbabilityMass, hsf_amplitudes_bitstrings, hsf_amplitudes_full, hsf_backward, hsf_norm2, hsf_plan,
                   hsf_run_paths, hsf_workspace_size)
 from ._lib import HsfError
 
-__all__ = ["Plan", "ProbabilityMass", "HsfError", "hsf_plan", "hsf_run_paths", "hsf_amplitudes_full", "hsf_amplitudes_bitstrings",
+__all__ = ["Batch", "Plan", "ProbabilityMass", "HsfError", "hsf_plan", "hsf_run_paths", "hsf_amplitudes_full", "hsf_amplitudes_bitstrings",
            "hsf_norm2", "hsf_backward", "hsf_workspace_size"]

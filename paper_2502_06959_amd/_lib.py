@@ -68,6 +68,11 @@ SIGNATURES = {
                             c_void_p]),
     "hsf_backward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_size_t,
                                c_void_p]),
+    "hsf_batch_create": (c_int32, [P(c_void_p), c_int32, P(c_void_p)]),
+    "hsf_batch_destroy": (None, [c_void_p]),
+    "hsf_batch_workspace_size": (c_size_t, [c_void_p, c_int32]),
+    "hsf_batch_run": (c_int32, [c_void_p, P(c_void_p), c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
+    "hsf_batch_tune": (c_int32, [c_void_p, P(c_void_p), c_int32, c_void_p, c_size_t, c_void_p, P(c_int32)]),
     "hsf_last_error": (ctypes.c_char_p, []),
     "hsf_version": (ctypes.c_char_p, []),
 }

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "device.h"
 #include "internal.h"
@@ -225,6 +226,58 @@ hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double*
     hsf_status s = ensure_device(*p, &d);
     if (s != HSF_OK) return s;
     return backward(*p, *d, x, n_x, grad, n_params, chunk, ws, ws_bytes, (hipStream_t)stream);
+    HSF_GUARD_END
+}
+
+hsf_status hsf_batch_create(const hsf_plan_t* plans, int32_t n_plans, hsf_batch_t* out) {
+    HSF_GUARD_BEGIN
+    if (!out || (n_plans > 0 && !plans) || n_plans <= 0) return fail(HSF_E_ARG, "need at least one plan");
+    *out = nullptr;
+    std::vector<Plan*> ps(n_plans);
+    for (int i = 0; i < n_plans; ++i) {
+        if (!plans[i]) return fail(HSF_E_ARG, "null plan in batch");
+        ps[i] = P_(plans[i]);
+    }
+    Batch* b = nullptr;
+    hsf_status s = batch_create(ps.data(), n_plans, &b);
+    if (s != HSF_OK) return s;
+    *out = reinterpret_cast<hsf_batch_t>(b);
+    return HSF_OK;
+    HSF_GUARD_END
+}
+
+void hsf_batch_destroy(hsf_batch_t batch) { batch_destroy(reinterpret_cast<Batch*>(batch)); }
+
+size_t hsf_batch_workspace_size(hsf_batch_t batch, int32_t mode) {
+    return batch ? batch_workspace(*reinterpret_cast<Batch*>(batch), mode) : 0;
+}
+
+static hsf_status batch_args(hsf_batch_t batch, void* const* outs, int32_t mode, void* ws, size_t ws_bytes) {
+    if (!batch || !outs || !ws) return fail(HSF_E_ARG, "null argument");
+    if (mode != HSF_SUM_F32 && mode != HSF_SUM_BF16X3) return fail(HSF_E_ARG, "batches use HSF_SUM_F32 or HSF_SUM_BF16X3");
+    Batch* b = reinterpret_cast<Batch*>(batch);
+    if (ws_bytes < batch_workspace(*b, mode)) return fail(HSF_E_ARG, "workspace too small for the batch");
+    return HSF_OK;
+}
+
+hsf_status hsf_batch_run(hsf_batch_t batch, void* const* outs, int32_t mode, int32_t use_graph, void* ws,
+                         size_t ws_bytes, hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    hsf_status s = batch_args(batch, outs, mode, ws, ws_bytes);
+    if (s != HSF_OK) return s;
+    return batch_run(*reinterpret_cast<Batch*>(batch), outs, mode, use_graph, ws, (hipStream_t)stream);
+    HSF_GUARD_END
+}
+
+hsf_status hsf_batch_tune(hsf_batch_t batch, void* const* outs, int32_t mode, void* ws, size_t ws_bytes,
+                          hsf_stream_t stream, int32_t* policy) {
+    HSF_GUARD_BEGIN
+    hsf_status s = batch_args(batch, outs, mode, ws, ws_bytes);
+    if (s != HSF_OK) return s;
+    int chosen = 0;
+    s = batch_tune(*reinterpret_cast<Batch*>(batch), outs, mode, ws, (hipStream_t)stream, &chosen);
+    if (policy) *policy = chosen;
+    return s;
     HSF_GUARD_END
 }
 

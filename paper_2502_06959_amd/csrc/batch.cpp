@@ -1,0 +1,325 @@
+// Batches of independent circuits run together: every circuit's LDS pass k
+// in one launch (a table of (circuit, side) segments), one split launch and
+// one persistent path-sum launch over the union of all circuits' output
+// tiles.  The launch sequence is captured once into a HIP graph and replayed;
+// an autotuner picks the tile policy by timing the candidates on the device.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+namespace hsf {
+
+struct Batch {
+    std::vector<Plan*> plans;
+    int policy = 0;                      // 0: largest tiles; 1: per-circuit fill rule; 2: one size smaller
+    int device = -1;
+    // workspace layout (bytes from the 256-aligned base)
+    std::vector<int64_t> offA, offB, offPA, offPB, kp;
+    size_t ws_f32 = 0, ws_bf16 = 0;
+    // device tables
+    void* segs = nullptr;
+    void* splits = nullptr;
+    void* gemms = nullptr;
+    std::vector<int> round_first, round_n;
+    std::vector<uint32_t> round_blocks, round_emax;
+    int n_split = 0;
+    uint32_t split_blocks = 0;
+    int64_t tiles = 0;
+    // what the tables were built for
+    int built_policy = -1, built_mode = -1;
+    std::vector<void*> built_outs;
+    // graph cache
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned char* graph_base = nullptr;
+    bool graph_valid = false;
+};
+
+namespace {
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int sched_index(const Batch& b, const Plan& p) {
+    const int n = (int)std::max(p.side[0].sched.size(), p.side[1].sched.size());
+    if (b.policy == 0) return 0;
+    if (b.policy == 1) return pick_schedule(p, p.P);
+    return std::min(1, n - 1);
+}
+
+void free_tables(Batch& b) {
+    for (void* q : {b.segs, b.splits, b.gemms})
+        if (q) (void)hipFree(q);
+    b.segs = b.splits = b.gemms = nullptr;
+    b.built_policy = b.built_mode = -1;
+    b.built_outs.clear();
+}
+
+void drop_graph(Batch& b) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    b.graph_valid = false;
+}
+
+template <typename T>
+hsf_status upload_table(const std::vector<T>& v, void** dst) {
+    if (*dst) (void)hipFree(*dst);
+    *dst = nullptr;
+    hsf_status s = hip_check(hipMalloc(dst, std::max<size_t>(v.size() * sizeof(T), 64)), "hipMalloc(batch table)");
+    if (s != HSF_OK || v.empty()) return s;
+    return hip_check(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy(batch table)");
+}
+
+hsf_status build_tables(Batch& b, void* const* outs, int mode) {
+    const int n = (int)b.plans.size();
+    for (int i = 0; i < n; ++i) {
+        const Plan& p = *b.plans[i];
+        for (int s = 0; s < 2; ++s)
+            for (const Schedule& sc : p.side[s].sched)
+                for (const Pass& ps : sc.passes)
+                    if (ps.n_local < 3) return fail(HSF_E_UNSUPPORTED, "batched sweeps need sides of at least 3 qubits");
+    }
+    std::vector<DeviceCopy*> dc(n);
+    for (int i = 0; i < n; ++i) {
+        hsf_status s = ensure_device(*b.plans[i], &dc[i]);
+        if (s != HSF_OK) return s;
+    }
+    batch_sweep_prepare();
+    // sweep segments, round by round
+    std::vector<BatchSeg> segs;
+    b.round_first.clear();
+    b.round_n.clear();
+    b.round_blocks.clear();
+    b.round_emax.clear();
+    size_t rounds = 0;
+    std::vector<int> si(n);
+    for (int i = 0; i < n; ++i) {
+        si[i] = sched_index(b, *b.plans[i]);
+        for (int s = 0; s < 2; ++s) {
+            const auto& v = b.plans[i]->side[s].sched;
+            rounds = std::max(rounds, v[std::min<size_t>(si[i], v.size() - 1)].passes.size());
+        }
+    }
+    for (size_t k = 0; k < rounds; ++k) {
+        b.round_first.push_back((int)segs.size());
+        uint32_t start = 0, emax = 1;
+        for (int i = 0; i < n; ++i) {
+            const Plan& p = *b.plans[i];
+            for (int s = 0; s < 2; ++s) {
+                const auto& v = p.side[s].sched;
+                const size_t idx = std::min<size_t>(si[i], v.size() - 1);
+                const Schedule& sc = v[idx];
+                if (k >= sc.passes.size()) continue;
+                const DeviceSchedule& ds = dc[i]->side[s][idx];
+                BatchSeg g{};
+                g.pass = reinterpret_cast<const Pass*>(ds.passes) + k;
+                g.psi_off = s == 0 ? b.offA[i] : b.offB[i];
+                g.ld = int64_t(1) << (s == 0 ? p.na : p.nb);
+                g.ops = (const DevOp*)ds.ops;
+                g.subs = ds.subs;
+                g.pool = ds.pool;
+                g.n_tiles = 1u << sc.passes[k].n_nonlocal;
+                g.block_start = start;
+                start += (uint32_t)(p.P * g.n_tiles);
+                emax = std::max(emax, 1u << sc.passes[k].n_local);
+                segs.push_back(g);
+            }
+        }
+        b.round_n.push_back((int)segs.size() - b.round_first.back());
+        b.round_blocks.push_back(start);
+        b.round_emax.push_back(emax);
+    }
+    hsf_status s = upload_table(segs, &b.segs);
+    if (s != HSF_OK) return s;
+    // split descriptors (BF16 planes) and path-sum descriptors
+    std::vector<SplitDesc> sp;
+    std::vector<GemmDesc> gm;
+    uint32_t sb = 0;
+    int64_t tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        const Plan& p = *b.plans[i];
+        const int64_t M = int64_t(1) << p.na, N = int64_t(1) << p.nb;
+        if (mode == HSF_SUM_BF16X3) {
+            for (int side = 0; side < 2; ++side) {
+                SplitDesc d{};
+                d.x_off = side == 0 ? b.offA[i] : b.offB[i];
+                d.ldx = side == 0 ? M : N;
+                d.K = p.P;
+                d.R = side == 0 ? M : N;
+                d.Kp = b.kp[i];
+                d.planes_off = side == 0 ? b.offPA[i] : b.offPB[i];
+                d.blocks_x = (uint32_t)((d.R + 255) / 256);
+                d.block_start = sb;
+                sb += d.blocks_x * (uint32_t)(d.Kp / 8);
+                sp.push_back(d);
+            }
+        }
+        GemmDesc g{};
+        if (mode == HSF_SUM_BF16X3) {
+            g.a_off = b.offPA[i];
+            g.b_off = b.offPB[i];
+            g.K = b.kp[i];
+        } else {
+            g.a_off = b.offA[i];
+            g.b_off = b.offB[i];
+            g.K = p.P;
+        }
+        g.ldA = M;
+        g.ldB = N;
+        g.M = M;
+        g.N = N;
+        g.out = outs[i];
+        g.ldo = N;
+        g.tiles_n = (N + 127) / 128;
+        g.tile_start = tiles;
+        tiles += g.tiles_n * ((M + 127) / 128);
+        gm.push_back(g);
+    }
+    if ((s = upload_table(sp, &b.splits)) != HSF_OK) return s;
+    if ((s = upload_table(gm, &b.gemms)) != HSF_OK) return s;
+    b.n_split = (int)sp.size();
+    b.split_blocks = sb;
+    b.tiles = tiles;
+    b.built_policy = b.policy;
+    b.built_mode = mode;
+    b.built_outs.assign(outs, outs + n);
+    return HSF_OK;
+}
+
+hsf_status enqueue(Batch& b, int mode, unsigned char* base, hipStream_t st) {
+    hsf_status s;
+    for (size_t k = 0; k < b.round_first.size(); ++k) {
+        const uint32_t emax = b.round_emax[k];
+        const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, emax >> 3));
+        const size_t shmem = ((size_t)emax + 256) * 8;
+        if (b.round_blocks[k] == 0) continue;
+        s = launch_sweep_batch(reinterpret_cast<const BatchSeg*>(b.segs) + b.round_first[k], b.round_n[k],
+                               b.round_blocks[k], threads, shmem, base, st);
+        if (s != HSF_OK) return s;
+    }
+    if (mode == HSF_SUM_BF16X3) {
+        if ((s = launch_split_batch(b.splits, b.n_split, b.split_blocks, base, st)) != HSF_OK) return s;
+        return launch_bf16x3_batch(b.gemms, (int)b.plans.size(), b.tiles, base, st);
+    }
+    return launch_f32_batch(b.gemms, (int)b.plans.size(), b.tiles, base, st);
+}
+
+}  // namespace
+
+hsf_status batch_create(Plan* const* plans, int n, Batch** out) {
+    for (int i = 0; i < n; ++i)
+        if (plans[i]->dtype != HSF_C64) return fail(HSF_E_UNSUPPORTED, "batches run complex64 plans");
+    Batch* b = new Batch();
+    b->plans.assign(plans, plans + n);
+    size_t o = 0, ob = 0;
+    for (int i = 0; i < n; ++i) {
+        const Plan& p = *plans[i];
+        const int64_t M = int64_t(1) << p.na, N = int64_t(1) << p.nb;
+        b->offA.push_back((int64_t)o);
+        o += a256((size_t)p.P * M * 8);
+        b->offB.push_back((int64_t)o);
+        o += a256((size_t)p.P * N * 8);
+    }
+    ob = o;
+    for (int i = 0; i < n; ++i) {
+        const Plan& p = *plans[i];
+        const int64_t M = int64_t(1) << p.na, N = int64_t(1) << p.nb;
+        const int64_t kp = std::max<int64_t>(16, (p.P + 15) / 16 * 16);
+        b->kp.push_back(kp);
+        b->offPA.push_back((int64_t)ob);
+        ob += a256((size_t)4 * M * kp * 2);
+        b->offPB.push_back((int64_t)ob);
+        ob += a256((size_t)4 * N * kp * 2);
+    }
+    b->ws_f32 = o + 256;
+    b->ws_bf16 = ob + 256;
+    *out = b;
+    return HSF_OK;
+}
+
+void batch_destroy(Batch* b) {
+    if (!b) return;
+    drop_graph(*b);
+    free_tables(*b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+size_t batch_workspace(const Batch& b, int mode) { return mode == HSF_SUM_BF16X3 ? b.ws_bf16 : b.ws_f32; }
+
+hsf_status batch_run(Batch& b, void* const* outs, int mode, int use_graph, void* ws, hipStream_t st) {
+    unsigned char* base = reinterpret_cast<unsigned char*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    const int n = (int)b.plans.size();
+    const bool same = b.built_policy == b.policy && b.built_mode == mode &&
+                      b.built_outs.size() == (size_t)n && std::equal(b.built_outs.begin(), b.built_outs.end(), outs);
+    hsf_status s;
+    if (!same) {
+        drop_graph(b);
+        if ((s = build_tables(b, outs, mode)) != HSF_OK) return s;
+    }
+    if (!use_graph) return enqueue(b, mode, base, st);
+    if (!b.graph_valid || b.graph_base != base) {
+        drop_graph(b);
+        if (!b.cap && (s = hip_check(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking), "hipStreamCreate")) != HSF_OK)
+            return s;
+        if ((s = hip_check(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")) != HSF_OK)
+            return s;
+        hsf_status se = enqueue(b, mode, base, b.cap);
+        hipGraph_t g = nullptr;
+        hsf_status sc = hip_check(hipStreamEndCapture(b.cap, &g), "hipStreamEndCapture");
+        if (se != HSF_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return se;
+        }
+        if (sc != HSF_OK) return sc;
+        b.graph = g;
+        if ((s = hip_check(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "hipGraphInstantiate")) != HSF_OK) {
+            drop_graph(b);
+            return s;
+        }
+        b.graph_base = base;
+        b.graph_valid = true;
+    }
+    return hip_check(hipGraphLaunch(b.exec, st), "hipGraphLaunch");
+}
+
+hsf_status batch_tune(Batch& b, void* const* outs, int mode, void* ws, hipStream_t st, int* chosen) {
+    hipEvent_t e0, e1;
+    hsf_status s;
+    if ((s = hip_check(hipEventCreate(&e0), "hipEventCreate")) != HSF_OK) return s;
+    if ((s = hip_check(hipEventCreate(&e1), "hipEventCreate")) != HSF_OK) {
+        (void)hipEventDestroy(e0);
+        return s;
+    }
+    float best = 1e30f;
+    int best_p = 0;
+    for (int pol = 0; pol < 3; ++pol) {
+        b.policy = pol;
+        if ((s = batch_run(b, outs, mode, 0, ws, st)) != HSF_OK) break;     // warm-up, builds tables
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < 3; ++r)
+            if ((s = batch_run(b, outs, mode, 0, ws, st)) != HSF_OK) break;
+        (void)hipEventRecord(e1, st);
+        if (s != HSF_OK) break;
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_p = pol;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b.policy = best_p;
+    if (chosen) *chosen = best_p;
+    return s;
+}
+
+}  // namespace hsf

@@ -148,7 +148,70 @@ __global__ __launch_bounds__(256) void pathsum_bf16x3_kernel(const unsigned shor
         bf16x3_tile(PA, M, PB, N, Kp, out, ldo, accumulate, tm * BF_TILE, tn * BF_TILE);
     }
 }
+__global__ __launch_bounds__(256) void split_batch(const SplitDesc* __restrict__ d, int n, unsigned char* base) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].block_start <= blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const SplitDesc& s = d[lo];
+    const uint32_t local = blockIdx.x - s.block_start;
+    const uint32_t by = local / s.blocks_x, bx = local - by * s.blocks_x;
+    const int64_t r = (int64_t)bx * 256 + threadIdx.x;
+    const int64_t k0 = (int64_t)by * 8;
+    if (r >= s.R || k0 >= s.Kp) return;
+    const float2* X = reinterpret_cast<const float2*>(base + s.x_off);
+    unsigned short* planes = reinterpret_cast<unsigned short*>(base + s.planes_off);
+    u16x8 rh, rl, ih, il;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t k = k0 + e;
+        const float2 v = k < s.K ? X[k * s.ldx + r] : make_float2(0.f, 0.f);
+        const unsigned short a = bf16_rne(v.x), b = bf16_rne(v.y);
+        rh[e] = a;
+        rl[e] = bf16_rne(v.x - bf16_to_f32(a));
+        ih[e] = b;
+        il[e] = bf16_rne(v.y - bf16_to_f32(b));
+    }
+    const int64_t plane = s.R * s.Kp;
+    *reinterpret_cast<u16x8*>(planes + r * s.Kp + k0) = rh;
+    *reinterpret_cast<u16x8*>(planes + plane + r * s.Kp + k0) = rl;
+    *reinterpret_cast<u16x8*>(planes + 2 * plane + r * s.Kp + k0) = ih;
+    *reinterpret_cast<u16x8*>(planes + 3 * plane + r * s.Kp + k0) = il;
+}
+
+// Persistent over the union of all circuits' output tiles.
+__global__ __launch_bounds__(256) void pathsum_bf16x3_batch(const GemmDesc* __restrict__ d, int n,
+                                                            unsigned char* base, int64_t tiles) {
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d[mid].tile_start <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const GemmDesc& g = d[lo];
+        const int64_t local = tile - g.tile_start;
+        const int64_t tm = local / g.tiles_n, tn = local - tm * g.tiles_n;
+        bf16x3_tile(reinterpret_cast<const unsigned short*>(base + g.a_off), g.M,
+                    reinterpret_cast<const unsigned short*>(base + g.b_off), g.N, g.K, (float2*)g.out, g.ldo, 0,
+                    tm * BF_TILE, tn * BF_TILE);
+    }
+}
+
 }  // namespace
+
+hsf_status launch_split_batch(const void* descs, int n, uint32_t total_blocks, unsigned char* base, hipStream_t st) {
+    hipLaunchKernelGGL(split_batch, dim3(total_blocks), dim3(256), 0, st, (const SplitDesc*)descs, n, base);
+    return hip_check(hipGetLastError(), "split_batch launch");
+}
+
+hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st) {
+    const int grid = persistent_grid((const void*)pathsum_bf16x3_batch, 256, 0, tiles);
+    hipLaunchKernelGGL(pathsum_bf16x3_batch, dim3(grid), dim3(256), 0, st, (const GemmDesc*)descs, n, base, tiles);
+    return hip_check(hipGetLastError(), "pathsum_bf16x3_batch launch");
+}
 
 hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
                            int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st) {

@@ -16,6 +16,15 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
 
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths);
 
+// Batched launches (tables are device arrays; offsets are relative to `base`).
+hsf_status launch_sweep_batch(const void* segs, int nseg, uint32_t total_blocks, int threads, size_t shmem,
+                              unsigned char* base, hipStream_t stream);
+void batch_sweep_prepare();
+hsf_status launch_split_batch(const void* descs, int n, uint32_t total_blocks, unsigned char* base, hipStream_t st);
+hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);
+hsf_status launch_f32_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);
+int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t tiles);
+
 // out[r * ldo + c] (+)= sum_k A[k * ldA + row0 + r] * B[k * ldB + c], r < M, c < N.
 hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void* B, int64_t ldB,
                     int64_t K, int64_t row0, int64_t M, int64_t N, void* out, int64_t ldo,

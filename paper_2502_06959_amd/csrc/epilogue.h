@@ -44,8 +44,3 @@ __device__ __forceinline__ void store_tile_128(const f32x16_t (&cr)[2][2], const
 }
 
 }  // namespace hsf
-
-namespace hsf {
-// Persistent grid for a tile loop: workgroups that fit at once on the device.
-int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t tiles);
-}  // namespace hsf

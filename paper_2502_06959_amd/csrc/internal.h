@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime_api.h>
+
 #include "hsf.h"
 
 namespace hsf {
@@ -128,6 +130,35 @@ struct SideProgram {
     std::vector<Schedule> sched;      // one per candidate tile size, largest first
 };
 
+// One (circuit, side) segment of a batched sweep launch (device table).
+struct BatchSeg {
+    const Pass* pass;
+    int64_t psi_off;         // bytes from the batch workspace base to the side's row 0
+    int64_t ld;
+    const DevOp* ops;
+    const void* subs;
+    const void* pool;
+    uint32_t n_tiles;
+    uint32_t block_start;    // first workgroup of the segment
+};
+
+// Batched path sum: one circuit's operands and output (device tables).
+struct SplitDesc {           // split of one operand into BF16 planes
+    int64_t x_off;           // bytes from the workspace base to the half-states
+    int64_t ldx, K, R, Kp;
+    int64_t planes_off;      // bytes from the workspace base to the planes
+    uint32_t blocks_x;       // workgroups along R
+    uint32_t block_start;
+};
+struct GemmDesc {
+    int64_t a_off, b_off;    // bytes from the workspace base (planes or half-states)
+    int64_t ldA, ldB, K, M, N;
+    void* out;
+    int64_t ldo;
+    int64_t tiles_n;
+    int64_t tile_start;      // first 128 x 128 tile of this circuit in the batch
+};
+
 struct DeviceSchedule {
     void* passes = nullptr;           // Pass[]
     void* ops = nullptr;              // DevOp[]
@@ -172,6 +203,14 @@ void fuse_side(Plan& p, int side);
 Schedule schedule_side(const Plan& p, int side, int tile_bits);
 // Index of the schedule used for a launch over n_paths paths.
 int pick_schedule(const Plan& p, int64_t n_paths);
+
+// Batches of circuits (batch.cpp).
+struct Batch;
+hsf_status batch_create(Plan* const* plans, int n, Batch** out);
+void batch_destroy(Batch* b);
+size_t batch_workspace(const Batch& b, int mode);
+hsf_status batch_run(Batch& b, void* const* outs, int mode, int use_graph, void* ws, hipStream_t st);
+hsf_status batch_tune(Batch& b, void* const* outs, int mode, void* ws, hipStream_t st, int* chosen);
 
 // Device side (sweep.hip / pathsum.hip).
 hsf_status ensure_device(Plan& p, DeviceCopy** out);

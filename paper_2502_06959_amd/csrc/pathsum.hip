@@ -90,6 +90,25 @@ __global__ __launch_bounds__(256) void pathsum_f32(const float2* __restrict__ A,
     }
 }
 
+// Persistent over the union of all circuits' output tiles.
+__global__ __launch_bounds__(256) void pathsum_f32_batch(const GemmDesc* __restrict__ d, int n, unsigned char* base,
+                                                         int64_t tiles) {
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d[mid].tile_start <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const GemmDesc& g = d[lo];
+        const int64_t local = tile - g.tile_start;
+        const int64_t tm = local / g.tiles_n, tn = local - tm * g.tiles_n;
+        f32_tile(reinterpret_cast<const float2*>(base + g.a_off), g.ldA,
+                 reinterpret_cast<const float2*>(base + g.b_off), g.ldB, g.K, g.M, g.N, (float2*)g.out, g.ldo, 0,
+                 tm * F32_TILE, tn * F32_TILE);
+    }
+}
+
 // ---------------------------------------------------------------- FP64 ----
 // Same structure on the 16x16x4 FP64 MFMA: wave 32 x 32 outputs (2 x 2
 // blocks), workgroup 64 x 64.  Inputs are c128, or c64 widened on load.
@@ -274,6 +293,12 @@ int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t tiles
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, shmem) != hipSuccess || per < 1) per = 1;
     return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per));
+}
+
+hsf_status launch_f32_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st) {
+    const int grid = persistent_grid((const void*)pathsum_f32_batch, 256, 0, tiles);
+    hipLaunchKernelGGL(pathsum_f32_batch, dim3(grid), dim3(256), 0, st, (const GemmDesc*)descs, n, base, tiles);
+    return hip_check(hipGetLastError(), "pathsum_f32_batch launch");
 }
 
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths) {

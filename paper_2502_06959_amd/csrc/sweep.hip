@@ -226,25 +226,15 @@ template <> struct Threads<float> { static constexpr int max = 512; };
 template <> struct Threads<double> { static constexpr int max = 512; };
 
 // KG: register-group width (4 for every tile of four or more bits).
+// One tile of one path's half-state through one LDS pass: load (or set
+// |0...0>), apply the pass's ops, store.  `st` is the path's row.
 template <typename T, int KG>
-__global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideArgs s1, int64_t p_begin) {
+__device__ __forceinline__ void sweep_tile(const Pass* __restrict__ ps, const DevOp* __restrict__ ops,
+                                           const DSub<T>* __restrict__ subs, const typename Cx<T>::v* __restrict__ pool,
+                                           typename Cx<T>::v* st, uint32_t t, int64_t path,
+                                           typename Cx<T>::v* tile) {
     using V = typename Cx<T>::v;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    V* tile = reinterpret_cast<V*>(smem_raw);
-    const bool sd = blockIdx.x >= s0.n_blocks;
-    const Pass* __restrict__ ps = sd ? s1.pass : s0.pass;
-    const DevOp* __restrict__ ops = sd ? s1.ops : s0.ops;
-    const DSub<T>* __restrict__ subs = reinterpret_cast<const DSub<T>*>(sd ? s1.subs : s0.subs);
-    const V* __restrict__ pool = reinterpret_cast<const V*>(sd ? s1.pool : s0.pool);
-    const int64_t ld = sd ? s1.ld : s0.ld;
-    const uint32_t n_tiles = sd ? s1.n_tiles : s0.n_tiles;
-    const uint32_t blk = sd ? blockIdx.x - s0.n_blocks : blockIdx.x;
-    const uint32_t pl = blk / n_tiles;
-    const uint32_t t = blk - pl * n_tiles;
-    const int64_t path = p_begin + pl;
-    V* st = reinterpret_cast<V*>(sd ? s1.psi : s0.psi) + (int64_t)pl * ld;
     const int tid = threadIdx.x, nt = blockDim.x;
-
     const int L = ps->n_local;
     const uint32_t E = 1u << L;
     V* mstage = tile + E;       // 256-entry matrix staging area after the tile
@@ -297,6 +287,46 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideA
     }
 
     for (uint32_t e = tid; e < E; e += nt) st[gidx(e)] = tile[swz(e)];
+}
+
+template <typename T, int KG>
+__global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideArgs s1, int64_t p_begin) {
+    using V = typename Cx<T>::v;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const bool sd = blockIdx.x >= s0.n_blocks;
+    const uint32_t n_tiles = sd ? s1.n_tiles : s0.n_tiles;
+    const uint32_t blk = sd ? blockIdx.x - s0.n_blocks : blockIdx.x;
+    const uint32_t pl = blk / n_tiles;
+    const uint32_t t = blk - pl * n_tiles;
+    const int64_t ld = sd ? s1.ld : s0.ld;
+    V* st = reinterpret_cast<V*>(sd ? s1.psi : s0.psi) + (int64_t)pl * ld;
+    sweep_tile<T, KG>(sd ? s1.pass : s0.pass, sd ? s1.ops : s0.ops,
+                      reinterpret_cast<const DSub<T>*>(sd ? s1.subs : s0.subs),
+                      reinterpret_cast<const V*>(sd ? s1.pool : s0.pool), st, t, p_begin + pl,
+                      reinterpret_cast<V*>(smem_raw));
+}
+
+// Many circuits' pass k in one launch: segment i covers workgroups
+// [segs[i].block_start, segs[i+1].block_start); its half-states start at
+// base + psi_off.
+template <typename T, int KG>
+__global__ __launch_bounds__(Threads<T>::max) void sweep_batch(const BatchSeg* __restrict__ segs, int nseg,
+                                                               unsigned char* base) {
+    using V = typename Cx<T>::v;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].block_start <= blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchSeg& sg = segs[lo];
+    const uint32_t blk = blockIdx.x - sg.block_start;
+    const uint32_t pl = blk / sg.n_tiles;
+    const uint32_t t = blk - pl * sg.n_tiles;
+    V* st = reinterpret_cast<V*>(base + sg.psi_off) + (int64_t)pl * sg.ld;
+    sweep_tile<T, KG>(sg.pass, sg.ops, reinterpret_cast<const DSub<T>*>(sg.subs),
+                      reinterpret_cast<const V*>(sg.pool), st, t, pl, reinterpret_cast<V*>(smem_raw));
 }
 
 std::mutex g_dev_mutex;
@@ -419,6 +449,22 @@ hsf_status launch_pass(bool dbl, int kg, uint32_t total, int threads, size_t shm
 }
 
 }  // namespace
+
+hsf_status launch_sweep_batch(const void* segs, int nseg, uint32_t total_blocks, int threads, size_t shmem,
+                              unsigned char* base, hipStream_t stream) {
+    hipLaunchKernelGGL((sweep_batch<float, kGroupBits>), dim3(total_blocks), dim3(threads), shmem, stream,
+                       (const BatchSeg*)segs, nseg, base);
+    return hip_check(hipGetLastError(), "sweep_batch launch");
+}
+
+void batch_sweep_prepare() {
+    static bool done = false;
+    if (done) return;
+    const size_t bytes = ((size_t(1) << max_tile_bits(HSF_C64)) + 256) * 8;
+    (void)hipFuncSetAttribute((const void*)sweep_batch<float, kGroupBits>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+    done = true;
+}
 
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
                      void* psiB, int64_t ldB, hipStream_t stream) {

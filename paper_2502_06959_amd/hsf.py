@@ -260,3 +260,53 @@ class ProbabilityMass(torch.autograd.Function):
     def backward(ctx, gout):
         g = ctx.plan.backward(ctx.x, ctx.chunk)
         return (gout.to(g.device) * g).to(torch.float64).cpu(), None, None, None, None
+
+
+class Batch:
+    """Many planned circuits run together (hsf_batch_*): batched LDS passes,
+    one persistent path-sum launch, optionally replayed from a HIP graph."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle for p in self.plans])
+        h = ctypes.c_void_p()
+        L.check(L.lib().hsf_batch_create(arr, len(self.plans), ctypes.byref(h)))
+        self.handle = h.value
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib().hsf_batch_destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, mode, device="cuda"):
+        m = L.SUM_MODE[mode]
+        if m not in self._ws:
+            n = int(L.lib().hsf_batch_workspace_size(ctypes.c_void_p(self.handle), m))
+            self._ws[m] = torch.empty(n, dtype=torch.uint8, device=device)
+        return self._ws[m]
+
+    def alloc_outputs(self, device="cuda"):
+        return [torch.empty((1 << p.na, 1 << p.nb), dtype=torch.complex64, device=device) for p in self.plans]
+
+    def _outs(self, outs):
+        return (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+
+    def run(self, outs, mode="bf16x3", graph=True):
+        ws = self.workspace(mode, outs[0].device)
+        L.check(L.lib().hsf_batch_run(ctypes.c_void_p(self.handle), self._outs(outs), L.SUM_MODE[mode],
+                                      1 if graph else 0, _ptr(ws), ws.numel(), _stream(outs[0])))
+        return outs
+
+    def tune(self, outs, mode="bf16x3"):
+        ws = self.workspace(mode, outs[0].device)
+        pol = ctypes.c_int32()
+        L.check(L.lib().hsf_batch_tune(ctypes.c_void_p(self.handle), self._outs(outs), L.SUM_MODE[mode], _ptr(ws),
+                                       ws.numel(), _stream(outs[0]), ctypes.byref(pol)))
+        return pol.value

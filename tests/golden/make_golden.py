@@ -1,0 +1,69 @@
+"""Writes the expected values used by the full-size GPU parity tests.
+
+Calls only the FP64 oracle (`oracle/`) and the seeded circuit generators:
+
+    python tests/golden/make_golden.py [c2 c3 c4]
+
+c2_literal.npz  C2 (P=1024): psi at 4096 seeded basis states
+c3.npz          C3: psi at its 1024 bitstrings, L, and dL/dt for 16 seeded
+                parameter ids (parameter-shift rule on the oracle HSF)
+c4.npz          C4 (P=4096): psi at 4096 seeded basis states
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import circuitgen as cg  # noqa: E402
+from oracle import grad as OG  # noqa: E402
+from oracle import hsf as H  # noqa: E402
+
+OUT = os.path.dirname(os.path.abspath(__file__))
+
+
+def sampled_psi(c, count, seed):
+    t = time.time()
+    pl = H.plan(c)
+    a = H.half_states(c, pl, "A")
+    b = H.half_states(c, pl, "B")
+    rng = np.random.default_rng(seed)
+    xs = np.unique(rng.integers(0, 1 << c["n"], size=count, dtype=np.uint64))
+    amp = H.amplitudes_at(a, b, xs, pl["nb"])
+    print(c["name"], "P", pl["P"], "sampled", len(xs), f"{time.time() - t:.1f}s", flush=True)
+    return xs, amp
+
+
+def main(which):
+    if "c2" in which:
+        xs, amp = sampled_psi(cg.c2(), 4096, 22)
+        np.savez(os.path.join(OUT, "c2_literal.npz"), x=xs, psi=amp)
+    if "c3" in which:
+        c = cg.c3()
+        xs = cg.c3_bitstrings()
+        t = time.time()
+        pl = H.plan(c)
+        a = H.half_states(c, pl, "A")
+        b = H.half_states(c, pl, "B")
+        amp = H.amplitudes_at(a, b, xs, pl["nb"])
+        L = float(np.sum(np.abs(amp) ** 2))
+        print("c3 psi", f"{time.time() - t:.1f}s", flush=True)
+        inhull = sorted({c["gates"][g]["param_id"] for blk in pl["blocks"] for g in blk["hull"]
+                         if c["gates"][g]["param_id"] >= 0})
+        rng = np.random.default_rng(333)
+        outside = [t_ for t_ in range(c["meta"]["n_params"]) if t_ not in set(inhull)]
+        ids = sorted(set(rng.choice(outside, 12, replace=False).tolist()) | set(rng.choice(inhull, 4, replace=False).tolist()))
+        g = OG.loss_grad_shift(c, xs, ids, use_hsf=True)
+        print("c3 grads", f"{time.time() - t:.1f}s", flush=True)
+        np.savez(os.path.join(OUT, "c3.npz"), x=xs, psi=amp, loss=L, grad_ids=np.array(ids),
+                 grad=np.array([g[i] for i in ids]))
+    if "c4" in which:
+        xs, amp = sampled_psi(cg.c4(), 4096, 44)
+        np.savez(os.path.join(OUT, "c4.npz"), x=xs, psi=amp)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["c2", "c3", "c4"])

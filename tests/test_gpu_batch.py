@@ -1,0 +1,77 @@
+"""GPU parity of batched runs (hsf_batch_*): many circuits with uneven qubit
+counts, cuts and path counts in batched LDS passes and one persistent path-sum
+launch, eager and replayed from a HIP graph, against per-circuit runs and the
+FP64 Schroedinger oracle."""
+import numpy as np
+import pytest
+import torch
+
+import circuitgen as cg
+from oracle import hsf as ohsf
+from oracle import sv
+from paper_2502_06959_amd import Batch, Plan
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    # the C5 recipe with smaller registers, so the oracle checks every circuit
+    cs = cg.c5(master_seed=55, count=8, n_range=(12, 17), depth_range=(6, 14))
+    return cs, [Plan(c) for c in cs]
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "f32"])
+def test_batch_matches_oracle_and_single_runs(small_batch, mode):
+    cs, plans = small_batch
+    b = Batch(plans)
+    outs = b.alloc_outputs()
+    for o in outs:
+        o.fill_(float("nan"))
+    b.run(outs, mode=mode, graph=False)
+    torch.cuda.synchronize()
+    for c, p, o in zip(cs, plans, outs):
+        got = o.cpu().numpy().reshape(-1)
+        assert np.isfinite(got).all()
+        assert ohsf.rel_l2(got, sv.run(c)) < 1e-5, c["name"]
+        A, B = p.run_paths()
+        single = p.amplitudes_full(A, B, mode=mode)
+        torch.cuda.synchronize()
+        # a batch may use larger tiles than a single run: FP32 rounding order differs
+        assert ohsf.rel_l2(got, single.cpu().numpy().reshape(-1)) < 1e-5
+
+
+def test_graph_replays_match_eager(small_batch):
+    cs, plans = small_batch
+    b = Batch(plans)
+    eager = b.alloc_outputs()
+    b.run(eager, mode="bf16x3", graph=False)
+    torch.cuda.synchronize()
+    ref = [e.clone() for e in eager]
+    outs = b.alloc_outputs()
+    for rep in range(4):
+        for o in outs:
+            o.zero_()                    # eager work between replays
+        torch.cuda.synchronize()
+        b.run(outs, mode="bf16x3", graph=True)
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), rep
+
+
+def test_autotune_keeps_results(small_batch):
+    cs, plans = small_batch
+    b = Batch(plans)
+    outs = b.alloc_outputs()
+    pol = b.tune(outs, mode="bf16x3")
+    assert pol in (0, 1, 2)
+    b.run(outs, mode="bf16x3", graph=True)
+    torch.cuda.synchronize()
+    for c, o in zip(cs, outs):
+        assert ohsf.rel_l2(o.cpu().numpy().reshape(-1), sv.run(c)) < 1e-5
