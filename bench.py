@@ -98,12 +98,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2p", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2p", choices=sorted(WORKLOADS) + ["c4", "c5"])
     ap.add_argument("--mode", default="bf16x3", choices=["f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP32 path sum")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--c4-mode", default=None, choices=["f32", "bf16x3", "f64"])
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -128,6 +129,10 @@ def main():
     from paper_2502_06959_amd import Plan
 
     torch.cuda.set_device(0)
+    if args.workload == "c5":
+        return bench_c5(args)
+    if args.workload == "c4":
+        return bench_c4(args)
     gen, desc = WORKLOADS[args.workload]
     circuit = getattr(cg, gen)()
     t0 = time.perf_counter()
@@ -243,6 +248,130 @@ def main():
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(circuit, (sa["ops_logical"], sb["ops_logical"]), P, na, nb)
+    print(json.dumps(res), flush=True)
+
+
+def bench_c5(args):
+    """64 independent circuits (n 20..30, uneven cuts, depths and path counts):
+    one tuned batch replayed from a HIP graph against per-circuit launches."""
+    import numpy as np
+    import torch
+
+    import circuitgen as cg
+    from paper_2502_06959_amd import Batch, Plan
+    cs = cg.c5()
+    plans = [Plan(c) for c in cs]
+    b = Batch(plans)
+    outs = b.alloc_outputs()
+    mode = args.mode
+    pol = b.tune(outs, mode=mode)
+    logical = sum(p.P * (p.side_stats(0)["ops_logical"] + p.side_stats(1)["ops_logical"]) for p in plans)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms = timed(lambda: b.run(outs, mode=mode, graph=True), args.steps, args.warmup)
+    halves = [p.alloc_halves(p.P) for p in plans]
+
+    def per_circuit():
+        for p, (A, B), o in zip(plans, halves, outs):
+            p.run_paths(0, p.P, A, B)
+            p.amplitudes_full(A, B, mode="f32", out=o)
+
+    ms_plain = timed(per_circuit, max(1, args.steps // 2), 1)
+    out_bytes = sum(8.0 * o.numel() for o in outs)
+    res = {"metric": "path-gate updates/s (batch of 64 circuits)", "value": logical / (ms * 1e-3),
+           "unit": "path-gate updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": f"c64 (f32 sweeps, {mode} path sum)", "data": "synthetic",
+           "config": {"workload": "c5: 64 circuits, n 20..30, cut near n/2, depth 8..24, CZ/RZZ brick, "
+                                  "joint blocks of 1-3 crossing gates, full states",
+                      "circuits": len(plans), "paths_total": sum(p.P for p in plans),
+                      "output_gib": out_bytes / 2 ** 30, "tuned_policy": pol},
+           "plain_per_circuit": {"ms_per_step": ms_plain, "path_sum": "f32",
+                                 "speedup_of_batch": ms_plain / ms},
+           "output_write_gbs": out_bytes / (ms * 1e-3) / 1e9}
+    print(json.dumps(res), flush=True)
+
+
+def c4_errors(plan, A, B, tile, mode, rows):
+    """Relative L2 error of one row tile in `mode` against the FP64 path sum
+    of the same half-states (the path sum's own error), and of the oracle's
+    sampled amplitudes that fall in that tile (the whole result's error)."""
+    import numpy as np
+    import torch
+
+    from paper_2502_06959_amd import hsf_norm2
+    g = np.load(os.path.join(ROOT, "tests", "golden", "c4.npz"))
+    xs = np.asarray(g["x"], dtype=np.uint64)
+    row_of = (xs >> np.uint64(plan.nb)).astype(np.int64)
+    r0 = int(row_of[0] // rows) * rows
+    sel = np.nonzero((row_of >= r0) & (row_of < r0 + rows))[0]
+    plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode=mode, out=tile)
+    o64 = plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode="f64")
+    d = hsf_norm2(tile.reshape(-1), o64.reshape(-1)).cpu().numpy()
+    ref = hsf_norm2(o64.reshape(-1)).cpu().numpy()[0]
+    del o64
+    col = (xs[sel] & np.uint64((1 << plan.nb) - 1)).astype(np.int64)
+    idx = torch.from_numpy((row_of[sel] - r0) * (1 << plan.nb) + col).cuda()
+    got = tile.reshape(-1)[idx].cpu().numpy().astype(np.complex128)
+    want = g["psi"][sel]
+    return {"vs_fp64_path_sum_rel_l2": float(np.sqrt(d[1] / ref)),
+            "vs_oracle_rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+            "oracle_samples": int(len(sel)), "tile_rows": [r0, r0 + rows]}
+
+
+def bench_c4(args):
+    """n=34 (P=4096): sweeps of all paths, then the path sum over every output
+    row, streamed in row tiles through one reusable tile buffer, in the
+    requested precision (f32, bf16x3 or f64)."""
+    import numpy as np
+    import torch
+
+    import circuitgen as cg
+    from paper_2502_06959_amd import Plan, hsf_workspace_size
+    c = cg.c4()
+    plan = Plan(c)
+    A, B = plan.alloc_halves(plan.P)
+    rows = 1 << 13
+    mode = args.c4_mode or args.mode
+    odt = torch.complex128 if mode == "f64" else torch.complex64
+    tile = torch.empty((rows, 1 << plan.nb), dtype=odt, device="cuda")
+    ws = None
+    if mode == "bf16x3":
+        ws = torch.empty(hsf_workspace_size(plan.handle, 1, plan.P, 1), dtype=torch.uint8, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    plan.run_paths(0, plan.P, A, B)
+    ev[1].record()
+    for r0 in range(0, 1 << plan.na, rows):
+        plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode=mode, out=tile, ws=ws)
+    ev[2].record()
+    torch.cuda.synchronize()
+    sw, ps = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    flops = 8.0 * (1 << plan.na) * (1 << plan.nb) * plan.P
+    logical = plan.P * (plan.side_stats(0)["ops_logical"] + plan.side_stats(1)["ops_logical"])
+    peak = {"f32": 157.3, "bf16x3": 2500.0 / 3, "f64": 78.6}[mode]
+    err = None
+    if not args.no_check:
+        err = c4_errors(plan, A, B, tile, mode, rows)
+    res = {"metric": "path-sum TFLOP/s (n=34, P=4096)", "value": flops / (ps * 1e-3) / 1e12, "unit": "TFLOP/s",
+           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": sw + ps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": mode, "data": "synthetic",
+           "config": {"workload": "c4: n=34 cut 17|17 depth-24 Haar+CZ brickwork, 6 joint blocks of rank 4 "
+                                  "(P=4096), all 2^34 amplitudes in 2^13-row tiles", "path_sum": mode},
+           "breakdown_ms": {"sweeps": sw, "path_sum": ps},
+           "sweep_updates_per_s": logical / (sw * 1e-3),
+           "mfma_frac_of_mode_peak": flops / (ps * 1e-3) / 1e12 / peak,
+           "mode_peak_tflops": peak, "error": err}
     print(json.dumps(res), flush=True)
 
 

@@ -16,6 +16,15 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
 
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths);
 
+// Path sums staged through LDS for K >= kLdsMinPaths (pathsum_lds.hip).
+constexpr int64_t kLdsMinPaths = 128;
+bool path_sum_lds_fits(int mode, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K, int64_t M,
+                       int64_t N);
+hsf_status path_sum_f32_lds(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
+                            int64_t N, float2* out, int64_t ldo, int accumulate, hipStream_t st);
+hsf_status path_sum_bf16x3_lds(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
+                               int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st);
+
 // Batched launches (tables are device arrays; offsets are relative to `base`).
 hsf_status launch_sweep_batch(const void* segs, int nseg, uint32_t total_blocks, int threads, size_t shmem,
                               unsigned char* base, hipStream_t stream);

@@ -303,8 +303,9 @@ hsf_status launch_f32_batch(const void* descs, int n, int64_t tiles, unsigned ch
 
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths) {
     // hi and lo BF16 planes of the real and imaginary parts of both operands,
-    // paths padded to a multiple of 16
-    const size_t kp = (size_t)std::max<int64_t>(16, (n_paths + 15) / 16 * 16);
+    // paths padded to a multiple of 32 (the streaming kernel pads to 16, the
+    // LDS-staged one to 32)
+    const size_t kp = (size_t)std::max<int64_t>(32, (n_paths + 31) / 32 * 32);
     return kp * ((size_t(1) << na) + (size_t(1) << nb)) * 4 * sizeof(uint16_t) + 256;
 }
 
@@ -314,6 +315,14 @@ hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_
 hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K,
                     int64_t row0, int64_t M, int64_t N, void* out, int64_t ldo, int accumulate, void* ws,
                     hipStream_t st) {
+    if (dtype == HSF_C64 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3) &&
+        path_sum_lds_fits(mode, (const float2*)A + row0, ldA, B, ldB, K, M, N)) {
+        if (mode == HSF_SUM_F32)
+            return path_sum_f32_lds((const float2*)A + row0, ldA, (const float2*)B, ldB, K, M, N, (float2*)out, ldo,
+                                    accumulate, st);
+        return path_sum_bf16x3_lds((const float2*)A + row0, ldA, (const float2*)B, ldB, K, M, N, (float2*)out, ldo,
+                                   accumulate, ws, st);
+    }
     if (dtype == HSF_C64 && mode == HSF_SUM_F32) {
         const int64_t tn = (N + F32_TILE - 1) / F32_TILE, tiles = tn * ((M + F32_TILE - 1) / F32_TILE);
         const int grid = persistent_grid((const void*)pathsum_f32, 256, 0, tiles);

@@ -29,8 +29,10 @@ def _rand(rng, k, d, dtype):
     return x.astype(dtype)
 
 
+# K >= 128 takes the LDS-staged kernels: several tiles, ragged path chunks
+# (K mod 16, K mod 32 != 0) and tiles cut by M or N < 128
 CASES = [(1, 1, 1), (5, 3, 2), (6, 6, 3), (7, 8, 17), (9, 7, 33), (8, 8, 64), (10, 6, 100), (6, 10, 257),
-         (12, 12, 32), (3, 11, 7)]
+         (12, 12, 32), (3, 11, 7), (7, 7, 128), (9, 8, 300), (5, 10, 1000), (10, 4, 161), (8, 9, 4096)]
 
 
 @pytest.mark.parametrize("na,nb,K", CASES)
@@ -69,6 +71,38 @@ def test_path_sum_row_range_ld_and_accumulate(mode):
     got = out.cpu().numpy()
     assert ohsf.rel_l2(got[:, :1 << nb], ref[100:400]) < (1e-12 if mode == "f64" else 1e-5)
     assert np.all(got[:, 1 << nb:] == 0)          # padding columns untouched
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+def test_many_paths_row_ranges(mode):
+    """LDS-staged path sums on row ranges that cut tiles (M = 322, even, and
+    M = 333, odd: FP32 then falls back to the streaming kernel), with
+    accumulation over two path chunks."""
+    rng = np.random.default_rng(11)
+    na, nb, K = 10, 9, 400
+    A = _rand(rng, K, 1 << na, np.complex64)
+    B = _rand(rng, K, 1 << nb, np.complex64)
+    ref = A.astype(np.complex128).T @ B.astype(np.complex128)
+    plan = _shape_plan(na, nb)
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    for r0, r1 in ((64, 386), (101, 434)):
+        out = plan.amplitudes_full(Ad[:250], Bd[:250], n_paths=250, rows=(r0, r1), mode=mode)
+        plan.amplitudes_full(Ad[250:], Bd[250:], n_paths=K - 250, rows=(r0, r1), mode=mode, out=out,
+                             accumulate=True)
+        assert ohsf.rel_l2(out.cpu().numpy(), ref[r0:r1]) < 1e-5, (r0, r1)
+
+
+def test_lds_and_streaming_fp32_sums_agree_bitwise():
+    """The LDS-staged FP32 kernel runs the streaming kernel's MFMA sequence:
+    rows 0..M-1 (even M, staged) equal rows 0..M-2 (odd M, streamed) bit for bit."""
+    rng = np.random.default_rng(12)
+    na, nb, K = 9, 8, 333
+    A = torch.from_numpy(_rand(rng, K, 1 << na, np.complex64)).cuda()
+    B = torch.from_numpy(_rand(rng, K, 1 << nb, np.complex64)).cuda()
+    plan = _shape_plan(na, nb)
+    staged = plan.amplitudes_full(A, B, mode="f32")
+    streamed = plan.amplitudes_full(A, B, mode="f32", rows=(0, (1 << na) - 1))
+    assert torch.equal(staged[:-1], streamed)
 
 
 def test_bf16x3_on_c2p_matches_fp64_mode():
