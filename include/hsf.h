@@ -105,7 +105,8 @@ typedef struct {
 
 typedef struct {
     double rank_tol;         /* s_m counted if s_m > rank_tol * s_0 (default 1e-10) */
-    int32_t max_side_qubits; /* hull qubits allowed per side (default 4, max 4)      */
+    int32_t max_side_qubits; /* hull qubits per side of SVD-factored blocks (default
+                                4, max 4); product-form blocks: see hsf_plan       */
     int32_t dtype;           /* hsf_dtype of the half-states (default HSF_C64)      */
     int32_t tile_qubits;     /* qubits per LDS tile (0 = largest that fits)         */
     int32_t fuse;            /* 1 = fuse gates on the host (default), 0 = off       */
@@ -126,11 +127,38 @@ typedef struct {
  *   out             receives the plan; destroy with hsf_plan_destroy.
  * Blocks are renumbered in the order of a topological sort of the circuit
  * with blocks contracted (ready node with smallest gate id first), and path
- * p has digit m_k = (p / R_k) mod r_k, R_k = prod_{k'>k} r_k'.            */
+ * p has digit m_k = (p / R_k) mod r_k, R_k = prod_{k'>k} r_k'.
+ * Decomposition: a hull made of diagonal gates that each touch at most one
+ * qubit of one side (a cascade, Sec. V, and the analytic decompositions of
+ * Sec. IV's cascade example) is decomposed in the computational basis of its
+ * other side s: U = sum_m c(m) |m><m| (x) prod_j diag(phi_j(m, 0),
+ * phi_j(m, 1)), r_k = 2^|s|, |s| <= 4 and up to HSF_MAX_BLOCK_SIDE qubits on
+ * the wide side; it is used only when 2^|s| equals the Schmidt rank (the
+ * singular values of the operator's reshape).  Every other hull is reshaped
+ * and SVD-factored (Sec. IV-A) and may have at most max_side_qubits per
+ * side (HSF_E_BLOCK_TOO_LARGE otherwise).                                  */
 hsf_status hsf_plan(const hsf_circuit* circuit, int32_t cut, const int64_t* block_gate_ids,
                     const int64_t* block_offsets, int32_t n_blocks,
                     const hsf_plan_options* opts, hsf_plan_t* out);
 void hsf_plan_destroy(hsf_plan_t plan);
+
+/* Joint blocks for a cut (host only), Sec. III-A and Sec. V: the gates of
+ * every maximal run of consecutive diagonal gates commute, so the run's
+ * crossing two-qubit gates are regrouped into the fewest stars (gates that
+ * share one qubit; each star has Schmidt rank <= 2), a minimum vertex cover
+ * of the bipartite graph of those gates (Koenig's theorem).  Other crossing
+ * gates are blocks of their own.
+ *   order           n_gates entries: a gate order with the same unitary
+ *                   (order[i] = original index of the i-th gate); inside a
+ *                   run the non-crossing gates come first (circuit order),
+ *                   then each star's gates together.
+ *   block_gate_ids  positions in `order` of every block's gates, back to back
+ *                   (at most n_gates entries);
+ *   block_offsets   n_blocks + 1 entries (room for n_gates + 1);
+ *   n_blocks        receives the block count.
+ * Pass the reordered circuit and these blocks to hsf_plan.                   */
+hsf_status hsf_find_blocks(const hsf_circuit* circuit, int32_t cut, int64_t* order,
+                           int64_t* block_gate_ids, int64_t* block_offsets, int32_t* n_blocks);
 
 /* Dimensions: n, cut, n_a = n - cut - 1, n_b = cut + 1, K blocks, P paths.  */
 hsf_status hsf_plan_dims(hsf_plan_t plan, int32_t* n, int32_t* cut, int32_t* n_a,
@@ -138,18 +166,22 @@ hsf_status hsf_plan_dims(hsf_plan_t plan, int32_t* n, int32_t* cut, int32_t* n_a
 int64_t hsf_num_paths(hsf_plan_t plan);
 
 /* Block k (plan order): rank r_k, digit stride R_k, side-a and side-b
- * supports (ascending qubits, at most 4 each), hull size and the caller's
- * index of the block.                                                         */
+ * supports (ascending qubits; sa and sb need room for HSF_MAX_BLOCK_SIDE
+ * entries each, or are NULL), hull size and the caller's index of the block. */
+#define HSF_MAX_BLOCK_SIDE 16
 hsf_status hsf_block_info(hsf_plan_t plan, int32_t k, int32_t* rank, int64_t* stride,
-                          int32_t* n_sa, int32_t sa[4], int32_t* n_sb, int32_t sb[4],
+                          int32_t* n_sa, int32_t* sa, int32_t* n_sb, int32_t* sb,
                           int64_t* hull_len, int32_t* caller_index);
 /* Hull gate ids of block k, ascending (hull_len entries).                    */
 hsf_status hsf_block_hull(hsf_plan_t plan, int32_t k, int64_t* ids);
-/* Schmidt data of block k (Sec. IV-A): all singular values (4^min(|sa|,|sb|)
- * entries, descending) and the folded factors sqrt(s_m) X_m (side a) and
- * sqrt(s_m) Y_m (side b), m < r_k, each row-major 2^|s| x 2^|s| complex128
- * interleaved, ascending qubit = ascending significance.  Any pointer may be
- * NULL.                                                                       */
+/* Schmidt data of block k (Sec. IV-A): all singular values (SVD-factored:
+ * 4^min(|sa|,|sb|) entries; product form: 2^min(|sa|,|sb|); descending) and
+ * the factors the half-states receive, X_m (side a) and Y_m (side b),
+ * m < r_k, each row-major 2^|s| x 2^|s| complex128 interleaved, ascending
+ * qubit = ascending significance (SVD-factored: sqrt(s_m) times the singular
+ * operators; product form: the products of hsf_plan).  Any pointer may be
+ * NULL.  HSF_E_UNSUPPORTED if a factor is requested for a side of more than
+ * 8 qubits.                                                                   */
 hsf_status hsf_block_factors(hsf_plan_t plan, int32_t k, double* sigma, double* xa, double* yb);
 /* Digits m_k(p) of path p (K entries).                                       */
 hsf_status hsf_path_digits(hsf_plan_t plan, int64_t p, int32_t* digits);

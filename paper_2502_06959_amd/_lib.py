@@ -18,6 +18,7 @@ GATE_KIND = {"U": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "SDG": 6, "T": 7, "
              "RZ": 11, "PHASE": 12, "CX": 13, "CZ": 14, "CP": 15, "RZZ": 16, "SWAP": 17, "ISWAP": 18}
 
 HSF_C64, HSF_C128 = 0, 1
+HSF_MAX_BLOCK_SIDE = 16
 SUM_MODE = {"f32": 0, "bf16x3": 1, "f64": 2, "c128": 3}
 
 
@@ -48,6 +49,7 @@ SIGNATURES = {
     "hsf_plan": (c_int32, [P(HsfCircuit), c_int32, P(c_int64), P(c_int64), c_int32, P(HsfPlanOptions),
                            P(c_void_p)]),
     "hsf_plan_destroy": (None, [c_void_p]),
+    "hsf_find_blocks": (c_int32, [P(HsfCircuit), c_int32, P(c_int64), P(c_int64), P(c_int64), P(c_int32)]),
     "hsf_plan_dims": (c_int32, [c_void_p, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int32),
                                 P(c_int64)]),
     "hsf_num_paths": (c_int64, [c_void_p]),

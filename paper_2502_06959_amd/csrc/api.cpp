@@ -53,6 +53,13 @@ hsf_status hsf_plan(const hsf_circuit* circuit, int32_t cut, const int64_t* bloc
     HSF_GUARD_END
 }
 
+hsf_status hsf_find_blocks(const hsf_circuit* circuit, int32_t cut, int64_t* order, int64_t* block_gate_ids,
+                           int64_t* block_offsets, int32_t* n_blocks) {
+    HSF_GUARD_BEGIN
+    return find_blocks(circuit, cut, order, block_gate_ids, block_offsets, n_blocks);
+    HSF_GUARD_END
+}
+
 void hsf_plan_destroy(hsf_plan_t plan) {
     if (!plan) return;
     Plan* p = reinterpret_cast<Plan*>(plan);
@@ -78,7 +85,7 @@ hsf_status hsf_plan_dims(hsf_plan_t plan, int32_t* n, int32_t* cut, int32_t* n_a
 int64_t hsf_num_paths(hsf_plan_t plan) { return plan ? P_(plan)->P : -1; }
 
 hsf_status hsf_block_info(hsf_plan_t plan, int32_t k, int32_t* rank, int64_t* stride, int32_t* n_sa,
-                          int32_t sa[4], int32_t* n_sb, int32_t sb[4], int64_t* hull_len,
+                          int32_t* sa, int32_t* n_sb, int32_t* sb, int64_t* hull_len,
                           int32_t* caller_index) {
     if (!plan) return fail(HSF_E_ARG, "null plan");
     const Plan* p = P_(plan);
@@ -110,6 +117,8 @@ hsf_status hsf_block_factors(hsf_plan_t plan, int32_t k, double* sigma, double* 
     const Plan* p = P_(plan);
     if (k < 0 || k >= (int32_t)p->blocks.size()) return fail(HSF_E_ARG, "block index out of range");
     const Block& b = p->blocks[k];
+    if ((xa && b.xa.empty() && !b.sa.empty()) || (yb && b.yb.empty() && !b.sb.empty()))
+        return fail(HSF_E_UNSUPPORTED, "the block's factor on a side wider than 8 qubits is not expanded");
     if (sigma) std::memcpy(sigma, b.sigma.data(), b.sigma.size() * sizeof(double));
     if (xa) std::memcpy(xa, b.xa.data(), b.xa.size() * sizeof(cd));
     if (yb) std::memcpy(yb, b.yb.data(), b.yb.size() * sizeof(cd));

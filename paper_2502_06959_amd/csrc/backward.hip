@@ -320,11 +320,10 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
     L.dimA = int64_t(1) << p.na;
     L.dimB = int64_t(1) << p.nb;
+    // one checkpoint per factor op of each side (a product-form block has one per qubit)
     L.ka = L.kb = 0;
-    for (const Block& b : p.blocks) {
-        L.ka += !b.sa.empty();
-        L.kb += !b.sb.empty();
-    }
+    for (const SideOp& o : p.side[0].raw) L.ka += o.kind == SideOp::SLOT;
+    for (const SideOp& o : p.side[1].raw) L.kb += o.kind == SideOp::SLOT;
     L.n_occ = 0;
     for (int s = 0; s < 2; ++s)
         for (const SideOp& o : p.side[s].raw) L.n_occ += o.param_id >= 0;
@@ -613,6 +612,8 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             for (size_t i = 0; i < raw.size(); ++i) {
                 const SideOp& o = raw[i];
                 if (o.kind == SideOp::SLOT) {
+                    if (kc >= (side == 0 ? Lo.ka : Lo.kb))
+                        return fail(HSF_E_ARG, "internal: more factor slots than checkpoints");
                     V* c = ck[side] + (size_t)kc * chunk * dim[side];
                     if ((s = R.copy_rows(vS[side], dim[side], c, dim[side], dim[side], np)) != HSF_OK) return s;
                     ++kc;
@@ -695,27 +696,29 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
                 const int t = gp.second;
                 if (t >= n_params) continue;
                 for (int sg = 0; sg < 2; ++sg) {
-                    std::vector<double> sig;
-                    std::vector<cd> xa, yb;
-                    int r = 0;
+                    Factors fs;
                     const double ang = p.gates[gid].param + (sg == 0 ? half_pi : -half_pi);
-                    if ((s = factor_block(p, b, gid, ang, sig, xa, yb, r)) != HSF_OK) return s;
+                    if ((s = factor_block(p, b, gid, ang, fs)) != HSF_OK) return s;
+                    const int r = fs.rank;
                     if (r > b.rank)
                         return fail(HSF_E_UNSUPPORTED, "a shifted block has a larger Schmidt rank than the plan's");
+                    if (fs.product != b.product || fs.pa.size() != b.pa.size() || fs.pb.size() != b.pb.size())
+                        return fail(HSF_E_UNSUPPORTED, "a shifted block changes its decomposition form");
                     // patched pools: factors of block k replaced (missing ranks zero)
                     std::vector<cd> all;
                     all.reserve(Lo.pool_elems);
                     for (int side = 0; side < 2; ++side) {
-                        const std::vector<cd>& f = side == 0 ? xa : yb;
-                        const int kk = (int)(side == 0 ? b.sa.size() : b.sb.size());
-                        const size_t d2 = (size_t)1 << (2 * kk);
+                        const std::vector<FactorPiece>& pcs = side == 0 ? fs.pa : fs.pb;
                         for (const Schedule& sc : p.side[side].sched) {
                             std::vector<cd> pl = sc.pool;
                             for (const DevOp& op : sc.devops)
-                                if (op.type == DOP_SLOT && op.block == (int)k)
+                                if (op.type == DOP_SLOT && op.block == (int)k) {
+                                    const std::vector<cd>& f = pcs[op.piece].m;
+                                    const size_t d2 = (size_t)1 << (2 * op.k);
                                     for (int m = 0; m < b.rank; ++m)
                                         for (size_t e = 0; e < d2; ++e)
                                             pl[op.mat + m * d2 + e] = m < r ? f[m * d2 + e] : cd(0);
+                                }
                             if (pl.empty()) pl.push_back(cd(0));
                             all.insert(all.end(), pl.begin(), pl.end());
                         }

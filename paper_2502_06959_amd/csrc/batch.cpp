@@ -23,7 +23,10 @@ struct Batch {
     // device tables
     void* segs = nullptr;
     void* splits = nullptr;
-    void* gemms = nullptr;
+    void* gemms = nullptr;               // streaming path sums (fewer than kLdsMinPaths paths)
+    void* gemms_lds = nullptr;           // LDS-staged path sums
+    int n_gemm = 0, n_gemm_lds = 0;
+    int64_t tiles_lds = 0;
     std::vector<int> round_first, round_n;
     std::vector<uint32_t> round_blocks, round_emax;
     int n_split = 0;
@@ -52,9 +55,9 @@ int sched_index(const Batch& b, const Plan& p) {
 }
 
 void free_tables(Batch& b) {
-    for (void* q : {b.segs, b.splits, b.gemms})
+    for (void* q : {b.segs, b.splits, b.gemms, b.gemms_lds})
         if (q) (void)hipFree(q);
-    b.segs = b.splits = b.gemms = nullptr;
+    b.segs = b.splits = b.gemms = b.gemms_lds = nullptr;
     b.built_policy = b.built_mode = -1;
     b.built_outs.clear();
 }
@@ -139,12 +142,13 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
     if (s != HSF_OK) return s;
     // split descriptors (BF16 planes) and path-sum descriptors
     std::vector<SplitDesc> sp;
-    std::vector<GemmDesc> gm;
+    std::vector<GemmDesc> gm, gl;
     uint32_t sb = 0;
-    int64_t tiles = 0;
+    int64_t tiles = 0, tiles_lds = 0;
     for (int i = 0; i < n; ++i) {
         const Plan& p = *b.plans[i];
         const int64_t M = int64_t(1) << p.na, N = int64_t(1) << p.nb;
+        const bool deep = p.P >= kLdsMinPaths;
         if (mode == HSF_SUM_BF16X3) {
             for (int side = 0; side < 2; ++side) {
                 SplitDesc d{};
@@ -156,6 +160,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
                 d.planes_off = side == 0 ? b.offPA[i] : b.offPB[i];
                 d.blocks_x = (uint32_t)((d.R + 255) / 256);
                 d.block_start = sb;
+                d.chunked = deep ? 1u : 0u;
                 sb += d.blocks_x * (uint32_t)(d.Kp / 8);
                 sp.push_back(d);
             }
@@ -177,12 +182,17 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
         g.out = outs[i];
         g.ldo = N;
         g.tiles_n = (N + 127) / 128;
-        g.tile_start = tiles;
-        tiles += g.tiles_n * ((M + 127) / 128);
-        gm.push_back(g);
+        int64_t& t = deep ? tiles_lds : tiles;
+        g.tile_start = t;
+        t += g.tiles_n * ((M + 127) / 128);
+        (deep ? gl : gm).push_back(g);
     }
     if ((s = upload_table(sp, &b.splits)) != HSF_OK) return s;
     if ((s = upload_table(gm, &b.gemms)) != HSF_OK) return s;
+    if ((s = upload_table(gl, &b.gemms_lds)) != HSF_OK) return s;
+    b.n_gemm = (int)gm.size();
+    b.n_gemm_lds = (int)gl.size();
+    b.tiles_lds = tiles_lds;
     b.n_split = (int)sp.size();
     b.split_blocks = sb;
     b.tiles = tiles;
@@ -203,11 +213,16 @@ hsf_status enqueue(Batch& b, int mode, unsigned char* base, hipStream_t st) {
                                b.round_blocks[k], threads, shmem, base, st);
         if (s != HSF_OK) return s;
     }
-    if (mode == HSF_SUM_BF16X3) {
-        if ((s = launch_split_batch(b.splits, b.n_split, b.split_blocks, base, st)) != HSF_OK) return s;
-        return launch_bf16x3_batch(b.gemms, (int)b.plans.size(), b.tiles, base, st);
+    const bool bf = mode == HSF_SUM_BF16X3;
+    if (bf && (s = launch_split_batch(b.splits, b.n_split, b.split_blocks, base, st)) != HSF_OK) return s;
+    if (b.n_gemm_lds > 0) {
+        s = bf ? launch_bf16x3_lds_batch(b.gemms_lds, b.n_gemm_lds, b.tiles_lds, base, st)
+               : launch_f32_lds_batch(b.gemms_lds, b.n_gemm_lds, b.tiles_lds, base, st);
+        if (s != HSF_OK) return s;
     }
-    return launch_f32_batch(b.gemms, (int)b.plans.size(), b.tiles, base, st);
+    if (b.n_gemm == 0) return HSF_OK;
+    return bf ? launch_bf16x3_batch(b.gemms, b.n_gemm, b.tiles, base, st)
+              : launch_f32_batch(b.gemms, b.n_gemm, b.tiles, base, st);
 }
 
 }  // namespace
@@ -230,7 +245,8 @@ hsf_status batch_create(Plan* const* plans, int n, Batch** out) {
     for (int i = 0; i < n; ++i) {
         const Plan& p = *plans[i];
         const int64_t M = int64_t(1) << p.na, N = int64_t(1) << p.nb;
-        const int64_t kp = std::max<int64_t>(16, (p.P + 15) / 16 * 16);
+        // streaming kernel: paths padded to 16; LDS-staged kernel: chunks of 32
+        const int64_t kp = p.P >= kLdsMinPaths ? (p.P + 31) / 32 * 32 : std::max<int64_t>(16, (p.P + 15) / 16 * 16);
         b->kp.push_back(kp);
         b->offPA.push_back((int64_t)ob);
         ob += a256((size_t)4 * M * kp * 2);

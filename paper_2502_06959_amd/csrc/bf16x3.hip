@@ -174,6 +174,15 @@ __global__ __launch_bounds__(256) void split_batch(const SplitDesc* __restrict__
         ih[e] = b;
         il[e] = bf16_rne(v.y - bf16_to_f32(b));
     }
+    if (s.chunked) {
+        // chunks of 32 paths: row r of chunk c holds 4 planes x 32 paths
+        unsigned short* row = planes + ((k0 >> 5) * s.R + r) * 128 + (k0 & 31);
+        *reinterpret_cast<u16x8*>(row) = rh;
+        *reinterpret_cast<u16x8*>(row + 32) = rl;
+        *reinterpret_cast<u16x8*>(row + 64) = ih;
+        *reinterpret_cast<u16x8*>(row + 96) = il;
+        return;
+    }
     const int64_t plane = s.R * s.Kp;
     *reinterpret_cast<u16x8*>(planes + r * s.Kp + k0) = rh;
     *reinterpret_cast<u16x8*>(planes + plane + r * s.Kp + k0) = rl;

@@ -32,6 +32,8 @@ void batch_sweep_prepare();
 hsf_status launch_split_batch(const void* descs, int n, uint32_t total_blocks, unsigned char* base, hipStream_t st);
 hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);
 hsf_status launch_f32_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);
+hsf_status launch_f32_lds_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);
+hsf_status launch_bf16x3_lds_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);
 int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t tiles);
 
 // out[r * ldo + c] (+)= sum_k A[k * ldA + row0 + r] * B[k * ldB + c], r < M, c < N.

@@ -14,7 +14,9 @@ namespace hsf {
 
 using cd = std::complex<double>;
 
-constexpr int kMaxSideQubits = 4;     // widest block support per side
+constexpr int kMaxSideQubits = 4;     // widest block support per side (SVD-factored blocks)
+constexpr int kMaxProductSide = 16;   // widest side of a product-form block (must match HSF_MAX_BLOCK_SIDE)
+constexpr int kMaxExpandSide = 8;     // product factors are expanded to dense matrices up to this width
 constexpr int kMaxOpQubits = 4;       // widest dense op in a side program
 constexpr int kMaxTileBits = 24;
 
@@ -41,6 +43,27 @@ bool gate_matrix(int kind, int nq, double param, const double* explicit_m, std::
 void jacobi_svd(int m, int n, const std::vector<cd>& A, std::vector<cd>& W,
                 std::vector<double>& s, std::vector<cd>& Vh);
 
+// Factor of one block applied on one side, on qubits q (ascending, global
+// numbering): rank matrices of size 2^|q| x 2^|q| (q.back() = most
+// significant bit of the matrix index).
+struct FactorPiece {
+    std::vector<int> q;
+    std::vector<cd> m;
+};
+
+// The decomposition U_k = sum_m X_m (x) Y_m of one block.  SVD-factored
+// blocks have one piece per side (X_m = sqrt(s_m) times the m-th right
+// singular operator, Y_m likewise).  Product-form blocks (every gate
+// diagonal and touching at most one qubit of the wide side) are decomposed
+// in the computational basis of the narrow side: X_m (x) Y_m =
+// |m><m| (x) prod_j phi_j(m), one 1-qubit piece per qubit.
+struct Factors {
+    std::vector<double> sigma;       // singular values of the block operator, descending
+    int rank = 0;
+    bool product = false;
+    std::vector<FactorPiece> pa, pb; // pieces on side a / side b
+};
+
 struct Block {
     int caller_index = 0;
     std::vector<std::pair<int64_t, int>> params;   // (gate id, param id) of rotations in the hull
@@ -49,8 +72,10 @@ struct Block {
     std::vector<double> sigma;       // all singular values, descending
     int rank = 0;
     int64_t stride = 1;              // R_k
-    std::vector<cd> xa;              // rank x (dA x dA), sqrt(s) folded
+    std::vector<cd> xa;              // rank x (dA x dA): the whole side-a factor (empty if too wide to expand)
     std::vector<cd> yb;              // rank x (dB x dB)
+    bool product = false;            // product-form decomposition (see Factors)
+    std::vector<FactorPiece> pa, pb; // what the side programs apply
 };
 
 // One op of a side program on side-local qubits (q[0] = most significant
@@ -62,6 +87,7 @@ struct SideOp {
     int q[kMaxOpQubits] = {0, 0, 0, 0};
     std::vector<cd> m;       // DENSE: d x d; DIAG: d entries; SLOT: rank x d x d
     int block = -1;          // SLOT: plan block index
+    int piece = 0;           // SLOT: which piece of the block's factor on this side
     int rank = 1;
     int64_t stride = 1;
     int64_t logical = 1;     // circuit gates represented by this op
@@ -84,7 +110,7 @@ struct DevOp {
     int32_t rank;        // SLOT: factor count; GROUP: sub-op count
     int64_t stride;      // SLOT: digit stride R_k
     int32_t block;       // SLOT: plan block index
-    int32_t pad;
+    int32_t piece;       // SLOT: factor piece of that block on this side
 };
 
 // Sub-op of a group.  D1: 2x2 matrix m on register position g.  SIGN/PHASE:
@@ -149,6 +175,8 @@ struct SplitDesc {           // split of one operand into BF16 planes
     int64_t planes_off;      // bytes from the workspace base to the planes
     uint32_t blocks_x;       // workgroups along R
     uint32_t block_start;
+    uint32_t chunked;        // 1: planes chunked by 32 paths (LDS-staged path sum); 0: [plane][row][Kp]
+    uint32_t pad;
 };
 struct GemmDesc {
     int64_t a_off, b_off;    // bytes from the workspace base (planes or half-states)
@@ -186,14 +214,25 @@ struct Plan {
     int64_t n_params = 0;
 };
 
+// Joint blocks of commuting crossing gates (blocks.cpp): a gate order and
+// the blocks as positions in that order (hsf_find_blocks).
+hsf_status find_blocks(const hsf_circuit* c, int32_t cut, int64_t* order, int64_t* ids, int64_t* offs,
+                       int32_t* n_blocks);
+
+// Validates gate i of an n-qubit circuit and builds its matrix.
+hsf_status load_gate(const hsf_gate& in, int n, int64_t i, Gate& g);
+
 hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, const int64_t* offs,
                       int32_t n_blocks, const hsf_plan_options* opts, Plan** out);
 
-// Operator-Schmidt factors of block k with gate `gate_id` taking angle
-// `param` instead of its own (gate_id < 0: unchanged).  Fills sigma, the
-// folded factors (rank x d x d each) and the rank under the plan's tolerance.
-hsf_status factor_block(const Plan& p, const Block& b, int64_t gate_id, double param, std::vector<double>& sigma,
-                        std::vector<cd>& xa, std::vector<cd>& yb, int& rank);
+// Operator-Schmidt decomposition of block b with gate `gate_id` taking angle
+// `param` instead of its own (gate_id < 0: unchanged), as factor pieces,
+// with the rank under the plan's tolerance.  A block that qualifies for the
+// product form gets it; others need at most kMaxSideQubits per side.
+hsf_status factor_block(const Plan& p, const Block& b, int64_t gate_id, double param, Factors& f);
+// Dense side factors (rank x d x d) from the pieces; empty if the side has
+// more than kMaxExpandSide qubits.
+void expand_factors(const Block& b, const Factors& f, std::vector<cd>& xa, std::vector<cd>& yb);
 
 // dU/dparam = D U for a rotation gate (RX, RY, RZ, RZZ, PHASE, CP); false otherwise.
 bool gate_generator(int kind, int nq, std::vector<cd>& d);

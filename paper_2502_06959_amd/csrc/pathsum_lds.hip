@@ -56,20 +56,17 @@ constexpr int F_KC = 16;                          // paths per stage
 constexpr int F_STAGE = 2 * F_KC * 128;           // float2 entries of A and B per stage
 constexpr size_t F_LDS = 2 * F_STAGE * sizeof(float2);
 
-// A, B 16-byte aligned, ldA, ldB, M and N even (checked by the launcher).
-__global__ __launch_bounds__(256) void pathsum_f32_lds(const float2* __restrict__ A, int64_t ldA,
-                                                       const float2* __restrict__ B, int64_t ldB, int64_t K,
-                                                       int64_t M, int64_t N, float2* __restrict__ out, int64_t ldo,
-                                                       int accumulate, int64_t tiles_m, int64_t tiles_n,
-                                                       int xcd_bands) {
-    extern __shared__ __align__(16) float2 fl[];
+// One 128 x 128 output tile at (m0, n0).  A, B 16-byte aligned; ldA, ldB,
+// M and N even (checked by the launchers).  Ends with a barrier, so the
+// caller may start the next tile at once.
+__device__ __forceinline__ void f32_lds_tile(const float2* __restrict__ A, int64_t ldA,
+                                             const float2* __restrict__ B, int64_t ldB, int64_t K, int64_t M,
+                                             int64_t N, float2* __restrict__ out, int64_t ldo, int accumulate,
+                                             int64_t m0, int64_t n0, float2* fl) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int li = lane & 31, lk = lane >> 5, wm = w >> 1, wn = w & 1;
-    const int64_t chunks = (K + F_KC - 1) / F_KC, tiles = tiles_m * tiles_n;
-    for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
-        int64_t tm, tn;
-        tile_coords(item, tiles_m, tiles_n, xcd_bands != 0, tm, tn);
-        const int64_t m0 = tm * 128, n0 = tn * 128;
+    const int64_t chunks = (K + F_KC - 1) / F_KC;
+    {
         // staging: thread t moves entries 2q, 2q+1 of path row q / 64 for
         // q = t + 256 i, i < 4, of both operands
         float4 ra[4], rb[4];
@@ -137,6 +134,45 @@ __global__ __launch_bounds__(256) void pathsum_f32_lds(const float2* __restrict_
     }
 }
 
+__global__ __launch_bounds__(256) void pathsum_f32_lds(const float2* __restrict__ A, int64_t ldA,
+                                                       const float2* __restrict__ B, int64_t ldB, int64_t K,
+                                                       int64_t M, int64_t N, float2* __restrict__ out, int64_t ldo,
+                                                       int accumulate, int64_t tiles_m, int64_t tiles_n,
+                                                       int xcd_bands) {
+    extern __shared__ __align__(16) float2 fl[];
+    const int64_t tiles = tiles_m * tiles_n;
+    for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
+        int64_t tm, tn;
+        tile_coords(item, tiles_m, tiles_n, xcd_bands != 0, tm, tn);
+        f32_lds_tile(A, ldA, B, ldB, K, M, N, out, ldo, accumulate, tm * 128, tn * 128, fl);
+    }
+}
+
+// Persistent over the union of the output tiles of several circuits (a
+// sorted table of descriptors, offsets from `base`).
+__device__ __forceinline__ const GemmDesc& find_desc(const GemmDesc* __restrict__ d, int n, int64_t tile) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile_start <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return d[lo];
+}
+
+__global__ __launch_bounds__(256) void pathsum_f32_lds_batch(const GemmDesc* __restrict__ d, int n,
+                                                             unsigned char* base, int64_t tiles) {
+    extern __shared__ __align__(16) float2 fl[];
+    for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
+        const GemmDesc& g = find_desc(d, n, item);
+        int64_t tm, tn;
+        tile_coords(item - g.tile_start, (g.M + 127) / 128, g.tiles_n, false, tm, tn);
+        f32_lds_tile(reinterpret_cast<const float2*>(base + g.a_off), g.ldA,
+                     reinterpret_cast<const float2*>(base + g.b_off), g.ldB, g.K, g.M, g.N, (float2*)g.out, g.ldo,
+                     0, tm * 128, tn * 128, fl);
+    }
+}
+
 // ------------------------------------------------------- split-BF16 x3 ----
 // Chunked planes: for path chunk c (32 paths) and row r, 256 contiguous bytes
 // [re hi | re lo | im hi | im lo] x 32 paths, so one tile's rows of one
@@ -195,19 +231,15 @@ __device__ __forceinline__ void stash_rows(unsigned char* stage, int srow, int s
     }
 }
 
-__global__ __launch_bounds__(256) void pathsum_bf16x3_lds(const unsigned short* __restrict__ PA, int64_t M,
-                                                          const unsigned short* __restrict__ PB, int64_t N,
-                                                          int64_t chunks, float2* __restrict__ out, int64_t ldo,
-                                                          int accumulate, int64_t tiles_m, int64_t tiles_n,
-                                                          int xcd_bands) {
-    extern __shared__ __align__(16) unsigned char bl[];
+// One 128 x 128 output tile at (m0, n0) from chunked planes; ends with a
+// barrier.
+__device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict__ PA, int64_t M,
+                                                const unsigned short* __restrict__ PB, int64_t N, int64_t chunks,
+                                                float2* __restrict__ out, int64_t ldo, int accumulate, int64_t m0,
+                                                int64_t n0, unsigned char* bl) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int li = lane & 31, lk = lane >> 5, wm = w >> 1, wn = w & 1;
-    const int64_t tiles = tiles_m * tiles_n;
-    for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
-        int64_t tm, tn;
-        tile_coords(item, tiles_m, tiles_n, xcd_bands != 0, tm, tn);
-        const int64_t m0 = tm * 128, n0 = tn * 128;
+    {
         // staging: 16 threads move one 256-byte row; thread t takes rows
         // t / 16 + 16 i, i < 8, bytes 16 (t % 16) .. +15, of both operands
         uint4 ra[8], rb[8];
@@ -280,6 +312,35 @@ __global__ __launch_bounds__(256) void pathsum_bf16x3_lds(const unsigned short* 
     }
 }
 
+__global__ __launch_bounds__(256) void pathsum_bf16x3_lds(const unsigned short* __restrict__ PA, int64_t M,
+                                                          const unsigned short* __restrict__ PB, int64_t N,
+                                                          int64_t chunks, float2* __restrict__ out, int64_t ldo,
+                                                          int accumulate, int64_t tiles_m, int64_t tiles_n,
+                                                          int xcd_bands) {
+    extern __shared__ __align__(16) unsigned char bl[];
+    const int64_t tiles = tiles_m * tiles_n;
+    for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
+        int64_t tm, tn;
+        tile_coords(item, tiles_m, tiles_n, xcd_bands != 0, tm, tn);
+        bf16x3_lds_tile(PA, M, PB, N, chunks, out, ldo, accumulate, tm * 128, tn * 128, bl);
+    }
+}
+
+// Batched: descriptors hold chunked planes (a_off, b_off) and the padded path
+// count K (a multiple of 32).
+__global__ __launch_bounds__(256) void pathsum_bf16x3_lds_batch(const GemmDesc* __restrict__ d, int n,
+                                                                unsigned char* base, int64_t tiles) {
+    extern __shared__ __align__(16) unsigned char bl[];
+    for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
+        const GemmDesc& g = find_desc(d, n, item);
+        int64_t tm, tn;
+        tile_coords(item - g.tile_start, (g.M + 127) / 128, g.tiles_n, false, tm, tn);
+        bf16x3_lds_tile(reinterpret_cast<const unsigned short*>(base + g.a_off), g.M,
+                        reinterpret_cast<const unsigned short*>(base + g.b_off), g.N, g.K / B_KC, (float2*)g.out,
+                        g.ldo, 0, tm * 128, tn * 128, bl);
+    }
+}
+
 // (cheap host calls, repeated per launch so that every device gets them)
 hsf_status set_lds_attrs() {
     hsf_status s = hip_check(hipFuncSetAttribute((const void*)pathsum_bf16x3_lds,
@@ -289,7 +350,14 @@ hsf_status set_lds_attrs() {
     s = hip_check(hipFuncSetAttribute((const void*)pathsum_f32_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)F_LDS),
                   "hipFuncSetAttribute");
-    return s;
+    if (s != HSF_OK) return s;
+    s = hip_check(hipFuncSetAttribute((const void*)pathsum_bf16x3_lds_batch,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)B_LDS),
+                  "hipFuncSetAttribute");
+    if (s != HSF_OK) return s;
+    return hip_check(hipFuncSetAttribute((const void*)pathsum_f32_lds_batch,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)F_LDS),
+                     "hipFuncSetAttribute");
 }
 
 void grid_shape(const void* kernel, size_t shmem, int64_t M, int64_t N, int64_t& tiles_m, int64_t& tiles_n,
@@ -345,6 +413,24 @@ hsf_status path_sum_bf16x3_lds(const float2* A, int64_t ldA, const float2* B, in
     hipLaunchKernelGGL(pathsum_bf16x3_lds, dim3(grid), dim3(256), B_LDS, st, PA, M, PB, N, chunks, out, ldo,
                        accumulate, tm, tn, bands);
     return hip_check(hipGetLastError(), "pathsum_bf16x3_lds launch");
+}
+
+hsf_status launch_f32_lds_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st) {
+    hsf_status s = set_lds_attrs();
+    if (s != HSF_OK) return s;
+    const int grid = persistent_grid((const void*)pathsum_f32_lds_batch, 256, F_LDS, tiles);
+    hipLaunchKernelGGL(pathsum_f32_lds_batch, dim3(grid), dim3(256), F_LDS, st, (const GemmDesc*)descs, n, base,
+                       tiles);
+    return hip_check(hipGetLastError(), "pathsum_f32_lds_batch launch");
+}
+
+hsf_status launch_bf16x3_lds_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st) {
+    hsf_status s = set_lds_attrs();
+    if (s != HSF_OK) return s;
+    const int grid = persistent_grid((const void*)pathsum_bf16x3_lds_batch, 256, B_LDS, tiles);
+    hipLaunchKernelGGL(pathsum_bf16x3_lds_batch, dim3(grid), dim3(256), B_LDS, st, (const GemmDesc*)descs, n, base,
+                       tiles);
+    return hip_check(hipGetLastError(), "pathsum_bf16x3_lds_batch launch");
 }
 
 }  // namespace hsf

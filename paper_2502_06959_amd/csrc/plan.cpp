@@ -66,9 +66,148 @@ std::vector<char> closure(const std::vector<Gate>& gs, int n, const std::vector<
 
 }  // namespace
 
-hsf_status factor_block(const Plan& p, const Block& blk, int64_t gate_id, double param, std::vector<double>& sigma,
-                        std::vector<cd>& xa, std::vector<cd>& yb, int& rank) {
+namespace {
+
+// Counts singular values above the plan's tolerance; fails inside the
+// ambiguity window around it.
+hsf_status count_rank(const Plan& p, const std::vector<double>& sigma, int& rank) {
+    const double s0 = sigma.empty() ? 0.0 : sigma[0];
+    if (!(s0 > 0)) return fail(HSF_E_RANK_AMBIGUOUS, "operator is zero");
+    int r = 0;
+    for (double sv : sigma) {
+        const double rel = sv / s0;
+        if (rel > p.rank_tol * 1e-3 && rel <= p.rank_tol * 1e3)
+            return fail(HSF_E_RANK_AMBIGUOUS, "singular value ratio " + std::to_string(rel) + " near the rank tolerance");
+        if (rel > p.rank_tol) ++r;
+    }
+    rank = r;
+    return HSF_OK;
+}
+
+// Diagonal entry of gate g (matrix m) at the basis state given by bit(q).
+template <typename BitOf>
+cd diag_entry(const Gate& g, const std::vector<cd>& m, BitOf bit) {
+    int idx = 0;
+    for (int j = 0; j < g.nq; ++j) idx |= bit(g.q[j]) << (g.nq - 1 - j);
+    const int d = 1 << g.nq;
+    return m[(size_t)idx * d + idx];
+}
+
+// Product form (computational basis of the narrow side s, Sec. IV's
+// cascade example): possible when every hull gate is diagonal and touches at
+// most one qubit of the wide side.  Then U = sum_m c(m) |m><m| (x) prod_j
+// diag(phi_j(m, 0), phi_j(m, 1)).  Taken only when its rank 2^|s| is the
+// operator's Schmidt rank (the singular values of u(m, x_wide)).
+hsf_status try_product(const Plan& p, const Block& blk, int64_t gate_id, double param, Factors& f,
+                       bool& taken) {
+    taken = false;
+    const int ka = (int)blk.sa.size(), kb = (int)blk.sb.size();
+    if (ka == 0 || kb == 0) return HSF_OK;
+    for (int64_t gi : blk.hull)
+        if (!p.gates[gi].diag) return HSF_OK;
+    std::vector<cd> alt;
+    auto mat = [&](int64_t gi) -> const std::vector<cd>& {
+        if (gi != gate_id) return p.gates[gi].m;
+        gate_matrix(p.gates[gi].kind, p.gates[gi].nq, param, nullptr, alt);
+        return alt;
+    };
+    for (int narrow_a = 0; narrow_a < 2; ++narrow_a) {
+        // try the smaller side first (side b on a tie)
+        const bool a_narrow = (ka < kb) ? narrow_a == 0 : narrow_a == 1;
+        const std::vector<int>& sq = a_narrow ? blk.sa : blk.sb;
+        const std::vector<int>& wq = a_narrow ? blk.sb : blk.sa;
+        const int ks = (int)sq.size(), kw = (int)wq.size();
+        if (ks > 4 || kw > kMaxProductSide) continue;
+        std::vector<int> wpos(64, -1), spos(64, -1);
+        for (int j = 0; j < kw; ++j) wpos[wq[j]] = j;
+        for (int i = 0; i < ks; ++i) spos[sq[i]] = i;
+        // gates: the wide qubit each one touches (-1: none)
+        std::vector<int> wide_of;
+        bool ok = true;
+        for (int64_t gi : blk.hull) {
+            const Gate& g = p.gates[gi];
+            int w = -1, nw = 0;
+            for (int j = 0; j < g.nq; ++j)
+                if (wpos[g.q[j]] >= 0) {
+                    w = wpos[g.q[j]];
+                    ++nw;
+                }
+            if (nw > 1) ok = false;
+            wide_of.push_back(w);
+        }
+        if (!ok) continue;
+        const int R = 1 << ks;
+        // c(m) and phi_j(m, z)
+        std::vector<cd> c(R, cd(1.0)), phi((size_t)R * kw * 2, cd(1.0));
+        for (int m = 0; m < R; ++m)
+            for (size_t h = 0; h < blk.hull.size(); ++h) {
+                const int64_t gi = blk.hull[h];
+                const Gate& g = p.gates[gi];
+                const std::vector<cd>& gm = mat(gi);
+                const int w = wide_of[h];
+                if (w < 0) {
+                    c[m] *= diag_entry(g, gm, [&](int q) { return (m >> spos[q]) & 1; });
+                    continue;
+                }
+                for (int z = 0; z < 2; ++z)
+                    phi[((size_t)m * kw + w) * 2 + z] *=
+                        diag_entry(g, gm, [&](int q) { return spos[q] >= 0 ? (m >> spos[q]) & 1 : z; });
+            }
+        // Schmidt coefficients: singular values of u(m, x_w) (rows m)
+        const int64_t W = int64_t(1) << kw;
+        std::vector<cd> u((size_t)R * W);
+        for (int m = 0; m < R; ++m)
+            for (int64_t x = 0; x < W; ++x) {
+                cd v = c[m];
+                for (int j = 0; j < kw; ++j) v *= phi[((size_t)m * kw + j) * 2 + ((x >> j) & 1)];
+                u[(size_t)m * W + x] = v;
+            }
+        std::vector<cd> Wl, Vh;
+        std::vector<double> sigma;
+        jacobi_svd(R, (int)W, u, Wl, sigma, Vh);
+        int rank = 0;
+        hsf_status st = count_rank(p, sigma, rank);
+        if (st != HSF_OK) return st;
+        if (rank != R) continue;
+        f.sigma = sigma;
+        f.rank = R;
+        f.product = true;
+        std::vector<FactorPiece> ns(ks), ws(kw);
+        for (int i = 0; i < ks; ++i) {
+            ns[i].q = {sq[i]};
+            ns[i].m.assign((size_t)R * 4, cd(0));
+            for (int m = 0; m < R; ++m) {
+                const int bit = (m >> i) & 1;
+                ns[i].m[(size_t)m * 4 + bit * 3] = i == 0 ? c[m] : cd(1.0);
+            }
+        }
+        for (int j = 0; j < kw; ++j) {
+            ws[j].q = {wq[j]};
+            ws[j].m.assign((size_t)R * 4, cd(0));
+            for (int m = 0; m < R; ++m) {
+                ws[j].m[(size_t)m * 4] = phi[((size_t)m * kw + j) * 2];
+                ws[j].m[(size_t)m * 4 + 3] = phi[((size_t)m * kw + j) * 2 + 1];
+            }
+        }
+        f.pa = a_narrow ? ns : ws;
+        f.pb = a_narrow ? ws : ns;
+        taken = true;
+        return HSF_OK;
+    }
+    return HSF_OK;
+}
+
+}  // namespace
+
+hsf_status factor_block(const Plan& p, const Block& blk, int64_t gate_id, double param, Factors& f) {
     const int ka = (int)blk.sa.size(), kb = (int)blk.sb.size(), nl = ka + kb;
+    f = Factors();
+    bool taken = false;
+    hsf_status ps = try_product(p, blk, gate_id, param, f, taken);
+    if (ps != HSF_OK || taken) return ps;
+    if (ka > p.max_side || kb > p.max_side)
+        return fail(HSF_E_BLOCK_TOO_LARGE, "support " + std::to_string(ka) + "|" + std::to_string(kb) +
+                                               " exceeds the per-side limit of SVD-factored blocks");
     const int da = 1 << ka, db = 1 << kb, d = 1 << nl;
     int local[64];
     for (int i = 0; i < kb; ++i) local[blk.sb[i]] = i;
@@ -96,21 +235,14 @@ hsf_status factor_block(const Plan& p, const Block& blk, int64_t gate_id, double
                 for (int jb = 0; jb < db; ++jb)
                     At[(size_t)(ib * db + jb) * cols + (ia * da + ja)] = U[(size_t)(ia * db + ib) * d + (ja * db + jb)];
     std::vector<cd> W, Vh;
-    jacobi_svd(rows, cols, At, W, sigma, Vh);
-    const double s0 = sigma.empty() ? 0.0 : sigma[0];
-    if (!(s0 > 0)) return fail(HSF_E_RANK_AMBIGUOUS, "operator is zero");
+    jacobi_svd(rows, cols, At, W, f.sigma, Vh);
     int r = 0;
-    for (double sv : sigma) {
-        const double rel = sv / s0;
-        if (rel > p.rank_tol * 1e-3 && rel <= p.rank_tol * 1e3)
-            return fail(HSF_E_RANK_AMBIGUOUS, "singular value ratio " + std::to_string(rel) + " near the rank tolerance");
-        if (rel > p.rank_tol) ++r;
-    }
-    rank = r;
-    xa.assign((size_t)r * da * da, cd(0));
-    yb.assign((size_t)r * db * db, cd(0));
+    hsf_status st = count_rank(p, f.sigma, r);
+    if (st != HSF_OK) return st;
+    f.rank = r;
+    std::vector<cd> xa((size_t)r * da * da, cd(0)), yb((size_t)r * db * db, cd(0));
     for (int m = 0; m < r; ++m) {
-        const double rt = std::sqrt(sigma[m]);
+        const double rt = std::sqrt(f.sigma[m]);
         for (int e = 0; e < da * da; ++e) xa[(size_t)m * da * da + e] = rt * Vh[(size_t)m * cols + e];
         for (int e = 0; e < db * db; ++e) yb[(size_t)m * db * db + e] = rt * W[(size_t)m * rows + e];
     }
@@ -121,6 +253,57 @@ hsf_status factor_block(const Plan& p, const Block& blk, int64_t gate_id, double
     if (kb == 0)
         for (int m = 0; m < r; ++m)
             for (int e = 0; e < da * da; ++e) xa[(size_t)m * da * da + e] *= yb[m];
+    if (ka > 0) f.pa.push_back(FactorPiece{blk.sa, std::move(xa)});
+    if (kb > 0) f.pb.push_back(FactorPiece{blk.sb, std::move(yb)});
+    return HSF_OK;
+}
+
+void expand_factors(const Block& b, const Factors& f, std::vector<cd>& xa, std::vector<cd>& yb) {
+    for (int s = 0; s < 2; ++s) {
+        const std::vector<int>& sup = s == 0 ? b.sa : b.sb;
+        const std::vector<FactorPiece>& pcs = s == 0 ? f.pa : f.pb;
+        std::vector<cd>& out = s == 0 ? xa : yb;
+        out.clear();
+        const int k = (int)sup.size();
+        if (k == 0 || k > kMaxExpandSide) continue;
+        if (!f.product) {
+            out = pcs[0].m;
+            continue;
+        }
+        // product of 1-qubit pieces; piece i acts on sup[i], bit i of the index
+        const int64_t d = int64_t(1) << k;
+        out.assign((size_t)f.rank * d * d, cd(0));
+        for (int m = 0; m < f.rank; ++m)
+            for (int64_t r = 0; r < d; ++r)
+                for (int64_t c = 0; c < d; ++c) {
+                    cd v(1.0);
+                    for (int i = 0; i < k && v != cd(0); ++i)
+                        v *= pcs[i].m[(size_t)m * 4 + ((r >> i) & 1) * 2 + ((c >> i) & 1)];
+                    out[((size_t)m * d + r) * d + c] = v;
+                }
+    }
+}
+
+hsf_status load_gate(const hsf_gate& in, int n, int64_t i, Gate& g) {
+    g.kind = in.kind;
+    g.nq = in.nq;
+    g.param = in.param;
+    g.param_id = in.param_id;
+    if (in.nq < 1 || in.nq > 3) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": nq must be 1..3");
+    for (int j = 0; j < in.nq; ++j) {
+        if (in.q[j] < 0 || in.q[j] >= n) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": qubit out of range");
+        for (int l = 0; l < j; ++l)
+            if (in.q[l] == in.q[j]) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": repeated qubit");
+        g.q[j] = in.q[j];
+    }
+    const int want = (in.kind >= HSF_GATE_H && in.kind <= HSF_GATE_PHASE) ? 1
+                     : (in.kind >= HSF_GATE_CX && in.kind <= HSF_GATE_ISWAP) ? 2 : 0;
+    if (in.kind != HSF_GATE_U && want != in.nq)
+        return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": kind does not match nq");
+    if (in.kind == HSF_GATE_U && !in.matrix) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": U needs a matrix");
+    if (!gate_matrix(in.kind, in.nq, in.param, in.matrix, g.m))
+        return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": unknown kind");
+    g.diag = matrix_is_diag(g.m, 1 << in.nq);
     return HSF_OK;
 }
 
@@ -154,27 +337,9 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
     const int64_t G = c->n_gates;
     p->gates.resize(G);
     for (int64_t i = 0; i < G; ++i) {
-        const hsf_gate& in = c->gates[i];
         Gate& g = p->gates[i];
-        g.kind = in.kind;
-        g.nq = in.nq;
-        g.param = in.param;
-        g.param_id = in.param_id;
-        if (in.nq < 1 || in.nq > 3) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": nq must be 1..3");
-        for (int j = 0; j < in.nq; ++j) {
-            if (in.q[j] < 0 || in.q[j] >= n) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": qubit out of range");
-            for (int l = 0; l < j; ++l)
-                if (in.q[l] == in.q[j]) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": repeated qubit");
-            g.q[j] = in.q[j];
-        }
-        const int want = (in.kind >= HSF_GATE_H && in.kind <= HSF_GATE_PHASE) ? 1
-                         : (in.kind >= HSF_GATE_CX && in.kind <= HSF_GATE_ISWAP) ? 2 : 0;
-        if (in.kind != HSF_GATE_U && want != in.nq)
-            return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": kind does not match nq");
-        if (in.kind == HSF_GATE_U && !in.matrix) return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": U needs a matrix");
-        if (!gate_matrix(in.kind, in.nq, in.param, in.matrix, g.m))
-            return fail(HSF_E_ARG, "gate " + std::to_string(i) + ": unknown kind");
-        g.diag = matrix_is_diag(g.m, 1 << in.nq);
+        hsf_status gs = load_gate(c->gates[i], n, i, g);
+        if (gs != HSF_OK) return gs;
         if (g.param_id >= 0) p->n_params = std::max<int64_t>(p->n_params, g.param_id + 1);
     }
 
@@ -264,12 +429,17 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
         for (int64_t gi : blk.hull)
             for (int j = 0; j < p->gates[gi].nq; ++j) qs.insert(p->gates[gi].q[j]);
         for (int q : qs) (q > cut ? blk.sa : blk.sb).push_back(q);
-        if ((int)blk.sa.size() > p->max_side || (int)blk.sb.size() > p->max_side)
-            return fail(HSF_E_BLOCK_TOO_LARGE, "block " + std::to_string(b) + " support " + std::to_string(blk.sa.size()) + "|" + std::to_string(blk.sb.size()));
         for (int64_t gi : blk.hull)
             if (p->gates[gi].param_id >= 0) blk.params.push_back({gi, p->gates[gi].param_id});
-        hsf_status fs = factor_block(*p, blk, -1, 0.0, blk.sigma, blk.xa, blk.yb, blk.rank);
+        Factors fb;
+        hsf_status fs = factor_block(*p, blk, -1, 0.0, fb);
         if (fs != HSF_OK) return fail(fs, "block " + std::to_string(b) + ": " + hsf::g_last_error_copy());
+        blk.sigma = fb.sigma;
+        blk.rank = fb.rank;
+        blk.product = fb.product;
+        expand_factors(blk, fb, blk.xa, blk.yb);
+        blk.pa = std::move(fb.pa);
+        blk.pb = std::move(fb.pb);
         p->blocks.push_back(std::move(blk));
     }
 
@@ -314,19 +484,22 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
             const int k = plan_index[nd - G];
             const Block& b = p->blocks[k];
             for (int s = 0; s < 2; ++s) {
-                const std::vector<int>& sup = s == 0 ? b.sa : b.sb;
-                if (sup.empty()) continue;
+                const std::vector<FactorPiece>& pcs = s == 0 ? b.pa : b.pb;
                 const int off = s == 0 ? p->nb : 0;
-                SideOp op;
-                op.kind = SideOp::SLOT;
-                op.k = (int)sup.size();
-                // factor index: ascending qubit = ascending significance => q[0] is the top qubit
-                for (int j = 0; j < op.k; ++j) op.q[j] = sup[op.k - 1 - j] - off;
-                op.m = s == 0 ? b.xa : b.yb;
-                op.block = k;
-                op.rank = b.rank;
-                op.stride = b.stride;
-                p->side[s].ops.push_back(std::move(op));
+                for (size_t pi = 0; pi < pcs.size(); ++pi) {
+                    const FactorPiece& pc = pcs[pi];
+                    SideOp op;
+                    op.kind = SideOp::SLOT;
+                    op.k = (int)pc.q.size();
+                    // factor index: ascending qubit = ascending significance => q[0] is the top qubit
+                    for (int j = 0; j < op.k; ++j) op.q[j] = pc.q[op.k - 1 - j] - off;
+                    op.m = pc.m;
+                    op.block = k;
+                    op.piece = (int)pi;
+                    op.rank = b.rank;
+                    op.stride = b.stride;
+                    p->side[s].ops.push_back(std::move(op));
+                }
             }
         }
     }
@@ -574,6 +747,7 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
             d.rank = o.rank;
             d.stride = o.stride;
             d.block = o.block;
+            d.piece = o.piece;
             sc.pool.insert(sc.pool.end(), o.m.begin(), o.m.end());
             sc.devops.push_back(d);
         }

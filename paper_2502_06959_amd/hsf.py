@@ -36,6 +36,48 @@ def _gate_struct(g):
     return s, m
 
 
+def _circuit_struct(circuit):
+    gates = circuit["gates"]
+    arr = (L.HsfGate * max(1, len(gates)))()
+    keep = [arr]
+    for i, g in enumerate(gates):
+        s, m = _gate_struct(g)
+        arr[i] = s
+        keep.append(m)
+    c = L.HsfCircuit(n_qubits=int(circuit["n"]), reserved=0, n_gates=len(gates),
+                     gates=ctypes.cast(arr, ctypes.POINTER(L.HsfGate)))
+    return c, keep
+
+
+def hsf_find_blocks(circuit, cut=None):
+    """(order, blocks): a gate order with the same unitary and joint blocks of
+    the commuting crossing gates, as positions in that order."""
+    cut = circuit["cut"] if cut is None else cut
+    c, keep = _circuit_struct(circuit)
+    G = len(circuit["gates"])
+    order = np.zeros(max(1, G), dtype=np.int64)
+    ids = np.zeros(max(1, G), dtype=np.int64)
+    offs = np.zeros(G + 1, dtype=np.int64)
+    nb = ctypes.c_int32()
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    L.check(L.lib().hsf_find_blocks(ctypes.byref(c), int(cut), order.ctypes.data_as(p64), ids.ctypes.data_as(p64),
+                                    offs.ctypes.data_as(p64), ctypes.byref(nb)))
+    del keep
+    blocks = [[int(v) for v in ids[offs[k]:offs[k + 1]]] for k in range(nb.value)]
+    return [int(v) for v in order[:G]], blocks
+
+
+def joint_blocked(circuit, cut=None):
+    """The circuit with its gates in hsf_find_blocks' order and those blocks."""
+    order, blocks = hsf_find_blocks(circuit, cut)
+    out = dict(circuit)
+    out["gates"] = [circuit["gates"][i] for i in order]
+    out["blocks"] = blocks
+    if cut is not None:
+        out["cut"] = cut
+    return out
+
+
 def hsf_plan(circuit, cut=None, blocks=None, dtype="c64", rank_tol=1e-10, max_side_qubits=4, tile_qubits=0,
              fuse=True):
     """Plan for `circuit` (a dict with n, gates[, cut, blocks]); returns the
@@ -43,15 +85,7 @@ def hsf_plan(circuit, cut=None, blocks=None, dtype="c64", rank_tol=1e-10, max_si
     lib = L.lib()
     cut = circuit["cut"] if cut is None else cut
     blocks = circuit.get("blocks", []) if blocks is None else blocks
-    gates = circuit["gates"]
-    arr = (L.HsfGate * max(1, len(gates)))()
-    keep = []
-    for i, g in enumerate(gates):
-        s, m = _gate_struct(g)
-        arr[i] = s
-        keep.append(m)
-    c = L.HsfCircuit(n_qubits=int(circuit["n"]), reserved=0, n_gates=len(gates),
-                     gates=ctypes.cast(arr, ctypes.POINTER(L.HsfGate)))
+    c, keep = _circuit_struct(circuit)
     ids = np.array([int(i) for b in blocks for i in b] or [0], dtype=np.int64)
     offs = np.zeros(len(blocks) + 1, dtype=np.int64)
     offs[1:] = np.cumsum([len(b) for b in blocks]) if blocks else []
@@ -142,7 +176,7 @@ class Plan:
     def block_info(self, k):
         r, na_, nb_, ci = (ctypes.c_int32() for _ in range(4))
         st, hl = ctypes.c_int64(), ctypes.c_int64()
-        sa, sb = (ctypes.c_int32 * 4)(), (ctypes.c_int32 * 4)()
+        sa, sb = (ctypes.c_int32 * L.HSF_MAX_BLOCK_SIDE)(), (ctypes.c_int32 * L.HSF_MAX_BLOCK_SIDE)()
         L.check(L.lib().hsf_block_info(ctypes.c_void_p(self.handle), k, ctypes.byref(r), ctypes.byref(st),
                                        ctypes.byref(na_), sa, ctypes.byref(nb_), sb, ctypes.byref(hl),
                                        ctypes.byref(ci)))
@@ -153,13 +187,16 @@ class Plan:
                 "hull": [int(v) for v in hull[:hl.value]], "caller_index": ci.value}
 
     def block_factors(self, k):
+        """(sigma, xa, yb): singular values and the dense side factors of
+        block k (a side wider than 8 qubits gives None)."""
         info = self.block_info(k)
         ka, kb, r = len(info["sa"]), len(info["sb"]), info["rank"]
-        sig = np.zeros(4 ** min(ka, kb), dtype=np.float64)
-        xa = np.zeros((r, 2 ** ka, 2 ** ka), dtype=np.complex128)
-        yb = np.zeros((r, 2 ** kb, 2 ** kb), dtype=np.complex128)
-        L.check(L.lib().hsf_block_factors(ctypes.c_void_p(self.handle), k, sig.ctypes.data, xa.ctypes.data,
-                                          yb.ctypes.data))
+        sig = np.zeros(4 ** min(ka, kb, 8), dtype=np.float64)
+        xa = np.zeros((r, 2 ** ka, 2 ** ka), dtype=np.complex128) if ka <= 8 else None
+        yb = np.zeros((r, 2 ** kb, 2 ** kb), dtype=np.complex128) if kb <= 8 else None
+        L.check(L.lib().hsf_block_factors(ctypes.c_void_p(self.handle), k, sig.ctypes.data,
+                                          xa.ctypes.data if xa is not None else None,
+                                          yb.ctypes.data if yb is not None else None))
         return sig, xa, yb
 
     def digits(self, p):

@@ -8,6 +8,10 @@ c2_literal.npz  C2 (P=1024): psi at 4096 seeded basis states
 c3.npz          C3: psi at its 1024 bitstrings, L, and dL/dt for 16 seeded
                 parameter ids (parameter-shift rule on the oracle HSF)
 c4.npz          C4 (P=4096): psi at 4096 seeded basis states
+qaoa_q30.npz    single-layer QAOA MaxCut on a seeded SBM graph with Table II's
+                q30-1 shape (15|15 qubits, p_intra 0.8, p_inter 0.1): psi at
+                4096 seeded basis states among the first 10^6 (the oracle HSF
+                over the generator's own cascades, not the library's blocks)
 """
 import os
 import sys
@@ -63,7 +67,18 @@ def main(which):
     if "c4" in which:
         xs, amp = sampled_psi(cg.c4(), 4096, 44)
         np.savez(os.path.join(OUT, "c4.npz"), x=xs, psi=amp)
+    if "qaoa" in which:
+        c = cg.qaoa_sbm(100, (15, 15), 0.8, 0.1)
+        t = time.time()
+        pl = H.plan(c)
+        a = H.half_states(c, pl, "A")
+        b = H.half_states(c, pl, "B")
+        rng = np.random.default_rng(300)
+        xs = np.unique(rng.integers(0, 10 ** 6, size=4096, dtype=np.uint64))
+        amp = H.amplitudes_at(a, b, xs, pl["nb"])
+        print(c["name"], "P", pl["P"], "sampled", len(xs), f"{time.time() - t:.1f}s", flush=True)
+        np.savez(os.path.join(OUT, "qaoa_q30.npz"), x=xs, psi=amp)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c2", "c3", "c4"])
+    main(sys.argv[1:] or ["c2", "c3", "c4", "qaoa"])
