@@ -105,6 +105,28 @@ def test_lds_and_streaming_fp32_sums_agree_bitwise():
     assert torch.equal(staged[:-1], streamed)
 
 
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+@pytest.mark.parametrize("K", [40, 200])
+def test_odd_leading_dimension_output(mode, K):
+    """An output whose leading dimension is odd cannot take the 16-byte paired
+    stores; the per-lane stores must give the same values (streaming and
+    LDS-staged kernels)."""
+    rng = np.random.default_rng(13)
+    na, nb = 9, 8
+    A = _rand(rng, K, 1 << na, np.complex64)
+    B = _rand(rng, K, 1 << nb, np.complex64)
+    ref = A.astype(np.complex128).T @ B.astype(np.complex128)
+    plan = _shape_plan(na, nb)
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    odd = torch.zeros((1 << na, (1 << nb) + 1), dtype=torch.complex64, device="cuda")
+    plan.amplitudes_full(Ad, Bd, mode=mode, out=odd)
+    even = plan.amplitudes_full(Ad, Bd, mode=mode)
+    got = odd.cpu().numpy()
+    assert ohsf.rel_l2(got[:, :1 << nb], ref) < 1e-5
+    assert np.all(got[:, 1 << nb:] == 0)
+    assert np.array_equal(got[:, :1 << nb], even.cpu().numpy())
+
+
 def test_bf16x3_on_c2p_matches_fp64_mode():
     """The chosen form on the benchmarked workload: split-BF16 x3 against the
     FP64 path sum of the same half-states, over all 2^28 amplitudes."""
