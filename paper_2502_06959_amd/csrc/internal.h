@@ -96,6 +96,10 @@ struct SideOp {
 };
 
 // Device op (plain data, read by the sweep kernels).
+// A register group whose bits all lie below 6 + k ("wave-private") maps the
+// 64 lanes and its k bits onto tile bits 0 .. 5+k, so wave w only touches the
+// elements whose higher tile bits spell w (and the loop index): two
+// consecutive wave-private groups need no workgroup barrier between them.
 //   DOP_GROUP: every thread holds the 2^k amplitudes that differ in tile bits
 //     bit[0..k) (register position g <-> tile bit bit[g]) and applies the
 //     sub-ops subs[mat .. mat + rank) to them in order.
@@ -111,6 +115,8 @@ struct DevOp {
     int64_t stride;      // SLOT: digit stride R_k
     int32_t block;       // SLOT: plan block index
     int32_t piece;       // SLOT: factor piece of that block on this side
+    int32_t barrier;     // 1: workgroup barrier after this op (0: only this wave's own slice was touched)
+    int32_t spare;
 };
 
 // Sub-op of a group.  D1: 2x2 matrix m on register position g.  SIGN/PHASE:

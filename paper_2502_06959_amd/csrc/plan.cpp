@@ -823,6 +823,18 @@ Schedule schedule_side(const Plan& p, int s, int L) {
         ps.op_begin = (int32_t)sc.devops.size();
         emit_pass(sp, sc, ps, ids);
         ps.op_end = (int32_t)sc.devops.size();
+        // barriers: only between ops that are not both wave-private (a wave
+        // holds 64 lanes x 2^k amplitudes of a group, tile bits 0 .. 5+k)
+        auto wave_private = [&](const DevOp& d) {
+            if (d.type != DOP_GROUP || d.k != kGroupBits) return false;
+            for (int g = 0; g < d.k; ++g)
+                if (d.bit[g] >= 6 + d.k) return false;
+            return true;
+        };
+        for (int32_t i = ps.op_begin; i < ps.op_end; ++i) {
+            const bool last = i + 1 == ps.op_end;
+            sc.devops[i].barrier = (last || !wave_private(sc.devops[i]) || !wave_private(sc.devops[i + 1])) ? 1 : 0;
+        }
         sc.passes.push_back(ps);
         first = false;
         if (sc.passes.size() > (size_t)4 * nops + 8) break;  // every pass applies an op; never reached

@@ -57,6 +57,24 @@ struct DSub {
     };
 };
 
+// Read-only plan tables (passes, ops, sub-op records, batch segments) are
+// read through the constant address space: their loads are uniform, and the
+// compiler may then use scalar loads, which it otherwise avoids because the
+// kernels also store to global memory.
+// (The host pass of this file never runs these device functions; it sees
+// plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using ctab = const __attribute__((address_space(4))) T*;
+#else
+template <typename T>
+using ctab = const T*;
+#endif
+template <typename T>
+__device__ __forceinline__ ctab<T> as_table(const T* p) {
+    return (ctab<T>)p;
+}
+
 struct SideArgs {
     const Pass* pass;        // device copy of the pass record
     void* psi;
@@ -145,7 +163,7 @@ __device__ __forceinline__ void d1g(V (&v)[1 << K], V m00, V m01, V m10, V m11) 
 
 template <int K, typename T>
 __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E, const DevOp& op,
-                                            const DSub<T>* __restrict__ subs, const typename Cx<T>::v* __restrict__ pool,
+                                            ctab<DSub<T>> subs, const typename Cx<T>::v* __restrict__ pool,
                                             uint64_t gbase, int tid, int nt) {
     using V = typename Cx<T>::v;
     constexpr int D = 1 << K;
@@ -229,8 +247,8 @@ template <> struct Threads<double> { static constexpr int max = 512; };
 // One tile of one path's half-state through one LDS pass: load (or set
 // |0...0>), apply the pass's ops, store.  `st` is the path's row.
 template <typename T, int KG>
-__device__ __forceinline__ void sweep_tile(const Pass* __restrict__ ps, const DevOp* __restrict__ ops,
-                                           const DSub<T>* __restrict__ subs, const typename Cx<T>::v* __restrict__ pool,
+__device__ __forceinline__ void sweep_tile(ctab<Pass> ps, ctab<DevOp> ops, ctab<DSub<T>> subs,
+                                           const typename Cx<T>::v* __restrict__ pool,
                                            typename Cx<T>::v* st, uint32_t t, int64_t path,
                                            typename Cx<T>::v* tile) {
     using V = typename Cx<T>::v;
@@ -264,7 +282,7 @@ __device__ __forceinline__ void sweep_tile(const Pass* __restrict__ ps, const De
 
     const int o1 = ps->op_end;
     for (int o = ps->op_begin; o < o1; ++o) {
-        const DevOp& op = ops[o];
+        const DevOp op = ops[o];
         const int type = op.type;
         if (type == DOP_GROUP) {
             apply_group<KG, T>(tile, E, op, subs, pool, base, tid, nt);
@@ -283,7 +301,11 @@ __device__ __forceinline__ void sweep_tile(const Pass* __restrict__ ps, const De
                 default: apply_dense<4>(tile, E, op.bit, mstage, tid, nt); break;
             }
         }
-        __syncthreads();
+        // between two wave-private groups each wave reads only what it wrote
+        // itself, and a wave's LDS accesses complete in issue order: the
+        // compiler fence alone keeps them in that order
+        if (op.barrier) __syncthreads();
+        else asm volatile("" ::: "memory");
     }
 
     for (uint32_t e = tid; e < E; e += nt) st[gidx(e)] = tile[swz(e)];
@@ -300,8 +322,8 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideA
     const uint32_t t = blk - pl * n_tiles;
     const int64_t ld = sd ? s1.ld : s0.ld;
     V* st = reinterpret_cast<V*>(sd ? s1.psi : s0.psi) + (int64_t)pl * ld;
-    sweep_tile<T, KG>(sd ? s1.pass : s0.pass, sd ? s1.ops : s0.ops,
-                      reinterpret_cast<const DSub<T>*>(sd ? s1.subs : s0.subs),
+    sweep_tile<T, KG>(as_table(sd ? s1.pass : s0.pass), as_table(sd ? s1.ops : s0.ops),
+                      as_table(reinterpret_cast<const DSub<T>*>(sd ? s1.subs : s0.subs)),
                       reinterpret_cast<const V*>(sd ? s1.pool : s0.pool), st, t, p_begin + pl,
                       reinterpret_cast<V*>(smem_raw));
 }
@@ -310,22 +332,23 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideA
 // [segs[i].block_start, segs[i+1].block_start); its half-states start at
 // base + psi_off.
 template <typename T, int KG>
-__global__ __launch_bounds__(Threads<T>::max) void sweep_batch(const BatchSeg* __restrict__ segs, int nseg,
+__global__ __launch_bounds__(Threads<T>::max) void sweep_batch(const BatchSeg* __restrict__ segs_in, int nseg,
                                                                unsigned char* base) {
     using V = typename Cx<T>::v;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const ctab<BatchSeg> segs = as_table(segs_in);
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (segs[mid].block_start <= blockIdx.x) lo = mid;
         else hi = mid - 1;
     }
-    const BatchSeg& sg = segs[lo];
+    const BatchSeg sg = segs[lo];
     const uint32_t blk = blockIdx.x - sg.block_start;
     const uint32_t pl = blk / sg.n_tiles;
     const uint32_t t = blk - pl * sg.n_tiles;
     V* st = reinterpret_cast<V*>(base + sg.psi_off) + (int64_t)pl * sg.ld;
-    sweep_tile<T, KG>(sg.pass, sg.ops, reinterpret_cast<const DSub<T>*>(sg.subs),
+    sweep_tile<T, KG>(as_table(sg.pass), as_table(sg.ops), as_table(reinterpret_cast<const DSub<T>*>(sg.subs)),
                       reinterpret_cast<const V*>(sg.pool), st, t, pl, reinterpret_cast<V*>(smem_raw));
 }
 
