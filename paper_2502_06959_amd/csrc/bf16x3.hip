@@ -136,10 +136,16 @@ __device__ __forceinline__ void bf16x3_tile(const unsigned short* __restrict__ P
     store_tile_128(cr, ci, row0, col0, M, N, out, ldo, accumulate);
 }
 
-// Operands of one 16-path step of a tile: for each of the two 32-row blocks
-// of A (and of B) the four planes' eight path values of this lane.
+// Persistent streaming kernel: 8 waves per 128 x 128 tile, wave (wm, wn) =
+// (w / 4, w % 4) owns rows 64 wm .. +63 and columns 32 wn .. +31 (two 32x32
+// blocks).  Half the accumulators and operands of a 64 x 64 wave tile leave
+// room for two waves per SIMD, so one wave's stores drain while another
+// multiplies.  The operands of the next tile's first two 16-path steps are
+// loaded before this tile's results are stored: loads and stores share one
+// completion counter, so loads issued after the stores would wait for them.
+// Per output block the MFMA sequence is that of bf16x3_tile.
 struct Bf16Step {
-    u16x8 a[2][4], b[2][4];
+    u16x8 a[2][4], b[4];
 };
 
 __device__ __forceinline__ void load_step(const unsigned short* __restrict__ PA, int64_t M,
@@ -150,101 +156,115 @@ __device__ __forceinline__ void load_step(const unsigned short* __restrict__ PA,
     const u16x8 zero = (u16x8)0;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        const int64_t m = m0 + a * 32 + li, n = n0 + a * 32 + li;
-        const bool mok = m < M, nok = n < N;
+        const int64_t m = m0 + a * 32 + li;
+        const bool mok = m < M;
         const unsigned short* p = PA + (mok ? m : 0) * Kp + kk;
-        const unsigned short* q = PB + (nok ? n : 0) * Kp + kk;
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
-            st.a[a][pl] = mok ? *reinterpret_cast<const u16x8*>(p + pl * pa) : zero;
-            st.b[a][pl] = nok ? *reinterpret_cast<const u16x8*>(q + pl * pb) : zero;
-        }
+        for (int pl = 0; pl < 4; ++pl) st.a[a][pl] = mok ? *reinterpret_cast<const u16x8*>(p + pl * pa) : zero;
     }
+    const int64_t n = n0 + li;
+    const bool nok = n < N;
+    const unsigned short* q = PB + (nok ? n : 0) * Kp + kk;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) st.b[pl] = nok ? *reinterpret_cast<const u16x8*>(q + pl * pb) : zero;
 }
 
-__device__ __forceinline__ void mma_step(const Bf16Step& st, f32x16 (&cr)[2][2], f32x16 (&ci)[2][2]) {
+__device__ __forceinline__ void mma_step(const Bf16Step& st, f32x16 (&cr)[2], f32x16 (&ci)[2]) {
+    const bf16x8 yrh = as_bf(st.b[0]), yrl = as_bf(st.b[1]), yih = as_bf(st.b[2]), yil = as_bf(st.b[3]);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const bf16x8 xrh = as_bf(st.a[a][0]), xrl = as_bf(st.a[a][1]), xih = as_bf(st.a[a][2]),
                      xil = as_bf(st.a[a][3]);
         const bf16x8 nih = as_bf(st.a[a][2] ^ (u16x8)0x8000), nil = as_bf(st.a[a][3] ^ (u16x8)0x8000);
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const bf16x8 yrh = as_bf(st.b[b][0]), yrl = as_bf(st.b[b][1]), yih = as_bf(st.b[b][2]),
-                         yil = as_bf(st.b[b][3]);
-            f32x16 r = cr[a][b], i = ci[a][b];
-            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrh, r, 0, 0, 0);
-            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrl, r, 0, 0, 0);
-            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yrh, r, 0, 0, 0);
-            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yih, r, 0, 0, 0);
-            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yil, r, 0, 0, 0);
-            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nil, yih, r, 0, 0, 0);
-            i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yih, i, 0, 0, 0);
-            i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yil, i, 0, 0, 0);
-            i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yih, i, 0, 0, 0);
-            i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrh, i, 0, 0, 0);
-            i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrl, i, 0, 0, 0);
-            i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xil, yrh, i, 0, 0, 0);
-            cr[a][b] = r;
-            ci[a][b] = i;
-        }
+        f32x16 r = cr[a], i = ci[a];
+        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrh, r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrl, r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yrh, r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yih, r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yil, r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nil, yih, r, 0, 0, 0);
+        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yih, i, 0, 0, 0);
+        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yil, i, 0, 0, 0);
+        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yih, i, 0, 0, 0);
+        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrh, i, 0, 0, 0);
+        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrl, i, 0, 0, 0);
+        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xil, yrh, i, 0, 0, 0);
+        cr[a] = r;
+        ci[a] = i;
     }
 }
 
-// Persistent: workgroup g handles tiles g, g + gridDim.x, ... (tile t covers
-// rows (t / tiles_n) * 128 and columns (t % tiles_n) * 128).  The operands of
-// the first two 16-path steps of the next tile are loaded before this tile's
-// results are stored: loads and stores share one completion counter, so
-// loads issued after the stores would wait for the stores to drain.  The
-// MFMA sequence is that of bf16x3_tile.
-__global__ __launch_bounds__(256) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
+// Stores a wave's 64 x 32 block pair (accumulator r of a 32x32 block at row
+// (r/4)*8 + (lane/32)*4 + r%4, column lane%32).
+__device__ __forceinline__ void store_64x32(const f32x16 (&cr)[2], const f32x16 (&ci)[2], int64_t m0, int64_t n0,
+                                            int64_t M, int64_t N, float2* __restrict__ out, int64_t ldo,
+                                            int accumulate) {
+    const int lane = threadIdx.x & 63, li = lane & 31, lk = lane >> 5;
+    const int64_t col = n0 + li;
+    if (col >= N) return;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t row = m0 + a * 32 + (r >> 2) * 8 + lk * 4 + (r & 3);
+            if (row >= M) continue;
+            float2 v = make_float2(cr[a][r], ci[a][r]);
+            float2* o = out + row * ldo + col;
+            if (accumulate) {
+                const float2 old = *o;
+                v.x += old.x;
+                v.y += old.y;
+            }
+            *o = v;
+        }
+}
+
+__global__ __launch_bounds__(512) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
                                                              const unsigned short* __restrict__ PB, int64_t N,
                                                              int64_t Kp, float2* __restrict__ out, int64_t ldo,
                                                              int accumulate, int64_t tiles_n, int64_t tiles) {
     const int w = threadIdx.x >> 6;
+    const int64_t wr = (w >> 2) * 64, wc = (w & 3) * 32;
     int64_t tile = blockIdx.x;
     if (tile >= tiles) return;
     auto origin = [&](int64_t t, int64_t& r0, int64_t& c0) {
         const int64_t tm = t / tiles_n, tn = t - tm * tiles_n;
-        r0 = tm * BF_TILE;
-        c0 = tn * BF_TILE;
+        r0 = tm * BF_TILE + wr;
+        c0 = tn * BF_TILE + wc;
     };
-    int64_t row0, col0;
-    origin(tile, row0, col0);
+    int64_t m0, n0;
+    origin(tile, m0, n0);
     Bf16Step s0, s1;
-    load_step(PA, M, PB, N, Kp, row0 + (w >> 1) * 64, col0 + (w & 1) * 64, 0, s0);
-    if (Kp > 16) load_step(PA, M, PB, N, Kp, row0 + (w >> 1) * 64, col0 + (w & 1) * 64, 16, s1);
+    load_step(PA, M, PB, N, Kp, m0, n0, 0, s0);
+    if (Kp > 16) load_step(PA, M, PB, N, Kp, m0, n0, 16, s1);
     for (;;) {
-        const int64_t m0 = row0 + (w >> 1) * 64, n0 = col0 + (w & 1) * 64;
-        f32x16 cr[2][2], ci[2][2];
+        f32x16 cr[2], ci[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                cr[a][b] = (f32x16)0.0f;
-                ci[a][b] = (f32x16)0.0f;
-            }
+        for (int a = 0; a < 2; ++a) {
+            cr[a] = (f32x16)0.0f;
+            ci[a] = (f32x16)0.0f;
+        }
         mma_step(s0, cr, ci);
         if (Kp > 16) mma_step(s1, cr, ci);
         for (int64_t k0 = 32; k0 < Kp; k0 += 16) {
-            Bf16Step sk;
-            load_step(PA, M, PB, N, Kp, m0, n0, k0, sk);
-            mma_step(sk, cr, ci);
+            load_step(PA, M, PB, N, Kp, m0, n0, k0, s1);
+            mma_step(s1, cr, ci);
         }
         const int64_t next = tile + gridDim.x;
-        int64_t nr0 = 0, nc0 = 0;
+        int64_t nm0 = 0, nn0 = 0;
         if (next < tiles) {
-            origin(next, nr0, nc0);
-            load_step(PA, M, PB, N, Kp, nr0 + (w >> 1) * 64, nc0 + (w & 1) * 64, 0, s0);
-            if (Kp > 16) load_step(PA, M, PB, N, Kp, nr0 + (w >> 1) * 64, nc0 + (w & 1) * 64, 16, s1);
+            origin(next, nm0, nn0);
+            load_step(PA, M, PB, N, Kp, nm0, nn0, 0, s0);
+            if (Kp > 16) load_step(PA, M, PB, N, Kp, nm0, nn0, 16, s1);
         }
-        store_tile_128(cr, ci, row0, col0, M, N, out, ldo, accumulate);
+        store_64x32(cr, ci, m0, n0, M, N, out, ldo, accumulate);
         if (next >= tiles) break;
         tile = next;
-        row0 = nr0;
-        col0 = nc0;
+        m0 = nm0;
+        n0 = nn0;
     }
 }
+
 __global__ __launch_bounds__(256) void split_batch(const SplitDesc* __restrict__ d, int n, unsigned char* base) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -334,8 +354,8 @@ hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_
         if (s != HSF_OK) return s;
     }
     const int64_t tn = (N + BF_TILE - 1) / BF_TILE, tiles = tn * ((M + BF_TILE - 1) / BF_TILE);
-    const int grid = persistent_grid((const void*)pathsum_bf16x3_kernel, 256, 0, tiles);
-    hipLaunchKernelGGL(pathsum_bf16x3_kernel, dim3(grid), dim3(256), 0, st, PA, M, PB, N, Kp, out, ldo, accumulate,
+    const int grid = persistent_grid((const void*)pathsum_bf16x3_kernel, 512, 0, tiles);
+    hipLaunchKernelGGL(pathsum_bf16x3_kernel, dim3(grid), dim3(512), 0, st, PA, M, PB, N, Kp, out, ldo, accumulate,
                        tn, tiles);
     return hip_check(hipGetLastError(), "pathsum_bf16x3 launch");
 }
