@@ -89,7 +89,8 @@ struct SideArgs {
 // LDS position of tile element e: the low four index bits are XORed with the
 // next four, so that the 16 lanes that vary the lowest free bits of a
 // register group land on 16 distinct 8-byte bank pairs whatever the group's
-// bits are (a bijection on [0, 2^L) for every L).
+// bits are (a bijection on [0, 2^L) for every L).  It is linear over XOR:
+// swz(a ^ b) = swz(a) ^ swz(b).
 __device__ __forceinline__ uint32_t swz(uint32_t e) { return e ^ ((e >> 4) & 15u); }
 
 // Inserts a zero bit at position b of i.
@@ -120,29 +121,30 @@ __device__ __forceinline__ void apply_dense(V* tile, uint32_t E, const int32_t* 
     constexpr int D = 1 << K;
     int sb[K];
     sort_bits<K>(bit, sb);
-    uint32_t off[D];
+    uint32_t soff[D];                // swz(offset of element j); see apply_group
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         uint32_t o = 0;
 #pragma unroll
         for (int i = 0; i < K; ++i)
             if ((j >> (K - 1 - i)) & 1) o |= 1u << bit[i];
-        off[j] = o;
+        soff[j] = swz(o);
     }
     const uint32_t groups = E >> K;
     for (uint32_t g = tid; g < groups; g += nt) {
         uint32_t base = g;
 #pragma unroll
         for (int i = 0; i < K; ++i) base = ins0(base, sb[i]);
+        const uint32_t sbase = swz(base);
         V v[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = tile[swz(base | off[j])];
+        for (int j = 0; j < D; ++j) v[j] = tile[sbase ^ soff[j]];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             V acc = cmul(m[r * D], v[0]);
 #pragma unroll
             for (int j = 1; j < D; ++j) acc = cfma(m[r * D + j], v[j], acc);
-            tile[swz(base | off[r])] = acc;
+            tile[sbase ^ soff[r]] = acc;
         }
     }
 }
@@ -169,14 +171,16 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
     constexpr int D = 1 << K;
     int sb[K];
     sort_bits<K>(op.bit, sb);
-    uint32_t off[D];
+    // the swizzle is linear over XOR and a group's base and register bits
+    // are disjoint: slot(base | off_j) = swz(base) ^ swz(off_j)
+    uint32_t soff[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         uint32_t o = 0;
 #pragma unroll
         for (int g = 0; g < K; ++g)
             if ((j >> g) & 1) o |= 1u << op.bit[g];
-        off[j] = o;
+        soff[j] = swz(o);
     }
     const int s0 = op.mat, ns = op.rank;
     const uint32_t groups = E >> K;
@@ -184,9 +188,10 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
         uint32_t base = gi;
 #pragma unroll
         for (int i = 0; i < K; ++i) base = ins0(base, sb[i]);
+        const uint32_t sbase = swz(base);
         V v[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = tile[swz(base | off[j])];
+        for (int j = 0; j < D; ++j) v[j] = tile[sbase ^ soff[j]];
         // software pipeline: the next record's scalar loads are issued before
         // the current record is applied
         DSub<T> cur = subs[s0];
@@ -235,7 +240,7 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
             }
         }
 #pragma unroll
-        for (int j = 0; j < D; ++j) tile[swz(base | off[j])] = v[j];
+        for (int j = 0; j < D; ++j) tile[sbase ^ soff[j]] = v[j];
     }
 }
 
