@@ -27,7 +27,7 @@ struct Batch {
     void* gemms_lds = nullptr;           // LDS-staged path sums
     int n_gemm = 0, n_gemm_lds = 0;
     int64_t tiles_lds = 0;
-    std::vector<int> round_first, round_n;
+    std::vector<int> round_first, round_n, round_kg;
     std::vector<uint32_t> round_blocks, round_emax;
     int n_split = 0;
     uint32_t split_blocks = 0;
@@ -98,6 +98,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
     std::vector<BatchSeg> segs;
     b.round_first.clear();
     b.round_n.clear();
+    b.round_kg.clear();
     b.round_blocks.clear();
     b.round_emax.clear();
     size_t rounds = 0;
@@ -109,35 +110,40 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
             rounds = std::max(rounds, v[std::min<size_t>(si[i], v.size() - 1)].passes.size());
         }
     }
-    for (size_t k = 0; k < rounds; ++k) {
-        b.round_first.push_back((int)segs.size());
-        uint32_t start = 0, emax = 1;
-        for (int i = 0; i < n; ++i) {
-            const Plan& p = *b.plans[i];
-            for (int s = 0; s < 2; ++s) {
-                const auto& v = p.side[s].sched;
-                const size_t idx = std::min<size_t>(si[i], v.size() - 1);
-                const Schedule& sc = v[idx];
-                if (k >= sc.passes.size()) continue;
-                const DeviceSchedule& ds = dc[i]->side[s][idx];
-                BatchSeg g{};
-                g.pass = reinterpret_cast<const Pass*>(ds.passes) + k;
-                g.psi_off = s == 0 ? b.offA[i] : b.offB[i];
-                g.ld = int64_t(1) << (s == 0 ? p.na : p.nb);
-                g.ops = (const DevOp*)ds.ops;
-                g.subs = ds.subs;
-                g.pool = ds.pool;
-                g.n_tiles = 1u << sc.passes[k].n_nonlocal;
-                g.block_start = start;
-                start += (uint32_t)(p.P * g.n_tiles);
-                emax = std::max(emax, 1u << sc.passes[k].n_local);
-                segs.push_back(g);
+    // pass k of every (circuit, side), split by group width: one launch each
+    for (size_t k = 0; k < rounds; ++k)
+        for (int kg = 3; kg <= 4; ++kg) {
+            const int first = (int)segs.size();
+            uint32_t start = 0, emax = 1;
+            for (int i = 0; i < n; ++i) {
+                const Plan& p = *b.plans[i];
+                for (int s = 0; s < 2; ++s) {
+                    const auto& v = p.side[s].sched;
+                    const size_t idx = std::min<size_t>(si[i], v.size() - 1);
+                    const Schedule& sc = v[idx];
+                    if (k >= sc.passes.size() || group_bits(sc.passes[k].n_local) != kg) continue;
+                    const DeviceSchedule& ds = dc[i]->side[s][idx];
+                    BatchSeg g{};
+                    g.pass = reinterpret_cast<const Pass*>(ds.passes) + k;
+                    g.psi_off = s == 0 ? b.offA[i] : b.offB[i];
+                    g.ld = int64_t(1) << (s == 0 ? p.na : p.nb);
+                    g.ops = (const DevOp*)ds.ops;
+                    g.subs = ds.subs;
+                    g.pool = ds.pool;
+                    g.n_tiles = 1u << sc.passes[k].n_nonlocal;
+                    g.block_start = start;
+                    start += (uint32_t)(p.P * g.n_tiles);
+                    emax = std::max(emax, 1u << sc.passes[k].n_local);
+                    segs.push_back(g);
+                }
             }
+            if ((int)segs.size() == first) continue;
+            b.round_first.push_back(first);
+            b.round_n.push_back((int)segs.size() - first);
+            b.round_kg.push_back(kg);
+            b.round_blocks.push_back(start);
+            b.round_emax.push_back(emax);
         }
-        b.round_n.push_back((int)segs.size() - b.round_first.back());
-        b.round_blocks.push_back(start);
-        b.round_emax.push_back(emax);
-    }
     hsf_status s = upload_table(segs, &b.segs);
     if (s != HSF_OK) return s;
     // split descriptors (BF16 planes) and path-sum descriptors
@@ -206,10 +212,10 @@ hsf_status enqueue(Batch& b, int mode, unsigned char* base, hipStream_t st) {
     hsf_status s;
     for (size_t k = 0; k < b.round_first.size(); ++k) {
         const uint32_t emax = b.round_emax[k];
-        const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, emax >> 3));
+        const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, emax >> b.round_kg[k]));
         const size_t shmem = ((size_t)emax + 256) * 8;
         if (b.round_blocks[k] == 0) continue;
-        s = launch_sweep_batch(reinterpret_cast<const BatchSeg*>(b.segs) + b.round_first[k], b.round_n[k],
+        s = launch_sweep_batch(b.round_kg[k], reinterpret_cast<const BatchSeg*>(b.segs) + b.round_first[k], b.round_n[k],
                                b.round_blocks[k], threads, shmem, base, st);
         if (s != HSF_OK) return s;
     }

@@ -629,15 +629,13 @@ void fuse_side(Plan& p, int s) {
 
 namespace {
 
-// Tile bits held in registers by one thread of a group (2^kGroupBits amplitudes).
-constexpr int kGroupBits = 3;
 
 // Turns the ops of one pass into device ops: runs of one-qubit gates (on at
 // most four tile bits) and diagonal gates (on any qubits) become one
 // register-resident group; wider dense ops and factor slots stand alone.
 void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::vector<int>& ids) {
     const int L = ps.n_local;
-    const int KG = std::min(kGroupBits, L);
+    const int KG = group_bits(L);
     auto tbit = [&](int q) -> int {
         for (int l = 0; l < L; ++l)
             if (ps.local_q[l] == q) return l;
@@ -826,7 +824,7 @@ Schedule schedule_side(const Plan& p, int s, int L) {
         // barriers: only between ops that are not both wave-private (a wave
         // holds 64 lanes x 2^k amplitudes of a group, tile bits 0 .. 5+k)
         auto wave_private = [&](const DevOp& d) {
-            if (d.type != DOP_GROUP || d.k != kGroupBits) return false;
+            if (d.type != DOP_GROUP) return false;
             for (int g = 0; g < d.k; ++g)
                 if (d.bit[g] >= 6 + d.k) return false;
             return true;

@@ -398,7 +398,6 @@ hsf_status upload_schedule(const Schedule& sc, DeviceSchedule& d) {
 bool g_attr_done[2] = {false, false};
 
 // Tile bits per register group; must match the planner's group width.
-constexpr int kGroupBits = 3;
 
 }  // namespace
 
@@ -431,11 +430,13 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
     const int di = p.dtype == HSF_C128 ? 1 : 0;
     if (!g_attr_done[di]) {
         const size_t bytes = ((size_t(1) << max_tile_bits(p.dtype)) + 256) * (p.dtype == HSF_C128 ? 16 : 8);
-        if (p.dtype == HSF_C128)
-            s = hip_check(hipFuncSetAttribute((const void*)sweep_pass<double, kGroupBits>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes), "hipFuncSetAttribute");
-        else
-            s = hip_check(hipFuncSetAttribute((const void*)sweep_pass<float, kGroupBits>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes), "hipFuncSetAttribute");
-        if (s != HSF_OK) return s;
+        const void* ks[2] = {p.dtype == HSF_C128 ? (const void*)sweep_pass<double, 3> : (const void*)sweep_pass<float, 3>,
+                             p.dtype == HSF_C128 ? (const void*)sweep_pass<double, 4> : (const void*)sweep_pass<float, 4>};
+        for (const void* kf : ks) {
+            s = hip_check(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
+                          "hipFuncSetAttribute");
+            if (s != HSF_OK) return s;
+        }
         g_attr_done[di] = true;
     }
     *out = &d;
@@ -478,10 +479,16 @@ hsf_status launch_pass(bool dbl, int kg, uint32_t total, int threads, size_t shm
 
 }  // namespace
 
-hsf_status launch_sweep_batch(const void* segs, int nseg, uint32_t total_blocks, int threads, size_t shmem,
+hsf_status launch_sweep_batch(int kg, const void* segs, int nseg, uint32_t total_blocks, int threads, size_t shmem,
                               unsigned char* base, hipStream_t stream) {
-    hipLaunchKernelGGL((sweep_batch<float, kGroupBits>), dim3(total_blocks), dim3(threads), shmem, stream,
-                       (const BatchSeg*)segs, nseg, base);
+    if (kg == 4)
+        hipLaunchKernelGGL((sweep_batch<float, 4>), dim3(total_blocks), dim3(threads), shmem, stream,
+                           (const BatchSeg*)segs, nseg, base);
+    else if (kg == 3)
+        hipLaunchKernelGGL((sweep_batch<float, 3>), dim3(total_blocks), dim3(threads), shmem, stream,
+                           (const BatchSeg*)segs, nseg, base);
+    else
+        return fail(HSF_E_UNSUPPORTED, "batched sweeps need groups of 3 or 4 tile bits");
     return hip_check(hipGetLastError(), "sweep_batch launch");
 }
 
@@ -489,7 +496,9 @@ void batch_sweep_prepare() {
     static bool done = false;
     if (done) return;
     const size_t bytes = ((size_t(1) << max_tile_bits(HSF_C64)) + 256) * 8;
-    (void)hipFuncSetAttribute((const void*)sweep_batch<float, kGroupBits>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)sweep_batch<float, 3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+    (void)hipFuncSetAttribute((const void*)sweep_batch<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)bytes);
     done = true;
 }
@@ -530,13 +539,13 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
             a[s].n_tiles = 1u << ps.n_nonlocal;
             emax = std::max(emax, 1u << ps.n_local);
         }
-        // group width: every group of a pass uses min(kGroupBits, L) bits (L = that side's tile)
-        int kg = kGroupBits;
+        // group width: every group of a pass uses group_bits(L) bits (L = that side's tile)
+        int kg = 4;
         for (int s = 0; s < 2; ++s)
-            if (a[s].pass) kg = std::min(kg, std::min(kGroupBits, sc[s]->passes[k].n_local));
+            if (a[s].pass) kg = std::min(kg, group_bits(sc[s]->passes[k].n_local));
         bool kg_mixed = false;
         for (int s = 0; s < 2; ++s)
-            if (a[s].pass && std::min(kGroupBits, sc[s]->passes[k].n_local) != kg) kg_mixed = true;
+            if (a[s].pass && group_bits(sc[s]->passes[k].n_local) != kg) kg_mixed = true;
         const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, emax >> kg));
         const size_t shmem = ((size_t)emax + 256) * esz;
         for (int64_t p0 = 0; p0 < n_paths; p0 += max_paths) {
@@ -558,7 +567,7 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
                     c[1 - part].n_blocks = 0;
                     c[1 - part].pass = nullptr;
                     if (!c[part].pass) continue;
-                    kgp = std::min(kGroupBits, sc[part]->passes[k].n_local);
+                    kgp = group_bits(sc[part]->passes[k].n_local);
                 }
                 const uint32_t tot = c[0].n_blocks + c[1].n_blocks;
                 hsf_status s = launch_pass(dbl, kgp, tot, threads, shmem, stream, c[0], c[1], p_begin + p0);
