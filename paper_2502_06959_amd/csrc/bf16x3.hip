@@ -292,12 +292,12 @@ __global__ __launch_bounds__(256) void split_batch(const SplitDesc* __restrict__
         il[e] = bf16_rne(v.y - bf16_to_f32(b));
     }
     if (s.chunked) {
-        // chunks of 32 paths: row r of chunk c holds 4 planes x 32 paths
-        unsigned short* row = planes + ((k0 >> 5) * s.R + r) * 128 + (k0 & 31);
+        // chunks of kBf16Chunk paths: row r of chunk c holds 4 planes x kBf16Chunk paths
+        unsigned short* row = planes + ((k0 / kBf16Chunk) * s.R + r) * (4 * kBf16Chunk) + (k0 % kBf16Chunk);
         *reinterpret_cast<u16x8*>(row) = rh;
-        *reinterpret_cast<u16x8*>(row + 32) = rl;
-        *reinterpret_cast<u16x8*>(row + 64) = ih;
-        *reinterpret_cast<u16x8*>(row + 96) = il;
+        *reinterpret_cast<u16x8*>(row + kBf16Chunk) = rl;
+        *reinterpret_cast<u16x8*>(row + 2 * kBf16Chunk) = ih;
+        *reinterpret_cast<u16x8*>(row + 3 * kBf16Chunk) = il;
         return;
     }
     const int64_t plane = s.R * s.Kp;

@@ -16,7 +16,9 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
 
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths);
 
-// Path sums staged through LDS for K >= kLdsMinPaths (pathsum_lds.hip).
+// Path sums staged through LDS for K >= kLdsMinPaths (pathsum_lds.hip); their
+// split-BF16 planes are chunked by kBf16Chunk paths (a multiple of 16).
+constexpr int kBf16Chunk = 16;
 constexpr int64_t kLdsMinPaths = 128;
 bool path_sum_lds_fits(int mode, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K, int64_t M,
                        int64_t N);

@@ -174,11 +174,17 @@ __global__ __launch_bounds__(256) void pathsum_f32_lds_batch(const GemmDesc* __r
 }
 
 // ------------------------------------------------------- split-BF16 x3 ----
-// Chunked planes: for path chunk c (32 paths) and row r, 256 contiguous bytes
-// [re hi | re lo | im hi | im lo] x 32 paths, so one tile's rows of one
-// chunk are one contiguous run of 128 x 256 bytes.
-constexpr int B_KC = 32;
-constexpr int B_ROW = 4 * B_KC * 2 + 16;          // staged row bytes (16-byte pad: conflict-free b128 reads)
+// Chunked planes: for path chunk c (B_KC paths) and row r, B_RB contiguous
+// bytes [re hi | re lo | im hi | im lo] x B_KC paths, so one tile's rows of
+// one chunk are one contiguous run of 128 x B_RB bytes.  With 16-path chunks
+// the double-buffered stages take 72 KiB of LDS: two workgroups per CU, so
+// one's barrier and LDS waits are covered by the other's MFMAs.
+constexpr int B_KC = kBf16Chunk;                 // paths per chunk (a multiple of 16)
+constexpr int B_RB = 8 * B_KC;                    // bytes of one row of one chunk (4 planes x B_KC x 2 B)
+constexpr int B_TPR = B_RB / 16;                  // threads per row when staging (16 bytes each)
+constexpr int B_RPI = 256 / B_TPR;                // rows per staging instruction
+constexpr int B_NF = 128 / B_RPI;                 // staging loads per operand per chunk
+constexpr int B_ROW = B_RB + 16;                  // staged row bytes (16-byte pad: conflict-free b128 reads)
 constexpr int B_STAGE = 2 * 128 * B_ROW;          // bytes of A and B rows per stage
 constexpr size_t B_LDS = 2 * (size_t)B_STAGE;
 
@@ -207,25 +213,25 @@ __global__ __launch_bounds__(256) void split_chunked(const float2* __restrict__ 
     *reinterpret_cast<u16x8*>(row + 3 * B_KC) = il;
 }
 
-// Rows row0 + t / 16 + 16 i (i < 8) of path chunk c, bytes 16 (t % 16) ..
-// +15; rows at or beyond R read as zero.
+// Rows row0 + t / B_TPR + B_RPI i (i < B_NF) of path chunk c, bytes
+// 16 (t % B_TPR) .. +15; rows at or beyond R read as zero.
 __device__ __forceinline__ void fetch_rows(const unsigned short* __restrict__ P, int64_t R, int64_t row0, int64_t c,
-                                           int srow, int scol, uint4 (&r)[8]) {
+                                           int srow, int scol, uint4 (&r)[B_NF]) {
     const uint4* g = reinterpret_cast<const uint4*>(P + (c * R + row0) * (4 * B_KC));
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int row = srow + 16 * i;
+    for (int i = 0; i < B_NF; ++i) {
+        const int row = srow + B_RPI * i;
         const bool ok = row0 + row < R;
-        const uint4 v = g[(ok ? row : R - 1 - row0) * 16 + scol];
+        const uint4 v = g[(ok ? row : R - 1 - row0) * B_TPR + scol];
         r[i] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
     }
 }
 
-__device__ __forceinline__ void stash_rows(unsigned char* stage, int srow, int scol, const uint4 (&ra)[8],
-                                           const uint4 (&rb)[8]) {
+__device__ __forceinline__ void stash_rows(unsigned char* stage, int srow, int scol, const uint4 (&ra)[B_NF],
+                                           const uint4 (&rb)[B_NF]) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int off = (srow + 16 * i) * B_ROW + scol * 16;
+    for (int i = 0; i < B_NF; ++i) {
+        const int off = (srow + B_RPI * i) * B_ROW + scol * 16;
         *reinterpret_cast<uint4*>(stage + off) = ra[i];
         *reinterpret_cast<uint4*>(stage + 128 * B_ROW + off) = rb[i];
     }
@@ -240,10 +246,10 @@ __device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int li = lane & 31, lk = lane >> 5, wm = w >> 1, wn = w & 1;
     {
-        // staging: 16 threads move one 256-byte row; thread t takes rows
-        // t / 16 + 16 i, i < 8, bytes 16 (t % 16) .. +15, of both operands
-        uint4 ra[8], rb[8];
-        const int srow = t >> 4, scol = t & 15;
+        // staging: B_TPR threads move one row of a chunk; thread t takes rows
+        // t / B_TPR + B_RPI i, i < B_NF, bytes 16 (t % B_TPR) .. +15, of both operands
+        uint4 ra[B_NF], rb[B_NF];
+        const int srow = t / B_TPR, scol = t % B_TPR;
         f32x16 cr[2][2], ci[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -265,8 +271,8 @@ __device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict
             const unsigned char* sa = bl + buf * B_STAGE;
             const unsigned char* sb = sa + 128 * B_ROW;
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                // plane p of row r, paths 16 s + 8 lk .. +7: byte r * B_ROW + 64 p + 32 s + 16 lk
+            for (int s = 0; s < B_KC / 16; ++s) {
+                // plane p of row r, paths 16 s + 8 lk .. +7: byte r * B_ROW + 2 B_KC p + 32 s + 16 lk
                 u16x8 x[2][4], y[2][4];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
@@ -274,8 +280,8 @@ __device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict
                     const unsigned char* pb = sb + (wn * 64 + a * 32 + li) * B_ROW + 32 * s + 16 * lk;
 #pragma unroll
                     for (int p = 0; p < 4; ++p) {
-                        x[a][p] = *reinterpret_cast<const u16x8*>(pa + 64 * p);
-                        y[a][p] = *reinterpret_cast<const u16x8*>(pb + 64 * p);
+                        x[a][p] = *reinterpret_cast<const u16x8*>(pa + 2 * B_KC * p);
+                        y[a][p] = *reinterpret_cast<const u16x8*>(pb + 2 * B_KC * p);
                     }
                 }
 #pragma unroll
@@ -312,7 +318,7 @@ __device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict
     }
 }
 
-__global__ __launch_bounds__(256) void pathsum_bf16x3_lds(const unsigned short* __restrict__ PA, int64_t M,
+__global__ __launch_bounds__(256, 2) void pathsum_bf16x3_lds(const unsigned short* __restrict__ PA, int64_t M,
                                                           const unsigned short* __restrict__ PB, int64_t N,
                                                           int64_t chunks, float2* __restrict__ out, int64_t ldo,
                                                           int accumulate, int64_t tiles_m, int64_t tiles_n,
@@ -328,7 +334,7 @@ __global__ __launch_bounds__(256) void pathsum_bf16x3_lds(const unsigned short* 
 
 // Batched: descriptors hold chunked planes (a_off, b_off) and the padded path
 // count K (a multiple of 32).
-__global__ __launch_bounds__(256) void pathsum_bf16x3_lds_batch(const GemmDesc* __restrict__ d, int n,
+__global__ __launch_bounds__(256, 2) void pathsum_bf16x3_lds_batch(const GemmDesc* __restrict__ d, int n,
                                                                 unsigned char* base, int64_t tiles) {
     extern __shared__ __align__(16) unsigned char bl[];
     for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
@@ -373,7 +379,7 @@ void grid_shape(const void* kernel, size_t shmem, int64_t M, int64_t N, int64_t&
 bool path_sum_lds_fits(int mode, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K, int64_t M,
                        int64_t N) {
     if (K < kLdsMinPaths) return false;
-    if (mode == HSF_SUM_BF16X3) return (K + B_KC - 1) / B_KC * 4 <= 65535;
+    if (mode == HSF_SUM_BF16X3) return (K + B_KC - 1) / B_KC * (B_KC / 8) <= 65535;
     return ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && ldA % 2 == 0 && ldB % 2 == 0 && M % 2 == 0 &&
            N % 2 == 0;
 }
