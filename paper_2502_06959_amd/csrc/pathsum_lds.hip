@@ -134,7 +134,7 @@ __device__ __forceinline__ void f32_lds_tile(const float2* __restrict__ A, int64
     }
 }
 
-__global__ __launch_bounds__(256) void pathsum_f32_lds(const float2* __restrict__ A, int64_t ldA,
+__global__ __launch_bounds__(256, 2) void pathsum_f32_lds(const float2* __restrict__ A, int64_t ldA,
                                                        const float2* __restrict__ B, int64_t ldB, int64_t K,
                                                        int64_t M, int64_t N, float2* __restrict__ out, int64_t ldo,
                                                        int accumulate, int64_t tiles_m, int64_t tiles_n,
@@ -160,7 +160,7 @@ __device__ __forceinline__ const GemmDesc& find_desc(const GemmDesc* __restrict_
     return d[lo];
 }
 
-__global__ __launch_bounds__(256) void pathsum_f32_lds_batch(const GemmDesc* __restrict__ d, int n,
+__global__ __launch_bounds__(256, 2) void pathsum_f32_lds_batch(const GemmDesc* __restrict__ d, int n,
                                                              unsigned char* base, int64_t tiles) {
     extern __shared__ __align__(16) float2 fl[];
     for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
