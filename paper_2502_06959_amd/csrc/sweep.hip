@@ -7,10 +7,11 @@
 // is a single pass that starts from |0...0> in LDS and writes HBM once.
 //
 // Inside a pass, runs of one-qubit gates and diagonal gates are grouped: a
-// thread loads the 16 amplitudes that differ in four tile bits into
-// registers, applies the run there (one-qubit gates as 2x2 butterflies,
-// diagonal gates as sign masks or phase rows), and stores them back, so LDS
-// is touched once per group instead of once per gate.
+// thread loads the 8 or 16 amplitudes that differ in three or four tile bits
+// (group_bits of the tile size) into registers, applies the run there
+// (one-qubit gates as 2x2 butterflies, diagonal gates as sign masks or phase
+// rows), and stores them back, so LDS is touched once per group instead of
+// once per gate.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -248,7 +249,7 @@ template <typename T> struct Threads;
 template <> struct Threads<float> { static constexpr int max = 512; };
 template <> struct Threads<double> { static constexpr int max = 512; };
 
-// KG: register-group width (4 for every tile of four or more bits).
+// KG: register-group width, group_bits(L) of the pass's tile.
 // One tile of one path's half-state through one LDS pass: load (or set
 // |0...0>), apply the pass's ops, store.  `st` is the path's row.
 template <typename T, int KG>

@@ -8,6 +8,7 @@ c2_literal.npz  C2 (P=1024): psi at 4096 seeded basis states
 c3.npz          C3: psi at its 1024 bitstrings, L, and dL/dt for 16 seeded
                 parameter ids (parameter-shift rule on the oracle HSF)
 c4.npz          C4 (P=4096): psi at 4096 seeded basis states
+c5.npz          C5 (64 circuits): psi at 64 seeded basis states of each circuit
 qaoa_q30.npz    single-layer QAOA MaxCut on a seeded SBM graph with Table II's
                 q30-1 shape (15|15 qubits, p_intra 0.8, p_inter 0.1): psi at
                 4096 seeded basis states among the first 10^6 (the oracle HSF
@@ -67,6 +68,15 @@ def main(which):
     if "c4" in which:
         xs, amp = sampled_psi(cg.c4(), 4096, 44)
         np.savez(os.path.join(OUT, "c4.npz"), x=xs, psi=amp)
+    if "c5" in which:
+        xs_all, psi_all, owner = [], [], []
+        for i, c in enumerate(cg.c5()):
+            xs, amp = sampled_psi(c, 64, 500 + i)
+            xs_all.append(xs)
+            psi_all.append(amp)
+            owner.append(np.full(len(xs), i, dtype=np.int32))
+        np.savez(os.path.join(OUT, "c5.npz"), x=np.concatenate(xs_all), psi=np.concatenate(psi_all),
+                 circuit=np.concatenate(owner))
     if "qaoa" in which:
         c = cg.qaoa_sbm(100, (15, 15), 0.8, 0.1)
         t = time.time()
@@ -81,4 +91,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c2", "c3", "c4", "qaoa"])
+    main(sys.argv[1:] or ["c2", "c3", "c4", "c5", "qaoa"])

@@ -1,5 +1,5 @@
-"""Full-size GPU parity: the C2 (literal, P=1024), C3 and C4 (P=4096)
-workloads at their real sizes, through the same launches the benchmark
+"""Full-size GPU parity: the C2 (literal, P=1024), C3, C4 (P=4096) and C5
+(64 circuits) workloads at their real sizes, through the same launches the benchmark
 times, against values the FP64 oracle wrote (tests/golden/make_golden.py,
 which calls only oracle/).
 
@@ -16,7 +16,7 @@ import torch
 
 import circuitgen as cg
 from oracle import hsf as ohsf
-from paper_2502_06959_amd import Plan, hsf_norm2
+from paper_2502_06959_amd import Batch, Plan, hsf_norm2
 
 pytestmark = pytest.mark.gpu
 
@@ -114,3 +114,24 @@ def test_c4_all_row_tiles_sampled_and_norm():
         # the FP64 path sum still sums complex64 half-states, so the sweeps'
         # FP32 rounding (about 1e-6 here) remains in every mode
         assert ohsf.rel_l2(sub, ref[sel]) < C64_TOL, mode
+
+
+def test_c5_whole_batch_tuned_and_replayed():
+    """All 64 circuits in one tuned batch replayed from a HIP graph (73.7 GiB
+    of output): 64 oracle samples and the norm of every circuit's state."""
+    g = _golden("c5.npz")
+    plans = [Plan(c) for c in cg.c5()]
+    b = Batch(plans)
+    outs = b.alloc_outputs()
+    b.tune(outs, mode="bf16x3")
+    for o in outs:
+        o.zero_()
+    b.run(outs, mode="bf16x3", graph=True)
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        sel = g["circuit"] == i
+        got = o.reshape(-1)[_x(g["x"][sel])].cpu().numpy()
+        assert ohsf.rel_l2(got, g["psi"][sel]) < C64_TOL, i
+        nrm = float(hsf_norm2(o.reshape(-1)).cpu().numpy()[0])
+        assert abs(nrm - 1.0) < 1e-5, i
+    del outs
