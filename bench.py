@@ -98,7 +98,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2p", choices=sorted(WORKLOADS) + ["c4", "c5", "qaoa"])
+    ap.add_argument("--workload", default="c2p", choices=sorted(WORKLOADS) + ["c3", "c4", "c5", "qaoa"])
     ap.add_argument("--mode", default="bf16x3", choices=["f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -135,6 +135,8 @@ def main():
         return bench_c4(args)
     if args.workload == "qaoa":
         return bench_qaoa(args)
+    if args.workload == "c3":
+        return bench_c3(args)
     gen, desc = WORKLOADS[args.workload]
     circuit = getattr(cg, gen)()
     t0 = time.perf_counter()
@@ -300,6 +302,50 @@ def bench_c5(args):
            "plain_per_circuit": {"ms_per_step": ms_plain, "path_sum": "f32",
                                  "speedup_of_batch": ms_plain / ms},
            "output_write_gbs": out_bytes / (ms * 1e-3) / 1e9}
+    print(json.dumps(res), flush=True)
+
+
+def bench_c3(args):
+    """Gradient of L = sum_j |psi(x_j)|^2 over 1024 bitstrings with respect to
+    all 708 angles of the n=30 variational circuit (P=256): one hsf_backward
+    call per step, paths in chunks of 256.  The error is taken against the
+    oracle's parameter-shift gradients of 16 sampled angles."""
+    import numpy as np
+    import torch
+
+    import circuitgen as cg
+    from paper_2502_06959_amd import Plan
+    c = cg.c3()
+    plan = Plan(c)
+    x = torch.from_numpy(np.asarray(cg.c3_bitstrings(), dtype=np.uint64).astype(np.int64)).cuda()
+    for _ in range(args.warmup):
+        plan.backward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g = plan.backward(x)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    t0 = time.perf_counter()
+    L = plan.loss(x)
+    torch.cuda.synchronize()
+    ms_loss = (time.perf_counter() - t0) * 1e3
+    err = None
+    gold = os.path.join(ROOT, "tests", "golden", "c3.npz")
+    if not args.no_check and os.path.exists(gold):
+        z = np.load(gold)
+        got = g.cpu().numpy()[z["grad_ids"]]
+        err = {"max_abs_over_max_ref": float(np.max(np.abs(got - z["grad"])) / np.max(np.abs(z["grad"]))),
+               "loss_rel": float(abs(L - float(z["loss"])) / float(z["loss"])), "grad_ids_checked": int(len(got))}
+    sa, sb = plan.side_stats(0), plan.side_stats(1)
+    res = {"metric": "gradients/s (all 708 angles, 1024 bitstrings)", "value": 1e3 / ms, "unit": "gradients/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "c64 (f32 sweeps, f64 reductions)", "data": "synthetic",
+           "config": {"workload": "c3: n=30 cut 15|15, 12 layers RY/RZ + RZZ brick, 4 blocks of 3 crossing RZZ "
+                                  "(P=256), 708 parameters, loss over 1024 bitstrings",
+                      "paths": plan.P, "params": plan.n_params,
+                      "ops_logical": [sa["ops_logical"], sb["ops_logical"]]},
+           "forward_loss_ms": ms_loss, "error_vs_oracle": err}
     print(json.dumps(res), flush=True)
 
 

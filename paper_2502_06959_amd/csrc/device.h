@@ -24,6 +24,8 @@ bool path_sum_lds_fits(int mode, const void* A, int64_t ldA, const void* B, int6
                        int64_t N);
 hsf_status path_sum_f32_lds(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
                             int64_t N, float2* out, int64_t ldo, int accumulate, hipStream_t st);
+hsf_status path_sum_f64_lds(bool c128_in, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K, int64_t M,
+                            int64_t N, double2* out, int64_t ldo, int accumulate, hipStream_t st);
 hsf_status path_sum_bf16x3_lds(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
                                int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st);
 

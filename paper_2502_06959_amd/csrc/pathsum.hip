@@ -333,6 +333,11 @@ hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void*
     if (dtype == HSF_C64 && mode == HSF_SUM_BF16X3)
         return path_sum_bf16x3((const float2*)A + row0, ldA, (const float2*)B, ldB, K, M, N, (float2*)out, ldo,
                                accumulate, ws, st);
+    if (path_sum_lds_fits(mode, A, ldA, B, ldB, K, M, N)) {
+        const size_t esz = dtype == HSF_C64 ? sizeof(float2) : sizeof(double2);
+        return path_sum_f64_lds(dtype != HSF_C64, (const unsigned char*)A + row0 * esz, ldA, B, ldB, K, M, N,
+                                (double2*)out, ldo, accumulate, st);
+    }
     const dim3 grid((uint32_t)((N + F64_TILE - 1) / F64_TILE), (uint32_t)((M + F64_TILE - 1) / F64_TILE));
     if (grid.y > 65535u) return fail(HSF_E_ARG, "too many output rows in one call (split the row range)");
     if (dtype == HSF_C64)

@@ -284,32 +284,37 @@ __device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict
                         y[a][p] = *reinterpret_cast<const u16x8*>(pb + 2 * B_KC * p);
                     }
                 }
+                // term-major order over the 2 x 2 blocks: consecutive MFMAs
+                // write different accumulators; each accumulator sees its
+                // six terms in the order of bf16x3_tile
+                bf16x8 xs[2][6], ys[2][6];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
                     const bf16x8 xrh = as_bf(x[a][0]), xrl = as_bf(x[a][1]), xih = as_bf(x[a][2]),
                                  xil = as_bf(x[a][3]);
                     const bf16x8 nih = as_bf(x[a][2] ^ (u16x8)0x8000), nil = as_bf(x[a][3] ^ (u16x8)0x8000);
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const bf16x8 yrh = as_bf(y[b][0]), yrl = as_bf(y[b][1]), yih = as_bf(y[b][2]),
-                                     yil = as_bf(y[b][3]);
-                        f32x16 r = cr[a][b], i = ci[a][b];
-                        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrh, r, 0, 0, 0);
-                        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrl, r, 0, 0, 0);
-                        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yrh, r, 0, 0, 0);
-                        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yih, r, 0, 0, 0);
-                        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yil, r, 0, 0, 0);
-                        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nil, yih, r, 0, 0, 0);
-                        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yih, i, 0, 0, 0);
-                        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yil, i, 0, 0, 0);
-                        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yih, i, 0, 0, 0);
-                        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrh, i, 0, 0, 0);
-                        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrl, i, 0, 0, 0);
-                        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xil, yrh, i, 0, 0, 0);
-                        cr[a][b] = r;
-                        ci[a][b] = i;
-                    }
+                    // real part: xrh yrh, xrh yrl, xrl yrh, -xih yih, -xih yil, -xil yih
+                    xs[a][0] = xrh; xs[a][1] = xrh; xs[a][2] = xrl; xs[a][3] = nih; xs[a][4] = nih; xs[a][5] = nil;
+                    // imaginary part: xrh yih, xrh yil, xrl yih, xih yrh, xih yrl, xil yrh
+                    ys[a][0] = xrh; ys[a][1] = xrh; ys[a][2] = xrl; ys[a][3] = xih; ys[a][4] = xih; ys[a][5] = xil;
                 }
+                bf16x8 yr[2][6], yi[2][6];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const bf16x8 yrh = as_bf(y[b][0]), yrl = as_bf(y[b][1]), yih = as_bf(y[b][2]),
+                                 yil = as_bf(y[b][3]);
+                    yr[b][0] = yrh; yr[b][1] = yrl; yr[b][2] = yrh; yr[b][3] = yih; yr[b][4] = yil; yr[b][5] = yih;
+                    yi[b][0] = yih; yi[b][1] = yil; yi[b][2] = yih; yi[b][3] = yrh; yi[b][4] = yrl; yi[b][5] = yrh;
+                }
+#pragma unroll
+                for (int term = 0; term < 6; ++term)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b) {
+                            cr[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xs[a][term], yr[b][term], cr[a][b], 0, 0, 0);
+                            ci[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ys[a][term], yi[b][term], ci[a][b], 0, 0, 0);
+                        }
             }
             if (c + 1 < chunks) stash_rows(bl + (buf ^ 1) * B_STAGE, srow, scol, ra, rb);
             __syncthreads();
@@ -347,6 +352,136 @@ __global__ __launch_bounds__(256, 2) void pathsum_bf16x3_lds_batch(const GemmDes
     }
 }
 
+// ---------------------------------------------------------------- FP64 ----
+// 64 x 64 tiles of 4 waves (2 x 2, each 32 x 32 = 2 x 2 blocks of the
+// 16x16x4 FP64 MFMA), chunks of 16 paths of the tile's 64 A rows and 64 B
+// columns staged in LDS as complex128 (c64 inputs widened on the way in),
+// double-buffered; the MFMA sequence per block is the streaming FP64
+// kernel's.
+constexpr int D_KC = 16;
+constexpr int D_STAGE = 2 * D_KC * 64;            // double2 entries of A and B per stage
+constexpr size_t D_LDS = 2 * D_STAGE * sizeof(double2);
+
+using f64x4 = double __attribute__((ext_vector_type(4)));
+
+template <typename VIN>
+__device__ __forceinline__ double2 widen2(VIN v) {
+    return make_double2((double)v.x, (double)v.y);
+}
+
+template <typename VIN>
+__device__ __forceinline__ void f64_lds_tile(const VIN* __restrict__ A, int64_t ldA, const VIN* __restrict__ B,
+                                             int64_t ldB, int64_t K, int64_t M, int64_t N,
+                                             double2* __restrict__ out, int64_t ldo, int accumulate, int64_t m0,
+                                             int64_t n0, double2* dl) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int li = lane & 15, lk = lane >> 4, wm = w >> 1, wn = w & 1;
+    const int64_t chunks = (K + D_KC - 1) / D_KC;
+    // staging: thread t moves entry q % 64 of path row q / 64, q = t + 256 i, i < 4
+    double2 ra[4], rb[4];
+    auto fetch = [&](int64_t c) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = t + 256 * i, k = q >> 6, e = q & 63;
+            const int64_t kk = c * D_KC + k;
+            const bool kok = kk < K;
+            ra[i] = (kok && m0 + e < M) ? widen2(A[kk * ldA + m0 + e]) : make_double2(0.0, 0.0);
+            rb[i] = (kok && n0 + e < N) ? widen2(B[kk * ldB + n0 + e]) : make_double2(0.0, 0.0);
+        }
+    };
+    auto stash = [&](int buf) {
+        double2* sa = dl + buf * D_STAGE;
+        double2* sb = sa + D_KC * 64;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = t + 256 * i;
+            sa[q] = ra[i];
+            sb[q] = rb[i];
+        }
+    };
+    f64x4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cr[a][b] = (f64x4)0.0;
+            ci[a][b] = (f64x4)0.0;
+        }
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int64_t c = 0; c < chunks; ++c) {
+        const int buf = (int)(c & 1);
+        if (c + 1 < chunks) fetch(c + 1);
+        const double2* sa = dl + buf * D_STAGE;
+        const double2* sb = sa + D_KC * 64;
+#pragma unroll
+        for (int j = 0; j < D_KC / 4; ++j) {
+            const int kk = 4 * j + lk;
+            double2 av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                av[a] = sa[kk * 64 + wm * 32 + a * 16 + li];
+                bv[a] = sb[kk * 64 + wn * 32 + a * 16 + li];
+            }
+            // term-major order: consecutive MFMAs write different
+            // accumulators; each accumulator still sees its terms in the
+            // streaming kernel's order
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+                    ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+                }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, -bv[b].y, cr[a][b], 0, 0, 0);
+                    ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
+                }
+        }
+        if (c + 1 < chunks) stash(buf ^ 1);
+        __syncthreads();
+    }
+    // accumulator r of a 16x16 FP64 block: row lane/16 + 4 r, column lane%16
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t col = n0 + wn * 32 + b * 16 + li;
+            if (col >= N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wm * 32 + a * 16 + lk + 4 * r;
+                if (row >= M) continue;
+                double2 v = make_double2(cr[a][b][r], ci[a][b][r]);
+                double2* o = out + row * ldo + col;
+                if (accumulate) {
+                    const double2 old = *o;
+                    v.x += old.x;
+                    v.y += old.y;
+                }
+                *o = v;
+            }
+        }
+}
+
+template <typename VIN>
+__global__ __launch_bounds__(256) void pathsum_f64_lds(const VIN* __restrict__ A, int64_t ldA,
+                                                       const VIN* __restrict__ B, int64_t ldB, int64_t K, int64_t M,
+                                                       int64_t N, double2* __restrict__ out, int64_t ldo,
+                                                       int accumulate, int64_t tiles_m, int64_t tiles_n) {
+    extern __shared__ __align__(16) double2 dl[];
+    const int64_t tiles = tiles_m * tiles_n;
+    for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
+        int64_t tm, tn;
+        tile_coords(item, tiles_m, tiles_n, false, tm, tn);
+        f64_lds_tile<VIN>(A, ldA, B, ldB, K, M, N, out, ldo, accumulate, tm * 64, tn * 64, dl);
+    }
+}
+
 // (cheap host calls, repeated per launch so that every device gets them)
 hsf_status set_lds_attrs() {
     hsf_status s = hip_check(hipFuncSetAttribute((const void*)pathsum_bf16x3_lds,
@@ -361,8 +496,16 @@ hsf_status set_lds_attrs() {
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)B_LDS),
                   "hipFuncSetAttribute");
     if (s != HSF_OK) return s;
-    return hip_check(hipFuncSetAttribute((const void*)pathsum_f32_lds_batch,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)F_LDS),
+    s = hip_check(hipFuncSetAttribute((const void*)pathsum_f32_lds_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)F_LDS),
+                  "hipFuncSetAttribute");
+    if (s != HSF_OK) return s;
+    s = hip_check(hipFuncSetAttribute((const void*)pathsum_f64_lds<float2>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)D_LDS),
+                  "hipFuncSetAttribute");
+    if (s != HSF_OK) return s;
+    return hip_check(hipFuncSetAttribute((const void*)pathsum_f64_lds<double2>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)D_LDS),
                      "hipFuncSetAttribute");
 }
 
@@ -379,6 +522,7 @@ void grid_shape(const void* kernel, size_t shmem, int64_t M, int64_t N, int64_t&
 bool path_sum_lds_fits(int mode, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K, int64_t M,
                        int64_t N) {
     if (K < kLdsMinPaths) return false;
+    if (mode == HSF_SUM_F64 || mode == HSF_SUM_C128) return true;
     if (mode == HSF_SUM_BF16X3) return (K + B_KC - 1) / B_KC * (B_KC / 8) <= 65535;
     return ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && ldA % 2 == 0 && ldB % 2 == 0 && M % 2 == 0 &&
            N % 2 == 0;
@@ -437,6 +581,23 @@ hsf_status launch_bf16x3_lds_batch(const void* descs, int n, int64_t tiles, unsi
     hipLaunchKernelGGL(pathsum_bf16x3_lds_batch, dim3(grid), dim3(256), B_LDS, st, (const GemmDesc*)descs, n, base,
                        tiles);
     return hip_check(hipGetLastError(), "pathsum_bf16x3_lds_batch launch");
+}
+
+hsf_status path_sum_f64_lds(bool c128_in, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K, int64_t M,
+                            int64_t N, double2* out, int64_t ldo, int accumulate, hipStream_t st) {
+    hsf_status s = set_lds_attrs();
+    if (s != HSF_OK) return s;
+    const int64_t tm = (M + 63) / 64, tn = (N + 63) / 64;
+    if (c128_in) {
+        const int grid = persistent_grid((const void*)pathsum_f64_lds<double2>, 256, D_LDS, tm * tn);
+        hipLaunchKernelGGL(pathsum_f64_lds<double2>, dim3(grid), dim3(256), D_LDS, st, (const double2*)A, ldA,
+                           (const double2*)B, ldB, K, M, N, out, ldo, accumulate, tm, tn);
+    } else {
+        const int grid = persistent_grid((const void*)pathsum_f64_lds<float2>, 256, D_LDS, tm * tn);
+        hipLaunchKernelGGL(pathsum_f64_lds<float2>, dim3(grid), dim3(256), D_LDS, st, (const float2*)A, ldA,
+                           (const float2*)B, ldB, K, M, N, out, ldo, accumulate, tm, tn);
+    }
+    return hip_check(hipGetLastError(), "pathsum_f64_lds launch");
 }
 
 }  // namespace hsf
