@@ -193,53 +193,58 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
         V v[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) v[j] = tile[sbase ^ soff[j]];
-        // software pipeline: the next record's scalar loads are issued before
-        // the current record is applied
-        DSub<T> cur = subs[s0];
-        for (int s = s0; s < s0 + ns; ++s) {
-            const DSub<T> so = cur;
-            if (s + 1 < s0 + ns) cur = subs[s + 1];
-            const int ty = so.type;
-            if (ty == SUB_D1) {
-                V m00, m01, m10, m11;
-                m00.x = so.m[0]; m00.y = so.m[1];
-                m01.x = so.m[2]; m01.y = so.m[3];
-                m10.x = so.m[4]; m10.y = so.m[5];
-                m11.x = so.m[6]; m11.y = so.m[7];
-                switch (so.g) {
-                    case 0: d1g<K, 0>(v, m00, m01, m10, m11); break;
-                    case 1: d1g<K, 1>(v, m00, m01, m10, m11); break;
-                    case 2: d1g<K, 2>(v, m00, m01, m10, m11); break;
-                    default: d1g<K, 3>(v, m00, m01, m10, m11); break;
-                }
-            } else {
-                uint32_t c = 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (i >= so.nc) break;
-                    const int b = so.qb[i];
-                    const uint32_t bit = b >= 0 ? (base >> b) & 1u : (uint32_t)((gbase >> (-1 - b)) & 1u);
-                    c |= bit << i;
-                }
-                if (ty == SUB_SIGN) {
-                    // the 16 combos' masks are uniform; pick this group's by c
-                    uint32_t w = so.mask[0];
-#pragma unroll
-                    for (int q = 1; q < 8; ++q) w = ((c >> 1) == (uint32_t)q) ? so.mask[q] : w;
-                    const uint32_t mask = (w >> ((c & 1u) * 16u)) & 0xffffu;
-#pragma unroll
-                    for (int j = 0; j < D; ++j)
-                        if ((mask >> j) & 1u) {
-                            v[j].x = -v[j].x;
-                            v[j].y = -v[j].y;
-                        }
-                } else {
-                    const V* row = pool + so.mat + (c << K);
-#pragma unroll
-                    for (int j = 0; j < D; ++j) v[j] = cmul(row[j], v[j]);
-                }
-            }
+        // Records alternate between two register sets (unrolled by two, the
+        // next index clamped so the loads are unconditional): the next
+        // record's scalar loads are issued before the current one is applied,
+        // with no register-to-register copies of the 64-byte records.
+#define HSF_APPLY_SUB(so)                                                                                \
+    {                                                                                                    \
+        const int ty = (so).type;                                                                        \
+        if (ty == SUB_D1) {                                                                              \
+            V m00, m01, m10, m11;                                                                        \
+            m00.x = (so).m[0]; m00.y = (so).m[1];                                                        \
+            m01.x = (so).m[2]; m01.y = (so).m[3];                                                        \
+            m10.x = (so).m[4]; m10.y = (so).m[5];                                                        \
+            m11.x = (so).m[6]; m11.y = (so).m[7];                                                        \
+            switch ((so).g) {                                                                            \
+                case 0: d1g<K, 0>(v, m00, m01, m10, m11); break;                                         \
+                case 1: d1g<K, 1>(v, m00, m01, m10, m11); break;                                         \
+                case 2: d1g<K, 2>(v, m00, m01, m10, m11); break;                                         \
+                default: d1g<K, 3>(v, m00, m01, m10, m11); break;                                        \
+            }                                                                                            \
+        } else {                                                                                         \
+            uint32_t c = 0;                                                                              \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                              \
+                if (i >= (so).nc) break;                                                                 \
+                const int b = (so).qb[i];                                                                \
+                const uint32_t bit = b >= 0 ? (base >> b) & 1u : (uint32_t)((gbase >> (-1 - b)) & 1u);   \
+                c |= bit << i;                                                                           \
+            }                                                                                            \
+            if (ty == SUB_SIGN) {                                                                        \
+                /* the 16 combos' masks are uniform; pick this group's by c */                          \
+                uint32_t w = (so).mask[0];                                                               \
+                _Pragma("unroll") for (int q = 1; q < 8; ++q) w = ((c >> 1) == (uint32_t)q) ? (so).mask[q] : w; \
+                const uint32_t mask = (w >> ((c & 1u) * 16u)) & 0xffffu;                                 \
+                _Pragma("unroll") for (int j = 0; j < D; ++j) if ((mask >> j) & 1u) {                    \
+                    v[j].x = -v[j].x;                                                                    \
+                    v[j].y = -v[j].y;                                                                    \
+                }                                                                                        \
+            } else {                                                                                     \
+                const V* row = pool + (so).mat + (c << K);                                               \
+                _Pragma("unroll") for (int j = 0; j < D; ++j) v[j] = cmul(row[j], v[j]);                 \
+            }                                                                                            \
+        }                                                                                                \
+    }
+        const int s_end = s0 + ns;
+        DSub<T> ra = subs[s0];
+        for (int s = s0; s < s_end; s += 2) {
+            const DSub<T> rb = subs[s + 1 < s_end ? s + 1 : s_end - 1];
+            HSF_APPLY_SUB(ra);
+            if (s + 1 >= s_end) break;
+            ra = subs[s + 2 < s_end ? s + 2 : s_end - 1];
+            HSF_APPLY_SUB(rb);
         }
+#undef HSF_APPLY_SUB
 #pragma unroll
         for (int j = 0; j < D; ++j) tile[sbase ^ soff[j]] = v[j];
     }
