@@ -719,6 +719,14 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
                                         for (size_t e = 0; e < d2; ++e)
                                             pl[op.mat + m * d2 + e] = m < r ? f[m * d2 + e] : cd(0);
                                 }
+                            // one-qubit factor pieces applied inside register groups
+                            for (const SubOp& so : sc.subs)
+                                if (so.type == SUB_SLOT1 && so.block == (int)k) {
+                                    const std::vector<cd>& f = pcs[so.piece].m;
+                                    for (int m = 0; m < b.rank; ++m)
+                                        for (size_t e = 0; e < 4; ++e)
+                                            pl[so.mat + m * 4 + e] = m < r ? f[m * 4 + e] : cd(0);
+                                }
                             if (pl.empty()) pl.push_back(cd(0));
                             all.insert(all.end(), pl.begin(), pl.end());
                         }

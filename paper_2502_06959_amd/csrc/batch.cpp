@@ -27,7 +27,7 @@ struct Batch {
     void* gemms_lds = nullptr;           // LDS-staged path sums
     int n_gemm = 0, n_gemm_lds = 0;
     int64_t tiles_lds = 0;
-    std::vector<int> round_first, round_n, round_kg;
+    std::vector<int> round_first, round_n, round_kg, round_s1;
     std::vector<uint32_t> round_blocks, round_emax;
     int n_split = 0;
     uint32_t split_blocks = 0;
@@ -99,6 +99,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
     b.round_first.clear();
     b.round_n.clear();
     b.round_kg.clear();
+    b.round_s1.clear();
     b.round_blocks.clear();
     b.round_emax.clear();
     size_t rounds = 0;
@@ -115,6 +116,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
         for (int kg = 3; kg <= 4; ++kg) {
             const int first = (int)segs.size();
             uint32_t start = 0, emax = 1;
+            int s1 = 0;
             for (int i = 0; i < n; ++i) {
                 const Plan& p = *b.plans[i];
                 for (int s = 0; s < 2; ++s) {
@@ -134,6 +136,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
                     g.block_start = start;
                     start += (uint32_t)(p.P * g.n_tiles);
                     emax = std::max(emax, 1u << sc.passes[k].n_local);
+                    s1 |= sc.passes[k].has_slot1;
                     segs.push_back(g);
                 }
             }
@@ -141,6 +144,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
             b.round_first.push_back(first);
             b.round_n.push_back((int)segs.size() - first);
             b.round_kg.push_back(kg);
+            b.round_s1.push_back(s1);
             b.round_blocks.push_back(start);
             b.round_emax.push_back(emax);
         }
@@ -215,7 +219,7 @@ hsf_status enqueue(Batch& b, int mode, unsigned char* base, hipStream_t st) {
         const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, emax >> b.round_kg[k]));
         const size_t shmem = ((size_t)emax + 256) * 8;
         if (b.round_blocks[k] == 0) continue;
-        s = launch_sweep_batch(b.round_kg[k], reinterpret_cast<const BatchSeg*>(b.segs) + b.round_first[k], b.round_n[k],
+        s = launch_sweep_batch(b.round_kg[k], b.round_s1[k] != 0, reinterpret_cast<const BatchSeg*>(b.segs) + b.round_first[k], b.round_n[k],
                                b.round_blocks[k], threads, shmem, base, st);
         if (s != HSF_OK) return s;
     }

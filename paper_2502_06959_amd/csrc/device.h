@@ -30,8 +30,8 @@ hsf_status path_sum_bf16x3_lds(const float2* A, int64_t ldA, const float2* B, in
                                int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st);
 
 // Batched launches (tables are device arrays; offsets are relative to `base`).
-hsf_status launch_sweep_batch(int kg, const void* segs, int nseg, uint32_t total_blocks, int threads, size_t shmem,
-                              unsigned char* base, hipStream_t stream);
+hsf_status launch_sweep_batch(int kg, bool s1, const void* segs, int nseg, uint32_t total_blocks, int threads,
+                              size_t shmem, unsigned char* base, hipStream_t stream);
 void batch_sweep_prepare();
 hsf_status launch_split_batch(const void* descs, int n, uint32_t total_blocks, unsigned char* base, hipStream_t st);
 hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);

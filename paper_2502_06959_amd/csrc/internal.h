@@ -125,15 +125,20 @@ struct DevOp {
 // c = sum_i bit_i 2^i, uniform over a thread's group; SIGN negates register
 // element j when bit j of the 16-bit mask (mask[c / 2] >> 16 (c % 2)) is set,
 // PHASE multiplies element j by pool[mat + c 2^k + j].
-enum SubOpType : int32_t { SUB_D1 = 0, SUB_SIGN = 1, SUB_PHASE = 2 };
+enum SubOpType : int32_t { SUB_D1 = 0, SUB_SIGN = 1, SUB_PHASE = 2, SUB_SLOT1 = 3 };
 struct SubOp {
     int32_t type;
     int32_t g;
     int32_t nc;
-    int32_t mat;
+    int32_t mat;          // PHASE: table offset in the pool; SLOT1: first of the rank 2x2 factors
     int32_t qb[4];
     uint32_t mask[8];
     double m[8];
+    // SLOT1 (a one-qubit factor piece on register position g; the path's
+    // digit (path / stride) % rank picks the 2x2 matrix)
+    int32_t rank = 1;
+    int64_t stride = 1;
+    int32_t block = -1, piece = 0;
 };
 
 struct Pass {
@@ -143,6 +148,7 @@ struct Pass {
     int32_t local_q[kMaxTileBits] = {};   // side-local qubit of tile bit i (ascending)
     int32_t n_nonlocal = 0;
     int32_t nonlocal_q[kMaxTileBits] = {};
+    int32_t has_slot1 = 0;             // some group applies a one-qubit factor piece (SUB_SLOT1)
 };
 
 // LDS pass schedule of one side for one tile size.

@@ -633,7 +633,9 @@ namespace {
 // Turns the ops of one pass into device ops: runs of one-qubit gates (on at
 // most four tile bits) and diagonal gates (on any qubits) become one
 // register-resident group; wider dense ops and factor slots stand alone.
-void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::vector<int>& ids) {
+// group_slots: one-qubit factor pieces join register groups (as SUB_SLOT1);
+// otherwise they stay separate ops.
+void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::vector<int>& ids, bool group_slots) {
     const int L = ps.n_local;
     const int KG = group_bits(L);
     auto tbit = [&](int q) -> int {
@@ -670,7 +672,16 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
         for (int id : grp) {
             const SideOp& o = sp.ops[id];
             SubOp so{};
-            if (o.kind == SideOp::DENSE) {
+            if (o.kind == SideOp::SLOT) {
+                so.type = SUB_SLOT1;
+                so.g = pos_in(bits, tbit(o.q[0]));
+                so.mat = (int32_t)sc.pool.size();
+                sc.pool.insert(sc.pool.end(), o.m.begin(), o.m.end());
+                so.rank = o.rank;
+                so.stride = o.stride;
+                so.block = o.block;
+                so.piece = o.piece;
+            } else if (o.kind == SideOp::DENSE) {
                 so.type = SUB_D1;
                 so.g = pos_in(bits, tbit(o.q[0]));
                 for (int i = 0; i < 4; ++i) {
@@ -726,7 +737,8 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
     };
     for (int id : ids) {
         const SideOp& o = sp.ops[id];
-        if (o.kind == SideOp::DENSE && o.k == 1) {
+        // one-qubit gates and one-qubit factor pieces join register groups
+        if ((o.kind == SideOp::DENSE || (o.kind == SideOp::SLOT && group_slots)) && o.k == 1) {
             const int b = tbit(o.q[0]);
             if (pos_in(gbits, b) < 0 && (int)gbits.size() >= KG) close();
             if (pos_in(gbits, b) < 0) gbits.push_back(b);
@@ -764,6 +776,17 @@ Schedule schedule_side(const Plan& p, int s, int L) {
     L = std::max(L, 1);
     sc.tile_bits = L;
     const int nops = (int)sp.ops.size();
+    // fold one-qubit factor pieces into register groups only when blocks
+    // bring several of them to this side (cascades, Sec. V): then the group
+    // saves LDS passes; a lone piece per block is cheaper as its own op
+    std::set<int> piece_blocks;
+    int pieces = 0;
+    for (const SideOp& o : sp.ops)
+        if (o.kind == SideOp::SLOT && o.k == 1) {
+            ++pieces;
+            piece_blocks.insert(o.block);
+        }
+    const bool group_slots = pieces > (int)piece_blocks.size();
     std::vector<char> done(nops, 0);
     int remaining = nops;
     const int low = L >= nq ? L : std::max(0, std::min(5, L - kMaxOpQubits));
@@ -819,7 +842,7 @@ Schedule schedule_side(const Plan& p, int s, int L) {
             }
         }
         ps.op_begin = (int32_t)sc.devops.size();
-        emit_pass(sp, sc, ps, ids);
+        emit_pass(sp, sc, ps, ids, group_slots);
         ps.op_end = (int32_t)sc.devops.size();
         // barriers: only between ops that are not both wave-private (a wave
         // holds 64 lanes x 2^k amplitudes of a group, tile bits 0 .. 5+k)
@@ -832,6 +855,9 @@ Schedule schedule_side(const Plan& p, int s, int L) {
         for (int32_t i = ps.op_begin; i < ps.op_end; ++i) {
             const bool last = i + 1 == ps.op_end;
             sc.devops[i].barrier = (last || !wave_private(sc.devops[i]) || !wave_private(sc.devops[i + 1])) ? 1 : 0;
+            const DevOp& d = sc.devops[i];
+            if (d.type == DOP_GROUP)
+                for (int j = d.mat; j < d.mat + d.rank; ++j) ps.has_slot1 |= sc.subs[j].type == SUB_SLOT1;
         }
         sc.passes.push_back(ps);
         first = false;

@@ -164,10 +164,13 @@ __device__ __forceinline__ void d1g(V (&v)[1 << K], V m00, V m01, V m10, V m11) 
     }
 }
 
-template <int K, typename T>
+// S1: the group may hold one-qubit factor pieces (SUB_SLOT1); instantiated
+// separately so the kernels of passes without them keep their code.
+template <int K, typename T, bool S1>
 __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E, const DevOp& op,
                                             ctab<DSub<T>> subs, const typename Cx<T>::v* __restrict__ pool,
-                                            uint64_t gbase, int tid, int nt) {
+                                            uint64_t gbase, int64_t path, int tid, int nt) {
+    const ctab<T> pool_s = as_table(reinterpret_cast<const T*>(pool));   // uniform reads of factor pieces
     using V = typename Cx<T>::v;
     constexpr int D = 1 << K;
     int sb[K];
@@ -211,6 +214,23 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
                 case 1: d1g<K, 1>(v, m00, m01, m10, m11); break;                                         \
                 case 2: d1g<K, 2>(v, m00, m01, m10, m11); break;                                         \
                 default: d1g<K, 3>(v, m00, m01, m10, m11); break;                                        \
+            }                                                                                            \
+        } else if (S1 && ty == SUB_SLOT1) {                                                              \
+            /* this path's factor: digit (path / stride) % rank (uniform) */                             \
+            const int64_t dig = (so).mask[1]                                                             \
+                ? ((path >> (so).mask[2]) & (int64_t)(so).mask[3])                                       \
+                : (path / (int64_t)(((uint64_t)(so).mask[3] << 32) | (so).mask[2])) % (int64_t)(so).mask[0]; \
+            const int64_t e0 = 2 * ((int64_t)(so).mat + 4 * dig);                                        \
+            V f00, f01, f10, f11;                                                                        \
+            f00.x = pool_s[e0]; f00.y = pool_s[e0 + 1];                                                  \
+            f01.x = pool_s[e0 + 2]; f01.y = pool_s[e0 + 3];                                              \
+            f10.x = pool_s[e0 + 4]; f10.y = pool_s[e0 + 5];                                              \
+            f11.x = pool_s[e0 + 6]; f11.y = pool_s[e0 + 7];                                              \
+            switch ((so).g) {                                                                            \
+                case 0: d1g<K, 0>(v, f00, f01, f10, f11); break;                                         \
+                case 1: d1g<K, 1>(v, f00, f01, f10, f11); break;                                         \
+                case 2: d1g<K, 2>(v, f00, f01, f10, f11); break;                                         \
+                default: d1g<K, 3>(v, f00, f01, f10, f11); break;                                        \
             }                                                                                            \
         } else {                                                                                         \
             uint32_t c = 0;                                                                              \
@@ -257,7 +277,7 @@ template <> struct Threads<double> { static constexpr int max = 512; };
 // KG: register-group width, group_bits(L) of the pass's tile.
 // One tile of one path's half-state through one LDS pass: load (or set
 // |0...0>), apply the pass's ops, store.  `st` is the path's row.
-template <typename T, int KG>
+template <typename T, int KG, bool S1>
 __device__ __forceinline__ void sweep_tile(ctab<Pass> ps, ctab<DevOp> ops, ctab<DSub<T>> subs,
                                            const typename Cx<T>::v* __restrict__ pool,
                                            typename Cx<T>::v* st, uint32_t t, int64_t path,
@@ -296,7 +316,7 @@ __device__ __forceinline__ void sweep_tile(ctab<Pass> ps, ctab<DevOp> ops, ctab<
         const DevOp op = ops[o];
         const int type = op.type;
         if (type == DOP_GROUP) {
-            apply_group<KG, T>(tile, E, op, subs, pool, base, tid, nt);
+            apply_group<KG, T, S1>(tile, E, op, subs, pool, base, path, tid, nt);
         } else {
             // dense factor or wide gate: its matrix goes through LDS so the
             // 4^k uniform entries are read as broadcasts, not held in registers
@@ -322,7 +342,7 @@ __device__ __forceinline__ void sweep_tile(ctab<Pass> ps, ctab<DevOp> ops, ctab<
     for (uint32_t e = tid; e < E; e += nt) st[gidx(e)] = tile[swz(e)];
 }
 
-template <typename T, int KG>
+template <typename T, int KG, bool S1>
 __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideArgs s1, int64_t p_begin) {
     using V = typename Cx<T>::v;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -333,7 +353,7 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideA
     const uint32_t t = blk - pl * n_tiles;
     const int64_t ld = sd ? s1.ld : s0.ld;
     V* st = reinterpret_cast<V*>(sd ? s1.psi : s0.psi) + (int64_t)pl * ld;
-    sweep_tile<T, KG>(as_table(sd ? s1.pass : s0.pass), as_table(sd ? s1.ops : s0.ops),
+    sweep_tile<T, KG, S1>(as_table(sd ? s1.pass : s0.pass), as_table(sd ? s1.ops : s0.ops),
                       as_table(reinterpret_cast<const DSub<T>*>(sd ? s1.subs : s0.subs)),
                       reinterpret_cast<const V*>(sd ? s1.pool : s0.pool), st, t, p_begin + pl,
                       reinterpret_cast<V*>(smem_raw));
@@ -342,7 +362,7 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideA
 // Many circuits' pass k in one launch: segment i covers workgroups
 // [segs[i].block_start, segs[i+1].block_start); its half-states start at
 // base + psi_off.
-template <typename T, int KG>
+template <typename T, int KG, bool S1>
 __global__ __launch_bounds__(Threads<T>::max) void sweep_batch(const BatchSeg* __restrict__ segs_in, int nseg,
                                                                unsigned char* base) {
     using V = typename Cx<T>::v;
@@ -359,7 +379,7 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_batch(const BatchSeg* _
     const uint32_t pl = blk / sg.n_tiles;
     const uint32_t t = blk - pl * sg.n_tiles;
     V* st = reinterpret_cast<V*>(base + sg.psi_off) + (int64_t)pl * sg.ld;
-    sweep_tile<T, KG>(as_table(sg.pass), as_table(sg.ops), as_table(reinterpret_cast<const DSub<T>*>(sg.subs)),
+    sweep_tile<T, KG, S1>(as_table(sg.pass), as_table(sg.ops), as_table(reinterpret_cast<const DSub<T>*>(sg.subs)),
                       reinterpret_cast<const V*>(sg.pool), st, t, pl, reinterpret_cast<V*>(smem_raw));
 }
 
@@ -387,8 +407,18 @@ hsf_status upload_schedule(const Schedule& sc, DeviceSchedule& d) {
         o.nc = so.nc;
         o.mat = so.mat;
         for (int j = 0; j < 4; ++j) o.qb[j] = so.qb[j];
-        if (so.type == SUB_SIGN)
+        if (so.type == SUB_SIGN) {
             for (int j = 0; j < 8; ++j) o.mask[j] = so.mask[j];
+        } else if (so.type == SUB_SLOT1) {
+            // digit (path / stride) % rank: a shift and a mask when both are powers of two
+            const bool pow2 = so.stride > 0 && (so.stride & (so.stride - 1)) == 0 && (so.rank & (so.rank - 1)) == 0;
+            int lg = 0;
+            while (pow2 && (int64_t(1) << lg) < so.stride) ++lg;
+            o.mask[0] = (uint32_t)so.rank;
+            o.mask[1] = pow2 ? 1u : 0u;
+            o.mask[2] = pow2 ? (uint32_t)lg : (uint32_t)(uint64_t)so.stride;
+            o.mask[3] = pow2 ? (uint32_t)(so.rank - 1) : (uint32_t)((uint64_t)so.stride >> 32);
+        }
         else
             for (int j = 0; j < 8; ++j) o.m[j] = (T)so.m[j];
     }
@@ -436,8 +466,11 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
     const int di = p.dtype == HSF_C128 ? 1 : 0;
     if (!g_attr_done[di]) {
         const size_t bytes = ((size_t(1) << max_tile_bits(p.dtype)) + 256) * (p.dtype == HSF_C128 ? 16 : 8);
-        const void* ks[2] = {p.dtype == HSF_C128 ? (const void*)sweep_pass<double, 3> : (const void*)sweep_pass<float, 3>,
-                             p.dtype == HSF_C128 ? (const void*)sweep_pass<double, 4> : (const void*)sweep_pass<float, 4>};
+        const bool c128 = p.dtype == HSF_C128;
+        const void* ks[4] = {c128 ? (const void*)sweep_pass<double, 3, false> : (const void*)sweep_pass<float, 3, false>,
+                             c128 ? (const void*)sweep_pass<double, 4, false> : (const void*)sweep_pass<float, 4, false>,
+                             c128 ? (const void*)sweep_pass<double, 3, true> : (const void*)sweep_pass<float, 3, true>,
+                             c128 ? (const void*)sweep_pass<double, 4, true> : (const void*)sweep_pass<float, 4, true>};
         for (const void* kf : ks) {
             s = hip_check(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
                           "hipFuncSetAttribute");
@@ -465,34 +498,40 @@ void release_device(Plan& p) {
 
 namespace {
 
-template <typename T>
-hsf_status launch_pass_t(int kg, uint32_t total, int threads, size_t shmem, hipStream_t stream, const SideArgs& a,
-                         const SideArgs& b, int64_t p0) {
+template <typename T, bool S1>
+hsf_status launch_pass_ts(int kg, uint32_t total, int threads, size_t shmem, hipStream_t stream, const SideArgs& a,
+                          const SideArgs& b, int64_t p0) {
     switch (kg) {
-        case 4: hipLaunchKernelGGL((sweep_pass<T, 4>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
-        case 3: hipLaunchKernelGGL((sweep_pass<T, 3>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
-        case 2: hipLaunchKernelGGL((sweep_pass<T, 2>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
-        default: hipLaunchKernelGGL((sweep_pass<T, 1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
+        case 4: hipLaunchKernelGGL((sweep_pass<T, 4, S1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
+        case 3: hipLaunchKernelGGL((sweep_pass<T, 3, S1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
+        case 2: hipLaunchKernelGGL((sweep_pass<T, 2, S1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
+        default: hipLaunchKernelGGL((sweep_pass<T, 1, S1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
     }
     return hip_check(hipGetLastError(), "sweep_pass launch");
 }
 
-hsf_status launch_pass(bool dbl, int kg, uint32_t total, int threads, size_t shmem, hipStream_t stream,
+hsf_status launch_pass(bool dbl, int kg, bool s1, uint32_t total, int threads, size_t shmem, hipStream_t stream,
                        const SideArgs& a, const SideArgs& b, int64_t p0) {
-    return dbl ? launch_pass_t<double>(kg, total, threads, shmem, stream, a, b, p0)
-               : launch_pass_t<float>(kg, total, threads, shmem, stream, a, b, p0);
+    if (dbl)
+        return s1 ? launch_pass_ts<double, true>(kg, total, threads, shmem, stream, a, b, p0)
+                  : launch_pass_ts<double, false>(kg, total, threads, shmem, stream, a, b, p0);
+    return s1 ? launch_pass_ts<float, true>(kg, total, threads, shmem, stream, a, b, p0)
+              : launch_pass_ts<float, false>(kg, total, threads, shmem, stream, a, b, p0);
 }
 
 }  // namespace
 
-hsf_status launch_sweep_batch(int kg, const void* segs, int nseg, uint32_t total_blocks, int threads, size_t shmem,
-                              unsigned char* base, hipStream_t stream) {
-    if (kg == 4)
-        hipLaunchKernelGGL((sweep_batch<float, 4>), dim3(total_blocks), dim3(threads), shmem, stream,
-                           (const BatchSeg*)segs, nseg, base);
+hsf_status launch_sweep_batch(int kg, bool s1, const void* segs, int nseg, uint32_t total_blocks, int threads,
+                              size_t shmem, unsigned char* base, hipStream_t stream) {
+    const BatchSeg* sg = (const BatchSeg*)segs;
+    if (kg == 4 && s1)
+        hipLaunchKernelGGL((sweep_batch<float, 4, true>), dim3(total_blocks), dim3(threads), shmem, stream, sg, nseg, base);
+    else if (kg == 4)
+        hipLaunchKernelGGL((sweep_batch<float, 4, false>), dim3(total_blocks), dim3(threads), shmem, stream, sg, nseg, base);
+    else if (kg == 3 && s1)
+        hipLaunchKernelGGL((sweep_batch<float, 3, true>), dim3(total_blocks), dim3(threads), shmem, stream, sg, nseg, base);
     else if (kg == 3)
-        hipLaunchKernelGGL((sweep_batch<float, 3>), dim3(total_blocks), dim3(threads), shmem, stream,
-                           (const BatchSeg*)segs, nseg, base);
+        hipLaunchKernelGGL((sweep_batch<float, 3, false>), dim3(total_blocks), dim3(threads), shmem, stream, sg, nseg, base);
     else
         return fail(HSF_E_UNSUPPORTED, "batched sweeps need groups of 3 or 4 tile bits");
     return hip_check(hipGetLastError(), "sweep_batch launch");
@@ -502,10 +541,9 @@ void batch_sweep_prepare() {
     static bool done = false;
     if (done) return;
     const size_t bytes = ((size_t(1) << max_tile_bits(HSF_C64)) + 256) * 8;
-    (void)hipFuncSetAttribute((const void*)sweep_batch<float, 3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)bytes);
-    (void)hipFuncSetAttribute((const void*)sweep_batch<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)bytes);
+    for (const void* kf : {(const void*)sweep_batch<float, 3, false>, (const void*)sweep_batch<float, 4, false>,
+                           (const void*)sweep_batch<float, 3, true>, (const void*)sweep_batch<float, 4, true>})
+        (void)hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     done = true;
 }
 
@@ -576,7 +614,10 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
                     kgp = group_bits(sc[part]->passes[k].n_local);
                 }
                 const uint32_t tot = c[0].n_blocks + c[1].n_blocks;
-                hsf_status s = launch_pass(dbl, kgp, tot, threads, shmem, stream, c[0], c[1], p_begin + p0);
+                bool s1 = false;
+                for (int q = 0; q < 2; ++q)
+                    if (c[q].pass && c[q].n_blocks) s1 |= sc[q]->passes[k].has_slot1 != 0;
+                hsf_status s = launch_pass(dbl, kgp, s1, tot, threads, shmem, stream, c[0], c[1], p_begin + p0);
                 if (s != HSF_OK) return s;
             }
         }
