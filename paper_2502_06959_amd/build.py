@@ -18,8 +18,8 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, "-I", SRC,
              # packed FP32 instructions stay off (see the design notes)
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wno-unused-command-line-argument"]
-CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-I", INC, "-I", SRC, "-D__HIP_PLATFORM_AMD__",
+             "-pthread", "-Wno-unused-command-line-argument"]
+CXX_FLAGS = ["-O3", "-std=c++17", "-pthread", "-fPIC", "-I", INC, "-I", SRC, "-D__HIP_PLATFORM_AMD__",
              "-I", "/opt/rocm/include", "-Wall", "-Wno-unused-result"]
 
 
@@ -51,7 +51,7 @@ def build(jobs=None, verbose=False):
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, tasks))
     tmp = OUT + f".tmp{os.getpid()}"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

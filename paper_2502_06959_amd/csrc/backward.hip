@@ -20,6 +20,10 @@
 // bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <string>
+#include <thread>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -300,6 +304,7 @@ struct Layout {
     int64_t dimA, dimB;
     int ka, kb;            // checkpoints per side
     int64_t n_occ;         // parametrised ops outside blocks, both sides
+    int64_t n_shift;       // shifted forward runs for angles inside blocks
     size_t table_elems, mat_elems, pool_elems;
 };
 
@@ -332,6 +337,10 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     L.pool_elems = 0;
     for (int s = 0; s < 2; ++s)
         for (const Schedule& sc : p.side[s].sched) L.pool_elems += std::max<size_t>(sc.pool.size(), 1);
+    // parameter shifts of angles inside blocks: two forward runs each, each
+    // with its own copy of the pools
+    L.n_shift = 0;
+    for (const Block& b : p.blocks) L.n_shift += 2 * (int64_t)b.params.size();
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -346,11 +355,11 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     L.ckB = take((size_t)L.kb * chunk * L.dimB * esz);
     L.psi_x = take((size_t)nx * 16);
     L.psi_s = take((size_t)nx * 16);
-    L.loss = take(4 * sizeof(double));
+    L.loss = take((size_t)std::max<int64_t>(4, L.n_shift) * sizeof(double));
     L.partial = take((size_t)std::max<int64_t>(L.n_occ, 1) * chunk * 16);
     L.tables = take(L.table_elems * sizeof(int64_t));
     L.mats = take(L.mat_elems * esz);
-    L.pools = take(L.pool_elems * esz);
+    L.pools = take(L.pool_elems * (size_t)std::max<int64_t>(1, L.n_shift) * esz);
     L.total = o + 256;
     return L;
 }
@@ -675,82 +684,123 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
     // ---- angles inside blocks: parameter shift on the re-factored block
     bool any = false;
     for (const Block& b : p.blocks) any |= !b.params.empty();
+    std::vector<V> staged;    // host copy of the shifted pools; must outlive the upload (final sync)
     if (any) {
         // device pools of every schedule, to be patched per shifted block
         std::vector<std::vector<size_t>> pool_at(2);
         size_t o = 0;
-        std::vector<std::vector<V>> hpool;
         for (int side = 0; side < 2; ++side)
             for (const Schedule& sc : p.side[side].sched) {
                 pool_at[side].push_back(o);
                 o += std::max<size_t>(sc.pool.size(), 1);
             }
-        DeviceCopy dd = d;
-        for (int side = 0; side < 2; ++side)
-            for (size_t i = 0; i < p.side[side].sched.size(); ++i) dd.side[side][i].pool = pools + pool_at[side][i];
         const double half_pi = std::acos(0.0);
-        for (size_t k = 0; k < p.blocks.size(); ++k) {
-            const Block& b = p.blocks[k];
-            for (const auto& gp : b.params) {
-                const int64_t gid = gp.first;
-                const int t = gp.second;
-                if (t >= n_params) continue;
-                for (int sg = 0; sg < 2; ++sg) {
-                    Factors fs;
-                    const double ang = p.gates[gid].param + (sg == 0 ? half_pi : -half_pi);
-                    if ((s = factor_block(p, b, gid, ang, fs)) != HSF_OK) return s;
-                    const int r = fs.rank;
-                    if (r > b.rank)
-                        return fail(HSF_E_UNSUPPORTED, "a shifted block has a larger Schmidt rank than the plan's");
-                    if (fs.product != b.product || fs.pa.size() != b.pa.size() || fs.pb.size() != b.pb.size())
-                        return fail(HSF_E_UNSUPPORTED, "a shifted block changes its decomposition form");
-                    // patched pools: factors of block k replaced (missing ranks zero)
-                    std::vector<cd> all;
-                    all.reserve(Lo.pool_elems);
-                    for (int side = 0; side < 2; ++side) {
-                        const std::vector<FactorPiece>& pcs = side == 0 ? fs.pa : fs.pb;
-                        for (const Schedule& sc : p.side[side].sched) {
-                            std::vector<cd> pl = sc.pool;
-                            for (const DevOp& op : sc.devops)
-                                if (op.type == DOP_SLOT && op.block == (int)k) {
-                                    const std::vector<cd>& f = pcs[op.piece].m;
-                                    const size_t d2 = (size_t)1 << (2 * op.k);
-                                    for (int m = 0; m < b.rank; ++m)
-                                        for (size_t e = 0; e < d2; ++e)
-                                            pl[op.mat + m * d2 + e] = m < r ? f[m * d2 + e] : cd(0);
-                                }
-                            // one-qubit factor pieces applied inside register groups
-                            for (const SubOp& so : sc.subs)
-                                if (so.type == SUB_SLOT1 && so.block == (int)k) {
-                                    const std::vector<cd>& f = pcs[so.piece].m;
-                                    for (int m = 0; m < b.rank; ++m)
-                                        for (size_t e = 0; e < 4; ++e)
-                                            pl[so.mat + m * 4 + e] = m < r ? f[m * 4 + e] : cd(0);
-                                }
-                            if (pl.empty()) pl.push_back(cd(0));
-                            all.insert(all.end(), pl.begin(), pl.end());
-                        }
-                    }
-                    std::vector<V> av;
-                    to_dev<T>(all, av);
-                    if ((s = hip_check(hipMemcpyAsync(pools, av.data(), av.size() * sizeof(V), hipMemcpyHostToDevice, st),
-                                       "upload shifted factors")) != HSF_OK)
-                        return s;
-                    for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
-                        const int64_t np = std::min(chunk, p.P - p0);
-                        if ((s = run_sides(p, dd, p0, np, vS[0], dim[0], vS[1], dim[1], st)) != HSF_OK) return s;
-                        if ((s = gather_dot(p.dtype, vS[0], dim[0], vS[1], dim[1], np, p.nb, p.n, x, nx, psi_s,
-                                            p0 > 0 ? 1 : 0, st)) != HSF_OK)
-                            return s;
-                    }
-                    hipLaunchKernelGGL(bw_loss, dim3(1), dim3(256), 0, st, (const double2*)psi_s, nx, lossb + sg);
-                    if ((s = hip_check(hipGetLastError(), "bw_loss launch")) != HSF_OK) return s;
-                    // the host copy of the pools must outlive the upload
-                    if ((s = hip_check(hipStreamSynchronize(st), "sync")) != HSF_OK) return s;
-                }
-                hipLaunchKernelGGL(bw_shift_combine, dim3(1), dim3(1), 0, st, lossb, lossb + 1, grad, (int64_t)t);
-                if ((s = hip_check(hipGetLastError(), "bw_shift_combine launch")) != HSF_OK) return s;
+        struct Shift {
+            size_t k;
+            int64_t gid;
+            int t, sg;
+        };
+        std::vector<Shift> shifts;
+        for (size_t k = 0; k < p.blocks.size(); ++k)
+            for (const auto& gp : p.blocks[k].params)
+                if (gp.second < n_params)
+                    for (int sg = 0; sg < 2; ++sg) shifts.push_back({k, gp.first, gp.second, sg});
+        const size_t ns = shifts.size();
+        // every shifted block re-factored on the host, in parallel (they are
+        // independent), into its own patched copy of the pools
+        staged.assign(ns * Lo.pool_elems, V{});
+        std::vector<hsf_status> hst(ns, HSF_OK);
+        std::vector<std::string> herr(ns);
+        auto refactor = [&](size_t i) {
+            const Shift& sh = shifts[i];
+            const Block& b = p.blocks[sh.k];
+            Factors fs;
+            const double ang = p.gates[sh.gid].param + (sh.sg == 0 ? half_pi : -half_pi);
+            hsf_status e = factor_block(p, b, sh.gid, ang, fs);
+            if (e != HSF_OK) {
+                hst[i] = e;
+                herr[i] = hsf::g_last_error_copy();
+                return;
             }
+            const int r = fs.rank;
+            if (r > b.rank) {
+                hst[i] = HSF_E_UNSUPPORTED;
+                herr[i] = "a shifted block has a larger Schmidt rank than the plan's";
+                return;
+            }
+            if (fs.product != b.product || fs.pa.size() != b.pa.size() || fs.pb.size() != b.pb.size()) {
+                hst[i] = HSF_E_UNSUPPORTED;
+                herr[i] = "a shifted block changes its decomposition form";
+                return;
+            }
+            // patched pools: factors of block k replaced (missing ranks zero)
+            std::vector<cd> all;
+            all.reserve(Lo.pool_elems);
+            for (int side = 0; side < 2; ++side) {
+                const std::vector<FactorPiece>& pcs = side == 0 ? fs.pa : fs.pb;
+                for (const Schedule& sc : p.side[side].sched) {
+                    std::vector<cd> pl = sc.pool;
+                    for (const DevOp& op : sc.devops)
+                        if (op.type == DOP_SLOT && op.block == (int)sh.k) {
+                            const std::vector<cd>& f = pcs[op.piece].m;
+                            const size_t d2 = (size_t)1 << (2 * op.k);
+                            for (int m = 0; m < b.rank; ++m)
+                                for (size_t e2 = 0; e2 < d2; ++e2)
+                                    pl[op.mat + m * d2 + e2] = m < r ? f[m * d2 + e2] : cd(0);
+                        }
+                    // one-qubit factor pieces applied inside register groups
+                    for (const SubOp& so : sc.subs)
+                        if (so.type == SUB_SLOT1 && so.block == (int)sh.k) {
+                            const std::vector<cd>& f = pcs[so.piece].m;
+                            for (int m = 0; m < b.rank; ++m)
+                                for (size_t e2 = 0; e2 < 4; ++e2)
+                                    pl[so.mat + m * 4 + e2] = m < r ? f[m * 4 + e2] : cd(0);
+                        }
+                    if (pl.empty()) pl.push_back(cd(0));
+                    all.insert(all.end(), pl.begin(), pl.end());
+                }
+            }
+            std::vector<V> av;
+            to_dev<T>(all, av);
+            std::copy(av.begin(), av.end(), staged.begin() + i * Lo.pool_elems);
+        };
+        {
+            const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+            const size_t nthr = std::min<size_t>(ns, std::min(16u, hw));
+            std::atomic<size_t> next(0);
+            std::vector<std::thread> pool_threads;
+            for (size_t w = 0; w < nthr; ++w)
+                pool_threads.emplace_back([&]() {
+                    for (size_t i = next++; i < ns; i = next++) refactor(i);
+                });
+            for (std::thread& th : pool_threads) th.join();
+        }
+        for (size_t i = 0; i < ns; ++i)
+            if (hst[i] != HSF_OK) return fail(hst[i], herr[i]);
+        // one upload for all shifted pools (the host copy lives until the final sync)
+        if ((s = hip_check(hipMemcpyAsync(pools, staged.data(), staged.size() * sizeof(V), hipMemcpyHostToDevice, st),
+                           "upload shifted factors")) != HSF_OK)
+            return s;
+        DeviceCopy dd = d;
+        for (size_t i = 0; i < ns; ++i) {
+            for (int side = 0; side < 2; ++side)
+                for (size_t q = 0; q < p.side[side].sched.size(); ++q)
+                    dd.side[side][q].pool = pools + i * Lo.pool_elems + pool_at[side][q];
+            for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
+                const int64_t np = std::min(chunk, p.P - p0);
+                if ((s = run_sides(p, dd, p0, np, vS[0], dim[0], vS[1], dim[1], st)) != HSF_OK) return s;
+                if ((s = gather_dot(p.dtype, vS[0], dim[0], vS[1], dim[1], np, p.nb, p.n, x, nx, psi_s,
+                                    p0 > 0 ? 1 : 0, st)) != HSF_OK)
+                    return s;
+            }
+            hipLaunchKernelGGL(bw_loss, dim3(1), dim3(256), 0, st, (const double2*)psi_s, nx, lossb + i);
+            if ((s = hip_check(hipGetLastError(), "bw_loss launch")) != HSF_OK) return s;
+        }
+        // dL/dt += (L(t + pi/2) - L(t - pi/2)) / 2 per occurrence, in plan order
+        for (size_t i = 0; i < ns; i += 2) {
+            hipLaunchKernelGGL(bw_shift_combine, dim3(1), dim3(1), 0, st, lossb + i, lossb + i + 1, grad,
+                               (int64_t)shifts[i].t);
+            if ((s = hip_check(hipGetLastError(), "bw_shift_combine launch")) != HSF_OK) return s;
         }
     }
     // host staging buffers above must outlive their async uploads
