@@ -43,12 +43,15 @@ def _src_hash(*names):
     return h.hexdigest()[:12]
 
 
-def _traffic_from_profiles(kernel, src_hash):
+def _traffic_from_profiles(kernel, src_hash, workload):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE +
     WRITE_SIZE, copy-kernel calibrated), read from profiles/traffic.md if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source and this workload; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.md")
     if not os.path.exists(path):
+        return None
+    head = open(path).readline()
+    if not head.strip().endswith(f"workload {workload}"):
         return None
     for line in open(path):
         parts = line.strip().strip("|").split("|")
@@ -206,7 +209,11 @@ def main():
         src = _src_hash("pathsum.hip", "bf16x3.hip", "epilogue.h")
         # the timed path-sum call: one MFMA kernel (FP32), or the two split
         # passes plus the MFMA kernel (split-BF16 x3)
-        kern = "pathsum_f32" if args.mode == "f32" else "split_planes x2 + pathsum_bf16x3_kernel"
+        many = P >= 128      # LDS-staged kernels from 128 paths on
+        if args.mode == "f32":
+            kern = "pathsum_f32_lds" if many else "pathsum_f32"
+        else:
+            kern = "split_chunked x2 + pathsum_bf16x3_lds" if many else "split_planes x2 + pathsum_bf16x3_kernel"
         ach_tf = flops / (sum_ms * 1e-3) / 1e12
         if args.mode == "f32":
             bound, peak, unit, achieved = "mfma", MFMA_PEAK["f32"], "TFLOP/s", ach_tf
@@ -219,7 +226,7 @@ def main():
                 achieved = (out_bytes + in_bytes) / (sum_ms * 1e-3) / 1e9
             else:
                 bound, peak, unit, achieved = "mfma", MFMA_PEAK["bf16x3"], "TFLOP/s", 3 * ach_tf
-        traffic = _traffic_from_profiles(kern, src)
+        traffic = _traffic_from_profiles(kern, src, args.workload)
     else:
         src = _src_hash("sweep.hip")
         kern = "sweep_pass<float> (all passes)"
@@ -229,7 +236,7 @@ def main():
         fl = P * 14.0 * ((1 << na) * sa["ops_fused"] + (1 << nb) * sb["ops_fused"])
         bound, peak, unit = "alu", 78.6, "TFLOP/s"
         achieved = fl / (sweep_ms * 1e-3) / 1e12
-        traffic = _traffic_from_profiles(kern, src)
+        traffic = _traffic_from_profiles(kern, src, args.workload)
 
     res = {
         "metric": "path-gate updates/s (%HBM peak) + path-sum TFLOP/s; vs plain c64 HSF at rel-L2<=1e-5",
