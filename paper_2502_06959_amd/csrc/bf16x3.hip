@@ -136,132 +136,180 @@ __device__ __forceinline__ void bf16x3_tile(const unsigned short* __restrict__ P
     store_tile_128(cr, ci, row0, col0, M, N, out, ldo, accumulate);
 }
 
-// Persistent streaming kernel: 8 waves per 128 x 128 tile, wave (wm, wn) =
-// (w / 4, w % 4) owns rows 64 wm .. +63 and columns 32 wn .. +31 (two 32x32
-// blocks).  Half the accumulators and operands of a 64 x 64 wave tile leave
-// room for two waves per SIMD, so one wave's stores drain while another
-// multiplies.  The operands of the next tile's first two 16-path steps are
-// loaded before this tile's results are stored: loads and stores share one
-// completion counter, so loads issued after the stores would wait for them.
-// Per output block the MFMA sequence is that of bf16x3_tile.
-struct Bf16Step {
-    u16x8 a[2][4], b[4];
-};
+// Persistent streaming kernel.  The complex product is taken as one real
+// product with the real and imaginary parts of the output interleaved,
+// exactly as the output is laid out in memory:
+//   C2[m][2n]   = sum_k Ar[k][m] Br[k][n] + Ai[k][m] (-Bi[k][n])
+//   C2[m][2n+1] = sum_k Ar[k][m] Bi[k][n] + Ai[k][m]   Br[k][n]
+// i.e. A2 = [Ar | Ai] along a doubled path axis and real column 2n + p of
+// B2 = [Br Bi ; -Bi Br] (column pairs).  An MFMA lane then holds single
+// floats of consecutive output columns, stored as they are (no register
+// pairing).  Per 16 paths a block takes the real-plane half of the axis with
+// lane 2q holding Br and lane 2q+1 Bi of column n = q (one load each), then
+// the imaginary-plane half with the two lanes' operands swapped (a DPP
+// exchange) and the even lane's negated: each B value is loaded once.
+//
+// Workgroup tile: 256 rows x 128 complex columns; wave w owns rows
+// 32 w .. +31 and all 256 real columns as eight 32x32 blocks side by side,
+// so each wave writes whole 1 KiB row segments, which the HBM write path
+// drains faster than narrower per-wave strips.  Each block's B2 operand for
+// the next step (or the next tile's first step) is loaded right after the
+// block's MFMAs, and A2's at the start of the chunk, so the loads of a
+// tile's successor are issued before the tile's stores (loads and stores
+// share one completion counter: loads issued after the stores would wait
+// for them).  Per block and half: hi*hi + hi*lo + lo*hi.
+constexpr int BW_ROWS = 256, BW_COLS = 128;
 
-__device__ __forceinline__ void load_step(const unsigned short* __restrict__ PA, int64_t M,
-                                          const unsigned short* __restrict__ PB, int64_t N, int64_t Kp,
-                                          int64_t m0, int64_t n0, int64_t k0, Bf16Step& st) {
-    const int lane = threadIdx.x & 63, li = lane & 31, lk = lane >> 5;
-    const int64_t pa = M * Kp, pb = N * Kp, kk = k0 + lk * 8;
-    const u16x8 zero = (u16x8)0;
+// a value the caller knows to be equal in all lanes, kept in scalar registers
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// A2 operands of the 16 paths from k0: row r0 + lane % 32, paths
+// k0 + 8 (lane / 32) .. +7 of the four planes (re hi, re lo, im hi, im lo).
+// lane = (lane % 32) Kp + 8 (lane / 32), the lane's fixed element offset.
+template <bool FULL>
+__device__ __forceinline__ void load_a2(const unsigned short* __restrict__ P, int64_t M, int64_t Kp, int64_t r0,
+                                        int64_t k0, uint32_t lane_off, u16x8 (&v)[4]) {
+    const int64_t plane = M * Kp;
+    if (FULL) {
+        // wave-uniform base in scalar registers + the 32-bit lane offset
+        const unsigned short* base = P + uniform_i64(r0 * Kp + k0);
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int64_t m = m0 + a * 32 + li;
-        const bool mok = m < M;
-        const unsigned short* p = PA + (mok ? m : 0) * Kp + kk;
-#pragma unroll
-        for (int pl = 0; pl < 4; ++pl) st.a[a][pl] = mok ? *reinterpret_cast<const u16x8*>(p + pl * pa) : zero;
+        for (int pl = 0; pl < 4; ++pl) v[pl] = *reinterpret_cast<const u16x8*>(base + pl * plane + lane_off);
+        return;
     }
-    const int64_t n = n0 + li;
-    const bool nok = n < N;
-    const unsigned short* q = PB + (nok ? n : 0) * Kp + kk;
-#pragma unroll
-    for (int pl = 0; pl < 4; ++pl) st.b[pl] = nok ? *reinterpret_cast<const u16x8*>(q + pl * pb) : zero;
-}
-
-__device__ __forceinline__ void mma_step(const Bf16Step& st, f32x16 (&cr)[2], f32x16 (&ci)[2]) {
-    const bf16x8 yrh = as_bf(st.b[0]), yrl = as_bf(st.b[1]), yih = as_bf(st.b[2]), yil = as_bf(st.b[3]);
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const bf16x8 xrh = as_bf(st.a[a][0]), xrl = as_bf(st.a[a][1]), xih = as_bf(st.a[a][2]),
-                     xil = as_bf(st.a[a][3]);
-        const bf16x8 nih = as_bf(st.a[a][2] ^ (u16x8)0x8000), nil = as_bf(st.a[a][3] ^ (u16x8)0x8000);
-        f32x16 r = cr[a], i = ci[a];
-        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrh, r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrl, r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yrh, r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yih, r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yil, r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nil, yih, r, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yih, i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yil, i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yih, i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrh, i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrl, i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xil, yrh, i, 0, 0, 0);
-        cr[a] = r;
-        ci[a] = i;
-    }
-}
-
-// Stores a wave's 64 x 32 block pair (accumulator r of a 32x32 block at row
-// (r/4)*8 + (lane/32)*4 + r%4, column lane%32).
-__device__ __forceinline__ void store_64x32(const f32x16 (&cr)[2], const f32x16 (&ci)[2], int64_t m0, int64_t n0,
-                                            int64_t M, int64_t N, float2* __restrict__ out, int64_t ldo,
-                                            int accumulate) {
     const int lane = threadIdx.x & 63, li = lane & 31, lk = lane >> 5;
-    const int64_t col = n0 + li;
-    if (col >= N) return;
+    const int64_t r = r0 + li;
+    const bool ok = r < M;
+    const unsigned short* p = P + (ok ? r : 0) * Kp + k0 + lk * 8;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t row = m0 + a * 32 + (r >> 2) * 8 + lk * 4 + (r & 3);
-            if (row >= M) continue;
-            float2 v = make_float2(cr[a][r], ci[a][r]);
-            float2* o = out + row * ldo + col;
-            if (accumulate) {
-                const float2 old = *o;
-                v.x += old.x;
-                v.y += old.y;
-            }
-            *o = v;
-        }
+    for (int pl = 0; pl < 4; ++pl) v[pl] = ok ? *reinterpret_cast<const u16x8*>(p + pl * plane) : (u16x8)0;
 }
 
+// B2 operand of the real-plane half for the 32 real columns c0 .. c0+31
+// (c0 even): lane column c0 + lane % 32 is part lane % 2 of complex column
+// c0/2 + (lane % 32)/2.  lane_off = ((lane % 32)/2) Kp + 8 (lane / 32) +
+// (lane % 2) 2 N Kp, the lane's fixed element offset.
+template <bool FULL>
+__device__ __forceinline__ void load_b2(const unsigned short* __restrict__ P, int64_t N, int64_t Kp, int64_t c0,
+                                        int64_t k0, uint32_t lane_off, u16x8& hi, u16x8& lo) {
+    const int64_t plane = N * Kp;
+    if (FULL) {
+        const unsigned short* base = P + uniform_i64((c0 >> 1) * Kp + k0);
+        hi = *reinterpret_cast<const u16x8*>(base + lane_off);
+        lo = *reinterpret_cast<const u16x8*>(base + plane + lane_off);
+        return;
+    }
+    const int lane = threadIdx.x & 63, li = lane & 31, lk = lane >> 5, par = li & 1;
+    const int64_t n = (c0 >> 1) + (li >> 1);
+    const bool ok = n < N;
+    const unsigned short* p = P + (par ? 2 * plane : 0) + (ok ? n : 0) * Kp + k0 + lk * 8;
+    hi = ok ? *reinterpret_cast<const u16x8*>(p) : (u16x8)0;
+    lo = ok ? *reinterpret_cast<const u16x8*>(p + plane) : (u16x8)0;
+}
+
+// The imaginary-plane half's B2 operand: lanes 2q and 2q+1 exchange their
+// values (Br <-> Bi) and the even lane negates (-Bi).
+__device__ __forceinline__ u16x8 swap_pair(u16x8 v, uint32_t neg) {
+    const auto d = __builtin_bit_cast(uint32_t __attribute__((ext_vector_type(4))), v);
+    uint32_t __attribute__((ext_vector_type(4))) o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        o[e] = (uint32_t)__builtin_amdgcn_mov_dpp((int)d[e], 0xB1, 0xF, 0xF, false) ^ neg;   // quad_perm [1,0,3,2]
+    return __builtin_bit_cast(u16x8, o);
+}
+
+// FULL: M a multiple of 256, N of 128, no accumulation, 32 output rows
+// spanning less than 2^31 bytes and each operand's planes less than 2^31
+// elements: no bounds tests anywhere, and every load and store takes a
+// wave-uniform base plus a fixed 32-bit lane offset.
+template <bool FULL>
 __global__ __launch_bounds__(512) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
                                                              const unsigned short* __restrict__ PB, int64_t N,
                                                              int64_t Kp, float2* __restrict__ out, int64_t ldo,
                                                              int accumulate, int64_t tiles_n, int64_t tiles) {
-    const int w = threadIdx.x >> 6;
-    const int64_t wr = (w >> 2) * 64, wc = (w & 3) * 32;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, li = lane & 31, lk = lane >> 5;
+    float* __restrict__ of = reinterpret_cast<float*>(out);
+    const uint32_t neg = (li & 1) ? 0u : 0x80008000u;
+    const uint32_t a_off = (uint32_t)li * (uint32_t)Kp + lk * 8;
+    const uint32_t b_off = (uint32_t)(li >> 1) * (uint32_t)Kp + lk * 8 + ((li & 1) ? (uint32_t)(2 * N * Kp) : 0u);
     int64_t tile = blockIdx.x;
     if (tile >= tiles) return;
     auto origin = [&](int64_t t, int64_t& r0, int64_t& c0) {
         const int64_t tm = t / tiles_n, tn = t - tm * tiles_n;
-        r0 = tm * BF_TILE + wr;
-        c0 = tn * BF_TILE + wc;
+        r0 = tm * BW_ROWS + w * 32;
+        c0 = tn * (2 * BW_COLS);    // real columns
     };
-    int64_t m0, n0;
-    origin(tile, m0, n0);
-    Bf16Step s0, s1;
-    load_step(PA, M, PB, N, Kp, m0, n0, 0, s0);
-    if (Kp > 16) load_step(PA, M, PB, N, Kp, m0, n0, 16, s1);
-    for (;;) {
-        f32x16 cr[2], ci[2];
+    int64_t m0, c0;
+    origin(tile, m0, c0);
+    u16x8 a[4], bh[8], bl[8];
+    load_a2<FULL>(PA, M, Kp, m0, 0, a_off, a);
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            cr[a] = (f32x16)0.0f;
-            ci[a] = (f32x16)0.0f;
-        }
-        mma_step(s0, cr, ci);
-        if (Kp > 16) mma_step(s1, cr, ci);
-        for (int64_t k0 = 32; k0 < Kp; k0 += 16) {
-            load_step(PA, M, PB, N, Kp, m0, n0, k0, s1);
-            mma_step(s1, cr, ci);
-        }
+    for (int blk = 0; blk < 8; ++blk) load_b2<FULL>(PB, N, Kp, c0 + blk * 32, 0, b_off, bh[blk], bl[blk]);
+    for (;;) {
         const int64_t next = tile + gridDim.x;
-        int64_t nm0 = 0, nn0 = 0;
-        if (next < tiles) {
-            origin(next, nm0, nn0);
-            load_step(PA, M, PB, N, Kp, nm0, nn0, 0, s0);
-            if (Kp > 16) load_step(PA, M, PB, N, Kp, nm0, nn0, 16, s1);
+        int64_t nm0 = m0, nc0 = c0;
+        if (next < tiles) origin(next, nm0, nc0);
+        f32x16 acc[8];
+#pragma unroll
+        for (int blk = 0; blk < 8; ++blk) acc[blk] = (f32x16)0.0f;
+        for (int64_t k0 = 0; k0 < Kp; k0 += 16) {
+            // operands of the following 16 paths: this tile's, else the next tile's first
+            const bool last = k0 + 16 >= Kp, more = !last || next < tiles;
+            const int64_t lm = last ? nm0 : m0, lc = last ? nc0 : c0, lk0 = last ? 0 : k0 + 16;
+            const bf16x8 xrh = as_bf(a[0]), xrl = as_bf(a[1]), xih = as_bf(a[2]), xil = as_bf(a[3]);
+            if (more) load_a2<FULL>(PA, M, Kp, lm, lk0, a_off, a);
+#pragma unroll
+            for (int blk = 0; blk < 8; ++blk) {
+                const bf16x8 yh = as_bf(bh[blk]), yl = as_bf(bl[blk]);
+                const bf16x8 zh = as_bf(swap_pair(bh[blk], neg)), zl = as_bf(swap_pair(bl[blk], neg));
+                f32x16 c = acc[blk];
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yh, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yl, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yh, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, zh, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, zl, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xil, zh, c, 0, 0, 0);
+                acc[blk] = c;
+                if (more) load_b2<FULL>(PB, N, Kp, lc + blk * 32, lk0, b_off, bh[blk], bl[blk]);
+            }
         }
-        store_64x32(cr, ci, m0, n0, M, N, out, ldo, accumulate);
+        // accumulator r of block blk: row m0 + (r/4)*8 + (lane/32)*4 + r%4,
+        // real column c0 + 32 blk + lane%32
+        if (FULL) {
+            const int64_t ldf = 2 * ldo;
+            const int64_t wofs = uniform_i64(m0 * ldf + c0);
+            const uint32_t voff = (uint32_t)(lk * 4) * (uint32_t)ldf + (uint32_t)li;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t rofs =
+                    wofs + (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)((r >> 2) * 8 + (r & 3)) * (uint32_t)ldf);
+                float* __restrict__ pl = of + rofs + voff;
+#pragma unroll
+                for (int blk = 0; blk < 8; ++blk) pl[blk * 32] = acc[blk][r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = m0 + (r >> 2) * 8 + lk * 4 + (r & 3);
+                if (row >= M) continue;
+#pragma unroll
+                for (int blk = 0; blk < 8; ++blk) {
+                    const int64_t col = c0 + blk * 32 + li;
+                    if ((col >> 1) >= N) continue;
+                    float* o = of + row * 2 * ldo + col;
+                    *o = accumulate ? *o + acc[blk][r] : acc[blk][r];
+                }
+            }
+        }
         if (next >= tiles) break;
         tile = next;
         m0 = nm0;
-        n0 = nn0;
+        c0 = nc0;
     }
 }
 
@@ -353,10 +401,17 @@ hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_
         hsf_status s = hip_check(hipGetLastError(), "split_planes launch");
         if (s != HSF_OK) return s;
     }
-    const int64_t tn = (N + BF_TILE - 1) / BF_TILE, tiles = tn * ((M + BF_TILE - 1) / BF_TILE);
-    const int grid = persistent_grid((const void*)pathsum_bf16x3_kernel, 512, 0, tiles);
-    hipLaunchKernelGGL(pathsum_bf16x3_kernel, dim3(grid), dim3(512), 0, st, PA, M, PB, N, Kp, out, ldo, accumulate,
-                       tn, tiles);
+    const int64_t tn = (N + BW_COLS - 1) / BW_COLS, tiles = tn * ((M + BW_ROWS - 1) / BW_ROWS);
+    const bool full = !accumulate && M % BW_ROWS == 0 && N % BW_COLS == 0 && ldo <= (int64_t)(INT32_MAX / 8 / 32) &&
+                      4 * std::max(M, N) * Kp <= (int64_t)INT32_MAX;
+    const void* kern = full ? (const void*)pathsum_bf16x3_kernel<true> : (const void*)pathsum_bf16x3_kernel<false>;
+    const int grid = persistent_grid(kern, 512, 0, tiles);
+    if (full)
+        hipLaunchKernelGGL(pathsum_bf16x3_kernel<true>, dim3(grid), dim3(512), 0, st, PA, M, PB, N, Kp, out, ldo, 0,
+                           tn, tiles);
+    else
+        hipLaunchKernelGGL(pathsum_bf16x3_kernel<false>, dim3(grid), dim3(512), 0, st, PA, M, PB, N, Kp, out, ldo,
+                           accumulate, tn, tiles);
     return hip_check(hipGetLastError(), "pathsum_bf16x3 launch");
 }
 
