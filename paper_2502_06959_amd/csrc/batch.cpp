@@ -26,6 +26,7 @@ struct Batch {
     void* gemms = nullptr;               // streaming path sums (fewer than kLdsMinPaths paths)
     void* gemms_lds = nullptr;           // LDS-staged path sums
     int n_gemm = 0, n_gemm_lds = 0;
+    bool stream_full = false;            // every streaming product takes the bounds-free kernel
     int64_t tiles_lds = 0;
     std::vector<int> round_first, round_n, round_kg, round_s1;
     std::vector<uint32_t> round_blocks, round_emax;
@@ -155,6 +156,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
     std::vector<GemmDesc> gm, gl;
     uint32_t sb = 0;
     int64_t tiles = 0, tiles_lds = 0;
+    bool stream_full = true;
     for (int i = 0; i < n; ++i) {
         const Plan& p = *b.plans[i];
         const int64_t M = int64_t(1) << p.na, N = int64_t(1) << p.nb;
@@ -191,10 +193,17 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
         g.N = N;
         g.out = outs[i];
         g.ldo = N;
-        g.tiles_n = (N + 127) / 128;
         int64_t& t = deep ? tiles_lds : tiles;
         g.tile_start = t;
-        t += g.tiles_n * ((M + 127) / 128);
+        if (mode == HSF_SUM_BF16X3 && !deep) {
+            // streaming split-BF16 tiles
+            g.tiles_n = (N + kBf16StreamCols - 1) / kBf16StreamCols;
+            t += g.tiles_n * ((M + kBf16StreamRows - 1) / kBf16StreamRows);
+            stream_full = stream_full && bf16x3_stream_full(M, N, g.K, g.ldo, 0);
+        } else {
+            g.tiles_n = (N + 127) / 128;
+            t += g.tiles_n * ((M + 127) / 128);
+        }
         (deep ? gl : gm).push_back(g);
     }
     if ((s = upload_table(sp, &b.splits)) != HSF_OK) return s;
@@ -206,6 +215,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
     b.n_split = (int)sp.size();
     b.split_blocks = sb;
     b.tiles = tiles;
+    b.stream_full = stream_full;
     b.built_policy = b.policy;
     b.built_mode = mode;
     b.built_outs.assign(outs, outs + n);
@@ -231,7 +241,7 @@ hsf_status enqueue(Batch& b, int mode, unsigned char* base, hipStream_t st) {
         if (s != HSF_OK) return s;
     }
     if (b.n_gemm == 0) return HSF_OK;
-    return bf ? launch_bf16x3_batch(b.gemms, b.n_gemm, b.tiles, base, st)
+    return bf ? launch_bf16x3_batch(b.gemms, b.n_gemm, b.tiles, b.stream_full, base, st)
               : launch_f32_batch(b.gemms, b.n_gemm, b.tiles, base, st);
 }
 

@@ -2,8 +2,8 @@
 // x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), and each real product
 // is taken as hi*hi + hi*lo + lo*hi on the BF16 MFMA with FP32
 // accumulation (the lo*lo term, ~2^-16 relative, is dropped).  The complex
-// product C = PsiA^T PsiB then needs 12 BF16 MFMAs per 32x32 block and
-// 16-path chunk: Cr = Ar Br - Ai Bi, Ci = Ar Bi + Ai Br.
+// product C = PsiA^T PsiB (Cr = Ar Br - Ai Bi, Ci = Ar Bi + Ai Br) then
+// costs 12 BF16 MFMAs per 32x32 complex outputs and 16 paths.
 //
 // A split pass first rewrites the half-states (rows = paths, interleaved
 // complex) into four BF16 planes (re hi, re lo, im hi, im lo) laid out
@@ -59,83 +59,6 @@ __global__ __launch_bounds__(256) void split_planes(const float2* __restrict__ X
 
 __device__ __forceinline__ bf16x8 as_bf(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
 
-// Workgroup: 4 waves in 2 x 2, each wave 64 x 64 complex outputs (2 x 2
-// blocks of the 32x32x16 BF16 MFMA).  Lane l of a block supplies row
-// (l % 32) and paths k0 + 8 (l / 32) .. +7.
-constexpr int BF_TILE = 128;
-
-__device__ __forceinline__ void bf16x3_tile(const unsigned short* __restrict__ PA, int64_t M,
-                                            const unsigned short* __restrict__ PB, int64_t N, int64_t Kp,
-                                            float2* __restrict__ out, int64_t ldo, int accumulate, int64_t row0,
-                                            int64_t col0) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int li = lane & 31, lk = lane >> 5;
-    const int64_t m0 = row0 + (w >> 1) * 64;
-    const int64_t n0 = col0 + (w & 1) * 64;
-    const int64_t pa = M * Kp, pb = N * Kp;
-    f32x16 cr[2][2], ci[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            cr[a][b] = (f32x16)0.0f;
-            ci[a][b] = (f32x16)0.0f;
-        }
-    int64_t ra[2], rb[2];
-    bool mok[2], nok[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int64_t m = m0 + a * 32 + li, n = n0 + a * 32 + li;
-        mok[a] = m < M;
-        nok[a] = n < N;
-        ra[a] = (mok[a] ? m : 0) * Kp;
-        rb[a] = (nok[a] ? n : 0) * Kp;
-    }
-    const u16x8 zero = (u16x8)0;
-    for (int64_t k0 = 0; k0 < Kp; k0 += 16) {
-        const int64_t kk = k0 + lk * 8;
-        u16x8 arh[2], arl[2], aih[2], ail[2], brh[2], brl[2], bih[2], bil[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const unsigned short* p = PA + ra[a] + kk;
-            arh[a] = mok[a] ? *reinterpret_cast<const u16x8*>(p) : zero;
-            arl[a] = mok[a] ? *reinterpret_cast<const u16x8*>(p + pa) : zero;
-            aih[a] = mok[a] ? *reinterpret_cast<const u16x8*>(p + 2 * pa) : zero;
-            ail[a] = mok[a] ? *reinterpret_cast<const u16x8*>(p + 3 * pa) : zero;
-            const unsigned short* q = PB + rb[a] + kk;
-            brh[a] = nok[a] ? *reinterpret_cast<const u16x8*>(q) : zero;
-            brl[a] = nok[a] ? *reinterpret_cast<const u16x8*>(q + pb) : zero;
-            bih[a] = nok[a] ? *reinterpret_cast<const u16x8*>(q + 2 * pb) : zero;
-            bil[a] = nok[a] ? *reinterpret_cast<const u16x8*>(q + 3 * pb) : zero;
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const bf16x8 xrh = as_bf(arh[a]), xrl = as_bf(arl[a]), xih = as_bf(aih[a]), xil = as_bf(ail[a]);
-            const bf16x8 nih = as_bf(aih[a] ^ (u16x8)0x8000), nil = as_bf(ail[a] ^ (u16x8)0x8000);
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const bf16x8 yrh = as_bf(brh[b]), yrl = as_bf(brl[b]), yih = as_bf(bih[b]), yil = as_bf(bil[b]);
-                f32x16 r = cr[a][b], i = ci[a][b];
-                r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrh, r, 0, 0, 0);
-                r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yrl, r, 0, 0, 0);
-                r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yrh, r, 0, 0, 0);
-                r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yih, r, 0, 0, 0);
-                r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, yil, r, 0, 0, 0);
-                r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nil, yih, r, 0, 0, 0);
-                i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yih, i, 0, 0, 0);
-                i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrh, yil, i, 0, 0, 0);
-                i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xrl, yih, i, 0, 0, 0);
-                i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrh, i, 0, 0, 0);
-                i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, yrl, i, 0, 0, 0);
-                i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xil, yrh, i, 0, 0, 0);
-                cr[a][b] = r;
-                ci[a][b] = i;
-            }
-        }
-    }
-    store_tile_128(cr, ci, row0, col0, M, N, out, ldo, accumulate);
-}
-
 // Persistent streaming kernel.  The complex product is taken as one real
 // product with the real and imaginary parts of the output interleaved,
 // exactly as the output is laid out in memory:
@@ -158,7 +81,7 @@ __device__ __forceinline__ void bf16x3_tile(const unsigned short* __restrict__ P
 // tile's successor are issued before the tile's stores (loads and stores
 // share one completion counter: loads issued after the stores would wait
 // for them).  Per block and half: hi*hi + hi*lo + lo*hi.
-constexpr int BW_ROWS = 256, BW_COLS = 128;
+constexpr int BW_ROWS = (int)kBf16StreamRows, BW_COLS = (int)kBf16StreamCols;
 
 // a value the caller knows to be equal in all lanes, kept in scalar registers
 __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
@@ -222,47 +145,56 @@ __device__ __forceinline__ u16x8 swap_pair(u16x8 v, uint32_t neg) {
     return __builtin_bit_cast(u16x8, o);
 }
 
-// FULL: M a multiple of 256, N of 128, no accumulation, 32 output rows
-// spanning less than 2^31 bytes and each operand's planes less than 2^31
-// elements: no bounds tests anywhere, and every load and store takes a
-// wave-uniform base plus a fixed 32-bit lane offset.
-template <bool FULL>
-__global__ __launch_bounds__(512) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
-                                                             const unsigned short* __restrict__ PB, int64_t N,
-                                                             int64_t Kp, float2* __restrict__ out, int64_t ldo,
-                                                             int accumulate, int64_t tiles_n, int64_t tiles) {
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+// One tile of work: the operand planes and output of one product, and the
+// wave's origin in it (row m0, real column c0).  All fields are
+// wave-uniform.
+struct StreamJob {
+    const unsigned short* PA;
+    const unsigned short* PB;
+    float* out;
+    int64_t M, N, Kp, ldo, m0, c0;
+};
+
+// Persistent loop over `tiles` tiles handed out by loc(t) (t = this
+// workgroup's tiles, blockIdx.x + i gridDim.x).
+// FULL: every product has M a multiple of 256, N of 128, 32 output rows
+// spanning less than 2^31 bytes and operand planes under 2^31 elements, and
+// nothing is accumulated: no bounds tests anywhere, and every load and store
+// takes a wave-uniform base plus a fixed 32-bit lane offset.
+template <bool FULL, typename Loc>
+__device__ __forceinline__ void stream_tiles(const Loc& loc, int64_t tiles, int accumulate) {
     const int lane = threadIdx.x & 63, li = lane & 31, lk = lane >> 5;
-    float* __restrict__ of = reinterpret_cast<float*>(out);
     const uint32_t neg = (li & 1) ? 0u : 0x80008000u;
-    const uint32_t a_off = (uint32_t)li * (uint32_t)Kp + lk * 8;
-    const uint32_t b_off = (uint32_t)(li >> 1) * (uint32_t)Kp + lk * 8 + ((li & 1) ? (uint32_t)(2 * N * Kp) : 0u);
+    auto offsets = [&](const StreamJob& j, uint32_t& ao, uint32_t& bo) {
+        ao = (uint32_t)li * (uint32_t)j.Kp + lk * 8;
+        bo = (uint32_t)(li >> 1) * (uint32_t)j.Kp + lk * 8 + ((li & 1) ? (uint32_t)(2 * j.N * j.Kp) : 0u);
+    };
     int64_t tile = blockIdx.x;
     if (tile >= tiles) return;
-    auto origin = [&](int64_t t, int64_t& r0, int64_t& c0) {
-        const int64_t tm = t / tiles_n, tn = t - tm * tiles_n;
-        r0 = tm * BW_ROWS + w * 32;
-        c0 = tn * (2 * BW_COLS);    // real columns
-    };
-    int64_t m0, c0;
-    origin(tile, m0, c0);
+    StreamJob cur = loc(tile);
+    uint32_t a_off, b_off;
+    offsets(cur, a_off, b_off);
     u16x8 a[4], bh[8], bl[8];
-    load_a2<FULL>(PA, M, Kp, m0, 0, a_off, a);
+    load_a2<FULL>(cur.PA, cur.M, cur.Kp, cur.m0, 0, a_off, a);
 #pragma unroll
-    for (int blk = 0; blk < 8; ++blk) load_b2<FULL>(PB, N, Kp, c0 + blk * 32, 0, b_off, bh[blk], bl[blk]);
+    for (int blk = 0; blk < 8; ++blk)
+        load_b2<FULL>(cur.PB, cur.N, cur.Kp, cur.c0 + blk * 32, 0, b_off, bh[blk], bl[blk]);
     for (;;) {
         const int64_t next = tile + gridDim.x;
-        int64_t nm0 = m0, nc0 = c0;
-        if (next < tiles) origin(next, nm0, nc0);
+        const StreamJob nxt = next < tiles ? loc(next) : cur;
+        uint32_t na_off, nb_off;
+        offsets(nxt, na_off, nb_off);
         f32x16 acc[8];
 #pragma unroll
         for (int blk = 0; blk < 8; ++blk) acc[blk] = (f32x16)0.0f;
-        for (int64_t k0 = 0; k0 < Kp; k0 += 16) {
+        for (int64_t k0 = 0; k0 < cur.Kp; k0 += 16) {
             // operands of the following 16 paths: this tile's, else the next tile's first
-            const bool last = k0 + 16 >= Kp, more = !last || next < tiles;
-            const int64_t lm = last ? nm0 : m0, lc = last ? nc0 : c0, lk0 = last ? 0 : k0 + 16;
+            const bool last = k0 + 16 >= cur.Kp, more = !last || next < tiles;
+            const StreamJob& lj = last ? nxt : cur;
+            const int64_t lk0 = last ? 0 : k0 + 16;
+            const uint32_t la = last ? na_off : a_off, lb = last ? nb_off : b_off;
             const bf16x8 xrh = as_bf(a[0]), xrl = as_bf(a[1]), xih = as_bf(a[2]), xil = as_bf(a[3]);
-            if (more) load_a2<FULL>(PA, M, Kp, lm, lk0, a_off, a);
+            if (more) load_a2<FULL>(lj.PA, lj.M, lj.Kp, lj.m0, lk0, la, a);
 #pragma unroll
             for (int blk = 0; blk < 8; ++blk) {
                 const bf16x8 yh = as_bf(bh[blk]), yl = as_bf(bl[blk]);
@@ -275,42 +207,112 @@ __global__ __launch_bounds__(512) void pathsum_bf16x3_kernel(const unsigned shor
                 c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xih, zl, c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xil, zh, c, 0, 0, 0);
                 acc[blk] = c;
-                if (more) load_b2<FULL>(PB, N, Kp, lc + blk * 32, lk0, b_off, bh[blk], bl[blk]);
+                if (more) load_b2<FULL>(lj.PB, lj.N, lj.Kp, lj.c0 + blk * 32, lk0, lb, bh[blk], bl[blk]);
             }
         }
         // accumulator r of block blk: row m0 + (r/4)*8 + (lane/32)*4 + r%4,
         // real column c0 + 32 blk + lane%32
         if (FULL) {
-            const int64_t ldf = 2 * ldo;
-            const int64_t wofs = uniform_i64(m0 * ldf + c0);
+            const int64_t ldf = 2 * cur.ldo;
+            const int64_t wofs = uniform_i64(cur.m0 * ldf + cur.c0);
             const uint32_t voff = (uint32_t)(lk * 4) * (uint32_t)ldf + (uint32_t)li;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t rofs =
                     wofs + (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)((r >> 2) * 8 + (r & 3)) * (uint32_t)ldf);
-                float* __restrict__ pl = of + rofs + voff;
+                float* __restrict__ pl = cur.out + rofs + voff;
 #pragma unroll
                 for (int blk = 0; blk < 8; ++blk) pl[blk * 32] = acc[blk][r];
             }
         } else {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + (r >> 2) * 8 + lk * 4 + (r & 3);
-                if (row >= M) continue;
+                const int64_t row = cur.m0 + (r >> 2) * 8 + lk * 4 + (r & 3);
+                if (row >= cur.M) continue;
 #pragma unroll
                 for (int blk = 0; blk < 8; ++blk) {
-                    const int64_t col = c0 + blk * 32 + li;
-                    if ((col >> 1) >= N) continue;
-                    float* o = of + row * 2 * ldo + col;
+                    const int64_t col = cur.c0 + blk * 32 + li;
+                    if ((col >> 1) >= cur.N) continue;
+                    float* o = cur.out + row * 2 * cur.ldo + col;
                     *o = accumulate ? *o + acc[blk][r] : acc[blk][r];
                 }
             }
         }
         if (next >= tiles) break;
         tile = next;
-        m0 = nm0;
-        c0 = nc0;
+        cur = nxt;
+        a_off = na_off;
+        b_off = nb_off;
     }
+}
+
+// one product: tiles in row-major order
+struct SingleLoc {
+    const unsigned short* PA;
+    const unsigned short* PB;
+    float* out;
+    int64_t M, N, Kp, ldo, tiles_n;
+    int w;
+    __device__ __forceinline__ StreamJob operator()(int64_t t) const {
+        const int64_t tm = t / tiles_n, tn = t - tm * tiles_n;
+        return {PA, PB, out, M, N, Kp, ldo, tm * BW_ROWS + w * 32, tn * (2 * BW_COLS)};
+    }
+};
+
+template <bool FULL>
+__global__ __launch_bounds__(512) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
+                                                             const unsigned short* __restrict__ PB, int64_t N,
+                                                             int64_t Kp, float2* __restrict__ out, int64_t ldo,
+                                                             int accumulate, int64_t tiles_n, int64_t tiles) {
+    const SingleLoc loc{PA, PB, reinterpret_cast<float*>(out), M, N, Kp, ldo, tiles_n,
+                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)};
+    stream_tiles<FULL>(loc, tiles, accumulate);
+}
+
+// several products (a batch of circuits): a sorted descriptor table read as
+// uniform data, tiles numbered consecutively over the products
+#if defined(__HIP_DEVICE_COMPILE__)
+using cdesc = const __attribute__((address_space(4))) GemmDesc*;
+#else
+using cdesc = const GemmDesc*;
+#endif
+
+struct BatchLoc {
+    cdesc d;
+    int n;
+    unsigned char* base;
+    int w;
+    __device__ __forceinline__ StreamJob operator()(int64_t t) const {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d[mid].tile_start <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t local = t - d[lo].tile_start, tiles_n = d[lo].tiles_n;
+        const int64_t tm = local / tiles_n, tn = local - tm * tiles_n;
+        return {reinterpret_cast<const unsigned short*>(base + d[lo].a_off),
+                reinterpret_cast<const unsigned short*>(base + d[lo].b_off),
+                reinterpret_cast<float*>(d[lo].out),
+                d[lo].M,
+                d[lo].N,
+                d[lo].K,
+                d[lo].ldo,
+                tm * BW_ROWS + w * 32,
+                tn * (2 * BW_COLS)};
+    }
+};
+
+template <bool FULL>
+__global__ __launch_bounds__(512) void pathsum_bf16x3_batch(const GemmDesc* __restrict__ d, int n,
+                                                            unsigned char* base, int64_t tiles) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const cdesc cd = (cdesc)d;
+#else
+    const cdesc cd = d;
+#endif
+    const BatchLoc loc{cd, n, base, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)};
+    stream_tiles<FULL>(loc, tiles, 0);
 }
 
 __global__ __launch_bounds__(256) void split_batch(const SplitDesc* __restrict__ d, int n, unsigned char* base) {
@@ -355,25 +357,6 @@ __global__ __launch_bounds__(256) void split_batch(const SplitDesc* __restrict__
     *reinterpret_cast<u16x8*>(planes + 3 * plane + r * s.Kp + k0) = il;
 }
 
-// Persistent over the union of all circuits' output tiles.
-__global__ __launch_bounds__(256) void pathsum_bf16x3_batch(const GemmDesc* __restrict__ d, int n,
-                                                            unsigned char* base, int64_t tiles) {
-    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (d[mid].tile_start <= tile) lo = mid;
-            else hi = mid - 1;
-        }
-        const GemmDesc& g = d[lo];
-        const int64_t local = tile - g.tile_start;
-        const int64_t tm = local / g.tiles_n, tn = local - tm * g.tiles_n;
-        bf16x3_tile(reinterpret_cast<const unsigned short*>(base + g.a_off), g.M,
-                    reinterpret_cast<const unsigned short*>(base + g.b_off), g.N, g.K, (float2*)g.out, g.ldo, 0,
-                    tm * BF_TILE, tn * BF_TILE);
-    }
-}
-
 }  // namespace
 
 hsf_status launch_split_batch(const void* descs, int n, uint32_t total_blocks, unsigned char* base, hipStream_t st) {
@@ -381,9 +364,16 @@ hsf_status launch_split_batch(const void* descs, int n, uint32_t total_blocks, u
     return hip_check(hipGetLastError(), "split_batch launch");
 }
 
-hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st) {
-    const int grid = persistent_grid((const void*)pathsum_bf16x3_batch, 256, 0, tiles);
-    hipLaunchKernelGGL(pathsum_bf16x3_batch, dim3(grid), dim3(256), 0, st, (const GemmDesc*)descs, n, base, tiles);
+hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, bool full, unsigned char* base,
+                               hipStream_t st) {
+    const void* kern = full ? (const void*)pathsum_bf16x3_batch<true> : (const void*)pathsum_bf16x3_batch<false>;
+    const int grid = persistent_grid(kern, 512, 0, tiles);
+    if (full)
+        hipLaunchKernelGGL(pathsum_bf16x3_batch<true>, dim3(grid), dim3(512), 0, st, (const GemmDesc*)descs, n, base,
+                           tiles);
+    else
+        hipLaunchKernelGGL(pathsum_bf16x3_batch<false>, dim3(grid), dim3(512), 0, st, (const GemmDesc*)descs, n, base,
+                           tiles);
     return hip_check(hipGetLastError(), "pathsum_bf16x3_batch launch");
 }
 
@@ -402,8 +392,7 @@ hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_
         if (s != HSF_OK) return s;
     }
     const int64_t tn = (N + BW_COLS - 1) / BW_COLS, tiles = tn * ((M + BW_ROWS - 1) / BW_ROWS);
-    const bool full = !accumulate && M % BW_ROWS == 0 && N % BW_COLS == 0 && ldo <= (int64_t)(INT32_MAX / 8 / 32) &&
-                      4 * std::max(M, N) * Kp <= (int64_t)INT32_MAX;
+    const bool full = bf16x3_stream_full(M, N, Kp, ldo, accumulate);
     const void* kern = full ? (const void*)pathsum_bf16x3_kernel<true> : (const void*)pathsum_bf16x3_kernel<false>;
     const int grid = persistent_grid(kern, 512, 0, tiles);
     if (full)

@@ -34,7 +34,18 @@ hsf_status launch_sweep_batch(int kg, bool s1, const void* segs, int nseg, uint3
                               size_t shmem, unsigned char* base, hipStream_t stream);
 void batch_sweep_prepare();
 hsf_status launch_split_batch(const void* descs, int n, uint32_t total_blocks, unsigned char* base, hipStream_t st);
-hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);
+// full: every product qualifies for the bounds-free streaming kernel (see
+// bf16x3_stream_full)
+hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, bool full, unsigned char* base,
+                               hipStream_t st);
+// Tile shape of the streaming split-BF16 path sum (rows x complex columns)
+// and whether a product of M x N outputs over Kp padded paths, leading
+// dimension ldo, takes its bounds-free form.
+constexpr int64_t kBf16StreamRows = 256, kBf16StreamCols = 128;
+inline bool bf16x3_stream_full(int64_t M, int64_t N, int64_t Kp, int64_t ldo, int accumulate) {
+    return !accumulate && M % kBf16StreamRows == 0 && N % kBf16StreamCols == 0 && ldo <= (int64_t)(INT32_MAX / 8 / 32) &&
+           4 * (M > N ? M : N) * Kp <= (int64_t)INT32_MAX;
+}
 hsf_status launch_f32_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);
 hsf_status launch_f32_lds_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);
 hsf_status launch_bf16x3_lds_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st);

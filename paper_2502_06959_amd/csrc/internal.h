@@ -196,7 +196,7 @@ struct GemmDesc {
     void* out;
     int64_t ldo;
     int64_t tiles_n;
-    int64_t tile_start;      // first 128 x 128 tile of this circuit in the batch
+    int64_t tile_start;      // first output tile of this circuit in the batch (tiles_n per tile row)
 };
 
 struct DeviceSchedule {

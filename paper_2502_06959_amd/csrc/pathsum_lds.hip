@@ -286,7 +286,7 @@ __device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict
                 }
                 // term-major order over the 2 x 2 blocks: consecutive MFMAs
                 // write different accumulators; each accumulator sees its
-                // six terms in the order of bf16x3_tile
+                // six terms in the fixed order listed below
                 bf16x8 xs[2][6], ys[2][6];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
