@@ -19,6 +19,10 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, 
              # packed FP32 instructions stay off (see the design notes)
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-pthread", "-Wno-unused-command-line-argument"]
+# Per-file additions.  The sweep kernels branch on uniform plan-record fields
+# inside their op loops; by default LLVM structurizes uniform regions too,
+# which inserts register copies of the amplitude array at every merge.
+FILE_FLAGS = {"sweep.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
 CXX_FLAGS = ["-O3", "-std=c++17", "-pthread", "-fPIC", "-I", INC, "-I", SRC, "-D__HIP_PLATFORM_AMD__",
              "-I", "/opt/rocm/include", "-Wall", "-Wno-unused-result"]
 
@@ -43,7 +47,7 @@ def build(jobs=None, verbose=False):
     tasks = []
     for f in hip:
         obj = os.path.join(OBJ, f + ".o")
-        tasks.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(SRC, f), "-o", obj], obj))
+        tasks.append((["hipcc", *HIP_FLAGS, *FILE_FLAGS.get(f, []), "-c", os.path.join(SRC, f), "-o", obj], obj))
     for f in cpp:
         obj = os.path.join(OBJ, f + ".o")
         tasks.append((["g++", *CXX_FLAGS, "-c", os.path.join(SRC, f), "-o", obj], obj))
