@@ -186,9 +186,15 @@ hsf_status hsf_block_factors(hsf_plan_t plan, int32_t k, double* sigma, double* 
 /* Digits m_k(p) of path p (K entries).                                       */
 hsf_status hsf_path_digits(hsf_plan_t plan, int64_t p, int32_t* digits);
 /* Gate-program statistics of side 0 = a, 1 = b: ops before fusion, ops after
- * fusion, LDS passes per path chunk, qubits per tile.                          */
+ * fusion, LDS passes per path chunk, qubits per tile, and the shared prefix:
+ * the fused ops before the side's first factor slot (diagonal gates commuted
+ * ahead of diagonal factor pieces), applied once per plan and device to a
+ * single state that every path then starts from (Sec. II-B: they act the
+ * same way on all paths), and the LDS passes that apply them.  Any pointer
+ * may be NULL.                                                                */
 hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical,
-                          int64_t* ops_fused, int32_t* passes, int32_t* tile_qubits);
+                          int64_t* ops_fused, int32_t* passes, int32_t* tile_qubits,
+                          int64_t* ops_shared, int32_t* shared_passes);
 
 /* --------------------------------------------------------------- paths ---- */
 

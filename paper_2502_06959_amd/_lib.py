@@ -58,7 +58,8 @@ SIGNATURES = {
     "hsf_block_hull": (c_int32, [c_void_p, c_int32, P(c_int64)]),
     "hsf_block_factors": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "hsf_path_digits": (c_int32, [c_void_p, c_int64, P(c_int32)]),
-    "hsf_side_stats": (c_int32, [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int32), P(c_int32)]),
+    "hsf_side_stats": (c_int32, [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int32), P(c_int32), P(c_int64),
+                                 P(c_int32)]),
     "hsf_workspace_size": (c_size_t, [c_void_p, c_int32, c_int64, c_int32]),
     "hsf_run_paths": (c_int32, [c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                 c_size_t, c_void_p]),

@@ -135,7 +135,7 @@ hsf_status hsf_path_digits(hsf_plan_t plan, int64_t path, int32_t* digits) {
 }
 
 hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical, int64_t* ops_fused,
-                          int32_t* passes, int32_t* tile_qubits) {
+                          int32_t* passes, int32_t* tile_qubits, int64_t* ops_shared, int32_t* shared_passes) {
     if (!plan) return fail(HSF_E_ARG, "null plan");
     if (side != 0 && side != 1) return fail(HSF_E_ARG, "side must be 0 (a) or 1 (b)");
     const Plan* p = P_(plan);
@@ -143,8 +143,10 @@ hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical, i
     const size_t i = std::min<size_t>((size_t)pick_schedule(*p, p->P), s.sched.size() - 1);
     if (ops_logical) *ops_logical = s.ops_logical;
     if (ops_fused) *ops_fused = (int64_t)s.ops.size();
-    if (passes) *passes = (int32_t)s.sched[i].passes.size();
+    if (passes) *passes = (int32_t)(s.sched[i].passes.size() - (size_t)s.sched[i].n_prefix_passes);
     if (tile_qubits) *tile_qubits = s.sched[i].tile_bits;
+    if (ops_shared) *ops_shared = s.n_prefix;
+    if (shared_passes) *shared_passes = s.sched[i].n_prefix_passes;
     return HSF_OK;
 }
 

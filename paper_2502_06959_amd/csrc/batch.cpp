@@ -105,15 +105,21 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
     b.round_emax.clear();
     size_t rounds = 0;
     std::vector<int> si(n);
+    // a side with a shared prefix state starts after its prefix passes
+    auto first_pass = [&](int i, int s) -> size_t {
+        const auto& v = b.plans[i]->side[s].sched;
+        const size_t idx = std::min<size_t>(si[i], v.size() - 1);
+        return dc[i]->side[s][idx].prefix ? (size_t)v[idx].n_prefix_passes : 0;
+    };
     for (int i = 0; i < n; ++i) {
         si[i] = sched_index(b, *b.plans[i]);
         for (int s = 0; s < 2; ++s) {
             const auto& v = b.plans[i]->side[s].sched;
-            rounds = std::max(rounds, v[std::min<size_t>(si[i], v.size() - 1)].passes.size());
+            rounds = std::max(rounds, v[std::min<size_t>(si[i], v.size() - 1)].passes.size() - first_pass(i, s));
         }
     }
     // pass k of every (circuit, side), split by group width: one launch each
-    for (size_t k = 0; k < rounds; ++k)
+    for (size_t j = 0; j < rounds; ++j)
         for (int kg = 3; kg <= 4; ++kg) {
             const int first = (int)segs.size();
             uint32_t start = 0, emax = 1;
@@ -124,6 +130,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
                     const auto& v = p.side[s].sched;
                     const size_t idx = std::min<size_t>(si[i], v.size() - 1);
                     const Schedule& sc = v[idx];
+                    const size_t f = first_pass(i, s), k = f + j;
                     if (k >= sc.passes.size() || group_bits(sc.passes[k].n_local) != kg) continue;
                     const DeviceSchedule& ds = dc[i]->side[s][idx];
                     BatchSeg g{};
@@ -135,6 +142,7 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
                     g.pool = ds.pool;
                     g.n_tiles = 1u << sc.passes[k].n_nonlocal;
                     g.block_start = start;
+                    g.shared = (j == 0 && f > 0) ? ds.prefix : nullptr;
                     start += (uint32_t)(p.P * g.n_tiles);
                     emax = std::max(emax, 1u << sc.passes[k].n_local);
                     s1 |= sc.passes[k].has_slot1;

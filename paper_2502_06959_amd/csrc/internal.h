@@ -149,11 +149,16 @@ struct Pass {
     int32_t n_nonlocal = 0;
     int32_t nonlocal_q[kMaxTileBits] = {};
     int32_t has_slot1 = 0;             // some group applies a one-qubit factor piece (SUB_SLOT1)
+    int32_t prefix = 0;                // applies ops of the path-independent prefix only
 };
 
 // LDS pass schedule of one side for one tile size.
 struct Schedule {
     int tile_bits = 0;
+    // passes [0, n_prefix_passes) apply the side's path-independent prefix
+    // (every op before the first factor op); the pass after them reads the
+    // state they leave, which is the same for every path
+    int n_prefix_passes = 0;
     std::vector<Pass> passes;
     std::vector<DevOp> devops;
     std::vector<SubOp> subs;
@@ -164,6 +169,7 @@ struct SideProgram {
     int nq = 0;
     std::vector<SideOp> raw;          // before fusion (one op per gate or slot)
     std::vector<SideOp> ops;          // after fusion
+    int n_prefix = 0;                 // leading ops of `ops` without factor slots
     int64_t ops_logical = 0;
     std::vector<Schedule> sched;      // one per candidate tile size, largest first
 };
@@ -178,6 +184,7 @@ struct BatchSeg {
     const void* pool;
     uint32_t n_tiles;
     uint32_t block_start;    // first workgroup of the segment
+    const void* shared;      // non-null: the pass reads this state (the shared prefix) instead of the rows
 };
 
 // Batched path sum: one circuit's operands and output (device tables).
@@ -204,6 +211,7 @@ struct DeviceSchedule {
     void* ops = nullptr;              // DevOp[]
     void* subs = nullptr;             // SubOp[]
     void* pool = nullptr;             // float2[] or double2[]
+    void* prefix = nullptr;           // the side's state after the prefix passes (2^nq amplitudes), or null
 };
 
 struct DeviceCopy {
@@ -260,6 +268,8 @@ bool gate_generator(int kind, int nq, std::vector<cd>& d);
 
 // Side-program fusion and pass scheduling (plan.cpp).
 void fuse_side(Plan& p, int side);
+// Commutes diagonal gates ahead of diagonal factor pieces and sets n_prefix.
+void order_prefix(SideProgram& sp);
 Schedule schedule_side(const Plan& p, int side, int tile_bits);
 // Index of the schedule used for a launch over n_paths paths.
 int pick_schedule(const Plan& p, int64_t n_paths);

@@ -507,6 +507,7 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
         p->side[s].ops_logical = (int64_t)p->side[s].ops.size();
         p->side[s].raw = p->side[s].ops;
         fuse_side(*p, s);
+        order_prefix(p->side[s]);
         const int nq = std::max(p->side[s].nq, 1);
         const int tmax = p->tile_req > 0 ? p->tile_req : max_tile_bits(p->dtype);
         // candidate tile sizes, largest first (a requested size is the only one)
@@ -626,6 +627,51 @@ void fuse_ops(std::vector<SideOp>& ops, int nq) {
 void fuse_side(Plan& p, int s) {
     if (p.fuse) fuse_ops(p.side[s].ops, std::max(p.side[s].nq, 1));
 }
+
+// Ops that act the same way on all paths can run once, on one shared state,
+// before every path's factor slots: an op joins that prefix when it is not a
+// factor slot and commutes with every op left behind it -- they act on
+// disjoint qubits, or both are diagonal.  Prefix and rest each keep their
+// order.  In a brickwork this is every gate outside the forward light cone of
+// the first block; for the cascades of Sec. V the cost layer outside the
+// blocks.
+void order_prefix(SideProgram& sp) {
+    auto diagonal = [](const SideOp& o) {
+        if (o.kind == SideOp::DIAG) return true;
+        if (o.kind == SideOp::DENSE) {
+            const int d = 1 << o.k;
+            for (int i = 0; i < d; ++i)
+                for (int j = 0; j < d; ++j)
+                    if (i != j && o.m[(size_t)i * d + j] != cd(0.0)) return false;
+            return true;
+        }
+        const int d = 1 << o.k;
+        for (int r = 0; r < o.rank; ++r)
+            for (int i = 0; i < d; ++i)
+                for (int j = 0; j < d; ++j)
+                    if (i != j && o.m[(size_t)r * d * d + (size_t)i * d + j] != cd(0.0)) return false;
+        return true;
+    };
+    const int nq = std::max(sp.nq, 1);
+    std::vector<char> dense_left(nq, 0), diag_left(nq, 0);   // qubits of the ops left behind
+    std::vector<SideOp> pre, rest;
+    for (SideOp& o : sp.ops) {
+        const bool od = diagonal(o);
+        bool hoist = o.kind != SideOp::SLOT;
+        for (int j = 0; j < o.k && hoist; ++j)
+            if (dense_left[o.q[j]] || (!od && diag_left[o.q[j]])) hoist = false;
+        if (hoist) {
+            pre.push_back(std::move(o));
+        } else {
+            for (int j = 0; j < o.k; ++j) (od ? diag_left : dense_left)[o.q[j]] = 1;
+            rest.push_back(std::move(o));
+        }
+    }
+    sp.n_prefix = (int)pre.size();
+    sp.ops = std::move(pre);
+    sp.ops.insert(sp.ops.end(), std::make_move_iterator(rest.begin()), std::make_move_iterator(rest.end()));
+}
+
 
 namespace {
 
@@ -787,82 +833,94 @@ Schedule schedule_side(const Plan& p, int s, int L) {
             piece_blocks.insert(o.block);
         }
     const bool group_slots = pieces > (int)piece_blocks.size();
-    std::vector<char> done(nops, 0);
-    int remaining = nops;
     const int low = L >= nq ? L : std::max(0, std::min(5, L - kMaxOpQubits));
-    bool first = true;
-    while (first || remaining > 0) {
-        Pass ps;
-        ps.init_zero = first ? 1 : 0;
-        std::vector<char> local(std::max(nq, 1), 0);
-        int nloc = 0;
-        if (L >= nq) {
-            for (int q = 0; q < nq; ++q) local[q] = 1;
-            nloc = nq;
-        } else {
-            for (int q = 0; q < low; ++q) local[q] = 1, ++nloc;
-            // the qubits of the earliest pending non-diagonal ops
-            for (int i = 0; i < nops && nloc < L; ++i) {
+    // ops [lo, hi) into passes; the first starts from |0...0> when lo == 0
+    // and otherwise reads the state the previous passes left
+    auto schedule_range = [&](int lo, int hi, bool prefix) {
+        std::vector<char> done(nops, 1);
+        for (int i = lo; i < hi; ++i) done[i] = 0;
+        int remaining = hi - lo;
+        bool first = true;
+        while (first || remaining > 0) {
+            Pass ps;
+            ps.init_zero = (first && lo == 0) ? 1 : 0;
+            ps.prefix = prefix ? 1 : 0;
+            std::vector<char> local(std::max(nq, 1), 0);
+            int nloc = 0;
+            if (L >= nq) {
+                for (int q = 0; q < nq; ++q) local[q] = 1;
+                nloc = nq;
+            } else {
+                for (int q = 0; q < low; ++q) local[q] = 1, ++nloc;
+                // the qubits of the earliest pending non-diagonal ops
+                for (int i = 0; i < nops && nloc < L; ++i) {
+                    if (done[i]) continue;
+                    const SideOp& o = sp.ops[i];
+                    if (o.kind != SideOp::DIAG) {
+                        int need = 0;
+                        for (int j = 0; j < o.k; ++j) need += !local[o.q[j]];
+                        if (nloc + need <= L)
+                            for (int j = 0; j < o.k; ++j)
+                                if (!local[o.q[j]]) local[o.q[j]] = 1, ++nloc;
+                    }
+                }
+                for (int q = nq - 1; q >= 0 && nloc < L; --q)
+                    if (!local[q]) local[q] = 1, ++nloc;
+            }
+            int t = 0, u = 0;
+            for (int q = 0; q < nq; ++q) {
+                if (local[q]) ps.local_q[t++] = q;
+                else ps.nonlocal_q[u++] = q;
+            }
+            ps.n_local = std::max(t, 1);
+            ps.n_nonlocal = u;
+            std::vector<int> ids;
+            std::vector<char> blocked(std::max(nq, 1), 0);
+            for (int i = 0; i < nops; ++i) {
                 if (done[i]) continue;
                 const SideOp& o = sp.ops[i];
-                if (o.kind != SideOp::DIAG) {
-                    int need = 0;
-                    for (int j = 0; j < o.k; ++j) need += !local[o.q[j]];
-                    if (nloc + need <= L)
-                        for (int j = 0; j < o.k; ++j)
-                            if (!local[o.q[j]]) local[o.q[j]] = 1, ++nloc;
+                bool blk = false, fits = true;
+                for (int j = 0; j < o.k; ++j) {
+                    blk |= (bool)blocked[o.q[j]];
+                    fits &= (bool)local[o.q[j]];
+                }
+                if (!blk && (fits || o.kind == SideOp::DIAG)) {
+                    done[i] = 1;
+                    --remaining;
+                    ids.push_back(i);
+                } else {
+                    for (int j = 0; j < o.k; ++j) blocked[o.q[j]] = 1;
                 }
             }
-            for (int q = nq - 1; q >= 0 && nloc < L; --q)
-                if (!local[q]) local[q] = 1, ++nloc;
-        }
-        int t = 0, u = 0;
-        for (int q = 0; q < nq; ++q) {
-            if (local[q]) ps.local_q[t++] = q;
-            else ps.nonlocal_q[u++] = q;
-        }
-        ps.n_local = std::max(t, 1);
-        ps.n_nonlocal = u;
-        std::vector<int> ids;
-        std::vector<char> blocked(std::max(nq, 1), 0);
-        for (int i = 0; i < nops; ++i) {
-            if (done[i]) continue;
-            const SideOp& o = sp.ops[i];
-            bool blk = false, fits = true;
-            for (int j = 0; j < o.k; ++j) {
-                blk |= (bool)blocked[o.q[j]];
-                fits &= (bool)local[o.q[j]];
+            ps.op_begin = (int32_t)sc.devops.size();
+            emit_pass(sp, sc, ps, ids, group_slots);
+            ps.op_end = (int32_t)sc.devops.size();
+            // barriers: only between ops that are not both wave-private (a wave
+            // holds 64 lanes x 2^k amplitudes of a group, tile bits 0 .. 5+k)
+            auto wave_private = [&](const DevOp& d) {
+                if (d.type != DOP_GROUP) return false;
+                for (int g = 0; g < d.k; ++g)
+                    if (d.bit[g] >= 6 + d.k) return false;
+                return true;
+            };
+            for (int32_t i = ps.op_begin; i < ps.op_end; ++i) {
+                const bool last = i + 1 == ps.op_end;
+                sc.devops[i].barrier =
+                    (last || !wave_private(sc.devops[i]) || !wave_private(sc.devops[i + 1])) ? 1 : 0;
+                const DevOp& d = sc.devops[i];
+                if (d.type == DOP_GROUP)
+                    for (int j = d.mat; j < d.mat + d.rank; ++j) ps.has_slot1 |= sc.subs[j].type == SUB_SLOT1;
             }
-            if (!blk && (fits || o.kind == SideOp::DIAG)) {
-                done[i] = 1;
-                --remaining;
-                ids.push_back(i);
-            } else {
-                for (int j = 0; j < o.k; ++j) blocked[o.q[j]] = 1;
-            }
+            sc.passes.push_back(ps);
+            first = false;
+            if (sc.passes.size() > (size_t)4 * nops + 8) break;  // every pass applies an op; never reached
         }
-        ps.op_begin = (int32_t)sc.devops.size();
-        emit_pass(sp, sc, ps, ids, group_slots);
-        ps.op_end = (int32_t)sc.devops.size();
-        // barriers: only between ops that are not both wave-private (a wave
-        // holds 64 lanes x 2^k amplitudes of a group, tile bits 0 .. 5+k)
-        auto wave_private = [&](const DevOp& d) {
-            if (d.type != DOP_GROUP) return false;
-            for (int g = 0; g < d.k; ++g)
-                if (d.bit[g] >= 6 + d.k) return false;
-            return true;
-        };
-        for (int32_t i = ps.op_begin; i < ps.op_end; ++i) {
-            const bool last = i + 1 == ps.op_end;
-            sc.devops[i].barrier = (last || !wave_private(sc.devops[i]) || !wave_private(sc.devops[i + 1])) ? 1 : 0;
-            const DevOp& d = sc.devops[i];
-            if (d.type == DOP_GROUP)
-                for (int j = d.mat; j < d.mat + d.rank; ++j) ps.has_slot1 |= sc.subs[j].type == SUB_SLOT1;
-        }
-        sc.passes.push_back(ps);
-        first = false;
-        if (sc.passes.size() > (size_t)4 * nops + 8) break;  // every pass applies an op; never reached
-    }
+    };
+    // the shared prefix, then the per-path rest (at least one pass: it also
+    // copies the prefix state into each path's row)
+    if (sp.n_prefix > 0) schedule_range(0, sp.n_prefix, true);
+    sc.n_prefix_passes = (int)sc.passes.size();
+    schedule_range(sp.n_prefix, nops, false);
     return sc;
 }
 

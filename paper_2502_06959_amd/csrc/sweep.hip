@@ -85,6 +85,7 @@ struct SideArgs {
     const void* pool;
     uint32_t n_tiles;
     uint32_t n_blocks;       // paths x tiles
+    const void* shared;      // non-null: the pass reads this state (the shared prefix) instead of the path's row
 };
 
 // LDS position of tile element e: the low four index bits are XORed with the
@@ -280,8 +281,8 @@ template <> struct Threads<double> { static constexpr int max = 512; };
 template <typename T, int KG, bool S1>
 __device__ __forceinline__ void sweep_tile(ctab<Pass> ps, ctab<DevOp> ops, ctab<DSub<T>> subs,
                                            const typename Cx<T>::v* __restrict__ pool,
-                                           typename Cx<T>::v* st, uint32_t t, int64_t path,
-                                           typename Cx<T>::v* tile) {
+                                           typename Cx<T>::v* st, const typename Cx<T>::v* src, uint32_t t,
+                                           int64_t path, typename Cx<T>::v* tile) {
     using V = typename Cx<T>::v;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int L = ps->n_local;
@@ -307,7 +308,7 @@ __device__ __forceinline__ void sweep_tile(ctab<Pass> ps, ctab<DevOp> ops, ctab<
             tile[swz(e)] = z;
         }
     } else {
-        for (uint32_t e = tid; e < E; e += nt) tile[swz(e)] = st[gidx(e)];
+        for (uint32_t e = tid; e < E; e += nt) tile[swz(e)] = src[gidx(e)];
     }
     __syncthreads();
 
@@ -353,10 +354,11 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideA
     const uint32_t t = blk - pl * n_tiles;
     const int64_t ld = sd ? s1.ld : s0.ld;
     V* st = reinterpret_cast<V*>(sd ? s1.psi : s0.psi) + (int64_t)pl * ld;
+    const V* shared = reinterpret_cast<const V*>(sd ? s1.shared : s0.shared);
     sweep_tile<T, KG, S1>(as_table(sd ? s1.pass : s0.pass), as_table(sd ? s1.ops : s0.ops),
                       as_table(reinterpret_cast<const DSub<T>*>(sd ? s1.subs : s0.subs)),
-                      reinterpret_cast<const V*>(sd ? s1.pool : s0.pool), st, t, p_begin + pl,
-                      reinterpret_cast<V*>(smem_raw));
+                      reinterpret_cast<const V*>(sd ? s1.pool : s0.pool), st, shared ? shared : st, t,
+                      p_begin + pl, reinterpret_cast<V*>(smem_raw));
 }
 
 // Many circuits' pass k in one launch: segment i covers workgroups
@@ -379,8 +381,9 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_batch(const BatchSeg* _
     const uint32_t pl = blk / sg.n_tiles;
     const uint32_t t = blk - pl * sg.n_tiles;
     V* st = reinterpret_cast<V*>(base + sg.psi_off) + (int64_t)pl * sg.ld;
+    const V* src = sg.shared ? reinterpret_cast<const V*>(sg.shared) : st;
     sweep_tile<T, KG, S1>(as_table(sg.pass), as_table(sg.ops), as_table(reinterpret_cast<const DSub<T>*>(sg.subs)),
-                      reinterpret_cast<const V*>(sg.pool), st, t, pl, reinterpret_cast<V*>(smem_raw));
+                      reinterpret_cast<const V*>(sg.pool), st, src, t, pl, reinterpret_cast<V*>(smem_raw));
 }
 
 std::mutex g_dev_mutex;
@@ -439,6 +442,49 @@ bool g_attr_done[2] = {false, false};
 
 int max_tile_bits(int dtype) { return dtype == HSF_C128 ? 13 : 14; }
 
+namespace {
+hsf_status launch_pass(bool dbl, int kg, bool s1, uint32_t total, int threads, size_t shmem, hipStream_t stream,
+                       const SideArgs& a, const SideArgs& b, int64_t p0);
+}  // namespace
+
+// Runs a schedule's prefix passes for a single path into a new buffer (the
+// side's state after its path-independent ops); every path's first
+// remaining pass then reads that buffer.
+hsf_status compute_prefix(const Plan& p, DeviceSchedule& ds, const Schedule& sc, int nq) {
+    if (sc.n_prefix_passes == 0) return HSF_OK;
+    const bool dbl = p.dtype == HSF_C128;
+    const size_t esz = dbl ? 16 : 8;
+    hsf_status s = hip_check(hipMalloc(&ds.prefix, esz << std::max(nq, 0)), "hipMalloc(prefix state)");
+    if (s != HSF_OK) {
+        ds.prefix = nullptr;
+        return s;
+    }
+    for (int k = 0; k < sc.n_prefix_passes; ++k) {
+        const Pass& ps = sc.passes[k];
+        SideArgs a, b;
+        std::memset(&a, 0, sizeof(a));
+        std::memset(&b, 0, sizeof(b));
+        a.pass = reinterpret_cast<const Pass*>(ds.passes) + k;
+        a.psi = ds.prefix;
+        a.ld = int64_t(1) << std::max(nq, 0);
+        a.ops = (const DevOp*)ds.ops;
+        a.subs = ds.subs;
+        a.pool = ds.pool;
+        a.n_tiles = 1u << ps.n_nonlocal;
+        a.n_blocks = a.n_tiles;
+        const uint32_t E = 1u << ps.n_local;
+        const int kg = group_bits(ps.n_local);
+        const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, E >> kg));
+        s = launch_pass(dbl, kg, ps.has_slot1 != 0, a.n_blocks, threads, ((size_t)E + 256) * esz, nullptr, a, b, 0);
+        if (s != HSF_OK) return s;
+    }
+    return HSF_OK;
+}
+
+hsf_status compute_prefix(Plan& p, DeviceCopy& d, int side, int q) {
+    return compute_prefix(p, d.side[side][q], p.side[side].sched[q], p.side[side].nq);
+}
+
 hsf_status ensure_device(Plan& p, DeviceCopy** out) {
     int dev = 0;
     hsf_status s = hip_check(hipGetDevice(&dev), "hipGetDevice");
@@ -478,6 +524,21 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
         }
         g_attr_done[di] = true;
     }
+    // the shared prefix states, once per schedule (passes without factor
+    // slots, one path), before any caller's work
+    for (int side = 0; side < 2; ++side)
+        for (size_t q = 0; q < p.side[side].sched.size(); ++q) {
+            s = compute_prefix(p, d, side, (int)q);
+            if (s != HSF_OK) {
+                release_device(p);
+                return s;
+            }
+        }
+    s = hip_check(hipStreamSynchronize(nullptr), "prefix states");
+    if (s != HSF_OK) {
+        release_device(p);
+        return s;
+    }
     *out = &d;
     return HSF_OK;
 }
@@ -489,7 +550,7 @@ void release_device(Plan& p) {
         (void)hipSetDevice(d.device);
         for (int side = 0; side < 2; ++side)
             for (DeviceSchedule& ds : d.side[side])
-                for (void* q : {ds.passes, ds.ops, ds.subs, ds.pool})
+                for (void* q : {ds.passes, ds.ops, ds.subs, ds.pool, ds.prefix})
                     if (q) (void)hipFree(q);
     }
     (void)hipSetDevice(cur);
@@ -556,22 +617,26 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
     const int64_t ld[2] = {ldA, ldB};
     const Schedule* sc[2];
     int si[2];
-    size_t npass = 0;
+    size_t first[2] = {0, 0}, npass = 0;
     for (int s = 0; s < 2; ++s) {
         si[s] = std::min<int>(pick, (int)p.side[s].sched.size() - 1);
         sc[s] = &p.side[s].sched[si[s]];
-        if (psi[s]) npass = std::max(npass, sc[s]->passes.size());
+        // a side with a shared prefix state starts after its prefix passes
+        if (d.side[s][si[s]].prefix) first[s] = (size_t)sc[s]->n_prefix_passes;
+        if (psi[s]) npass = std::max(npass, sc[s]->passes.size() - first[s]);
     }
     // paths per launch bounded so the grid stays below 2^31 workgroups
     int64_t tiles_max = 1;
     for (int s = 0; s < 2; ++s)
-        if (psi[s]) tiles_max = std::max<int64_t>(tiles_max, int64_t(1) << sc[s]->passes[0].n_nonlocal);
+        if (psi[s]) tiles_max = std::max<int64_t>(tiles_max, int64_t(1) << sc[s]->passes[first[s]].n_nonlocal);
     const int64_t max_paths = std::max<int64_t>(1, (int64_t(1) << 29) / tiles_max);
-    for (size_t k = 0; k < npass; ++k) {
+    for (size_t j = 0; j < npass; ++j) {
         SideArgs a[2];
         std::memset(a, 0, sizeof(a));
         uint32_t emax = 1;
+        size_t kk[2] = {first[0] + j, first[1] + j};
         for (int s = 0; s < 2; ++s) {
+            const size_t k = kk[s];
             if (!psi[s] || k >= sc[s]->passes.size()) continue;
             const Pass& ps = sc[s]->passes[k];
             const DeviceSchedule& ds = d.side[s][si[s]];
@@ -581,15 +646,16 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
             a[s].subs = ds.subs;
             a[s].pool = ds.pool;
             a[s].n_tiles = 1u << ps.n_nonlocal;
+            a[s].shared = (j == 0 && first[s] > 0) ? ds.prefix : nullptr;
             emax = std::max(emax, 1u << ps.n_local);
         }
         // group width: every group of a pass uses group_bits(L) bits (L = that side's tile)
         int kg = 4;
         for (int s = 0; s < 2; ++s)
-            if (a[s].pass) kg = std::min(kg, group_bits(sc[s]->passes[k].n_local));
+            if (a[s].pass) kg = std::min(kg, group_bits(sc[s]->passes[kk[s]].n_local));
         bool kg_mixed = false;
         for (int s = 0; s < 2; ++s)
-            if (a[s].pass && group_bits(sc[s]->passes[k].n_local) != kg) kg_mixed = true;
+            if (a[s].pass && group_bits(sc[s]->passes[kk[s]].n_local) != kg) kg_mixed = true;
         const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, emax >> kg));
         const size_t shmem = ((size_t)emax + 256) * esz;
         for (int64_t p0 = 0; p0 < n_paths; p0 += max_paths) {
@@ -611,12 +677,12 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
                     c[1 - part].n_blocks = 0;
                     c[1 - part].pass = nullptr;
                     if (!c[part].pass) continue;
-                    kgp = group_bits(sc[part]->passes[k].n_local);
+                    kgp = group_bits(sc[part]->passes[kk[part]].n_local);
                 }
                 const uint32_t tot = c[0].n_blocks + c[1].n_blocks;
                 bool s1 = false;
                 for (int q = 0; q < 2; ++q)
-                    if (c[q].pass && c[q].n_blocks) s1 |= sc[q]->passes[k].has_slot1 != 0;
+                    if (c[q].pass && c[q].n_blocks) s1 |= sc[q]->passes[kk[q]].has_slot1 != 0;
                 hsf_status s = launch_pass(dbl, kgp, s1, tot, threads, shmem, stream, c[0], c[1], p_begin + p0);
                 if (s != HSF_OK) return s;
             }

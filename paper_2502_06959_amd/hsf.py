@@ -205,11 +205,12 @@ class Plan:
         return list(d[:self.K])
 
     def side_stats(self, side):
-        a, b = ctypes.c_int64(), ctypes.c_int64()
-        c, d = ctypes.c_int32(), ctypes.c_int32()
+        a, b, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        c, d, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         L.check(L.lib().hsf_side_stats(ctypes.c_void_p(self.handle), side, ctypes.byref(a), ctypes.byref(b),
-                                       ctypes.byref(c), ctypes.byref(d)))
-        return {"ops_logical": a.value, "ops_fused": b.value, "passes": c.value, "tile_qubits": d.value}
+                                       ctypes.byref(c), ctypes.byref(d), ctypes.byref(e), ctypes.byref(f)))
+        return {"ops_logical": a.value, "ops_fused": b.value, "passes": c.value, "tile_qubits": d.value,
+                "ops_shared": e.value, "shared_passes": f.value}
 
     # ------------------------------------------------------------ device ----
     def alloc_halves(self, n_paths, device="cuda"):

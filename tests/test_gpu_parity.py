@@ -106,7 +106,11 @@ def test_multi_pass_equals_single_pass():
     outs = []
     for tq in (0, 8, 9):
         plan = Plan(c, dtype="c128", tile_qubits=tq)
-        assert (plan.side_stats(0)["passes"] > 1) == (tq > 0)
+        st = plan.side_stats(0)
+        # the shared prefix and the per-path rest are separate pass ranges;
+        # a tile narrower than the side needs more than one pass per range
+        ranges = 1 + (st["shared_passes"] > 0)
+        assert (st["passes"] + st["shared_passes"] > ranges) == (tq > 0)
         A, B = plan.run_paths()
         outs.append((A.cpu().numpy(), B.cpu().numpy()))
     for A, B in outs[1:]:
