@@ -139,3 +139,35 @@ def test_multi_pass_schedule_shapes():
             st = p.side_stats(s)
             assert st["tile_qubits"] == tq
             assert (st["passes"] == 1) == (tq >= 14)
+
+
+def test_shared_prefix_hoists_commuting_ops():
+    """Ops that commute with every factor slot before them (disjoint qubits,
+    or both diagonal) join the prefix every path shares; ops that do not
+    stay per path (Sec. II-B: paths differ only in the factor slots)."""
+    g = cg.gate
+    # cut 1: side b = qubits 0, 1; side a = qubits 2, 3.  The block is the
+    # crossing CZ(1, 2); its factors (product form) are diagonal.
+    gates = [g("CZ", (1, 2)),          # block: factor slots on qubit 2 (a) and 1 (b)
+             g("H", (3,)),             # a: disjoint from the slot -> shared
+             g("RZZ", (2, 3), 0.3),    # a: diagonal, the slot is diagonal -> shared
+             g("H", (2,)),             # a: dense on the slot's qubit -> per path
+             g("H", (3,)),             # a: disjoint from everything left behind -> shared
+             g("H", (0,)),             # b: disjoint from the slot on 1 -> shared
+             g("H", (1,))]             # b: dense on the slot's qubit -> per path
+    p = Plan(cg.circuit("prefix", 4, gates, 1, [[0]]))
+    a, b = p.side_stats(0), p.side_stats(1)
+    # side a: slot, H(3), RZZ, H(2), H(3) (the RZZ keeps the two H(3) apart);
+    # shared: H(3), RZZ, H(3)
+    assert a["ops_shared"] == 3 and a["ops_fused"] == 5
+    assert b["ops_shared"] == 1 and b["ops_fused"] == 3
+    # a dense op on the qubit of a dense factor slot stays per path
+    gates2 = [g("CX", (1, 2)), g("H", (2,)), g("H", (3,))]
+    p2 = Plan(cg.circuit("prefix2", 4, gates2, 1, [[0]]))
+    assert p2.side_stats(0)["ops_shared"] == 1     # H(3) only
+    # every side's shared ops are a part of its fused ops
+    p3 = Plan(cg.ghz(6))
+    for s in (0, 1):
+        st = p3.side_stats(s)
+        assert 0 <= st["ops_shared"] <= st["ops_fused"]
+        assert st["passes"] >= 1
