@@ -186,12 +186,12 @@ hsf_status hsf_block_factors(hsf_plan_t plan, int32_t k, double* sigma, double* 
 /* Digits m_k(p) of path p (K entries).                                       */
 hsf_status hsf_path_digits(hsf_plan_t plan, int64_t p, int32_t* digits);
 /* Gate-program statistics of side 0 = a, 1 = b: ops before fusion, ops after
- * fusion, LDS passes per path chunk, qubits per tile, and the shared prefix:
- * the fused ops before the side's first factor slot (diagonal gates commuted
- * ahead of diagonal factor pieces), applied once per plan and device to a
- * single state that every path then starts from (Sec. II-B: they act the
- * same way on all paths), and the LDS passes that apply them.  Any pointer
- * may be NULL.                                                                */
+ * fusion, LDS passes per path after the shared prefix, qubits per tile, and
+ * the shared prefix itself: the fused ops that are not factor slots and
+ * commute with every factor slot before them (disjoint qubits, or both
+ * diagonal), applied once per plan and device to a single state that every
+ * path then starts from (Sec. II-B: they act the same way on all paths), and
+ * the LDS passes that apply them.  Any pointer may be NULL.                   */
 hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical,
                           int64_t* ops_fused, int32_t* passes, int32_t* tile_qubits,
                           int64_t* ops_shared, int32_t* shared_passes);
@@ -208,7 +208,11 @@ size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t 
  * psiA (ld ldA elements) receives side a's state for path p_begin + j,
  * 2^n_a amplitudes; psiB likewise with 2^n_b.  Either side may be NULL to
  * skip it.  Element type is the plan's dtype (c64 = 2 x float, c128 =
- * 2 x double).  Rows are overwritten; nothing is read.                      */
+ * 2 x double).  Rows are overwritten; nothing is read.  The first call on a
+ * device uploads the plan's tables and simulates each side's shared prefix
+ * once (device memory of 2^n_side amplitudes per side and tile schedule,
+ * owned by the plan, freed by hsf_plan_destroy; this call synchronizes the
+ * device once).                                                             */
 hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* psiA,
                          int64_t ldA, void* psiB, int64_t ldB, void* ws, size_t ws_bytes,
                          hsf_stream_t stream);
