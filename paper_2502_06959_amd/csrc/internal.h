@@ -88,6 +88,7 @@ struct SideOp {
     std::vector<cd> m;       // DENSE: d x d; DIAG: d entries; SLOT: rank x d x d
     int block = -1;          // SLOT: plan block index
     int piece = 0;           // SLOT: which piece of the block's factor on this side
+    bool product = false;    // SLOT: a product-form piece (diagonal for every angle of the block)
     int rank = 1;
     int64_t stride = 1;
     int64_t logical = 1;     // circuit gates represented by this op

@@ -496,6 +496,7 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
                     op.m = pc.m;
                     op.block = k;
                     op.piece = (int)pi;
+                    op.product = b.product;
                     op.rank = b.rank;
                     op.stride = b.stride;
                     p->side[s].ops.push_back(std::move(op));
@@ -628,6 +629,19 @@ void fuse_side(Plan& p, int s) {
     if (p.fuse) fuse_ops(p.side[s].ops, std::max(p.side[s].nq, 1));
 }
 
+// An op that is diagonal.  A factor slot counts only in the product form,
+// which is diagonal for every angle of its block: the backward pass
+// re-factors blocks at shifted angles and reuses this plan's op order.
+bool op_is_diagonal(const SideOp& o) {
+    if (o.kind == SideOp::DIAG) return true;
+    if (o.kind == SideOp::SLOT) return o.product;
+    const int d = 1 << o.k;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            if (i != j && o.m[(size_t)i * d + j] != cd(0.0)) return false;
+    return true;
+}
+
 // Ops that act the same way on all paths can run once, on one shared state,
 // before every path's factor slots: an op joins that prefix when it is not a
 // factor slot and commutes with every op left behind it -- they act on
@@ -636,27 +650,11 @@ void fuse_side(Plan& p, int s) {
 // the first block; for the cascades of Sec. V the cost layer outside the
 // blocks.
 void order_prefix(SideProgram& sp) {
-    auto diagonal = [](const SideOp& o) {
-        if (o.kind == SideOp::DIAG) return true;
-        if (o.kind == SideOp::DENSE) {
-            const int d = 1 << o.k;
-            for (int i = 0; i < d; ++i)
-                for (int j = 0; j < d; ++j)
-                    if (i != j && o.m[(size_t)i * d + j] != cd(0.0)) return false;
-            return true;
-        }
-        const int d = 1 << o.k;
-        for (int r = 0; r < o.rank; ++r)
-            for (int i = 0; i < d; ++i)
-                for (int j = 0; j < d; ++j)
-                    if (i != j && o.m[(size_t)r * d * d + (size_t)i * d + j] != cd(0.0)) return false;
-        return true;
-    };
     const int nq = std::max(sp.nq, 1);
     std::vector<char> dense_left(nq, 0), diag_left(nq, 0);   // qubits of the ops left behind
     std::vector<SideOp> pre, rest;
     for (SideOp& o : sp.ops) {
-        const bool od = diagonal(o);
+        const bool od = op_is_diagonal(o);
         bool hoist = o.kind != SideOp::SLOT;
         for (int j = 0; j < o.k && hoist; ++j)
             if (dense_left[o.q[j]] || (!od && diag_left[o.q[j]])) hoist = false;
@@ -666,6 +664,21 @@ void order_prefix(SideProgram& sp) {
             for (int j = 0; j < o.k; ++j) (od ? diag_left : dense_left)[o.q[j]] = 1;
             rest.push_back(std::move(o));
         }
+    }
+    // within each run of diagonal ops left per path, the one-qubit factor
+    // pieces go last, ordered by qubit, so that the pieces on one qubit meet
+    // in a register group and are multiplied before being applied
+    for (size_t i = 0; i < rest.size();) {
+        size_t j = i;
+        while (j < rest.size() && op_is_diagonal(rest[j])) ++j;
+        if (j > i + 1) {
+            auto piece = [](const SideOp& o) { return o.kind == SideOp::SLOT && o.k == 1; };
+            auto mid = std::stable_partition(rest.begin() + (std::ptrdiff_t)i, rest.begin() + (std::ptrdiff_t)j,
+                                             [&](const SideOp& o) { return !piece(o); });
+            std::stable_sort(mid, rest.begin() + (std::ptrdiff_t)j,
+                             [](const SideOp& x, const SideOp& y) { return x.q[0] < y.q[0]; });
+        }
+        i = j > i ? j : i + 1;
     }
     sp.n_prefix = (int)pre.size();
     sp.ops = std::move(pre);
@@ -721,6 +734,7 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
             if (o.kind == SideOp::SLOT) {
                 so.type = SUB_SLOT1;
                 so.g = pos_in(bits, tbit(o.q[0]));
+                so.qb[0] = op_is_diagonal(o) ? 1 : 0;   // bit 0: diagonal; bit 1: chained (below)
                 so.mat = (int32_t)sc.pool.size();
                 sc.pool.insert(sc.pool.end(), o.m.begin(), o.m.end());
                 so.rank = o.rank;
@@ -776,6 +790,14 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
                 }
             }
             sc.subs.push_back(so);
+        }
+        // a diagonal piece followed by another on the same register bit only
+        // multiplies into the chain; the last of the chain applies it
+        for (int j = d.mat; j + 1 < d.mat + d.rank; ++j) {
+            SubOp& x = sc.subs[j];
+            const SubOp& y = sc.subs[j + 1];
+            if (x.type == SUB_SLOT1 && y.type == SUB_SLOT1 && (x.qb[0] & 1) && (y.qb[0] & 1) && x.g == y.g)
+                x.qb[0] |= 2;
         }
         sc.devops.push_back(d);
         grp.clear();

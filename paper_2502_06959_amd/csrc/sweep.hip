@@ -227,11 +227,24 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
             f01.x = pool_s[e0 + 2]; f01.y = pool_s[e0 + 3];                                              \
             f10.x = pool_s[e0 + 4]; f10.y = pool_s[e0 + 5];                                              \
             f11.x = pool_s[e0 + 6]; f11.y = pool_s[e0 + 7];                                              \
-            switch ((so).g) {                                                                            \
-                case 0: d1g<K, 0>(v, f00, f01, f10, f11); break;                                         \
-                case 1: d1g<K, 1>(v, f00, f01, f10, f11); break;                                         \
-                case 2: d1g<K, 2>(v, f00, f01, f10, f11); break;                                         \
-                default: d1g<K, 3>(v, f00, f01, f10, f11); break;                                        \
+            const int fl = (so).qb[0];                                                                   \
+            if (fl & 2) {                                                                                \
+                /* diagonal piece followed by another on this bit: multiply into the chain */           \
+                ch0 = cmul(f00, ch0);                                                                    \
+                ch1 = cmul(f11, ch1);                                                                    \
+            } else {                                                                                     \
+                if (fl & 1) {                                                                            \
+                    /* last diagonal piece of a chain: apply the product */                             \
+                    f00 = cmul(f00, ch0);                                                                \
+                    f11 = cmul(f11, ch1);                                                                \
+                    ch0.x = T(1); ch0.y = T(0); ch1 = ch0;                                               \
+                }                                                                                        \
+                switch ((so).g) {                                                                        \
+                    case 0: d1g<K, 0>(v, f00, f01, f10, f11); break;                                     \
+                    case 1: d1g<K, 1>(v, f00, f01, f10, f11); break;                                     \
+                    case 2: d1g<K, 2>(v, f00, f01, f10, f11); break;                                     \
+                    default: d1g<K, 3>(v, f00, f01, f10, f11); break;                                    \
+                }                                                                                        \
             }                                                                                            \
         } else {                                                                                         \
             uint32_t c = 0;                                                                              \
@@ -257,6 +270,9 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
         }                                                                                                \
     }
         const int s_end = s0 + ns;
+        // product of the chained diagonal factor pieces not yet applied
+        V ch0, ch1;
+        ch0.x = T(1); ch0.y = T(0); ch1 = ch0;
         DSub<T> ra = subs[s0];
         for (int s = s0; s < s_end; s += 2) {
             const DSub<T> rb = subs[s + 1 < s_end ? s + 1 : s_end - 1];
