@@ -82,6 +82,7 @@ __device__ __forceinline__ bf16x8 as_bf(u16x8 v) { return __builtin_bit_cast(bf1
 // share one completion counter: loads issued after the stores would wait
 // for them).  Per block and half: hi*hi + hi*lo + lo*hi.
 constexpr int BW_ROWS = (int)kBf16StreamRows, BW_COLS = (int)kBf16StreamCols;
+constexpr int BW_THREADS = 2 * BW_ROWS;    // one wave per 32 rows
 
 // a value the caller knows to be equal in all lanes, kept in scalar registers
 __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
@@ -260,7 +261,7 @@ struct SingleLoc {
 };
 
 template <bool FULL>
-__global__ __launch_bounds__(512) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
+__global__ __launch_bounds__(BW_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
                                                              const unsigned short* __restrict__ PB, int64_t N,
                                                              int64_t Kp, float2* __restrict__ out, int64_t ldo,
                                                              int accumulate, int64_t tiles_n, int64_t tiles) {
@@ -304,7 +305,7 @@ struct BatchLoc {
 };
 
 template <bool FULL>
-__global__ __launch_bounds__(512) void pathsum_bf16x3_batch(const GemmDesc* __restrict__ d, int n,
+__global__ __launch_bounds__(BW_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void pathsum_bf16x3_batch(const GemmDesc* __restrict__ d, int n,
                                                             unsigned char* base, int64_t tiles) {
 #if defined(__HIP_DEVICE_COMPILE__)
     const cdesc cd = (cdesc)d;
@@ -367,12 +368,12 @@ hsf_status launch_split_batch(const void* descs, int n, uint32_t total_blocks, u
 hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, bool full, unsigned char* base,
                                hipStream_t st) {
     const void* kern = full ? (const void*)pathsum_bf16x3_batch<true> : (const void*)pathsum_bf16x3_batch<false>;
-    const int grid = persistent_grid(kern, 512, 0, tiles);
+    const int grid = persistent_grid(kern, BW_THREADS, 0, tiles);
     if (full)
-        hipLaunchKernelGGL(pathsum_bf16x3_batch<true>, dim3(grid), dim3(512), 0, st, (const GemmDesc*)descs, n, base,
+        hipLaunchKernelGGL(pathsum_bf16x3_batch<true>, dim3(grid), dim3(BW_THREADS), 0, st, (const GemmDesc*)descs, n, base,
                            tiles);
     else
-        hipLaunchKernelGGL(pathsum_bf16x3_batch<false>, dim3(grid), dim3(512), 0, st, (const GemmDesc*)descs, n, base,
+        hipLaunchKernelGGL(pathsum_bf16x3_batch<false>, dim3(grid), dim3(BW_THREADS), 0, st, (const GemmDesc*)descs, n, base,
                            tiles);
     return hip_check(hipGetLastError(), "pathsum_bf16x3_batch launch");
 }
@@ -394,12 +395,12 @@ hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_
     const int64_t tn = (N + BW_COLS - 1) / BW_COLS, tiles = tn * ((M + BW_ROWS - 1) / BW_ROWS);
     const bool full = bf16x3_stream_full(M, N, Kp, ldo, accumulate);
     const void* kern = full ? (const void*)pathsum_bf16x3_kernel<true> : (const void*)pathsum_bf16x3_kernel<false>;
-    const int grid = persistent_grid(kern, 512, 0, tiles);
+    const int grid = persistent_grid(kern, BW_THREADS, 0, tiles);
     if (full)
-        hipLaunchKernelGGL(pathsum_bf16x3_kernel<true>, dim3(grid), dim3(512), 0, st, PA, M, PB, N, Kp, out, ldo, 0,
+        hipLaunchKernelGGL(pathsum_bf16x3_kernel<true>, dim3(grid), dim3(BW_THREADS), 0, st, PA, M, PB, N, Kp, out, ldo, 0,
                            tn, tiles);
     else
-        hipLaunchKernelGGL(pathsum_bf16x3_kernel<false>, dim3(grid), dim3(512), 0, st, PA, M, PB, N, Kp, out, ldo,
+        hipLaunchKernelGGL(pathsum_bf16x3_kernel<false>, dim3(grid), dim3(BW_THREADS), 0, st, PA, M, PB, N, Kp, out, ldo,
                            accumulate, tn, tiles);
     return hip_check(hipGetLastError(), "pathsum_bf16x3 launch");
 }
