@@ -43,6 +43,15 @@ def _src_hash(*names):
     return h.hexdigest()[:12]
 
 
+def _paths_ws(plan, n_paths):
+    """Device workspace of hsf_run_paths over n_paths paths (the path-tree
+    levels), or None when the sweep needs none."""
+    import torch
+    from paper_2502_06959_amd import hsf_workspace_size
+    nbytes = hsf_workspace_size(plan.handle, 0, n_paths, 0)
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda") if nbytes else None
+
+
 def _traffic_from_profiles(kernel, src_hash, workload):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE +
     WRITE_SIZE, copy-kernel calibrated), read from profiles/traffic.md if it
@@ -108,6 +117,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP32 path sum")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--c4-mode", default=None, choices=["f32", "bf16x3", "f64"])
+    ap.add_argument("--tree", default="auto", choices=["auto", "on", "off"],
+                    help="path-tree sweeps (one state per distinct leading-digit prefix)")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -143,12 +154,13 @@ def main():
     gen, desc = WORKLOADS[args.workload]
     circuit = getattr(cg, gen)()
     t0 = time.perf_counter()
-    plan = Plan(circuit, dtype="c64")
+    plan = Plan(circuit, dtype="c64", tree=args.tree)
     plan_s = time.perf_counter() - t0
     P, na, nb = plan.P, plan.na, plan.nb
     sa, sb = plan.side_stats(0), plan.side_stats(1)
     A, B = plan.alloc_halves(P)
     out = torch.empty((1 << na, 1 << nb), dtype=torch.complex64, device="cuda")
+    sw_ws = _paths_ws(plan, P)
 
     def run_mode(mode, steps, warmup):
         ws = None
@@ -159,7 +171,7 @@ def main():
         def step(ev=None):
             if ev:
                 ev[0].record()
-            plan.run_paths(0, P, A, B)
+            plan.run_paths(0, P, A, B, ws=sw_ws)
             if ev:
                 ev[1].record()
             plan.amplitudes_full(A, B, mode=mode, out=out, ws=ws)
@@ -276,7 +288,7 @@ def bench_c5(args):
     import circuitgen as cg
     from paper_2502_06959_amd import Batch, Plan
     cs = cg.c5()
-    plans = [Plan(c) for c in cs]
+    plans = [Plan(c, tree=args.tree) for c in cs]
     b = Batch(plans)
     outs = b.alloc_outputs()
     mode = args.mode
@@ -295,10 +307,11 @@ def bench_c5(args):
 
     ms = timed(lambda: b.run(outs, mode=mode, graph=True), args.steps, args.warmup)
     halves = [p.alloc_halves(p.P) for p in plans]
+    sws = [_paths_ws(p, p.P) for p in plans]
 
     def per_circuit():
-        for p, (A, B), o in zip(plans, halves, outs):
-            p.run_paths(0, p.P, A, B)
+        for p, (A, B), o, w in zip(plans, halves, outs, sws):
+            p.run_paths(0, p.P, A, B, ws=w)
             p.amplitudes_full(A, B, mode="f32", out=o)
 
     ms_plain = timed(per_circuit, max(1, args.steps // 2), 1)
@@ -328,7 +341,7 @@ def bench_c3(args):
     import circuitgen as cg
     from paper_2502_06959_amd import Plan
     c = cg.c3()
-    plan = Plan(c)
+    plan = Plan(c, tree=args.tree)
     x = torch.from_numpy(np.asarray(cg.c3_bitstrings(), dtype=np.uint64).astype(np.int64)).cuda()
     for _ in range(args.warmup):
         plan.backward(x)
@@ -398,7 +411,7 @@ def bench_c4(args):
     import circuitgen as cg
     from paper_2502_06959_amd import Plan, hsf_workspace_size
     c = cg.c4()
-    plan = Plan(c)
+    plan = Plan(c, tree=args.tree)
     A, B = plan.alloc_halves(plan.P)
     rows = 1 << 13
     mode = args.c4_mode or args.mode
@@ -409,8 +422,10 @@ def bench_c4(args):
         ws = torch.empty(hsf_workspace_size(plan.handle, 1, plan.P, 1), dtype=torch.uint8, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
+    sw_ws = _paths_ws(plan, plan.P)
+    torch.cuda.synchronize()
     ev[0].record()
-    plan.run_paths(0, plan.P, A, B)
+    plan.run_paths(0, plan.P, A, B, ws=sw_ws)
     ev[1].record()
     for r0 in range(0, 1 << plan.na, rows):
         plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode=mode, out=tile, ws=ws)
@@ -452,11 +467,12 @@ def _first_amplitudes(plan, chunk, rows, mode, out):
     for [p_lo, p_hi) (default all paths)."""
     import torch
     A, B = plan.alloc_halves(chunk)
+    ws = _paths_ws(plan, chunk)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for p0 in range(0, plan.P, chunk):
         n = min(chunk, plan.P - p0)
-        plan.run_paths(p0, p0 + n, A[:n], B[:n])
+        plan.run_paths(p0, p0 + n, A[:n], B[:n], ws=ws)
         plan.amplitudes_full(A[:n], B[:n], n_paths=n, rows=(0, rows), mode=mode, out=out, accumulate=p0 > 0)
     e1.record()
     torch.cuda.synchronize()
@@ -481,7 +497,7 @@ def bench_qaoa(args):
         c = cg.qaoa_sbm(100 + i, sizes, 0.8, pout)
         t0 = time.perf_counter()
         r = joint_blocked(c)
-        pj = Plan(r)
+        pj = Plan(r, tree=args.tree)
         host_ms = (time.perf_counter() - t0) * 1e3
         rows = (10 ** 6 + (1 << pj.nb) - 1) >> pj.nb
         out = torch.empty((rows, 1 << pj.nb), dtype=torch.complex64, device="cuda")
@@ -492,7 +508,7 @@ def bench_qaoa(args):
         std = dict(c)
         std["blocks"] = [[k] for k, g in enumerate(c["gates"])
                          if 0 < sum(q <= c["cut"] for q in g["q"]) < len(g["q"])]
-        ps = Plan(std)
+        ps = Plan(std, tree=args.tree)
         if ps.P <= (1 << 16):
             t_ms = _first_amplitudes(ps, min(ps.P, 1 << 14), rows, mode, out)
             t_kind = "measured"
@@ -532,8 +548,12 @@ class _PathWindow:
     def alloc_halves(self, n):
         return self.plan.alloc_halves(n)
 
-    def run_paths(self, p0, p1, A, B):
-        return self.plan.run_paths(p0, p1, A, B)
+    @property
+    def handle(self):
+        return self.plan.handle
+
+    def run_paths(self, p0, p1, A, B, ws=None):
+        return self.plan.run_paths(p0, p1, A, B, ws=ws)
 
     def amplitudes_full(self, *a, **k):
         return self.plan.amplitudes_full(*a, **k)

@@ -110,6 +110,9 @@ typedef struct {
     int32_t dtype;           /* hsf_dtype of the half-states (default HSF_C64)      */
     int32_t tile_qubits;     /* qubits per LDS tile (0 = largest that fits)         */
     int32_t fuse;            /* 1 = fuse gates on the host (default), 0 = off       */
+    int32_t tree;            /* path-tree sweeps (hsf_side_levels): 0 = where the
+                                planner's cost estimate favours them (default),
+                                1 = never, 2 = always                               */
 } hsf_plan_options;
 
 /* ---------------------------------------------------------------- plan ---- */
@@ -196,10 +199,32 @@ hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical,
                           int64_t* ops_fused, int32_t* passes, int32_t* tile_qubits,
                           int64_t* ops_shared, int32_t* shared_passes);
 
+/* Path-tree levels of side 0 = a, 1 = b.  A path's half-state depends on its
+ * digits only through the factor slots applied so far (Sec. II-B), so the
+ * paths that agree on the leading digits m_0 .. m_{d-1} (block 0 most
+ * significant) share one state until the first op that needs a later digit.
+ * The level of a fused op is the number of leading digits its result depends
+ * on (a slot of block k needs k + 1, and an op follows every earlier op it
+ * does not commute with); the ops, stably sorted by level, are swept level by
+ * level, each level keeping P / S states (S = prod_{k >= d} r_k) for all P
+ * paths.  Level 0 is the shared prefix (one state).
+ *   cap        entries of ops and states;
+ *   n_levels   receives the number of levels (at least 1);
+ *   ops        fused ops of the first min(cap, n_levels) levels;
+ *   states     their state counts for all P paths.
+ * Any output pointer may be NULL.                                              */
+hsf_status hsf_side_levels(hsf_plan_t plan, int32_t side, int32_t cap, int32_t* n_levels, int64_t* ops,
+                           int64_t* states);
+/* 1 if hsf_run_paths over n_paths paths sweeps level by level (path tree),
+ * 0 if every path runs every per-path op, -1 for a null plan.                */
+int32_t hsf_uses_tree(hsf_plan_t plan, int64_t n_paths);
+
 /* --------------------------------------------------------------- paths ---- */
 
 /* Device workspace in bytes for `op` over `n_paths` paths:
- *   op 0 = hsf_run_paths (none), 1 = hsf_amplitudes_full with path-sum mode
+ *   op 0 = hsf_run_paths (the path-tree levels below the last, when the
+ *   planner sweeps n_paths paths level by level; else 0), 1 =
+ *   hsf_amplitudes_full with path-sum mode
  *   `mode`, 2 = hsf_backward with chunks of `n_paths` paths and `mode` =
  *   number of bitstrings n_x.                                                  */
 size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t mode);
@@ -212,7 +237,10 @@ size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t 
  * device uploads the plan's tables and simulates each side's shared prefix
  * once (device memory of 2^n_side amplitudes per side and tile schedule,
  * owned by the plan, freed by hsf_plan_destroy; this call synchronizes the
- * device once).                                                             */
+ * device once).  ws: hsf_workspace_size(plan, 0, p_end - p_begin, 0) bytes
+ * (device) for the path-tree levels (hsf_side_levels); with a smaller or
+ * NULL workspace every path runs every per-path op (same result).  Calls
+ * that overlap on one workspace race.                                       */
 hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* psiA,
                          int64_t ldA, void* psiB, int64_t ldB, void* ws, size_t ws_bytes,
                          hsf_stream_t stream);

@@ -33,7 +33,7 @@ class HsfCircuit(ctypes.Structure):
 
 class HsfPlanOptions(ctypes.Structure):
     _fields_ = [("rank_tol", c_double), ("max_side_qubits", c_int32), ("dtype", c_int32),
-                ("tile_qubits", c_int32), ("fuse", c_int32)]
+                ("tile_qubits", c_int32), ("fuse", c_int32), ("tree", c_int32)]
 
 
 class HsfError(RuntimeError):
@@ -60,6 +60,8 @@ SIGNATURES = {
     "hsf_path_digits": (c_int32, [c_void_p, c_int64, P(c_int32)]),
     "hsf_side_stats": (c_int32, [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int32), P(c_int32), P(c_int64),
                                  P(c_int32)]),
+    "hsf_side_levels": (c_int32, [c_void_p, c_int32, c_int32, P(c_int32), P(c_int64), P(c_int64)]),
+    "hsf_uses_tree": (c_int32, [c_void_p, c_int64]),
     "hsf_workspace_size": (c_size_t, [c_void_p, c_int32, c_int64, c_int32]),
     "hsf_run_paths": (c_int32, [c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                 c_size_t, c_void_p]),

@@ -150,9 +150,37 @@ hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical, i
     return HSF_OK;
 }
 
+hsf_status hsf_side_levels(hsf_plan_t plan, int32_t side, int32_t cap, int32_t* n_levels, int64_t* ops,
+                           int64_t* states) {
+    if (!plan) return fail(HSF_E_ARG, "null plan");
+    if (side != 0 && side != 1) return fail(HSF_E_ARG, "side must be 0 (a) or 1 (b)");
+    if (cap < 0) return fail(HSF_E_ARG, "cap must be non-negative");
+    const Plan* p = P_(plan);
+    const SideProgram& s = p->side[side];
+    std::vector<int64_t> o(1, (int64_t)s.n_prefix), st(1, 1);
+    if (!s.tree.empty())
+        for (const TreeLevel& tl : s.tree[0].levels) {
+            o.push_back(tl.ops);
+            st.push_back(p->P / tl.S);
+        }
+    if (n_levels) *n_levels = (int32_t)o.size();
+    for (size_t i = 0; i < o.size() && (int32_t)i < cap; ++i) {
+        if (ops) ops[i] = o[i];
+        if (states) states[i] = st[i];
+    }
+    return HSF_OK;
+}
+
+int32_t hsf_uses_tree(hsf_plan_t plan, int64_t n_paths) {
+    if (!plan) return -1;
+    const Plan* p = P_(plan);
+    return use_tree(*p, pick_schedule(*p, n_paths), n_paths) ? 1 : 0;
+}
+
 size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t mode) {
     if (!plan || n_paths < 0) return 0;
     const Plan* p = P_(plan);
+    if (op == 0) return tree_workspace(*p, n_paths);
     if (op == 1 && mode == HSF_SUM_BF16X3) return bf16x3_workspace(p->na, p->nb, n_paths);
     if (op == 2) return backward_workspace(*p, n_paths, mode);
     return 0;
@@ -170,9 +198,7 @@ hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* 
     DeviceCopy* d = nullptr;
     hsf_status s = ensure_device(*p, &d);
     if (s != HSF_OK) return s;
-    (void)ws;
-    (void)ws_bytes;
-    return run_sides(*p, *d, p_begin, p_end - p_begin, psiA, ldA, psiB, ldB, (hipStream_t)stream);
+    return run_sides(*p, *d, p_begin, p_end - p_begin, psiA, ldA, psiB, ldB, ws, ws_bytes, (hipStream_t)stream);
     HSF_GUARD_END
 }
 

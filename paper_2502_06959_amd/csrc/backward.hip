@@ -300,7 +300,7 @@ __global__ void bw_shift_combine(const double* __restrict__ lp, const double* __
 // ---------------------------------------------------------------- host ----
 
 struct Layout {
-    size_t vA, vB, lA, lB, ckA, ckB, psi_x, psi_s, loss, partial, tables, mats, pools, total;
+    size_t vA, vB, lA, lB, ckA, ckB, psi_x, psi_s, loss, partial, tables, mats, pools, tree, tree_bytes, total;
     int64_t dimA, dimB;
     int ka, kb;            // checkpoints per side
     int64_t n_occ;         // parametrised ops outside blocks, both sides
@@ -336,7 +336,9 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     L.mat_elems = side_mat_elems(p.side[0]) + side_mat_elems(p.side[1]);
     L.pool_elems = 0;
     for (int s = 0; s < 2; ++s)
-        for (const Schedule& sc : p.side[s].sched) L.pool_elems += std::max<size_t>(sc.pool.size(), 1);
+        for (int tr = 0; tr < 2; ++tr)
+            for (const Schedule& sc : tr ? p.side[s].tree : p.side[s].sched)
+                L.pool_elems += std::max<size_t>(sc.pool.size(), 1);
     // parameter shifts of angles inside blocks: two forward runs each, each
     // with its own copy of the pools
     L.n_shift = 0;
@@ -360,6 +362,8 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     L.tables = take(L.table_elems * sizeof(int64_t));
     L.mats = take(L.mat_elems * esz);
     L.pools = take(L.pool_elems * (size_t)std::max<int64_t>(1, L.n_shift) * esz);
+    L.tree_bytes = tree_workspace(p, chunk);     // path-tree levels of the forward runs
+    L.tree = take(L.tree_bytes);
     L.total = o + 256;
     return L;
 }
@@ -602,7 +606,8 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
     // ---- psi(x_j) for every bitstring: tiled forward over all paths
     for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
         const int64_t np = std::min(chunk, p.P - p0);
-        if ((s = run_sides(p, d, p0, np, vS[0], dim[0], vS[1], dim[1], st)) != HSF_OK) return s;
+        if ((s = run_sides(p, d, p0, np, vS[0], dim[0], vS[1], dim[1], base + Lo.tree, Lo.tree_bytes, st)) != HSF_OK)
+            return s;
         if ((s = gather_dot(p.dtype, vS[0], dim[0], vS[1], dim[1], np, p.nb, p.n, x, nx, psi_x, p0 > 0 ? 1 : 0, st)) != HSF_OK)
             return s;
     }
@@ -686,14 +691,16 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
     for (const Block& b : p.blocks) any |= !b.params.empty();
     std::vector<V> staged;    // host copy of the shifted pools; must outlive the upload (final sync)
     if (any) {
-        // device pools of every schedule, to be patched per shifted block
-        std::vector<std::vector<size_t>> pool_at(2);
+        // device pools of every schedule (flat, then path-tree), to be
+        // patched per shifted block
+        std::vector<std::vector<size_t>> pool_at(4);
         size_t o = 0;
         for (int side = 0; side < 2; ++side)
-            for (const Schedule& sc : p.side[side].sched) {
-                pool_at[side].push_back(o);
-                o += std::max<size_t>(sc.pool.size(), 1);
-            }
+            for (int tr = 0; tr < 2; ++tr)
+                for (const Schedule& sc : tr ? p.side[side].tree : p.side[side].sched) {
+                    pool_at[2 * side + tr].push_back(o);
+                    o += std::max<size_t>(sc.pool.size(), 1);
+                }
         const double half_pi = std::acos(0.0);
         struct Shift {
             size_t k;
@@ -738,7 +745,8 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             all.reserve(Lo.pool_elems);
             for (int side = 0; side < 2; ++side) {
                 const std::vector<FactorPiece>& pcs = side == 0 ? fs.pa : fs.pb;
-                for (const Schedule& sc : p.side[side].sched) {
+                for (int tr = 0; tr < 2; ++tr)
+                for (const Schedule& sc : tr ? p.side[side].tree : p.side[side].sched) {
                     std::vector<cd> pl = sc.pool;
                     for (const DevOp& op : sc.devops)
                         if (op.type == DOP_SLOT && op.block == (int)sh.k) {
@@ -784,11 +792,15 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
         DeviceCopy dd = d;
         for (size_t i = 0; i < ns; ++i) {
             for (int side = 0; side < 2; ++side)
-                for (size_t q = 0; q < p.side[side].sched.size(); ++q)
-                    dd.side[side][q].pool = pools + i * Lo.pool_elems + pool_at[side][q];
+                for (int tr = 0; tr < 2; ++tr) {
+                    std::vector<DeviceSchedule>& dv = tr ? dd.tree[side] : dd.side[side];
+                    for (size_t q = 0; q < dv.size(); ++q) dv[q].pool = pools + i * Lo.pool_elems + pool_at[2 * side + tr][q];
+                }
             for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
                 const int64_t np = std::min(chunk, p.P - p0);
-                if ((s = run_sides(p, dd, p0, np, vS[0], dim[0], vS[1], dim[1], st)) != HSF_OK) return s;
+                if ((s = run_sides(p, dd, p0, np, vS[0], dim[0], vS[1], dim[1], base + Lo.tree, Lo.tree_bytes, st)) !=
+                    HSF_OK)
+                    return s;
                 if ((s = gather_dot(p.dtype, vS[0], dim[0], vS[1], dim[1], np, p.nb, p.n, x, nx, psi_s,
                                     p0 > 0 ? 1 : 0, st)) != HSF_OK)
                     return s;

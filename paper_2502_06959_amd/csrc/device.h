@@ -11,8 +11,12 @@ constexpr size_t kNormWsDoubles = 8192;
 
 // Runs both sides' programs (a side with a null pointer is skipped) for
 // paths [p_begin, p_begin + n_paths), one launch per LDS pass.
+// Half-states of paths [p_begin, p_begin + n_paths) into psiA / psiB (either
+// may be null).  ws: tree_workspace(p, n_paths) bytes for the path-tree
+// levels; with less (or null) every path runs every per-path op.
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
-                     void* psiB, int64_t ldB, hipStream_t stream);
+                     void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t tree_workspace(const Plan& p, int64_t n_paths);
 
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths);
 

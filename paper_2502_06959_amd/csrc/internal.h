@@ -153,6 +153,16 @@ struct Pass {
     int32_t prefix = 0;                // applies ops of the path-independent prefix only
 };
 
+// One level of a path-tree schedule: passes [pass_begin, pass_end) apply
+// the ops whose result depends on the digits m_0 .. m_{d-1} only (block 0
+// most significant), so the level keeps one state per value of those
+// digits, shared by the S = prod_{k >= d} r_k paths that agree on them.
+struct TreeLevel {
+    int pass_begin = 0, pass_end = 0;
+    int64_t S = 1;
+    int64_t ops = 0;                  // fused ops in the level
+};
+
 // LDS pass schedule of one side for one tile size.
 struct Schedule {
     int tile_bits = 0;
@@ -164,6 +174,9 @@ struct Schedule {
     std::vector<DevOp> devops;
     std::vector<SubOp> subs;
     std::vector<cd> pool;             // matrices referenced by devops / subs
+    // path-tree schedules only: the per-path passes level by level (the
+    // first level reads the prefix state, each later one its parent level)
+    std::vector<TreeLevel> levels;
 };
 
 struct SideProgram {
@@ -173,6 +186,9 @@ struct SideProgram {
     int n_prefix = 0;                 // leading ops of `ops` without factor slots
     int64_t ops_logical = 0;
     std::vector<Schedule> sched;      // one per candidate tile size, largest first
+    // the same tile sizes as path-tree schedules (empty when the plan has
+    // no blocks); ops reordered by level, see level_order
+    std::vector<Schedule> tree;
 };
 
 // One (circuit, side) segment of a batched sweep launch (device table).
@@ -218,6 +234,7 @@ struct DeviceSchedule {
 struct DeviceCopy {
     int device = -1;
     std::vector<DeviceSchedule> side[2];
+    std::vector<DeviceSchedule> tree[2];   // the sides' path-tree schedules
 };
 
 struct Plan {
@@ -227,6 +244,7 @@ struct Plan {
     int max_side = kMaxSideQubits;
     int fuse = 1;
     int tile_req = 0;
+    int tree_mode = 0;                // path-tree sweeps: 0 = by cost estimate, 1 = never, 2 = always
     std::vector<Gate> gates;
     std::vector<Block> blocks;
     int64_t P = 1;
@@ -271,7 +289,17 @@ bool gate_generator(int kind, int nq, std::vector<cd>& d);
 void fuse_side(Plan& p, int side);
 // Commutes diagonal gates ahead of diagonal factor pieces and sets n_prefix.
 void order_prefix(SideProgram& sp);
-Schedule schedule_side(const Plan& p, int side, int tile_bits);
+// Fused ops of a side in path-tree order (stable by level) and the bounds
+// of each level's range (cuts[0] = 0, ..., cuts.back() = ops) with the
+// level of each range.
+std::vector<SideOp> level_order(const Plan& p, int side, std::vector<int>& cuts, std::vector<int>& levels);
+// Passes for ops[cuts[0] .. cuts[1]) (the shared prefix, may be empty) and
+// then each range [cuts[i], cuts[i+1]); tree: record each later range as a
+// TreeLevel with S from `levels`.
+Schedule schedule_side(const Plan& p, int side, int tile_bits, const std::vector<SideOp>& ops,
+                       const std::vector<int>& cuts, const std::vector<int>& levels, bool tree);
+// Whether run_sides takes the path-tree schedules for this launch shape.
+bool use_tree(const Plan& p, int pick, int64_t n_paths);
 // Index of the schedule used for a launch over n_paths paths.
 int pick_schedule(const Plan& p, int64_t n_paths);
 

@@ -329,6 +329,8 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
         p->dtype = opts->dtype;
         p->tile_req = opts->tile_qubits;
         p->fuse = opts->fuse;
+        if (opts->tree < 0 || opts->tree > 2) return fail(HSF_E_ARG, "tree must be 0, 1 or 2");
+        p->tree_mode = opts->tree;
     }
     if (p->tile_req < 0 || p->tile_req > max_tile_bits(p->dtype))
         return fail(HSF_E_ARG, "tile_qubits out of range");
@@ -514,7 +516,18 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
         // candidate tile sizes, largest first (a requested size is the only one)
         const int top = std::min(tmax, nq);
         const int bottom = p->tile_req > 0 ? top : std::max(std::min(nq, 8), top - 3);
-        for (int L = top; L >= bottom; --L) p->side[s].sched.push_back(schedule_side(*p, s, L));
+        const std::vector<int> flat_cuts = {0, p->side[s].n_prefix, (int)p->side[s].ops.size()};
+        for (int L = top; L >= bottom; --L)
+            p->side[s].sched.push_back(schedule_side(*p, s, L, p->side[s].ops, flat_cuts, {}, false));
+        if (!p->blocks.empty()) {
+            std::vector<int> cuts, levels;
+            const std::vector<SideOp> lops = level_order(*p, s, cuts, levels);
+            // every block has a slot on both sides, so the last level holds
+            // all digits; a side without per-path ops keeps the flat form only
+            if (levels.size() >= 2 && levels.back() == (int)p->blocks.size())
+                for (int L = top; L >= bottom; --L)
+                    p->side[s].tree.push_back(schedule_side(*p, s, L, lops, cuts, levels, true));
+        }
     }
     *out = guard.release();
     return HSF_OK;
@@ -649,6 +662,28 @@ bool op_is_diagonal(const SideOp& o) {
 // order.  In a brickwork this is every gate outside the forward light cone of
 // the first block; for the cascades of Sec. V the cost layer outside the
 // blocks.
+namespace {
+
+// Within each run of diagonal ops in v[lo, hi), the one-qubit factor pieces
+// go last, ordered by qubit, so that the pieces on one qubit meet in a
+// register group and are multiplied before being applied.
+void order_pieces(std::vector<SideOp>& v, size_t lo, size_t hi) {
+    for (size_t i = lo; i < hi;) {
+        size_t j = i;
+        while (j < hi && op_is_diagonal(v[j])) ++j;
+        if (j > i + 1) {
+            auto piece = [](const SideOp& o) { return o.kind == SideOp::SLOT && o.k == 1; };
+            auto mid = std::stable_partition(v.begin() + (std::ptrdiff_t)i, v.begin() + (std::ptrdiff_t)j,
+                                             [&](const SideOp& o) { return !piece(o); });
+            std::stable_sort(mid, v.begin() + (std::ptrdiff_t)j,
+                             [](const SideOp& x, const SideOp& y) { return x.q[0] < y.q[0]; });
+        }
+        i = j > i ? j : i + 1;
+    }
+}
+
+}  // namespace
+
 void order_prefix(SideProgram& sp) {
     const int nq = std::max(sp.nq, 1);
     std::vector<char> dense_left(nq, 0), diag_left(nq, 0);   // qubits of the ops left behind
@@ -665,26 +700,62 @@ void order_prefix(SideProgram& sp) {
             rest.push_back(std::move(o));
         }
     }
-    // within each run of diagonal ops left per path, the one-qubit factor
-    // pieces go last, ordered by qubit, so that the pieces on one qubit meet
-    // in a register group and are multiplied before being applied
-    for (size_t i = 0; i < rest.size();) {
-        size_t j = i;
-        while (j < rest.size() && op_is_diagonal(rest[j])) ++j;
-        if (j > i + 1) {
-            auto piece = [](const SideOp& o) { return o.kind == SideOp::SLOT && o.k == 1; };
-            auto mid = std::stable_partition(rest.begin() + (std::ptrdiff_t)i, rest.begin() + (std::ptrdiff_t)j,
-                                             [&](const SideOp& o) { return !piece(o); });
-            std::stable_sort(mid, rest.begin() + (std::ptrdiff_t)j,
-                             [](const SideOp& x, const SideOp& y) { return x.q[0] < y.q[0]; });
-        }
-        i = j > i ? j : i + 1;
-    }
+    order_pieces(rest, 0, rest.size());
     sp.n_prefix = (int)pre.size();
     sp.ops = std::move(pre);
     sp.ops.insert(sp.ops.end(), std::make_move_iterator(rest.begin()), std::make_move_iterator(rest.end()));
 }
 
+
+// Path-tree order.  A path's half-state after an op depends on the path
+// only through the digits of the factor slots applied so far (Sec. II-B:
+// every other op acts the same way on all paths), so the paths that agree
+// on m_0 .. m_{d-1} share one state up to the first op that needs a later
+// digit.  The level of an op is the number of leading digits its result
+// depends on: a slot of block k needs k + 1, and an op must follow every
+// earlier op it does not commute with (disjoint qubits, or both diagonal,
+// commute), so it takes the largest level among those.  Sorting the ops
+// stably by level keeps every such pair in order; level 0 is the shared
+// prefix.
+std::vector<SideOp> level_order(const Plan& p, int side, std::vector<int>& cuts, std::vector<int>& levels) {
+    const SideProgram& sp = p.side[side];
+    const int nq = std::max(sp.nq, 1);
+    const int n = (int)sp.ops.size();
+    std::vector<int> dense_lev(nq, 0), diag_lev(nq, 0), lev(n, 0);
+    for (int i = 0; i < n; ++i) {
+        const SideOp& o = sp.ops[i];
+        const bool od = op_is_diagonal(o);
+        int l = o.kind == SideOp::SLOT ? o.block + 1 : 0;
+        for (int j = 0; j < o.k; ++j) {
+            l = std::max(l, dense_lev[o.q[j]]);
+            if (!od) l = std::max(l, diag_lev[o.q[j]]);
+        }
+        lev[i] = l;
+        for (int j = 0; j < o.k; ++j) {
+            int& t = (od ? diag_lev : dense_lev)[o.q[j]];
+            t = std::max(t, l);
+        }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return lev[a] < lev[b]; });
+    std::vector<SideOp> out;
+    out.reserve(n);
+    cuts.assign(1, 0);
+    levels.assign(1, 0);
+    // range 0 is level 0 (possibly empty); then one range per level present
+    for (int i = 0; i < n; ++i) {
+        const int l = lev[idx[i]];
+        if (l != levels.back()) {
+            cuts.push_back(i);
+            levels.push_back(l);
+        }
+        out.push_back(sp.ops[idx[i]]);
+    }
+    cuts.push_back(n);
+    for (size_t r = 1; r + 1 < cuts.size(); ++r) order_pieces(out, (size_t)cuts[r], (size_t)cuts[r + 1]);
+    return out;
+}
 
 namespace {
 
@@ -694,7 +765,8 @@ namespace {
 // register-resident group; wider dense ops and factor slots stand alone.
 // group_slots: one-qubit factor pieces join register groups (as SUB_SLOT1);
 // otherwise they stay separate ops.
-void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::vector<int>& ids, bool group_slots) {
+void emit_pass(const std::vector<SideOp>& sops, Schedule& sc, const Pass& ps, const std::vector<int>& ids,
+               bool group_slots) {
     const int L = ps.n_local;
     const int KG = group_bits(L);
     auto tbit = [&](int q) -> int {
@@ -712,7 +784,7 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
         if (grp.empty()) return;
         std::vector<int> bits = gbits;
         for (int id : grp) {
-            const SideOp& o = sp.ops[id];
+            const SideOp& o = sops[id];
             if (o.kind != SideOp::DIAG) continue;
             for (int j = 0; j < o.k && (int)bits.size() < KG; ++j) {
                 const int b = tbit(o.q[j]);
@@ -729,7 +801,7 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
         d.mat = (int32_t)sc.subs.size();
         d.rank = (int32_t)grp.size();
         for (int id : grp) {
-            const SideOp& o = sp.ops[id];
+            const SideOp& o = sops[id];
             SubOp so{};
             if (o.kind == SideOp::SLOT) {
                 so.type = SUB_SLOT1;
@@ -804,7 +876,7 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
         gbits.clear();
     };
     for (int id : ids) {
-        const SideOp& o = sp.ops[id];
+        const SideOp& o = sops[id];
         // one-qubit gates and one-qubit factor pieces join register groups
         if ((o.kind == SideOp::DENSE || (o.kind == SideOp::SLOT && group_slots)) && o.k == 1) {
             const int b = tbit(o.q[0]);
@@ -835,7 +907,8 @@ void emit_pass(const SideProgram& sp, Schedule& sc, const Pass& ps, const std::v
 
 }  // namespace
 
-Schedule schedule_side(const Plan& p, int s, int L) {
+Schedule schedule_side(const Plan& p, int s, int L, const std::vector<SideOp>& ops, const std::vector<int>& cuts,
+                       const std::vector<int>& levels, bool tree) {
     const SideProgram& sp = p.side[s];
     Schedule sc;
     const int nq = sp.nq;
@@ -843,13 +916,13 @@ Schedule schedule_side(const Plan& p, int s, int L) {
     L = std::max(std::min(nq, 8), std::min(L, nq));
     L = std::max(L, 1);
     sc.tile_bits = L;
-    const int nops = (int)sp.ops.size();
+    const int nops = (int)ops.size();
     // fold one-qubit factor pieces into register groups only when blocks
     // bring several of them to this side (cascades, Sec. V): then the group
     // saves LDS passes; a lone piece per block is cheaper as its own op
     std::set<int> piece_blocks;
     int pieces = 0;
-    for (const SideOp& o : sp.ops)
+    for (const SideOp& o : ops)
         if (o.kind == SideOp::SLOT && o.k == 1) {
             ++pieces;
             piece_blocks.insert(o.block);
@@ -877,7 +950,7 @@ Schedule schedule_side(const Plan& p, int s, int L) {
                 // the qubits of the earliest pending non-diagonal ops
                 for (int i = 0; i < nops && nloc < L; ++i) {
                     if (done[i]) continue;
-                    const SideOp& o = sp.ops[i];
+                    const SideOp& o = ops[i];
                     if (o.kind != SideOp::DIAG) {
                         int need = 0;
                         for (int j = 0; j < o.k; ++j) need += !local[o.q[j]];
@@ -900,7 +973,7 @@ Schedule schedule_side(const Plan& p, int s, int L) {
             std::vector<char> blocked(std::max(nq, 1), 0);
             for (int i = 0; i < nops; ++i) {
                 if (done[i]) continue;
-                const SideOp& o = sp.ops[i];
+                const SideOp& o = ops[i];
                 bool blk = false, fits = true;
                 for (int j = 0; j < o.k; ++j) {
                     blk |= (bool)blocked[o.q[j]];
@@ -915,7 +988,7 @@ Schedule schedule_side(const Plan& p, int s, int L) {
                 }
             }
             ps.op_begin = (int32_t)sc.devops.size();
-            emit_pass(sp, sc, ps, ids, group_slots);
+            emit_pass(ops, sc, ps, ids, group_slots);
             ps.op_end = (int32_t)sc.devops.size();
             // barriers: only between ops that are not both wave-private (a wave
             // holds 64 lanes x 2^k amplitudes of a group, tile bits 0 .. 5+k)
@@ -938,11 +1011,24 @@ Schedule schedule_side(const Plan& p, int s, int L) {
             if (sc.passes.size() > (size_t)4 * nops + 8) break;  // every pass applies an op; never reached
         }
     };
-    // the shared prefix, then the per-path rest (at least one pass: it also
-    // copies the prefix state into each path's row)
-    if (sp.n_prefix > 0) schedule_range(0, sp.n_prefix, true);
+    // the shared prefix, then the per-path ranges (each at least one pass:
+    // the first also copies the prefix state into each path's row)
+    if (cuts[1] > cuts[0]) schedule_range(cuts[0], cuts[1], true);
     sc.n_prefix_passes = (int)sc.passes.size();
-    schedule_range(sp.n_prefix, nops, false);
+    for (size_t r = 1; r + 1 < cuts.size(); ++r) {
+        const int pb = (int)sc.passes.size();
+        schedule_range(cuts[r], cuts[r + 1], false);
+        if (tree) {
+            TreeLevel tl;
+            tl.pass_begin = pb;
+            tl.pass_end = (int)sc.passes.size();
+            // paths per state: the digits of blocks levels[r] .. K-1 still open
+            tl.S = 1;
+            for (size_t k = (size_t)levels[r]; k < p.blocks.size(); ++k) tl.S *= p.blocks[k].rank;
+            tl.ops = cuts[r + 1] - cuts[r];
+            sc.levels.push_back(tl);
+        }
+    }
     return sc;
 }
 
@@ -961,6 +1047,50 @@ int pick_schedule(const Plan& p, int64_t n_paths) {
         if (wgs >= target) return (int)i;
     }
     return (int)n - 1;
+}
+
+namespace {
+
+// Rough cost of a sweep launch of W workgroups on one pass: the waves of
+// workgroups the chip runs (by LDS per workgroup) times the pass's work per
+// tile (register-group sub-ops, other device ops counted four each, and the
+// tile's load and store).
+double pass_cost(const Schedule& sc, int k, int64_t wgs, size_t esz) {
+    const Pass& ps = sc.passes[(size_t)k];
+    double work = 8.0;
+    for (int32_t i = ps.op_begin; i < ps.op_end; ++i) {
+        const DevOp& d = sc.devops[(size_t)i];
+        work += d.type == DOP_GROUP ? (double)d.rank : 4.0;
+    }
+    const size_t lds = ((size_t(1) << ps.n_local) + 256) * esz;
+    const int64_t per_cu = std::max<int64_t>(1, (int64_t)((160u << 10) / lds));
+    const int64_t slots = 256 * per_cu;
+    return (double)((wgs + slots - 1) / slots) * work;
+}
+
+}  // namespace
+
+bool use_tree(const Plan& p, int pick, int64_t n_paths) {
+    if (p.tree_mode == 1 || n_paths <= 0) return false;
+    for (int s = 0; s < 2; ++s)
+        if (p.side[s].tree.empty()) return false;
+    if (p.tree_mode == 2) return true;
+    const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
+    double flat = 0, tree = 0;
+    for (int s = 0; s < 2; ++s) {
+        const Schedule& f = p.side[s].sched[std::min<size_t>((size_t)pick, p.side[s].sched.size() - 1)];
+        const Schedule& t = p.side[s].tree[std::min<size_t>((size_t)pick, p.side[s].tree.size() - 1)];
+        for (size_t k = (size_t)f.n_prefix_passes; k < f.passes.size(); ++k)
+            flat += pass_cost(f, (int)k, n_paths << f.passes[k].n_nonlocal, esz);
+        // a chunk of n_paths consecutive paths holds about n_paths / S + 1
+        // states of a level
+        for (const TreeLevel& tl : t.levels) {
+            const int64_t rows = std::min<int64_t>(n_paths, n_paths / tl.S + 1);
+            for (int k = tl.pass_begin; k < tl.pass_end; ++k)
+                tree += pass_cost(t, k, rows << t.passes[(size_t)k].n_nonlocal, esz);
+        }
+    }
+    return tree < 0.9 * flat;
 }
 
 }  // namespace hsf

@@ -84,9 +84,21 @@ struct SideArgs {
     const void* subs;        // DSub<T>[]
     const void* pool;
     uint32_t n_tiles;
-    uint32_t n_blocks;       // paths x tiles
-    const void* shared;      // non-null: the pass reads this state (the shared prefix) instead of the path's row
+    uint32_t n_blocks;       // rows x tiles
+    // Rows.  A launch row is a level row i = i_lo + j, the state of the S
+    // paths [i S, (i + 1) S) (S = 1: one path); it is written to row
+    // i - dst_lo of psi and takes its digits from the first of its paths at
+    // or after p0, max(i S, p0).
+    int64_t p0, S, i_lo, dst_lo;
+    // Input: ROW_INPLACE its own row; ROW_SHARED the single state `src`;
+    // ROW_PARENT row i S / S_par - src_lo of `src` (ld src_ld), the state of
+    // the S_par paths it belongs to at the previous level.
+    const void* src;
+    int64_t src_ld, src_lo, S_par;
+    int32_t mode;
 };
+
+enum RowMode : int32_t { ROW_INPLACE = 0, ROW_SHARED = 1, ROW_PARENT = 2 };
 
 // LDS position of tile element e: the low four index bits are XORed with the
 // next four, so that the 16 lanes that vary the lowest free bits of a
@@ -360,21 +372,30 @@ __device__ __forceinline__ void sweep_tile(ctab<Pass> ps, ctab<DevOp> ops, ctab<
 }
 
 template <typename T, int KG, bool S1>
-__global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideArgs s1, int64_t p_begin) {
+__global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideArgs s1) {
     using V = typename Cx<T>::v;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    // fields picked one by one (selects of kernel arguments, no copy of a whole record)
     const bool sd = blockIdx.x >= s0.n_blocks;
-    const uint32_t n_tiles = sd ? s1.n_tiles : s0.n_tiles;
+#define HSF_SEL(f) (sd ? s1.f : s0.f)
+    const uint32_t n_tiles = HSF_SEL(n_tiles);
     const uint32_t blk = sd ? blockIdx.x - s0.n_blocks : blockIdx.x;
     const uint32_t pl = blk / n_tiles;
     const uint32_t t = blk - pl * n_tiles;
-    const int64_t ld = sd ? s1.ld : s0.ld;
-    V* st = reinterpret_cast<V*>(sd ? s1.psi : s0.psi) + (int64_t)pl * ld;
-    const V* shared = reinterpret_cast<const V*>(sd ? s1.shared : s0.shared);
-    sweep_tile<T, KG, S1>(as_table(sd ? s1.pass : s0.pass), as_table(sd ? s1.ops : s0.ops),
-                      as_table(reinterpret_cast<const DSub<T>*>(sd ? s1.subs : s0.subs)),
-                      reinterpret_cast<const V*>(sd ? s1.pool : s0.pool), st, shared ? shared : st, t,
-                      p_begin + pl, reinterpret_cast<V*>(smem_raw));
+    const int64_t i = HSF_SEL(i_lo) + (int64_t)pl;
+    const int64_t S = HSF_SEL(S);
+    const int64_t path = max(i * S, HSF_SEL(p0));
+    V* st = reinterpret_cast<V*>(HSF_SEL(psi)) + (i - HSF_SEL(dst_lo)) * HSF_SEL(ld);
+    const V* src = st;
+    const int32_t mode = HSF_SEL(mode);
+    if (mode == ROW_SHARED)
+        src = reinterpret_cast<const V*>(HSF_SEL(src));
+    else if (mode == ROW_PARENT)
+        src = reinterpret_cast<const V*>(HSF_SEL(src)) + ((i * S) / HSF_SEL(S_par) - HSF_SEL(src_lo)) * HSF_SEL(src_ld);
+    sweep_tile<T, KG, S1>(as_table(HSF_SEL(pass)), as_table(HSF_SEL(ops)),
+                          as_table(reinterpret_cast<const DSub<T>*>(HSF_SEL(subs))),
+                          reinterpret_cast<const V*>(HSF_SEL(pool)), st, src, t, path, reinterpret_cast<V*>(smem_raw));
+#undef HSF_SEL
 }
 
 // Many circuits' pass k in one launch: segment i covers workgroups
@@ -460,7 +481,7 @@ int max_tile_bits(int dtype) { return dtype == HSF_C128 ? 13 : 14; }
 
 namespace {
 hsf_status launch_pass(bool dbl, int kg, bool s1, uint32_t total, int threads, size_t shmem, hipStream_t stream,
-                       const SideArgs& a, const SideArgs& b, int64_t p0);
+                       const SideArgs& a, const SideArgs& b);
 }  // namespace
 
 // Runs a schedule's prefix passes for a single path into a new buffer (the
@@ -488,18 +509,18 @@ hsf_status compute_prefix(const Plan& p, DeviceSchedule& ds, const Schedule& sc,
         a.pool = ds.pool;
         a.n_tiles = 1u << ps.n_nonlocal;
         a.n_blocks = a.n_tiles;
+        a.S = 1;              // one row (path 0), in place
+        a.mode = ROW_INPLACE;
         const uint32_t E = 1u << ps.n_local;
         const int kg = group_bits(ps.n_local);
         const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, E >> kg));
-        s = launch_pass(dbl, kg, ps.has_slot1 != 0, a.n_blocks, threads, ((size_t)E + 256) * esz, nullptr, a, b, 0);
+        s = launch_pass(dbl, kg, ps.has_slot1 != 0, a.n_blocks, threads, ((size_t)E + 256) * esz, nullptr, a, b);
         if (s != HSF_OK) return s;
     }
     return HSF_OK;
 }
 
-hsf_status compute_prefix(Plan& p, DeviceCopy& d, int side, int q) {
-    return compute_prefix(p, d.side[side][q], p.side[side].sched[q], p.side[side].nq);
-}
+
 
 hsf_status ensure_device(Plan& p, DeviceCopy** out) {
     int dev = 0;
@@ -514,17 +535,17 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
     p.dev.emplace_back();
     DeviceCopy& d = p.dev.back();
     d.device = dev;
-    for (int side = 0; side < 2; ++side) {
-        for (const Schedule& sc : p.side[side].sched) {
-            d.side[side].emplace_back();
-            s = p.dtype == HSF_C128 ? upload_schedule<double>(sc, d.side[side].back())
-                                    : upload_schedule<float>(sc, d.side[side].back());
-            if (s != HSF_OK) {
-                release_device(p);
-                return s;
+    for (int side = 0; side < 2; ++side)
+        for (int tr = 0; tr < 2; ++tr)
+            for (const Schedule& sc : tr ? p.side[side].tree : p.side[side].sched) {
+                std::vector<DeviceSchedule>& v = tr ? d.tree[side] : d.side[side];
+                v.emplace_back();
+                s = p.dtype == HSF_C128 ? upload_schedule<double>(sc, v.back()) : upload_schedule<float>(sc, v.back());
+                if (s != HSF_OK) {
+                    release_device(p);
+                    return s;
+                }
             }
-        }
-    }
     const int di = p.dtype == HSF_C128 ? 1 : 0;
     if (!g_attr_done[di]) {
         const size_t bytes = ((size_t(1) << max_tile_bits(p.dtype)) + 256) * (p.dtype == HSF_C128 ? 16 : 8);
@@ -543,11 +564,14 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
     // the shared prefix states, once per schedule (passes without factor
     // slots, one path), before any caller's work
     for (int side = 0; side < 2; ++side)
-        for (size_t q = 0; q < p.side[side].sched.size(); ++q) {
-            s = compute_prefix(p, d, side, (int)q);
-            if (s != HSF_OK) {
-                release_device(p);
-                return s;
+        for (int tr = 0; tr < 2; ++tr) {
+            const std::vector<Schedule>& v = tr ? p.side[side].tree : p.side[side].sched;
+            for (size_t q = 0; q < v.size(); ++q) {
+                s = compute_prefix(p, (tr ? d.tree[side] : d.side[side])[q], v[q], p.side[side].nq);
+                if (s != HSF_OK) {
+                    release_device(p);
+                    return s;
+                }
             }
         }
     s = hip_check(hipStreamSynchronize(nullptr), "prefix states");
@@ -565,9 +589,10 @@ void release_device(Plan& p) {
     for (DeviceCopy& d : p.dev) {
         (void)hipSetDevice(d.device);
         for (int side = 0; side < 2; ++side)
-            for (DeviceSchedule& ds : d.side[side])
-                for (void* q : {ds.passes, ds.ops, ds.subs, ds.pool, ds.prefix})
-                    if (q) (void)hipFree(q);
+            for (int tr = 0; tr < 2; ++tr)
+                for (DeviceSchedule& ds : tr ? d.tree[side] : d.side[side])
+                    for (void* q : {ds.passes, ds.ops, ds.subs, ds.pool, ds.prefix})
+                        if (q) (void)hipFree(q);
     }
     (void)hipSetDevice(cur);
     p.dev.clear();
@@ -577,23 +602,23 @@ namespace {
 
 template <typename T, bool S1>
 hsf_status launch_pass_ts(int kg, uint32_t total, int threads, size_t shmem, hipStream_t stream, const SideArgs& a,
-                          const SideArgs& b, int64_t p0) {
+                          const SideArgs& b) {
     switch (kg) {
-        case 4: hipLaunchKernelGGL((sweep_pass<T, 4, S1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
-        case 3: hipLaunchKernelGGL((sweep_pass<T, 3, S1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
-        case 2: hipLaunchKernelGGL((sweep_pass<T, 2, S1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
-        default: hipLaunchKernelGGL((sweep_pass<T, 1, S1>), dim3(total), dim3(threads), shmem, stream, a, b, p0); break;
+        case 4: hipLaunchKernelGGL((sweep_pass<T, 4, S1>), dim3(total), dim3(threads), shmem, stream, a, b); break;
+        case 3: hipLaunchKernelGGL((sweep_pass<T, 3, S1>), dim3(total), dim3(threads), shmem, stream, a, b); break;
+        case 2: hipLaunchKernelGGL((sweep_pass<T, 2, S1>), dim3(total), dim3(threads), shmem, stream, a, b); break;
+        default: hipLaunchKernelGGL((sweep_pass<T, 1, S1>), dim3(total), dim3(threads), shmem, stream, a, b); break;
     }
     return hip_check(hipGetLastError(), "sweep_pass launch");
 }
 
 hsf_status launch_pass(bool dbl, int kg, bool s1, uint32_t total, int threads, size_t shmem, hipStream_t stream,
-                       const SideArgs& a, const SideArgs& b, int64_t p0) {
+                       const SideArgs& a, const SideArgs& b) {
     if (dbl)
-        return s1 ? launch_pass_ts<double, true>(kg, total, threads, shmem, stream, a, b, p0)
-                  : launch_pass_ts<double, false>(kg, total, threads, shmem, stream, a, b, p0);
-    return s1 ? launch_pass_ts<float, true>(kg, total, threads, shmem, stream, a, b, p0)
-              : launch_pass_ts<float, false>(kg, total, threads, shmem, stream, a, b, p0);
+        return s1 ? launch_pass_ts<double, true>(kg, total, threads, shmem, stream, a, b)
+                  : launch_pass_ts<double, false>(kg, total, threads, shmem, stream, a, b);
+    return s1 ? launch_pass_ts<float, true>(kg, total, threads, shmem, stream, a, b)
+              : launch_pass_ts<float, false>(kg, total, threads, shmem, stream, a, b);
 }
 
 }  // namespace
@@ -624,63 +649,181 @@ void batch_sweep_prepare() {
     done = true;
 }
 
+namespace {
+
+// One launch's worth of one side: pass k over the level rows
+// [i_lo, i_lo + rows) (see SideArgs).
+struct Item {
+    size_t k;
+    int32_t mode;
+    int64_t S, i_lo, rows;
+    void* dst;
+    int64_t dst_ld;
+    const void* src;
+    int64_t src_ld, src_lo, S_par;
+};
+
+// Level rows of a chunk of n paths from p_begin: [p_begin / S, (p_begin + n - 1) / S].
+int64_t level_rows(int64_t p_begin, int64_t n, int64_t S) { return (p_begin + n - 1) / S - p_begin / S + 1; }
+// A bound on level_rows over every p_begin.
+int64_t level_rows_max(int64_t n, int64_t S) { return (n - 1) / S + 2; }
+
+// Scratch of the path-tree levels below the last: two buffers per side,
+// level l in buffer l % 2 (it reads level l - 1 from the other).
+struct TreeScratch {
+    size_t off[2][2] = {{0, 0}, {0, 0}}, total = 0;
+};
+
+TreeScratch tree_scratch(const Plan& p, int64_t n_paths) {
+    TreeScratch t;
+    const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
+    size_t o = 0;
+    for (int s = 0; s < 2; ++s) {
+        if (p.side[s].tree.empty()) continue;
+        const std::vector<TreeLevel>& lv = p.side[s].tree[0].levels;
+        int64_t rows[2] = {0, 0};
+        for (size_t l = 0; l + 1 < lv.size(); ++l)
+            rows[l % 2] = std::max(rows[l % 2], level_rows_max(n_paths, lv[l].S));
+        for (int b = 0; b < 2; ++b) {
+            t.off[s][b] = o;
+            o += ((size_t)rows[b] * ((size_t)1 << p.side[s].nq) * esz + 255) & ~size_t(255);
+        }
+    }
+    t.total = o == 0 ? 0 : o + 256;
+    return t;
+}
+
+// Flat: every per-path pass over every path of the chunk (the first reads
+// the prefix state when there is one).  Tree: level by level, each level's
+// rows written to its scratch buffer (the last level to psi), its first pass
+// reading the prefix state or the previous level.
+std::vector<Item> side_items(const Schedule& sc, bool tree, const void* prefix, int64_t p_begin, int64_t n_paths,
+                             void* psi, int64_t ld, unsigned char* buf0, unsigned char* buf1, int64_t dim) {
+    std::vector<Item> v;
+    const size_t first = prefix ? (size_t)sc.n_prefix_passes : 0;
+    if (!tree) {
+        for (size_t k = first; k < sc.passes.size(); ++k) {
+            const bool sh = k == first && prefix;
+            v.push_back({k, sh ? ROW_SHARED : ROW_INPLACE, 1, p_begin, n_paths, psi, ld, sh ? prefix : nullptr, 0, 0, 1});
+        }
+        return v;
+    }
+    unsigned char* buf[2] = {buf0, buf1};
+    const size_t nl = sc.levels.size();
+    for (size_t l = 0; l < nl; ++l) {
+        const TreeLevel& tl = sc.levels[l];
+        const int64_t lo = p_begin / tl.S, rows = level_rows(p_begin, n_paths, tl.S);
+        void* dst = l + 1 == nl ? psi : (void*)buf[l % 2];
+        const int64_t dld = l + 1 == nl ? ld : dim;
+        for (size_t k = (size_t)tl.pass_begin; k < (size_t)tl.pass_end; ++k) {
+            Item it{k, ROW_INPLACE, tl.S, lo, rows, dst, dld, nullptr, 0, 0, 1};
+            if (k == (size_t)tl.pass_begin && l == 0 && prefix) {
+                it.mode = ROW_SHARED;
+                it.src = prefix;
+            } else if (k == (size_t)tl.pass_begin && l > 0) {
+                it.mode = ROW_PARENT;
+                it.src = buf[(l - 1) % 2];
+                it.src_ld = dim;
+                it.S_par = sc.levels[l - 1].S;
+                it.src_lo = p_begin / it.S_par;
+            }
+            v.push_back(it);
+        }
+    }
+    return v;
+}
+
+}  // namespace
+
+size_t tree_workspace(const Plan& p, int64_t n_paths) {
+    if (n_paths <= 0 || !use_tree(p, pick_schedule(p, n_paths), n_paths)) return 0;
+    return tree_scratch(p, n_paths).total;
+}
+
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
-                     void* psiB, int64_t ldB, hipStream_t stream) {
+                     void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream) {
     const bool dbl = p.dtype == HSF_C128;
     const size_t esz = dbl ? 16 : 8;
     const int pick = pick_schedule(p, n_paths);
+    // the path tree when it pays and the caller's workspace holds its levels
+    bool tree = use_tree(p, pick, n_paths);
+    TreeScratch tsc;
+    unsigned char* base = reinterpret_cast<unsigned char*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    if (tree) {
+        tsc = tree_scratch(p, n_paths);
+        tree = ws != nullptr && ws_bytes >= tsc.total;
+    }
     void* psi[2] = {psiA, psiB};
     const int64_t ld[2] = {ldA, ldB};
     const Schedule* sc[2];
-    int si[2];
-    size_t first[2] = {0, 0}, npass = 0;
+    const DeviceSchedule* dsc[2];
+    std::vector<Item> items[2];
+    size_t rounds = 0;
     for (int s = 0; s < 2; ++s) {
-        si[s] = std::min<int>(pick, (int)p.side[s].sched.size() - 1);
-        sc[s] = &p.side[s].sched[si[s]];
+        const std::vector<Schedule>& hv = tree ? p.side[s].tree : p.side[s].sched;
+        const std::vector<DeviceSchedule>& dv = tree ? d.tree[s] : d.side[s];
+        const size_t si = std::min<size_t>((size_t)pick, hv.size() - 1);
+        sc[s] = &hv[si];
+        dsc[s] = &dv[si];
+        if (!psi[s]) continue;
         // a side with a shared prefix state starts after its prefix passes
-        if (d.side[s][si[s]].prefix) first[s] = (size_t)sc[s]->n_prefix_passes;
-        if (psi[s]) npass = std::max(npass, sc[s]->passes.size() - first[s]);
+        items[s] = side_items(*sc[s], tree, dsc[s]->prefix, p_begin, n_paths, psi[s], ld[s],
+                              tree ? base + tsc.off[s][0] : nullptr, tree ? base + tsc.off[s][1] : nullptr,
+                              int64_t(1) << p.side[s].nq);
+        rounds = std::max(rounds, items[s].size());
     }
-    // paths per launch bounded so the grid stays below 2^31 workgroups
+    // rows per launch bounded so the grid stays below 2^31 workgroups
     int64_t tiles_max = 1;
     for (int s = 0; s < 2; ++s)
-        if (psi[s]) tiles_max = std::max<int64_t>(tiles_max, int64_t(1) << sc[s]->passes[first[s]].n_nonlocal);
-    const int64_t max_paths = std::max<int64_t>(1, (int64_t(1) << 29) / tiles_max);
-    for (size_t j = 0; j < npass; ++j) {
+        for (const Item& it : items[s]) tiles_max = std::max<int64_t>(tiles_max, int64_t(1) << sc[s]->passes[it.k].n_nonlocal);
+    const int64_t max_rows = std::max<int64_t>(1, (int64_t(1) << 29) / tiles_max);
+    for (size_t j = 0; j < rounds; ++j) {
         SideArgs a[2];
         std::memset(a, 0, sizeof(a));
+        const Item* it[2] = {nullptr, nullptr};
         uint32_t emax = 1;
-        size_t kk[2] = {first[0] + j, first[1] + j};
+        int64_t rows_max = 0;
         for (int s = 0; s < 2; ++s) {
-            const size_t k = kk[s];
-            if (!psi[s] || k >= sc[s]->passes.size()) continue;
-            const Pass& ps = sc[s]->passes[k];
-            const DeviceSchedule& ds = d.side[s][si[s]];
-            a[s].pass = reinterpret_cast<const Pass*>(ds.passes) + k;
-            a[s].ld = ld[s];
+            if (j >= items[s].size()) continue;
+            it[s] = &items[s][j];
+            const Item& m = *it[s];
+            const Pass& ps = sc[s]->passes[m.k];
+            const DeviceSchedule& ds = *dsc[s];
+            a[s].pass = reinterpret_cast<const Pass*>(ds.passes) + m.k;
+            a[s].psi = m.dst;
+            a[s].ld = m.dst_ld;
             a[s].ops = (const DevOp*)ds.ops;
             a[s].subs = ds.subs;
             a[s].pool = ds.pool;
             a[s].n_tiles = 1u << ps.n_nonlocal;
-            a[s].shared = (j == 0 && first[s] > 0) ? ds.prefix : nullptr;
+            a[s].p0 = p_begin;
+            a[s].S = m.S;
+            a[s].dst_lo = m.i_lo;
+            a[s].src = m.src;
+            a[s].src_ld = m.src_ld;
+            a[s].src_lo = m.src_lo;
+            a[s].S_par = m.S_par;
+            a[s].mode = m.mode;
             emax = std::max(emax, 1u << ps.n_local);
+            rows_max = std::max(rows_max, m.rows);
         }
         // group width: every group of a pass uses group_bits(L) bits (L = that side's tile)
         int kg = 4;
         for (int s = 0; s < 2; ++s)
-            if (a[s].pass) kg = std::min(kg, group_bits(sc[s]->passes[kk[s]].n_local));
+            if (a[s].pass) kg = std::min(kg, group_bits(sc[s]->passes[it[s]->k].n_local));
         bool kg_mixed = false;
         for (int s = 0; s < 2; ++s)
-            if (a[s].pass && group_bits(sc[s]->passes[kk[s]].n_local) != kg) kg_mixed = true;
+            if (a[s].pass && group_bits(sc[s]->passes[it[s]->k].n_local) != kg) kg_mixed = true;
         const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, emax >> kg));
         const size_t shmem = ((size_t)emax + 256) * esz;
-        for (int64_t p0 = 0; p0 < n_paths; p0 += max_paths) {
-            const int64_t np = std::min(max_paths, n_paths - p0);
+        for (int64_t r0 = 0; r0 < rows_max; r0 += max_rows) {
             SideArgs b[2] = {a[0], a[1]};
             for (int s = 0; s < 2; ++s) {
                 if (!b[s].pass) continue;
-                b[s].psi = (unsigned char*)psi[s] + (size_t)(p0 * ld[s]) * esz;
-                b[s].n_blocks = (uint32_t)(np * b[s].n_tiles);
+                const int64_t nr = std::max<int64_t>(0, std::min(max_rows, it[s]->rows - r0));
+                b[s].i_lo = it[s]->i_lo + r0;
+                b[s].n_blocks = (uint32_t)(nr * b[s].n_tiles);
+                if (nr == 0) b[s].pass = nullptr;
             }
             // a side with no pass this round contributes no workgroups
             const uint32_t total = b[0].n_blocks + b[1].n_blocks;
@@ -693,13 +836,14 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
                     c[1 - part].n_blocks = 0;
                     c[1 - part].pass = nullptr;
                     if (!c[part].pass) continue;
-                    kgp = group_bits(sc[part]->passes[kk[part]].n_local);
+                    kgp = group_bits(sc[part]->passes[it[part]->k].n_local);
                 }
                 const uint32_t tot = c[0].n_blocks + c[1].n_blocks;
+                if (tot == 0) continue;
                 bool s1 = false;
                 for (int q = 0; q < 2; ++q)
-                    if (c[q].pass && c[q].n_blocks) s1 |= sc[q]->passes[kk[q]].has_slot1 != 0;
-                hsf_status s = launch_pass(dbl, kgp, s1, tot, threads, shmem, stream, c[0], c[1], p_begin + p0);
+                    if (c[q].pass && c[q].n_blocks) s1 |= sc[q]->passes[it[q]->k].has_slot1 != 0;
+                hsf_status s = launch_pass(dbl, kgp, s1, tot, threads, shmem, stream, c[0], c[1]);
                 if (s != HSF_OK) return s;
             }
         }

@@ -78,10 +78,15 @@ def joint_blocked(circuit, cut=None):
     return out
 
 
+_TREE = {"auto": 0, "off": 1, "on": 2}
+
+
 def hsf_plan(circuit, cut=None, blocks=None, dtype="c64", rank_tol=1e-10, max_side_qubits=4, tile_qubits=0,
-             fuse=True):
+             fuse=True, tree="auto"):
     """Plan for `circuit` (a dict with n, gates[, cut, blocks]); returns the
-    opaque handle (int).  Raises HsfError with the library's status."""
+    opaque handle (int).  tree: path-tree sweeps "auto" (by the planner's
+    cost estimate), "off" or "on".  Raises HsfError with the library's
+    status."""
     lib = L.lib()
     cut = circuit["cut"] if cut is None else cut
     blocks = circuit.get("blocks", []) if blocks is None else blocks
@@ -90,7 +95,7 @@ def hsf_plan(circuit, cut=None, blocks=None, dtype="c64", rank_tol=1e-10, max_si
     offs = np.zeros(len(blocks) + 1, dtype=np.int64)
     offs[1:] = np.cumsum([len(b) for b in blocks]) if blocks else []
     opts = L.HsfPlanOptions(rank_tol=rank_tol, max_side_qubits=max_side_qubits, dtype=_DT[dtype],
-                            tile_qubits=tile_qubits, fuse=1 if fuse else 0)
+                            tile_qubits=tile_qubits, fuse=1 if fuse else 0, tree=_TREE[tree])
     h = ctypes.c_void_p()
     L.check(lib.hsf_plan(ctypes.byref(c), int(cut), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                          offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(blocks), ctypes.byref(opts),
@@ -104,8 +109,13 @@ def hsf_workspace_size(plan, op, n_paths, mode=0):
 
 
 def hsf_run_paths(plan, p_begin, p_end, psiA, psiB, ws=None):
-    """Half-states of paths [p_begin, p_end) into rows of psiA / psiB."""
+    """Half-states of paths [p_begin, p_end) into rows of psiA / psiB.  ws:
+    device workspace for the path-tree levels (allocated here when None)."""
     ref = psiA if psiA is not None else psiB
+    if ws is None and p_end > p_begin:
+        nbytes = hsf_workspace_size(plan, 0, p_end - p_begin, 0)
+        if nbytes > 0:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=ref.device)
     L.check(L.lib().hsf_run_paths(ctypes.c_void_p(plan), p_begin, p_end, _ptr(psiA),
                                   psiA.stride(0) if psiA is not None else 0, _ptr(psiB),
                                   psiB.stride(0) if psiB is not None else 0, _ptr(ws),
@@ -212,17 +222,31 @@ class Plan:
         return {"ops_logical": a.value, "ops_fused": b.value, "passes": c.value, "tile_qubits": d.value,
                 "ops_shared": e.value, "shared_passes": f.value}
 
+    def side_levels(self, side):
+        """Path-tree levels of a side: [(fused ops, states for all P paths)],
+        level 0 being the shared prefix."""
+        n = ctypes.c_int32()
+        L.check(L.lib().hsf_side_levels(ctypes.c_void_p(self.handle), side, 0, ctypes.byref(n), None, None))
+        ops = (ctypes.c_int64 * n.value)()
+        st = (ctypes.c_int64 * n.value)()
+        L.check(L.lib().hsf_side_levels(ctypes.c_void_p(self.handle), side, n.value, ctypes.byref(n), ops, st))
+        return [(int(ops[i]), int(st[i])) for i in range(n.value)]
+
+    def uses_tree(self, n_paths):
+        """Whether a sweep over n_paths paths runs level by level."""
+        return L.lib().hsf_uses_tree(ctypes.c_void_p(self.handle), int(n_paths)) == 1
+
     # ------------------------------------------------------------ device ----
     def alloc_halves(self, n_paths, device="cuda"):
         A = torch.empty((n_paths, 1 << self.na), dtype=self.torch_dtype, device=device)
         B = torch.empty((n_paths, 1 << self.nb), dtype=self.torch_dtype, device=device)
         return A, B
 
-    def run_paths(self, p_begin=0, p_end=None, psiA=None, psiB=None):
+    def run_paths(self, p_begin=0, p_end=None, psiA=None, psiB=None, ws=None):
         p_end = self.P if p_end is None else p_end
         if psiA is None and psiB is None:
             psiA, psiB = self.alloc_halves(p_end - p_begin)
-        hsf_run_paths(self.handle, p_begin, p_end, psiA, psiB)
+        hsf_run_paths(self.handle, p_begin, p_end, psiA, psiB, ws)
         return psiA, psiB
 
     def amplitudes_full(self, psiA, psiB, n_paths=None, rows=None, mode=None, out=None, accumulate=False,

@@ -141,6 +141,61 @@ def test_multi_pass_schedule_shapes():
             assert (st["passes"] == 1) == (tq >= 14)
 
 
+def test_path_tree_levels_by_hand():
+    """Levels of the path tree (hsf_side_levels): an op's level is the number
+    of leading digits its result depends on -- a slot of block k needs
+    k + 1, and an op follows every earlier op it does not commute with
+    (disjoint qubits, or both diagonal).  Derived by hand for this circuit
+    (no fusion): the two crossing CZ(1, 2) are blocks 0 and 1 (product form,
+    rank 2, diagonal slots on qubit 2 of side a and qubit 1 of side b)."""
+    g = cg.gate
+    gates = [g("H", (0,)), g("H", (1,)), g("H", (2,)), g("H", (3,)),   # level 0
+             g("CZ", (1, 2)),                 # block 0: slots at level 1
+             g("RX", (2,), 0.4, 0),           # a: dense after slot 0 on qubit 2 -> 1
+             g("H", (3,)),                    # a: disjoint from both slots -> 0
+             g("CZ", (1, 2)),                 # block 1: slots at level 2
+             g("RX", (0,), 0.5, 1),           # b: disjoint -> 0
+             g("RX", (1,), 0.6, 2),           # b: dense after slot 1 on qubit 1 -> 2
+             g("RZ", (2,), 0.7, 3)]           # a: diagonal; the level-2 slot on 2 is diagonal
+    #                                           and commutes, RX(2) at level 1 does not -> 1
+    c = cg.circuit("levels", 4, gates, 1, [[4], [7]])
+    p = Plan(c, fuse=False, tree="on")
+    assert p.P == 4
+    # side a: H2 H3 H3 | slot0 RX2 RZ2 | slot1 ; side b: H0 H1 RX0 | slot0 | slot1 RX1
+    assert p.side_levels(0) == [(3, 1), (3, 2), (1, 4)]
+    assert p.side_levels(1) == [(3, 1), (1, 2), (2, 4)]
+    assert p.side_stats(0)["ops_shared"] == 3 and p.side_stats(1)["ops_shared"] == 3
+
+
+def test_path_tree_options_and_invariants():
+    from paper_2502_06959_amd.hsf import hsf_workspace_size
+    c = cg.c3(seed=3, n=12, layers=8)
+    on, off, auto = Plan(c, tree="on"), Plan(c, tree="off"), Plan(c)
+    assert on.uses_tree(on.P) and not off.uses_tree(off.P)
+    assert hsf_workspace_size(on.handle, 0, on.P, 0) > 0 and hsf_workspace_size(off.handle, 0, off.P, 0) == 0
+    assert hsf_workspace_size(auto.handle, 0, auto.P, 0) == (hsf_workspace_size(on.handle, 0, on.P, 0)
+                                                             if auto.uses_tree(auto.P) else 0)
+    for s in (0, 1):
+        lv, st = on.side_levels(s), on.side_stats(s)
+        assert lv == off.side_levels(s)                 # levels are a property of the plan
+        assert sum(o for o, _ in lv) == st["ops_fused"] and lv[0] == (st["ops_shared"], 1)
+        states = [n for _, n in lv]
+        assert states[-1] == on.P and all(a < b for a, b in zip(states, states[1:]))
+        assert all(on.P % n == 0 for n in states)
+    # no blocks: one level, everything shared; the tree is never taken
+    g = Plan(cg.circuit("noblocks", 4, [cg.gate("H", (0,)), cg.gate("H", (3,))], 1, []), tree="on")
+    assert g.side_levels(0) == [(1, 1)] and not g.uses_tree(1)
+    # an out-of-range option is the caller's error
+    from paper_2502_06959_amd import hsf as H
+    H._TREE["bad"] = 3
+    try:
+        with pytest.raises(HsfError) as e:
+            Plan(c, tree="bad")
+        assert e.value.code == "HSF_E_ARG"
+    finally:
+        del H._TREE["bad"]
+
+
 def test_shared_prefix_hoists_commuting_ops():
     """Ops that commute with every factor slot before them (disjoint qubits,
     or both diagonal) join the prefix every path shares; ops that do not
