@@ -1051,10 +1051,12 @@ int pick_schedule(const Plan& p, int64_t n_paths) {
 
 namespace {
 
-// Rough cost of a sweep launch of W workgroups on one pass: the waves of
-// workgroups the chip runs (by LDS per workgroup) times the pass's work per
-// tile (register-group sub-ops, other device ops counted four each, and the
-// tile's load and store).
+// Rough cost of a sweep launch of W workgroups on one pass, in units of one
+// register-group sub-op on one tile: the workgroups run in waves (by LDS
+// per workgroup), each taking the pass's work per tile (sub-ops one each,
+// other device ops four each, its own load and store eight); the tiles'
+// trips through HBM add about 22 units per wave-full of tiles when every
+// compute unit streams at once.
 double pass_cost(const Schedule& sc, int k, int64_t wgs, size_t esz) {
     const Pass& ps = sc.passes[(size_t)k];
     double work = 8.0;
@@ -1065,7 +1067,7 @@ double pass_cost(const Schedule& sc, int k, int64_t wgs, size_t esz) {
     const size_t lds = ((size_t(1) << ps.n_local) + 256) * esz;
     const int64_t per_cu = std::max<int64_t>(1, (int64_t)((160u << 10) / lds));
     const int64_t slots = 256 * per_cu;
-    return (double)((wgs + slots - 1) / slots) * work;
+    return (double)((wgs + slots - 1) / slots) * work + 22.0 * (double)wgs / (double)slots;
 }
 
 }  // namespace
