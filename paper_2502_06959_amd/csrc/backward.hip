@@ -159,41 +159,70 @@ __global__ __launch_bounds__(256) void bw_apply2(typename Cx<T>::v* __restrict__
     }
 }
 
-// partial[row] = sum_y l[y] (Dg s)[y]   (FP64; one block per row, fixed order)
+// bw_apply2 for an op with an angle, and first, from the same loads,
+// partial[row * blocks_per_row + blk] = sum over the block's groups of
+// sum_y l[y] (Dg s)[y] (FP64, fixed-order reduction in the block): the
+// gradient term of the op's angle before the op is undone.
 template <int K, typename T>
-__global__ __launch_bounds__(256) void bw_grad_dot(const typename Cx<T>::v* __restrict__ s,
-                                                   const typename Cx<T>::v* __restrict__ l, int64_t ld, int nq,
-                                                   Bits bits, const typename Cx<T>::v* __restrict__ dg,
-                                                   double2* __restrict__ partial) {
+__global__ __launch_bounds__(256) void bw_apply2_grad(typename Cx<T>::v* __restrict__ s,
+                                                      typename Cx<T>::v* __restrict__ l, int64_t ld, int nq, Bits bits,
+                                                      const typename Cx<T>::v* __restrict__ ms,
+                                                      const typename Cx<T>::v* __restrict__ ml,
+                                                      const typename Cx<T>::v* __restrict__ dg,
+                                                      double2* __restrict__ partial, uint32_t blocks_per_row) {
     using V = typename Cx<T>::v;
     constexpr int D = 1 << K;
-    __shared__ V m[D * D];
+    __shared__ V m1[D * D], m2[D * D], m3[D * D];
     __shared__ double rr[256], ri[256];
-    for (int i = threadIdx.x; i < D * D; i += blockDim.x) m[i] = dg[i];
+    for (int i = threadIdx.x; i < D * D; i += blockDim.x) {
+        m1[i] = ms[i];
+        m2[i] = ml[i];
+        m3[i] = dg[i];
+    }
     __syncthreads();
-    const int64_t row = blockIdx.x;
-    const V* sr = s + row * ld;
-    const V* lr = l + row * ld;
+    const uint32_t row = blockIdx.x / blocks_per_row;
+    const uint32_t blk = blockIdx.x - row * blocks_per_row;
     const uint64_t groups = uint64_t(1) << (nq - K);
+    const uint64_t g = (uint64_t)blk * blockDim.x + threadIdx.x;
     double accr = 0.0, acci = 0.0;
-    for (uint64_t g = threadIdx.x; g < groups; g += blockDim.x) {
+    if (g < groups) {
         uint64_t idx[D];
         group_offsets<K>(bits, g, idx);
-        V v[D];
+        V* sr = s + (int64_t)row * ld;
+        V* lr = l + (int64_t)row * ld;
+        V vs[D], vl[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = sr[idx[j]];
+        for (int j = 0; j < D; ++j) {
+            vs[j] = sr[idx[j]];
+            vl[j] = lr[idx[j]];
+        }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             double tr = 0.0, ti = 0.0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const V t = cmul(m[i * D + j], v[j]);
+                const V t = cmul(m3[i * D + j], vs[j]);
                 tr += (double)t.x;
                 ti += (double)t.y;
             }
-            const V lv = lr[idx[i]];
-            accr += (double)lv.x * tr - (double)lv.y * ti;
-            acci += (double)lv.x * ti + (double)lv.y * tr;
+            accr += (double)vl[i].x * tr - (double)vl[i].y * ti;
+            acci += (double)vl[i].x * ti + (double)vl[i].y * tr;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            V as, al;
+            as.x = as.y = al.x = al.y = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const V t1 = cmul(m1[i * D + j], vs[j]);
+                const V t2 = cmul(m2[i * D + j], vl[j]);
+                as.x += t1.x;
+                as.y += t1.y;
+                al.x += t2.x;
+                al.y += t2.y;
+            }
+            sr[idx[i]] = as;
+            lr[idx[i]] = al;
         }
     }
     rr[threadIdx.x] = accr;
@@ -206,7 +235,7 @@ __global__ __launch_bounds__(256) void bw_grad_dot(const typename Cx<T>::v* __re
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[row] = make_double2(rr[0], ri[0]);
+    if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(rr[0], ri[0]);
 }
 
 template <typename T>
@@ -259,16 +288,18 @@ __global__ __launch_bounds__(256) void bw_cotangent(const typename Cx<T>::v* __r
     lam[(int64_t)row * ldl + gidx[g]] = v;
 }
 
-// grad[t] += sum over occurrences of t, over rows, of 2 Re partial[occ][row]
+// grad[t] += sum over occurrences o of t, over the rows x per_row[o] block
+// partials of o, of 2 Re partial[o][.]   (fixed order)
 __global__ void bw_reduce(const double2* __restrict__ partial, int64_t stride, int64_t rows,
-                          const int64_t* __restrict__ occ_off, const int64_t* __restrict__ occ, int64_t n_params,
-                          double* __restrict__ grad) {
+                          const int64_t* __restrict__ occ_off, const int64_t* __restrict__ occ,
+                          const int64_t* __restrict__ per_row, int64_t n_params, double* __restrict__ grad) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_params) return;
     double acc = 0.0;
     for (int64_t i = occ_off[t]; i < occ_off[t + 1]; ++i) {
         const double2* p = partial + occ[i] * stride;
-        for (int64_t r = 0; r < rows; ++r) acc += 2.0 * p[r].x;
+        const int64_t n = rows * per_row[occ[i]];
+        for (int64_t r = 0; r < n; ++r) acc += 2.0 * p[r].x;
     }
     grad[t] += acc;
 }
@@ -304,11 +335,18 @@ struct Layout {
     int64_t dimA, dimB;
     int ka, kb;            // checkpoints per side
     int64_t n_occ;         // parametrised ops outside blocks, both sides
+    int64_t per_row_max;   // block partials per path row, largest over those ops
     int64_t n_shift;       // shifted forward runs for angles inside blocks
     size_t table_elems, mat_elems, pool_elems;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workgroups per path row of the per-op adjoint kernels (one group of 2^k
+// amplitudes per thread, 256 threads).
+int64_t adj_blocks_per_row(int nq, int k) {
+    return std::max<int64_t>(1, ((int64_t(1) << (nq - k)) + 255) / 256);
+}
 
 size_t side_mat_elems(const SideProgram& sp) {
     size_t e = 0;
@@ -332,7 +370,12 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     L.n_occ = 0;
     for (int s = 0; s < 2; ++s)
         for (const SideOp& o : p.side[s].raw) L.n_occ += o.param_id >= 0;
-    L.table_elems = 2 * (size_t)(4 * nx + 1) + (size_t)(p.n_params + 1) + (size_t)L.n_occ;
+    // block partials per path row of the fused adjoint kernel, the most of any op with an angle
+    L.per_row_max = 1;
+    for (int s = 0; s < 2; ++s)
+        for (const SideOp& o : p.side[s].raw)
+            if (o.param_id >= 0) L.per_row_max = std::max(L.per_row_max, adj_blocks_per_row(s == 0 ? p.na : p.nb, o.k));
+    L.table_elems = 2 * (size_t)(4 * nx + 1) + (size_t)(p.n_params + 1) + 2 * (size_t)L.n_occ;
     L.mat_elems = side_mat_elems(p.side[0]) + side_mat_elems(p.side[1]);
     L.pool_elems = 0;
     for (int s = 0; s < 2; ++s)
@@ -358,7 +401,7 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     L.psi_x = take((size_t)nx * 16);
     L.psi_s = take((size_t)nx * 16);
     L.loss = take((size_t)std::max<int64_t>(4, L.n_shift) * sizeof(double));
-    L.partial = take((size_t)std::max<int64_t>(L.n_occ, 1) * chunk * 16);
+    L.partial = take((size_t)std::max<int64_t>(L.n_occ, 1) * chunk * L.per_row_max * 16);
     L.tables = take(L.table_elems * sizeof(int64_t));
     L.mats = take(L.mat_elems * esz);
     L.pools = take(L.pool_elems * (size_t)std::max<int64_t>(1, L.n_shift) * esz);
@@ -449,13 +492,14 @@ struct Runner {
         });
     }
 
-    hsf_status grad_dot(const V* s, const V* l, int64_t ld, int64_t rows, int nq, const SideOp& o, const V* dg,
-                        double2* partial) {
+    hsf_status apply2_grad(V* s, V* l, int64_t ld, int64_t rows, int nq, const SideOp& o, const V* ms, const V* ml,
+                           const V* dg, double2* partial) {
+        const uint32_t bpr = (uint32_t)adj_blocks_per_row(nq, o.k);
         return dispatch_k(o.k, [&](auto kk) {
             constexpr int K = decltype(kk)::value;
-            hipLaunchKernelGGL((bw_grad_dot<K, T>), dim3((uint32_t)rows), dim3(256), 0, st, s, l, ld, nq, bits_of(o),
-                               dg, partial);
-            return hip_check(hipGetLastError(), "bw_grad_dot launch");
+            hipLaunchKernelGGL((bw_apply2_grad<K, T>), dim3((uint32_t)(rows * bpr)), dim3(256), 0, st, s, l, ld, nq,
+                               bits_of(o), ms, ml, dg, partial, bpr);
+            return hip_check(hipGetLastError(), "bw_apply2_grad launch");
         });
     }
 
@@ -551,12 +595,20 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             for (int64_t q : per[t]) ht[occ_list + w++] = q;
         }
         ht[occ_off + p.n_params] = w;
+        // block partials per row of each occurrence
+        const size_t occ_rows = occ_list + (size_t)Lo.n_occ;
+        int64_t q = 0;
+        for (int side = 0; side < 2; ++side)
+            for (const SideOp& op : p.side[side].raw)
+                if (op.param_id >= 0) ht[occ_rows + q++] = adj_blocks_per_row(nq[side], op.k);
         if ((s = hip_check(hipMemcpyAsync(tables, ht.data(), ht.size() * sizeof(int64_t), hipMemcpyHostToDevice, st),
                            "upload tables")) != HSF_OK)
             return s;
     }
     const int64_t* occ_off_d = tables + 2 * (4 * nx + 1);
     const int64_t* occ_d = occ_off_d + p.n_params + 1;
+    const int64_t* occ_rows_d = occ_d + Lo.n_occ;
+    const int64_t pstride = chunk * Lo.per_row_max;
 
     // ---- matrices of the raw side programs
     std::vector<std::vector<OpMats>> om(2);
@@ -662,10 +714,15 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             for (size_t ii = raw.size(); ii-- > 0;) {
                 const SideOp& o = raw[ii];
                 if (o.param_id >= 0) {
+                    // angles sit on gates, never on factor slots
+                    if (o.kind == SideOp::SLOT) return fail(HSF_E_ARG, "internal: an angle on a factor slot");
+                    // the angle's term from the state and adjoint after the op, then the op undone
                     --oc;
-                    if ((s = R.grad_dot(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].dg,
-                                        partial + oc * chunk)) != HSF_OK)
+                    if ((s = R.apply2_grad(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].inv,
+                                           mats + om[side][ii].tr, mats + om[side][ii].dg, partial + oc * pstride)) !=
+                        HSF_OK)
                         return s;
+                    continue;
                 }
                 if (o.kind == SideOp::SLOT) {
                     --kc;
@@ -682,7 +739,7 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             (void)occ_side;
         }
         hipLaunchKernelGGL(bw_reduce, dim3(std::max<uint32_t>(1, (uint32_t)((p.n_params + 63) / 64))), dim3(64), 0, st,
-                           (const double2*)partial, chunk, np, occ_off_d, occ_d, p.n_params, grad);
+                           (const double2*)partial, pstride, np, occ_off_d, occ_d, occ_rows_d, p.n_params, grad);
         if ((s = hip_check(hipGetLastError(), "bw_reduce launch")) != HSF_OK) return s;
     }
 
