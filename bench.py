@@ -52,6 +52,22 @@ def _paths_ws(plan, n_paths):
     return torch.empty(nbytes, dtype=torch.uint8, device="cuda") if nbytes else None
 
 
+def _sweep_desc(plan, n_paths):
+    """How the sweeps over n_paths paths run: path tree or flat, tile sizes."""
+    tree, tiles = plan.sweep_form(n_paths)
+    return {"form": "path tree" if tree else "flat", "tile_qubits": list(tiles)}
+
+
+def _executed_ops(plan, side, n_paths):
+    """Fused ops a sweep over all n_paths paths applies on one side: once per
+    state of each path-tree level, or the shared prefix once and every
+    per-path op on every path."""
+    lv = plan.side_levels(side)
+    if plan.sweep_form(n_paths)[0]:
+        return sum(o * n for o, n in lv)
+    return lv[0][0] + n_paths * sum(o for o, _ in lv[1:])
+
+
 def _traffic_from_profiles(kernel, src_hash, workload):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE +
     WRITE_SIZE, copy-kernel calibrated), read from profiles/traffic.md if it
@@ -246,8 +262,7 @@ def main():
         # 256 CU x 64 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s); a one-qubit
         # gate costs 14 flop per amplitude
         # ops executed: the per-path ones on every path, the shared prefix once
-        ex_a = P * (sa["ops_fused"] - sa["ops_shared"]) + sa["ops_shared"]
-        ex_b = P * (sb["ops_fused"] - sb["ops_shared"]) + sb["ops_shared"]
+        ex_a, ex_b = _executed_ops(plan, 0, P), _executed_ops(plan, 1, P)
         fl = 14.0 * ((1 << na) * ex_a + (1 << nb) * ex_b)
         bound, peak, unit = "alu", 78.6, "TFLOP/s"
         achieved = fl / (sweep_ms * 1e-3) / 1e12
@@ -261,7 +276,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "paths": P, "n": plan.n, "cut": f"{nb}|{na}",
                    "path_sum": args.mode, "ops_logical": [sa["ops_logical"], sb["ops_logical"]],
-                   "ops_fused": [sa["ops_fused"], sb["ops_fused"]], "passes": [sa["passes"], sb["passes"]],
+                   "ops_fused": [sa["ops_fused"], sb["ops_fused"]], "sweep": _sweep_desc(plan, P),
                    # fused ops every path starts from (simulated once per plan and device)
                    "ops_shared": [sa["ops_shared"], sb["ops_shared"]]},
         "breakdown_ms": {"sweeps": sweep_ms, "path_sum": sum_ms, "plan_host": plan_s * 1e3},
@@ -368,7 +383,7 @@ def bench_c3(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "c64 (f32 sweeps, f64 reductions)", "data": "synthetic",
            "config": {"workload": "c3: n=30 cut 15|15, 12 layers RY/RZ + RZZ brick, 4 blocks of 3 crossing RZZ "
                                   "(P=256), 708 parameters, loss over 1024 bitstrings",
-                      "paths": plan.P, "params": plan.n_params,
+                      "paths": plan.P, "params": plan.n_params, "sweep": _sweep_desc(plan, plan.P),
                       "ops_logical": [sa["ops_logical"], sb["ops_logical"]]},
            "forward_loss_ms": ms_loss, "error_vs_oracle": err}
     print(json.dumps(res), flush=True)
@@ -442,7 +457,8 @@ def bench_c4(args):
            "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": sw + ps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": mode, "data": "synthetic",
            "config": {"workload": "c4: n=34 cut 17|17 depth-24 Haar+CZ brickwork, 6 joint blocks of rank 4 "
-                                  "(P=4096), all 2^34 amplitudes in 2^13-row tiles", "path_sum": mode},
+                                  "(P=4096), all 2^34 amplitudes in 2^13-row tiles", "path_sum": mode,
+                      "sweep": _sweep_desc(plan, plan.P)},
            "breakdown_ms": {"sweeps": sw, "path_sum": ps},
            "sweep_updates_per_s": logical / (sw * 1e-3),
            "mfma_frac_of_mode_peak": flops / (ps * 1e-3) / 1e12 / peak,

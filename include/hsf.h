@@ -215,9 +215,13 @@ hsf_status hsf_side_stats(hsf_plan_t plan, int32_t side, int64_t* ops_logical,
  * Any output pointer may be NULL.                                              */
 hsf_status hsf_side_levels(hsf_plan_t plan, int32_t side, int32_t cap, int32_t* n_levels, int64_t* ops,
                            int64_t* states);
-/* 1 if hsf_run_paths over n_paths paths sweeps level by level (path tree),
- * 0 if every path runs every per-path op, -1 for a null plan.                */
-int32_t hsf_uses_tree(hsf_plan_t plan, int64_t n_paths);
+/* How hsf_run_paths sweeps a chunk of n_paths paths (given the workspace
+ * hsf_workspace_size(plan, 0, n_paths, 0)): tree receives 1 for level by
+ * level (path tree), 0 if every path runs every per-path op; tile_qubits
+ * (2 entries, side a and b) the LDS tile sizes.  The planner takes the form
+ * and tile size with the lowest timing estimate (or the form the plan's
+ * option forces).  Either pointer may be NULL.                              */
+hsf_status hsf_sweep_form(hsf_plan_t plan, int64_t n_paths, int32_t* tree, int32_t* tile_qubits);
 
 /* --------------------------------------------------------------- paths ---- */
 

@@ -61,7 +61,7 @@ SIGNATURES = {
     "hsf_side_stats": (c_int32, [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int32), P(c_int32), P(c_int64),
                                  P(c_int32)]),
     "hsf_side_levels": (c_int32, [c_void_p, c_int32, c_int32, P(c_int32), P(c_int64), P(c_int64)]),
-    "hsf_uses_tree": (c_int32, [c_void_p, c_int64]),
+    "hsf_sweep_form": (c_int32, [c_void_p, c_int64, P(c_int32), P(c_int32)]),
     "hsf_workspace_size": (c_size_t, [c_void_p, c_int32, c_int64, c_int32]),
     "hsf_run_paths": (c_int32, [c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                 c_size_t, c_void_p]),

@@ -171,10 +171,18 @@ hsf_status hsf_side_levels(hsf_plan_t plan, int32_t side, int32_t cap, int32_t* 
     return HSF_OK;
 }
 
-int32_t hsf_uses_tree(hsf_plan_t plan, int64_t n_paths) {
-    if (!plan) return -1;
+hsf_status hsf_sweep_form(hsf_plan_t plan, int64_t n_paths, int32_t* tree, int32_t* tile_qubits) {
+    if (!plan) return fail(HSF_E_ARG, "null plan");
+    if (n_paths <= 0) return fail(HSF_E_ARG, "n_paths must be positive");
     const Plan* p = P_(plan);
-    return use_tree(*p, pick_schedule(*p, n_paths), n_paths) ? 1 : 0;
+    const SweepChoice ch = choose_sweep(*p, n_paths);
+    if (tree) *tree = ch.tree ? 1 : 0;
+    if (tile_qubits)
+        for (int s = 0; s < 2; ++s) {
+            const std::vector<Schedule>& v = ch.tree ? p->side[s].tree : p->side[s].sched;
+            tile_qubits[s] = v[std::min<size_t>((size_t)ch.sched, v.size() - 1)].tile_bits;
+        }
+    return HSF_OK;
 }
 
 size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t mode) {

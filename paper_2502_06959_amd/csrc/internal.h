@@ -298,8 +298,14 @@ std::vector<SideOp> level_order(const Plan& p, int side, std::vector<int>& cuts,
 // TreeLevel with S from `levels`.
 Schedule schedule_side(const Plan& p, int side, int tile_bits, const std::vector<SideOp>& ops,
                        const std::vector<int>& cuts, const std::vector<int>& levels, bool tree);
-// Whether run_sides takes the path-tree schedules for this launch shape.
-bool use_tree(const Plan& p, int pick, int64_t n_paths);
+// The sweep form and tile schedule run_sides takes for a chunk of n_paths
+// paths: the path tree or the flat sweep (as the plan's option allows) and
+// the candidate tile size, whichever a timing estimate puts lowest.
+struct SweepChoice {
+    bool tree = false;
+    int sched = 0;      // index into SideProgram::sched / tree (clamped per side)
+};
+SweepChoice choose_sweep(const Plan& p, int64_t n_paths, bool allow_tree = true);
 // Index of the schedule used for a launch over n_paths paths.
 int pick_schedule(const Plan& p, int64_t n_paths);
 

@@ -515,7 +515,7 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
         const int tmax = p->tile_req > 0 ? p->tile_req : max_tile_bits(p->dtype);
         // candidate tile sizes, largest first (a requested size is the only one)
         const int top = std::min(tmax, nq);
-        const int bottom = p->tile_req > 0 ? top : std::max(std::min(nq, 8), top - 3);
+        const int bottom = p->tile_req > 0 ? top : std::max(std::min(nq, 8), top - 4);
         const std::vector<int> flat_cuts = {0, p->side[s].n_prefix, (int)p->side[s].ops.size()};
         for (int L = top; L >= bottom; --L)
             p->side[s].sched.push_back(schedule_side(*p, s, L, p->side[s].ops, flat_cuts, {}, false));
@@ -1051,48 +1051,100 @@ int pick_schedule(const Plan& p, int64_t n_paths) {
 
 namespace {
 
-// Rough cost of a sweep launch of W workgroups on one pass, in units of one
-// register-group sub-op on one tile: the workgroups run in waves (by LDS
-// per workgroup), each taking the pass's work per tile (sub-ops one each,
-// other device ops four each, its own load and store eight); the tiles'
-// trips through HBM add about 22 units per wave-full of tiles when every
-// compute unit streams at once.
-double pass_cost(const Schedule& sc, int k, int64_t wgs, size_t esz) {
+// Estimated time (ns) of a chunk of sweeps.  A pass costs each workgroup
+// about 2^L x (its work) x 0.13 ns on an L-qubit tile: every register group
+// is one round trip of the tile through LDS and every sub-op one sweep of
+// the VALU over it, a dense k-qubit op about 2^k of those, the tile's load
+// and store about six (constants fitted to MI355X timings of the c2p, C2
+// and C3 sweeps at tile sizes 9..14).  The workgroups of both sides share
+// 256 compute units: a round of launches takes the larger of its total work
+// spread over them and one workgroup's own time, plus about 4 us to launch.
+struct PassRun {
+    const Schedule* sc;
+    int k;
+    int64_t rows;
+};
+
+double pass_ns(const Schedule& sc, int k) {
     const Pass& ps = sc.passes[(size_t)k];
-    double work = 8.0;
+    double work = 6.0;
     for (int32_t i = ps.op_begin; i < ps.op_end; ++i) {
         const DevOp& d = sc.devops[(size_t)i];
-        work += d.type == DOP_GROUP ? (double)d.rank : 4.0;
+        work += d.type == DOP_GROUP ? 1.0 + (double)d.rank : 1.0 + (double)(1 << d.k);
     }
-    const size_t lds = ((size_t(1) << ps.n_local) + 256) * esz;
-    const int64_t per_cu = std::max<int64_t>(1, (int64_t)((160u << 10) / lds));
-    const int64_t slots = 256 * per_cu;
-    return (double)((wgs + slots - 1) / slots) * work + 22.0 * (double)wgs / (double)slots;
+    return std::ldexp(work * 0.13, ps.n_local);
+}
+
+// Throughput penalty of a tile size when the chip is full: fewer waves per
+// SIMD hide less of each group's LDS latency.  Waves per SIMD from the
+// workgroups the LDS admits per compute unit (at most 6 waves, the sweep
+// kernels' register occupancy); measured on MI355X (C4 and the q33-3 QAOA
+// shape, path-tree sweeps): 2 waves 2x slower than 6, 4 waves 1.2x.
+double occupancy_penalty(int L, size_t esz) {
+    const int64_t E = int64_t(1) << L;
+    const int64_t threads = std::min<int64_t>(512, std::max<int64_t>(64, E >> group_bits(L)));
+    const int64_t wg_per_cu = std::max<int64_t>(1, (int64_t)((160u << 10) / (((size_t)E + 256) * esz)));
+    const int64_t waves = std::min<int64_t>(6, wg_per_cu * (threads / 64) / 4);
+    return waves <= 2 ? 2.0 : waves <= 4 ? 1.2 : 1.0;
+}
+
+std::vector<PassRun> side_runs(const Schedule& sc, bool tree, int64_t n) {
+    std::vector<PassRun> v;
+    if (!tree) {
+        for (size_t k = (size_t)sc.n_prefix_passes; k < sc.passes.size(); ++k) v.push_back({&sc, (int)k, n});
+        return v;
+    }
+    for (const TreeLevel& tl : sc.levels)
+        for (int k = tl.pass_begin; k < tl.pass_end; ++k) v.push_back({&sc, k, (n - 1) / tl.S + 1});
+    return v;
+}
+
+double sweep_ns(const Plan& p, bool tree, size_t i, int64_t n) {
+    const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
+    std::vector<PassRun> runs[2];
+    for (int s = 0; s < 2; ++s) {
+        const std::vector<Schedule>& v = tree ? p.side[s].tree : p.side[s].sched;
+        runs[s] = side_runs(v[std::min(i, v.size() - 1)], tree, n);
+    }
+    double t = 0;
+    for (size_t j = 0; j < std::max(runs[0].size(), runs[1].size()); ++j) {
+        double spread = 0, one = 0;
+        for (int s = 0; s < 2; ++s) {
+            if (j >= runs[s].size()) continue;
+            const PassRun& r = runs[s][j];
+            const double c = pass_ns(*r.sc, r.k);
+            const Pass& ps = r.sc->passes[(size_t)r.k];
+            spread += (double)(r.rows << ps.n_nonlocal) * c * occupancy_penalty(ps.n_local, esz) / 256.0;
+            one = std::max(one, c);
+        }
+        t += 4000.0 + std::max(spread, one);
+    }
+    return t;
 }
 
 }  // namespace
 
-bool use_tree(const Plan& p, int pick, int64_t n_paths) {
-    if (p.tree_mode == 1 || n_paths <= 0) return false;
-    for (int s = 0; s < 2; ++s)
-        if (p.side[s].tree.empty()) return false;
-    if (p.tree_mode == 2) return true;
-    const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
-    double flat = 0, tree = 0;
-    for (int s = 0; s < 2; ++s) {
-        const Schedule& f = p.side[s].sched[std::min<size_t>((size_t)pick, p.side[s].sched.size() - 1)];
-        const Schedule& t = p.side[s].tree[std::min<size_t>((size_t)pick, p.side[s].tree.size() - 1)];
-        for (size_t k = (size_t)f.n_prefix_passes; k < f.passes.size(); ++k)
-            flat += pass_cost(f, (int)k, n_paths << f.passes[k].n_nonlocal, esz);
-        // a chunk of n_paths consecutive paths holds about n_paths / S + 1
-        // states of a level
-        for (const TreeLevel& tl : t.levels) {
-            const int64_t rows = std::min<int64_t>(n_paths, n_paths / tl.S + 1);
-            for (int k = tl.pass_begin; k < tl.pass_end; ++k)
-                tree += pass_cost(t, k, rows << t.passes[(size_t)k].n_nonlocal, esz);
+SweepChoice choose_sweep(const Plan& p, int64_t n_paths, bool allow_tree) {
+    SweepChoice best;
+    best.tree = false;
+    best.sched = pick_schedule(p, n_paths);
+    if (n_paths <= 0) return best;
+    const bool have_tree = allow_tree && !p.side[0].tree.empty() && !p.side[1].tree.empty() && p.tree_mode != 1;
+    const bool have_flat = !(have_tree && p.tree_mode == 2);
+    const size_t nc = std::max(p.side[0].sched.size(), p.side[1].sched.size());
+    double t_best = -1;
+    for (int tree = 0; tree < 2; ++tree) {
+        if ((tree && !have_tree) || (!tree && !have_flat)) continue;
+        for (size_t i = 0; i < nc; ++i) {
+            const double t = sweep_ns(p, tree != 0, i, n_paths);
+            if (t_best < 0 || t < t_best) {
+                t_best = t;
+                best.tree = tree != 0;
+                best.sched = (int)i;
+            }
         }
     }
-    return tree < 0.9 * flat;
+    return best;
 }
 
 }  // namespace hsf

@@ -736,7 +736,7 @@ std::vector<Item> side_items(const Schedule& sc, bool tree, const void* prefix, 
 }  // namespace
 
 size_t tree_workspace(const Plan& p, int64_t n_paths) {
-    if (n_paths <= 0 || !use_tree(p, pick_schedule(p, n_paths), n_paths)) return 0;
+    if (n_paths <= 0 || !choose_sweep(p, n_paths).tree) return 0;
     return tree_scratch(p, n_paths).total;
 }
 
@@ -744,15 +744,16 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
                      void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream) {
     const bool dbl = p.dtype == HSF_C128;
     const size_t esz = dbl ? 16 : 8;
-    const int pick = pick_schedule(p, n_paths);
     // the path tree when it pays and the caller's workspace holds its levels
-    bool tree = use_tree(p, pick, n_paths);
+    SweepChoice ch = choose_sweep(p, n_paths);
     TreeScratch tsc;
     unsigned char* base = reinterpret_cast<unsigned char*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
-    if (tree) {
+    if (ch.tree) {
         tsc = tree_scratch(p, n_paths);
-        tree = ws != nullptr && ws_bytes >= tsc.total;
+        if (ws == nullptr || ws_bytes < tsc.total) ch = choose_sweep(p, n_paths, false);
     }
+    const bool tree = ch.tree;
+    const int pick = ch.sched;
     void* psi[2] = {psiA, psiB};
     const int64_t ld[2] = {ldA, ldB};
     const Schedule* sc[2];

@@ -232,9 +232,16 @@ class Plan:
         L.check(L.lib().hsf_side_levels(ctypes.c_void_p(self.handle), side, n.value, ctypes.byref(n), ops, st))
         return [(int(ops[i]), int(st[i])) for i in range(n.value)]
 
+    def sweep_form(self, n_paths):
+        """(tree, (tile qubits a, b)) of a sweep over n_paths paths."""
+        t = ctypes.c_int32()
+        q = (ctypes.c_int32 * 2)()
+        L.check(L.lib().hsf_sweep_form(ctypes.c_void_p(self.handle), int(n_paths), ctypes.byref(t), q))
+        return t.value == 1, (q[0], q[1])
+
     def uses_tree(self, n_paths):
         """Whether a sweep over n_paths paths runs level by level."""
-        return L.lib().hsf_uses_tree(ctypes.c_void_p(self.handle), int(n_paths)) == 1
+        return self.sweep_form(n_paths)[0]
 
     # ------------------------------------------------------------ device ----
     def alloc_halves(self, n_paths, device="cuda"):

@@ -185,6 +185,19 @@ def test_path_tree_options_and_invariants():
     # no blocks: one level, everything shared; the tree is never taken
     g = Plan(cg.circuit("noblocks", 4, [cg.gate("H", (0,)), cg.gate("H", (3,))], 1, []), tree="on")
     assert g.side_levels(0) == [(1, 1)] and not g.uses_tree(1)
+    # the sweep form: a candidate tile size of the plan (12-qubit sides: 12
+    # down to 8); a forced form and tile size are kept
+    w = cg.c3(seed=3, n=24, layers=4)
+    for mode in ("on", "off", "auto"):
+        plan = Plan(w, tree=mode)
+        tree, tiles = plan.sweep_form(plan.P)
+        assert tree == plan.uses_tree(plan.P) and tree == (mode != "off" and (mode == "on" or tree))
+        assert all(8 <= t <= 12 for t in tiles)
+    one = Plan(w, tile_qubits=9, tree="on")
+    assert one.sweep_form(one.P) == (True, (9, 9))
+    assert on.sweep_form(on.P)[1] == (6, 6)                 # 6-qubit sides: one tile
+    with pytest.raises(HsfError):
+        on.sweep_form(0)
     # an out-of-range option is the caller's error
     from paper_2502_06959_amd import hsf as H
     H._TREE["bad"] = 3
