@@ -23,7 +23,9 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, 
 # inside their op loops; by default LLVM structurizes uniform regions too,
 # which inserts register copies of the amplitude array at every merge.
 FILE_FLAGS = {"sweep.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
-CXX_FLAGS = ["-O3", "-std=c++17", "-pthread", "-fPIC", "-I", INC, "-I", SRC, "-D__HIP_PLATFORM_AMD__",
+# complex products and quotients without the C99 inf/NaN recovery (the
+# planner's values are O(1)): inline arithmetic, 2.3x faster host SVDs
+CXX_FLAGS = ["-O3", "-fcx-limited-range", "-std=c++17", "-pthread", "-fPIC", "-I", INC, "-I", SRC, "-D__HIP_PLATFORM_AMD__",
              "-I", "/opt/rocm/include", "-Wall", "-Wno-unused-result"]
 
 

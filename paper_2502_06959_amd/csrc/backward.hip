@@ -289,19 +289,26 @@ __global__ __launch_bounds__(256) void bw_cotangent(const typename Cx<T>::v* __r
 }
 
 // grad[t] += sum over occurrences o of t, over the rows x per_row[o] block
-// partials of o, of 2 Re partial[o][.]   (fixed order)
-__global__ void bw_reduce(const double2* __restrict__ partial, int64_t stride, int64_t rows,
-                          const int64_t* __restrict__ occ_off, const int64_t* __restrict__ occ,
-                          const int64_t* __restrict__ per_row, int64_t n_params, double* __restrict__ grad) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_params) return;
+// partials of o, of 2 Re partial[o][.]: one workgroup per angle, each
+// thread a strided share, then a fixed-order tree (bitwise reproducible)
+__global__ __launch_bounds__(256) void bw_reduce(const double2* __restrict__ partial, int64_t stride, int64_t rows,
+                                                 const int64_t* __restrict__ occ_off, const int64_t* __restrict__ occ,
+                                                 const int64_t* __restrict__ per_row, double* __restrict__ grad) {
+    __shared__ double r[256];
+    const int64_t t = blockIdx.x;
     double acc = 0.0;
     for (int64_t i = occ_off[t]; i < occ_off[t + 1]; ++i) {
         const double2* p = partial + occ[i] * stride;
         const int64_t n = rows * per_row[occ[i]];
-        for (int64_t r = 0; r < n; ++r) acc += 2.0 * p[r].x;
+        for (int64_t e = threadIdx.x; e < n; e += 256) acc += p[e].x;
     }
-    grad[t] += acc;
+    r[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[t] += 2.0 * r[0];
 }
 
 __global__ void bw_zero_doubles(double* __restrict__ a, int64_t n) {
@@ -670,11 +677,15 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
         for (int i = 0; i < 4; ++i) gt[side][i] = tables + toff[side][i];
     for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
         const int64_t np = std::min(chunk, p.P - p0);
-        // forward, one op per launch, with a checkpoint in front of every factor slot
+        // forward replay with a checkpoint in front of every factor slot: the
+        // runs of ops between slots as LDS passes (their segment schedules),
+        // each slot as one launch
         for (int side = 0; side < 2; ++side) {
             if ((s = R.fill(vS[side], dim[side], dim[side], np, 1)) != HSF_OK) return s;
             int kc = 0;
-            const auto& raw = p.side[side].raw;
+            size_t sg = 0;
+            const SideProgram& sp = p.side[side];
+            const auto& raw = sp.raw;
             for (size_t i = 0; i < raw.size(); ++i) {
                 const SideOp& o = raw[i];
                 if (o.kind == SideOp::SLOT) {
@@ -684,6 +695,10 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
                     if ((s = R.copy_rows(vS[side], dim[side], c, dim[side], dim[side], np)) != HSF_OK) return s;
                     ++kc;
                     s = R.apply(vS[side], dim[side], np, nq[side], o, mats + om[side][i].fwd, o.rank, o.stride, p0);
+                } else if (sg < sp.seg.size() && (size_t)sp.seg_lo[sg] == i) {
+                    s = run_segment(p, d.seg[side][sg], sp.seg[sg], vS[side], dim[side], np, st);
+                    i = (size_t)sp.seg_hi[sg] - 1;
+                    ++sg;
                 } else {
                     s = R.apply(vS[side], dim[side], np, nq[side], o, mats + om[side][i].fwd, 1, 1, p0);
                 }
@@ -738,9 +753,11 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             }
             (void)occ_side;
         }
-        hipLaunchKernelGGL(bw_reduce, dim3(std::max<uint32_t>(1, (uint32_t)((p.n_params + 63) / 64))), dim3(64), 0, st,
-                           (const double2*)partial, pstride, np, occ_off_d, occ_d, occ_rows_d, p.n_params, grad);
-        if ((s = hip_check(hipGetLastError(), "bw_reduce launch")) != HSF_OK) return s;
+        if (p.n_params > 0) {
+            hipLaunchKernelGGL(bw_reduce, dim3((uint32_t)p.n_params), dim3(256), 0, st, (const double2*)partial, pstride,
+                               np, occ_off_d, occ_d, occ_rows_d, grad);
+            if ((s = hip_check(hipGetLastError(), "bw_reduce launch")) != HSF_OK) return s;
+        }
     }
 
     // ---- angles inside blocks: parameter shift on the re-factored block

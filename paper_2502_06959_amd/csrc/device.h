@@ -17,6 +17,10 @@ constexpr size_t kNormWsDoubles = 8192;
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
                      void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream);
 size_t tree_workspace(const Plan& p, int64_t n_paths);
+// The passes of one flat schedule without factor slots over rows 0 .. rows-1
+// of psi (ld elements apart), in place.
+hsf_status run_segment(const Plan& p, const DeviceSchedule& ds, const Schedule& sc, void* psi, int64_t ld, int64_t rows,
+                       hipStream_t stream);
 
 size_t bf16x3_workspace(int na, int nb, int64_t n_paths);
 

@@ -189,6 +189,11 @@ struct SideProgram {
     // the same tile sizes as path-tree schedules (empty when the plan has
     // no blocks); ops reordered by level, see level_order
     std::vector<Schedule> tree;
+    // the gradient's forward replay of `raw`: one flat schedule per run of
+    // raw ops between factor slots, raw[seg_lo[i] .. seg_hi[i]) (plans with
+    // angles only)
+    std::vector<Schedule> seg;
+    std::vector<int> seg_lo, seg_hi;
 };
 
 // One (circuit, side) segment of a batched sweep launch (device table).
@@ -235,6 +240,7 @@ struct DeviceCopy {
     int device = -1;
     std::vector<DeviceSchedule> side[2];
     std::vector<DeviceSchedule> tree[2];   // the sides' path-tree schedules
+    std::vector<DeviceSchedule> seg[2];    // the gradient's replay segments
 };
 
 struct Plan {

@@ -519,6 +519,24 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
         const std::vector<int> flat_cuts = {0, p->side[s].n_prefix, (int)p->side[s].ops.size()};
         for (int L = top; L >= bottom; --L)
             p->side[s].sched.push_back(schedule_side(*p, s, L, p->side[s].ops, flat_cuts, {}, false));
+        // replay segments of the raw program for gradients, on one tile size
+        // that suits many rows (12 qubits, or the whole side)
+        if (p->n_params > 0) {
+            const std::vector<SideOp>& raw = p->side[s].raw;
+            const int n = (int)raw.size();
+            for (int lo = 0; lo < n;) {
+                if (raw[lo].kind == SideOp::SLOT) {
+                    ++lo;
+                    continue;
+                }
+                int hi = lo;
+                while (hi < n && raw[hi].kind != SideOp::SLOT) ++hi;
+                p->side[s].seg.push_back(schedule_side(*p, s, std::min(12, tmax), raw, {lo, lo, hi}, {}, false));
+                p->side[s].seg_lo.push_back(lo);
+                p->side[s].seg_hi.push_back(hi);
+                lo = hi;
+            }
+        }
         if (!p->blocks.empty()) {
             std::vector<int> cuts, levels;
             const std::vector<SideOp> lops = level_order(*p, s, cuts, levels);

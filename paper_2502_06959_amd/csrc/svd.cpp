@@ -22,19 +22,30 @@ void jacobi_tall(int m, int n, const std::vector<cd>& A, std::vector<cd>& U,
     for (int j = 0; j < n; ++j) V[(size_t)j * n + j] = 1.0;
 
     const double eps = 1e-15;
+    // squared column norms, kept current through the rotations
+    std::vector<double> n2(n);
+    auto col_norm2 = [&](int j) {
+        double acc = 0;
+        for (int r = 0; r < m; ++r) acc += std::norm(a[(size_t)j * m + r]);
+        return acc;
+    };
     for (int sweep = 0; sweep < 80; ++sweep) {
         bool rotated = false;
+        double top = 0;
+        for (int j = 0; j < n; ++j) top = std::max(top, n2[j] = col_norm2(j));
+        // a column below 1e-16 of the largest holds a singular value far
+        // under any rank tolerance, and rotating it against another changes
+        // that one by less than rounding: such pairs are left alone (a block
+        // operator of Schmidt rank r has all but r columns go to zero)
+        const double tiny = top * 1e-32;
         for (int i = 0; i < n - 1; ++i) {
             cd* ci = &a[(size_t)i * m];
             for (int j = i + 1; j < n; ++j) {
+                if (n2[i] <= tiny || n2[j] <= tiny) continue;
                 cd* cj = &a[(size_t)j * m];
-                double alpha = 0, beta = 0;
+                const double alpha = n2[i], beta = n2[j];
                 cd gamma = 0;
-                for (int r = 0; r < m; ++r) {
-                    alpha += std::norm(ci[r]);
-                    beta += std::norm(cj[r]);
-                    gamma += std::conj(ci[r]) * cj[r];
-                }
+                for (int r = 0; r < m; ++r) gamma += std::conj(ci[r]) * cj[r];
                 const double g = std::abs(gamma);
                 if (g == 0.0 || g <= eps * std::sqrt(alpha * beta)) continue;
                 rotated = true;
@@ -50,6 +61,8 @@ void jacobi_tall(int m, int n, const std::vector<cd>& A, std::vector<cd>& U,
                     ci[r] = cs * x - sn * y;
                     cj[r] = sn * x + cs * y;
                 }
+                n2[i] = col_norm2(i);
+                n2[j] = col_norm2(j);
                 cd* vi = &V[(size_t)i * n];
                 cd* vj = &V[(size_t)j * n];
                 for (int r = 0; r < n; ++r) {

@@ -536,9 +536,9 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
     DeviceCopy& d = p.dev.back();
     d.device = dev;
     for (int side = 0; side < 2; ++side)
-        for (int tr = 0; tr < 2; ++tr)
-            for (const Schedule& sc : tr ? p.side[side].tree : p.side[side].sched) {
-                std::vector<DeviceSchedule>& v = tr ? d.tree[side] : d.side[side];
+        for (int tr = 0; tr < 3; ++tr)
+            for (const Schedule& sc : tr == 2 ? p.side[side].seg : tr ? p.side[side].tree : p.side[side].sched) {
+                std::vector<DeviceSchedule>& v = tr == 2 ? d.seg[side] : tr ? d.tree[side] : d.side[side];
                 v.emplace_back();
                 s = p.dtype == HSF_C128 ? upload_schedule<double>(sc, v.back()) : upload_schedule<float>(sc, v.back());
                 if (s != HSF_OK) {
@@ -589,8 +589,8 @@ void release_device(Plan& p) {
     for (DeviceCopy& d : p.dev) {
         (void)hipSetDevice(d.device);
         for (int side = 0; side < 2; ++side)
-            for (int tr = 0; tr < 2; ++tr)
-                for (DeviceSchedule& ds : tr ? d.tree[side] : d.side[side])
+            for (int tr = 0; tr < 3; ++tr)
+                for (DeviceSchedule& ds : tr == 2 ? d.seg[side] : tr ? d.tree[side] : d.side[side])
                     for (void* q : {ds.passes, ds.ops, ds.subs, ds.pool, ds.prefix})
                         if (q) (void)hipFree(q);
     }
@@ -647,6 +647,40 @@ void batch_sweep_prepare() {
                            (const void*)sweep_batch<float, 3, true>, (const void*)sweep_batch<float, 4, true>})
         (void)hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     done = true;
+}
+
+hsf_status run_segment(const Plan& p, const DeviceSchedule& ds, const Schedule& sc, void* psi, int64_t ld, int64_t rows,
+                       hipStream_t stream) {
+    const bool dbl = p.dtype == HSF_C128;
+    const size_t esz = dbl ? 16 : 8;
+    for (size_t k = 0; k < sc.passes.size(); ++k) {
+        const Pass& ps = sc.passes[k];
+        SideArgs a, b;
+        std::memset(&a, 0, sizeof(a));
+        std::memset(&b, 0, sizeof(b));
+        a.pass = reinterpret_cast<const Pass*>(ds.passes) + k;
+        a.psi = psi;
+        a.ld = ld;
+        a.ops = (const DevOp*)ds.ops;
+        a.subs = ds.subs;
+        a.pool = ds.pool;
+        a.n_tiles = 1u << ps.n_nonlocal;
+        a.S = 1;             // rows 0 .. rows-1 in place (no factor slots: digits unused)
+        a.mode = ROW_INPLACE;
+        const uint32_t E = 1u << ps.n_local;
+        const int kg = group_bits(ps.n_local);
+        const int threads = (int)std::min<uint32_t>(512u, std::max<uint32_t>(64u, E >> kg));
+        const int64_t max_rows = std::max<int64_t>(1, (int64_t(1) << 29) / a.n_tiles);
+        for (int64_t r0 = 0; r0 < rows; r0 += max_rows) {
+            SideArgs c = a;
+            c.psi = (unsigned char*)psi + (size_t)(r0 * ld) * esz;
+            c.n_blocks = (uint32_t)(std::min(max_rows, rows - r0) * a.n_tiles);
+            hsf_status s = launch_pass(dbl, kg, ps.has_slot1 != 0, c.n_blocks, threads, ((size_t)E + 256) * esz, stream,
+                                       c, b);
+            if (s != HSF_OK) return s;
+        }
+    }
+    return HSF_OK;
 }
 
 namespace {
