@@ -515,7 +515,7 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
         const int tmax = p->tile_req > 0 ? p->tile_req : max_tile_bits(p->dtype);
         // candidate tile sizes, largest first (a requested size is the only one)
         const int top = std::min(tmax, nq);
-        const int bottom = p->tile_req > 0 ? top : std::max(std::min(nq, 8), top - 4);
+        const int bottom = p->tile_req > 0 ? top : std::max(std::min(nq, 8), top - 5);
         const std::vector<int> flat_cuts = {0, p->side[s].n_prefix, (int)p->side[s].ops.size()};
         for (int L = top; L >= bottom; --L)
             p->side[s].sched.push_back(schedule_side(*p, s, L, p->side[s].ops, flat_cuts, {}, false));
@@ -1073,10 +1073,13 @@ namespace {
 // about 2^L x (its work) x 0.13 ns on an L-qubit tile: every register group
 // is one round trip of the tile through LDS and every sub-op one sweep of
 // the VALU over it, a dense k-qubit op about 2^k of those, the tile's load
-// and store about six (constants fitted to MI355X timings of the c2p, C2
-// and C3 sweeps at tile sizes 9..14).  The workgroups of both sides share
-// 256 compute units: a round of launches takes the larger of its total work
-// spread over them and one workgroup's own time, plus about 4 us to launch.
+// and store about six.  The workgroups of both sides share 256 compute
+// units: a round of launches takes the larger of its total work spread over
+// them (scaled by the tile size's throughput factor) and one workgroup's
+// own time, plus about 10 us (the shortest sweep launch measured).  The
+// constants are fitted to MI355X timings of the c2p, C2, C3, C4 and QAOA
+// sweeps at forced tile sizes 9 .. 14; the estimate ranks the candidates of
+// one workload, its absolute scale is loose.
 struct PassRun {
     const Schedule* sc;
     int k;
@@ -1093,17 +1096,23 @@ double pass_ns(const Schedule& sc, int k) {
     return std::ldexp(work * 0.13, ps.n_local);
 }
 
-// Throughput penalty of a tile size when the chip is full: fewer waves per
-// SIMD hide less of each group's LDS latency.  Waves per SIMD from the
-// workgroups the LDS admits per compute unit (at most 6 waves, the sweep
-// kernels' register occupancy); measured on MI355X (C4 and the q33-3 QAOA
-// shape, path-tree sweeps): 2 waves 2x slower than 6, 4 waves 1.2x.
-double occupancy_penalty(int L, size_t esz) {
-    const int64_t E = int64_t(1) << L;
-    const int64_t threads = std::min<int64_t>(512, std::max<int64_t>(64, E >> group_bits(L)));
-    const int64_t wg_per_cu = std::max<int64_t>(1, (int64_t)((160u << 10) / (((size_t)E + 256) * esz)));
-    const int64_t waves = std::min<int64_t>(6, wg_per_cu * (threads / 64) / 4);
-    return waves <= 2 ? 2.0 : waves <= 4 ? 1.2 : 1.0;
+// One workgroup's own time on the pass: the work above, and at least about
+// 400 ns per device op however small the tile (LDS and record latency and
+// the barrier between groups do not shrink with it).
+double pass_latency_ns(const Schedule& sc, int k) {
+    const Pass& ps = sc.passes[(size_t)k];
+    return pass_ns(sc, k) + 400.0 * (double)(ps.op_end - ps.op_begin);
+}
+
+// Throughput factor of a tile size when the chip is full: larger tiles hold
+// fewer waves per SIMD to hide each group's LDS latency.  Measured on
+// MI355X (path-tree sweeps of C4 and the q31-1 / q33-3 QAOA shapes at forced
+// tile sizes), complex64 tiles of 9 .. 14 qubits relative to 9; a complex128
+// tile of L qubits takes the LDS of a complex64 tile of L + 1.
+double tile_factor(int L, size_t esz) {
+    static const double f[] = {1.0, 1.04, 1.09, 1.15, 1.4, 2.2};   // L = 9 .. 14
+    const int i = std::min(5, std::max(0, L + (esz > 8 ? 1 : 0) - 9));
+    return f[i];
 }
 
 std::vector<PassRun> side_runs(const Schedule& sc, bool tree, int64_t n) {
@@ -1132,10 +1141,10 @@ double sweep_ns(const Plan& p, bool tree, size_t i, int64_t n) {
             const PassRun& r = runs[s][j];
             const double c = pass_ns(*r.sc, r.k);
             const Pass& ps = r.sc->passes[(size_t)r.k];
-            spread += (double)(r.rows << ps.n_nonlocal) * c * occupancy_penalty(ps.n_local, esz) / 256.0;
-            one = std::max(one, c);
+            spread += (double)(r.rows << ps.n_nonlocal) * c * tile_factor(ps.n_local, esz) / 256.0;
+            one = std::max(one, pass_latency_ns(*r.sc, r.k));
         }
-        t += 4000.0 + std::max(spread, one);
+        t += 10000.0 + std::max(spread, one);
     }
     return t;
 }
