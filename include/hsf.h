@@ -309,7 +309,8 @@ typedef struct hsf_batch_s* hsf_batch_t;
 hsf_status hsf_batch_create(const hsf_plan_t* plans, int32_t n_plans, hsf_batch_t* out);
 void hsf_batch_destroy(hsf_batch_t batch);
 /* Workspace bytes for hsf_batch_run with path-sum `mode` (F32 or BF16X3):
- * every circuit's half-states (all paths), plus BF16 planes for BF16X3.      */
+ * every circuit's half-states (all paths) and path-tree levels, plus BF16
+ * planes for BF16X3.                                                         */
 size_t hsf_batch_workspace_size(hsf_batch_t batch, int32_t mode);
 /* Full state of every circuit: outs[i] is a device array of 2^n_i complex64
  * amplitudes of circuit i (row-major, index i_a 2^n_b + i_b as for one plan).
@@ -319,8 +320,10 @@ size_t hsf_batch_workspace_size(hsf_batch_t batch, int32_t mode);
  * (re)built with synchronous copies when those change, outside any capture. */
 hsf_status hsf_batch_run(hsf_batch_t batch, void* const* outs, int32_t mode, int32_t use_graph, void* ws,
                          size_t ws_bytes, hsf_stream_t stream);
-/* Autotuner: times the tile policies (0: largest tiles, fewest passes; 1:
- * per-circuit tiles that fill the device alone; 2: one size smaller) with 3
+/* Autotuner: times the sweep policies (0: largest tiles, fewest passes; 1:
+ * per-circuit tiles that fill the device alone; 2: one size smaller -- all
+ * flat sweeps; 3, the default before tuning: each circuit's sweep form and
+ * tile size as hsf_sweep_form gives them, path trees where they pay) with 3
  * runs each on `stream`, keeps the fastest for later hsf_batch_run calls and
  * returns it in *policy.  Synchronises `stream`.                             */
 hsf_status hsf_batch_tune(hsf_batch_t batch, void* const* outs, int32_t mode, void* ws, size_t ws_bytes,

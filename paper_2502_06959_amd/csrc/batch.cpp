@@ -15,10 +15,14 @@ namespace hsf {
 
 struct Batch {
     std::vector<Plan*> plans;
-    int policy = 0;                      // 0: largest tiles; 1: per-circuit fill rule; 2: one size smaller
+    // 0: largest tiles; 1: per-circuit fill rule; 2: one size smaller (all
+    // flat sweeps); 3: each circuit's form and tile size from the planner's
+    // estimate (path tree where it pays)
+    int policy = 3;
     int device = -1;
     // workspace layout (bytes from the 256-aligned base)
     std::vector<int64_t> offA, offB, offPA, offPB, kp;
+    std::vector<int64_t> offT;           // each circuit's path-tree scratch (tree_scratch offsets from here)
     size_t ws_f32 = 0, ws_bf16 = 0;
     // device tables
     void* segs = nullptr;
@@ -48,11 +52,12 @@ namespace {
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int sched_index(const Batch& b, const Plan& p) {
+SweepChoice sweep_choice(const Batch& b, const Plan& p) {
     const int n = (int)std::max(p.side[0].sched.size(), p.side[1].sched.size());
-    if (b.policy == 0) return 0;
-    if (b.policy == 1) return pick_schedule(p, p.P);
-    return std::min(1, n - 1);
+    SweepChoice c;
+    if (b.policy == 3) return choose_sweep(p, p.P);
+    c.sched = b.policy == 0 ? 0 : b.policy == 1 ? pick_schedule(p, p.P) : std::min(1, n - 1);
+    return c;
 }
 
 void free_tables(Batch& b) {
@@ -85,9 +90,11 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
     for (int i = 0; i < n; ++i) {
         const Plan& p = *b.plans[i];
         for (int s = 0; s < 2; ++s)
-            for (const Schedule& sc : p.side[s].sched)
-                for (const Pass& ps : sc.passes)
-                    if (ps.n_local < 3) return fail(HSF_E_UNSUPPORTED, "batched sweeps need sides of at least 3 qubits");
+            for (int tr = 0; tr < 2; ++tr)
+                for (const Schedule& sc : tr ? p.side[s].tree : p.side[s].sched)
+                    for (const Pass& ps : sc.passes)
+                        if (ps.n_local < 3)
+                            return fail(HSF_E_UNSUPPORTED, "batched sweeps need sides of at least 3 qubits");
     }
     std::vector<DeviceCopy*> dc(n);
     for (int i = 0; i < n; ++i) {
@@ -103,47 +110,65 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
     b.round_s1.clear();
     b.round_blocks.clear();
     b.round_emax.clear();
+    // every (circuit, side)'s launches, as for a single plan over all its
+    // paths: flat, or path-tree levels in the circuit's scratch
+    std::vector<SweepChoice> ch(n);
+    std::vector<std::vector<SweepItem>> items(2 * (size_t)n);
+    std::vector<const Schedule*> hs(2 * (size_t)n);
+    std::vector<const DeviceSchedule*> dsv(2 * (size_t)n);
     size_t rounds = 0;
-    std::vector<int> si(n);
-    // a side with a shared prefix state starts after its prefix passes
-    auto first_pass = [&](int i, int s) -> size_t {
-        const auto& v = b.plans[i]->side[s].sched;
-        const size_t idx = std::min<size_t>(si[i], v.size() - 1);
-        return dc[i]->side[s][idx].prefix ? (size_t)v[idx].n_prefix_passes : 0;
-    };
     for (int i = 0; i < n; ++i) {
-        si[i] = sched_index(b, *b.plans[i]);
+        const Plan& p = *b.plans[i];
+        ch[i] = sweep_choice(b, p);
+        const TreeScratch ts = tree_scratch(p, p.P);
         for (int s = 0; s < 2; ++s) {
-            const auto& v = b.plans[i]->side[s].sched;
-            rounds = std::max(rounds, v[std::min<size_t>(si[i], v.size() - 1)].passes.size() - first_pass(i, s));
+            const std::vector<Schedule>& hv = ch[i].tree ? p.side[s].tree : p.side[s].sched;
+            const std::vector<DeviceSchedule>& dv = ch[i].tree ? dc[i]->tree[s] : dc[i]->side[s];
+            const size_t idx = std::min<size_t>((size_t)ch[i].sched, hv.size() - 1);
+            const size_t q = 2 * (size_t)i + s;
+            hs[q] = &hv[idx];
+            dsv[q] = &dv[idx];
+            // offsets from the workspace base stand in for the pointers
+            auto off = [](int64_t o) { return reinterpret_cast<unsigned char*>((uintptr_t)o); };
+            const int64_t dim = int64_t(1) << (s == 0 ? p.na : p.nb);
+            items[q] = side_items(*hs[q], ch[i].tree, dsv[q]->prefix, 0, p.P, off(s == 0 ? b.offA[i] : b.offB[i]), dim,
+                                  off(b.offT[i] + (int64_t)ts.off[s][0]), off(b.offT[i] + (int64_t)ts.off[s][1]), dim);
+            rounds = std::max(rounds, items[q].size());
         }
     }
-    // pass k of every (circuit, side), split by group width: one launch each
+    // item j of every (circuit, side), split by group width: one launch each
     for (size_t j = 0; j < rounds; ++j)
         for (int kg = 3; kg <= 4; ++kg) {
             const int first = (int)segs.size();
             uint32_t start = 0, emax = 1;
             int s1 = 0;
             for (int i = 0; i < n; ++i) {
-                const Plan& p = *b.plans[i];
                 for (int s = 0; s < 2; ++s) {
-                    const auto& v = p.side[s].sched;
-                    const size_t idx = std::min<size_t>(si[i], v.size() - 1);
-                    const Schedule& sc = v[idx];
-                    const size_t f = first_pass(i, s), k = f + j;
-                    if (k >= sc.passes.size() || group_bits(sc.passes[k].n_local) != kg) continue;
-                    const DeviceSchedule& ds = dc[i]->side[s][idx];
+                    const size_t q = 2 * (size_t)i + s;
+                    if (j >= items[q].size()) continue;
+                    const SweepItem& it = items[q][j];
+                    const Schedule& sc = *hs[q];
+                    const size_t k = it.k;
+                    if (group_bits(sc.passes[k].n_local) != kg) continue;
+                    const DeviceSchedule& ds = *dsv[q];
                     BatchSeg g{};
                     g.pass = reinterpret_cast<const Pass*>(ds.passes) + k;
-                    g.psi_off = s == 0 ? b.offA[i] : b.offB[i];
-                    g.ld = int64_t(1) << (s == 0 ? p.na : p.nb);
+                    g.psi_off = (int64_t)(uintptr_t)it.dst;
+                    g.ld = it.dst_ld;
                     g.ops = (const DevOp*)ds.ops;
                     g.subs = ds.subs;
                     g.pool = ds.pool;
                     g.n_tiles = 1u << sc.passes[k].n_nonlocal;
                     g.block_start = start;
-                    g.shared = (j == 0 && f > 0) ? ds.prefix : nullptr;
-                    start += (uint32_t)(p.P * g.n_tiles);
+                    g.mode = it.mode;
+                    g.shared = it.mode == ROW_SHARED ? it.src : nullptr;
+                    g.S = it.S;
+                    g.i_lo = it.i_lo;
+                    g.src_off = it.mode == ROW_PARENT ? (int64_t)(uintptr_t)it.src : 0;
+                    g.src_ld = it.src_ld;
+                    g.src_lo = it.src_lo;
+                    g.S_par = it.S_par;
+                    start += (uint32_t)(it.rows * g.n_tiles);
                     emax = std::max(emax, 1u << sc.passes[k].n_local);
                     s1 |= sc.passes[k].has_slot1;
                     segs.push_back(g);
@@ -269,6 +294,11 @@ hsf_status batch_create(Plan* const* plans, int n, Batch** out) {
         b->offB.push_back((int64_t)o);
         o += a256((size_t)p.P * N * 8);
     }
+    // path-tree scratch for every circuit that has tree schedules
+    for (int i = 0; i < n; ++i) {
+        b->offT.push_back((int64_t)o);
+        o += a256(tree_scratch(*plans[i], plans[i]->P).total);
+    }
     ob = o;
     for (int i = 0; i < n; ++i) {
         const Plan& p = *plans[i];
@@ -343,7 +373,7 @@ hsf_status batch_tune(Batch& b, void* const* outs, int mode, void* ws, hipStream
     }
     float best = 1e30f;
     int best_p = 0;
-    for (int pol = 0; pol < 3; ++pol) {
+    for (int pol = 0; pol < 4; ++pol) {
         b.policy = pol;
         if ((s = batch_run(b, outs, mode, 0, ws, st)) != HSF_OK) break;     // warm-up, builds tables
         (void)hipEventRecord(e0, st);

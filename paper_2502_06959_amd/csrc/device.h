@@ -17,6 +17,39 @@ constexpr size_t kNormWsDoubles = 8192;
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
                      void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream);
 size_t tree_workspace(const Plan& p, int64_t n_paths);
+
+// How a sweep launch row finds its input.  ROW_INPLACE: its own row.
+// ROW_SHARED: one shared state (the prefix).  ROW_PARENT: its parent's row at
+// the previous path-tree level.
+enum RowMode : int32_t { ROW_INPLACE = 0, ROW_SHARED = 1, ROW_PARENT = 2 };
+
+// One launch's worth of one side: pass k over the level rows [i_lo, i_lo +
+// rows), row i written to dst + (i - i_lo) * dst_ld (elements), its input
+// per `mode` (ROW_PARENT: src row i S / S_par - src_lo, ld src_ld).  dst and
+// src may be offsets from a workspace base (batches) instead of pointers.
+struct SweepItem {
+    size_t k;
+    int32_t mode;
+    int64_t S, i_lo, rows;
+    void* dst;
+    int64_t dst_ld;
+    const void* src;
+    int64_t src_ld, src_lo, S_par;
+};
+
+// Scratch of the path-tree levels below the last for a chunk of n_paths
+// paths: two buffers per side (byte offsets), level l in buffer l % 2.
+struct TreeScratch {
+    size_t off[2][2] = {{0, 0}, {0, 0}}, total = 0;
+};
+TreeScratch tree_scratch(const Plan& p, int64_t n_paths);
+
+// The launches of one side's sweep over paths [p_begin, p_begin + n_paths):
+// flat (every per-path pass on every path, the first reading `prefix` when
+// it is non-null) or level by level (buf0 / buf1: the side's tree scratch).
+std::vector<SweepItem> side_items(const Schedule& sc, bool tree, const void* prefix, int64_t p_begin,
+                                  int64_t n_paths, void* psi, int64_t ld, unsigned char* buf0, unsigned char* buf1,
+                                  int64_t dim);
 // The passes of one flat schedule without factor slots over rows 0 .. rows-1
 // of psi (ld elements apart), in place.
 hsf_status run_segment(const Plan& p, const DeviceSchedule& ds, const Schedule& sc, void* psi, int64_t ld, int64_t rows,

@@ -199,14 +199,20 @@ struct SideProgram {
 // One (circuit, side) segment of a batched sweep launch (device table).
 struct BatchSeg {
     const Pass* pass;
-    int64_t psi_off;         // bytes from the batch workspace base to the side's row 0
+    int64_t psi_off;         // bytes from the batch workspace base to the segment's output row 0
     int64_t ld;
     const DevOp* ops;
     const void* subs;
     const void* pool;
     uint32_t n_tiles;
     uint32_t block_start;    // first workgroup of the segment
-    const void* shared;      // non-null: the pass reads this state (the shared prefix) instead of the rows
+    const void* shared;      // ROW_SHARED: the state every row starts from (the shared prefix)
+    // rows as in a single plan's sweep: level rows i = i_lo + j, paths
+    // [i S, (i + 1) S), written to output row i - i_lo; ROW_PARENT reads row
+    // i S / S_par - src_lo of the buffer at base + src_off (ld src_ld)
+    int64_t S, i_lo, src_off, src_ld, src_lo, S_par;
+    int32_t mode;
+    int32_t spare;
 };
 
 // Batched path sum: one circuit's operands and output (device tables).

@@ -98,8 +98,6 @@ struct SideArgs {
     int32_t mode;
 };
 
-enum RowMode : int32_t { ROW_INPLACE = 0, ROW_SHARED = 1, ROW_PARENT = 2 };
-
 // LDS position of tile element e: the low four index bits are XORed with the
 // next four, so that the 16 lanes that vary the lowest free bits of a
 // register group land on 16 distinct 8-byte bank pairs whatever the group's
@@ -417,10 +415,16 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_batch(const BatchSeg* _
     const uint32_t blk = blockIdx.x - sg.block_start;
     const uint32_t pl = blk / sg.n_tiles;
     const uint32_t t = blk - pl * sg.n_tiles;
+    // a circuit's rows hold all its paths (p0 = 0)
+    const int64_t i = sg.i_lo + (int64_t)pl;
     V* st = reinterpret_cast<V*>(base + sg.psi_off) + (int64_t)pl * sg.ld;
-    const V* src = sg.shared ? reinterpret_cast<const V*>(sg.shared) : st;
+    const V* src = st;
+    if (sg.mode == ROW_SHARED)
+        src = reinterpret_cast<const V*>(sg.shared);
+    else if (sg.mode == ROW_PARENT)
+        src = reinterpret_cast<const V*>(base + sg.src_off) + ((i * sg.S) / sg.S_par - sg.src_lo) * sg.src_ld;
     sweep_tile<T, KG, S1>(as_table(sg.pass), as_table(sg.ops), as_table(reinterpret_cast<const DSub<T>*>(sg.subs)),
-                      reinterpret_cast<const V*>(sg.pool), st, src, t, pl, reinterpret_cast<V*>(smem_raw));
+                      reinterpret_cast<const V*>(sg.pool), st, src, t, i * sg.S, reinterpret_cast<V*>(smem_raw));
 }
 
 std::mutex g_dev_mutex;
@@ -685,28 +689,12 @@ hsf_status run_segment(const Plan& p, const DeviceSchedule& ds, const Schedule& 
 
 namespace {
 
-// One launch's worth of one side: pass k over the level rows
-// [i_lo, i_lo + rows) (see SideArgs).
-struct Item {
-    size_t k;
-    int32_t mode;
-    int64_t S, i_lo, rows;
-    void* dst;
-    int64_t dst_ld;
-    const void* src;
-    int64_t src_ld, src_lo, S_par;
-};
-
 // Level rows of a chunk of n paths from p_begin: [p_begin / S, (p_begin + n - 1) / S].
 int64_t level_rows(int64_t p_begin, int64_t n, int64_t S) { return (p_begin + n - 1) / S - p_begin / S + 1; }
 // A bound on level_rows over every p_begin.
 int64_t level_rows_max(int64_t n, int64_t S) { return (n - 1) / S + 2; }
 
-// Scratch of the path-tree levels below the last: two buffers per side,
-// level l in buffer l % 2 (it reads level l - 1 from the other).
-struct TreeScratch {
-    size_t off[2][2] = {{0, 0}, {0, 0}}, total = 0;
-};
+}  // namespace
 
 TreeScratch tree_scratch(const Plan& p, int64_t n_paths) {
     TreeScratch t;
@@ -731,9 +719,9 @@ TreeScratch tree_scratch(const Plan& p, int64_t n_paths) {
 // the prefix state when there is one).  Tree: level by level, each level's
 // rows written to its scratch buffer (the last level to psi), its first pass
 // reading the prefix state or the previous level.
-std::vector<Item> side_items(const Schedule& sc, bool tree, const void* prefix, int64_t p_begin, int64_t n_paths,
+std::vector<SweepItem> side_items(const Schedule& sc, bool tree, const void* prefix, int64_t p_begin, int64_t n_paths,
                              void* psi, int64_t ld, unsigned char* buf0, unsigned char* buf1, int64_t dim) {
-    std::vector<Item> v;
+    std::vector<SweepItem> v;
     const size_t first = prefix ? (size_t)sc.n_prefix_passes : 0;
     if (!tree) {
         for (size_t k = first; k < sc.passes.size(); ++k) {
@@ -750,7 +738,7 @@ std::vector<Item> side_items(const Schedule& sc, bool tree, const void* prefix, 
         void* dst = l + 1 == nl ? psi : (void*)buf[l % 2];
         const int64_t dld = l + 1 == nl ? ld : dim;
         for (size_t k = (size_t)tl.pass_begin; k < (size_t)tl.pass_end; ++k) {
-            Item it{k, ROW_INPLACE, tl.S, lo, rows, dst, dld, nullptr, 0, 0, 1};
+            SweepItem it{k, ROW_INPLACE, tl.S, lo, rows, dst, dld, nullptr, 0, 0, 1};
             if (k == (size_t)tl.pass_begin && l == 0 && prefix) {
                 it.mode = ROW_SHARED;
                 it.src = prefix;
@@ -766,8 +754,6 @@ std::vector<Item> side_items(const Schedule& sc, bool tree, const void* prefix, 
     }
     return v;
 }
-
-}  // namespace
 
 size_t tree_workspace(const Plan& p, int64_t n_paths) {
     if (n_paths <= 0 || !choose_sweep(p, n_paths).tree) return 0;
@@ -792,7 +778,7 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
     const int64_t ld[2] = {ldA, ldB};
     const Schedule* sc[2];
     const DeviceSchedule* dsc[2];
-    std::vector<Item> items[2];
+    std::vector<SweepItem> items[2];
     size_t rounds = 0;
     for (int s = 0; s < 2; ++s) {
         const std::vector<Schedule>& hv = tree ? p.side[s].tree : p.side[s].sched;
@@ -810,18 +796,18 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
     // rows per launch bounded so the grid stays below 2^31 workgroups
     int64_t tiles_max = 1;
     for (int s = 0; s < 2; ++s)
-        for (const Item& it : items[s]) tiles_max = std::max<int64_t>(tiles_max, int64_t(1) << sc[s]->passes[it.k].n_nonlocal);
+        for (const SweepItem& it : items[s]) tiles_max = std::max<int64_t>(tiles_max, int64_t(1) << sc[s]->passes[it.k].n_nonlocal);
     const int64_t max_rows = std::max<int64_t>(1, (int64_t(1) << 29) / tiles_max);
     for (size_t j = 0; j < rounds; ++j) {
         SideArgs a[2];
         std::memset(a, 0, sizeof(a));
-        const Item* it[2] = {nullptr, nullptr};
+        const SweepItem* it[2] = {nullptr, nullptr};
         uint32_t emax = 1;
         int64_t rows_max = 0;
         for (int s = 0; s < 2; ++s) {
             if (j >= items[s].size()) continue;
             it[s] = &items[s][j];
-            const Item& m = *it[s];
+            const SweepItem& m = *it[s];
             const Pass& ps = sc[s]->passes[m.k];
             const DeviceSchedule& ds = *dsc[s];
             a[s].pass = reinterpret_cast<const Pass*>(ds.passes) + m.k;
