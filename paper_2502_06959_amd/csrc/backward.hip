@@ -186,8 +186,14 @@ __global__ __launch_bounds__(256) void bw_apply2_grad(typename Cx<T>::v* __restr
     const uint64_t g = (uint64_t)blk * blockDim.x + threadIdx.x;
     double accr = 0.0, acci = 0.0;
     if (g < groups) {
-        uint64_t idx[D];
-        group_offsets<K>(bits, g, idx);
+        // 32-bit element offsets (the host sends rows of under 2^31 amplitudes)
+        uint32_t idx[D];
+        {
+            uint64_t i64[D];
+            group_offsets<K>(bits, g, i64);
+#pragma unroll
+            for (int j = 0; j < D; ++j) idx[j] = (uint32_t)i64[j];
+        }
         V* sr = s + (int64_t)row * ld;
         V* lr = l + (int64_t)row * ld;
         V vs[D], vl[D];
@@ -236,6 +242,215 @@ __global__ __launch_bounds__(256) void bw_apply2_grad(typename Cx<T>::v* __restr
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(rr[0], ri[0]);
+}
+
+// A run of consecutive gates (program order reversed) on at most three
+// qubits (four need more registers than the kernel's occupancy allows),
+// undone in registers in one pass over the rows: each thread holds the
+// 2^K amplitudes of the state and of the adjoint that differ in those qubits.
+constexpr int kAdjMaxOps = 8;
+constexpr int kAdjMaxBits = 3;
+struct AdjRun {
+    int32_t n_ops;
+    int32_t k[kAdjMaxOps];             // 1 or 2
+    int32_t rb[kAdjMaxOps][2];         // register bits of the op's qubits (q[0] first)
+    const void* inv[kAdjMaxOps];       // M^dagger, M^T and (angle ops) D, 2^k x 2^k
+    const void* tr[kAdjMaxOps];
+    const void* dg[kAdjMaxOps];        // null: no angle
+    double2* partial[kAdjMaxOps];      // block partials of the angle's term
+};
+
+template <typename V>
+__device__ __forceinline__ void cacc(V& acc, V m, V x) {
+    acc.x += m.x * x.x - m.y * x.y;
+    acc.y += m.x * x.y + m.y * x.x;
+}
+
+// One-qubit gate on register bit RB of both register sets, with the angle's
+// term first when md is set.
+template <int K, int RB, typename V>
+__device__ __forceinline__ void adj1(V (&vs)[1 << K], V (&vl)[1 << K], const V* mi, const V* mt, const V* md,
+                                     double& ar, double& ai) {
+#pragma unroll
+    for (int b = 0; b < (1 << K); ++b) {
+        if (b & (1 << RB)) continue;
+        // matrices are re-read from LDS per pair (broadcasts) rather than held
+        asm volatile("" ::: "memory");
+        const int i0 = b, i1 = b | (1 << RB);
+        const V s0 = vs[i0], s1 = vs[i1], l0 = vl[i0], l1 = vl[i1];
+        if (md) {
+            V t0, t1;
+            t0.x = t0.y = t1.x = t1.y = 0;
+            cacc(t0, md[0], s0); cacc(t0, md[1], s1);
+            cacc(t1, md[2], s0); cacc(t1, md[3], s1);
+            ar += (double)l0.x * t0.x - (double)l0.y * t0.y + (double)l1.x * t1.x - (double)l1.y * t1.y;
+            ai += (double)l0.x * t0.y + (double)l0.y * t0.x + (double)l1.x * t1.y + (double)l1.y * t1.x;
+        }
+        V a0, a1, c0, c1;
+        a0.x = a0.y = a1.x = a1.y = c0.x = c0.y = c1.x = c1.y = 0;
+        cacc(a0, mi[0], s0); cacc(a0, mi[1], s1);
+        cacc(a1, mi[2], s0); cacc(a1, mi[3], s1);
+        cacc(c0, mt[0], l0); cacc(c0, mt[1], l1);
+        cacc(c1, mt[2], l0); cacc(c1, mt[3], l1);
+        vs[i0] = a0; vs[i1] = a1; vl[i0] = c0; vl[i1] = c1;
+    }
+}
+
+// Two-qubit gate on register bits R0 (its q[0], the matrix index's high bit)
+// and R1.
+template <int K, int R0, int R1, typename V>
+__device__ __forceinline__ void adj2(V (&vs)[1 << K], V (&vl)[1 << K], const V* mi, const V* mt, const V* md,
+                                     double& ar, double& ai) {
+#pragma unroll
+    for (int b = 0; b < (1 << K); ++b) {
+        if (b & ((1 << R0) | (1 << R1))) continue;
+        asm volatile("" ::: "memory");
+        const int ix[4] = {b, b | (1 << R1), b | (1 << R0), b | (1 << R0) | (1 << R1)};
+        V x[4], y[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            x[m] = vs[ix[m]];
+            y[m] = vl[ix[m]];
+        }
+        // one matrix at a time (fences keep the compiler from loading all
+        // three 4x4 matrices at once)
+        if (md) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                V t;
+                t.x = t.y = 0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cacc(t, md[r * 4 + c], x[c]);
+                ar += (double)y[r].x * t.x - (double)y[r].y * t.y;
+                ai += (double)y[r].x * t.y + (double)y[r].y * t.x;
+            }
+            asm volatile("" ::: "memory");
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            V a;
+            a.x = a.y = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cacc(a, mi[r * 4 + c], x[c]);
+            vs[ix[r]] = a;
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            V c2;
+            c2.x = c2.y = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cacc(c2, mt[r * 4 + c], y[c]);
+            vl[ix[r]] = c2;
+        }
+    }
+}
+
+template <int K, typename V>
+__device__ __forceinline__ void adj_op(V (&vs)[1 << K], V (&vl)[1 << K], int k, int r0, int r1, const V* mi,
+                                       const V* mt, const V* md, double& ar, double& ai) {
+    if (k == 1) {
+        switch (r0) {
+            case 0: adj1<K, 0>(vs, vl, mi, mt, md, ar, ai); break;
+            case 1: if constexpr (K > 1) adj1<K, 1>(vs, vl, mi, mt, md, ar, ai); break;
+            case 2: if constexpr (K > 2) adj1<K, 2>(vs, vl, mi, mt, md, ar, ai); break;
+            default: if constexpr (K > 3) adj1<K, 3>(vs, vl, mi, mt, md, ar, ai); break;
+        }
+        return;
+    }
+    if constexpr (K >= 2) {
+#define HSF_ADJ2(A, B) \
+    if (r0 == A && r1 == B) { if constexpr (A < K && B < K) adj2<K, A, B>(vs, vl, mi, mt, md, ar, ai); return; }
+        HSF_ADJ2(0, 1) HSF_ADJ2(1, 0) HSF_ADJ2(0, 2) HSF_ADJ2(2, 0) HSF_ADJ2(0, 3) HSF_ADJ2(3, 0)
+        HSF_ADJ2(1, 2) HSF_ADJ2(2, 1) HSF_ADJ2(1, 3) HSF_ADJ2(3, 1) HSF_ADJ2(2, 3) HSF_ADJ2(3, 2)
+#undef HSF_ADJ2
+    }
+}
+
+// The run's gates in order on every row (grid: rows x blocks_per_row, one
+// group of 2^K amplitudes per thread), each angle's term from the state and
+// adjoint just after its gate, reduced per workgroup in a fixed order.
+template <int K, typename T>
+__global__ __launch_bounds__(256) void bw_adj_run(typename Cx<T>::v* __restrict__ s, typename Cx<T>::v* __restrict__ l,
+                                                  int64_t ld, int nq, Bits bits, AdjRun a, uint32_t blocks_per_row) {
+    using V = typename Cx<T>::v;
+    constexpr int D = 1 << K;
+    __shared__ V mm[kAdjMaxOps][3][16];
+    __shared__ double rr[kAdjMaxOps][256], ri[kAdjMaxOps][256];
+#pragma unroll
+    for (int j = 0; j < kAdjMaxOps; ++j) {
+        if (j >= a.n_ops) break;
+        const int d2 = 1 << (2 * a.k[j]);
+        for (int i = threadIdx.x; i < d2; i += blockDim.x) {
+            mm[j][0][i] = reinterpret_cast<const V*>(a.inv[j])[i];
+            mm[j][1][i] = reinterpret_cast<const V*>(a.tr[j])[i];
+            if (a.dg[j]) mm[j][2][i] = reinterpret_cast<const V*>(a.dg[j])[i];
+        }
+    }
+    __syncthreads();
+    const uint32_t row = blockIdx.x / blocks_per_row;
+    const uint32_t blk = blockIdx.x - row * blocks_per_row;
+    const uint64_t groups = uint64_t(1) << (nq - K);
+    const uint64_t g = (uint64_t)blk * blockDim.x + threadIdx.x;
+    // each thread's share of every angle's term, parked in LDS right after
+    // its gate (threads past the last group contribute zero)
+#pragma unroll
+    for (int j = 0; j < kAdjMaxOps; ++j) {
+        if (j >= a.n_ops) break;
+        rr[j][threadIdx.x] = 0.0;
+        ri[j][threadIdx.x] = 0.0;
+    }
+    if (g < groups) {
+        // 32-bit element offsets (the host sends rows of under 2^31 amplitudes)
+        uint32_t idx[D];
+        {
+            uint64_t i64[D];
+            group_offsets<K>(bits, g, i64);
+#pragma unroll
+            for (int j = 0; j < D; ++j) idx[j] = (uint32_t)i64[j];
+        }
+        V* sr = s + (int64_t)row * ld;
+        V* lr = l + (int64_t)row * ld;
+        V vs[D], vl[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            vs[j] = sr[idx[j]];
+            vl[j] = lr[idx[j]];
+        }
+        // one copy of each gate form's code: the run's table is read by index
+#pragma unroll 1
+        for (int j = 0; j < a.n_ops; ++j) {
+            double ar = 0.0, ai = 0.0;
+            adj_op<K>(vs, vl, a.k[j], a.rb[j][0], a.rb[j][1], mm[j][0], mm[j][1], a.dg[j] ? mm[j][2] : nullptr, ar, ai);
+            rr[j][threadIdx.x] = ar;
+            ri[j][threadIdx.x] = ai;
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            sr[idx[j]] = vs[j];
+            lr[idx[j]] = vl[j];
+        }
+    }
+    __syncthreads();
+    // fixed-order tree over the workgroup for every angle at once
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int j = 0; j < kAdjMaxOps; ++j) {
+                if (j >= a.n_ops) break;
+                rr[j][threadIdx.x] += rr[j][threadIdx.x + w];
+                ri[j][threadIdx.x] += ri[j][threadIdx.x + w];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < kAdjMaxOps; ++j) {
+            if (j >= a.n_ops) break;
+            if (a.dg[j]) a.partial[j][blockIdx.x] = make_double2(rr[j][0], ri[j][0]);
+        }
+    }
 }
 
 template <typename T>
@@ -449,6 +664,59 @@ std::vector<cd> transpose_of(const std::vector<cd>& m, int d) {
     return r;
 }
 
+// The adjoint pass's units of one side, in the order it takes them (program
+// order reversed): a factor slot alone, a gate on more than two qubits alone
+// (and every gate of a side of 31 qubits or more), or a run of consecutive
+// gates on at most kAdjMaxBits qubits together (at most kAdjMaxOps of them),
+// raw indices hi, hi - 1, ..., hi - n + 1.
+struct AdjUnit {
+    int kind;             // 0 run, 1 slot, 2 single wide gate
+    int hi, n, K;
+    int q[4];             // run: its qubits; register bit K - 1 - i holds q[i]
+};
+
+std::vector<AdjUnit> adj_units(const SideProgram& sp) {
+    std::vector<AdjUnit> u;
+    const auto& raw = sp.raw;
+    for (int ii = (int)raw.size() - 1; ii >= 0;) {
+        AdjUnit a{};
+        a.hi = ii;
+        a.n = 1;
+        const SideOp& o = raw[ii];
+        if (o.kind == SideOp::SLOT || o.k > 2 || sp.nq >= 31) {
+            a.kind = o.kind == SideOp::SLOT ? 1 : 2;
+            a.K = o.k;
+            u.push_back(a);
+            --ii;
+            continue;
+        }
+        a.kind = 0;
+        for (int j = 0; j < o.k; ++j) a.q[a.K++] = o.q[j];
+        int j = ii - 1;
+        while (j >= 0 && a.n < kAdjMaxOps && raw[j].kind != SideOp::SLOT && raw[j].k <= 2 && sp.nq < 31) {
+            int qq[4], nq = a.K;
+            for (int t = 0; t < a.K; ++t) qq[t] = a.q[t];
+            bool fits = true;
+            for (int t = 0; t < raw[j].k && fits; ++t) {
+                bool have = false;
+                for (int r = 0; r < nq; ++r) have |= qq[r] == raw[j].q[t];
+                if (!have) {
+                    if (nq == kAdjMaxBits) fits = false;
+                    else qq[nq++] = raw[j].q[t];
+                }
+            }
+            if (!fits) break;
+            a.K = nq;
+            for (int t = 0; t < nq; ++t) a.q[t] = qq[t];
+            ++a.n;
+            --j;
+        }
+        u.push_back(a);
+        ii = j;
+    }
+    return u;
+}
+
 // Offsets (in complex elements, inside the backward matrix area) of each raw op's matrices.
 struct OpMats {
     size_t fwd, inv, tr, dg;
@@ -510,6 +778,22 @@ struct Runner {
         });
     }
 
+    hsf_status adj_run(V* s, V* l, int64_t ld, int64_t rows, int nq, const Bits& bits, int K, const AdjRun& a) {
+        const uint32_t bpr = (uint32_t)adj_blocks_per_row(nq, K);
+        auto go = [&](auto kk) {
+            constexpr int KK = decltype(kk)::value;
+            hipLaunchKernelGGL((bw_adj_run<KK, T>), dim3((uint32_t)(rows * bpr)), dim3(256), 0, st, s, l, ld, nq, bits,
+                               a, bpr);
+            return hip_check(hipGetLastError(), "bw_adj_run launch");
+        };
+        switch (K) {
+            case 1: return go(std::integral_constant<int, 1>());
+            case 2: return go(std::integral_constant<int, 2>());
+            case 3: return go(std::integral_constant<int, 3>());
+            default: return fail(HSF_E_ARG, "internal: an adjoint run wider than three qubits");
+        }
+    }
+
     hsf_status fill(V* x, int64_t ld, int64_t dim, int64_t rows, int one) {
         const int64_t n = rows * dim;
         const uint32_t g = (uint32_t)std::min<int64_t>(65536, (n + 255) / 256);
@@ -545,6 +829,8 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
     const int64_t dim[2] = {Lo.dimA, Lo.dimB};
     const int nq[2] = {p.na, p.nb};
     hsf_status s;
+
+    const std::vector<AdjUnit> units[2] = {adj_units(p.side[0]), adj_units(p.side[1])};
 
     // ---- host tables: bitstring groups per side, parameter occurrences
     std::vector<uint64_t> hx((size_t)std::max<int64_t>(nx, 1));
@@ -602,12 +888,17 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             for (int64_t q : per[t]) ht[occ_list + w++] = q;
         }
         ht[occ_off + p.n_params] = w;
-        // block partials per row of each occurrence
+        // block partials per row of each occurrence: those of the adjoint
+        // unit that holds its gate
         const size_t occ_rows = occ_list + (size_t)Lo.n_occ;
         int64_t q = 0;
-        for (int side = 0; side < 2; ++side)
-            for (const SideOp& op : p.side[side].raw)
-                if (op.param_id >= 0) ht[occ_rows + q++] = adj_blocks_per_row(nq[side], op.k);
+        for (int side = 0; side < 2; ++side) {
+            std::vector<int> width(p.side[side].raw.size(), 1);
+            for (const AdjUnit& a : units[side])
+                for (int t = 0; t < a.n; ++t) width[(size_t)(a.hi - t)] = a.K;
+            for (size_t i = 0; i < p.side[side].raw.size(); ++i)
+                if (p.side[side].raw[i].param_id >= 0) ht[occ_rows + q++] = adj_blocks_per_row(nq[side], width[i]);
+        }
         if ((s = hip_check(hipMemcpyAsync(tables, ht.data(), ht.size() * sizeof(int64_t), hipMemcpyHostToDevice, st),
                            "upload tables")) != HSF_OK)
             return s;
@@ -726,30 +1017,55 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             int64_t oc = occ;                 // occurrences are numbered in program order
             int kc = 0;
             for (const SideOp& o : raw) kc += o.kind == SideOp::SLOT;
-            for (size_t ii = raw.size(); ii-- > 0;) {
-                const SideOp& o = raw[ii];
-                if (o.param_id >= 0) {
-                    // angles sit on gates, never on factor slots
-                    if (o.kind == SideOp::SLOT) return fail(HSF_E_ARG, "internal: an angle on a factor slot");
-                    // the angle's term from the state and adjoint after the op, then the op undone
-                    --oc;
-                    if ((s = R.apply2_grad(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].inv,
-                                           mats + om[side][ii].tr, mats + om[side][ii].dg, partial + oc * pstride)) !=
-                        HSF_OK)
-                        return s;
-                    continue;
-                }
-                if (o.kind == SideOp::SLOT) {
+            for (const AdjUnit& u : units[side]) {
+                const int ii = u.hi;
+                const SideOp& o = raw[(size_t)ii];
+                if (u.kind == 1) {
+                    if (o.param_id >= 0) return fail(HSF_E_ARG, "internal: an angle on a factor slot");
                     --kc;
                     V* c = ck[side] + (size_t)kc * chunk * dim[side];
                     if ((s = R.copy_rows(c, dim[side], vS[side], dim[side], dim[side], np)) != HSF_OK) return s;
                     if ((s = R.apply(lS[side], dim[side], np, nq[side], o, mats + om[side][ii].tr, o.rank, o.stride, p0)) != HSF_OK)
                         return s;
-                } else {
-                    if ((s = R.apply2(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].inv,
-                                      mats + om[side][ii].tr)) != HSF_OK)
-                        return s;
+                    continue;
                 }
+                if (u.kind == 2) {
+                    if (o.param_id >= 0) {
+                        // the angle's term from the state and adjoint after the gate, then the gate undone
+                        --oc;
+                        s = R.apply2_grad(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].inv,
+                                          mats + om[side][ii].tr, mats + om[side][ii].dg, partial + oc * pstride);
+                    } else {
+                        s = R.apply2(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].inv,
+                                     mats + om[side][ii].tr);
+                    }
+                    if (s != HSF_OK) return s;
+                    continue;
+                }
+                // a run of gates in registers, each angle's term at its gate
+                AdjRun a{};
+                a.n_ops = u.n;
+                Bits bits{};
+                for (int t = 0; t < u.K; ++t) bits.b[t] = u.q[t];
+                for (int t = 0; t < u.n; ++t) {
+                    const SideOp& g = raw[(size_t)(ii - t)];
+                    a.k[t] = g.k;
+                    for (int e = 0; e < g.k; ++e) {
+                        int pos = 0;
+                        while (u.q[pos] != g.q[e]) ++pos;
+                        a.rb[t][e] = u.K - 1 - pos;
+                    }
+                    a.inv[t] = mats + om[side][(size_t)(ii - t)].inv;
+                    a.tr[t] = mats + om[side][(size_t)(ii - t)].tr;
+                    a.dg[t] = nullptr;
+                    a.partial[t] = nullptr;
+                    if (g.param_id >= 0) {
+                        --oc;
+                        a.dg[t] = mats + om[side][(size_t)(ii - t)].dg;
+                        a.partial[t] = partial + oc * pstride;
+                    }
+                }
+                if ((s = R.adj_run(vS[side], lS[side], dim[side], np, nq[side], bits, u.K, a)) != HSF_OK) return s;
             }
             (void)occ_side;
         }
