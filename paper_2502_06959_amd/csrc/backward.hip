@@ -553,7 +553,9 @@ __global__ void bw_shift_combine(const double* __restrict__ lp, const double* __
 // ---------------------------------------------------------------- host ----
 
 struct Layout {
-    size_t vA, vB, lA, lB, ckA, ckB, psi_x, psi_s, loss, partial, tables, mats, pools, tree, tree_bytes, total;
+    size_t vA, vB, lA, lB, ckA, ckB, psi_x, psi_s, loss, partial, tables, mats, pools, tree, tree_bytes, lane,
+        lane_bytes, total;
+    int lanes;             // concurrent shifted forward runs
     int64_t dimA, dimB;
     int ka, kb;            // checkpoints per side
     int64_t n_occ;         // parametrised ops outside blocks, both sides
@@ -563,6 +565,11 @@ struct Layout {
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Streams the parameter-shift forward runs share: the early path-tree levels
+// of one run hold too few states to fill the chip, so several runs go at
+// once (at most the hardware queues a process gets by default).
+constexpr int kShiftLanes = 4;
 
 // Workgroups per path row of the per-op adjoint kernels (one group of 2^k
 // amplitudes per thread, 256 threads).
@@ -629,6 +636,12 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     L.pools = take(L.pool_elems * (size_t)std::max<int64_t>(1, L.n_shift) * esz);
     L.tree_bytes = tree_workspace(p, chunk);     // path-tree levels of the forward runs
     L.tree = take(L.tree_bytes);
+    // the shifted forward runs go round kShiftLanes streams; lanes past the
+    // first bring their own half-states, bitstring amplitudes and tree levels
+    L.lanes = (int)std::min<int64_t>(kShiftLanes, std::max<int64_t>(1, L.n_shift));
+    L.lane_bytes = align256((size_t)chunk * L.dimA * esz) + align256((size_t)chunk * L.dimB * esz) +
+                   align256((size_t)nx * 16) + align256(L.tree_bytes);
+    L.lane = take(L.lane_bytes * (size_t)(L.lanes - 1));
     L.total = o + 256;
     return L;
 }
@@ -1179,31 +1192,96 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
         if ((s = hip_check(hipMemcpyAsync(pools, staged.data(), staged.size() * sizeof(V), hipMemcpyHostToDevice, st),
                            "upload shifted factors")) != HSF_OK)
             return s;
+        // shift i runs on lane i mod lanes: lane 0 on the caller's stream with
+        // the buffers above, the others on streams of their own (default
+        // priority) that start after everything queued so far
+        const int nl = (int)std::max<size_t>(1, std::min<size_t>((size_t)Lo.lanes, ns));
+        struct Lane {
+            hipStream_t st;
+            V* v[2];
+            double2* psi;
+            unsigned char* tree;
+        };
+        std::vector<Lane> lanes((size_t)nl);
+        std::vector<hipEvent_t> evs;
+        auto cleanup = [&]() {
+            for (size_t l = 1; l < lanes.size(); ++l)
+                if (lanes[l].st) (void)hipStreamDestroy(lanes[l].st);
+            for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        };
+        lanes[0] = {st, {vS[0], vS[1]}, psi_s, base + Lo.tree};
+        hipEvent_t start = nullptr;
+        if (nl > 1) {
+            if ((s = hip_check(hipEventCreateWithFlags(&start, hipEventDisableTiming), "hipEventCreate")) != HSF_OK)
+                return s;
+            evs.push_back(start);
+            if ((s = hip_check(hipEventRecord(start, st), "hipEventRecord")) != HSF_OK) {
+                cleanup();
+                return s;
+            }
+        }
+        for (int l = 1; l < nl; ++l) {
+            unsigned char* lb = base + Lo.lane + (size_t)(l - 1) * Lo.lane_bytes;
+            Lane& ln = lanes[(size_t)l];
+            ln.st = nullptr;
+            ln.v[0] = (V*)lb;
+            lb += align256((size_t)chunk * dim[0] * sizeof(V));
+            ln.v[1] = (V*)lb;
+            lb += align256((size_t)chunk * dim[1] * sizeof(V));
+            ln.psi = (double2*)lb;
+            lb += align256((size_t)nx * 16);
+            ln.tree = lb;
+            if ((s = hip_check(hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking), "hipStreamCreate")) != HSF_OK ||
+                (s = hip_check(hipStreamWaitEvent(ln.st, start, 0), "hipStreamWaitEvent")) != HSF_OK) {
+                cleanup();
+                return s;
+            }
+        }
         DeviceCopy dd = d;
-        for (size_t i = 0; i < ns; ++i) {
+        for (size_t i = 0; i < ns && s == HSF_OK; ++i) {
+            const Lane& ln = lanes[i % (size_t)nl];
             for (int side = 0; side < 2; ++side)
                 for (int tr = 0; tr < 2; ++tr) {
                     std::vector<DeviceSchedule>& dv = tr ? dd.tree[side] : dd.side[side];
                     for (size_t q = 0; q < dv.size(); ++q) dv[q].pool = pools + i * Lo.pool_elems + pool_at[2 * side + tr][q];
                 }
-            for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
+            for (int64_t p0 = 0; p0 < p.P && s == HSF_OK; p0 += chunk) {
                 const int64_t np = std::min(chunk, p.P - p0);
-                if ((s = run_sides(p, dd, p0, np, vS[0], dim[0], vS[1], dim[1], base + Lo.tree, Lo.tree_bytes, st)) !=
-                    HSF_OK)
-                    return s;
-                if ((s = gather_dot(p.dtype, vS[0], dim[0], vS[1], dim[1], np, p.nb, p.n, x, nx, psi_s,
-                                    p0 > 0 ? 1 : 0, st)) != HSF_OK)
-                    return s;
+                s = run_sides(p, dd, p0, np, ln.v[0], dim[0], ln.v[1], dim[1], ln.tree, Lo.tree_bytes, ln.st);
+                if (s == HSF_OK)
+                    s = gather_dot(p.dtype, ln.v[0], dim[0], ln.v[1], dim[1], np, p.nb, p.n, x, nx, ln.psi,
+                                   p0 > 0 ? 1 : 0, ln.st);
             }
-            hipLaunchKernelGGL(bw_loss, dim3(1), dim3(256), 0, st, (const double2*)psi_s, nx, lossb + i);
-            if ((s = hip_check(hipGetLastError(), "bw_loss launch")) != HSF_OK) return s;
+            if (s != HSF_OK) break;
+            hipLaunchKernelGGL(bw_loss, dim3(1), dim3(256), 0, ln.st, (const double2*)ln.psi, nx, lossb + i);
+            s = hip_check(hipGetLastError(), "bw_loss launch");
+        }
+        // the caller's stream waits for every lane before combining
+        for (int l = 1; l < nl && s == HSF_OK; ++l) {
+            hipEvent_t e = nullptr;
+            if ((s = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate")) != HSF_OK) break;
+            evs.push_back(e);
+            if ((s = hip_check(hipEventRecord(e, lanes[(size_t)l].st), "hipEventRecord")) != HSF_OK ||
+                (s = hip_check(hipStreamWaitEvent(st, e, 0), "hipStreamWaitEvent")) != HSF_OK)
+                break;
+        }
+        if (s != HSF_OK) {
+            for (int l = 1; l < nl; ++l)
+                if (lanes[(size_t)l].st) (void)hipStreamSynchronize(lanes[(size_t)l].st);
+            cleanup();
+            return s;
         }
         // dL/dt += (L(t + pi/2) - L(t - pi/2)) / 2 per occurrence, in plan order
-        for (size_t i = 0; i < ns; i += 2) {
+        for (size_t i = 0; i < ns && s == HSF_OK; i += 2) {
             hipLaunchKernelGGL(bw_shift_combine, dim3(1), dim3(1), 0, st, lossb + i, lossb + i + 1, grad,
                                (int64_t)shifts[i].t);
-            if ((s = hip_check(hipGetLastError(), "bw_shift_combine launch")) != HSF_OK) return s;
+            s = hip_check(hipGetLastError(), "bw_shift_combine launch");
         }
+        // the lanes' streams go once the caller's stream has drained them
+        const hsf_status sync = hip_check(hipStreamSynchronize(st), "sync");
+        cleanup();
+        if (s != HSF_OK) return s;
+        return sync;
     }
     // host staging buffers above must outlive their async uploads
     return hip_check(hipStreamSynchronize(st), "sync");
