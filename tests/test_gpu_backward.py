@@ -73,6 +73,50 @@ def test_random_rotations_outside_blocks_only():
     _check(c, xs, "c64")
 
 
+def _runs_circuit(kinds_1q, kinds_2q, seed):
+    # long runs of one- and two-qubit rotations on few qubits, a three-qubit
+    # unitary in the middle of them, angles at every position of a run
+    rng = np.random.default_rng(seed)
+    gs, pid = [], 0
+    for layer in range(5):
+        for q in (0, 1, 2, 5, 6, 7):
+            gs.append(cg.gate(kinds_1q[rng.integers(len(kinds_1q))], (q,), param=rng.uniform(0, 6), param_id=pid))
+            pid += 1
+        for a, b in ((0, 1), (1, 2), (5, 6), (6, 7)):
+            gs.append(cg.gate(kinds_2q[rng.integers(len(kinds_2q))], (a, b), param=rng.uniform(0, 6), param_id=pid))
+            pid += 1
+        if layer == 2:
+            gs.append(cg.gate("U", (0, 1, 2), matrix=cg.haar_unitary(rng, 8)))
+            gs.append(cg.gate("U", (7, 6, 5), matrix=cg.haar_unitary(rng, 8)))
+        gs.append(cg.gate("CZ", (3, 4)))
+        gs.append(cg.gate("RY", (3,), param=rng.uniform(0, 6), param_id=pid))
+        pid += 1
+        gs.append(cg.gate("RY", (4,), param=rng.uniform(0, 6), param_id=pid))
+        pid += 1
+    return cg.circuit("runs", 8, gs, 3, [[i] for i, g in enumerate(gs) if cg.crossing(g, 3)])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_adjoint_runs_and_wide_gates(dtype):
+    # the adjoint pass undoes runs of gates on up to three qubits in
+    # registers and wider gates one by one
+    c = _runs_circuit(("RX", "RY", "RZ"), ("RZZ",), 21)
+    _check(c, np.arange(1, 256, 5, dtype=np.uint64), dtype)
+
+
+def test_phase_angles_against_finite_differences():
+    # PHASE and CP angles (generator i|1><1|) in runs, against the oracle's
+    # central differences (h = 1e-4: truncation far below the bar)
+    c = _runs_circuit(("PHASE", "RY"), ("CP", "RZZ"), 22)
+    xs = np.arange(1, 256, 5, dtype=np.uint64)
+    ref = OG.loss_grad_fd(c, xs, h=1e-4, use_hsf=True)
+    plan = Plan(c, dtype="c128")
+    x = torch.from_numpy(np.asarray(xs, dtype=np.int64)).cuda()
+    g = plan.backward(x).cpu().numpy()
+    r = np.array([ref.get(t, 0.0) for t in range(plan.n_params)])
+    assert np.max(np.abs(g - r)) / np.max(np.abs(r)) < 1e-6
+
+
 def test_autograd_function():
     c = cg.c3(seed=5, n=8, layers=4)
     xs = cg.c3_bitstrings(n=8, count=32, seed=11)
