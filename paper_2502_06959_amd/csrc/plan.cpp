@@ -771,6 +771,26 @@ std::vector<SideOp> level_order(const Plan& p, int side, std::vector<int>& cuts,
         out.push_back(sp.ops[idx[i]]);
     }
     cuts.push_back(n);
+    // A thin level costs a pass of its own (every state read and written)
+    // for few ops: it joins the next level when repeating its ops on the
+    // next level's states costs less than that pass -- about 1.5 units per op
+    // and state against 8 for a state's load, store and launch share (the
+    // sweep estimate's units).  Level 0, the shared prefix, stays.
+    auto states = [&](int lv) {
+        double st = 1;
+        for (int k = 0; k < lv && k < (int)p.blocks.size(); ++k) st *= (double)p.blocks[k].rank;
+        return st;
+    };
+    for (size_t r = 1; r + 2 < cuts.size();) {
+        const double ops = (double)(cuts[r + 1] - cuts[r]);
+        const double ratio = states(levels[r + 1]) / states(levels[r]);
+        if (ops * 1.5 * (ratio - 1.0) < 8.0) {
+            cuts.erase(cuts.begin() + (std::ptrdiff_t)(r + 1));   // range r absorbs range r + 1
+            levels.erase(levels.begin() + (std::ptrdiff_t)r);    // and takes its (higher) level
+        } else {
+            ++r;
+        }
+    }
     for (size_t r = 1; r + 1 < cuts.size(); ++r) order_pieces(out, (size_t)cuts[r], (size_t)cuts[r + 1]);
     return out;
 }

@@ -161,10 +161,18 @@ def test_path_tree_levels_by_hand():
     c = cg.circuit("levels", 4, gates, 1, [[4], [7]])
     p = Plan(c, fuse=False, tree="on")
     assert p.P == 4
-    # side a: H2 H3 H3 | slot0 RX2 RZ2 | slot1 ; side b: H0 H1 RX0 | slot0 | slot1 RX1
-    assert p.side_levels(0) == [(3, 1), (3, 2), (1, 4)]
-    assert p.side_levels(1) == [(3, 1), (1, 2), (2, 4)]
+    # levels -- side a: H2 H3 H3 | slot0 RX2 RZ2 | slot1 ; side b: H0 H1 RX0 |
+    # slot0 | slot1 RX1.  Then a thin level joins the next when repeating its
+    # ops on the next level's states costs less than its own pass (1.5 per op
+    # and extra state against 8 per state): side a's level 1 (3 ops, 2 -> 4
+    # states: 4.5 < 8) and side b's (1 op: 1.5 < 8) both join level 2
+    assert p.side_levels(0) == [(3, 1), (4, 4)]
+    assert p.side_levels(1) == [(3, 1), (3, 4)]
     assert p.side_stats(0)["ops_shared"] == 3 and p.side_stats(1)["ops_shared"] == 3
+    # thick levels keep their boundaries (C3 at n=12, side a: 13, 10 and 2
+    # ops on 4, 16 and 32 states)
+    q = Plan(cg.c3(seed=3, n=12, layers=8), tree="on")
+    assert [n for _, n in q.side_levels(0)] == [1, 4, 16, 32]
 
 
 def test_path_tree_options_and_invariants():
