@@ -292,8 +292,11 @@ hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dt
  * device doubles, overwritten.  Paths are processed `chunk` at a time; ws:
  * hsf_workspace_size(plan, 2, chunk, n_x) bytes.  Reductions run in a fixed
  * order (bitwise reproducible).  Synchronises `stream` (host tables are
- * staged through it), so it cannot be captured in a graph.  Returns
- * HSF_E_UNSUPPORTED if a shifted block needs more Schmidt terms than the plan. */
+ * staged through it), so it cannot be captured in a graph; the shifted
+ * forward runs also use up to three streams of its own (default priority,
+ * created and destroyed within the call, joined to `stream` before it
+ * returns).  Returns HSF_E_UNSUPPORTED if a shifted block needs more Schmidt
+ * terms than the plan.                                                       */
 hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* grad,
                         int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes,
                         hsf_stream_t stream);
