@@ -254,7 +254,10 @@ hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* 
  * c < 2^n_b.  Input type: the plan's dtype.  Output type: c64 for HSF_SUM_F32
  * and HSF_SUM_BF16X3, c128 for HSF_SUM_F64 / HSF_SUM_C128.  accumulate = 1
  * adds into `out` (path chunks, resume).  ws: hsf_workspace_size(plan, 1,
- * n_paths, mode) bytes (only HSF_SUM_BF16X3 uses it).                        */
+ * n_paths, mode) bytes (only HSF_SUM_BF16X3 uses it).  n_paths = 0 is the
+ * empty sum: the rows are set to zero (left as they are with accumulate = 1)
+ * and psiA / psiB are not read (they may be NULL).  An empty row range
+ * writes nothing and `out` may then be NULL.                                */
 hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA,
                                const void* psiB, int64_t ldB, int64_t n_paths,
                                int64_t row_begin, int64_t row_end, void* out, int64_t ldo,
@@ -264,7 +267,9 @@ hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA,
 /* Amplitudes of chosen basis states (Sec. V computes a subset):
  * out[j] = sum_{p < n_paths} psiA[p][x_j >> n_b] psiB[p][x_j & (2^n_b - 1)],
  * accumulated in FP64; `out` is c128 (2 doubles per entry).  x: device
- * array of n_x indices < 2^n.  accumulate = 1 adds into `out`.               */
+ * array of n_x indices < 2^n.  accumulate = 1 adds into `out`.  n_x = 0
+ * writes nothing (x and out may then be NULL); n_paths = 0 gives zeros (psiA
+ * and psiB may then be NULL).                                                */
 hsf_status hsf_amplitudes_bitstrings(hsf_plan_t plan, const void* psiA, int64_t ldA,
                                      const void* psiB, int64_t ldB, int64_t n_paths,
                                      const uint64_t* x, int64_t n_x, void* out,
@@ -275,7 +280,8 @@ hsf_status hsf_amplitudes_bitstrings(hsf_plan_t plan, const void* psiA, int64_t 
 /* FP64-accumulated sums over n complex entries of type dtype: out[0] =
  * sum |a_i|^2 and, if b != NULL, out[1] = sum |a_i - b_i|^2 (b of the same
  * type; b may be c64 or c128 per b_dtype).  out: 2 device doubles.
- * Deterministic (fixed reduction order).  ws: at least 4096 doubles.          */
+ * Deterministic (fixed reduction order).  ws: at least 4096 doubles.  n = 0
+ * gives zeros (a may then be NULL).                                          */
 hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dtype, int64_t n,
                      double* out, void* ws, size_t ws_bytes, hsf_stream_t stream);
 
@@ -296,7 +302,8 @@ hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dt
  * forward runs also use up to three streams of its own (default priority,
  * created and destroyed within the call, joined to `stream` before it
  * returns).  Returns HSF_E_UNSUPPORTED if a shifted block needs more Schmidt
- * terms than the plan.                                                       */
+ * terms than the plan.  n_x = 0, or a circuit without angles, gives a zero
+ * gradient.                                                                  */
 hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* grad,
                         int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes,
                         hsf_stream_t stream);

@@ -215,7 +215,7 @@ hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA, c
                                void* out, int64_t ldo, int32_t mode, int32_t accumulate, void* ws,
                                size_t ws_bytes, hsf_stream_t stream) {
     HSF_GUARD_BEGIN
-    if (!plan || !psiA || !psiB || !out) return fail(HSF_E_ARG, "null argument");
+    if (!plan || (n_paths > 0 && (!psiA || !psiB))) return fail(HSF_E_ARG, "null argument");
     const Plan* p = P_(plan);
     const int64_t M = int64_t(1) << p->na, N = int64_t(1) << p->nb;
     if (n_paths < 0) return fail(HSF_E_ARG, "negative path count");
@@ -227,6 +227,7 @@ hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA, c
     if (mode == HSF_SUM_BF16X3 && ws_bytes < bf16x3_workspace(p->na, p->nb, n_paths))
         return fail(HSF_E_ARG, "workspace too small for HSF_SUM_BF16X3");
     if (row_begin == row_end) return HSF_OK;
+    if (!out) return fail(HSF_E_ARG, "null argument");
     return path_sum(p->dtype, mode, psiA, ldA, psiB, ldB, n_paths, row_begin, row_end - row_begin, N,
                     out, ldo, accumulate, ws, (hipStream_t)stream);
     HSF_GUARD_END
@@ -236,7 +237,8 @@ hsf_status hsf_amplitudes_bitstrings(hsf_plan_t plan, const void* psiA, int64_t 
                                      int64_t ldB, int64_t n_paths, const uint64_t* x, int64_t n_x,
                                      void* out, int32_t accumulate, hsf_stream_t stream) {
     HSF_GUARD_BEGIN
-    if (!plan || !psiA || !psiB || !out || (n_x > 0 && !x)) return fail(HSF_E_ARG, "null argument");
+    if (!plan || (n_x > 0 && (!x || !out)) || (n_x > 0 && n_paths > 0 && (!psiA || !psiB)))
+        return fail(HSF_E_ARG, "null argument");
     const Plan* p = P_(plan);
     if (n_paths < 0 || n_x < 0) return fail(HSF_E_ARG, "negative size");
     if (ldA < (int64_t(1) << p->na) || ldB < (int64_t(1) << p->nb)) return fail(HSF_E_ARG, "leading dimension too small");
@@ -249,7 +251,7 @@ hsf_status hsf_amplitudes_bitstrings(hsf_plan_t plan, const void* psiA, int64_t 
 hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dtype, int64_t n, double* out,
                      void* ws, size_t ws_bytes, hsf_stream_t stream) {
     HSF_GUARD_BEGIN
-    if (!a || !out || !ws) return fail(HSF_E_ARG, "null argument");
+    if ((!a && n > 0) || !out || !ws) return fail(HSF_E_ARG, "null argument");
     if ((a_dtype != HSF_C64 && a_dtype != HSF_C128) || (b && b_dtype != HSF_C64 && b_dtype != HSF_C128))
         return fail(HSF_E_ARG, "dtype must be HSF_C64 or HSF_C128");
     if (n < 0) return fail(HSF_E_ARG, "negative size");

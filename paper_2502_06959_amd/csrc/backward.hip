@@ -828,6 +828,12 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
     using V = typename Cx<T>::v;
     const Layout Lo = layout(p, chunk, nx);
     if (ws_bytes < Lo.total) return fail(HSF_E_ARG, "workspace too small for hsf_backward");
+    if (nx == 0 || p.n_params == 0) {
+        // no bitstrings (L = 0 for every angle) or no angles: the gradient is zero
+        hipLaunchKernelGGL(bw_zero_doubles, dim3(std::max<uint32_t>(1, (uint32_t)((n_params + 255) / 256))), dim3(256),
+                           0, st, grad, n_params);
+        return hip_check(hipGetLastError(), "zero grad");
+    }
     unsigned char* base = reinterpret_cast<unsigned char*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
     V* vS[2] = {(V*)(base + Lo.vA), (V*)(base + Lo.vB)};
     V* lS[2] = {(V*)(base + Lo.lA), (V*)(base + Lo.lB)};

@@ -223,6 +223,16 @@ __global__ __launch_bounds__(256) void gather_dot_kernel(const VIN* __restrict__
 // ------------------------------------------------------------------ norms ----
 constexpr int NORM_BLOCKS = 4096;
 
+// Rows of the empty sum (no paths): `rows` rows of `cols` 8-byte words, row
+// stride `ld` words, set to zero.
+__global__ __launch_bounds__(256) void zero_rows(uint2* __restrict__ out, int64_t ld, int64_t rows, int64_t cols) {
+    const int64_t total = rows * cols;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int64_t r = i / cols;
+        out[r * ld + (i - r * cols)] = make_uint2(0u, 0u);
+    }
+}
+
 template <typename VA, typename VB, bool HAS_B>
 __global__ __launch_bounds__(256) void norm_partial(const VA* __restrict__ a, const VB* __restrict__ b, int64_t n,
                                                     double* __restrict__ part) {
@@ -315,6 +325,15 @@ hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_
 hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K,
                     int64_t row0, int64_t M, int64_t N, void* out, int64_t ldo, int accumulate, void* ws,
                     hipStream_t st) {
+    if (K == 0) {
+        // the sum over no paths: zero rows, nothing to add when accumulating;
+        // the operands are not read
+        if (accumulate) return HSF_OK;
+        const int64_t words = (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3) ? 1 : 2;
+        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(4096, (M * N * words + 255) / 256));
+        hipLaunchKernelGGL(zero_rows, dim3((uint32_t)blocks), dim3(256), 0, st, (uint2*)out, ldo * words, M, N * words);
+        return hip_check(hipGetLastError(), "zero_rows launch");
+    }
     if (dtype == HSF_C64 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3) &&
         path_sum_lds_fits(mode, (const float2*)A + row0, ldA, B, ldB, K, M, N)) {
         if (mode == HSF_SUM_F32)
