@@ -235,13 +235,13 @@ def main():
     # dominant kernel roofline
     if sum_ms >= sweep_ms:
         src = _src_hash("pathsum.hip", "bf16x3.hip", "epilogue.h")
-        # the timed path-sum call: one MFMA kernel (FP32), or the two split
-        # passes plus the MFMA kernel (split-BF16 x3)
+        # the timed path-sum call: one MFMA kernel (FP32), or the split of both
+        # operands plus the MFMA kernel (split-BF16 x3)
         many = P >= 128      # LDS-staged kernels from 128 paths on
         if args.mode == "f32":
             kern = "pathsum_f32_lds" if many else "pathsum_f32"
         else:
-            kern = "split_chunked x2 + pathsum_bf16x3_lds" if many else "split_planes x2 + pathsum_bf16x3_kernel"
+            kern = "split_chunked x2 + pathsum_bf16x3_lds" if many else "split_planes + pathsum_bf16x3_kernel"
         ach_tf = flops / (sum_ms * 1e-3) / 1e12
         if args.mode == "f32":
             bound, peak, unit, achieved = "mfma", MFMA_PEAK["f32"], "TFLOP/s", ach_tf

@@ -31,10 +31,22 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
 
+// One operand of the split: R rows of X (row k of path k at X + k ldx) into
+// `planes`.
+struct SplitOperand {
+    const float2* X;
+    int64_t ldx, R;
+    unsigned short* planes;
+};
+
 // planes[p][r][k] for p in {re hi, re lo, im hi, im lo}, r < R, k < Kp.
-// Thread: one row r, eight consecutive paths k0..k0+7 (zero beyond K).
-__global__ __launch_bounds__(256) void split_planes(const float2* __restrict__ X, int64_t ldx, int64_t K,
-                                                    int64_t R, int64_t Kp, unsigned short* __restrict__ planes) {
+// Thread: one row r, eight consecutive paths k0..k0+7 (zero beyond K).  Both
+// operands in one launch: blockIdx.z 0 splits a, 1 splits b.
+__global__ __launch_bounds__(256) void split_planes(SplitOperand a, SplitOperand b, int64_t K, int64_t Kp) {
+    const bool second = blockIdx.z != 0;
+    const float2* __restrict__ X = second ? b.X : a.X;
+    const int64_t ldx = second ? b.ldx : a.ldx, R = second ? b.R : a.R;
+    unsigned short* __restrict__ planes = second ? b.planes : a.planes;
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t k0 = (int64_t)blockIdx.y * 8;
     if (r >= R || k0 >= Kp) return;
@@ -384,11 +396,10 @@ hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_
     unsigned short* PA = reinterpret_cast<unsigned short*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
     unsigned short* PB = PA + 4 * M * Kp;
     {
-        const dim3 ga((uint32_t)((M + 255) / 256), (uint32_t)(Kp / 8));
-        const dim3 gb((uint32_t)((N + 255) / 256), (uint32_t)(Kp / 8));
-        if (ga.y > 65535u) return fail(HSF_E_ARG, "too many paths in one HSF_SUM_BF16X3 call (split the path range)");
-        hipLaunchKernelGGL(split_planes, ga, dim3(256), 0, st, A, ldA, K, M, Kp, PA);
-        hipLaunchKernelGGL(split_planes, gb, dim3(256), 0, st, B, ldB, K, N, Kp, PB);
+        const dim3 g((uint32_t)((std::max(M, N) + 255) / 256), (uint32_t)(Kp / 8), 2);
+        if (g.y > 65535u) return fail(HSF_E_ARG, "too many paths in one HSF_SUM_BF16X3 call (split the path range)");
+        const SplitOperand a{A, ldA, M, PA}, b{B, ldB, N, PB};
+        hipLaunchKernelGGL(split_planes, g, dim3(256), 0, st, a, b, K, Kp);
         hsf_status s = hip_check(hipGetLastError(), "split_planes launch");
         if (s != HSF_OK) return s;
     }
