@@ -237,7 +237,7 @@ def main():
         src = _src_hash("pathsum.hip", "bf16x3.hip", "epilogue.h")
         # the timed path-sum call: one MFMA kernel (FP32), or the split of both
         # operands plus the MFMA kernel (split-BF16 x3)
-        many = P >= 128      # LDS-staged kernels from 128 paths on
+        many = P >= 64       # LDS-staged kernels from 64 paths on
         if args.mode == "f32":
             kern = "pathsum_f32_lds" if many else "pathsum_f32"
         else:

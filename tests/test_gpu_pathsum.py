@@ -29,7 +29,7 @@ def _rand(rng, k, d, dtype):
     return x.astype(dtype)
 
 
-# K >= 128 takes the LDS-staged kernels: several tiles, ragged path chunks
+# K >= 64 takes the LDS-staged kernels: several tiles, ragged path chunks
 # (K mod 16, K mod 32 != 0) and tiles cut by M or N < 128
 CASES = [(1, 1, 1), (5, 3, 2), (6, 6, 3), (7, 8, 17), (9, 7, 33), (8, 8, 64), (10, 6, 100), (6, 10, 257),
          (12, 12, 32), (3, 11, 7), (7, 7, 128), (9, 8, 300), (5, 10, 1000), (10, 4, 161), (8, 9, 4096)]
