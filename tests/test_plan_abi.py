@@ -129,6 +129,15 @@ def test_null_and_range_arguments():
     d = (ctypes.c_int32 * 8)()
     assert lib.hsf_path_digits(ctypes.c_void_p(p.handle), p.P, d) == 1
     assert lib.hsf_workspace_size(ctypes.c_void_p(p.handle), 1, 16, 1) > 0
+    # empty calls need no buffers and return before any device work
+    h, ma, mb = ctypes.c_void_p(p.handle), 1 << p.na, 1 << p.nb
+    assert lib.hsf_run_paths(h, 3, 3, None, 0, None, 0, None, 0, None) == 0
+    assert lib.hsf_amplitudes_full(h, None, ma, None, mb, 0, 3, 3, None, mb, 3, 0, None, 0, None) == 0
+    assert lib.hsf_amplitudes_bitstrings(h, None, ma, None, mb, 0, None, 0, None, 0, None) == 0
+    # paths without operands, or rows without an output: errors
+    assert lib.hsf_amplitudes_full(h, None, ma, None, mb, 4, 0, 1, None, mb, 3, 0, None, 0, None) == 1
+    assert "null" in lib.hsf_last_error().decode()
+    assert lib.hsf_amplitudes_bitstrings(h, None, ma, None, mb, 4, None, 2, None, 0, None) == 1
 
 
 def test_multi_pass_schedule_shapes():
