@@ -2,21 +2,30 @@
 per-path half-state sweeps of both sides for all paths, then the path sum
 into every output amplitude -- over a seeded synthetic circuit.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2p] [--mode bf16x3|f32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2p|c2|c3|c5|qaoa]
     python bench.py --calibrate-copy      # a plain 1 GiB device copy, for counter scaling
 
-Prints one JSON line.  `value` is logical path-gate updates per second of
-the whole step (paths x circuit ops of both sides, Schmidt-factor slots
-included, divided by the step time) with the chosen path sum (split-BF16
-x3); the same step with the plain FP32 path sum ("plain c64 HSF") is timed
-beside it.  The path-sum TFLOP/s, the per-phase times, the roofline of the
-dominant phase and the FP64 oracle's throughput on the host (bounded sample)
-ride along.
+The default workload is the largest single-GPU configuration: n = 34, cut
+17|17, P = 4096 paths, all 2^34 amplitudes (128 GiB of complex64, resident
+in HBM) in 16 row tiles of 2^13 rows.  A step sweeps all paths, splits both
+operands into BF16 hi/lo planes once, and runs the split-BF16 x3 path sum on
+every row tile; the same step with the plain FP32 path sum ("plain c64 HSF")
+is timed beside it.
+
+Prints one JSON line.  `value` is executed path-gate updates per second of
+the whole step: fused ops applied to half-states as the sweeps run them (the
+shared prefix once, each path-tree level once per state), divided by the
+step time; logical updates (every path x every circuit op, the count a
+per-path simulation does) are reported beside it.  Step times are the mean
+over the timed steps, with std and median (the paper reports mean and std
+of 5 runs).  The roofline object covers the dominant kernel, timed with HIP
+events around each of its launches on the stream it runs on.
 """
 import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -24,7 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK = {"f32": 157.3, "bf16x3": 2500.0, "f64": 78.6}   # TFLOP/s, dense, MI355X datasheet
+MFMA_PEAK = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}   # TFLOP/s, dense, MI355X datasheet
+METRIC = "path-gate updates/s (%HBM peak) + path-sum TFLOP/s; vs plain c64 HSF at rel-L2\u22641e-5"
 
 WORKLOADS = {
     # name: (generator, description)
@@ -35,12 +45,23 @@ WORKLOADS = {
 }
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _src_hash(*names):
     h = hashlib.sha256()
     for n in names:
         with open(os.path.join(ROOT, "paper_2502_06959_amd", "csrc", n), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:12]
+
+
+def _stats(xs):
+    import numpy as np
+    a = np.asarray(xs, dtype=np.float64)
+    return {"mean": float(a.mean()), "std": float(a.std(ddof=1)) if len(a) > 1 else 0.0,
+            "median": float(np.median(a)), "n": int(len(a))}
 
 
 def _paths_ws(plan, n_paths):
@@ -68,56 +89,83 @@ def _executed_ops(plan, side, n_paths):
     return lv[0][0] + n_paths * sum(o for o, _ in lv[1:])
 
 
+def _updates(plan):
+    """(executed, logical) path-gate updates of one sweep over all paths."""
+    ex = _executed_ops(plan, 0, plan.P) + _executed_ops(plan, 1, plan.P)
+    lg = plan.P * (plan.side_stats(0)["ops_logical"] + plan.side_stats(1)["ops_logical"])
+    return ex, lg
+
+
 def _traffic_from_profiles(kernel, src_hash, workload):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE +
-    WRITE_SIZE, copy-kernel calibrated), read from profiles/traffic.md if it
-    was taken on the current kernel source and this workload; else None."""
+    WRITE_SIZE, copy-kernel calibrated), from profiles/traffic.md rows
+    `| kernel | workload | source hash | bytes per launch | ...` taken on the
+    current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.md")
     if not os.path.exists(path):
         return None
-    head = open(path).readline()
-    if not head.strip().endswith(f"workload {workload}"):
-        return None
     for line in open(path):
-        parts = line.strip().strip("|").split("|")
-        parts = [p.strip() for p in parts]
-        if len(parts) >= 4 and parts[0] == kernel and parts[1] == src_hash:
+        parts = [p.strip() for p in line.strip().strip("|").split("|")]
+        if len(parts) >= 4 and parts[0] == kernel and parts[1] == workload and parts[2] == src_hash:
             try:
-                return float(parts[2])
+                return float(parts[3])
             except ValueError:
                 return None
     return None
 
 
-def cpu_baseline(circuit, plan_stats, P, na, nb, budget_s=20.0):
-    """The FP64 oracle (test infrastructure, untuned) on the host: half-states
-    of every path for both sides plus the path sum for a sample of output
-    rows, extrapolated to the full step in the same unit as `value`."""
+def _host():
+    """Host CPU model and thread count the oracle runs with."""
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return model, threads
+
+
+def cpu_baseline(circuit, plan, budget_paths=None, rows=256):
+    """The FP64 oracle (test infrastructure, untuned) on the host, on a
+    bounded sample of the same workload: half-states of a sample of paths on
+    both sides and the path sum of a sample of output rows over those paths,
+    extrapolated linearly to all paths and rows (both costs are linear in
+    each).  Returns the oracle's own executed path-gate updates per second
+    (it runs every op on every path) and its extrapolated step time."""
     import numpy as np
     from oracle import hsf as ohsf
+    P, na, nb = plan.P, plan.na, plan.nb
+    n_s = min(P, budget_paths or max(1, min(P, (32 << 17) >> max(na, nb))))
+    paths = np.linspace(0, P - 1, n_s).round().astype(np.int64)
     t0 = time.perf_counter()
     o = ohsf.plan(circuit)
     ta = time.perf_counter()
-    a = ohsf.half_states(circuit, o, "A")
-    b = ohsf.half_states(circuit, o, "B")
+    a = ohsf.half_states(circuit, o, "A", paths=paths)
+    b = ohsf.half_states(circuit, o, "B", paths=paths)
     tb = time.perf_counter()
-    rows = 1024
+    rows = min(rows, 1 << na)
     rr = np.arange(rows)
     reps = 0
     tr0 = time.perf_counter()
     while True:
         ohsf.amplitudes_rows(a, b, rr)
         reps += 1
-        if time.perf_counter() - tr0 > min(5.0, budget_s / 4):
+        if time.perf_counter() - tr0 > 2.0:
             break
     t_rows = (time.perf_counter() - tr0) / reps
-    t_step = (tb - ta) + t_rows * ((1 << na) / rows)
-    logical = P * (plan_stats[0] + plan_stats[1])
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": logical / t_step, "unit": "path-gate updates/s", "cores": cores, "kind": "oracle",
-            "sample": (f"oracle plan + half-states of all {P} paths on both sides "
-                       f"({tb - ta:.2f} s) + path sum of {rows} of {1 << na} output rows x{reps} "
-                       f"({t_rows * 1e3:.1f} ms each), extrapolated to all rows; plan {ta - t0:.3f} s"),
+    scale = P / n_s
+    t_step = (tb - ta) * scale + t_rows * ((1 << na) / rows) * scale
+    logical = P * (plan.side_stats(0)["ops_logical"] + plan.side_stats(1)["ops_logical"])
+    model, threads = _host()
+    return {"value": logical / t_step, "unit": "path-gate updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model,
+            "sample": (f"oracle plan ({ta - t0:.3f} s) + half-states of {n_s} of {P} paths on both sides "
+                       f"({tb - ta:.2f} s) + path sum of {rows} of {1 << na} output rows over those paths "
+                       f"x{reps} ({t_rows * 1e3:.1f} ms each), extrapolated to all paths and rows; the oracle "
+                       f"applies every op to every path, so its updates are the logical count"),
             "step_s_extrapolated": t_step}
 
 
@@ -126,13 +174,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2p", choices=sorted(WORKLOADS) + ["c3", "c4", "c5", "qaoa"])
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["c3", "c4", "c5", "qaoa"])
     ap.add_argument("--mode", default="bf16x3", choices=["f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP32 path sum")
+    ap.add_argument("--plain-steps", type=int, default=None,
+                    help="timed steps of the plain FP32 leg (default: all steps, at most 2 on c4)")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--c4-mode", default=None, choices=["f32", "bf16x3", "f64"])
     ap.add_argument("--tree", default="auto", choices=["auto", "on", "off"],
                     help="path-tree sweeps (one state per distinct leading-digit prefix)")
     args = ap.parse_args()
@@ -152,12 +201,7 @@ def main():
               "described in the design notes but not run. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    import circuitgen as cg
-    from paper_2502_06959_amd import Plan
-
     torch.cuda.set_device(0)
     if args.workload == "c5":
         return bench_c5(args)
@@ -167,16 +211,43 @@ def main():
         return bench_qaoa(args)
     if args.workload == "c3":
         return bench_c3(args)
+    return bench_full(args)
+
+
+def _dominant_roofline(kind, kern, src, workload, per_launch, launch_ms):
+    """Roofline object of the dominant kernel: `per_launch` algorithmic
+    flops (kind mfma-*) or bytes (hbm) of one launch over its average
+    event-timed duration."""
+    if kind == "hbm":
+        achieved = per_launch / (launch_ms * 1e-3) / 1e9
+        bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved = per_launch / (launch_ms * 1e-3) / 1e12
+        bound, peak, unit = "mfma", MFMA_PEAK[kind.split("-")[1]], "TFLOP/s"
+    return {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": _traffic_from_profiles(kern, src, workload),
+            "launch_ms": launch_ms, "per_launch": per_launch}
+
+
+def bench_full(args):
+    """c2p / c2: one plan, every output amplitude in one path-sum call."""
+    import numpy as np
+    import torch
+
+    import circuitgen as cg
+    from paper_2502_06959_amd import Plan
     gen, desc = WORKLOADS[args.workload]
     circuit = getattr(cg, gen)()
     t0 = time.perf_counter()
     plan = Plan(circuit, dtype="c64", tree=args.tree)
     plan_s = time.perf_counter() - t0
     P, na, nb = plan.P, plan.na, plan.nb
-    sa, sb = plan.side_stats(0), plan.side_stats(1)
     A, B = plan.alloc_halves(P)
     out = torch.empty((1 << na, 1 << nb), dtype=torch.complex64, device="cuda")
     sw_ws = _paths_ws(plan, P)
+    plan.run_paths(0, 1, A[:1], B[:1])        # tables to the device, prefix states: set-up, not timed
+    torch.cuda.synchronize()
+    cache = {}
 
     def run_mode(mode, steps, warmup):
         ws = None
@@ -190,23 +261,29 @@ def main():
             plan.run_paths(0, P, A, B, ws=sw_ws)
             if ev:
                 ev[1].record()
-            plan.amplitudes_full(A, B, mode=mode, out=out, ws=ws)
+            if mode == "bf16x3":
+                plan.split_operands(A, B, ws=ws)
             if ev:
                 ev[2].record()
+            plan.amplitudes_full(A, B, mode="bf16x3_split" if mode == "bf16x3" else mode, out=out, ws=ws)
+            if ev:
+                ev[3].record()
 
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
             step(evs[i])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        sweep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-        sum_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-        rel = None
+        r = {"ms_per_step": wall * 1e3 / steps,
+             "step_ms": _stats([e[0].elapsed_time(e[3]) for e in evs]),
+             "sweeps_ms": _stats([e[0].elapsed_time(e[1]) for e in evs]),
+             "split_ms": _stats([e[1].elapsed_time(e[2]) for e in evs]),
+             "path_sum_ms": _stats([e[2].elapsed_time(e[3]) for e in evs])}
         if not args.no_check:
             from oracle import hsf as ohsf
             if "oracle" not in cache:
@@ -215,82 +292,59 @@ def main():
             oa, ob = cache["oracle"]
             rows = np.random.default_rng(7).choice(1 << na, 32, replace=False)
             got = out[torch.from_numpy(rows).to("cuda")].cpu().numpy()
-            rel = ohsf.rel_l2(got, ohsf.amplitudes_rows(oa, ob, rows))
-        return wall * 1e3 / steps, sweep_ms, sum_ms, rel
+            r["rel_l2_sampled_rows"] = ohsf.rel_l2(got, ohsf.amplitudes_rows(oa, ob, rows))
+        return r
 
-    cache = {}
     plain = None
     if not args.no_plain and args.mode != "f32":
-        p_ms, p_sw, p_sum, p_rel = run_mode("f32", args.steps, args.warmup)
-        plain = {"path_sum": "f32", "ms_per_step": p_ms, "breakdown_ms": {"sweeps": p_sw, "path_sum": p_sum},
-                 "rel_l2_sampled_rows": p_rel}
-    ms_step, sweep_ms, sum_ms, rel = run_mode(args.mode, args.steps, args.warmup)
-
-    logical_updates = P * (sa["ops_logical"] + sb["ops_logical"])
+        log("plain FP32 path sum")
+        plain = run_mode("f32", args.plain_steps or args.steps, args.warmup)
+    log(f"{args.mode} path sum")
+    res_m = run_mode(args.mode, args.steps, args.warmup)
+    ms_step = res_m["ms_per_step"]
+    executed, logical = _updates(plan)
     flops = 8.0 * (1 << na) * (1 << nb) * P
-    value = logical_updates / (ms_step * 1e-3)
     out_bytes = 8.0 * (1 << na) * (1 << nb)
     in_bytes = 8.0 * P * ((1 << na) + (1 << nb))
-
-    # dominant kernel roofline
-    if sum_ms >= sweep_ms:
-        src = _src_hash("pathsum.hip", "bf16x3.hip", "epilogue.h")
-        # the timed path-sum call: one MFMA kernel (FP32), or the split of both
-        # operands plus the MFMA kernel (split-BF16 x3)
-        many = P >= 64       # LDS-staged kernels from 64 paths on
-        if args.mode == "f32":
-            kern = "pathsum_f32_lds" if many else "pathsum_f32"
-        else:
-            kern = "split_chunked x2 + pathsum_bf16x3_lds" if many else "split_planes + pathsum_bf16x3_kernel"
-        ach_tf = flops / (sum_ms * 1e-3) / 1e12
-        if args.mode == "f32":
-            bound, peak, unit, achieved = "mfma", MFMA_PEAK["f32"], "TFLOP/s", ach_tf
-        else:
-            # split-BF16 x3: 3 real BF16 products per FP32 product; bound by the output write
-            t_mfma = 3 * flops / (MFMA_PEAK["bf16x3"] * 1e12)
-            t_hbm = (out_bytes + in_bytes) / (HBM_PEAK_GBS * 1e9)
-            if t_hbm >= t_mfma:
-                bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
-                achieved = (out_bytes + in_bytes) / (sum_ms * 1e-3) / 1e9
-            else:
-                bound, peak, unit, achieved = "mfma", MFMA_PEAK["bf16x3"], "TFLOP/s", 3 * ach_tf
-        traffic = _traffic_from_profiles(kern, src, args.workload)
+    sum_ms = res_m["path_sum_ms"]["mean"]
+    if args.mode == "f32":
+        kern = "pathsum_f32_lds" if P >= 64 else "pathsum_f32"
+        roof = _dominant_roofline("mfma-f32", kern, _src_hash("pathsum.hip", "pathsum_lds.hip", "epilogue.h"),
+                                  args.workload, flops, sum_ms)
+    elif P >= 64:
+        roof = _dominant_roofline("mfma-bf16", "pathsum_bf16x3_lds", _src_hash("pathsum_lds.hip", "epilogue.h"),
+                                  args.workload, 3 * flops, sum_ms)
     else:
-        src = _src_hash("sweep.hip")
-        kern = "sweep_pass<float> (all passes)"
-        # ops are applied on-chip; the bound is the VALU (non-packed FP32:
-        # 256 CU x 64 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s); a one-qubit
-        # gate costs 14 flop per amplitude
-        # ops executed: the per-path ones on every path, the shared prefix once
-        ex_a, ex_b = _executed_ops(plan, 0, P), _executed_ops(plan, 1, P)
-        fl = 14.0 * ((1 << na) * ex_a + (1 << nb) * ex_b)
-        bound, peak, unit = "alu", 78.6, "TFLOP/s"
-        achieved = fl / (sweep_ms * 1e-3) / 1e12
-        traffic = _traffic_from_profiles(kern, src, args.workload)
-
+        # few paths: the split-BF16 sum is bound by its output write
+        roof = _dominant_roofline("hbm", "pathsum_bf16x3_kernel", _src_hash("bf16x3.hip", "epilogue.h"),
+                                  args.workload, out_bytes + in_bytes, sum_ms)
     res = {
-        "metric": "path-gate updates/s (%HBM peak) + path-sum TFLOP/s; vs plain c64 HSF at rel-L2<=1e-5",
-        "value": value, "unit": "path-gate updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64 (f32 sweeps, " + ("split-bf16x3" if args.mode == "bf16x3" else "f32") + " path sum)",
+        "metric": METRIC, "value": executed / (ms_step * 1e-3), "unit": "path-gate updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 (f32 sweeps, " + ("split-bf16x3" if args.mode == "bf16x3" else "f32") + " path sum)",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "paths": P, "n": plan.n, "cut": f"{nb}|{na}",
-                   "path_sum": args.mode, "ops_logical": [sa["ops_logical"], sb["ops_logical"]],
-                   "ops_fused": [sa["ops_fused"], sb["ops_fused"]], "sweep": _sweep_desc(plan, P),
-                   # fused ops every path starts from (simulated once per plan and device)
-                   "ops_shared": [sa["ops_shared"], sb["ops_shared"]]},
-        "breakdown_ms": {"sweeps": sweep_ms, "path_sum": sum_ms, "plan_host": plan_s * 1e3},
-        "path_sum_tflops": flops / (sum_ms * 1e-3) / 1e12,
-        "sweep_updates_per_s": logical_updates / (sweep_ms * 1e-3),
-        "sweep_hbm_equiv_pct": 100.0 * logical_updates * 2 * 8 * (1 << max(na, nb)) / (sweep_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
-        "rel_l2_sampled_rows": rel,
-        "plain_c64_hsf": None if plain is None else {**plain, "value": logical_updates / (plain["ms_per_step"] * 1e-3),
-                                                     "speedup_of_chosen": plain["ms_per_step"] / ms_step},
-        "roofline": {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": traffic},
+                   "path_sum": args.mode, "sweep": _sweep_desc(plan, P)},
+        "updates": {"executed": executed, "logical": logical,
+                    "logical_per_s": logical / (ms_step * 1e-3),
+                    "note": "executed = fused ops applied as the sweeps run them (shared prefix once, each "
+                            "path-tree level once per state); logical = every path x every circuit op"},
+        "step_ms": res_m["step_ms"], "breakdown_ms": {"sweeps": res_m["sweeps_ms"], "split": res_m["split_ms"],
+                                                      "path_sum": res_m["path_sum_ms"], "plan_host": plan_s * 1e3},
+        "path_sum_tflops_fp32_equiv": flops / (sum_ms * 1e-3) / 1e12,
+        "sweep_executed_updates_per_s": executed / (res_m["sweeps_ms"]["mean"] * 1e-3),
+        "rel_l2_sampled_rows": res_m.get("rel_l2_sampled_rows"),
+        "plain_c64_hsf": None if plain is None else {
+            "path_sum": "f32", "ms_per_step": plain["ms_per_step"], "step_ms": plain["step_ms"],
+            "path_sum_ms": plain["path_sum_ms"], "rel_l2_sampled_rows": plain.get("rel_l2_sampled_rows"),
+            "value": executed / (plain["ms_per_step"] * 1e-3), "speedup_of_chosen": plain["ms_per_step"] / ms_step},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(circuit, (sa["ops_logical"], sb["ops_logical"]), P, na, nb)
+        log("cpu baseline")
+        res["cpu_baseline"] = cpu_baseline(circuit, plan)
+        res["cpu_baseline"]["gpu_speedup"] = res["cpu_baseline"]["step_s_extrapolated"] / (ms_step * 1e-3)
     print(json.dumps(res), flush=True)
 
 
@@ -308,7 +362,8 @@ def bench_c5(args):
     outs = b.alloc_outputs()
     mode = args.mode
     pol = b.tune(outs, mode=mode)
-    logical = sum(p.P * (p.side_stats(0)["ops_logical"] + p.side_stats(1)["ops_logical"]) for p in plans)
+    executed = sum(_updates(p)[0] for p in plans)
+    logical = sum(_updates(p)[1] for p in plans)
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -331,7 +386,7 @@ def bench_c5(args):
 
     ms_plain = timed(per_circuit, max(1, args.steps // 2), 1)
     out_bytes = sum(8.0 * o.numel() for o in outs)
-    res = {"metric": "path-gate updates/s (batch of 64 circuits)", "value": logical / (ms * 1e-3),
+    res = {"metric": "path-gate updates/s (batch of 64 circuits)", "value": executed / (ms * 1e-3),
            "unit": "path-gate updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": f"c64 (f32 sweeps, {mode} path sum)", "data": "synthetic",
@@ -339,6 +394,7 @@ def bench_c5(args):
                                   "joint blocks of 1-3 crossing gates, full states",
                       "circuits": len(plans), "paths_total": sum(p.P for p in plans),
                       "output_gib": out_bytes / 2 ** 30, "tuned_policy": pol},
+           "updates": {"executed": executed, "logical": logical, "logical_per_s": logical / (ms * 1e-3)},
            "plain_per_circuit": {"ms_per_step": ms_plain, "path_sum": "f32",
                                  "speedup_of_batch": ms_plain / ms},
            "output_write_gbs": out_bytes / (ms * 1e-3) / 1e9}
@@ -389,81 +445,152 @@ def bench_c3(args):
     print(json.dumps(res), flush=True)
 
 
-def c4_errors(plan, A, B, tile, mode, rows):
-    """Relative L2 error of one row tile in `mode` against the FP64 path sum
-    of the same half-states (the path sum's own error), and of the oracle's
-    sampled amplitudes that fall in that tile (the whole result's error)."""
-    import numpy as np
-    import torch
-
-    from paper_2502_06959_amd import hsf_norm2
-    g = np.load(os.path.join(ROOT, "tests", "golden", "c4.npz"))
-    xs = np.asarray(g["x"], dtype=np.uint64)
-    row_of = (xs >> np.uint64(plan.nb)).astype(np.int64)
-    r0 = int(row_of[0] // rows) * rows
-    sel = np.nonzero((row_of >= r0) & (row_of < r0 + rows))[0]
-    plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode=mode, out=tile)
-    o64 = plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode="f64")
-    d = hsf_norm2(tile.reshape(-1), o64.reshape(-1)).cpu().numpy()
-    ref = hsf_norm2(o64.reshape(-1)).cpu().numpy()[0]
-    del o64
-    col = (xs[sel] & np.uint64((1 << plan.nb) - 1)).astype(np.int64)
-    idx = torch.from_numpy((row_of[sel] - r0) * (1 << plan.nb) + col).cuda()
-    got = tile.reshape(-1)[idx].cpu().numpy().astype(np.complex128)
-    want = g["psi"][sel]
-    return {"vs_fp64_path_sum_rel_l2": float(np.sqrt(d[1] / ref)),
-            "vs_oracle_rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
-            "oracle_samples": int(len(sel)), "tile_rows": [r0, r0 + rows]}
+C4_DESC = ("c4: n=34 cut 17|17 depth-24 Haar+CZ brickwork, 6 joint blocks of rank 4 (P=4096), complex64, all 2^34 "
+           "amplitudes resident in HBM (128 GiB) as 16 row tiles of 2^13 rows")
 
 
 def bench_c4(args):
-    """n=34 (P=4096): sweeps of all paths, then the path sum over every output
-    row, streamed in row tiles through one reusable tile buffer, in the
-    requested precision (f32, bf16x3 or f64)."""
+    """n=34, P=4096: sweeps of all paths, the split of both operands, then the
+    path sum of every 2^13-row tile into one 2^17 x 2^17 output."""
     import numpy as np
     import torch
 
     import circuitgen as cg
-    from paper_2502_06959_amd import Plan, hsf_workspace_size
+    from paper_2502_06959_amd import Plan, hsf_norm2, hsf_workspace_size
     c = cg.c4()
+    t0 = time.perf_counter()
     plan = Plan(c, tree=args.tree)
-    A, B = plan.alloc_halves(plan.P)
+    plan_s = time.perf_counter() - t0
+    P, na, nb = plan.P, plan.na, plan.nb
+    A, B = plan.alloc_halves(P)
     rows = 1 << 13
-    mode = args.c4_mode or args.mode
-    odt = torch.complex128 if mode == "f64" else torch.complex64
-    tile = torch.empty((rows, 1 << plan.nb), dtype=odt, device="cuda")
-    ws = None
-    if mode == "bf16x3":
-        ws = torch.empty(hsf_workspace_size(plan.handle, 1, plan.P, 1), dtype=torch.uint8, device="cuda")
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    torch.cuda.synchronize()
-    sw_ws = _paths_ws(plan, plan.P)
+    tiles = list(range(0, 1 << na, rows))
+    log(f"c4: P={P}, allocating the {8 * (1 << (na + nb)) / 2**30:.0f} GiB output")
+    out = torch.empty((1 << na, 1 << nb), dtype=torch.complex64, device="cuda")
+    ws = torch.empty(hsf_workspace_size(plan.handle, 1, P, 1), dtype=torch.uint8, device="cuda")
+    sw_ws = _paths_ws(plan, P)
     plan.run_paths(0, 1, A[:1], B[:1])        # tables to the device, prefix states: set-up, not timed
     torch.cuda.synchronize()
-    ev[0].record()
-    plan.run_paths(0, plan.P, A, B, ws=sw_ws)
-    ev[1].record()
-    for r0 in range(0, 1 << plan.na, rows):
-        plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode=mode, out=tile, ws=ws)
-    ev[2].record()
-    torch.cuda.synchronize()
-    sw, ps = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
-    flops = 8.0 * (1 << plan.na) * (1 << plan.nb) * plan.P
-    logical = plan.P * (plan.side_stats(0)["ops_logical"] + plan.side_stats(1)["ops_logical"])
-    peak = {"f32": 157.3, "bf16x3": 2500.0 / 3, "f64": 78.6}[mode]
-    err = None
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "c4.npz"))
+    xs = np.asarray(gold["x"], dtype=np.uint64)
+    xs_dev = torch.from_numpy(xs.astype(np.int64)).cuda()
+
+    def run_mode(mode, steps, warmup):
+        def step(ev=None):
+            if ev:
+                ev["s"][0].record()
+            plan.run_paths(0, P, A, B, ws=sw_ws)
+            if ev:
+                ev["s"][1].record()
+            if mode == "bf16x3":
+                plan.split_operands(A, B, ws=ws)
+            if ev:
+                ev["s"][2].record()
+            for i, r0 in enumerate(tiles):
+                if ev:
+                    ev["t"][i][0].record()
+                if mode == "bf16x3":
+                    plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode="bf16x3_split", out=out[r0:r0 + rows],
+                                         ws=ws)
+                else:
+                    plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode=mode, out=out[r0:r0 + rows])
+                if ev:
+                    ev["t"][i][1].record()
+            if ev:
+                ev["s"][3].record()
+
+        for w in range(warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"{mode}: warm-up step {w + 1}/{warmup} done")
+        mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+        evs = [{"s": [mk() for _ in range(4)], "t": [[mk(), mk()] for _ in tiles]} for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(evs[i])
+            if i % 5 == 4 or i == steps - 1:
+                torch.cuda.synchronize()
+                log(f"{mode}: timed step {i + 1}/{steps} done")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e = lambda a, b: a.elapsed_time(b)  # noqa: E731
+        r = {"ms_per_step": wall * 1e3 / steps,
+             "step_ms": _stats([e(v["s"][0], v["s"][3]) for v in evs]),
+             "sweeps_ms": _stats([e(v["s"][0], v["s"][1]) for v in evs]),
+             "split_ms": _stats([e(v["s"][1], v["s"][2]) for v in evs]),
+             "path_sum_ms": _stats([e(v["s"][2], v["s"][3]) for v in evs]),
+             "tile_launch_ms": _stats([e(t[0], t[1]) for v in evs for t in v["t"]])}
+        if not args.no_check:
+            # the oracle's sampled amplitudes (rows of every tile) and the
+            # norm of all 2^34 amplitudes the step left in HBM
+            got = out.reshape(-1)[xs_dev].cpu().numpy().astype(np.complex128)
+            r["rel_l2_vs_oracle_samples"] = float(np.linalg.norm(got - gold["psi"]) / np.linalg.norm(gold["psi"]))
+            r["oracle_samples"] = int(len(xs))
+            r["norm2_all_amplitudes"] = float(hsf_norm2(out.reshape(-1)).cpu().numpy()[0])
+        return r
+
+    plain = None
+    if not args.no_plain and args.mode != "f32":
+        n_plain = args.plain_steps or min(args.steps, 2)
+        log(f"plain FP32 path sum: {n_plain} steps")
+        plain = run_mode("f32", n_plain, 1 if args.warmup > 0 else 0)
+    log(f"{args.mode} path sum: {args.steps} steps after {args.warmup} warm-up")
+    res_m = run_mode(args.mode, args.steps, args.warmup)
+    sum_err = None
     if not args.no_check:
-        err = c4_errors(plan, A, B, tile, mode, rows)
-    res = {"metric": "path-sum TFLOP/s (n=34, P=4096)", "value": flops / (ps * 1e-3) / 1e12, "unit": "TFLOP/s",
-           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": sw + ps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": mode, "data": "synthetic",
-           "config": {"workload": "c4: n=34 cut 17|17 depth-24 Haar+CZ brickwork, 6 joint blocks of rank 4 "
-                                  "(P=4096), all 2^34 amplitudes in 2^13-row tiles", "path_sum": mode,
-                      "sweep": _sweep_desc(plan, plan.P)},
-           "breakdown_ms": {"sweeps": sw, "path_sum": ps},
-           "sweep_updates_per_s": logical / (sw * 1e-3),
-           "mfma_frac_of_mode_peak": flops / (ps * 1e-3) / 1e12 / peak,
-           "mode_peak_tflops": peak, "error": err}
+        # one tile against the FP64 path sum of the same half-states: the
+        # error of the path-sum arithmetic alone
+        r0 = int((xs[0] >> np.uint64(nb)) // rows) * rows
+        o64 = plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode="f64")
+        d = hsf_norm2(out[r0:r0 + rows].reshape(-1), o64.reshape(-1)).cpu().numpy()
+        ref = hsf_norm2(o64.reshape(-1)).cpu().numpy()[0]
+        del o64
+        sum_err = {"rel_l2_vs_fp64_path_sum": float(np.sqrt(d[1] / ref)), "tile_rows": [r0, r0 + rows]}
+    ms_step = res_m["ms_per_step"]
+    executed, logical = _updates(plan)
+    flops = 8.0 * (1 << na) * (1 << nb) * P
+    launch_flops = 8.0 * rows * (1 << nb) * P
+    if args.mode == "bf16x3":
+        # 3 BF16 products per FP32 product (hi.hi + hi.lo + lo.hi)
+        roof = _dominant_roofline("mfma-bf16", "pathsum_bf16x3_lds", _src_hash("pathsum_lds.hip", "epilogue.h"),
+                                  "c4", 3 * launch_flops, res_m["tile_launch_ms"]["mean"])
+    else:
+        roof = _dominant_roofline("mfma-f32", "pathsum_f32_lds", _src_hash("pathsum_lds.hip", "epilogue.h"),
+                                  "c4", launch_flops, res_m["tile_launch_ms"]["mean"])
+    sw_ms = res_m["sweeps_ms"]["mean"]
+    res = {
+        "metric": METRIC, "value": executed / (ms_step * 1e-3), "unit": "path-gate updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 (f32 sweeps, " + ("split-bf16x3" if args.mode == "bf16x3" else "f32") + " path sum)",
+        "data": "synthetic",
+        "config": {"workload": C4_DESC, "paths": P, "n": plan.n, "cut": f"{nb}|{na}", "path_sum": args.mode,
+                   "row_tile": rows, "sweep": _sweep_desc(plan, P)},
+        "updates": {"executed": executed, "logical": logical, "logical_per_s": logical / (ms_step * 1e-3),
+                    "note": "executed = fused ops applied as the sweeps run them (shared prefix once, each "
+                            "path-tree level once per state); logical = every path x every circuit op"},
+        "step_ms": res_m["step_ms"],
+        "breakdown_ms": {"sweeps": res_m["sweeps_ms"], "split": res_m["split_ms"], "path_sum": res_m["path_sum_ms"],
+                         "path_sum_launch": res_m["tile_launch_ms"], "plan_host": plan_s * 1e3},
+        "path_sum_tflops_fp32_equiv": flops / (res_m["path_sum_ms"]["mean"] * 1e-3) / 1e12,
+        "sweep_executed_updates_per_s": executed / (sw_ms * 1e-3),
+        "error": {"vs_oracle_samples": res_m.get("rel_l2_vs_oracle_samples"),
+                  "oracle_samples": res_m.get("oracle_samples"),
+                  "norm2_all_amplitudes": res_m.get("norm2_all_amplitudes"), "path_sum": sum_err},
+        "plain_c64_hsf": None if plain is None else {
+            "path_sum": "f32", "steps": plain["step_ms"]["n"], "ms_per_step": plain["ms_per_step"],
+            "step_ms": plain["step_ms"], "path_sum_launch_ms": plain["tile_launch_ms"],
+            "path_sum_tflops": flops / (plain["path_sum_ms"]["mean"] * 1e-3) / 1e12,
+            "frac_of_fp32_mfma_peak": flops / (plain["path_sum_ms"]["mean"] * 1e-3) / 1e12 / MFMA_PEAK["f32"],
+            "rel_l2_vs_oracle_samples": plain.get("rel_l2_vs_oracle_samples"),
+            "value": executed / (plain["ms_per_step"] * 1e-3), "speedup_of_chosen": plain["ms_per_step"] / ms_step},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a sample)")
+        res["cpu_baseline"] = cpu_baseline(c, plan)
+        res["cpu_baseline"]["gpu_speedup"] = res["cpu_baseline"]["step_s_extrapolated"] / (ms_step * 1e-3)
     print(json.dumps(res), flush=True)
 
 

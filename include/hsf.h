@@ -82,7 +82,9 @@ typedef enum {
     HSF_SUM_F32 = 0,     /* c64 in, FP32 MFMA with FP32 accumulation, c64 out      */
     HSF_SUM_BF16X3 = 1,  /* c64 in, split-BF16 x3 MFMA, FP32 accumulation, c64 out */
     HSF_SUM_F64 = 2,     /* c64 or c128 in, FP64 MFMA, c128 out (reference mode)   */
-    HSF_SUM_C128 = 3     /* alias of HSF_SUM_F64 for c128 plans                    */
+    HSF_SUM_C128 = 3,    /* alias of HSF_SUM_F64 for c128 plans                    */
+    HSF_SUM_BF16X3_SPLIT = 4 /* HSF_SUM_BF16X3 from the planes hsf_split_operands
+                                left in the workspace (no split in the call)     */
 } hsf_sum_mode;
 
 typedef struct {
@@ -254,7 +256,9 @@ hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* 
  * c < 2^n_b.  Input type: the plan's dtype.  Output type: c64 for HSF_SUM_F32
  * and HSF_SUM_BF16X3, c128 for HSF_SUM_F64 / HSF_SUM_C128.  accumulate = 1
  * adds into `out` (path chunks, resume).  ws: hsf_workspace_size(plan, 1,
- * n_paths, mode) bytes (only HSF_SUM_BF16X3 uses it).  n_paths = 0 is the
+ * n_paths, mode) bytes (HSF_SUM_BF16X3 uses it as scratch; with
+ * HSF_SUM_BF16X3_SPLIT it holds the planes of hsf_split_operands, psiA and
+ * psiB are not read and may be NULL).  n_paths = 0 is the
  * empty sum: the rows are set to zero (left as they are with accumulate = 1)
  * and psiA / psiB are not read (they may be NULL).  An empty row range
  * writes nothing and `out` may then be NULL.                                */
@@ -263,6 +267,21 @@ hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA,
                                int64_t row_begin, int64_t row_end, void* out, int64_t ldo,
                                int32_t mode, int32_t accumulate, void* ws, size_t ws_bytes,
                                hsf_stream_t stream);
+
+/* Split-BF16 operand planes for the path sum of Sec. II-B taken in the
+ * split-BF16 x3 arithmetic: every FP32 value x of the first n_paths rows of
+ * psiA (all 2^n_a amplitudes) and psiB (all 2^n_b) becomes hi = bf16(x) and
+ * lo = bf16(x - hi), written into ws (hsf_workspace_size(plan, 1, n_paths,
+ * HSF_SUM_BF16X3) bytes, device) in the layout the path sum of n_paths paths
+ * reads.  Later hsf_amplitudes_full calls with HSF_SUM_BF16X3_SPLIT, the
+ * same ws and the same n_paths then sum any row range without splitting
+ * again (row tiles of one large output split each operand once).  The plan
+ * records ws and n_paths of its last split; a HSF_SUM_BF16X3_SPLIT call that
+ * names others fails with HSF_E_ARG.  c64 plans only.  Overwriting psiA /
+ * psiB afterwards does not change the planes; calls that overlap on one ws
+ * race.                                                                      */
+hsf_status hsf_split_operands(hsf_plan_t plan, const void* psiA, int64_t ldA, const void* psiB, int64_t ldB,
+                              int64_t n_paths, void* ws, size_t ws_bytes, hsf_stream_t stream);
 
 /* Amplitudes of chosen basis states (Sec. V computes a subset):
  * out[j] = sum_{p < n_paths} psiA[p][x_j >> n_b] psiB[p][x_j & (2^n_b - 1)],

@@ -7,9 +7,10 @@ current stream.  Functions keep the C names (hsf_plan, hsf_run_paths, ...);
 `Plan` bundles them.
 """
 from .hsf import (Batch, Plan, ProbabilityMass, hsf_amplitudes_bitstrings, hsf_amplitudes_full, hsf_backward,
-                  hsf_find_blocks, hsf_norm2, hsf_plan, hsf_run_paths, hsf_workspace_size, joint_blocked)
+                  hsf_find_blocks, hsf_norm2, hsf_plan, hsf_run_paths, hsf_split_operands, hsf_workspace_size,
+                  joint_blocked)
 from ._lib import HsfError
 
 __all__ = ["Batch", "Plan", "ProbabilityMass", "HsfError", "hsf_plan", "hsf_find_blocks", "joint_blocked",
-           "hsf_run_paths", "hsf_amplitudes_full", "hsf_amplitudes_bitstrings", "hsf_norm2", "hsf_backward",
+           "hsf_run_paths", "hsf_amplitudes_full", "hsf_split_operands", "hsf_amplitudes_bitstrings", "hsf_norm2", "hsf_backward",
            "hsf_workspace_size"]

@@ -19,7 +19,7 @@ GATE_KIND = {"U": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "SDG": 6, "T": 7, "
 
 HSF_C64, HSF_C128 = 0, 1
 HSF_MAX_BLOCK_SIDE = 16
-SUM_MODE = {"f32": 0, "bf16x3": 1, "f64": 2, "c128": 3}
+SUM_MODE = {"f32": 0, "bf16x3": 1, "f64": 2, "c128": 3, "bf16x3_split": 4}
 
 
 class HsfGate(ctypes.Structure):
@@ -67,6 +67,8 @@ SIGNATURES = {
                                 c_size_t, c_void_p]),
     "hsf_amplitudes_full": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64, c_int64,
                                       c_void_p, c_int64, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
+    "hsf_split_operands": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_size_t,
+                                     c_void_p]),
     "hsf_amplitudes_bitstrings": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p,
                                             c_int64, c_void_p, c_int32, c_void_p]),
     "hsf_norm2": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_size_t,

@@ -189,7 +189,8 @@ size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t 
     if (!plan || n_paths < 0) return 0;
     const Plan* p = P_(plan);
     if (op == 0) return tree_workspace(*p, n_paths);
-    if (op == 1 && mode == HSF_SUM_BF16X3) return bf16x3_workspace(p->na, p->nb, n_paths);
+    if (op == 1 && (mode == HSF_SUM_BF16X3 || mode == HSF_SUM_BF16X3_SPLIT))
+        return bf16x3_workspace(p->na, p->nb, n_paths);
     if (op == 2) return backward_workspace(*p, n_paths, mode);
     return 0;
 }
@@ -215,21 +216,51 @@ hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA, c
                                void* out, int64_t ldo, int32_t mode, int32_t accumulate, void* ws,
                                size_t ws_bytes, hsf_stream_t stream) {
     HSF_GUARD_BEGIN
-    if (!plan || (n_paths > 0 && (!psiA || !psiB))) return fail(HSF_E_ARG, "null argument");
+    const bool presplit = mode == HSF_SUM_BF16X3_SPLIT;
+    if (!plan || (n_paths > 0 && !presplit && (!psiA || !psiB))) return fail(HSF_E_ARG, "null argument");
     const Plan* p = P_(plan);
     const int64_t M = int64_t(1) << p->na, N = int64_t(1) << p->nb;
     if (n_paths < 0) return fail(HSF_E_ARG, "negative path count");
     if (row_begin < 0 || row_end > M || row_begin > row_end) return fail(HSF_E_ARG, "row range outside [0, 2^n_a)");
-    if (ldA < M || ldB < N || ldo < N) return fail(HSF_E_ARG, "leading dimension too small");
-    if (mode < HSF_SUM_F32 || mode > HSF_SUM_C128) return fail(HSF_E_ARG, "unknown path-sum mode");
-    if (p->dtype == HSF_C128 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3))
+    if ((!presplit && (ldA < M || ldB < N)) || ldo < N) return fail(HSF_E_ARG, "leading dimension too small");
+    if (mode < HSF_SUM_F32 || mode > HSF_SUM_BF16X3_SPLIT) return fail(HSF_E_ARG, "unknown path-sum mode");
+    if (p->dtype == HSF_C128 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3 || presplit))
         return fail(HSF_E_ARG, "c128 half-states need HSF_SUM_F64 or HSF_SUM_C128");
-    if (mode == HSF_SUM_BF16X3 && ws_bytes < bf16x3_workspace(p->na, p->nb, n_paths))
+    if ((mode == HSF_SUM_BF16X3 || presplit) && ws_bytes < bf16x3_workspace(p->na, p->nb, n_paths))
         return fail(HSF_E_ARG, "workspace too small for HSF_SUM_BF16X3");
+    if (presplit && n_paths > 0 && (!ws || ws != p->split_ws || n_paths != p->split_paths))
+        return fail(HSF_E_ARG, "HSF_SUM_BF16X3_SPLIT needs the workspace and path count of the plan's last "
+                               "hsf_split_operands call");
     if (row_begin == row_end) return HSF_OK;
     if (!out) return fail(HSF_E_ARG, "null argument");
+    if (presplit && n_paths > 0)
+        return path_sum_presplit(n_paths, M, row_begin, row_end - row_begin, N, ws, (float2*)out, ldo, accumulate,
+                                 (hipStream_t)stream);
     return path_sum(p->dtype, mode, psiA, ldA, psiB, ldB, n_paths, row_begin, row_end - row_begin, N,
                     out, ldo, accumulate, ws, (hipStream_t)stream);
+    HSF_GUARD_END
+}
+
+hsf_status hsf_split_operands(hsf_plan_t plan, const void* psiA, int64_t ldA, const void* psiB, int64_t ldB,
+                              int64_t n_paths, void* ws, size_t ws_bytes, hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    if (!plan) return fail(HSF_E_ARG, "null plan");
+    Plan* p = P_(plan);
+    const int64_t M = int64_t(1) << p->na, N = int64_t(1) << p->nb;
+    if (p->dtype != HSF_C64) return fail(HSF_E_ARG, "split-BF16 planes are made from c64 half-states");
+    if (n_paths < 0) return fail(HSF_E_ARG, "negative path count");
+    if (n_paths > 0 && (!psiA || !psiB || !ws)) return fail(HSF_E_ARG, "null argument");
+    if (ldA < M || ldB < N) return fail(HSF_E_ARG, "leading dimension too small");
+    if (ws_bytes < bf16x3_workspace(p->na, p->nb, n_paths))
+        return fail(HSF_E_ARG, "workspace too small for the split planes");
+    if (n_paths > 0) {
+        hsf_status s = split_operands((const float2*)psiA, ldA, M, (const float2*)psiB, ldB, N, n_paths, ws,
+                                      (hipStream_t)stream);
+        if (s != HSF_OK) return s;
+    }
+    p->split_ws = ws;
+    p->split_paths = n_paths;
+    return HSF_OK;
     HSF_GUARD_END
 }
 

@@ -106,10 +106,12 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
 // A2 operands of the 16 paths from k0: row r0 + lane % 32, paths
 // k0 + 8 (lane / 32) .. +7 of the four planes (re hi, re lo, im hi, im lo).
 // lane = (lane % 32) Kp + 8 (lane / 32), the lane's fixed element offset.
+// The planes hold pa_rows rows each (M <= pa_rows: a product may cover a
+// row range of operands split over more rows).
 template <bool FULL>
-__device__ __forceinline__ void load_a2(const unsigned short* __restrict__ P, int64_t M, int64_t Kp, int64_t r0,
-                                        int64_t k0, uint32_t lane_off, u16x8 (&v)[4]) {
-    const int64_t plane = M * Kp;
+__device__ __forceinline__ void load_a2(const unsigned short* __restrict__ P, int64_t M, int64_t pa_rows, int64_t Kp,
+                                        int64_t r0, int64_t k0, uint32_t lane_off, u16x8 (&v)[4]) {
+    const int64_t plane = pa_rows * Kp;
     if (FULL) {
         // wave-uniform base in scalar registers + the 32-bit lane offset
         const unsigned short* base = P + uniform_i64(r0 * Kp + k0);
@@ -165,7 +167,7 @@ struct StreamJob {
     const unsigned short* PA;
     const unsigned short* PB;
     float* out;
-    int64_t M, N, Kp, ldo, m0, c0;
+    int64_t M, N, Kp, ldo, m0, c0, pa_rows;
 };
 
 // Persistent loop over `tiles` tiles handed out by loc(t) (t = this
@@ -188,7 +190,7 @@ __device__ __forceinline__ void stream_tiles(const Loc& loc, int64_t tiles, int 
     uint32_t a_off, b_off;
     offsets(cur, a_off, b_off);
     u16x8 a[4], bh[8], bl[8];
-    load_a2<FULL>(cur.PA, cur.M, cur.Kp, cur.m0, 0, a_off, a);
+    load_a2<FULL>(cur.PA, cur.M, cur.pa_rows, cur.Kp, cur.m0, 0, a_off, a);
 #pragma unroll
     for (int blk = 0; blk < 8; ++blk)
         load_b2<FULL>(cur.PB, cur.N, cur.Kp, cur.c0 + blk * 32, 0, b_off, bh[blk], bl[blk]);
@@ -207,7 +209,7 @@ __device__ __forceinline__ void stream_tiles(const Loc& loc, int64_t tiles, int 
             const int64_t lk0 = last ? 0 : k0 + 16;
             const uint32_t la = last ? na_off : a_off, lb = last ? nb_off : b_off;
             const bf16x8 xrh = as_bf(a[0]), xrl = as_bf(a[1]), xih = as_bf(a[2]), xil = as_bf(a[3]);
-            if (more) load_a2<FULL>(lj.PA, lj.M, lj.Kp, lj.m0, lk0, la, a);
+            if (more) load_a2<FULL>(lj.PA, lj.M, lj.pa_rows, lj.Kp, lj.m0, lk0, la, a);
 #pragma unroll
             for (int blk = 0; blk < 8; ++blk) {
                 const bf16x8 yh = as_bf(bh[blk]), yl = as_bf(bl[blk]);
@@ -264,20 +266,23 @@ struct SingleLoc {
     const unsigned short* PA;
     const unsigned short* PB;
     float* out;
-    int64_t M, N, Kp, ldo, tiles_n;
+    int64_t M, N, Kp, ldo, tiles_n, pa_rows;
     int w;
     __device__ __forceinline__ StreamJob operator()(int64_t t) const {
         const int64_t tm = t / tiles_n, tn = t - tm * tiles_n;
-        return {PA, PB, out, M, N, Kp, ldo, tm * BW_ROWS + w * 32, tn * (2 * BW_COLS)};
+        return {PA, PB, out, M, N, Kp, ldo, tm * BW_ROWS + w * 32, tn * (2 * BW_COLS), pa_rows};
     }
 };
 
+// PA: the planes' first row of this product (rows of the planes pa_rows
+// apart per plane).
 template <bool FULL>
 __global__ __launch_bounds__(BW_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void pathsum_bf16x3_kernel(const unsigned short* __restrict__ PA, int64_t M,
-                                                             const unsigned short* __restrict__ PB, int64_t N,
-                                                             int64_t Kp, float2* __restrict__ out, int64_t ldo,
-                                                             int accumulate, int64_t tiles_n, int64_t tiles) {
-    const SingleLoc loc{PA, PB, reinterpret_cast<float*>(out), M, N, Kp, ldo, tiles_n,
+                                                             int64_t pa_rows, const unsigned short* __restrict__ PB,
+                                                             int64_t N, int64_t Kp, float2* __restrict__ out,
+                                                             int64_t ldo, int accumulate, int64_t tiles_n,
+                                                             int64_t tiles) {
+    const SingleLoc loc{PA, PB, reinterpret_cast<float*>(out), M, N, Kp, ldo, tiles_n, pa_rows,
                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)};
     stream_tiles<FULL>(loc, tiles, accumulate);
 }
@@ -312,7 +317,8 @@ struct BatchLoc {
                 d[lo].K,
                 d[lo].ldo,
                 tm * BW_ROWS + w * 32,
-                tn * (2 * BW_COLS)};
+                tn * (2 * BW_COLS),
+                d[lo].M};
     }
 };
 
@@ -390,30 +396,45 @@ hsf_status launch_bf16x3_batch(const void* descs, int n, int64_t tiles, bool ful
     return hip_check(hipGetLastError(), "pathsum_bf16x3_batch launch");
 }
 
-hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
-                           int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st) {
+size_t bf16x3_stream_planes(int64_t rows, int64_t K) {
     const int64_t Kp = std::max<int64_t>(16, (K + 15) / 16 * 16);
-    unsigned short* PA = reinterpret_cast<unsigned short*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
-    unsigned short* PB = PA + 4 * M * Kp;
-    {
-        const dim3 g((uint32_t)((std::max(M, N) + 255) / 256), (uint32_t)(Kp / 8), 2);
-        if (g.y > 65535u) return fail(HSF_E_ARG, "too many paths in one HSF_SUM_BF16X3 call (split the path range)");
-        const SplitOperand a{A, ldA, M, PA}, b{B, ldB, N, PB};
-        hipLaunchKernelGGL(split_planes, g, dim3(256), 0, st, a, b, K, Kp);
-        hsf_status s = hip_check(hipGetLastError(), "split_planes launch");
-        if (s != HSF_OK) return s;
-    }
+    return (size_t)(4 * rows * Kp) * sizeof(uint16_t);
+}
+
+hsf_status split_stream(const float2* A, int64_t ldA, int64_t MA, const float2* B, int64_t ldB, int64_t N, int64_t K,
+                        unsigned short* PA, unsigned short* PB, hipStream_t st) {
+    const int64_t Kp = std::max<int64_t>(16, (K + 15) / 16 * 16);
+    const dim3 g((uint32_t)((std::max(MA, N) + 255) / 256), (uint32_t)(Kp / 8), 2);
+    if (g.y > 65535u) return fail(HSF_E_ARG, "too many paths in one HSF_SUM_BF16X3 call (split the path range)");
+    const SplitOperand a{A, ldA, MA, PA}, b{B, ldB, N, PB};
+    hipLaunchKernelGGL(split_planes, g, dim3(256), 0, st, a, b, K, Kp);
+    return hip_check(hipGetLastError(), "split_planes launch");
+}
+
+hsf_status sum_stream(const unsigned short* PA, int64_t pa_rows, int64_t row0, int64_t M, const unsigned short* PB,
+                      int64_t N, int64_t K, float2* out, int64_t ldo, int accumulate, hipStream_t st) {
+    const int64_t Kp = std::max<int64_t>(16, (K + 15) / 16 * 16);
+    PA += row0 * Kp;
     const int64_t tn = (N + BW_COLS - 1) / BW_COLS, tiles = tn * ((M + BW_ROWS - 1) / BW_ROWS);
-    const bool full = bf16x3_stream_full(M, N, Kp, ldo, accumulate);
+    const bool full = bf16x3_stream_full(M, N, Kp, ldo, accumulate) && 4 * pa_rows * Kp <= (int64_t)INT32_MAX;
     const void* kern = full ? (const void*)pathsum_bf16x3_kernel<true> : (const void*)pathsum_bf16x3_kernel<false>;
     const int grid = persistent_grid(kern, BW_THREADS, 0, tiles);
     if (full)
-        hipLaunchKernelGGL(pathsum_bf16x3_kernel<true>, dim3(grid), dim3(BW_THREADS), 0, st, PA, M, PB, N, Kp, out, ldo, 0,
-                           tn, tiles);
+        hipLaunchKernelGGL(pathsum_bf16x3_kernel<true>, dim3(grid), dim3(BW_THREADS), 0, st, PA, M, pa_rows, PB, N, Kp,
+                           out, ldo, 0, tn, tiles);
     else
-        hipLaunchKernelGGL(pathsum_bf16x3_kernel<false>, dim3(grid), dim3(BW_THREADS), 0, st, PA, M, PB, N, Kp, out, ldo,
-                           accumulate, tn, tiles);
+        hipLaunchKernelGGL(pathsum_bf16x3_kernel<false>, dim3(grid), dim3(BW_THREADS), 0, st, PA, M, pa_rows, PB, N,
+                           Kp, out, ldo, accumulate, tn, tiles);
     return hip_check(hipGetLastError(), "pathsum_bf16x3 launch");
+}
+
+hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
+                           int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st) {
+    unsigned short* PA = reinterpret_cast<unsigned short*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    unsigned short* PB = PA + bf16x3_stream_planes(M, K) / sizeof(uint16_t);
+    hsf_status s = split_stream(A, ldA, M, B, ldB, N, K, PA, PB, st);
+    if (s != HSF_OK) return s;
+    return sum_stream(PA, M, 0, M, PB, N, K, out, ldo, accumulate, st);
 }
 
 }  // namespace hsf

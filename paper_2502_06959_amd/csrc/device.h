@@ -69,6 +69,27 @@ hsf_status path_sum_f64_lds(bool c128_in, const void* A, int64_t ldA, const void
                             int64_t N, double2* out, int64_t ldo, int accumulate, hipStream_t st);
 hsf_status path_sum_bf16x3_lds(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
                                int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st);
+// Split-BF16 planes, and the path sum over planes split beforehand: the
+// chunked layout of the LDS-staged kernel (split_lds / sum_lds) and the
+// [plane][row][path] layout of the streaming kernel (split_stream /
+// sum_stream).  MA: rows of A split; the sums take rows row0 .. row0+M-1 of
+// A's planes (RA / pa_rows rows per chunk or plane).
+size_t bf16x3_lds_planes(int64_t rows, int64_t K);
+size_t bf16x3_stream_planes(int64_t rows, int64_t K);
+hsf_status split_lds(const float2* A, int64_t ldA, int64_t MA, const float2* B, int64_t ldB, int64_t N, int64_t K,
+                     unsigned short* PA, unsigned short* PB, hipStream_t st);
+hsf_status sum_lds(const unsigned short* PA, int64_t RA, int64_t row0, int64_t M, const unsigned short* PB, int64_t N,
+                   int64_t K, float2* out, int64_t ldo, int accumulate, hipStream_t st);
+hsf_status split_stream(const float2* A, int64_t ldA, int64_t MA, const float2* B, int64_t ldB, int64_t N, int64_t K,
+                        unsigned short* PA, unsigned short* PB, hipStream_t st);
+hsf_status sum_stream(const unsigned short* PA, int64_t pa_rows, int64_t row0, int64_t M, const unsigned short* PB,
+                      int64_t N, int64_t K, float2* out, int64_t ldo, int accumulate, hipStream_t st);
+// Whole-operand split for later row-range sums (hsf_split_operands), and the
+// sum of rows [row0, row0 + M) from those planes.
+hsf_status split_operands(const float2* A, int64_t ldA, int64_t MA, const float2* B, int64_t ldB, int64_t N,
+                          int64_t K, void* ws, hipStream_t st);
+hsf_status path_sum_presplit(int64_t K, int64_t MA, int64_t row0, int64_t M, int64_t N, void* ws, float2* out,
+                             int64_t ldo, int accumulate, hipStream_t st);
 
 // Batched launches (tables are device arrays; offsets are relative to `base`).
 hsf_status launch_sweep_batch(int kg, bool s1, const void* segs, int nseg, uint32_t total_blocks, int threads,

@@ -263,6 +263,10 @@ struct Plan {
     SideProgram side[2];              // 0 = side a (upper), 1 = side b (lower)
     std::vector<DeviceCopy> dev;
     int64_t n_params = 0;
+    // the workspace and path count of the last hsf_split_operands call, which
+    // HSF_SUM_BF16X3_SPLIT path sums must name again
+    const void* split_ws = nullptr;
+    int64_t split_paths = -1;
 };
 
 // Joint blocks of commuting crossing gates (blocks.cpp): a gate order and

@@ -322,6 +322,26 @@ size_t bf16x3_workspace(int na, int nb, int64_t n_paths) {
 hsf_status path_sum_bf16x3(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
                            int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st);
 
+// The planes of A (MA rows) start at the 256-byte aligned workspace and B's
+// follow; the layout is the one the path sum of K paths takes.
+hsf_status split_operands(const float2* A, int64_t ldA, int64_t MA, const float2* B, int64_t ldB, int64_t N,
+                          int64_t K, void* ws, hipStream_t st) {
+    unsigned short* PA = reinterpret_cast<unsigned short*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    if (path_sum_lds_fits(HSF_SUM_BF16X3, A, ldA, B, ldB, K, MA, N))
+        return split_lds(A, ldA, MA, B, ldB, N, K, PA, PA + bf16x3_lds_planes(MA, K) / sizeof(uint16_t), st);
+    return split_stream(A, ldA, MA, B, ldB, N, K, PA, PA + bf16x3_stream_planes(MA, K) / sizeof(uint16_t), st);
+}
+
+hsf_status path_sum_presplit(int64_t K, int64_t MA, int64_t row0, int64_t M, int64_t N, void* ws, float2* out,
+                             int64_t ldo, int accumulate, hipStream_t st) {
+    const unsigned short* PA = reinterpret_cast<const unsigned short*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    if (path_sum_lds_fits(HSF_SUM_BF16X3, nullptr, 0, nullptr, 0, K, MA, N))
+        return sum_lds(PA, MA, row0, M, PA + bf16x3_lds_planes(MA, K) / sizeof(uint16_t), N, K, out, ldo, accumulate,
+                       st);
+    return sum_stream(PA, MA, row0, M, PA + bf16x3_stream_planes(MA, K) / sizeof(uint16_t), N, K, out, ldo, accumulate,
+                      st);
+}
+
 hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K,
                     int64_t row0, int64_t M, int64_t N, void* out, int64_t ldo, int accumulate, void* ws,
                     hipStream_t st) {
@@ -329,7 +349,7 @@ hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void*
         // the sum over no paths: zero rows, nothing to add when accumulating;
         // the operands are not read
         if (accumulate) return HSF_OK;
-        const int64_t words = (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3) ? 1 : 2;
+        const int64_t words = (mode == HSF_SUM_F64 || mode == HSF_SUM_C128) ? 2 : 1;
         const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(4096, (M * N * words + 255) / 256));
         hipLaunchKernelGGL(zero_rows, dim3((uint32_t)blocks), dim3(256), 0, st, (uint2*)out, ldo * words, M, N * words);
         return hip_check(hipGetLastError(), "zero_rows launch");

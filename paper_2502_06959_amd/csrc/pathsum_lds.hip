@@ -214,15 +214,16 @@ __global__ __launch_bounds__(256) void split_chunked(const float2* __restrict__ 
 }
 
 // Rows row0 + t / B_TPR + B_RPI i (i < B_NF) of path chunk c, bytes
-// 16 (t % B_TPR) .. +15; rows at or beyond R read as zero.
-__device__ __forceinline__ void fetch_rows(const unsigned short* __restrict__ P, int64_t R, int64_t row0, int64_t c,
-                                           int srow, int scol, uint4 (&r)[B_NF]) {
+// 16 (t % B_TPR) .. +15, of planes whose chunks hold R rows each; rows at or
+// beyond lim read as zero (lim <= R).
+__device__ __forceinline__ void fetch_rows(const unsigned short* __restrict__ P, int64_t R, int64_t lim, int64_t row0,
+                                           int64_t c, int srow, int scol, uint4 (&r)[B_NF]) {
     const uint4* g = reinterpret_cast<const uint4*>(P + (c * R + row0) * (4 * B_KC));
 #pragma unroll
     for (int i = 0; i < B_NF; ++i) {
         const int row = srow + B_RPI * i;
-        const bool ok = row0 + row < R;
-        const uint4 v = g[(ok ? row : R - 1 - row0) * B_TPR + scol];
+        const bool ok = row0 + row < lim;
+        const uint4 v = g[(ok ? row : lim - 1 - row0) * B_TPR + scol];
         r[i] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
     }
 }
@@ -237,9 +238,9 @@ __device__ __forceinline__ void stash_rows(unsigned char* stage, int srow, int s
     }
 }
 
-// One 128 x 128 output tile at (m0, n0) from chunked planes; ends with a
-// barrier.
-__device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict__ PA, int64_t M,
+// One 128 x 128 output tile at (m0, n0) from chunked planes (A's chunks of
+// RA >= M rows, PA at the product's first row); ends with a barrier.
+__device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict__ PA, int64_t M, int64_t RA,
                                                 const unsigned short* __restrict__ PB, int64_t N, int64_t chunks,
                                                 float2* __restrict__ out, int64_t ldo, int accumulate, int64_t m0,
                                                 int64_t n0, unsigned char* bl) {
@@ -258,15 +259,15 @@ __device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict
                 cr[a][b] = (f32x16)0.0f;
                 ci[a][b] = (f32x16)0.0f;
             }
-        fetch_rows(PA, M, m0, 0, srow, scol, ra);
-        fetch_rows(PB, N, n0, 0, srow, scol, rb);
+        fetch_rows(PA, RA, M, m0, 0, srow, scol, ra);
+        fetch_rows(PB, N, N, n0, 0, srow, scol, rb);
         stash_rows(bl, srow, scol, ra, rb);
         __syncthreads();
         for (int64_t c = 0; c < chunks; ++c) {
             const int buf = (int)(c & 1);
             if (c + 1 < chunks) {
-                fetch_rows(PA, M, m0, c + 1, srow, scol, ra);
-                fetch_rows(PB, N, n0, c + 1, srow, scol, rb);
+                fetch_rows(PA, RA, M, m0, c + 1, srow, scol, ra);
+                fetch_rows(PB, N, N, n0, c + 1, srow, scol, rb);
             }
             const unsigned char* sa = bl + buf * B_STAGE;
             const unsigned char* sb = sa + 128 * B_ROW;
@@ -324,7 +325,7 @@ __device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict
 }
 
 __global__ __launch_bounds__(256, 2) void pathsum_bf16x3_lds(const unsigned short* __restrict__ PA, int64_t M,
-                                                          const unsigned short* __restrict__ PB, int64_t N,
+                                                          int64_t RA, const unsigned short* __restrict__ PB, int64_t N,
                                                           int64_t chunks, float2* __restrict__ out, int64_t ldo,
                                                           int accumulate, int64_t tiles_m, int64_t tiles_n,
                                                           int xcd_bands) {
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(256, 2) void pathsum_bf16x3_lds(const unsigned shor
     for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
         int64_t tm, tn;
         tile_coords(item, tiles_m, tiles_n, xcd_bands != 0, tm, tn);
-        bf16x3_lds_tile(PA, M, PB, N, chunks, out, ldo, accumulate, tm * 128, tn * 128, bl);
+        bf16x3_lds_tile(PA, M, RA, PB, N, chunks, out, ldo, accumulate, tm * 128, tn * 128, bl);
     }
 }
 
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(256, 2) void pathsum_bf16x3_lds_batch(const GemmDes
         const GemmDesc& g = find_desc(d, n, item);
         int64_t tm, tn;
         tile_coords(item - g.tile_start, (g.M + 127) / 128, g.tiles_n, false, tm, tn);
-        bf16x3_lds_tile(reinterpret_cast<const unsigned short*>(base + g.a_off), g.M,
+        bf16x3_lds_tile(reinterpret_cast<const unsigned short*>(base + g.a_off), g.M, g.M,
                         reinterpret_cast<const unsigned short*>(base + g.b_off), g.N, g.K / B_KC, (float2*)g.out,
                         g.ldo, 0, tm * 128, tn * 128, bl);
     }
@@ -528,11 +529,6 @@ bool path_sum_lds_fits(int mode, const void* A, int64_t ldA, const void* B, int6
            N % 2 == 0;
 }
 
-size_t bf16x3_lds_workspace(int64_t M, int64_t N, int64_t K) {
-    const int64_t kp = (K + B_KC - 1) / B_KC * B_KC;
-    return (size_t)kp * (size_t)(M + N) * 4 * sizeof(uint16_t) + 256;
-}
-
 hsf_status path_sum_f32_lds(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
                             int64_t N, float2* out, int64_t ldo, int accumulate, hipStream_t st) {
     hsf_status s = set_lds_attrs();
@@ -545,24 +541,40 @@ hsf_status path_sum_f32_lds(const float2* A, int64_t ldA, const float2* B, int64
     return hip_check(hipGetLastError(), "pathsum_f32_lds launch");
 }
 
-hsf_status path_sum_bf16x3_lds(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
-                               int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st) {
+size_t bf16x3_lds_planes(int64_t rows, int64_t K) {
+    const int64_t kp = (K + B_KC - 1) / B_KC * B_KC;
+    return (size_t)(4 * rows * kp) * sizeof(uint16_t);
+}
+
+hsf_status split_lds(const float2* A, int64_t ldA, int64_t MA, const float2* B, int64_t ldB, int64_t N, int64_t K,
+                     unsigned short* PA, unsigned short* PB, hipStream_t st) {
+    const int64_t chunks = (K + B_KC - 1) / B_KC;
+    const uint32_t gy = (uint32_t)(chunks * (B_KC / 8));
+    hipLaunchKernelGGL(split_chunked, dim3((uint32_t)((MA + 255) / 256), gy), dim3(256), 0, st, A, ldA, K, MA, PA);
+    hipLaunchKernelGGL(split_chunked, dim3((uint32_t)((N + 255) / 256), gy), dim3(256), 0, st, B, ldB, K, N, PB);
+    return hip_check(hipGetLastError(), "split_chunked launch");
+}
+
+hsf_status sum_lds(const unsigned short* PA, int64_t RA, int64_t row0, int64_t M, const unsigned short* PB, int64_t N,
+                   int64_t K, float2* out, int64_t ldo, int accumulate, hipStream_t st) {
     hsf_status s = set_lds_attrs();
     if (s != HSF_OK) return s;
     const int64_t chunks = (K + B_KC - 1) / B_KC;
-    unsigned short* PA = reinterpret_cast<unsigned short*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
-    unsigned short* PB = PA + 4 * M * chunks * B_KC;
-    const uint32_t gy = (uint32_t)(chunks * (B_KC / 8));
-    hipLaunchKernelGGL(split_chunked, dim3((uint32_t)((M + 255) / 256), gy), dim3(256), 0, st, A, ldA, K, M, PA);
-    hipLaunchKernelGGL(split_chunked, dim3((uint32_t)((N + 255) / 256), gy), dim3(256), 0, st, B, ldB, K, N, PB);
-    s = hip_check(hipGetLastError(), "split_chunked launch");
-    if (s != HSF_OK) return s;
     int64_t tm, tn;
     int grid, bands;
     grid_shape((const void*)pathsum_bf16x3_lds, B_LDS, M, N, tm, tn, grid, bands);
-    hipLaunchKernelGGL(pathsum_bf16x3_lds, dim3(grid), dim3(256), B_LDS, st, PA, M, PB, N, chunks, out, ldo,
-                       accumulate, tm, tn, bands);
+    hipLaunchKernelGGL(pathsum_bf16x3_lds, dim3(grid), dim3(256), B_LDS, st, PA + row0 * (4 * B_KC), M, RA, PB, N,
+                       chunks, out, ldo, accumulate, tm, tn, bands);
     return hip_check(hipGetLastError(), "pathsum_bf16x3_lds launch");
+}
+
+hsf_status path_sum_bf16x3_lds(const float2* A, int64_t ldA, const float2* B, int64_t ldB, int64_t K, int64_t M,
+                               int64_t N, float2* out, int64_t ldo, int accumulate, void* ws, hipStream_t st) {
+    unsigned short* PA = reinterpret_cast<unsigned short*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    unsigned short* PB = PA + bf16x3_lds_planes(M, K) / sizeof(uint16_t);
+    hsf_status s = split_lds(A, ldA, M, B, ldB, N, K, PA, PB, st);
+    if (s != HSF_OK) return s;
+    return sum_lds(PA, M, 0, M, PB, N, K, out, ldo, accumulate, st);
 }
 
 hsf_status launch_f32_lds_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st) {

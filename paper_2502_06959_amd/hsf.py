@@ -131,6 +131,14 @@ def hsf_amplitudes_full(plan, psiA, psiB, n_paths, row_begin, row_end, out, mode
                                         _stream(psiA)))
 
 
+def hsf_split_operands(plan, psiA, psiB, n_paths, ws):
+    """Split-BF16 planes of both operands (all rows) into ws, for later
+    HSF_SUM_BF16X3_SPLIT path sums ("bf16x3_split") over row ranges."""
+    L.check(L.lib().hsf_split_operands(ctypes.c_void_p(plan), _ptr(psiA), psiA.stride(0), _ptr(psiB),
+                                       psiB.stride(0), n_paths, _ptr(ws), ws.numel() * ws.element_size(),
+                                       _stream(psiA)))
+
+
 def hsf_amplitudes_bitstrings(plan, psiA, psiB, n_paths, x, out, accumulate=False):
     L.check(L.lib().hsf_amplitudes_bitstrings(ctypes.c_void_p(plan), _ptr(psiA), psiA.stride(0), _ptr(psiB),
                                               psiB.stride(0), n_paths, _ptr(x), x.numel(), _ptr(out),
@@ -258,17 +266,32 @@ class Plan:
 
     def amplitudes_full(self, psiA, psiB, n_paths=None, rows=None, mode=None, out=None, accumulate=False,
                         ws=None):
+        """Rows [r0, r1) of the path sum.  mode "bf16x3_split" reads the
+        planes of the last split_operands call from ws (psiA and psiB then
+        only give the device and the path count)."""
         n_paths = psiA.shape[0] if n_paths is None else n_paths
         r0, r1 = (0, 1 << self.na) if rows is None else rows
         mode = mode or ("c128" if self.dtype == "c128" else "f32")
-        odt = torch.complex64 if mode in ("f32", "bf16x3") else torch.complex128
+        odt = torch.complex64 if mode in ("f32", "bf16x3", "bf16x3_split") else torch.complex128
         if out is None:
             out = torch.empty((r1 - r0, 1 << self.nb), dtype=odt, device=psiA.device)
         if mode == "bf16x3" and ws is None:
             nbytes = hsf_workspace_size(self.handle, 1, n_paths, L.SUM_MODE[mode])
             ws = torch.empty(nbytes, dtype=torch.uint8, device=psiA.device)
+        if mode == "bf16x3_split" and ws is None:
+            raise ValueError("mode bf16x3_split needs the workspace of split_operands")
         hsf_amplitudes_full(self.handle, psiA, psiB, n_paths, r0, r1, out, mode, accumulate, ws)
         return out
+
+    def split_operands(self, psiA, psiB, n_paths=None, ws=None):
+        """BF16 hi/lo planes of the first n_paths rows of both operands, for
+        amplitudes_full(..., mode="bf16x3_split", ws=ws).  Returns ws."""
+        n_paths = psiA.shape[0] if n_paths is None else n_paths
+        if ws is None:
+            nbytes = hsf_workspace_size(self.handle, 1, n_paths, L.SUM_MODE["bf16x3"])
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=psiA.device)
+        hsf_split_operands(self.handle, psiA, psiB, n_paths, ws)
+        return ws
 
     def amplitudes_bitstrings(self, psiA, psiB, x, n_paths=None, out=None, accumulate=False):
         n_paths = psiA.shape[0] if n_paths is None else n_paths
@@ -323,12 +346,15 @@ class ProbabilityMass(torch.autograd.Function):
         th = theta.detach().double().cpu().numpy()
         plan = Plan(_with_params(circuit, th), dtype=dtype)
         ctx.plan, ctx.x, ctx.chunk = plan, x, chunk
-        return torch.tensor(plan.loss(x, chunk), dtype=torch.float64)
+        ctx.theta_device, ctx.theta_dtype = theta.device, theta.dtype
+        return torch.tensor(plan.loss(x, chunk), dtype=torch.float64, device=theta.device)
 
     @staticmethod
     def backward(ctx, gout):
+        # gradients come back on theta's device and in its dtype
         g = ctx.plan.backward(ctx.x, ctx.chunk)
-        return (gout.to(g.device) * g).to(torch.float64).cpu(), None, None, None, None
+        g = (gout.to(g.device, torch.float64) * g).to(device=ctx.theta_device, dtype=ctx.theta_dtype)
+        return g, None, None, None, None
 
 
 class Batch:

@@ -129,3 +129,20 @@ def test_autograd_function():
     r = np.array([ref[t] for t in range(len(theta))])
     assert np.max(np.abs(theta.grad.numpy() - r)) < 1e-9 * np.max(np.abs(r))
     assert abs(L.item() - OG.loss(c, xs)) < 1e-12
+
+
+def test_autograd_function_on_device_angles():
+    """Angles held on the GPU: the loss and the gradient come back on the
+    GPU, and a non-scalar cotangent path (a weighted sum) works."""
+    c = cg.c3(seed=6, n=8, layers=4)
+    xs = cg.c3_bitstrings(n=8, count=32, seed=12)
+    x = torch.from_numpy(np.asarray(xs, dtype=np.int64)).cuda()
+    theta = torch.tensor([g["param"] for g in c["gates"] if g["param_id"] >= 0], dtype=torch.float64,
+                         device="cuda", requires_grad=True)
+    L = ProbabilityMass.apply(theta, c, x, "c128")
+    assert L.device.type == "cuda"
+    (3.0 * L).backward()
+    assert theta.grad.device.type == "cuda"
+    ref = OG.loss_grad_shift(c, xs)
+    r = 3.0 * np.array([ref[t] for t in range(len(theta))])
+    assert np.max(np.abs(theta.grad.cpu().numpy() - r)) < 1e-9 * np.max(np.abs(r))

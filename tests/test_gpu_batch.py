@@ -70,7 +70,8 @@ def test_autotune_keeps_results(small_batch):
     b = Batch(plans)
     outs = b.alloc_outputs()
     pol = b.tune(outs, mode="bf16x3")
-    assert pol in (0, 1, 2)
+    # any of the four policies may win on a given box
+    assert pol in range(4)
     b.run(outs, mode="bf16x3", graph=True)
     torch.cuda.synchronize()
     for c, o in zip(cs, outs):

@@ -142,3 +142,48 @@ def test_bf16x3_on_c2p_matches_fp64_mode():
     full = plan.amplitudes_full(A, B, mode="bf16x3")
     nrm = hsf_norm2(full.reshape(-1)).cpu().numpy()[0]
     assert abs(nrm - 1) < 1e-5
+
+
+@pytest.mark.parametrize("na,nb,K", [(9, 8, 40), (10, 9, 400), (8, 10, 17), (11, 7, 4096)])
+def test_presplit_row_tiles_equal_per_call_split(na, nb, K):
+    """hsf_split_operands once, then HSF_SUM_BF16X3_SPLIT on row tiles (some
+    cut by the tile size, the last one ragged): bit for bit the per-call
+    split-BF16 x3 sums of the same rows (the planes and the MFMA sequence are
+    the same), and within the c64 bar of the exact product.  Streaming
+    (K < 64) and LDS-staged (K >= 64) layouts."""
+    rng = np.random.default_rng(na * 100 + nb + K)
+    A = _rand(rng, K, 1 << na, np.complex64)
+    B = _rand(rng, K, 1 << nb, np.complex64)
+    ref = A.astype(np.complex128).T @ B.astype(np.complex128)
+    plan = _shape_plan(na, nb)
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ws = plan.split_operands(Ad, Bd)
+    M = 1 << na
+    cuts = [0, 64, 200, M // 2 + 3, M]
+    full = torch.zeros((M, 1 << nb), dtype=torch.complex64, device="cuda")
+    for r0, r1 in zip(cuts[:-1], cuts[1:]):
+        plan.amplitudes_full(Ad, Bd, rows=(r0, r1), mode="bf16x3_split", out=full[r0:r1], ws=ws)
+        one = plan.amplitudes_full(Ad, Bd, rows=(r0, r1), mode="bf16x3")
+        assert torch.equal(full[r0:r1], one), (r0, r1)
+    assert ohsf.rel_l2(full.cpu().numpy(), ref) < 1e-5
+
+
+def test_presplit_needs_the_split_workspace_and_path_count():
+    """HSF_SUM_BF16X3_SPLIT with another workspace or path count than the
+    plan's last split is rejected before any launch."""
+    from paper_2502_06959_amd import HsfError
+    rng = np.random.default_rng(5)
+    na, nb, K = 8, 8, 70
+    plan = _shape_plan(na, nb)
+    Ad = torch.from_numpy(_rand(rng, K, 1 << na, np.complex64)).cuda()
+    Bd = torch.from_numpy(_rand(rng, K, 1 << nb, np.complex64)).cuda()
+    ws = plan.split_operands(Ad, Bd)
+    other = torch.empty_like(ws)
+    out = torch.zeros((1 << na, 1 << nb), dtype=torch.complex64, device="cuda")
+    with pytest.raises(HsfError) as e:
+        plan.amplitudes_full(Ad, Bd, mode="bf16x3_split", out=out, ws=other)
+    assert e.value.code == "HSF_E_ARG"
+    with pytest.raises(HsfError) as e:
+        plan.amplitudes_full(Ad[:K - 1], Bd[:K - 1], n_paths=K - 1, mode="bf16x3_split", out=out, ws=ws)
+    assert e.value.code == "HSF_E_ARG"
+    assert torch.count_nonzero(out).item() == 0
