@@ -83,25 +83,27 @@ def loss_grad_fd(circuit, xs, param_ids=None, h=1e-4, use_hsf=True):
     return out
 
 
-def loss_grad_adjoint(circuit, xs):
-    """Full-state adjoint (n <= ~20): forward to the end, then walk back with
-    the bra lambda = sum_j conj(psi_j) <x_j| and the state, un-applying each
-    (unitary) gate."""
+def loss_grad_adjoint(circuit, xs, log=None):
+    """Full-state adjoint: forward to the end, then walk back with the bra
+    lambda = sum_j conj(psi_j) <x_j| and the state, un-applying each
+    (unitary) gate in place.  Two state vectors in memory (2 x 16 GiB at
+    n = 30); each rotation's term is one read-only inner product."""
     n = circuit["n"]
     xs = np.asarray(xs, dtype=np.uint64).astype(np.int64)
-    psi = sv.run(circuit)
-    lam = np.zeros_like(psi)
-    lam[xs] = psi[xs]                # ket form of the bra: <lam| = sum_j conj(psi_j) <x_j|
-    state = psi.copy()
+    state = sv.run(circuit)
+    lam = np.zeros_like(state)
+    lam[xs] = state[xs]              # ket form of the bra: <lam| = sum_j conj(psi_j) <x_j|
     grad = {}
-    for g in reversed(circuit["gates"]):
-        m = G.matrix(g)
+    gates = circuit["gates"]
+    for i in range(len(gates) - 1, -1, -1):
+        g = gates[i]
         if g["param_id"] >= 0 and g["kind"] in SHIFT_KINDS:
             # dU/dt = -i/2 P U  =>  contribution 2 Re <lam| (-i/2) P |state after gate>
-            gp = sv.run_ops(n, [(g["q"], G.generator(g))], psi=state.copy())
-            val = 2.0 * float(np.real(np.vdot(lam, -0.5j * gp)))
+            val = 2.0 * float(np.real(-0.5j * sv.braket(lam, state, n, g["q"], G.generator(g))))
             grad[g["param_id"]] = grad.get(g["param_id"], 0.0) + val
-        mh = m.conj().T
-        state = sv.run_ops(n, [(g["q"], mh)], psi=state)
-        lam = sv.run_ops(n, [(g["q"], mh)], psi=lam)
+        mh = np.ascontiguousarray(G.matrix(g).conj().T)
+        sv.apply(state, n, g["q"], mh)
+        sv.apply(lam, n, g["q"], mh)
+        if log is not None and i % 50 == 0:
+            log(f"adjoint: gate {i} of {len(gates)}")
     return grad

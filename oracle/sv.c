@@ -60,6 +60,50 @@ int sv_apply(cplx *psi, int n, const int *q, int k, const cplx *m) {
     return 0;
 }
 
+/* out = <l| (m on qubits q) |r> = sum_x conj(l[x]) (M r)[x] (the plain
+ * definition of a matrix element between two states, Sec. II-A indexing),
+ * one read-only pass over both states: the adjoint gradient's inner product
+ * without a temporary copy of the state. */
+int sv_braket(const cplx *l, const cplx *r, int n, const int *q, int k, const cplx *m, double *out) {
+    if (k < 1 || k > 8 || k > n) return -1;
+    int sorted[8];
+    for (int j = 0; j < k; ++j) {
+        if (q[j] < 0 || q[j] >= n) return -2;
+        sorted[j] = q[j];
+    }
+    for (int a = 0; a < k; ++a)
+        for (int b = a + 1; b < k; ++b)
+            if (sorted[b] < sorted[a]) { int t = sorted[a]; sorted[a] = sorted[b]; sorted[b] = t; }
+    for (int j = 1; j < k; ++j)
+        if (sorted[j] == sorted[j - 1]) return -3;
+    const int64_t d = 1ll << k;
+    const int64_t groups = 1ll << (n - k);
+    double re = 0.0, im = 0.0;
+#pragma omp parallel for schedule(static) reduction(+:re, im)
+    for (int64_t g = 0; g < groups; ++g) {
+        uint64_t base = spread((uint64_t)g, sorted, k);
+        uint64_t idx[256];
+        cplx v[256];
+        for (int64_t j = 0; j < d; ++j) {
+            uint64_t x = base;
+            for (int b = 0; b < k; ++b)
+                if ((j >> (k - 1 - b)) & 1) x |= 1ull << q[b];
+            idx[j] = x;
+            v[j] = r[x];
+        }
+        for (int64_t i = 0; i < d; ++i) {
+            cplx s = 0;
+            for (int64_t j = 0; j < d; ++j) s += m[i * d + j] * v[j];
+            cplx t = conj(l[idx[i]]) * s;
+            re += creal(t);
+            im += cimag(t);
+        }
+    }
+    out[0] = re;
+    out[1] = im;
+    return 0;
+}
+
 /* Apply a list of gates in order.  qs holds the qubits of all gates back to
  * back, ks their sizes, moff the offset of each matrix in mats. */
 int sv_run(cplx *psi, int n, int64_t n_ops, const int *qs, const int *ks,

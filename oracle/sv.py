@@ -38,6 +38,7 @@ def _load():
         lib.sv_apply.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P]
         lib.sv_run.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, P, P, P]
         lib.sv_run_many.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, P, P, P, P, P]
+        lib.sv_braket.argtypes = [P, P, ctypes.c_int, P, ctypes.c_int, P, P]
         _lib = lib
     return _lib
 
@@ -55,6 +56,20 @@ def apply(psi, n, qubits, m):
     rc = lib.sv_apply(_ptr(psi), n, _ptr(q), len(q), _ptr(m))
     if rc:
         raise ValueError(f"sv_apply failed ({rc})")
+
+
+def braket(lam, psi, n, qubits, m):
+    """<lam| (m on qubits) |psi> without copying either state."""
+    lib = _load()
+    for v in (lam, psi):
+        assert v.dtype == np.complex128 and v.flags.c_contiguous and v.size == 1 << n
+    q = np.asarray(qubits, dtype=np.int32)
+    m = np.ascontiguousarray(m, dtype=np.complex128)
+    out = np.zeros(2, dtype=np.float64)
+    rc = lib.sv_braket(_ptr(lam), _ptr(psi), n, _ptr(q), len(q), _ptr(m), _ptr(out))
+    if rc:
+        raise ValueError(f"sv_braket failed ({rc})")
+    return complex(out[0], out[1])
 
 
 def run_ops(n, ops, psi=None):

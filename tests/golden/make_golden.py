@@ -7,6 +7,10 @@ Calls only the FP64 oracle (`oracle/`) and the seeded circuit generators:
 c2_literal.npz  C2 (P=1024): psi at 4096 seeded basis states
 c3.npz          C3: psi at its 1024 bitstrings, L, and dL/dt for 16 seeded
                 parameter ids (parameter-shift rule on the oracle HSF)
+c3_grad.npz     C3: dL/dt for all 708 parameter ids by the full-state FP64
+                adjoint (two 2^30 states; about two hours on 8 cores), and
+                central differences (h = 1e-4) of the oracle HSF loss for 24
+                seeded ids
 c4.npz          C4 (P=4096): psi at 4096 seeded basis states
 c5.npz          C5 (64 circuits): psi at 64 seeded basis states of each circuit
 qaoa_q30.npz    single-layer QAOA MaxCut on a seeded SBM graph with Table II's
@@ -65,6 +69,20 @@ def main(which):
         print("c3 grads", f"{time.time() - t:.1f}s", flush=True)
         np.savez(os.path.join(OUT, "c3.npz"), x=xs, psi=amp, loss=L, grad_ids=np.array(ids),
                  grad=np.array([g[i] for i in ids]))
+    if "c3grad" in which:
+        c = cg.c3()
+        xs = cg.c3_bitstrings()
+        t = time.time()
+        log = lambda m: print(f"{m} ({time.time() - t:.0f}s)", flush=True)  # noqa: E731
+        rng = np.random.default_rng(3333)
+        fd_ids = sorted(rng.choice(c["meta"]["n_params"], 24, replace=False).tolist())
+        fd = OG.loss_grad_fd(c, xs, fd_ids, h=1e-4, use_hsf=True)
+        log("c3 central differences")
+        adj = OG.loss_grad_adjoint(c, xs, log=log)
+        log("c3 adjoint")
+        ids = np.arange(c["meta"]["n_params"])
+        np.savez(os.path.join(OUT, "c3_grad.npz"), grad=np.array([adj[i] for i in ids]),
+                 fd_ids=np.array(fd_ids), fd=np.array([fd[i] for i in fd_ids]), fd_h=1e-4)
     if "c4" in which:
         xs, amp = sampled_psi(cg.c4(), 4096, 44)
         np.savez(os.path.join(OUT, "c4.npz"), x=xs, psi=amp)

@@ -159,7 +159,7 @@ def test_presplit_row_tiles_equal_per_call_split(na, nb, K):
     Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     ws = plan.split_operands(Ad, Bd)
     M = 1 << na
-    cuts = [0, 64, 200, M // 2 + 3, M]
+    cuts = sorted({0, 64, 200, M // 2 + 3, M})
     full = torch.zeros((M, 1 << nb), dtype=torch.complex64, device="cuda")
     for r0, r1 in zip(cuts[:-1], cuts[1:]):
         plan.amplitudes_full(Ad, Bd, rows=(r0, r1), mode="bf16x3_split", out=full[r0:r1], ws=ws)

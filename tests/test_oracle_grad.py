@@ -49,3 +49,23 @@ def test_shared_parameter_sums_occurrences():
     gf = OG.loss_grad_fd(c, xs, h=1e-5, use_hsf=False)
     for t in gs:
         assert abs(gs[t] - gf[t]) < 1e-7
+
+
+def test_braket_is_matrix_element_of_embedded_gate():
+    """sv.braket(l, r, q, M) = l^H (M on q, as a dense 2^n x 2^n matrix built
+    entry by entry) r, for random states and a random non-unitary 2-qubit M
+    on non-adjacent qubits in both orders."""
+    import numpy as np
+    from oracle import sv
+    rng = np.random.default_rng(17)
+    n = 6
+    l = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    r = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    m = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+    for q in ([1, 4], [4, 1], [0, 5]):
+        want = np.vdot(l, sv.embed(n, q, m) @ r)
+        got = sv.braket(l, r, n, q, m)
+        assert abs(got - want) < 1e-12 * abs(want)
+    m1 = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+    want = np.vdot(l, sv.embed(n, [3], m1) @ r)
+    assert abs(sv.braket(l, r, n, [3], m1) - want) < 1e-12 * abs(want)
