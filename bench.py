@@ -181,6 +181,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP32 path sum")
     ap.add_argument("--plain-steps", type=int, default=None,
                     help="timed steps of the plain FP32 leg (default: all steps, at most 2 on c4)")
+    ap.add_argument("--qaoa-instances", default=None,
+                    help="comma-separated Table II names (q30-1, ...) to run with --workload qaoa (default: all 12)")
+    ap.add_argument("--no-standard", action="store_true",
+                    help="--workload qaoa: skip the standard-cutting comparison runs")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--tree", default="auto", choices=["auto", "on", "off"],
                     help="path-tree sweeps (one state per distinct leading-digit prefix)")
@@ -637,7 +641,10 @@ def bench_qaoa(args):
     mode = args.mode
     rows_out = []
     total_j = 0.0
+    pick = set(args.qaoa_instances.split(",")) if args.qaoa_instances else None
     for i, (name, sizes, pout, paper_j, paper_log2p) in enumerate(TABLE2):
+        if pick is not None and name not in pick:
+            continue
         c = cg.qaoa_sbm(100 + i, sizes, 0.8, pout)
         t0 = time.perf_counter()
         r = joint_blocked(c)
@@ -653,7 +660,9 @@ def bench_qaoa(args):
         std["blocks"] = [[k] for k, g in enumerate(c["gates"])
                          if 0 < sum(q <= c["cut"] for q in g["q"]) < len(g["q"])]
         ps = Plan(std, tree=args.tree)
-        if ps.P <= (1 << 16):
+        if args.no_standard:
+            t_ms, t_kind = float("nan"), "skipped"
+        elif ps.P <= (1 << 16):
             t_ms = _first_amplitudes(ps, min(ps.P, 1 << 14), rows, mode, out)
             t_kind = "measured"
         else:
@@ -667,7 +676,8 @@ def bench_qaoa(args):
                          "log2_paths_joint": int(pj.P).bit_length() - 1,
                          "log2_paths_standard": int(ps.P).bit_length() - 1,
                          "joint_ms": j_ms, "joint_host_plan_ms": host_ms,
-                         "standard_ms": t_ms, "standard_timing": t_kind, "standard_over_joint": t_ms / j_ms,
+                         "standard_ms": None if args.no_standard else t_ms, "standard_timing": t_kind,
+                         "standard_over_joint": None if args.no_standard else t_ms / j_ms,
                          "paper_joint_cpu_s": paper_j, "paper_log2_paths_joint": paper_log2p})
         del out
         torch.cuda.empty_cache()
@@ -678,7 +688,8 @@ def bench_qaoa(args):
            "config": {"workload": "qaoa: single-layer QAOA MaxCut on seeded SBM graphs, Table II sizes, "
                                   "p_intra 0.8, first 10^6 amplitudes"},
            "instances": rows_out,
-           "geomean_standard_over_joint": float(np.exp(np.mean([np.log(x["standard_over_joint"]) for x in rows_out])))}
+           "geomean_standard_over_joint": (float(np.exp(np.mean([np.log(x["standard_over_joint"]) for x in rows_out])))
+                                           if not args.no_standard else None)}
     print(json.dumps(res), flush=True)
 
 

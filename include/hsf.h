@@ -232,7 +232,8 @@ hsf_status hsf_sweep_form(hsf_plan_t plan, int64_t n_paths, int32_t* tree, int32
  *   planner sweeps n_paths paths level by level; else 0), 1 =
  *   hsf_amplitudes_full with path-sum mode
  *   `mode`, 2 = hsf_backward with chunks of `n_paths` paths and `mode` =
- *   number of bitstrings n_x.                                                  */
+ *   number of bitstrings n_x, 3 = hsf_loss with chunks of `n_paths` paths
+ *   and `mode` = n_x.                                                          */
 size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t mode);
 
 /* Per-path half-states for paths [p_begin, p_end) (Sec. II-B): row j of
@@ -306,15 +307,33 @@ hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dt
 
 /* ------------------------------------------------------------ gradient ---- */
 
-/* Gradient of the probability mass L = sum_j |psi(x_j)|^2 of n_x basis
- * states x (device array) with respect to every parameter id (0..n_params-1)
- * of the circuit's rotation gates (RX, RY, RZ, RZZ; PHASE and CP outside
- * blocks).  psi is the HSF state of Sec. II-B; d psi/d t follows from the
- * chain rule through the per-path half-states.  Angles outside blocks use an
- * adjoint sweep per path (state checkpointed in front of each Schmidt factor,
- * which has no inverse); angles inside a block use the exact parameter-shift
- * rule with the block re-factored (Sec. IV-A) at t +- pi/2.  grad: n_params
- * device doubles, overwritten.  Paths are processed `chunk` at a time; ws:
+/* Probability mass of chosen basis states (Sec. V computes a subset of the
+ * amplitudes): L = sum_j |psi(x_j)|^2 over the n_x basis states x (device
+ * array of indices < 2^n), psi the HSF state of Sec. II-B summed over all
+ * paths.  The library runs the half-states of both sides `chunk` paths at a
+ * time (the path tree where it pays), accumulates psi(x_j) in FP64 over the
+ * chunks and reduces L in a fixed order (bitwise reproducible).  loss: one
+ * device double, overwritten.  amps: NULL, or n_x complex128 device entries
+ * that receive psi(x_j).  ws: hsf_workspace_size(plan, 3, chunk, n_x) bytes
+ * (device).  n_x = 0 gives L = 0 (x may then be NULL).                      */
+hsf_status hsf_loss(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* loss, void* amps,
+                    int64_t chunk, void* ws, size_t ws_bytes, hsf_stream_t stream);
+
+/* Gradient with respect to every parameter id (0..n_params-1) of the
+ * circuit's rotation gates (RX, RY, RZ, RZZ; PHASE and CP outside blocks) of
+ * a real loss L of the amplitudes psi(x_j) of n_x basis states x (device
+ * array); psi is the HSF state of Sec. II-B and d psi/d t follows from the
+ * chain rule through the per-path half-states.  dL_dpsi: NULL for the
+ * probability mass L = sum_j |psi(x_j)|^2, else n_x complex128 device
+ * cotangents g_j = dL/dRe psi(x_j) + i dL/dIm psi(x_j) (the convention of
+ * torch's complex gradients), giving grad[t] = sum_j Re(conj(g_j)
+ * d psi(x_j)/d t).  Angles outside blocks use an adjoint sweep per path
+ * (state checkpointed in front of each Schmidt factor, which has no
+ * inverse); an angle inside a block's hull uses the exact shift rule on the
+ * amplitudes, d psi/d t = psi(t + pi) / 2 (every such gate is exp(-i t P/2)
+ * with P^2 = 1), psi(t + pi) being one forward with the block re-factored
+ * (Sec. IV-A) at the shifted angle.  grad: n_params device doubles,
+ * overwritten.  Paths are processed `chunk` at a time; ws:
  * hsf_workspace_size(plan, 2, chunk, n_x) bytes.  Reductions run in a fixed
  * order (bitwise reproducible).  Synchronises `stream` (host tables are
  * staged through it), so it cannot be captured in a graph; the shifted
@@ -323,7 +342,7 @@ hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dt
  * returns).  Returns HSF_E_UNSUPPORTED if a shifted block needs more Schmidt
  * terms than the plan.  n_x = 0, or a circuit without angles, gives a zero
  * gradient.                                                                  */
-hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* grad,
+hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, const void* dL_dpsi, double* grad,
                         int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes,
                         hsf_stream_t stream);
 

@@ -73,8 +73,9 @@ SIGNATURES = {
                                             c_int64, c_void_p, c_int32, c_void_p]),
     "hsf_norm2": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_size_t,
                             c_void_p]),
-    "hsf_backward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_size_t,
-                               c_void_p]),
+    "hsf_backward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_int64, c_void_p,
+                               c_size_t, c_void_p]),
+    "hsf_loss": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p]),
     "hsf_batch_create": (c_int32, [P(c_void_p), c_int32, P(c_void_p)]),
     "hsf_batch_destroy": (None, [c_void_p]),
     "hsf_batch_workspace_size": (c_size_t, [c_void_p, c_int32]),

@@ -34,6 +34,39 @@ using namespace hsf;
         return fail(HSF_E_ARG, std::string("internal error: ") + e.what()); \
     }
 
+namespace hsf {
+
+// Argument checks and dispatch of hsf_amplitudes_full (also the body of its
+// variant on the library's static scratch).
+hsf_status amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA, const void* psiB, int64_t ldB,
+                           int64_t n_paths, int64_t row_begin, int64_t row_end, void* out, int64_t ldo, int32_t mode,
+                           int32_t accumulate, void* ws, size_t ws_bytes, hipStream_t stream) {
+    const bool presplit = mode == HSF_SUM_BF16X3_SPLIT;
+    if (!plan || (n_paths > 0 && !presplit && (!psiA || !psiB))) return fail(HSF_E_ARG, "null argument");
+    const Plan* p = reinterpret_cast<const Plan*>(plan);
+    const int64_t M = int64_t(1) << p->na, N = int64_t(1) << p->nb;
+    if (n_paths < 0) return fail(HSF_E_ARG, "negative path count");
+    if (row_begin < 0 || row_end > M || row_begin > row_end) return fail(HSF_E_ARG, "row range outside [0, 2^n_a)");
+    if ((!presplit && (ldA < M || ldB < N)) || ldo < N) return fail(HSF_E_ARG, "leading dimension too small");
+    if (mode < HSF_SUM_F32 || mode > HSF_SUM_BF16X3_SPLIT) return fail(HSF_E_ARG, "unknown path-sum mode");
+    if (p->dtype == HSF_C128 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3 || presplit))
+        return fail(HSF_E_ARG, "c128 half-states need HSF_SUM_F64 or HSF_SUM_C128");
+    if ((mode == HSF_SUM_BF16X3 || presplit) && ws_bytes < bf16x3_workspace(p->na, p->nb, n_paths))
+        return fail(HSF_E_ARG, "workspace too small for HSF_SUM_BF16X3");
+    if (presplit && n_paths > 0 && (!ws || ws != p->split_ws || n_paths != p->split_paths))
+        return fail(HSF_E_ARG, "HSF_SUM_BF16X3_SPLIT needs the workspace and path count of the plan's last "
+                               "hsf_split_operands call");
+    if (row_begin == row_end) return HSF_OK;
+    if (!out) return fail(HSF_E_ARG, "null argument");
+    if (presplit && n_paths > 0)
+        return path_sum_presplit(n_paths, M, row_begin, row_end - row_begin, N, ws, (float2*)out, ldo, accumulate,
+                                 stream);
+    return path_sum(p->dtype, mode, psiA, ldA, psiB, ldB, n_paths, row_begin, row_end - row_begin, N, out, ldo,
+                    accumulate, ws, stream);
+}
+
+}  // namespace hsf
+
 extern "C" {
 
 const char* hsf_last_error(void) { return g_last_error.c_str(); }
@@ -192,6 +225,7 @@ size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t 
     if (op == 1 && (mode == HSF_SUM_BF16X3 || mode == HSF_SUM_BF16X3_SPLIT))
         return bf16x3_workspace(p->na, p->nb, n_paths);
     if (op == 2) return backward_workspace(*p, n_paths, mode);
+    if (op == 3) return loss_workspace(*p, std::max<int64_t>(n_paths, 1), mode);
     return 0;
 }
 
@@ -216,28 +250,8 @@ hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA, c
                                void* out, int64_t ldo, int32_t mode, int32_t accumulate, void* ws,
                                size_t ws_bytes, hsf_stream_t stream) {
     HSF_GUARD_BEGIN
-    const bool presplit = mode == HSF_SUM_BF16X3_SPLIT;
-    if (!plan || (n_paths > 0 && !presplit && (!psiA || !psiB))) return fail(HSF_E_ARG, "null argument");
-    const Plan* p = P_(plan);
-    const int64_t M = int64_t(1) << p->na, N = int64_t(1) << p->nb;
-    if (n_paths < 0) return fail(HSF_E_ARG, "negative path count");
-    if (row_begin < 0 || row_end > M || row_begin > row_end) return fail(HSF_E_ARG, "row range outside [0, 2^n_a)");
-    if ((!presplit && (ldA < M || ldB < N)) || ldo < N) return fail(HSF_E_ARG, "leading dimension too small");
-    if (mode < HSF_SUM_F32 || mode > HSF_SUM_BF16X3_SPLIT) return fail(HSF_E_ARG, "unknown path-sum mode");
-    if (p->dtype == HSF_C128 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3 || presplit))
-        return fail(HSF_E_ARG, "c128 half-states need HSF_SUM_F64 or HSF_SUM_C128");
-    if ((mode == HSF_SUM_BF16X3 || presplit) && ws_bytes < bf16x3_workspace(p->na, p->nb, n_paths))
-        return fail(HSF_E_ARG, "workspace too small for HSF_SUM_BF16X3");
-    if (presplit && n_paths > 0 && (!ws || ws != p->split_ws || n_paths != p->split_paths))
-        return fail(HSF_E_ARG, "HSF_SUM_BF16X3_SPLIT needs the workspace and path count of the plan's last "
-                               "hsf_split_operands call");
-    if (row_begin == row_end) return HSF_OK;
-    if (!out) return fail(HSF_E_ARG, "null argument");
-    if (presplit && n_paths > 0)
-        return path_sum_presplit(n_paths, M, row_begin, row_end - row_begin, N, ws, (float2*)out, ldo, accumulate,
-                                 (hipStream_t)stream);
-    return path_sum(p->dtype, mode, psiA, ldA, psiB, ldB, n_paths, row_begin, row_end - row_begin, N,
-                    out, ldo, accumulate, ws, (hipStream_t)stream);
+    return amplitudes_full(plan, psiA, ldA, psiB, ldB, n_paths, row_begin, row_end, out, ldo, mode, accumulate, ws,
+                           ws_bytes, (hipStream_t)stream);
     HSF_GUARD_END
 }
 
@@ -291,8 +305,8 @@ hsf_status hsf_norm2(const void* a, int32_t a_dtype, const void* b, int32_t b_dt
     HSF_GUARD_END
 }
 
-hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* grad, int64_t n_params,
-                        int64_t chunk, void* ws, size_t ws_bytes, hsf_stream_t stream) {
+hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, const void* dL_dpsi, double* grad,
+                        int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes, hsf_stream_t stream) {
     HSF_GUARD_BEGIN
     if (!plan || !grad || (n_x > 0 && !x)) return fail(HSF_E_ARG, "null argument");
     Plan* p = P_(plan);
@@ -303,7 +317,23 @@ hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double*
     DeviceCopy* d = nullptr;
     hsf_status s = ensure_device(*p, &d);
     if (s != HSF_OK) return s;
-    return backward(*p, *d, x, n_x, grad, n_params, chunk, ws, ws_bytes, (hipStream_t)stream);
+    return backward(*p, *d, x, n_x, n_x > 0 ? dL_dpsi : nullptr, grad, n_params, chunk, ws, ws_bytes,
+                    (hipStream_t)stream);
+    HSF_GUARD_END
+}
+
+hsf_status hsf_loss(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* loss, void* amps, int64_t chunk,
+                    void* ws, size_t ws_bytes, hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    if (!plan || !loss || (n_x > 0 && !x) || !ws) return fail(HSF_E_ARG, "null argument");
+    Plan* p = P_(plan);
+    if (chunk <= 0) return fail(HSF_E_ARG, "chunk must be positive");
+    if (n_x < 0) return fail(HSF_E_ARG, "negative bitstring count");
+    if (ws_bytes < loss_workspace(*p, chunk, n_x)) return fail(HSF_E_ARG, "workspace too small");
+    DeviceCopy* d = nullptr;
+    hsf_status s = ensure_device(*p, &d);
+    if (s != HSF_OK) return s;
+    return prob_mass(*p, *d, x, n_x, loss, amps, chunk, ws, ws_bytes, (hipStream_t)stream);
     HSF_GUARD_END
 }
 

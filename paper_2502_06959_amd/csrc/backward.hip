@@ -1,4 +1,8 @@
-// Gradient of L = sum_j |psi(x_j)|^2 with respect to rotation angles.
+// Gradient with respect to rotation angles of a real loss of the amplitudes
+// psi(x_j) of chosen basis states: by default L = sum_j |psi(x_j)|^2, or any
+// loss whose cotangents g_j = dL/dRe psi(x_j) + i dL/dIm psi(x_j) the caller
+// passes; with c_j = g_j / 2 (c_j = psi(x_j) for the default),
+// dL/dt = 2 Re sum_j conj(c_j) dpsi(x_j)/dt.
 //
 // psi(x) = sum_p a_p[x_a] b_p[x_b] (Sec. II-B), so for an angle t of a gate
 // outside every block, on side a,
@@ -12,9 +16,11 @@
 // every factor slot and the backward pass restores it there.
 //
 // Angles inside a block's hull change the block operator and with it the SVD;
-// they use the parameter-shift rule on the block: every gate here is
-// exp(-i t P / 2), so dL/dt = [L(t + pi/2) - L(t - pi/2)] / 2, each L a full
-// forward with that block re-factored.
+// they use the shift rule on the amplitudes: every gate here is
+// U(t) = exp(-i t P / 2) with P^2 = 1, so dU/dt = U(t + pi) / 2 and
+// dpsi/dt = psi(t + pi) / 2 exactly, psi(t + pi) being a full forward with
+// that block re-factored at t + pi: dL/dt = Re sum_j conj(c_j) psi_j(t + pi),
+// one shifted forward per occurrence of the angle.
 //
 // Every reduction runs in a fixed order (no atomics), so results are
 // bitwise reproducible.
@@ -545,9 +551,29 @@ __global__ __launch_bounds__(256) void bw_loss(const double2* __restrict__ amp, 
     if (threadIdx.x == 0) *out = r[0];
 }
 
-__global__ void bw_shift_combine(const double* __restrict__ lp, const double* __restrict__ lm, double* __restrict__ grad,
-                                 int64_t t) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) grad[t] += 0.5 * (*lp - *lm);
+// out = Re sum_j conj(c_j) amp_j in a fixed order (one block)
+__global__ __launch_bounds__(256) void bw_shift_dot(const double2* __restrict__ c, const double2* __restrict__ amp,
+                                                    int64_t n, double* __restrict__ out) {
+    __shared__ double r[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += c[i].x * amp[i].x + c[i].y * amp[i].y;
+    r[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = r[0];
+}
+
+__global__ void bw_shift_add(const double* __restrict__ v, double* __restrict__ grad, int64_t t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) grad[t] += *v;
+}
+
+// c_j = g_j / 2: the caller's cotangents as the coefficients of the adjoint
+__global__ void bw_half(const double2* __restrict__ g, double2* __restrict__ c, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c[i] = make_double2(0.5 * g[i].x, 0.5 * g[i].y);
 }
 
 // ---------------------------------------------------------------- host ----
@@ -611,10 +637,10 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
         for (int tr = 0; tr < 2; ++tr)
             for (const Schedule& sc : tr ? p.side[s].tree : p.side[s].sched)
                 L.pool_elems += std::max<size_t>(sc.pool.size(), 1);
-    // parameter shifts of angles inside blocks: two forward runs each, each
+    // shifts of angles inside blocks: one forward run per occurrence, each
     // with its own copy of the pools
     L.n_shift = 0;
-    for (const Block& b : p.blocks) L.n_shift += 2 * (int64_t)b.params.size();
+    for (const Block& b : p.blocks) L.n_shift += (int64_t)b.params.size();
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -823,8 +849,8 @@ struct Runner {
 };
 
 template <typename T>
-hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, double* grad, int64_t n_params,
-                      int64_t chunk, void* ws, size_t ws_bytes, hipStream_t st) {
+hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, const double2* dl_dpsi, double* grad,
+                      int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes, hipStream_t st) {
     using V = typename Cx<T>::v;
     const Layout Lo = layout(p, chunk, nx);
     if (ws_bytes < Lo.total) return fail(HSF_E_ARG, "workspace too small for hsf_backward");
@@ -972,13 +998,22 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
                        grad, n_params);
     if ((s = hip_check(hipGetLastError(), "zero grad")) != HSF_OK) return s;
 
-    // ---- psi(x_j) for every bitstring: tiled forward over all paths
-    for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
-        const int64_t np = std::min(chunk, p.P - p0);
-        if ((s = run_sides(p, d, p0, np, vS[0], dim[0], vS[1], dim[1], base + Lo.tree, Lo.tree_bytes, st)) != HSF_OK)
-            return s;
-        if ((s = gather_dot(p.dtype, vS[0], dim[0], vS[1], dim[1], np, p.nb, p.n, x, nx, psi_x, p0 > 0 ? 1 : 0, st)) != HSF_OK)
-            return s;
+    // ---- coefficients c_j: psi(x_j) for every bitstring (tiled forward over
+    // all paths), or half the caller's cotangents
+    if (dl_dpsi) {
+        hipLaunchKernelGGL(bw_half, dim3((uint32_t)std::min<int64_t>(1024, (nx + 255) / 256)), dim3(256), 0, st,
+                           dl_dpsi, psi_x, nx);
+        if ((s = hip_check(hipGetLastError(), "bw_half launch")) != HSF_OK) return s;
+    } else {
+        for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
+            const int64_t np = std::min(chunk, p.P - p0);
+            if ((s = run_sides(p, d, p0, np, vS[0], dim[0], vS[1], dim[1], base + Lo.tree, Lo.tree_bytes, st)) !=
+                HSF_OK)
+                return s;
+            if ((s = gather_dot(p.dtype, vS[0], dim[0], vS[1], dim[1], np, p.nb, p.n, x, nx, psi_x, p0 > 0 ? 1 : 0,
+                                st)) != HSF_OK)
+                return s;
+        }
     }
 
     // ---- adjoint over angles outside blocks
@@ -1095,7 +1130,7 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
         }
     }
 
-    // ---- angles inside blocks: parameter shift on the re-factored block
+    // ---- angles inside blocks: amplitude shift rule on the re-factored block
     bool any = false;
     for (const Block& b : p.blocks) any |= !b.params.empty();
     std::vector<V> staged;    // host copy of the shifted pools; must outlive the upload (final sync)
@@ -1110,17 +1145,16 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
                     pool_at[2 * side + tr].push_back(o);
                     o += std::max<size_t>(sc.pool.size(), 1);
                 }
-        const double half_pi = std::acos(0.0);
+        const double pi = 2.0 * std::acos(0.0);
         struct Shift {
             size_t k;
             int64_t gid;
-            int t, sg;
+            int t;
         };
         std::vector<Shift> shifts;
         for (size_t k = 0; k < p.blocks.size(); ++k)
             for (const auto& gp : p.blocks[k].params)
-                if (gp.second < n_params)
-                    for (int sg = 0; sg < 2; ++sg) shifts.push_back({k, gp.first, gp.second, sg});
+                if (gp.second < n_params) shifts.push_back({k, gp.first, gp.second});
         const size_t ns = shifts.size();
         // every shifted block re-factored on the host, in parallel (they are
         // independent), into its own patched copy of the pools
@@ -1131,7 +1165,7 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             const Shift& sh = shifts[i];
             const Block& b = p.blocks[sh.k];
             Factors fs;
-            const double ang = p.gates[sh.gid].param + (sh.sg == 0 ? half_pi : -half_pi);
+            const double ang = p.gates[sh.gid].param + pi;
             hsf_status e = factor_block(p, b, sh.gid, ang, fs);
             if (e != HSF_OK) {
                 hst[i] = e;
@@ -1259,8 +1293,9 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
                                    p0 > 0 ? 1 : 0, ln.st);
             }
             if (s != HSF_OK) break;
-            hipLaunchKernelGGL(bw_loss, dim3(1), dim3(256), 0, ln.st, (const double2*)ln.psi, nx, lossb + i);
-            s = hip_check(hipGetLastError(), "bw_loss launch");
+            hipLaunchKernelGGL(bw_shift_dot, dim3(1), dim3(256), 0, ln.st, (const double2*)psi_x,
+                               (const double2*)ln.psi, nx, lossb + i);
+            s = hip_check(hipGetLastError(), "bw_shift_dot launch");
         }
         // the caller's stream waits for every lane before combining
         for (int l = 1; l < nl && s == HSF_OK; ++l) {
@@ -1277,11 +1312,10 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
             cleanup();
             return s;
         }
-        // dL/dt += (L(t + pi/2) - L(t - pi/2)) / 2 per occurrence, in plan order
-        for (size_t i = 0; i < ns && s == HSF_OK; i += 2) {
-            hipLaunchKernelGGL(bw_shift_combine, dim3(1), dim3(1), 0, st, lossb + i, lossb + i + 1, grad,
-                               (int64_t)shifts[i].t);
-            s = hip_check(hipGetLastError(), "bw_shift_combine launch");
+        // dL/dt += Re sum_j conj(c_j) psi_j(t + pi) per occurrence, in plan order
+        for (size_t i = 0; i < ns && s == HSF_OK; ++i) {
+            hipLaunchKernelGGL(bw_shift_add, dim3(1), dim3(1), 0, st, lossb + i, grad, (int64_t)shifts[i].t);
+            s = hip_check(hipGetLastError(), "bw_shift_add launch");
         }
         // the lanes' streams go once the caller's stream has drained them
         const hsf_status sync = hip_check(hipStreamSynchronize(st), "sync");
@@ -1297,10 +1331,51 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, dou
 
 size_t backward_workspace(const Plan& p, int64_t chunk, int64_t nx) { return layout(p, chunk, nx).total; }
 
-hsf_status backward(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, double* grad, int64_t n_params,
-                    int64_t chunk, void* ws, size_t ws_bytes, hipStream_t stream) {
-    if (p.dtype == HSF_C128) return backward_t<double>(p, d, x, nx, grad, n_params, chunk, ws, ws_bytes, stream);
-    return backward_t<float>(p, d, x, nx, grad, n_params, chunk, ws, ws_bytes, stream);
+// hsf_loss: half-states of both sides per path chunk, then psi(x_j)
+// accumulated over the chunks (FP64), then L = sum_j |psi(x_j)|^2.
+size_t loss_workspace(const Plan& p, int64_t chunk, int64_t nx) {
+    const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
+    return align256((size_t)chunk * ((size_t)1 << p.na) * esz) + align256((size_t)chunk * ((size_t)1 << p.nb) * esz) +
+           align256((size_t)nx * 16) + align256(tree_workspace(p, chunk)) + 256;
+}
+
+hsf_status prob_mass(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, double* loss, void* amps, int64_t chunk,
+                     void* ws, size_t ws_bytes, hipStream_t st) {
+    if (ws_bytes < loss_workspace(p, chunk, nx)) return fail(HSF_E_ARG, "workspace too small for hsf_loss");
+    const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
+    const int64_t dA = int64_t(1) << p.na, dB = int64_t(1) << p.nb;
+    unsigned char* b = reinterpret_cast<unsigned char*>(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    void* vA = b;
+    b += align256((size_t)chunk * dA * esz);
+    void* vB = b;
+    b += align256((size_t)chunk * dB * esz);
+    double2* amp = amps ? (double2*)amps : (double2*)b;
+    b += align256((size_t)nx * 16);
+    unsigned char* tree = b;
+    const size_t tree_bytes = tree_workspace(p, chunk);
+    hsf_status s = HSF_OK;
+    if (nx > 0) {
+        if (p.P == 0) {
+            hipLaunchKernelGGL(bw_zero_doubles, dim3((uint32_t)std::min<int64_t>(1024, (2 * nx + 255) / 256)),
+                               dim3(256), 0, st, (double*)amp, 2 * nx);
+            if ((s = hip_check(hipGetLastError(), "zero amplitudes")) != HSF_OK) return s;
+        }
+        for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
+            const int64_t np = std::min(chunk, p.P - p0);
+            if ((s = run_sides(p, d, p0, np, vA, dA, vB, dB, tree, tree_bytes, st)) != HSF_OK) return s;
+            if ((s = gather_dot(p.dtype, vA, dA, vB, dB, np, p.nb, p.n, x, nx, amp, p0 > 0 ? 1 : 0, st)) != HSF_OK)
+                return s;
+        }
+    }
+    hipLaunchKernelGGL(bw_loss, dim3(1), dim3(256), 0, st, (const double2*)amp, nx, loss);
+    return hip_check(hipGetLastError(), "bw_loss launch");
+}
+
+hsf_status backward(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, const void* dl_dpsi, double* grad,
+                    int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes, hipStream_t stream) {
+    const double2* g = (const double2*)dl_dpsi;
+    if (p.dtype == HSF_C128) return backward_t<double>(p, d, x, nx, g, grad, n_params, chunk, ws, ws_bytes, stream);
+    return backward_t<float>(p, d, x, nx, g, grad, n_params, chunk, ws, ws_bytes, stream);
 }
 
 }  // namespace hsf

@@ -118,6 +118,11 @@ hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void*
                     int64_t K, int64_t row0, int64_t M, int64_t N, void* out, int64_t ldo,
                     int accumulate, void* ws, hipStream_t stream);
 
+// hsf_amplitudes_full's checks and dispatch (api.cpp).
+hsf_status amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA, const void* psiB, int64_t ldB,
+                           int64_t n_paths, int64_t row_begin, int64_t row_end, void* out, int64_t ldo, int32_t mode,
+                           int32_t accumulate, void* ws, size_t ws_bytes, hipStream_t stream);
+
 hsf_status gather_dot(int dtype, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K,
                       int nb, int n, const uint64_t* x, int64_t nx, void* out, int accumulate,
                       hipStream_t stream);
@@ -126,8 +131,13 @@ hsf_status norm2(const void* a, int adt, const void* b, int bdt, int64_t n, doub
                  hipStream_t stream);
 
 size_t backward_workspace(const Plan& p, int64_t chunk, int64_t nx);
-hsf_status backward(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, double* grad,
+// dl_dpsi: n x complex128 cotangents on the device, or null for the
+// probability mass
+hsf_status backward(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, const void* dl_dpsi, double* grad,
                     int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t loss_workspace(const Plan& p, int64_t chunk, int64_t nx);
+hsf_status prob_mass(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, double* loss, void* amps, int64_t chunk,
+                     void* ws, size_t ws_bytes, hipStream_t stream);
 
 inline hsf_status hip_check(hipError_t e, const char* what) {
     if (e == hipSuccess) return HSF_OK;

@@ -158,9 +158,20 @@ def hsf_norm2(a, b=None):
     return out
 
 
-def hsf_backward(plan, x, grad, chunk, ws):
-    L.check(L.lib().hsf_backward(ctypes.c_void_p(plan), _ptr(x), x.numel(), _ptr(grad), grad.numel(), chunk,
-                                 _ptr(ws), ws.numel() * ws.element_size(), _stream(grad)))
+def hsf_backward(plan, x, grad, chunk, ws, dl_dpsi=None):
+    """grad <- dL/dt for every parameter id; dl_dpsi: None (probability mass)
+    or complex128 cotangents of psi(x_j) on the device."""
+    if dl_dpsi is not None:
+        assert dl_dpsi.dtype == torch.complex128 and dl_dpsi.is_contiguous() and dl_dpsi.numel() == x.numel()
+    L.check(L.lib().hsf_backward(ctypes.c_void_p(plan), _ptr(x), x.numel(), _ptr(dl_dpsi), _ptr(grad), grad.numel(),
+                                 chunk, _ptr(ws), ws.numel() * ws.element_size(), _stream(grad)))
+
+
+def hsf_loss(plan, x, loss, chunk, ws, amps=None):
+    """loss (one float64 device entry) <- sum_j |psi(x_j)|^2; amps (optional
+    complex128, x.numel() entries) <- psi(x_j)."""
+    L.check(L.lib().hsf_loss(ctypes.c_void_p(plan), _ptr(x), x.numel(), _ptr(loss), _ptr(amps), chunk, _ptr(ws),
+                             ws.numel() * ws.element_size(), _stream(loss)))
 
 
 class Plan:
@@ -300,27 +311,32 @@ class Plan:
         hsf_amplitudes_bitstrings(self.handle, psiA, psiB, n_paths, x, out, accumulate)
         return out
 
-    def backward(self, x, chunk=None, grad=None):
-        """d/dt of L = sum_j |psi(x_j)|^2 for every parameter id (float64
-        tensor of n_params entries).  x: device tensor of basis-state indices."""
+    def backward(self, x, chunk=None, grad=None, dl_dpsi=None):
+        """dL/dt for every parameter id (float64 tensor of n_params entries).
+        x: device tensor of basis-state indices.  dl_dpsi: None for L =
+        sum_j |psi(x_j)|^2, else complex128 cotangents dL/dRe psi(x_j) +
+        i dL/dIm psi(x_j)."""
         chunk = min(self.P, 256) if chunk is None else chunk
         nbytes = hsf_workspace_size(self.handle, 2, chunk, x.numel())
         ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
         if grad is None:
             grad = torch.zeros(max(self.n_params, 1), dtype=torch.float64, device=x.device)
-        hsf_backward(self.handle, x, grad, chunk, ws)
+        hsf_backward(self.handle, x, grad, chunk, ws, dl_dpsi)
         return grad[:self.n_params]
+
+    def loss_device(self, x, chunk=None, amps=None):
+        """L = sum_j |psi(x_j)|^2 as a one-entry float64 device tensor, from
+        hsf_loss (every path chunk and the reduction inside the library);
+        amps, if given, receives psi(x_j)."""
+        chunk = min(self.P, 256) if chunk is None else chunk
+        ws = torch.empty(hsf_workspace_size(self.handle, 3, chunk, x.numel()), dtype=torch.uint8, device=x.device)
+        loss = torch.empty(1, dtype=torch.float64, device=x.device)
+        hsf_loss(self.handle, x, loss, chunk, ws, amps)
+        return loss
 
     def loss(self, x, chunk=None):
         """L = sum_j |psi(x_j)|^2 (forward only), as a float."""
-        chunk = min(self.P, 256) if chunk is None else chunk
-        A, B = self.alloc_halves(chunk, device=x.device)
-        amp = torch.zeros(x.numel(), dtype=torch.complex128, device=x.device)
-        for p0 in range(0, self.P, chunk):
-            p1 = min(self.P, p0 + chunk)
-            self.run_paths(p0, p1, A[:p1 - p0], B[:p1 - p0])
-            self.amplitudes_bitstrings(A, B, x, n_paths=p1 - p0, out=amp, accumulate=p0 > 0)
-        return float((amp.abs() ** 2).sum().item())
+        return float(self.loss_device(x, chunk).item())
 
 
 def _with_params(circuit, theta):
@@ -347,7 +363,7 @@ class ProbabilityMass(torch.autograd.Function):
         plan = Plan(_with_params(circuit, th), dtype=dtype)
         ctx.plan, ctx.x, ctx.chunk = plan, x, chunk
         ctx.theta_device, ctx.theta_dtype = theta.device, theta.dtype
-        return torch.tensor(plan.loss(x, chunk), dtype=torch.float64, device=theta.device)
+        return plan.loss_device(x, chunk)[0].to(theta.device)
 
     @staticmethod
     def backward(ctx, gout):
@@ -355,6 +371,28 @@ class ProbabilityMass(torch.autograd.Function):
         g = ctx.plan.backward(ctx.x, ctx.chunk)
         g = (gout.to(g.device, torch.float64) * g).to(device=ctx.theta_device, dtype=ctx.theta_dtype)
         return g, None, None, None, None
+
+
+class Amplitudes(torch.autograd.Function):
+    """psi(x_j; theta) = <x_j| U(theta) |0> through joint-cut HSF, as a
+    complex128 tensor: forward from hsf_loss's amplitudes, backward passes
+    the incoming cotangents to hsf_backward, so any real loss built on the
+    amplitudes differentiates through the library."""
+
+    @staticmethod
+    def forward(ctx, theta, circuit, x, dtype="c64", chunk=None):
+        th = theta.detach().double().cpu().numpy()
+        plan = Plan(_with_params(circuit, th), dtype=dtype)
+        ctx.plan, ctx.x, ctx.chunk = plan, x, chunk
+        ctx.theta_device, ctx.theta_dtype = theta.device, theta.dtype
+        amps = torch.empty(x.numel(), dtype=torch.complex128, device=x.device)
+        plan.loss_device(x, chunk, amps)
+        return amps
+
+    @staticmethod
+    def backward(ctx, gout):
+        g = ctx.plan.backward(ctx.x, ctx.chunk, dl_dpsi=gout.to(ctx.x.device, torch.complex128).contiguous())
+        return g.to(device=ctx.theta_device, dtype=ctx.theta_dtype), None, None, None, None
 
 
 class Batch:

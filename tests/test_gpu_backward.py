@@ -146,3 +146,93 @@ def test_autograd_function_on_device_angles():
     ref = OG.loss_grad_shift(c, xs)
     r = 3.0 * np.array([ref[t] for t in range(len(theta))])
     assert np.max(np.abs(theta.grad.cpu().numpy() - r)) < 1e-9 * np.max(np.abs(r))
+
+
+def _amps_oracle(c, xs):
+    from oracle import sv
+    return sv.run(c)[np.asarray(xs, dtype=np.int64)]
+
+
+def _fd_linear(c, xs, gco, h=1e-5):
+    """Central differences (FP64 Schroedinger oracle) of the real functional
+    L_g(t) = sum_j Re(conj(g_j) psi_j(t)), every occurrence of a parameter id
+    shifted together: its gradient is sum_j Re(conj(g_j) dpsi_j/dt)."""
+    occ = OG.occurrences(c)
+    out = np.zeros(max(occ) + 1)
+    for t, ids in occ.items():
+        lp = np.sum(np.real(np.conj(gco) * _amps_oracle(OG._with_param(c, ids, h), xs)))
+        lm = np.sum(np.real(np.conj(gco) * _amps_oracle(OG._with_param(c, ids, -h), xs)))
+        out[t] = (lp - lm) / (2 * h)
+    return out
+
+
+def test_loss_entry_point_matches_oracle():
+    """hsf_loss: psi(x_j) and L = sum_j |psi(x_j)|^2 summed inside the
+    library over path chunks, against the Schroedinger oracle; any chunking
+    gives the same amplitudes to rounding; no bitstrings give L = 0."""
+    c = cg.c3(seed=7, n=10, layers=6)
+    xs = cg.c3_bitstrings(n=10, count=64, seed=13)
+    plan = Plan(c, dtype="c128")
+    x = torch.from_numpy(np.asarray(xs, dtype=np.int64)).cuda()
+    ref = _amps_oracle(c, xs)
+    amps = torch.empty(len(xs), dtype=torch.complex128, device="cuda")
+    L = plan.loss_device(x, chunk=plan.P, amps=amps).item()
+    assert np.max(np.abs(amps.cpu().numpy() - ref)) < 1e-12
+    assert abs(L - np.sum(np.abs(ref) ** 2)) < 1e-12
+    amps5 = torch.empty_like(amps)
+    L5 = plan.loss_device(x, chunk=5, amps=amps5).item()
+    assert np.max(np.abs(amps5.cpu().numpy() - ref)) < 1e-12 and abs(L5 - L) < 1e-13
+    empty = torch.empty(0, dtype=torch.int64, device="cuda")
+    assert plan.loss_device(empty).item() == 0.0
+    p64 = Plan(c)
+    assert abs(p64.loss(x) - L) < 1e-6 * L
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_caller_cotangent_gradient(dtype):
+    """hsf_backward with caller cotangents g_j: sum_j Re(conj(g_j) dpsi_j/dt)
+    for every angle (inside the 3|3 block hulls as well) against central
+    differences of the oracle's amplitudes; g = 2 psi gives the probability
+    mass gradient."""
+    c = cg.c3(seed=8, n=10, layers=6)
+    xs = cg.c3_bitstrings(n=10, count=40, seed=14)
+    rng = np.random.default_rng(15)
+    gco = rng.standard_normal(len(xs)) + 1j * rng.standard_normal(len(xs))
+    plan = Plan(c, dtype=dtype)
+    x = torch.from_numpy(np.asarray(xs, dtype=np.int64)).cuda()
+    g = plan.backward(x, dl_dpsi=torch.from_numpy(gco).cuda()).cpu().numpy()
+    ref = _fd_linear(c, xs, gco)
+    tol = 1e-6 if dtype == "c128" else 1e-4
+    assert np.max(np.abs(g - ref)) < tol * np.max(np.abs(ref))
+    amps = torch.empty(len(xs), dtype=torch.complex128, device="cuda")
+    plan.loss_device(x, amps=amps)
+    g2 = plan.backward(x, dl_dpsi=2 * amps).cpu().numpy()
+    g0 = plan.backward(x).cpu().numpy()
+    assert np.max(np.abs(g2 - g0)) <= 1e-12 * np.max(np.abs(g0))
+
+
+def test_amplitudes_autograd_nonlinear_loss():
+    """Amplitudes (torch.autograd.Function over hsf_loss / hsf_backward with
+    cotangents): L = sum_j |psi_j|^4 + Re(psi_0 psi_1), gradient against
+    central differences of the same L on the oracle's amplitudes."""
+    from paper_2502_06959_amd import Amplitudes
+    c = cg.c3(seed=9, n=8, layers=4)
+    xs = cg.c3_bitstrings(n=8, count=24, seed=16)
+    x = torch.from_numpy(np.asarray(xs, dtype=np.int64)).cuda()
+    theta = torch.tensor([g["param"] for g in c["gates"] if g["param_id"] >= 0], dtype=torch.float64,
+                         device="cuda", requires_grad=True)
+    psi = Amplitudes.apply(theta, c, x, "c128")
+    L = (psi.abs() ** 4).sum() + (psi[0] * psi[1]).real
+    L.backward()
+
+    def Lo(cc):
+        a = _amps_oracle(cc, xs)
+        return np.sum(np.abs(a) ** 4) + np.real(a[0] * a[1])
+
+    assert abs(L.item() - Lo(c)) < 1e-12
+    h = 1e-5
+    ref = np.array([(Lo(OG._with_param(c, ids, h)) - Lo(OG._with_param(c, ids, -h))) / (2 * h)
+                    for t, ids in sorted(OG.occurrences(c).items())])
+    got = theta.grad.cpu().numpy()
+    assert theta.grad.device.type == "cuda"
+    assert np.max(np.abs(got - ref)) < 1e-6 * np.max(np.abs(ref))
