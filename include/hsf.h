@@ -295,6 +295,25 @@ hsf_status hsf_amplitudes_bitstrings(hsf_plan_t plan, const void* psiA, int64_t 
                                      const uint64_t* x, int64_t n_x, void* out,
                                      int32_t accumulate, hsf_stream_t stream);
 
+/* hsf_amplitudes_full without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and errors as
+ * hsf_amplitudes_full, except: the scratch of HSF_SUM_BF16X3 (the split-BF16
+ * planes) lives in a static device array of HSF_NOALLOC_SCRATCH_BYTES bytes
+ * that the library holds on every device it runs on until the process ends;
+ * a call whose planes, hsf_workspace_size(plan, 1, n_paths, HSF_SUM_BF16X3),
+ * would exceed it fails with HSF_E_ARG before any launch (sum fewer paths per
+ * call with accumulate = 1).  HSF_SUM_BF16X3_SPLIT is rejected (its planes
+ * are the caller's).  The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine.  All calls on one device share its array, so
+ * calls that overlap on one device (other streams, other threads) race; a
+ * call leaves the array holding its own planes.                              */
+#define HSF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+hsf_status hsf_amplitudes_full_noalloc(hsf_plan_t plan, const void* psiA, int64_t ldA,
+                                       const void* psiB, int64_t ldB, int64_t n_paths,
+                                       int64_t row_begin, int64_t row_end, void* out, int64_t ldo,
+                                       int32_t mode, int32_t accumulate, hsf_stream_t stream);
+
 /* ------------------------------------------------------------- checks ---- */
 
 /* FP64-accumulated sums over n complex entries of type dtype: out[0] =

@@ -67,6 +67,8 @@ SIGNATURES = {
                                 c_size_t, c_void_p]),
     "hsf_amplitudes_full": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64, c_int64,
                                       c_void_p, c_int64, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
+    "hsf_amplitudes_full_noalloc": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64,
+                                              c_int64, c_void_p, c_int64, c_int32, c_int32, c_void_p]),
     "hsf_split_operands": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_size_t,
                                      c_void_p]),
     "hsf_amplitudes_bitstrings": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p,

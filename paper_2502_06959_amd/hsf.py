@@ -131,6 +131,16 @@ def hsf_amplitudes_full(plan, psiA, psiB, n_paths, row_begin, row_end, out, mode
                                         _stream(psiA)))
 
 
+def hsf_amplitudes_full_noalloc(plan, psiA, psiB, n_paths, row_begin, row_end, out, mode="bf16x3",
+                                accumulate=False):
+    """hsf_amplitudes_full with its scratch in the library's static device
+    array (no workspace, no allocation)."""
+    L.check(L.lib().hsf_amplitudes_full_noalloc(ctypes.c_void_p(plan), _ptr(psiA), psiA.stride(0), _ptr(psiB),
+                                                psiB.stride(0), n_paths, row_begin, row_end, _ptr(out),
+                                                out.stride(0), L.SUM_MODE[mode], 1 if accumulate else 0,
+                                                _stream(psiA)))
+
+
 def hsf_split_operands(plan, psiA, psiB, n_paths, ws):
     """Split-BF16 planes of both operands (all rows) into ws, for later
     HSF_SUM_BF16X3_SPLIT path sums ("bf16x3_split") over row ranges."""
