@@ -234,8 +234,9 @@ hsf_status build_tables(Batch& b, void* const* outs, int mode) {
             t += g.tiles_n * ((M + kBf16StreamRows - 1) / kBf16StreamRows);
             stream_full = stream_full && bf16x3_stream_full(M, N, g.K, g.ldo, 0);
         } else {
+            const int64_t tile_rows = mode == HSF_SUM_BF16X3 ? kBf16LdsTileRows : 128;
             g.tiles_n = (N + 127) / 128;
-            t += g.tiles_n * ((M + 127) / 128);
+            t += g.tiles_n * ((M + tile_rows - 1) / tile_rows);
         }
         (deep ? gl : gm).push_back(g);
     }

@@ -60,6 +60,9 @@ size_t bf16x3_workspace(int na, int nb, int64_t n_paths);
 // Path sums staged through LDS for K >= kLdsMinPaths (pathsum_lds.hip); their
 // split-BF16 planes are chunked by kBf16Chunk paths (a multiple of 16).
 constexpr int kBf16Chunk = 16;
+// Output tiles of the LDS-staged split-BF16 path sum: kBf16LdsTileRows A rows
+// x 128 B rows (batches count their tiles in this shape).
+constexpr int64_t kBf16LdsTileRows = 256;
 constexpr int64_t kLdsMinPaths = 64;
 bool path_sum_lds_fits(int mode, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K, int64_t M,
                        int64_t N);

@@ -174,19 +174,65 @@ __global__ __launch_bounds__(256, 2) void pathsum_f32_lds_batch(const GemmDesc* 
 }
 
 // ------------------------------------------------------- split-BF16 x3 ----
-// Chunked planes: for path chunk c (B_KC paths) and row r, B_RB contiguous
-// bytes [re hi | re lo | im hi | im lo] x B_KC paths, so one tile's rows of
-// one chunk are one contiguous run of 128 x B_RB bytes.  With 16-path chunks
-// the double-buffered stages take 72 KiB of LDS: two workgroups per CU, so
-// one's barrier and LDS waits are covered by the other's MFMAs.
-constexpr int B_KC = kBf16Chunk;                 // paths per chunk (a multiple of 16)
-constexpr int B_RB = 8 * B_KC;                    // bytes of one row of one chunk (4 planes x B_KC x 2 B)
-constexpr int B_TPR = B_RB / 16;                  // threads per row when staging (16 bytes each)
-constexpr int B_RPI = 256 / B_TPR;                // rows per staging instruction
-constexpr int B_NF = 128 / B_RPI;                 // staging loads per operand per chunk
-constexpr int B_ROW = B_RB + 16;                  // staged row bytes (16-byte pad: conflict-free b128 reads)
-constexpr int B_STAGE = 2 * 128 * B_ROW;          // bytes of A and B rows per stage
-constexpr size_t B_LDS = 2 * (size_t)B_STAGE;
+// Chunked planes: for path chunk c (B_KC paths) and row r, B_RB = 128
+// contiguous bytes [re hi | re lo | im hi | im lo] x 16 paths, so one tile's
+// rows of one chunk are one contiguous run.
+//
+// Sum kernel: output tiles of 256 A rows x 128 B rows, 8 waves in 4 x 2
+// (each 64 x 64 outputs as 2 x 2 blocks of 32 x 32), one workgroup per CU.
+// Chunks are copied global -> LDS by the DMA form of the vector load
+// (global_load_lds_dwordx4: each lane's 16 bytes land at M0 + 16 lane), so no
+// registers stage them, into three LDS stages of 48 KiB: while chunk c feeds
+// the MFMAs, chunks c + 1 and c + 2 are in flight.  Each wave copies six 1 KiB
+// pieces of a chunk; a barrier per chunk makes every piece visible.  LDS rows
+// of 128 bytes hold eight 16-byte units XOR-swizzled by the row
+// (unit u of row r at u ^ swz(r)): the lane order of a DMA fixes where each
+// unit lands, so the swizzle is applied to the global addresses, and the
+// 16-byte operand reads of 32 consecutive rows are then conflict-free.
+constexpr int B_KC = kBf16Chunk;                 // paths per chunk
+constexpr int B_RB = 8 * B_KC;                    // bytes of one row of one chunk
+constexpr int B_TM = kBf16LdsTileRows, B_TN = 128, B_WAVES = 8;
+constexpr int B_STAGE = (B_TM + B_TN) * B_RB;     // 48 KiB
+constexpr int B_NST = 3;
+constexpr size_t B_LDS = (size_t)B_NST * B_STAGE; // 144 KiB
+constexpr int B_DMA = B_STAGE / 1024 / B_WAVES;   // 1 KiB DMA pieces per wave per chunk
+constexpr int B_A_DMA = B_TM * B_RB / 1024;       // pieces of a chunk that hold A rows
+static_assert(B_KC == 16 && B_RB == 128, "eight 16-byte units per staged row");
+static_assert(B_DMA == 6, "the barrier's vmcnt below counts six DMA pieces per chunk");
+static_assert(B_TM == 64 * (B_WAVES / 2), "waves in TM / 64 x 2");
+
+__device__ __forceinline__ int b_swz(int r) { return ((r >> 1) ^ (r << 2)) & 7; }
+
+// 16 bytes per lane from base + off into LDS at lds + 16 lane.  M0 is set
+// for the copy and restored; it is read when the load issues.
+__device__ __forceinline__ void lds_dma16(uint32_t lds, const void* base, uint32_t off) {
+    uint32_t saved;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %1\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %2, %3\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "s"(lds), "v"(off), "s"(base)
+        : "memory");
+}
+// Every wave's copies of a chunk are in LDS and every wave's reads of the
+// stage about to be refilled are done: this wave's own copies of all but the
+// newest chunk (B_DMA pieces) and its LDS reads, then the barrier.  No
+// release fence: it would wait for the copies still in flight.
+__device__ __forceinline__ void dma_barrier_keep_one() {
+    asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+__device__ __forceinline__ void dma_barrier_all() {
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+__device__ __forceinline__ const void* uniform_ptr(const void* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const void*)(((uint64_t)hi << 32) | lo);
+}
 
 // Thread: row r, eight consecutive paths 8y .. 8y+7 (zero at or beyond K).
 __global__ __launch_bounds__(256) void split_chunked(const float2* __restrict__ X, int64_t ldx, int64_t K,
@@ -213,143 +259,145 @@ __global__ __launch_bounds__(256) void split_chunked(const float2* __restrict__ 
     *reinterpret_cast<u16x8*>(row + 3 * B_KC) = il;
 }
 
-// Rows row0 + t / B_TPR + B_RPI i (i < B_NF) of path chunk c, bytes
-// 16 (t % B_TPR) .. +15, of planes whose chunks hold R rows each; rows at or
-// beyond lim read as zero (lim <= R).
-__device__ __forceinline__ void fetch_rows(const unsigned short* __restrict__ P, int64_t R, int64_t lim, int64_t row0,
-                                           int64_t c, int srow, int scol, uint4 (&r)[B_NF]) {
-    const uint4* g = reinterpret_cast<const uint4*>(P + (c * R + row0) * (4 * B_KC));
+// This wave's six pieces of chunk c of the tile at (m0, n0) into stage s:
+// piece g = 6 w + j holds staged rows 8 g .. 8 g + 7 (A rows first, then B
+// rows); rows at or beyond M (N) repeat the last row, whose products land
+// only in outputs that are not stored.
+__device__ __forceinline__ void bf16x3_issue(const unsigned char* PA, int64_t RA, int64_t M, int64_t m0,
+                                             const unsigned char* PB, int64_t N, int64_t n0, int64_t c, int s,
+                                             uint32_t lds0, int w, int lane) {
+    const unsigned char* ba = (const unsigned char*)uniform_ptr(PA + c * RA * B_RB);
+    const unsigned char* bb = (const unsigned char*)uniform_ptr(PB + c * N * B_RB);
 #pragma unroll
-    for (int i = 0; i < B_NF; ++i) {
-        const int row = srow + B_RPI * i;
-        const bool ok = row0 + row < lim;
-        const uint4 v = g[(ok ? row : lim - 1 - row0) * B_TPR + scol];
-        r[i] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+    for (int j = 0; j < B_DMA; ++j) {
+        const int g = w * B_DMA + j;
+        const int rowl = g * 8 + (lane >> 3);
+        const int unit = (lane & 7) ^ b_swz(rowl);
+        const uint32_t dst = __builtin_amdgcn_readfirstlane(lds0 + (uint32_t)(s * B_STAGE + g * 1024));
+        if (g < B_A_DMA) {
+            const int64_t r = m0 + rowl < M ? m0 + rowl : M - 1;
+            lds_dma16(dst, ba, (uint32_t)(r * B_RB + unit * 16));
+        } else {
+            const int64_t r = n0 + (rowl - B_TM) < N ? n0 + (rowl - B_TM) : N - 1;
+            lds_dma16(dst, bb, (uint32_t)(r * B_RB + unit * 16));
+        }
     }
 }
 
-__device__ __forceinline__ void stash_rows(unsigned char* stage, int srow, int scol, const uint4 (&ra)[B_NF],
-                                           const uint4 (&rb)[B_NF]) {
+// The six split terms of one 16-path chunk, terms [T0, T1), on the 2 x 2
+// blocks of a wave; consecutive MFMAs write different accumulators and each
+// accumulator sees its terms in the fixed order listed.
+template <int T0, int T1>
+__device__ __forceinline__ void bf16x3_terms(const u16x8 (&x)[2][4], const u16x8 (&y)[2][4], f32x16 (&cr)[2][2],
+                                             f32x16 (&ci)[2][2]) {
+    bf16x8 xs[2][6], ys[2][6];
 #pragma unroll
-    for (int i = 0; i < B_NF; ++i) {
-        const int off = (srow + B_RPI * i) * B_ROW + scol * 16;
-        *reinterpret_cast<uint4*>(stage + off) = ra[i];
-        *reinterpret_cast<uint4*>(stage + 128 * B_ROW + off) = rb[i];
+    for (int a = 0; a < 2; ++a) {
+        const bf16x8 xrh = as_bf(x[a][0]), xrl = as_bf(x[a][1]), xih = as_bf(x[a][2]), xil = as_bf(x[a][3]);
+        const bf16x8 nih = as_bf(x[a][2] ^ (u16x8)0x8000), nil = as_bf(x[a][3] ^ (u16x8)0x8000);
+        // real part: xrh yrh, xrh yrl, xrl yrh, -xih yih, -xih yil, -xil yih
+        xs[a][0] = xrh; xs[a][1] = xrh; xs[a][2] = xrl; xs[a][3] = nih; xs[a][4] = nih; xs[a][5] = nil;
+        // imaginary part: xrh yih, xrh yil, xrl yih, xih yrh, xih yrl, xil yrh
+        ys[a][0] = xrh; ys[a][1] = xrh; ys[a][2] = xrl; ys[a][3] = xih; ys[a][4] = xih; ys[a][5] = xil;
     }
-}
-
-// One 128 x 128 output tile at (m0, n0) from chunked planes (A's chunks of
-// RA >= M rows, PA at the product's first row); ends with a barrier.
-__device__ __forceinline__ void bf16x3_lds_tile(const unsigned short* __restrict__ PA, int64_t M, int64_t RA,
-                                                const unsigned short* __restrict__ PB, int64_t N, int64_t chunks,
-                                                float2* __restrict__ out, int64_t ldo, int accumulate, int64_t m0,
-                                                int64_t n0, unsigned char* bl) {
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int li = lane & 31, lk = lane >> 5, wm = w >> 1, wn = w & 1;
-    {
-        // staging: B_TPR threads move one row of a chunk; thread t takes rows
-        // t / B_TPR + B_RPI i, i < B_NF, bytes 16 (t % B_TPR) .. +15, of both operands
-        uint4 ra[B_NF], rb[B_NF];
-        const int srow = t / B_TPR, scol = t % B_TPR;
-        f32x16 cr[2][2], ci[2][2];
+    bf16x8 yr[2][6], yi[2][6];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const bf16x8 yrh = as_bf(y[b][0]), yrl = as_bf(y[b][1]), yih = as_bf(y[b][2]), yil = as_bf(y[b][3]);
+        yr[b][0] = yrh; yr[b][1] = yrl; yr[b][2] = yrh; yr[b][3] = yih; yr[b][4] = yil; yr[b][5] = yih;
+        yi[b][0] = yih; yi[b][1] = yil; yi[b][2] = yih; yi[b][3] = yrh; yi[b][4] = yrl; yi[b][5] = yrh;
+    }
+#pragma unroll
+    for (int term = T0; term < T1; ++term)
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                cr[a][b] = (f32x16)0.0f;
-                ci[a][b] = (f32x16)0.0f;
+                cr[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xs[a][term], yr[b][term], cr[a][b], 0, 0, 0);
+                ci[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ys[a][term], yi[b][term], ci[a][b], 0, 0, 0);
             }
-        fetch_rows(PA, RA, M, m0, 0, srow, scol, ra);
-        fetch_rows(PB, N, N, n0, 0, srow, scol, rb);
-        stash_rows(bl, srow, scol, ra, rb);
-        __syncthreads();
-        for (int64_t c = 0; c < chunks; ++c) {
-            const int buf = (int)(c & 1);
-            if (c + 1 < chunks) {
-                fetch_rows(PA, RA, M, m0, c + 1, srow, scol, ra);
-                fetch_rows(PB, N, N, n0, c + 1, srow, scol, rb);
-            }
-            const unsigned char* sa = bl + buf * B_STAGE;
-            const unsigned char* sb = sa + 128 * B_ROW;
-#pragma unroll
-            for (int s = 0; s < B_KC / 16; ++s) {
-                // plane p of row r, paths 16 s + 8 lk .. +7: byte r * B_ROW + 2 B_KC p + 32 s + 16 lk
-                u16x8 x[2][4], y[2][4];
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const unsigned char* pa = sa + (wm * 64 + a * 32 + li) * B_ROW + 32 * s + 16 * lk;
-                    const unsigned char* pb = sb + (wn * 64 + a * 32 + li) * B_ROW + 32 * s + 16 * lk;
-#pragma unroll
-                    for (int p = 0; p < 4; ++p) {
-                        x[a][p] = *reinterpret_cast<const u16x8*>(pa + 2 * B_KC * p);
-                        y[a][p] = *reinterpret_cast<const u16x8*>(pb + 2 * B_KC * p);
-                    }
-                }
-                // term-major order over the 2 x 2 blocks: consecutive MFMAs
-                // write different accumulators; each accumulator sees its
-                // six terms in the fixed order listed below
-                bf16x8 xs[2][6], ys[2][6];
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const bf16x8 xrh = as_bf(x[a][0]), xrl = as_bf(x[a][1]), xih = as_bf(x[a][2]),
-                                 xil = as_bf(x[a][3]);
-                    const bf16x8 nih = as_bf(x[a][2] ^ (u16x8)0x8000), nil = as_bf(x[a][3] ^ (u16x8)0x8000);
-                    // real part: xrh yrh, xrh yrl, xrl yrh, -xih yih, -xih yil, -xil yih
-                    xs[a][0] = xrh; xs[a][1] = xrh; xs[a][2] = xrl; xs[a][3] = nih; xs[a][4] = nih; xs[a][5] = nil;
-                    // imaginary part: xrh yih, xrh yil, xrl yih, xih yrh, xih yrl, xil yrh
-                    ys[a][0] = xrh; ys[a][1] = xrh; ys[a][2] = xrl; ys[a][3] = xih; ys[a][4] = xih; ys[a][5] = xil;
-                }
-                bf16x8 yr[2][6], yi[2][6];
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const bf16x8 yrh = as_bf(y[b][0]), yrl = as_bf(y[b][1]), yih = as_bf(y[b][2]),
-                                 yil = as_bf(y[b][3]);
-                    yr[b][0] = yrh; yr[b][1] = yrl; yr[b][2] = yrh; yr[b][3] = yih; yr[b][4] = yil; yr[b][5] = yih;
-                    yi[b][0] = yih; yi[b][1] = yil; yi[b][2] = yih; yi[b][3] = yrh; yi[b][4] = yrl; yi[b][5] = yrh;
-                }
-#pragma unroll
-                for (int term = 0; term < 6; ++term)
-#pragma unroll
-                    for (int a = 0; a < 2; ++a)
-#pragma unroll
-                        for (int b = 0; b < 2; ++b) {
-                            cr[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xs[a][term], yr[b][term], cr[a][b], 0, 0, 0);
-                            ci[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ys[a][term], yi[b][term], ci[a][b], 0, 0, 0);
-                        }
-            }
-            if (c + 1 < chunks) stash_rows(bl + (buf ^ 1) * B_STAGE, srow, scol, ra, rb);
-            __syncthreads();
-        }
-        store_tile_128(cr, ci, m0, n0, M, N, out, ldo, accumulate);
-    }
 }
 
-__global__ __launch_bounds__(256, 2) void pathsum_bf16x3_lds(const unsigned short* __restrict__ PA, int64_t M,
-                                                          int64_t RA, const unsigned short* __restrict__ PB, int64_t N,
-                                                          int64_t chunks, float2* __restrict__ out, int64_t ldo,
-                                                          int accumulate, int64_t tiles_m, int64_t tiles_n,
-                                                          int xcd_bands) {
+// One 256 x 128 output tile at (m0, n0) from chunked planes (A's chunks of
+// RA >= M rows, PA at the product's first row).  Starts with a barrier after
+// every earlier store and LDS read of the workgroup, so tiles follow each
+// other directly.
+__device__ __forceinline__ void bf16x3_lds_tile(const unsigned char* PA, int64_t M, int64_t RA,
+                                                const unsigned char* PB, int64_t N, int64_t chunks,
+                                                float2* __restrict__ out, int64_t ldo, int accumulate, int64_t m0,
+                                                int64_t n0, unsigned char* bl) {
+    const uint32_t lds0 = (uint32_t)(uintptr_t)((__attribute__((address_space(3))) unsigned char*)bl);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int li = lane & 31, lk = lane >> 5, wm = w >> 1, wn = w & 1;
+    dma_barrier_all();
+    bf16x3_issue(PA, RA, M, m0, PB, N, n0, 0, 0, lds0, w, lane);
+    if (chunks > 1) bf16x3_issue(PA, RA, M, m0, PB, N, n0, 1, 1, lds0, w, lane);
+    f32x16 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cr[a][b] = (f32x16)0.0f;
+            ci[a][b] = (f32x16)0.0f;
+        }
+    int s = 0;
+    for (int64_t c = 0; c < chunks; ++c) {
+        // chunk c is in the LDS (only chunk c + 1 may still be in flight)
+        if (c + 1 < chunks) dma_barrier_keep_one();
+        else dma_barrier_all();
+        const unsigned char* st = bl + s * B_STAGE;
+        // plane p of staged row r, paths 8 lk .. 8 lk + 7: unit 2 p + lk
+        u16x8 x[2][4], y[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int ra = wm * 64 + a * 32 + li;
+            const int rb = B_TM + wn * 64 + a * 32 + li;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                x[a][p] = *reinterpret_cast<const u16x8*>(st + ra * B_RB + (((2 * p + lk) ^ b_swz(ra)) << 4));
+                y[a][p] = *reinterpret_cast<const u16x8*>(st + rb * B_RB + (((2 * p + lk) ^ b_swz(rb)) << 4));
+            }
+        }
+        // the copy of chunk c + 2 goes out after the first two terms: right
+        // after the barrier the MFMAs start first (measured: 1.05x over
+        // issuing the copy before the reads)
+        bf16x3_terms<0, 2>(x, y, cr, ci);
+        if (c + 2 < chunks)
+            bf16x3_issue(PA, RA, M, m0, PB, N, n0, c + 2, s == 0 ? B_NST - 1 : s - 1, lds0, w, lane);
+        bf16x3_terms<2, 6>(x, y, cr, ci);
+        s = s == B_NST - 1 ? 0 : s + 1;
+    }
+    store_tile_128(cr, ci, m0, n0, M, N, out, ldo, accumulate);
+}
+
+__global__ __launch_bounds__(64 * B_WAVES, 1) void pathsum_bf16x3_lds(const unsigned short* __restrict__ PA, int64_t M,
+                                                                    int64_t RA, const unsigned short* __restrict__ PB,
+                                                                    int64_t N, int64_t chunks,
+                                                                    float2* __restrict__ out, int64_t ldo,
+                                                                    int accumulate, int64_t tiles_m, int64_t tiles_n,
+                                                                    int xcd_bands) {
     extern __shared__ __align__(16) unsigned char bl[];
     const int64_t tiles = tiles_m * tiles_n;
     for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
         int64_t tm, tn;
         tile_coords(item, tiles_m, tiles_n, xcd_bands != 0, tm, tn);
-        bf16x3_lds_tile(PA, M, RA, PB, N, chunks, out, ldo, accumulate, tm * 128, tn * 128, bl);
+        bf16x3_lds_tile((const unsigned char*)PA, M, RA, (const unsigned char*)PB, N, chunks, out, ldo, accumulate,
+                        tm * B_TM, tn * B_TN, bl);
     }
 }
 
-// Batched: descriptors hold chunked planes (a_off, b_off) and the padded path
-// count K (a multiple of 32).
-__global__ __launch_bounds__(256, 2) void pathsum_bf16x3_lds_batch(const GemmDesc* __restrict__ d, int n,
-                                                                unsigned char* base, int64_t tiles) {
+// Batched: descriptors hold chunked planes (a_off, b_off), the padded path
+// count K (a multiple of 32) and tiles of B_TM x B_TN.
+__global__ __launch_bounds__(64 * B_WAVES, 1) void pathsum_bf16x3_lds_batch(const GemmDesc* __restrict__ d, int n,
+                                                                          unsigned char* base, int64_t tiles) {
     extern __shared__ __align__(16) unsigned char bl[];
     for (int64_t item = blockIdx.x; item < tiles; item += gridDim.x) {
         const GemmDesc& g = find_desc(d, n, item);
         int64_t tm, tn;
-        tile_coords(item - g.tile_start, (g.M + 127) / 128, g.tiles_n, false, tm, tn);
-        bf16x3_lds_tile(reinterpret_cast<const unsigned short*>(base + g.a_off), g.M, g.M,
-                        reinterpret_cast<const unsigned short*>(base + g.b_off), g.N, g.K / B_KC, (float2*)g.out,
-                        g.ldo, 0, tm * 128, tn * 128, bl);
+        tile_coords(item - g.tile_start, (g.M + B_TM - 1) / B_TM, g.tiles_n, false, tm, tn);
+        bf16x3_lds_tile(base + g.a_off, g.M, g.M, base + g.b_off, g.N, g.K / B_KC, (float2*)g.out, g.ldo, 0,
+                        tm * B_TM, tn * B_TN, bl);
     }
 }
 
@@ -510,11 +558,13 @@ hsf_status set_lds_attrs() {
                      "hipFuncSetAttribute");
 }
 
-void grid_shape(const void* kernel, size_t shmem, int64_t M, int64_t N, int64_t& tiles_m, int64_t& tiles_n,
-                int& grid, int& bands) {
-    tiles_m = (M + 127) / 128;
+// Persistent grid over tiles of tile_rows x 128 outputs; XCD bands when the
+// tile rows and the grid split evenly over the eight XCDs.
+void grid_shape(const void* kernel, int threads, size_t shmem, int64_t tile_rows, int64_t M, int64_t N,
+                int64_t& tiles_m, int64_t& tiles_n, int& grid, int& bands) {
+    tiles_m = (M + tile_rows - 1) / tile_rows;
     tiles_n = (N + 127) / 128;
-    grid = persistent_grid(kernel, 256, shmem, tiles_m * tiles_n);
+    grid = persistent_grid(kernel, threads, shmem, tiles_m * tiles_n);
     bands = (tiles_m % 8 == 0 && grid % 8 == 0) ? 1 : 0;
 }
 
@@ -535,7 +585,7 @@ hsf_status path_sum_f32_lds(const float2* A, int64_t ldA, const float2* B, int64
     if (s != HSF_OK) return s;
     int64_t tm, tn;
     int grid, bands;
-    grid_shape((const void*)pathsum_f32_lds, F_LDS, M, N, tm, tn, grid, bands);
+    grid_shape((const void*)pathsum_f32_lds, 256, F_LDS, 128, M, N, tm, tn, grid, bands);
     hipLaunchKernelGGL(pathsum_f32_lds, dim3(grid), dim3(256), F_LDS, st, A, ldA, B, ldB, K, M, N, out, ldo,
                        accumulate, tm, tn, bands);
     return hip_check(hipGetLastError(), "pathsum_f32_lds launch");
@@ -562,9 +612,9 @@ hsf_status sum_lds(const unsigned short* PA, int64_t RA, int64_t row0, int64_t M
     const int64_t chunks = (K + B_KC - 1) / B_KC;
     int64_t tm, tn;
     int grid, bands;
-    grid_shape((const void*)pathsum_bf16x3_lds, B_LDS, M, N, tm, tn, grid, bands);
-    hipLaunchKernelGGL(pathsum_bf16x3_lds, dim3(grid), dim3(256), B_LDS, st, PA + row0 * (4 * B_KC), M, RA, PB, N,
-                       chunks, out, ldo, accumulate, tm, tn, bands);
+    grid_shape((const void*)pathsum_bf16x3_lds, 64 * B_WAVES, B_LDS, B_TM, M, N, tm, tn, grid, bands);
+    hipLaunchKernelGGL(pathsum_bf16x3_lds, dim3(grid), dim3(64 * B_WAVES), B_LDS, st, PA + row0 * (4 * B_KC), M, RA,
+                       PB, N, chunks, out, ldo, accumulate, tm, tn, bands);
     return hip_check(hipGetLastError(), "pathsum_bf16x3_lds launch");
 }
 
@@ -589,9 +639,9 @@ hsf_status launch_f32_lds_batch(const void* descs, int n, int64_t tiles, unsigne
 hsf_status launch_bf16x3_lds_batch(const void* descs, int n, int64_t tiles, unsigned char* base, hipStream_t st) {
     hsf_status s = set_lds_attrs();
     if (s != HSF_OK) return s;
-    const int grid = persistent_grid((const void*)pathsum_bf16x3_lds_batch, 256, B_LDS, tiles);
-    hipLaunchKernelGGL(pathsum_bf16x3_lds_batch, dim3(grid), dim3(256), B_LDS, st, (const GemmDesc*)descs, n, base,
-                       tiles);
+    const int grid = persistent_grid((const void*)pathsum_bf16x3_lds_batch, 64 * B_WAVES, B_LDS, tiles);
+    hipLaunchKernelGGL(pathsum_bf16x3_lds_batch, dim3(grid), dim3(64 * B_WAVES), B_LDS, st, (const GemmDesc*)descs,
+                       n, base, tiles);
     return hip_check(hipGetLastError(), "pathsum_bf16x3_lds_batch launch");
 }
 
