@@ -100,7 +100,7 @@ def _traffic_from_profiles(kernel, src_hash, workload):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE +
     WRITE_SIZE, copy-kernel calibrated), from profiles/traffic.md rows
     `| kernel | workload | source hash | bytes per launch | ...` taken on the
-    current kernel source; else None."""
+    current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.md")
     if not os.path.exists(path):
         return None
@@ -112,6 +112,45 @@ def _traffic_from_profiles(kernel, src_hash, workload):
             except ValueError:
                 return None
     return None
+
+
+VALU_PEAK_TFLOPS = 78.6   # non-packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+
+
+def _sweep_work_from_profiles(workload):
+    """(HBM bytes, VALU flop) of one step's sweeps, measured with rocprofv3
+    counters (profiles/sweeps_c4_qaoa.md rows `| workload | source hash |
+    launches | ms | bytes | flop |`) on the current sweep sources; else None."""
+    path = os.path.join(ROOT, "profiles", "sweeps_c4_qaoa.md")
+    if not os.path.exists(path):
+        return None
+    src = _src_hash("sweep.hip", "plan.cpp")
+    for line in open(path):
+        parts = [p.strip() for p in line.strip().strip("|").split("|")]
+        if len(parts) >= 6 and parts[0] == workload and parts[1] == src:
+            try:
+                return float(parts[4]), float(parts[5])
+            except ValueError:
+                return None
+    return None
+
+
+def _sweep_roofline(workload, sweep_ms):
+    """Measured HBM traffic and VALU work of a step's sweeps over the live
+    sweep time, as fractions of the HBM and non-packed FP32 VALU peaks; the
+    bound named is the one the sweeps come closer to."""
+    w = _sweep_work_from_profiles(workload)
+    if w is None:
+        return None
+    nbytes, flop = w
+    gbs = nbytes / (sweep_ms * 1e-3) / 1e9
+    tfs = flop / (sweep_ms * 1e-3) / 1e12
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tfs / VALU_PEAK_TFLOPS
+    return {"kernel": "sweep_pass", "bound": "hbm" if hbm_frac >= alu_frac else "alu",
+            "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_frac, "traffic": nbytes},
+            "alu": {"achieved": tfs, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": alu_frac, "flop": flop},
+            "sweep_ms": sweep_ms,
+            "note": "bytes and flop per step from rocprofv3 counters (profiles/sweeps_c4_qaoa.md), time live"}
 
 
 def _host():
@@ -579,6 +618,7 @@ def bench_c4(args):
                          "path_sum_launch": res_m["tile_launch_ms"], "plan_host": plan_s * 1e3},
         "path_sum_tflops_fp32_equiv": flops / (res_m["path_sum_ms"]["mean"] * 1e-3) / 1e12,
         "sweep_executed_updates_per_s": executed / (sw_ms * 1e-3),
+        "sweep_roofline": _sweep_roofline("c4", sw_ms),
         "error": {"vs_oracle_samples": res_m.get("rel_l2_vs_oracle_samples"),
                   "oracle_samples": res_m.get("oracle_samples"),
                   "norm2_all_amplitudes": res_m.get("norm2_all_amplitudes"), "path_sum": sum_err},
