@@ -13,6 +13,11 @@ c3_grad.npz     C3: dL/dt for all 708 parameter ids by the full-state FP64
                 seeded ids
 c4.npz          C4 (P=4096): psi at 4096 seeded basis states
 c5.npz          C5 (64 circuits): psi at 64 seeded basis states of each circuit
+c5_rows.npz     C5: four whole output rows of each circuit (row 0, the last
+                row, two seeded), kept as the FP64 norm of each row and 8
+                seeded random complex projections sum_c w_c psi[r, c]
+                (rows from numpy PCG64 seed 5000 + circuit, weights from
+                seed 6000 + circuit)
 qaoa_q30.npz    single-layer QAOA MaxCut on a seeded SBM graph with Table II's
                 q30-1 shape (15|15 qubits, p_intra 0.8, p_inter 0.1): psi at
                 4096 seeded basis states among the first 10^6 (the oracle HSF
@@ -44,6 +49,13 @@ def sampled_psi(c, count, seed):
     amp = H.amplitudes_at(a, b, xs, pl["nb"])
     print(c["name"], "P", pl["P"], "sampled", len(xs), f"{time.time() - t:.1f}s", flush=True)
     return xs, amp
+
+
+def c5_row_weights(i, nb):
+    """The 8 x 2^nb complex projection weights of circuit i's rows (numpy
+    PCG64, seed 6000 + i; the GPU test draws the same ones)."""
+    rng = np.random.default_rng(6000 + i)
+    return rng.standard_normal((8, 1 << nb)) + 1j * rng.standard_normal((8, 1 << nb))
 
 
 def main(which):
@@ -95,6 +107,25 @@ def main(which):
             owner.append(np.full(len(xs), i, dtype=np.int32))
         np.savez(os.path.join(OUT, "c5.npz"), x=np.concatenate(xs_all), psi=np.concatenate(psi_all),
                  circuit=np.concatenate(owner))
+    if "c5rows" in which:
+        rows_all, norm_all, proj_all = [], [], []
+        for i, c in enumerate(cg.c5()):
+            t = time.time()
+            pl = H.plan(c)
+            a = H.half_states(c, pl, "A")
+            b = H.half_states(c, pl, "B")
+            na, nb = c["n"] - pl["nb"], pl["nb"]
+            rng = np.random.default_rng(5000 + i)
+            rows = np.array([0, (1 << na) - 1] + list(rng.choice(np.arange(1, (1 << na) - 1), 2, replace=False)),
+                            dtype=np.int64)
+            w = c5_row_weights(i, nb)
+            psi = H.amplitudes_rows(a, b, rows)            # 4 x 2^nb
+            rows_all.append(rows)
+            norm_all.append(np.sum(np.abs(psi) ** 2, axis=1))
+            proj_all.append(psi @ w.T)                     # 4 x 8
+            print(c["name"], "P", pl["P"], "rows", f"{time.time() - t:.1f}s", flush=True)
+        np.savez(os.path.join(OUT, "c5_rows.npz"), rows=np.array(rows_all), norm2=np.array(norm_all),
+                 proj=np.array(proj_all))
     if "qaoa" in which:
         c = cg.qaoa_sbm(100, (15, 15), 0.8, 0.1)
         t = time.time()

@@ -7,7 +7,8 @@ Amplitudes: rel-L2 <= 1e-5 over the sampled basis states (complex64 bar).
 C4 computes every one of its 2^34 amplitudes in row tiles, so the norm of
 the whole output (a property that holds at any size: the state is unit norm)
 covers the rows that no golden sample hits.  C3 gradients: max |g - g_ref|
-<= 1e-4 max |g_ref| on the 16 sampled parameter ids."""
+<= 1e-4 max |g_ref| on all 708 angles (the oracle's adjoint) and on the 16
+shift-rule samples."""
 import os
 
 import numpy as np
@@ -73,12 +74,16 @@ def test_c3_amplitudes_loss_and_gradients():
     ref = g["grad"]
     got = grad[g["grad_ids"]]
     assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref)), (got, ref)
+    # all 708 angles against the oracle's adjoint gradient
+    full = _golden("c3_grad.npz")["grad"]
+    err = np.abs(grad - full)
+    assert np.max(err) <= 1e-4 * np.max(np.abs(full)), (int(np.argmax(err)), float(np.max(err)))
 
 
 def test_c4_all_row_tiles_sampled_and_norm():
     """Every output row tile in split-BF16 x3 (the chosen form), samples
-    checked, the norm summed over all tiles; then one tile each in FP32 and
-    FP64 against the same samples."""
+    checked, the norm summed over all tiles; then FP32 and FP64 on a 64-row
+    block of every tile against the same samples."""
     g = _golden("c4.npz")
     plan = Plan(cg.c4(), dtype="c64")
     assert plan.P == 4096 and plan.na == 17 and plan.nb == 17
@@ -103,23 +108,41 @@ def test_c4_all_row_tiles_sampled_and_norm():
     assert ohsf.rel_l2(got, ref) < C64_TOL
     assert abs(total - 1.0) < 1e-5
     del tile
-    r0 = int(row_of[0] // rows) * rows
-    sel = np.nonzero((row_of >= r0) & (row_of < r0 + rows))[0]
-    assert len(sel) > 100
-    idx = torch.from_numpy((row_of[sel] - r0) * (1 << plan.nb) + col_of[sel]).cuda()
+    # FP32 and FP64 path sums on every row tile: in each tile the 64-row
+    # block holding the most samples (the same LDS-staged kernels the full
+    # tiles run, on a ragged 64-row product)
     for mode in ("f32", "f64"):
-        out = plan.amplitudes_full(A, B, rows=(r0, r0 + rows), mode=mode)
-        sub = out.reshape(-1)[idx].cpu().numpy()
-        del out
+        got = []
+        refs = []
+        for r0 in range(0, 1 << plan.na, rows):
+            in_tile = (row_of >= r0) & (row_of < r0 + rows)
+            blocks = np.bincount((row_of[in_tile] - r0) // 64, minlength=rows // 64)
+            b0 = r0 + int(np.argmax(blocks)) * 64
+            sel = np.nonzero((row_of >= b0) & (row_of < b0 + 64))[0]
+            assert len(sel) >= 2, (mode, r0)
+            out = plan.amplitudes_full(A, B, rows=(b0, b0 + 64), mode=mode)
+            idx = torch.from_numpy((row_of[sel] - b0) * (1 << plan.nb) + col_of[sel]).cuda()
+            got.append(out.reshape(-1)[idx].cpu().numpy())
+            refs.append(ref[sel])
+            del out
         # the FP64 path sum still sums complex64 half-states, so the sweeps'
         # FP32 rounding (about 1e-6 here) remains in every mode
-        assert ohsf.rel_l2(sub, ref[sel]) < C64_TOL, mode
+        assert ohsf.rel_l2(np.concatenate(got), np.concatenate(refs)) < C64_TOL, mode
+
+
+def _c5_row_weights(i, nb):
+    # the projection weights tests/golden/make_golden.py drew for circuit i
+    rng = np.random.default_rng(6000 + i)
+    return rng.standard_normal((8, 1 << nb)) + 1j * rng.standard_normal((8, 1 << nb))
 
 
 def test_c5_whole_batch_tuned_and_replayed():
     """All 64 circuits in one tuned batch replayed from a HIP graph (73.7 GiB
-    of output): 64 oracle samples and the norm of every circuit's state."""
+    of output): 64 oracle samples and the norm of every circuit's state, and
+    four whole output rows of every circuit (row 0, the last row, two seeded)
+    through their norms and 8 random projections against the oracle's."""
     g = _golden("c5.npz")
+    gr = _golden("c5_rows.npz")
     plans = [Plan(c) for c in cg.c5()]
     b = Batch(plans)
     outs = b.alloc_outputs()
@@ -134,4 +157,10 @@ def test_c5_whole_batch_tuned_and_replayed():
         assert ohsf.rel_l2(got, g["psi"][sel]) < C64_TOL, i
         nrm = float(hsf_norm2(o.reshape(-1)).cpu().numpy()[0])
         assert abs(nrm - 1.0) < 1e-5, i
+        rows = gr["rows"][i]
+        whole = o[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.complex128)
+        n2 = np.sum(np.abs(whole) ** 2, axis=1)
+        assert np.max(np.abs(n2 - gr["norm2"][i]) / gr["norm2"][i]) < 1e-5, i
+        proj = whole @ _c5_row_weights(i, plans[i].nb).T
+        assert ohsf.rel_l2(proj, gr["proj"][i]) < C64_TOL, i
     del outs

@@ -182,15 +182,17 @@ def test_norm_and_difference():
     assert np.sqrt(s[1]) < C64_TOL
 
 
-def test_c2p_full_size_sampled_rows_and_norm():
-    """The benchmarked workload (n=28, cut 14|14, P=32): all 2^28 amplitudes
-    through the FP32 path sum; rows sampled against the oracle, the norm of
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+def test_c2p_full_size_sampled_rows_and_norm(mode):
+    """The C2' workload (n=28, cut 14|14, P=32): all 2^28 amplitudes through
+    the FP32 and the split-BF16 x3 path sums (the form the benchmark times
+    with --workload c2p); whole rows sampled against the oracle, the norm of
     the whole output checked on the device."""
     c = cg.c2p()
     plan = Plan(c, dtype="c64")
     assert plan.P == 32
     A, B = plan.run_paths()
-    out = plan.amplitudes_full(A, B, mode="f32")
+    out = plan.amplitudes_full(A, B, mode=mode)
     nrm = hsf_norm2(out.reshape(-1)).cpu().numpy()[0]
     o = ohsf.plan(c)
     oa = ohsf.half_states(c, o, "A")

@@ -69,3 +69,20 @@ def test_braket_is_matrix_element_of_embedded_gate():
     m1 = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
     want = np.vdot(l, sv.embed(n, [3], m1) @ r)
     assert abs(sv.braket(l, r, n, [3], m1) - want) < 1e-12 * abs(want)
+
+
+def test_c3_stored_gradients_agree_across_routes():
+    """The stored full-size C3 gradient (all 708 angles, the oracle's
+    two-state adjoint) against two other routes the oracle took for the same
+    loss: the parameter-shift rule on 16 sampled angles (golden c3.npz) and
+    central finite differences on 24 more (step h, truncation error O(h^2))."""
+    import os
+    gold = os.path.join(os.path.dirname(__file__), "golden")
+    z = np.load(os.path.join(gold, "c3_grad.npz"))
+    c = np.load(os.path.join(gold, "c3.npz"))
+    g = z["grad"]
+    assert g.shape == (708,) and np.all(np.isfinite(g))
+    scale = np.max(np.abs(g))
+    assert scale > 0
+    assert np.max(np.abs(g[c["grad_ids"]] - c["grad"])) < 1e-10 * scale
+    assert np.max(np.abs(g[z["fd_ids"]] - z["fd"])) < 1e-6 * scale
