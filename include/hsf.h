@@ -232,8 +232,9 @@ hsf_status hsf_sweep_form(hsf_plan_t plan, int64_t n_paths, int32_t* tree, int32
  *   planner sweeps n_paths paths level by level; else 0), 1 =
  *   hsf_amplitudes_full with path-sum mode
  *   `mode`, 2 = hsf_backward with chunks of `n_paths` paths and `mode` =
- *   number of bitstrings n_x, 3 = hsf_loss with chunks of `n_paths` paths
- *   and `mode` = n_x.                                                          */
+ *   number of bitstrings n_x (the preferred size), 3 = hsf_loss with chunks
+ *   of `n_paths` paths and `mode` = n_x, 4 = the least workspace
+ *   hsf_backward accepts (same arguments as op 2).                             */
 size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t mode);
 
 /* Per-path half-states for paths [p_begin, p_end) (Sec. II-B): row j of
@@ -352,15 +353,18 @@ hsf_status hsf_loss(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* los
  * amplitudes, d psi/d t = psi(t + pi) / 2 (every such gate is exp(-i t P/2)
  * with P^2 = 1), psi(t + pi) being one forward with the block re-factored
  * (Sec. IV-A) at the shifted angle.  grad: n_params device doubles,
- * overwritten.  Paths are processed `chunk` at a time; ws:
- * hsf_workspace_size(plan, 2, chunk, n_x) bytes.  Reductions run in a fixed
- * order (bitwise reproducible).  Synchronises `stream` (host tables are
- * staged through it), so it cannot be captured in a graph; the shifted
- * forward runs also use up to three streams of its own (default priority,
- * created and destroyed within the call, joined to `stream` before it
- * returns).  Returns HSF_E_UNSUPPORTED if a shifted block needs more Schmidt
- * terms than the plan.  n_x = 0, or a circuit without angles, gives a zero
- * gradient.                                                                  */
+ * overwritten.  Paths are processed `chunk` at a time; ws: at least
+ * hsf_workspace_size(plan, 4, chunk, n_x) bytes, best
+ * hsf_workspace_size(plan, 2, chunk, n_x): the shifted forward runs go as
+ * copies of one run in the same launches, as many per batch as the
+ * workspace holds (up to 4 GiB of copies; the result does not depend on
+ * it).  Reductions run in a fixed order (bitwise reproducible).
+ * Synchronises `stream` (host tables are staged through it), so it cannot
+ * be captured in a graph; the shifted forward runs use one stream of its own
+ * (default priority, created and destroyed within the call, joined to
+ * `stream` before it returns).  Returns HSF_E_UNSUPPORTED if a shifted block
+ * needs more Schmidt terms than the plan.  n_x = 0, or a circuit without
+ * angles, gives a zero gradient.                                            */
 hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, const void* dL_dpsi, double* grad,
                         int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes,
                         hsf_stream_t stream);

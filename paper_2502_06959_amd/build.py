@@ -19,10 +19,12 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, 
              # packed FP32 instructions stay off (see the design notes)
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-pthread", "-Wno-unused-command-line-argument"]
-# Per-file additions.  The sweep kernels branch on uniform plan-record fields
-# inside their op loops; by default LLVM structurizes uniform regions too,
-# which inserts register copies of the amplitude array at every merge.
-FILE_FLAGS = {"sweep.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
+# Per-file additions.  The sweep kernels and the adjoint's tile passes branch
+# on uniform plan-record fields inside their op loops; by default LLVM
+# structurizes uniform regions too, which inserts register copies of the
+# amplitude arrays at every merge.
+_SKIP_UNIFORM = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
+FILE_FLAGS = {"sweep.hip": _SKIP_UNIFORM, "backward.hip": _SKIP_UNIFORM}
 # complex products and quotients without the C99 inf/NaN recovery (the
 # planner's values are O(1)): inline arithmetic, 2.3x faster host SVDs
 CXX_FLAGS = ["-O3", "-fcx-limited-range", "-std=c++17", "-pthread", "-fPIC", "-I", INC, "-I", SRC, "-D__HIP_PLATFORM_AMD__",

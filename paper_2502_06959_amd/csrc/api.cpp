@@ -225,6 +225,7 @@ size_t hsf_workspace_size(hsf_plan_t plan, int32_t op, int64_t n_paths, int32_t 
     if (op == 1 && (mode == HSF_SUM_BF16X3 || mode == HSF_SUM_BF16X3_SPLIT))
         return bf16x3_workspace(p->na, p->nb, n_paths);
     if (op == 2) return backward_workspace(*p, n_paths, mode);
+    if (op == 4) return backward_workspace(*p, n_paths, mode, true);
     if (op == 3) return loss_workspace(*p, std::max<int64_t>(n_paths, 1), mode);
     return 0;
 }
@@ -313,7 +314,7 @@ hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, const v
     if (n_params < p->n_params) return fail(HSF_E_ARG, "grad has fewer slots than the circuit's parameter ids");
     if (chunk <= 0) return fail(HSF_E_ARG, "chunk must be positive");
     if (n_x < 0) return fail(HSF_E_ARG, "negative bitstring count");
-    if (ws_bytes < backward_workspace(*p, chunk, n_x)) return fail(HSF_E_ARG, "workspace too small");
+    if (ws_bytes < backward_workspace(*p, chunk, n_x, true)) return fail(HSF_E_ARG, "workspace too small");
     DeviceCopy* d = nullptr;
     hsf_status s = ensure_device(*p, &d);
     if (s != HSF_OK) return s;

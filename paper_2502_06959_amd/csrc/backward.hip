@@ -53,6 +53,38 @@ __device__ __forceinline__ V cmul(V a, V b) {
     return r;
 }
 
+// Fused multiply-adds in a fixed chain (the compiler contracts a*b - c*d + e
+// into a multiply, an FMA and an add).
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc += m x
+template <typename V>
+__device__ __forceinline__ void cfma(V& acc, V m, V x) {
+    acc.x = fmad(m.x, x.x, acc.x);
+    acc.x = fmad(-m.y, x.y, acc.x);
+    acc.y = fmad(m.x, x.y, acc.y);
+    acc.y = fmad(m.y, x.x, acc.y);
+}
+
+// m x, as two FMAs on top of two products
+template <typename V>
+__device__ __forceinline__ V cmulf(V m, V x) {
+    V r;
+    r.x = fmad(m.x, x.x, -(m.y * x.y));
+    r.y = fmad(m.x, x.y, m.y * x.x);
+    return r;
+}
+
+// (ar, ai) += l t (no conjugate)
+template <typename V, typename A>
+__device__ __forceinline__ void cdot(A& ar, A& ai, V l, V t) {
+    ar = fmad(l.x, t.x, ar);
+    ar = fmad(-l.y, t.y, ar);
+    ai = fmad(l.x, t.y, ai);
+    ai = fmad(l.y, t.x, ai);
+}
+
 __device__ __forceinline__ uint64_t ins0(uint64_t i, int b) {
     const uint64_t lo = i & ((uint64_t(1) << b) - 1);
     return ((i >> b) << (b + 1)) | lo;
@@ -250,21 +282,10 @@ __global__ __launch_bounds__(256) void bw_apply2_grad(typename Cx<T>::v* __restr
     if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(rr[0], ri[0]);
 }
 
-// A run of consecutive gates (program order reversed) on at most three
-// qubits (four need more registers than the kernel's occupancy allows),
-// undone in registers in one pass over the rows: each thread holds the
-// 2^K amplitudes of the state and of the adjoint that differ in those qubits.
-constexpr int kAdjMaxOps = 8;
+// Runs of gates on at most three qubits together, at most kAdjMaxOps of them,
+// are undone in registers inside the adjoint tile passes below.
+constexpr int kAdjMaxOps = 16;
 constexpr int kAdjMaxBits = 3;
-struct AdjRun {
-    int32_t n_ops;
-    int32_t k[kAdjMaxOps];             // 1 or 2
-    int32_t rb[kAdjMaxOps][2];         // register bits of the op's qubits (q[0] first)
-    const void* inv[kAdjMaxOps];       // M^dagger, M^T and (angle ops) D, 2^k x 2^k
-    const void* tr[kAdjMaxOps];
-    const void* dg[kAdjMaxOps];        // null: no angle
-    double2* partial[kAdjMaxOps];      // block partials of the angle's term
-};
 
 template <typename V>
 __device__ __forceinline__ void cacc(V& acc, V m, V x) {
@@ -272,45 +293,104 @@ __device__ __forceinline__ void cacc(V& acc, V m, V x) {
     acc.y += m.x * x.y + m.y * x.x;
 }
 
-// One-qubit gate on register bit RB of both register sets, with the angle's
-// term first when md is set.
-template <int K, int RB, typename V>
-__device__ __forceinline__ void adj1(V (&vs)[1 << K], V (&vl)[1 << K], const V* mi, const V* mt, const V* md,
-                                     double& ar, double& ai) {
+// ---------------------------------------------------------- adjoint tiles ----
+// The run units of one tile pass (their qubits all lie in the tile's qubit
+// set; the host's scheduler picks them) are undone in one pass over LDS tiles of 2^L amplitudes of both the state and
+// the adjoint of one path row (the tile holds the row's five lowest qubits, so
+// its loads and stores are whole 256-byte runs): each run as register groups
+// of its 2^K amplitudes, a barrier between runs.  Each angle's term is summed
+// per thread over its groups, per wave by a butterfly of lane exchanges and
+// per tile over the waves in order: one partial per (row, tile), no atomics.
+
+// Read-only tables through the constant address space (uniform scalar loads).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using ctab = const __attribute__((address_space(4))) T*;
+#else
+template <typename T>
+using ctab = const T*;
+#endif
+
+constexpr int kTileMaxAngles = 64;
+constexpr int kTileThreads = 256;
+constexpr int kTileWaves = kTileThreads / 64;
+// a pass's gate matrices (M^dagger, M^T, D) are staged in LDS; at most this
+// many bytes of them per pass (tile + partial slots + matrices fit twice per CU)
+constexpr size_t kTileMatBytes = 12 << 10;
+
+struct AdjTileOp {
+    int32_t k, rb0, rb1, ang;      // register bits of the op's qubits (q[0] first); pass-local angle or -1
+    int32_t inv, tr, dg;           // element offsets of M^dagger, M^T, D in the pass's matrix block (dg: ang >= 0)
+    int32_t diag;                  // M and D diagonal: only their diagonal entries are read
+};
+struct AdjTileUnit {
+    int32_t K, op_begin, op_end;
+    int32_t bit[3];                // tile bit of register bit K - 1 - i
+};
+struct AdjTilePass {
+    int32_t L, nc, n_nonlocal, unit_begin, unit_end, n_ang;
+    int32_t local_q[16];           // ascending; local_q[i] = i for i < nc
+    int32_t nonlocal_q[32];
+    int64_t occ_begin;             // occurrence of angle a: occ[occ_begin + a]
+    int64_t mat_begin;             // the pass's matrix block: elements [mat_begin, mat_begin + n_mat) of the table
+    int32_t n_mat, pad;
+};
+
+__device__ __forceinline__ uint32_t tswz(uint32_t e) { return e ^ ((e >> 4) & 15u); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Gate helpers of the tile passes: the state takes M^dagger, the adjoint M^T,
+// and an angle's term (l, D s) is accumulated first in A (FP32 for complex64
+// rows: each thread sums a few dozen terms, the waves and tiles then in FP64).
+// DG: M and D diagonal (RZ, RZZ, PHASE, CP), only their diagonal entries read.
+template <int K, int RB, typename V, typename A, bool DG>
+__device__ __forceinline__ void tadj1(V (&vs)[1 << K], V (&vl)[1 << K], const V* mi, const V* mt, const V* md,
+                                      A& ar, A& ai) {
 #pragma unroll
     for (int b = 0; b < (1 << K); ++b) {
         if (b & (1 << RB)) continue;
-        // matrices are re-read from LDS per pair (broadcasts) rather than held
-        asm volatile("" ::: "memory");
         const int i0 = b, i1 = b | (1 << RB);
         const V s0 = vs[i0], s1 = vs[i1], l0 = vl[i0], l1 = vl[i1];
-        if (md) {
-            V t0, t1;
-            t0.x = t0.y = t1.x = t1.y = 0;
-            cacc(t0, md[0], s0); cacc(t0, md[1], s1);
-            cacc(t1, md[2], s0); cacc(t1, md[3], s1);
-            ar += (double)l0.x * t0.x - (double)l0.y * t0.y + (double)l1.x * t1.x - (double)l1.y * t1.y;
-            ai += (double)l0.x * t0.y + (double)l0.y * t0.x + (double)l1.x * t1.y + (double)l1.y * t1.x;
+        if constexpr (DG) {
+            if (md) {
+                cdot(ar, ai, l0, cmulf(md[0], s0));
+                cdot(ar, ai, l1, cmulf(md[3], s1));
+            }
+            vs[i0] = cmulf(mi[0], s0);
+            vs[i1] = cmulf(mi[3], s1);
+            vl[i0] = cmulf(mt[0], l0);
+            vl[i1] = cmulf(mt[3], l1);
+        } else {
+            if (md) {
+                V t0 = cmulf(md[0], s0), t1 = cmulf(md[2], s0);
+                cfma(t0, md[1], s1);
+                cfma(t1, md[3], s1);
+                cdot(ar, ai, l0, t0);
+                cdot(ar, ai, l1, t1);
+            }
+            V a0 = cmulf(mi[0], s0), a1 = cmulf(mi[2], s0), c0 = cmulf(mt[0], l0), c1 = cmulf(mt[2], l0);
+            cfma(a0, mi[1], s1);
+            cfma(a1, mi[3], s1);
+            cfma(c0, mt[1], l1);
+            cfma(c1, mt[3], l1);
+            vs[i0] = a0; vs[i1] = a1; vl[i0] = c0; vl[i1] = c1;
         }
-        V a0, a1, c0, c1;
-        a0.x = a0.y = a1.x = a1.y = c0.x = c0.y = c1.x = c1.y = 0;
-        cacc(a0, mi[0], s0); cacc(a0, mi[1], s1);
-        cacc(a1, mi[2], s0); cacc(a1, mi[3], s1);
-        cacc(c0, mt[0], l0); cacc(c0, mt[1], l1);
-        cacc(c1, mt[2], l0); cacc(c1, mt[3], l1);
-        vs[i0] = a0; vs[i1] = a1; vl[i0] = c0; vl[i1] = c1;
     }
 }
 
 // Two-qubit gate on register bits R0 (its q[0], the matrix index's high bit)
 // and R1.
-template <int K, int R0, int R1, typename V>
-__device__ __forceinline__ void adj2(V (&vs)[1 << K], V (&vl)[1 << K], const V* mi, const V* mt, const V* md,
-                                     double& ar, double& ai) {
+template <int K, int R0, int R1, typename V, typename A, bool DG>
+__device__ __forceinline__ void tadj2(V (&vs)[1 << K], V (&vl)[1 << K], const V* mi, const V* mt, const V* md,
+                                      A& ar, A& ai) {
 #pragma unroll
     for (int b = 0; b < (1 << K); ++b) {
         if (b & ((1 << R0) | (1 << R1))) continue;
-        asm volatile("" ::: "memory");
         const int ix[4] = {b, b | (1 << R1), b | (1 << R0), b | (1 << R0) | (1 << R1)};
         V x[4], y[4];
 #pragma unroll
@@ -318,144 +398,190 @@ __device__ __forceinline__ void adj2(V (&vs)[1 << K], V (&vl)[1 << K], const V* 
             x[m] = vs[ix[m]];
             y[m] = vl[ix[m]];
         }
-        // one matrix at a time (fences keep the compiler from loading all
-        // three 4x4 matrices at once)
-        if (md) {
+        if constexpr (DG) {
+            if (md) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cdot(ar, ai, y[r], cmulf(md[r * 5], x[r]));
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                V t;
-                t.x = t.y = 0;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) cacc(t, md[r * 4 + c], x[c]);
-                ar += (double)y[r].x * t.x - (double)y[r].y * t.y;
-                ai += (double)y[r].x * t.y + (double)y[r].y * t.x;
+                vs[ix[r]] = cmulf(mi[r * 5], x[r]);
+                vl[ix[r]] = cmulf(mt[r * 5], y[r]);
             }
-            asm volatile("" ::: "memory");
-        }
+        } else {
+            if (md) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            V a;
-            a.x = a.y = 0;
+                for (int r = 0; r < 4; ++r) {
+                    V t = cmulf(md[r * 4], x[0]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cacc(a, mi[r * 4 + c], x[c]);
-            vs[ix[r]] = a;
-        }
-        asm volatile("" ::: "memory");
+                    for (int c = 1; c < 4; ++c) cfma(t, md[r * 4 + c], x[c]);
+                    cdot(ar, ai, y[r], t);
+                }
+            }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            V c2;
-            c2.x = c2.y = 0;
+            for (int r = 0; r < 4; ++r) {
+                V a = cmulf(mi[r * 4], x[0]), c2 = cmulf(mt[r * 4], y[0]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cacc(c2, mt[r * 4 + c], y[c]);
-            vl[ix[r]] = c2;
+                for (int c = 1; c < 4; ++c) {
+                    cfma(a, mi[r * 4 + c], x[c]);
+                    cfma(c2, mt[r * 4 + c], y[c]);
+                }
+                vs[ix[r]] = a;
+                vl[ix[r]] = c2;
+            }
         }
     }
 }
 
-template <int K, typename V>
-__device__ __forceinline__ void adj_op(V (&vs)[1 << K], V (&vl)[1 << K], int k, int r0, int r1, const V* mi,
-                                       const V* mt, const V* md, double& ar, double& ai) {
+template <int K, typename V, typename A, bool DG>
+__device__ __forceinline__ void tadj_op(V (&vs)[1 << K], V (&vl)[1 << K], int k, int r0, int r1, const V* mi,
+                                        const V* mt, const V* md, A& ar, A& ai) {
     if (k == 1) {
         switch (r0) {
-            case 0: adj1<K, 0>(vs, vl, mi, mt, md, ar, ai); break;
-            case 1: if constexpr (K > 1) adj1<K, 1>(vs, vl, mi, mt, md, ar, ai); break;
-            case 2: if constexpr (K > 2) adj1<K, 2>(vs, vl, mi, mt, md, ar, ai); break;
-            default: if constexpr (K > 3) adj1<K, 3>(vs, vl, mi, mt, md, ar, ai); break;
+            case 0: tadj1<K, 0, V, A, DG>(vs, vl, mi, mt, md, ar, ai); break;
+            case 1: if constexpr (K > 1) tadj1<K, 1, V, A, DG>(vs, vl, mi, mt, md, ar, ai); break;
+            default: if constexpr (K > 2) tadj1<K, 2, V, A, DG>(vs, vl, mi, mt, md, ar, ai); break;
         }
         return;
     }
     if constexpr (K >= 2) {
-#define HSF_ADJ2(A, B) \
-    if (r0 == A && r1 == B) { if constexpr (A < K && B < K) adj2<K, A, B>(vs, vl, mi, mt, md, ar, ai); return; }
-        HSF_ADJ2(0, 1) HSF_ADJ2(1, 0) HSF_ADJ2(0, 2) HSF_ADJ2(2, 0) HSF_ADJ2(0, 3) HSF_ADJ2(3, 0)
-        HSF_ADJ2(1, 2) HSF_ADJ2(2, 1) HSF_ADJ2(1, 3) HSF_ADJ2(3, 1) HSF_ADJ2(2, 3) HSF_ADJ2(3, 2)
-#undef HSF_ADJ2
+#define HSF_TADJ2(A0, B0) \
+    if (r0 == A0 && r1 == B0) { if constexpr (A0 < K && B0 < K) tadj2<K, A0, B0, V, A, DG>(vs, vl, mi, mt, md, ar, ai); return; }
+        HSF_TADJ2(0, 1) HSF_TADJ2(1, 0) HSF_TADJ2(0, 2) HSF_TADJ2(2, 0) HSF_TADJ2(1, 2) HSF_TADJ2(2, 1)
+#undef HSF_TADJ2
     }
 }
 
-// The run's gates in order on every row (grid: rows x blocks_per_row, one
-// group of 2^K amplitudes per thread), each angle's term from the state and
-// adjoint just after its gate, reduced per workgroup in a fixed order.
 template <int K, typename T>
-__global__ __launch_bounds__(256) void bw_adj_run(typename Cx<T>::v* __restrict__ s, typename Cx<T>::v* __restrict__ l,
-                                                  int64_t ld, int nq, Bits bits, AdjRun a, uint32_t blocks_per_row) {
+__device__ __forceinline__ void adj_tile_unit(typename Cx<T>::v* ts, typename Cx<T>::v* tl, uint32_t E,
+                                              const AdjTileUnit& u, ctab<AdjTileOp> ops,
+                                              const typename Cx<T>::v* mats, double2* wsum) {
     using V = typename Cx<T>::v;
     constexpr int D = 1 << K;
-    __shared__ V mm[kAdjMaxOps][3][16];
-    __shared__ double rr[kAdjMaxOps][256], ri[kAdjMaxOps][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int sb[K];
 #pragma unroll
-    for (int j = 0; j < kAdjMaxOps; ++j) {
-        if (j >= a.n_ops) break;
-        const int d2 = 1 << (2 * a.k[j]);
-        for (int i = threadIdx.x; i < d2; i += blockDim.x) {
-            mm[j][0][i] = reinterpret_cast<const V*>(a.inv[j])[i];
-            mm[j][1][i] = reinterpret_cast<const V*>(a.tr[j])[i];
-            if (a.dg[j]) mm[j][2][i] = reinterpret_cast<const V*>(a.dg[j])[i];
-        }
+    for (int i = 0; i < K; ++i) sb[i] = u.bit[i];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = i + 1; j < K; ++j)
+            if (sb[j] < sb[i]) {
+                const int t = sb[i];
+                sb[i] = sb[j];
+                sb[j] = t;
+            }
+    uint32_t soff[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((j >> (K - 1 - i)) & 1) o |= 1u << u.bit[i];
+        soff[j] = tswz(o);
     }
-    __syncthreads();
-    const uint32_t row = blockIdx.x / blocks_per_row;
-    const uint32_t blk = blockIdx.x - row * blocks_per_row;
-    const uint64_t groups = uint64_t(1) << (nq - K);
-    const uint64_t g = (uint64_t)blk * blockDim.x + threadIdx.x;
-    // each thread's share of every angle's term, parked in LDS right after
-    // its gate (threads past the last group contribute zero)
+    const int n_ops = u.op_end - u.op_begin;
+    T ar[kAdjMaxOps], ai[kAdjMaxOps];
 #pragma unroll
-    for (int j = 0; j < kAdjMaxOps; ++j) {
-        if (j >= a.n_ops) break;
-        rr[j][threadIdx.x] = 0.0;
-        ri[j][threadIdx.x] = 0.0;
-    }
-    if (g < groups) {
-        // 32-bit element offsets (the host sends rows of under 2^31 amplitudes)
-        uint32_t idx[D];
-        {
-            uint64_t i64[D];
-            group_offsets<K>(bits, g, i64);
+    for (int j = 0; j < kAdjMaxOps; ++j) ar[j] = ai[j] = T(0);
+    const uint32_t groups = E >> K;
+    for (uint32_t g = tid; g < groups; g += kTileThreads) {
+        uint32_t base = g;
 #pragma unroll
-            for (int j = 0; j < D; ++j) idx[j] = (uint32_t)i64[j];
+        for (int i = 0; i < K; ++i) {
+            const uint32_t lo = base & ((1u << sb[i]) - 1u);
+            base = ((base >> sb[i]) << (sb[i] + 1)) | lo;
         }
-        V* sr = s + (int64_t)row * ld;
-        V* lr = l + (int64_t)row * ld;
+        const uint32_t sbase = tswz(base);
         V vs[D], vl[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            vs[j] = sr[idx[j]];
-            vl[j] = lr[idx[j]];
+            vs[j] = ts[sbase ^ soff[j]];
+            vl[j] = tl[sbase ^ soff[j]];
         }
-        // one copy of each gate form's code: the run's table is read by index
-#pragma unroll 1
-        for (int j = 0; j < a.n_ops; ++j) {
-            double ar = 0.0, ai = 0.0;
-            adj_op<K>(vs, vl, a.k[j], a.rb[j][0], a.rb[j][1], mm[j][0], mm[j][1], a.dg[j] ? mm[j][2] : nullptr, ar, ai);
-            rr[j][threadIdx.x] = ar;
-            ri[j][threadIdx.x] = ai;
+#pragma unroll
+        for (int j = 0; j < kAdjMaxOps; ++j) {
+            if (j >= n_ops) break;
+            const AdjTileOp op = ops[u.op_begin + j];
+            const V* md = op.ang >= 0 ? mats + op.dg : nullptr;
+            if (op.diag)
+                tadj_op<K, V, T, true>(vs, vl, op.k, op.rb0, op.rb1, mats + op.inv, mats + op.tr, md, ar[j], ai[j]);
+            else
+                tadj_op<K, V, T, false>(vs, vl, op.k, op.rb0, op.rb1, mats + op.inv, mats + op.tr, md, ar[j], ai[j]);
         }
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            sr[idx[j]] = vs[j];
-            lr[idx[j]] = vl[j];
+            ts[sbase ^ soff[j]] = vs[j];
+            tl[sbase ^ soff[j]] = vl[j];
         }
     }
-    __syncthreads();
-    // fixed-order tree over the workgroup for every angle at once
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
 #pragma unroll
-            for (int j = 0; j < kAdjMaxOps; ++j) {
-                if (j >= a.n_ops) break;
-                rr[j][threadIdx.x] += rr[j][threadIdx.x + w];
-                ri[j][threadIdx.x] += ri[j][threadIdx.x + w];
-            }
+    for (int j = 0; j < kAdjMaxOps; ++j) {
+        if (j >= n_ops) break;
+        const int a = ops[u.op_begin + j].ang;
+        if (a < 0) continue;
+        const double r = wave_sum((double)ar[j]), i = wave_sum((double)ai[j]);
+        if (lane == 0) wsum[a * kTileWaves + wave] = make_double2(r, i);
+    }
+}
+
+// Grid: rows x tiles per row.  partial[occ * pstride + row * n_tiles + tile].
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void bw_adj_tile(typename Cx<T>::v* __restrict__ s,
+                                                            typename Cx<T>::v* __restrict__ l, int64_t ld,
+                                                            AdjTilePass ps, const AdjTileUnit* __restrict__ units_in,
+                                                            const AdjTileOp* __restrict__ ops_in,
+                                                            const typename Cx<T>::v* __restrict__ mats_in,
+                                                            const int64_t* __restrict__ occ, double2* partial,
+                                                            int64_t pstride, uint32_t n_tiles) {
+    using V = typename Cx<T>::v;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t E = 1u << ps.L;
+    V* ts = reinterpret_cast<V*>(smem);
+    V* tl = ts + E;
+    double2* wsum = reinterpret_cast<double2*>(tl + E);
+    V* sm = reinterpret_cast<V*>(wsum + kTileMaxAngles * kTileWaves);
+    const ctab<AdjTileUnit> units = (ctab<AdjTileUnit>)units_in;
+    const ctab<AdjTileOp> ops = (ctab<AdjTileOp>)ops_in;
+    for (int i = threadIdx.x; i < ps.n_mat; i += kTileThreads) sm[i] = mats_in[ps.mat_begin + i];
+    const uint32_t row = blockIdx.x / n_tiles, tile = blockIdx.x - row * n_tiles;
+    uint64_t base = 0;
+    for (int i = 0; i < ps.n_nonlocal; ++i) base |= (uint64_t)((tile >> i) & 1u) << ps.nonlocal_q[i];
+    const uint32_t cmask = (1u << ps.nc) - 1u;
+    auto gidx = [&](uint32_t e) -> uint64_t {
+        uint64_t g = base | (e & cmask);
+        for (int i = ps.nc; i < ps.L; ++i) g |= (uint64_t)((e >> i) & 1u) << ps.local_q[i];
+        return g;
+    };
+    V* sr = s + (int64_t)row * ld;
+    V* lr = l + (int64_t)row * ld;
+    for (uint32_t e = threadIdx.x; e < E; e += kTileThreads) {
+        const uint64_t g = gidx(e);
+        ts[tswz(e)] = sr[g];
+        tl[tswz(e)] = lr[g];
+    }
+    __syncthreads();
+    for (int ui = ps.unit_begin; ui < ps.unit_end; ++ui) {
+        const AdjTileUnit u = units[ui];
+        switch (u.K) {
+            case 1: adj_tile_unit<1, T>(ts, tl, E, u, ops, sm, wsum); break;
+            case 2: adj_tile_unit<2, T>(ts, tl, E, u, ops, sm, wsum); break;
+            default: adj_tile_unit<3, T>(ts, tl, E, u, ops, sm, wsum); break;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < kAdjMaxOps; ++j) {
-            if (j >= a.n_ops) break;
-            if (a.dg[j]) a.partial[j][blockIdx.x] = make_double2(rr[j][0], ri[j][0]);
+    for (uint32_t e = threadIdx.x; e < E; e += kTileThreads) {
+        const uint64_t g = gidx(e);
+        sr[g] = ts[tswz(e)];
+        lr[g] = tl[tswz(e)];
+    }
+    if ((int)threadIdx.x < ps.n_ang) {
+        double2 acc = wsum[threadIdx.x * kTileWaves];
+        for (int w = 1; w < kTileWaves; ++w) {
+            acc.x += wsum[threadIdx.x * kTileWaves + w].x;
+            acc.y += wsum[threadIdx.x * kTileWaves + w].y;
         }
+        partial[occ[ps.occ_begin + threadIdx.x] * pstride + (int64_t)row * n_tiles + tile] = acc;
     }
 }
 
@@ -551,9 +677,12 @@ __global__ __launch_bounds__(256) void bw_loss(const double2* __restrict__ amp, 
     if (threadIdx.x == 0) *out = r[0];
 }
 
-// out = Re sum_j conj(c_j) amp_j in a fixed order (one block)
+// out = Re sum_j conj(c_j) amp_j in a fixed order (one workgroup per copy)
 __global__ __launch_bounds__(256) void bw_shift_dot(const double2* __restrict__ c, const double2* __restrict__ amp,
                                                     int64_t n, double* __restrict__ out) {
+    // workgroup r: copy r of the shifted amplitudes (amp + r n) into out[r]
+    amp += (int64_t)blockIdx.x * n;
+    out += blockIdx.x;
     __shared__ double r[256];
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) s += c[i].x * amp[i].x + c[i].y * amp[i].y;
@@ -566,8 +695,11 @@ __global__ __launch_bounds__(256) void bw_shift_dot(const double2* __restrict__ 
     if (threadIdx.x == 0) *out = r[0];
 }
 
-__global__ void bw_shift_add(const double* __restrict__ v, double* __restrict__ grad, int64_t t) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) grad[t] += *v;
+// grad[t[i]] += v[i] for i = 0, 1, ..., n - 1 in that order (one thread)
+__global__ void bw_shift_add(const double* __restrict__ v, const int64_t* __restrict__ t, int64_t n,
+                             double* __restrict__ grad) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        for (int64_t i = 0; i < n; ++i) grad[t[i]] += v[i];
 }
 
 // c_j = g_j / 2: the caller's cotangents as the coefficients of the adjoint
@@ -579,9 +711,11 @@ __global__ void bw_half(const double2* __restrict__ g, double2* __restrict__ c, 
 // ---------------------------------------------------------------- host ----
 
 struct Layout {
-    size_t vA, vB, lA, lB, ckA, ckB, psi_x, psi_s, loss, partial, tables, mats, pools, tree, tree_bytes, lane,
-        lane_bytes, total;
-    int lanes;             // concurrent shifted forward runs
+    size_t adj_tiles, adj_tiles_bytes;   // tile-pass tables of the adjoint (units, ops, occurrences)
+    size_t shift_t;                      // parameter id of each shifted run
+    size_t vA, vB, lA, lB, ckA, ckB, psi_x, loss, partial, tables, mats, pools, tree, tree_bytes, total;
+    size_t repA, repB, rep_psi, rep_tree, rep_tree_bytes;   // copies of the shifted forward run
+    int64_t reps;          // copies per batch of shifted forward runs
     int64_t dimA, dimB;
     int ka, kb;            // checkpoints per side
     int64_t n_occ;         // parametrised ops outside blocks, both sides
@@ -592,10 +726,11 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Streams the parameter-shift forward runs share: the early path-tree levels
-// of one run hold too few states to fill the chip, so several runs go at
-// once (at most the hardware queues a process gets by default).
-constexpr int kShiftLanes = 4;
+// Device memory of the shifted forward runs' copies (half-states, bitstring
+// amplitudes and tree levels of each): one run's early path-tree levels hold
+// too few states to fill the chip, so up to this much goes to running many
+// shifted runs as copies of one in the same launches.
+constexpr size_t kShiftCopyBytes = size_t(4) << 30;
 
 // Workgroups per path row of the per-op adjoint kernels (one group of 2^k
 // amplitudes per thread, 256 threads).
@@ -613,7 +748,30 @@ size_t side_mat_elems(const SideProgram& sp) {
     return e;
 }
 
-Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
+// The schedules the forward runs over chunks of `chunk` paths take (tree
+// levels in tree_workspace(p, chunk) bytes): used[2 side + tree][index].
+// Only these get patched factor pools for the shifted runs.
+std::vector<std::vector<char>> forward_schedules(const Plan& p, int64_t chunk) {
+    std::vector<std::vector<char>> used(4);
+    for (int s = 0; s < 2; ++s)
+        for (int tr = 0; tr < 2; ++tr) used[2 * s + tr].assign((tr ? p.side[s].tree : p.side[s].sched).size(), 0);
+    if (p.P <= 0) return used;
+    const size_t tb = tree_workspace(p, std::min(chunk, p.P));
+    std::vector<int64_t> sizes{std::min(chunk, p.P)};
+    if (p.P > chunk && p.P % chunk) sizes.push_back(p.P % chunk);
+    for (int64_t n : sizes) {
+        SweepChoice ch = choose_sweep(p, n);
+        if (ch.tree && tree_scratch(p, n).total > tb) ch = choose_sweep(p, n, false);
+        for (int s = 0; s < 2; ++s) {
+            std::vector<char>& u = used[2 * s + (ch.tree ? 1 : 0)];
+            if (!u.empty()) u[std::min<size_t>((size_t)ch.sched, u.size() - 1)] = 1;
+        }
+    }
+    return used;
+}
+
+// reps_cap > 0: at most that many copies per batch of shifted runs.
+Layout layout(const Plan& p, int64_t chunk, int64_t nx, int64_t reps_cap = 0) {
     Layout L{};
     const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
     L.dimA = int64_t(1) << p.na;
@@ -633,10 +791,13 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     L.table_elems = 2 * (size_t)(4 * nx + 1) + (size_t)(p.n_params + 1) + 2 * (size_t)L.n_occ;
     L.mat_elems = side_mat_elems(p.side[0]) + side_mat_elems(p.side[1]);
     L.pool_elems = 0;
+    const std::vector<std::vector<char>> used = forward_schedules(p, chunk);
     for (int s = 0; s < 2; ++s)
-        for (int tr = 0; tr < 2; ++tr)
-            for (const Schedule& sc : tr ? p.side[s].tree : p.side[s].sched)
-                L.pool_elems += std::max<size_t>(sc.pool.size(), 1);
+        for (int tr = 0; tr < 2; ++tr) {
+            const std::vector<Schedule>& v = tr ? p.side[s].tree : p.side[s].sched;
+            for (size_t q = 0; q < v.size(); ++q)
+                if (used[2 * s + tr][q]) L.pool_elems += std::max<size_t>(v[q].pool.size(), 1);
+        }
     // shifts of angles inside blocks: one forward run per occurrence, each
     // with its own copy of the pools
     L.n_shift = 0;
@@ -654,20 +815,35 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx) {
     L.ckA = take((size_t)L.ka * chunk * L.dimA * esz);
     L.ckB = take((size_t)L.kb * chunk * L.dimB * esz);
     L.psi_x = take((size_t)nx * 16);
-    L.psi_s = take((size_t)nx * 16);
     L.loss = take((size_t)std::max<int64_t>(4, L.n_shift) * sizeof(double));
+    L.shift_t = take((size_t)std::max<int64_t>(1, L.n_shift) * sizeof(int64_t));
     L.partial = take((size_t)std::max<int64_t>(L.n_occ, 1) * chunk * L.per_row_max * 16);
     L.tables = take(L.table_elems * sizeof(int64_t));
     L.mats = take(L.mat_elems * esz);
     L.pools = take(L.pool_elems * (size_t)std::max<int64_t>(1, L.n_shift) * esz);
     L.tree_bytes = tree_workspace(p, chunk);     // path-tree levels of the forward runs
     L.tree = take(L.tree_bytes);
-    // the shifted forward runs go round kShiftLanes streams; lanes past the
-    // first bring their own half-states, bitstring amplitudes and tree levels
-    L.lanes = (int)std::min<int64_t>(kShiftLanes, std::max<int64_t>(1, L.n_shift));
-    L.lane_bytes = align256((size_t)chunk * L.dimA * esz) + align256((size_t)chunk * L.dimB * esz) +
-                   align256((size_t)nx * 16) + align256(L.tree_bytes);
-    L.lane = take(L.lane_bytes * (size_t)(L.lanes - 1));
+    // the shifted forward runs in balanced batches of `reps` copies, within
+    // kShiftCopyBytes (at least one copy)
+    L.rep_tree_bytes = align256(L.tree_bytes);
+    {
+        const size_t per = (size_t)chunk * (L.dimA + L.dimB) * esz + (size_t)nx * 16 + L.rep_tree_bytes;
+        const int64_t ns = std::max<int64_t>(1, L.n_shift);
+        int64_t rmax = std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)(kShiftCopyBytes / std::max<size_t>(per, 1))));
+        if (reps_cap > 0) rmax = std::min(rmax, reps_cap);
+        const int64_t batches = (ns + rmax - 1) / rmax;
+        L.reps = L.n_shift > 0 ? (ns + batches - 1) / batches : 0;
+    }
+    L.repA = take((size_t)L.reps * chunk * L.dimA * esz);
+    L.repB = take((size_t)L.reps * chunk * L.dimB * esz);
+    L.rep_psi = take((size_t)L.reps * nx * 16);
+    L.rep_tree = take((size_t)L.reps * L.rep_tree_bytes);
+    const size_t n_raw = p.side[0].raw.size() + p.side[1].raw.size();
+    size_t tile_mats = 0;
+    for (int s = 0; s < 2; ++s)
+        for (const SideOp& o : p.side[s].raw) tile_mats += (size_t)3 << (2 * o.k);
+    L.adj_tiles_bytes = n_raw * (sizeof(AdjTileUnit) + sizeof(AdjTileOp) + sizeof(int64_t)) + tile_mats * esz + 4 * 256;
+    L.adj_tiles = take(L.adj_tiles_bytes);
     L.total = o + 256;
     return L;
 }
@@ -703,57 +879,140 @@ std::vector<cd> transpose_of(const std::vector<cd>& m, int d) {
     return r;
 }
 
-// The adjoint pass's units of one side, in the order it takes them (program
-// order reversed): a factor slot alone, a gate on more than two qubits alone
-// (and every gate of a side of 31 qubits or more), or a run of consecutive
-// gates on at most kAdjMaxBits qubits together (at most kAdjMaxOps of them),
-// raw indices hi, hi - 1, ..., hi - n + 1.
+// Whether an op's matrix (and, with an angle, its D) is diagonal: two such
+// ops commute even where their qubits overlap.
+bool adj_diagonal(const SideOp& o) {
+    if (o.kind != SideOp::DIAG) return false;
+    if (o.param_id < 0) return true;
+    const int d = 1 << o.k;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            if (r != c && o.dgen[(size_t)r * d + c] != cd(0)) return false;
+    return true;
+}
+
+// The adjoint pass's units of one side, in the order it takes them: a factor
+// slot alone, a gate on more than two qubits alone (and every gate of a side
+// of 31 qubits or more), or a run of gates on at most kAdjMaxBits qubits
+// together (at most kAdjMaxOps of them).
 struct AdjUnit {
-    int kind;             // 0 run, 1 slot, 2 single wide gate
-    int hi, n, K;
-    int q[4];             // run: its qubits; register bit K - 1 - i holds q[i]
+    int kind;              // 0 run, 1 slot, 2 single wide gate
+    int K;
+    int q[4];              // run: its qubits; register bit K - 1 - i holds q[i]
+    std::vector<int> ops;  // raw indices, in the order the pass undoes them
 };
 
-std::vector<AdjUnit> adj_units(const SideProgram& sp) {
-    std::vector<AdjUnit> u;
+// Consecutive run units undone in one pass over LDS tiles of the qubits
+// local_q (ascending; the side's five lowest among them).
+struct TileGroup {
+    int u_begin, u_end;              // units[u_begin, u_end)
+    std::vector<int> local_q;
+};
+
+int adj_tile_bits(int nq, bool c128) { return std::min(nq, c128 ? 11 : 12); }
+
+// matrix elements an op stages in a tile pass: M^dagger, M^T (and D)
+size_t tile_op_mats(const SideOp& o) { return (size_t)(o.param_id >= 0 ? 3 : 2) << (2 * o.k); }
+
+// The adjoint pass of one side as units and tile passes.  Gates are undone in
+// reverse program order up to commutation: two gates commute when their
+// qubits are disjoint or both are diagonal, and then either order leaves the
+// same state and adjoint, and each angle's term 2 Re <lambda, D s> (its D
+// commutes with the same gates) is the same at either place.  Factor slots and
+// wide gates keep their places.  Between two of them, a tile pass takes the
+// side's five lowest qubits and those of the next gates up to L qubits, then
+// units are built greedily: scanning the gates left in order, a gate joins
+// the unit if its qubits lie in the tile, the unit stays within kAdjMaxBits
+// qubits and kAdjMaxOps gates (and the pass within its angle and matrix
+// slots), and no gate passed over before it fails to commute with it (a
+// passed-over gate blocks its qubits for the rest of the scan).
+hsf_status adj_schedule(const SideProgram& sp, int L, size_t mat_cap, std::vector<AdjUnit>& units,
+                        std::vector<TileGroup>& groups) {
     const auto& raw = sp.raw;
-    for (int ii = (int)raw.size() - 1; ii >= 0;) {
-        AdjUnit a{};
-        a.hi = ii;
-        a.n = 1;
-        const SideOp& o = raw[ii];
-        if (o.kind == SideOp::SLOT || o.k > 2 || sp.nq >= 31) {
-            a.kind = o.kind == SideOp::SLOT ? 1 : 2;
-            a.K = o.k;
-            u.push_back(a);
-            --ii;
+    const int nq = sp.nq, n = (int)raw.size();
+    std::vector<char> diag((size_t)n), done((size_t)n, 0);
+    for (int i = 0; i < n; ++i) diag[(size_t)i] = adj_diagonal(raw[(size_t)i]);
+    auto barrier = [&](int i) { return raw[(size_t)i].kind == SideOp::SLOT || raw[(size_t)i].k > 2 || nq >= 31; };
+    int pos = n - 1;   // the latest op in program order not yet undone
+    while (pos >= 0) {
+        if (done[(size_t)pos]) {
+            --pos;
             continue;
         }
-        a.kind = 0;
-        for (int j = 0; j < o.k; ++j) a.q[a.K++] = o.q[j];
-        int j = ii - 1;
-        while (j >= 0 && a.n < kAdjMaxOps && raw[j].kind != SideOp::SLOT && raw[j].k <= 2 && sp.nq < 31) {
-            int qq[4], nq = a.K;
-            for (int t = 0; t < a.K; ++t) qq[t] = a.q[t];
-            bool fits = true;
-            for (int t = 0; t < raw[j].k && fits; ++t) {
-                bool have = false;
-                for (int r = 0; r < nq; ++r) have |= qq[r] == raw[j].q[t];
-                if (!have) {
-                    if (nq == kAdjMaxBits) fits = false;
-                    else qq[nq++] = raw[j].q[t];
+        if (barrier(pos)) {
+            AdjUnit a{};
+            a.kind = raw[(size_t)pos].kind == SideOp::SLOT ? 1 : 2;
+            a.K = raw[(size_t)pos].k;
+            a.ops.push_back(pos);
+            units.push_back(std::move(a));
+            done[(size_t)pos] = 1;
+            --pos;
+            continue;
+        }
+        int lo = pos;     // the segment is (lo, pos]: lo is a barrier or -1
+        while (lo >= 0 && !barrier(lo)) --lo;
+        std::vector<char> in((size_t)nq, 0);
+        int count = 0;
+        for (int q = 0; q < std::min(5, L); ++q) in[(size_t)q] = 1, ++count;
+        for (int i = pos; i > lo; --i) {
+            if (done[(size_t)i]) continue;
+            const SideOp& o = raw[(size_t)i];
+            int add = 0;
+            for (int e = 0; e < o.k; ++e) add += in[(size_t)o.q[e]] ? 0 : 1;
+            if (count + add > L) break;
+            for (int e = 0; e < o.k; ++e)
+                if (!in[(size_t)o.q[e]]) in[(size_t)o.q[e]] = 1, ++count;
+        }
+        for (int q = 0; q < nq && count < L; ++q)
+            if (!in[(size_t)q]) in[(size_t)q] = 1, ++count;
+        TileGroup g;
+        g.u_begin = (int)units.size();
+        int angles = 0;
+        size_t mats = 0;
+        for (;;) {
+            std::vector<char> b_dense((size_t)nq, 0), b_diag((size_t)nq, 0);   // blocked by a passed-over gate
+            AdjUnit a{};
+            a.kind = 0;
+            int uang = 0;
+            size_t umat = 0;
+            for (int i = pos; i > lo; --i) {
+                if (done[(size_t)i]) continue;
+                const SideOp& o = raw[(size_t)i];
+                bool ok = (int)a.ops.size() < kAdjMaxOps;
+                int add[2], n_add = 0;
+                for (int e = 0; e < o.k; ++e) {
+                    const int q = o.q[e];
+                    if (b_dense[(size_t)q] || (!diag[(size_t)i] && b_diag[(size_t)q]) || !in[(size_t)q]) ok = false;
+                    bool have = false;
+                    for (int t = 0; t < a.K; ++t) have |= a.q[t] == q;
+                    if (!have) add[n_add++] = q;
+                }
+                if (ok && a.K + n_add > kAdjMaxBits) ok = false;
+                const int ga = o.param_id >= 0 ? 1 : 0;
+                const size_t gm = tile_op_mats(o);
+                if (ok && (angles + uang + ga > kTileMaxAngles || mats + umat + gm > mat_cap)) ok = false;
+                if (ok) {
+                    for (int t = 0; t < n_add; ++t) a.q[a.K++] = add[t];
+                    a.ops.push_back(i);
+                    uang += ga;
+                    umat += gm;
+                } else {
+                    for (int e = 0; e < o.k; ++e) (diag[(size_t)i] ? b_diag : b_dense)[(size_t)o.q[e]] = 1;
                 }
             }
-            if (!fits) break;
-            a.K = nq;
-            for (int t = 0; t < nq; ++t) a.q[t] = qq[t];
-            ++a.n;
-            --j;
+            if (a.ops.empty()) break;
+            for (int i : a.ops) done[(size_t)i] = 1;
+            angles += uang;
+            mats += umat;
+            units.push_back(std::move(a));
         }
-        u.push_back(a);
-        ii = j;
+        g.u_end = (int)units.size();
+        if (g.u_end == g.u_begin) return fail(HSF_E_ARG, "internal: an adjoint tile pass took no gate");
+        for (int q = 0; q < nq; ++q)
+            if (in[(size_t)q]) g.local_q.push_back(q);
+        groups.push_back(std::move(g));
     }
-    return u;
+    return HSF_OK;
 }
 
 // Offsets (in complex elements, inside the backward matrix area) of each raw op's matrices.
@@ -817,21 +1076,6 @@ struct Runner {
         });
     }
 
-    hsf_status adj_run(V* s, V* l, int64_t ld, int64_t rows, int nq, const Bits& bits, int K, const AdjRun& a) {
-        const uint32_t bpr = (uint32_t)adj_blocks_per_row(nq, K);
-        auto go = [&](auto kk) {
-            constexpr int KK = decltype(kk)::value;
-            hipLaunchKernelGGL((bw_adj_run<KK, T>), dim3((uint32_t)(rows * bpr)), dim3(256), 0, st, s, l, ld, nq, bits,
-                               a, bpr);
-            return hip_check(hipGetLastError(), "bw_adj_run launch");
-        };
-        switch (K) {
-            case 1: return go(std::integral_constant<int, 1>());
-            case 2: return go(std::integral_constant<int, 2>());
-            case 3: return go(std::integral_constant<int, 3>());
-            default: return fail(HSF_E_ARG, "internal: an adjoint run wider than three qubits");
-        }
-    }
 
     hsf_status fill(V* x, int64_t ld, int64_t dim, int64_t rows, int one) {
         const int64_t n = rows * dim;
@@ -852,8 +1096,18 @@ template <typename T>
 hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, const double2* dl_dpsi, double* grad,
                       int64_t n_params, int64_t chunk, void* ws, size_t ws_bytes, hipStream_t st) {
     using V = typename Cx<T>::v;
-    const Layout Lo = layout(p, chunk, nx);
-    if (ws_bytes < Lo.total) return fail(HSF_E_ARG, "workspace too small for hsf_backward");
+    // as many copies of the shifted run per batch as the workspace holds
+    Layout Lo = layout(p, chunk, nx);
+    if (ws_bytes < Lo.total) {
+        int64_t lo = 1, hi = std::max<int64_t>(1, Lo.reps - 1);
+        if (ws_bytes < layout(p, chunk, nx, 1).total) return fail(HSF_E_ARG, "workspace too small for hsf_backward");
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (layout(p, chunk, nx, mid).total <= ws_bytes) lo = mid;
+            else hi = mid - 1;
+        }
+        Lo = layout(p, chunk, nx, lo);
+    }
     if (nx == 0 || p.n_params == 0) {
         // no bitstrings (L = 0 for every angle) or no angles: the gradient is zero
         hipLaunchKernelGGL(bw_zero_doubles, dim3(std::max<uint32_t>(1, (uint32_t)((n_params + 255) / 256))), dim3(256),
@@ -865,7 +1119,6 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
     V* lS[2] = {(V*)(base + Lo.lA), (V*)(base + Lo.lB)};
     V* ck[2] = {(V*)(base + Lo.ckA), (V*)(base + Lo.ckB)};
     double2* psi_x = (double2*)(base + Lo.psi_x);
-    double2* psi_s = (double2*)(base + Lo.psi_s);
     double* lossb = (double*)(base + Lo.loss);
     double2* partial = (double2*)(base + Lo.partial);
     int64_t* tables = (int64_t*)(base + Lo.tables);
@@ -875,7 +1128,126 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
     const int nq[2] = {p.na, p.nb};
     hsf_status s;
 
-    const std::vector<AdjUnit> units[2] = {adj_units(p.side[0]), adj_units(p.side[1])};
+    // ---- angles inside blocks (amplitude shift rule): every shifted block is
+    // re-factored on host threads, started here so that they run while the
+    // tables are built and the forward and adjoint passes are enqueued and run
+    bool any = false;
+    for (const Block& b : p.blocks) any |= !b.params.empty();
+    int64_t* shift_t_d = reinterpret_cast<int64_t*>(base + Lo.shift_t);
+    const std::vector<std::vector<char>> used_sched = forward_schedules(p, chunk);
+    std::vector<std::vector<size_t>> pool_at(4);     // offset of a used schedule's pool in a shift's block
+    struct Shift {
+        size_t k;
+        int64_t gid;
+        int t;
+    };
+    std::vector<Shift> shifts;
+    std::vector<int64_t> shift_ids;
+    if (any) {
+        // device pools of the schedules the forward runs use (flat, then
+        // path-tree), to be patched per shifted block
+        size_t o = 0;
+        for (int side = 0; side < 2; ++side)
+            for (int tr = 0; tr < 2; ++tr) {
+                const std::vector<Schedule>& v = tr ? p.side[side].tree : p.side[side].sched;
+                pool_at[2 * side + tr].assign(v.size(), 0);
+                for (size_t q = 0; q < v.size(); ++q)
+                    if (used_sched[2 * side + tr][q]) {
+                        pool_at[2 * side + tr][q] = o;
+                        o += std::max<size_t>(v[q].pool.size(), 1);
+                    }
+            }
+        for (size_t k = 0; k < p.blocks.size(); ++k)
+            for (const auto& gp : p.blocks[k].params)
+                if (gp.second < n_params) shifts.push_back({k, gp.first, gp.second});
+        for (const Shift& sh : shifts) shift_ids.push_back(sh.t);
+    }
+    const size_t ns = shifts.size();
+    std::vector<V> staged(ns * Lo.pool_elems);     // host copy of the shifted pools; must outlive the upload
+    std::vector<hsf_status> hst(ns, HSF_OK);
+    std::vector<std::string> herr(ns);
+    auto refactor = [&](size_t i) {
+        const Shift& sh = shifts[i];
+        const Block& b = p.blocks[sh.k];
+        Factors fs;
+        const double ang = p.gates[sh.gid].param + 2.0 * std::acos(0.0);   // theta + pi
+        hsf_status e = factor_block_rank(p, b, sh.gid, ang, b.rank, fs);
+        if (e != HSF_OK) {
+            hst[i] = e;
+            herr[i] = hsf::g_last_error_copy();
+            return;
+        }
+        const int r = fs.rank;
+        if (r > b.rank) {
+            hst[i] = HSF_E_UNSUPPORTED;
+            herr[i] = "a shifted block has a larger Schmidt rank than the plan's";
+            return;
+        }
+        if (fs.product != b.product || fs.pa.size() != b.pa.size() || fs.pb.size() != b.pb.size()) {
+            hst[i] = HSF_E_UNSUPPORTED;
+            herr[i] = "a shifted block changes its decomposition form";
+            return;
+        }
+        // patched pools: factors of block k replaced (missing ranks zero)
+        std::vector<cd> all;
+        all.reserve(Lo.pool_elems);
+        for (int side = 0; side < 2; ++side) {
+            const std::vector<FactorPiece>& pcs = side == 0 ? fs.pa : fs.pb;
+            for (int tr = 0; tr < 2; ++tr)
+            for (size_t q = 0; q < (tr ? p.side[side].tree : p.side[side].sched).size(); ++q) {
+                if (!used_sched[2 * side + tr][q]) continue;
+                const Schedule& sc = (tr ? p.side[side].tree : p.side[side].sched)[q];
+                std::vector<cd> pl = sc.pool;
+                for (const DevOp& op : sc.devops)
+                    if (op.type == DOP_SLOT && op.block == (int)sh.k) {
+                        const std::vector<cd>& f = pcs[op.piece].m;
+                        const size_t d2 = (size_t)1 << (2 * op.k);
+                        for (int m = 0; m < b.rank; ++m)
+                            for (size_t e2 = 0; e2 < d2; ++e2)
+                                pl[op.mat + m * d2 + e2] = m < r ? f[m * d2 + e2] : cd(0);
+                    }
+                // one-qubit factor pieces applied inside register groups
+                for (const SubOp& so : sc.subs)
+                    if (so.type == SUB_SLOT1 && so.block == (int)sh.k) {
+                        const std::vector<cd>& f = pcs[so.piece].m;
+                        for (int m = 0; m < b.rank; ++m)
+                            for (size_t e2 = 0; e2 < 4; ++e2)
+                                pl[so.mat + m * 4 + e2] = m < r ? f[m * 4 + e2] : cd(0);
+                    }
+                if (pl.empty()) pl.push_back(cd(0));
+                all.insert(all.end(), pl.begin(), pl.end());
+            }
+        }
+        std::vector<V> av;
+        to_dev<T>(all, av);
+        std::copy(av.begin(), av.end(), staged.begin() + i * Lo.pool_elems);
+    };
+    // joined before the pools are uploaded, and on every exit
+    std::atomic<size_t> next_shift(0);
+    struct Workers {
+        std::vector<std::thread> t;
+        void join() {
+            for (std::thread& th : t)
+                if (th.joinable()) th.join();
+        }
+        ~Workers() { join(); }
+    } workers;
+    {
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        // a few cores stay free for this thread's enqueueing and the runtime's
+        const size_t nthr = std::min<size_t>(ns, std::min(12u, hw));
+        for (size_t w = 0; w < nthr; ++w)
+            workers.t.emplace_back([&]() {
+                for (size_t i = next_shift++; i < ns; i = next_shift++) refactor(i);
+            });
+    }
+
+    const int tbits[2] = {adj_tile_bits(p.na, p.dtype == HSF_C128), adj_tile_bits(p.nb, p.dtype == HSF_C128)};
+    const size_t mat_cap = kTileMatBytes / sizeof(V);
+    std::vector<AdjUnit> units[2];
+    std::vector<TileGroup> tgroups[2];
+    for (int side = 0; side < 2; ++side)
+        if ((s = adj_schedule(p.side[side], tbits[side], mat_cap, units[side], tgroups[side])) != HSF_OK) return s;
 
     // ---- host tables: bitstring groups per side, parameter occurrences
     std::vector<uint64_t> hx((size_t)std::max<int64_t>(nx, 1));
@@ -938,11 +1310,19 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
         const size_t occ_rows = occ_list + (size_t)Lo.n_occ;
         int64_t q = 0;
         for (int side = 0; side < 2; ++side) {
+            // angles of run units: one partial per (row, tile) of their tile
+            // pass; wider gates: one per workgroup of their own kernel
             std::vector<int> width(p.side[side].raw.size(), 1);
+            std::vector<char> in_run(p.side[side].raw.size(), 0);
             for (const AdjUnit& a : units[side])
-                for (int t = 0; t < a.n; ++t) width[(size_t)(a.hi - t)] = a.K;
+                for (int i : a.ops) {
+                    width[(size_t)i] = a.K;
+                    in_run[(size_t)i] = a.kind == 0;
+                }
+            const int64_t n_tiles = int64_t(1) << (nq[side] - tbits[side]);
             for (size_t i = 0; i < p.side[side].raw.size(); ++i)
-                if (p.side[side].raw[i].param_id >= 0) ht[occ_rows + q++] = adj_blocks_per_row(nq[side], width[i]);
+                if (p.side[side].raw[i].param_id >= 0)
+                    ht[occ_rows + q++] = in_run[i] ? n_tiles : adj_blocks_per_row(nq[side], width[i]);
         }
         if ((s = hip_check(hipMemcpyAsync(tables, ht.data(), ht.size() * sizeof(int64_t), hipMemcpyHostToDevice, st),
                            "upload tables")) != HSF_OK)
@@ -993,6 +1373,124 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
         (s = hip_check(hipMemcpyAsync(mats, hmv.data(), hmv.size() * sizeof(V), hipMemcpyHostToDevice, st), "upload mats")) != HSF_OK)
         return s;
 
+    // occurrence of each raw op with an angle (numbered in program order, side
+    // a first), -1 for the others
+    std::vector<int64_t> occ_of[2];
+    {
+        int64_t q = 0;
+        for (int side = 0; side < 2; ++side) {
+            occ_of[side].assign(p.side[side].raw.size(), -1);
+            for (size_t i = 0; i < p.side[side].raw.size(); ++i)
+                if (p.side[side].raw[i].param_id >= 0) occ_of[side][i] = q++;
+        }
+    }
+
+    // ---- tile-pass tables of the adjoint: units, ops, angle occurrences
+    std::vector<AdjTileUnit> tu;
+    std::vector<AdjTileOp> to;
+    std::vector<int64_t> tocc;
+    std::vector<cd> tmats;             // each pass's matrices, contiguous
+    std::vector<AdjTilePass> tpass[2];
+    {
+        for (int side = 0; side < 2; ++side) {
+            const auto& raw = p.side[side].raw;
+            for (const TileGroup& g : tgroups[side]) {
+                AdjTilePass ps{};
+                ps.L = (int)g.local_q.size();
+                std::vector<int> tbit(nq[side], -1);
+                for (int i = 0; i < ps.L; ++i) {
+                    ps.local_q[i] = g.local_q[i];
+                    tbit[g.local_q[i]] = i;
+                }
+                ps.nc = 0;
+                while (ps.nc < ps.L && ps.local_q[ps.nc] == ps.nc) ++ps.nc;
+                for (int qq = 0; qq < nq[side]; ++qq)
+                    if (tbit[qq] < 0) ps.nonlocal_q[ps.n_nonlocal++] = qq;
+                ps.unit_begin = (int)tu.size();
+                ps.occ_begin = (int64_t)tocc.size();
+                ps.mat_begin = (int64_t)tmats.size();
+                auto stage = [&](size_t at, int k) {
+                    const int32_t off = (int32_t)(tmats.size() - (size_t)ps.mat_begin);
+                    tmats.insert(tmats.end(), hm.begin() + (int64_t)at, hm.begin() + (int64_t)(at + ((size_t)1 << (2 * k))));
+                    return off;
+                };
+                for (int ui = g.u_begin; ui < g.u_end; ++ui) {
+                    const AdjUnit& u = units[side][(size_t)ui];
+                    AdjTileUnit r{};
+                    r.K = u.K;
+                    for (int t = 0; t < u.K; ++t) r.bit[t] = tbit[u.q[t]];
+                    r.op_begin = (int)to.size();
+                    for (int ri_ : u.ops) {
+                        const size_t ri = (size_t)ri_;
+                        const SideOp& gop = raw[ri];
+                        AdjTileOp op{};
+                        op.k = gop.k;
+                        for (int e = 0; e < gop.k; ++e) {
+                            int pos = 0;
+                            while (u.q[pos] != gop.q[e]) ++pos;
+                            (e == 0 ? op.rb0 : op.rb1) = u.K - 1 - pos;
+                        }
+                        op.inv = stage(om[side][ri].inv, gop.k);
+                        op.tr = stage(om[side][ri].tr, gop.k);
+                        op.diag = gop.kind == SideOp::DIAG ? 1 : 0;
+                        if (op.diag && gop.param_id >= 0) {
+                            const int dd2 = 1 << gop.k;
+                            for (int r = 0; r < dd2; ++r)
+                                for (int c = 0; c < dd2; ++c)
+                                    if (r != c && gop.dgen[(size_t)r * dd2 + c] != cd(0)) op.diag = 0;
+                        }
+                        op.ang = -1;
+                        if (gop.param_id >= 0) {
+                            op.dg = stage(om[side][ri].dg, gop.k);
+                            op.ang = ps.n_ang++;
+                            tocc.push_back(occ_of[side][ri]);
+                        }
+                        to.push_back(op);
+                    }
+                    r.op_end = (int)to.size();
+                    tu.push_back(r);
+                }
+                ps.unit_end = (int)tu.size();
+                ps.n_mat = (int32_t)(tmats.size() - (size_t)ps.mat_begin);
+                tpass[side].push_back(ps);
+            }
+        }
+    }
+    AdjTileUnit* tu_d = reinterpret_cast<AdjTileUnit*>(base + Lo.adj_tiles);
+    AdjTileOp* to_d = reinterpret_cast<AdjTileOp*>(base + Lo.adj_tiles + align256(tu.size() * sizeof(AdjTileUnit)));
+    int64_t* tocc_d = reinterpret_cast<int64_t*>(reinterpret_cast<unsigned char*>(to_d) +
+                                                 align256(to.size() * sizeof(AdjTileOp)));
+    V* tmats_d = reinterpret_cast<V*>(reinterpret_cast<unsigned char*>(tocc_d) + align256(tocc.size() * sizeof(int64_t)));
+    std::vector<V> tmats_v;
+    to_dev<T>(tmats, tmats_v);
+    if (!tu.empty()) {
+        if (align256(tu.size() * sizeof(AdjTileUnit)) + align256(to.size() * sizeof(AdjTileOp)) +
+                align256(tocc.size() * sizeof(int64_t)) + tmats_v.size() * sizeof(V) > Lo.adj_tiles_bytes)
+            return fail(HSF_E_ARG, "internal: adjoint tile tables exceed their workspace");
+        if ((s = hip_check(hipMemcpyAsync(tmats_d, tmats_v.data(), tmats_v.size() * sizeof(V), hipMemcpyHostToDevice,
+                                          st),
+                           "upload tile matrices")) != HSF_OK)
+            return s;
+        if ((s = hip_check(hipMemcpyAsync(tu_d, tu.data(), tu.size() * sizeof(AdjTileUnit), hipMemcpyHostToDevice, st),
+                           "upload tile units")) != HSF_OK ||
+            (s = hip_check(hipMemcpyAsync(to_d, to.data(), to.size() * sizeof(AdjTileOp), hipMemcpyHostToDevice, st),
+                           "upload tile ops")) != HSF_OK)
+            return s;
+        if (!tocc.empty() &&
+            (s = hip_check(hipMemcpyAsync(tocc_d, tocc.data(), tocc.size() * sizeof(int64_t), hipMemcpyHostToDevice, st),
+                           "upload tile occurrences")) != HSF_OK)
+            return s;
+        for (int side = 0; side < 2; ++side)
+            if (!tpass[side].empty()) {
+                const size_t shm = 2 * ((size_t)1 << tbits[side]) * sizeof(V) +
+                                   (size_t)kTileMaxAngles * kTileWaves * sizeof(double2) + kTileMatBytes;
+                if ((s = hip_check(hipFuncSetAttribute((const void*)bw_adj_tile<T>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm),
+                                   "hipFuncSetAttribute")) != HSF_OK)
+                    return s;
+            }
+    }
+
     Runner<T> R{p, st};
     hipLaunchKernelGGL(bw_zero_doubles, dim3(std::max<uint32_t>(1, (uint32_t)((n_params + 255) / 256))), dim3(256), 0, st,
                        grad, n_params);
@@ -1016,6 +1514,46 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
         }
     }
 
+    // ---- angles inside blocks: amplitude shift rule on the re-factored block.
+    // The shifted forwards need only the coefficients c_j and the re-factored
+    // blocks.  They run in batches of Lo.reps copies of one forward run (the
+    // same launches, each copy with its own block's factors at the shifted
+    // angle) on a stream of their own (default priority), which starts once
+    // the coefficients are on the device, beside the adjoint pass on the
+    // caller's stream.  The guard drains that stream and the caller's (host
+    // staging buffers declared above may still be read) and destroys it on
+    // every exit.
+    struct ShiftStream {
+        hipStream_t st = nullptr, caller = nullptr;
+        std::vector<hipEvent_t> evs;
+        hsf_status record(hipStream_t on, hipEvent_t* out) {
+            hipEvent_t e = nullptr;
+            hsf_status r = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+            if (r != HSF_OK) return r;
+            evs.push_back(e);
+            *out = e;
+            return hip_check(hipEventRecord(e, on), "hipEventRecord");
+        }
+        ~ShiftStream() {
+            if (caller) (void)hipStreamSynchronize(caller);
+            if (st) {
+                (void)hipStreamSynchronize(st);
+                (void)hipStreamDestroy(st);
+            }
+            for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        }
+    } ss;
+    ss.caller = st;
+    if (ns > 0) {
+        if ((s = hip_check(hipMemcpyAsync(shift_t_d, shift_ids.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice, st),
+                           "upload shift ids")) != HSF_OK)
+            return s;
+        hipEvent_t start = nullptr;
+        if ((s = ss.record(st, &start)) != HSF_OK ||
+            (s = hip_check(hipStreamCreateWithFlags(&ss.st, hipStreamNonBlocking), "hipStreamCreate")) != HSF_OK ||
+            (s = hip_check(hipStreamWaitEvent(ss.st, start, 0), "hipStreamWaitEvent")) != HSF_OK)
+            return s;
+    }
     // ---- adjoint over angles outside blocks
     const int64_t* gt[2][4];
     for (int side = 0; side < 2; ++side)
@@ -1063,16 +1601,30 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
             }
         }
         // backward sweep
-        int64_t occ = 0;
         for (int side = 0; side < 2; ++side) {
             const auto& raw = p.side[side].raw;
-            int64_t occ_side = occ;
-            for (const SideOp& o : raw) occ += o.param_id >= 0;
-            int64_t oc = occ;                 // occurrences are numbered in program order
             int kc = 0;
             for (const SideOp& o : raw) kc += o.kind == SideOp::SLOT;
-            for (const AdjUnit& u : units[side]) {
-                const int ii = u.hi;
+            size_t tg = 0;                    // next tile pass of this side
+            for (size_t ui = 0; ui < units[side].size(); ++ui) {
+                const AdjUnit& u = units[side][ui];
+                const int ii = u.ops[0];
+                if (tg < tgroups[side].size() && (size_t)tgroups[side][tg].u_begin == ui) {
+                    // a tile pass over this and the following run units
+                    const AdjTilePass& ps = tpass[side][tg];
+                    const uint32_t n_tiles = 1u << (nq[side] - ps.L);
+                    if (ps.n_ang > 0 && (int64_t)n_tiles > Lo.per_row_max)
+                        return fail(HSF_E_ARG, "internal: more adjoint tiles per row than partial slots");
+                    const size_t shm = 2 * ((size_t)1 << ps.L) * sizeof(V) +
+                                       (size_t)kTileMaxAngles * kTileWaves * sizeof(double2) + kTileMatBytes;
+                    hipLaunchKernelGGL(bw_adj_tile<T>, dim3((uint32_t)(np * n_tiles)), dim3(kTileThreads), shm, st,
+                                       vS[side], lS[side], dim[side], ps, tu_d, to_d, tmats_d, tocc_d, partial,
+                                       pstride, n_tiles);
+                    if ((s = hip_check(hipGetLastError(), "bw_adj_tile launch")) != HSF_OK) return s;
+                    ui = (size_t)tgroups[side][tg].u_end - 1;
+                    ++tg;
+                    continue;
+                }
                 const SideOp& o = raw[(size_t)ii];
                 if (u.kind == 1) {
                     if (o.param_id >= 0) return fail(HSF_E_ARG, "internal: an angle on a factor slot");
@@ -1086,9 +1638,9 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
                 if (u.kind == 2) {
                     if (o.param_id >= 0) {
                         // the angle's term from the state and adjoint after the gate, then the gate undone
-                        --oc;
                         s = R.apply2_grad(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].inv,
-                                          mats + om[side][ii].tr, mats + om[side][ii].dg, partial + oc * pstride);
+                                          mats + om[side][ii].tr, mats + om[side][ii].dg,
+                                          partial + occ_of[side][(size_t)ii] * pstride);
                     } else {
                         s = R.apply2(vS[side], lS[side], dim[side], np, nq[side], o, mats + om[side][ii].inv,
                                      mats + om[side][ii].tr);
@@ -1096,32 +1648,8 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
                     if (s != HSF_OK) return s;
                     continue;
                 }
-                // a run of gates in registers, each angle's term at its gate
-                AdjRun a{};
-                a.n_ops = u.n;
-                Bits bits{};
-                for (int t = 0; t < u.K; ++t) bits.b[t] = u.q[t];
-                for (int t = 0; t < u.n; ++t) {
-                    const SideOp& g = raw[(size_t)(ii - t)];
-                    a.k[t] = g.k;
-                    for (int e = 0; e < g.k; ++e) {
-                        int pos = 0;
-                        while (u.q[pos] != g.q[e]) ++pos;
-                        a.rb[t][e] = u.K - 1 - pos;
-                    }
-                    a.inv[t] = mats + om[side][(size_t)(ii - t)].inv;
-                    a.tr[t] = mats + om[side][(size_t)(ii - t)].tr;
-                    a.dg[t] = nullptr;
-                    a.partial[t] = nullptr;
-                    if (g.param_id >= 0) {
-                        --oc;
-                        a.dg[t] = mats + om[side][(size_t)(ii - t)].dg;
-                        a.partial[t] = partial + oc * pstride;
-                    }
-                }
-                if ((s = R.adj_run(vS[side], lS[side], dim[side], np, nq[side], bits, u.K, a)) != HSF_OK) return s;
+                return fail(HSF_E_ARG, "internal: a register run outside every adjoint tile pass");
             }
-            (void)occ_side;
         }
         if (p.n_params > 0) {
             hipLaunchKernelGGL(bw_reduce, dim3((uint32_t)p.n_params), dim3(256), 0, st, (const double2*)partial, pstride,
@@ -1130,198 +1658,49 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
         }
     }
 
-    // ---- angles inside blocks: amplitude shift rule on the re-factored block
-    bool any = false;
-    for (const Block& b : p.blocks) any |= !b.params.empty();
-    std::vector<V> staged;    // host copy of the shifted pools; must outlive the upload (final sync)
-    if (any) {
-        // device pools of every schedule (flat, then path-tree), to be
-        // patched per shifted block
-        std::vector<std::vector<size_t>> pool_at(4);
-        size_t o = 0;
-        for (int side = 0; side < 2; ++side)
-            for (int tr = 0; tr < 2; ++tr)
-                for (const Schedule& sc : tr ? p.side[side].tree : p.side[side].sched) {
-                    pool_at[2 * side + tr].push_back(o);
-                    o += std::max<size_t>(sc.pool.size(), 1);
-                }
-        const double pi = 2.0 * std::acos(0.0);
-        struct Shift {
-            size_t k;
-            int64_t gid;
-            int t;
-        };
-        std::vector<Shift> shifts;
-        for (size_t k = 0; k < p.blocks.size(); ++k)
-            for (const auto& gp : p.blocks[k].params)
-                if (gp.second < n_params) shifts.push_back({k, gp.first, gp.second});
-        const size_t ns = shifts.size();
-        // every shifted block re-factored on the host, in parallel (they are
-        // independent), into its own patched copy of the pools
-        staged.assign(ns * Lo.pool_elems, V{});
-        std::vector<hsf_status> hst(ns, HSF_OK);
-        std::vector<std::string> herr(ns);
-        auto refactor = [&](size_t i) {
-            const Shift& sh = shifts[i];
-            const Block& b = p.blocks[sh.k];
-            Factors fs;
-            const double ang = p.gates[sh.gid].param + pi;
-            hsf_status e = factor_block(p, b, sh.gid, ang, fs);
-            if (e != HSF_OK) {
-                hst[i] = e;
-                herr[i] = hsf::g_last_error_copy();
-                return;
-            }
-            const int r = fs.rank;
-            if (r > b.rank) {
-                hst[i] = HSF_E_UNSUPPORTED;
-                herr[i] = "a shifted block has a larger Schmidt rank than the plan's";
-                return;
-            }
-            if (fs.product != b.product || fs.pa.size() != b.pa.size() || fs.pb.size() != b.pb.size()) {
-                hst[i] = HSF_E_UNSUPPORTED;
-                herr[i] = "a shifted block changes its decomposition form";
-                return;
-            }
-            // patched pools: factors of block k replaced (missing ranks zero)
-            std::vector<cd> all;
-            all.reserve(Lo.pool_elems);
-            for (int side = 0; side < 2; ++side) {
-                const std::vector<FactorPiece>& pcs = side == 0 ? fs.pa : fs.pb;
-                for (int tr = 0; tr < 2; ++tr)
-                for (const Schedule& sc : tr ? p.side[side].tree : p.side[side].sched) {
-                    std::vector<cd> pl = sc.pool;
-                    for (const DevOp& op : sc.devops)
-                        if (op.type == DOP_SLOT && op.block == (int)sh.k) {
-                            const std::vector<cd>& f = pcs[op.piece].m;
-                            const size_t d2 = (size_t)1 << (2 * op.k);
-                            for (int m = 0; m < b.rank; ++m)
-                                for (size_t e2 = 0; e2 < d2; ++e2)
-                                    pl[op.mat + m * d2 + e2] = m < r ? f[m * d2 + e2] : cd(0);
-                        }
-                    // one-qubit factor pieces applied inside register groups
-                    for (const SubOp& so : sc.subs)
-                        if (so.type == SUB_SLOT1 && so.block == (int)sh.k) {
-                            const std::vector<cd>& f = pcs[so.piece].m;
-                            for (int m = 0; m < b.rank; ++m)
-                                for (size_t e2 = 0; e2 < 4; ++e2)
-                                    pl[so.mat + m * 4 + e2] = m < r ? f[m * 4 + e2] : cd(0);
-                        }
-                    if (pl.empty()) pl.push_back(cd(0));
-                    all.insert(all.end(), pl.begin(), pl.end());
-                }
-            }
-            std::vector<V> av;
-            to_dev<T>(all, av);
-            std::copy(av.begin(), av.end(), staged.begin() + i * Lo.pool_elems);
-        };
-        {
-            const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-            const size_t nthr = std::min<size_t>(ns, std::min(16u, hw));
-            std::atomic<size_t> next(0);
-            std::vector<std::thread> pool_threads;
-            for (size_t w = 0; w < nthr; ++w)
-                pool_threads.emplace_back([&]() {
-                    for (size_t i = next++; i < ns; i = next++) refactor(i);
-                });
-            for (std::thread& th : pool_threads) th.join();
-        }
+    if (ns > 0) {
+        workers.join();
         for (size_t i = 0; i < ns; ++i)
             if (hst[i] != HSF_OK) return fail(hst[i], herr[i]);
         // one upload for all shifted pools (the host copy lives until the final sync)
-        if ((s = hip_check(hipMemcpyAsync(pools, staged.data(), staged.size() * sizeof(V), hipMemcpyHostToDevice, st),
+        if ((s = hip_check(hipMemcpyAsync(pools, staged.data(), staged.size() * sizeof(V), hipMemcpyHostToDevice,
+                                          ss.st),
                            "upload shifted factors")) != HSF_OK)
             return s;
-        // shift i runs on lane i mod lanes: lane 0 on the caller's stream with
-        // the buffers above, the others on streams of their own (default
-        // priority) that start after everything queued so far
-        const int nl = (int)std::max<size_t>(1, std::min<size_t>((size_t)Lo.lanes, ns));
-        struct Lane {
-            hipStream_t st;
-            V* v[2];
-            double2* psi;
-            unsigned char* tree;
-        };
-        std::vector<Lane> lanes((size_t)nl);
-        std::vector<hipEvent_t> evs;
-        auto cleanup = [&]() {
-            for (size_t l = 1; l < lanes.size(); ++l)
-                if (lanes[l].st) (void)hipStreamDestroy(lanes[l].st);
-            for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-        };
-        lanes[0] = {st, {vS[0], vS[1]}, psi_s, base + Lo.tree};
-        hipEvent_t start = nullptr;
-        if (nl > 1) {
-            if ((s = hip_check(hipEventCreateWithFlags(&start, hipEventDisableTiming), "hipEventCreate")) != HSF_OK)
-                return s;
-            evs.push_back(start);
-            if ((s = hip_check(hipEventRecord(start, st), "hipEventRecord")) != HSF_OK) {
-                cleanup();
-                return s;
-            }
-        }
-        for (int l = 1; l < nl; ++l) {
-            unsigned char* lb = base + Lo.lane + (size_t)(l - 1) * Lo.lane_bytes;
-            Lane& ln = lanes[(size_t)l];
-            ln.st = nullptr;
-            ln.v[0] = (V*)lb;
-            lb += align256((size_t)chunk * dim[0] * sizeof(V));
-            ln.v[1] = (V*)lb;
-            lb += align256((size_t)chunk * dim[1] * sizeof(V));
-            ln.psi = (double2*)lb;
-            lb += align256((size_t)nx * 16);
-            ln.tree = lb;
-            if ((s = hip_check(hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking), "hipStreamCreate")) != HSF_OK ||
-                (s = hip_check(hipStreamWaitEvent(ln.st, start, 0), "hipStreamWaitEvent")) != HSF_OK) {
-                cleanup();
-                return s;
-            }
-        }
+        V* repS[2] = {(V*)(base + Lo.repA), (V*)(base + Lo.repB)};
+        double2* rpsi = (double2*)(base + Lo.rep_psi);
         DeviceCopy dd = d;
-        for (size_t i = 0; i < ns && s == HSF_OK; ++i) {
-            const Lane& ln = lanes[i % (size_t)nl];
+        for (size_t i0 = 0; i0 < ns; i0 += (size_t)Lo.reps) {
+            // shifts i0 .. i0 + R - 1: copy r reads the pools of shift i0 + r
+            const int R = (int)std::min<size_t>((size_t)Lo.reps, ns - i0);
             for (int side = 0; side < 2; ++side)
                 for (int tr = 0; tr < 2; ++tr) {
                     std::vector<DeviceSchedule>& dv = tr ? dd.tree[side] : dd.side[side];
-                    for (size_t q = 0; q < dv.size(); ++q) dv[q].pool = pools + i * Lo.pool_elems + pool_at[2 * side + tr][q];
+                    for (size_t q = 0; q < dv.size(); ++q)
+                        if (used_sched[2 * side + tr][q])
+                            dv[q].pool = pools + i0 * Lo.pool_elems + pool_at[2 * side + tr][q];
                 }
-            for (int64_t p0 = 0; p0 < p.P && s == HSF_OK; p0 += chunk) {
+            const SweepReplicas rp{R, (int64_t)Lo.pool_elems, {chunk * dim[0], chunk * dim[1]}, Lo.rep_tree_bytes};
+            for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
                 const int64_t np = std::min(chunk, p.P - p0);
-                s = run_sides(p, dd, p0, np, ln.v[0], dim[0], ln.v[1], dim[1], ln.tree, Lo.tree_bytes, ln.st);
-                if (s == HSF_OK)
-                    s = gather_dot(p.dtype, ln.v[0], dim[0], ln.v[1], dim[1], np, p.nb, p.n, x, nx, ln.psi,
-                                   p0 > 0 ? 1 : 0, ln.st);
+                if ((s = run_sides(p, dd, p0, np, repS[0], dim[0], repS[1], dim[1], base + Lo.rep_tree, Lo.tree_bytes,
+                                   ss.st, &rp)) != HSF_OK ||
+                    (s = gather_dot(p.dtype, repS[0], dim[0], repS[1], dim[1], np, p.nb, p.n, x, nx, rpsi,
+                                    p0 > 0 ? 1 : 0, ss.st, R, chunk * dim[0], chunk * dim[1])) != HSF_OK)
+                    return s;
             }
-            if (s != HSF_OK) break;
-            hipLaunchKernelGGL(bw_shift_dot, dim3(1), dim3(256), 0, ln.st, (const double2*)psi_x,
-                               (const double2*)ln.psi, nx, lossb + i);
-            s = hip_check(hipGetLastError(), "bw_shift_dot launch");
+            hipLaunchKernelGGL(bw_shift_dot, dim3((uint32_t)R), dim3(256), 0, ss.st, (const double2*)psi_x,
+                               (const double2*)rpsi, nx, lossb + i0);
+            if ((s = hip_check(hipGetLastError(), "bw_shift_dot launch")) != HSF_OK) return s;
         }
-        // the caller's stream waits for every lane before combining
-        for (int l = 1; l < nl && s == HSF_OK; ++l) {
-            hipEvent_t e = nullptr;
-            if ((s = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate")) != HSF_OK) break;
-            evs.push_back(e);
-            if ((s = hip_check(hipEventRecord(e, lanes[(size_t)l].st), "hipEventRecord")) != HSF_OK ||
-                (s = hip_check(hipStreamWaitEvent(st, e, 0), "hipStreamWaitEvent")) != HSF_OK)
-                break;
-        }
-        if (s != HSF_OK) {
-            for (int l = 1; l < nl; ++l)
-                if (lanes[(size_t)l].st) (void)hipStreamSynchronize(lanes[(size_t)l].st);
-            cleanup();
+        // the caller's stream waits for the shifted runs, then dL/dt +=
+        // Re sum_j conj(c_j) psi_j(t + pi) per occurrence, in plan order
+        hipEvent_t done = nullptr;
+        if ((s = ss.record(ss.st, &done)) != HSF_OK ||
+            (s = hip_check(hipStreamWaitEvent(st, done, 0), "hipStreamWaitEvent")) != HSF_OK)
             return s;
-        }
-        // dL/dt += Re sum_j conj(c_j) psi_j(t + pi) per occurrence, in plan order
-        for (size_t i = 0; i < ns && s == HSF_OK; ++i) {
-            hipLaunchKernelGGL(bw_shift_add, dim3(1), dim3(1), 0, st, lossb + i, grad, (int64_t)shifts[i].t);
-            s = hip_check(hipGetLastError(), "bw_shift_add launch");
-        }
-        // the lanes' streams go once the caller's stream has drained them
-        const hsf_status sync = hip_check(hipStreamSynchronize(st), "sync");
-        cleanup();
-        if (s != HSF_OK) return s;
-        return sync;
+        hipLaunchKernelGGL(bw_shift_add, dim3(1), dim3(1), 0, st, lossb, shift_t_d, (int64_t)ns, grad);
+        if ((s = hip_check(hipGetLastError(), "bw_shift_add launch")) != HSF_OK) return s;
     }
     // host staging buffers above must outlive their async uploads
     return hip_check(hipStreamSynchronize(st), "sync");
@@ -1329,7 +1708,9 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
 
 }  // namespace
 
-size_t backward_workspace(const Plan& p, int64_t chunk, int64_t nx) { return layout(p, chunk, nx).total; }
+size_t backward_workspace(const Plan& p, int64_t chunk, int64_t nx, bool minimal) {
+    return layout(p, chunk, nx, minimal ? 1 : 0).total;
+}
 
 // hsf_loss: half-states of both sides per path chunk, then psi(x_j)
 // accumulated over the chunks (FP64), then L = sum_j |psi(x_j)|^2.

@@ -9,13 +9,27 @@ namespace hsf {
 
 constexpr size_t kNormWsDoubles = 8192;
 
+// R copies of one forward run in the same launches, which differ only in
+// their factor pools and buffers: copy r reads every schedule's pool at
+// pool + r pool_rs, writes its half-states at psi + r psi_rs[side] (strides
+// in complex elements) and keeps its path-tree levels at ws + r ws_rs bytes
+// (a multiple of 256, each copy's share at least tree_workspace bytes).
+struct SweepReplicas {
+    int R;
+    int64_t pool_rs;
+    int64_t psi_rs[2];
+    size_t ws_rs;
+};
+
 // Runs both sides' programs (a side with a null pointer is skipped) for
 // paths [p_begin, p_begin + n_paths), one launch per LDS pass.
 // Half-states of paths [p_begin, p_begin + n_paths) into psiA / psiB (either
 // may be null).  ws: tree_workspace(p, n_paths) bytes for the path-tree
-// levels; with less (or null) every path runs every per-path op.
+// levels; with less (or null) every path runs every per-path op.  reps: the
+// run's copies (null: one).
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
-                     void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream);
+                     void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream,
+                     const SweepReplicas* reps = nullptr);
 size_t tree_workspace(const Plan& p, int64_t n_paths);
 
 // How a sweep launch row finds its input.  ROW_INPLACE: its own row.
@@ -126,14 +140,21 @@ hsf_status amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA, const
                            int64_t n_paths, int64_t row_begin, int64_t row_end, void* out, int64_t ldo, int32_t mode,
                            int32_t accumulate, void* ws, size_t ws_bytes, hipStream_t stream);
 
+// psi(x_j) = sum over the K paths of A[p][x_j >> nb] B[p][x_j mod 2^nb]
+// (FP64 sums), into out[j] (added to it with accumulate).  copies > 1: the
+// same for replicated half-states, copy r at A + r rsA, B + r rsB (elements)
+// into out + r nx.
 hsf_status gather_dot(int dtype, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K,
                       int nb, int n, const uint64_t* x, int64_t nx, void* out, int accumulate,
-                      hipStream_t stream);
+                      hipStream_t stream, int copies = 1, int64_t rsA = 0, int64_t rsB = 0);
 
 hsf_status norm2(const void* a, int adt, const void* b, int bdt, int64_t n, double* out, double* ws,
                  hipStream_t stream);
 
-size_t backward_workspace(const Plan& p, int64_t chunk, int64_t nx);
+// Workspace of hsf_backward: the preferred size (shifted forward runs in
+// batches of as many copies as fit a fixed budget), or the minimal one (one
+// copy per batch).
+size_t backward_workspace(const Plan& p, int64_t chunk, int64_t nx, bool minimal = false);
 // dl_dpsi: n x complex128 cotangents on the device, or null for the
 // probability mass
 hsf_status backward(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, const void* dl_dpsi, double* grad,

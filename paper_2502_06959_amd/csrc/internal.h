@@ -294,6 +294,11 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
 // with the rank under the plan's tolerance.  A block that qualifies for the
 // product form gets it; others need at most kMaxSideQubits per side.
 hsf_status factor_block(const Plan& p, const Block& b, int64_t gate_id, double param, Factors& f);
+// factor_block for a block whose Schmidt rank is at most `rank` (a gate moved
+// to another angle): range finder with `rank` probes and an r x cols SVD
+// instead of the full decomposition, checked by reconstruction (falls back to
+// factor_block when the check fails).
+hsf_status factor_block_rank(const Plan& p, const Block& b, int64_t gate_id, double param, int rank, Factors& f);
 // Dense side factors (rank x d x d) from the pieces; empty if the side has
 // more than kMaxExpandSide qubits.
 void expand_factors(const Block& b, const Factors& f, std::vector<cd>& xa, std::vector<cd>& yb);

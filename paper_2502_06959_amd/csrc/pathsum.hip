@@ -191,10 +191,15 @@ template <typename VIN>
 __global__ __launch_bounds__(256) void gather_dot_kernel(const VIN* __restrict__ A, int64_t ldA,
                                                          const VIN* __restrict__ B, int64_t ldB, int64_t K,
                                                          int nb, int n, const uint64_t* __restrict__ x, int64_t nx,
-                                                         double2* __restrict__ out, int accumulate) {
+                                                         double2* __restrict__ out, int accumulate, int64_t rsA,
+                                                         int64_t rsB) {
     const int lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (j >= nx) return;
+    // copy blockIdx.y of replicated half-states (strides rsA, rsB elements), its own nx outputs
+    A += (int64_t)blockIdx.y * rsA;
+    B += (int64_t)blockIdx.y * rsB;
+    out += (int64_t)blockIdx.y * nx;
     // index bits at or above n are ignored, so every read stays inside the half-states
     const uint64_t xj = x[j] & ((n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1));
     const int64_t ia = (int64_t)(xj >> nb);
@@ -389,15 +394,17 @@ hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void*
 }
 
 hsf_status gather_dot(int dtype, const void* A, int64_t ldA, const void* B, int64_t ldB, int64_t K, int nb, int n,
-                      const uint64_t* x, int64_t nx, void* out, int accumulate, hipStream_t st) {
+                      const uint64_t* x, int64_t nx, void* out, int accumulate, hipStream_t st, int copies,
+                      int64_t rsA, int64_t rsB) {
     const int waves = 4;
-    const dim3 grid((uint32_t)((nx + waves - 1) / waves));
+    if (copies < 1 || copies > 65535) return fail(HSF_E_ARG, "internal: replica count out of range");
+    const dim3 grid((uint32_t)((nx + waves - 1) / waves), (uint32_t)copies);
     if (dtype == HSF_C64)
         hipLaunchKernelGGL(gather_dot_kernel<float2>, grid, dim3(64 * waves), 0, st, (const float2*)A, ldA,
-                           (const float2*)B, ldB, K, nb, n, x, nx, (double2*)out, accumulate);
+                           (const float2*)B, ldB, K, nb, n, x, nx, (double2*)out, accumulate, rsA, rsB);
     else
         hipLaunchKernelGGL(gather_dot_kernel<double2>, grid, dim3(64 * waves), 0, st, (const double2*)A, ldA,
-                           (const double2*)B, ldB, K, nb, n, x, nx, (double2*)out, accumulate);
+                           (const double2*)B, ldB, K, nb, n, x, nx, (double2*)out, accumulate, rsA, rsB);
     return hip_check(hipGetLastError(), "gather_dot launch");
 }
 

@@ -2,12 +2,14 @@
 // kernels in pathsum.hip and bf16x3.hip read their operands straight from
 // global memory, which suits a few dozen paths (the sum is then bound by the
 // output write).  With thousands of paths the sum is bound by MFMA
-// throughput, and operand reuse decides: here each 128 x 128 output tile
-// stages a chunk of paths of its 128 A rows and 128 B columns in LDS (double
-// buffered: the next chunk is fetched into registers while the current one
-// feeds the MFMAs), so each operand byte fetched from L2 serves 128 outputs.
-// The MFMA sequence per output block is the same as the streaming kernels',
-// so both give bit-identical results.
+// throughput, and operand reuse decides: here each output tile stages a
+// chunk of paths of its A rows and B columns in LDS, so each operand byte
+// fetched from L2 serves 128 or more outputs.  FP32 and FP64: 128 x 128 (64 x
+// 64) tiles, double buffered through registers (the next chunk is fetched
+// while the current one feeds the MFMAs).  Split-BF16 x3: 256 x 128 tiles,
+// chunks copied straight into three LDS stages by DMA loads.  The FP32
+// kernel runs the streaming FP32 kernel's MFMA sequence per output block, so
+// both give bit-identical results.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -199,15 +199,11 @@ hsf_status try_product(const Plan& p, const Block& blk, int64_t gate_id, double 
 
 }  // namespace
 
-hsf_status factor_block(const Plan& p, const Block& blk, int64_t gate_id, double param, Factors& f) {
+// The block operator with gate `gate_id` at `param` (gate_id < 0: unchanged),
+// reshaped for the operator-Schmidt decomposition (Sec. IV-A): rows (i_b,
+// j_b), columns (i_a, j_a).
+static void reshaped_block(const Plan& p, const Block& blk, int64_t gate_id, double param, std::vector<cd>& At) {
     const int ka = (int)blk.sa.size(), kb = (int)blk.sb.size(), nl = ka + kb;
-    f = Factors();
-    bool taken = false;
-    hsf_status ps = try_product(p, blk, gate_id, param, f, taken);
-    if (ps != HSF_OK || taken) return ps;
-    if (ka > p.max_side || kb > p.max_side)
-        return fail(HSF_E_BLOCK_TOO_LARGE, "support " + std::to_string(ka) + "|" + std::to_string(kb) +
-                                               " exceeds the per-side limit of SVD-factored blocks");
     const int da = 1 << ka, db = 1 << kb, d = 1 << nl;
     int local[64];
     for (int i = 0; i < kb; ++i) local[blk.sb[i]] = i;
@@ -226,25 +222,26 @@ hsf_status factor_block(const Plan& p, const Block& blk, int64_t gate_id, double
         }
         left_multiply(U, nl, lb, g.nq, *m);
     }
-    // reshape: rows (i_b, j_b), columns (i_a, j_a)
     const int rows = db * db, cols = da * da;
-    std::vector<cd> At((size_t)rows * cols);
+    At.assign((size_t)rows * cols, cd(0));
     for (int ia = 0; ia < da; ++ia)
         for (int ib = 0; ib < db; ++ib)
             for (int ja = 0; ja < da; ++ja)
                 for (int jb = 0; jb < db; ++jb)
                     At[(size_t)(ib * db + jb) * cols + (ia * da + ja)] = U[(size_t)(ia * db + ib) * d + (ja * db + jb)];
-    std::vector<cd> W, Vh;
-    jacobi_svd(rows, cols, At, W, f.sigma, Vh);
-    int r = 0;
-    hsf_status st = count_rank(p, f.sigma, r);
-    if (st != HSF_OK) return st;
-    f.rank = r;
+}
+
+// Factor pieces from a decomposition At = sum_m Y_m X_m^T with the singular
+// values folded in (Y_m = sqrt(s_m) W[:, m], X_m = sqrt(s_m) Vh[m, :]).
+static void pieces_from_svd(const Block& blk, int r, const std::vector<double>& sig, const std::vector<cd>& W,
+                            int w_ld, const std::vector<cd>& Vh, int vh_ld, Factors& f) {
+    const int ka = (int)blk.sa.size(), kb = (int)blk.sb.size();
+    const int da = 1 << ka, db = 1 << kb;
     std::vector<cd> xa((size_t)r * da * da, cd(0)), yb((size_t)r * db * db, cd(0));
     for (int m = 0; m < r; ++m) {
-        const double rt = std::sqrt(f.sigma[m]);
-        for (int e = 0; e < da * da; ++e) xa[(size_t)m * da * da + e] = rt * Vh[(size_t)m * cols + e];
-        for (int e = 0; e < db * db; ++e) yb[(size_t)m * db * db + e] = rt * W[(size_t)m * rows + e];
+        const double rt = std::sqrt(sig[m]);
+        for (int e = 0; e < da * da; ++e) xa[(size_t)m * da * da + e] = rt * Vh[(size_t)m * vh_ld + e];
+        for (int e = 0; e < db * db; ++e) yb[(size_t)m * db * db + e] = rt * W[(size_t)m * w_ld + e];
     }
     // a side with no qubit in the block carries a scalar: fold it into the other side
     if (ka == 0)
@@ -255,6 +252,103 @@ hsf_status factor_block(const Plan& p, const Block& blk, int64_t gate_id, double
             for (int e = 0; e < da * da; ++e) xa[(size_t)m * da * da + e] *= yb[m];
     if (ka > 0) f.pa.push_back(FactorPiece{blk.sa, std::move(xa)});
     if (kb > 0) f.pb.push_back(FactorPiece{blk.sb, std::move(yb)});
+}
+
+hsf_status factor_block(const Plan& p, const Block& blk, int64_t gate_id, double param, Factors& f) {
+    const int ka = (int)blk.sa.size(), kb = (int)blk.sb.size();
+    f = Factors();
+    bool taken = false;
+    hsf_status ps = try_product(p, blk, gate_id, param, f, taken);
+    if (ps != HSF_OK || taken) return ps;
+    if (ka > p.max_side || kb > p.max_side)
+        return fail(HSF_E_BLOCK_TOO_LARGE, "support " + std::to_string(ka) + "|" + std::to_string(kb) +
+                                               " exceeds the per-side limit of SVD-factored blocks");
+    std::vector<cd> At;
+    reshaped_block(p, blk, gate_id, param, At);
+    const int rows = 1 << (2 * kb), cols = 1 << (2 * ka);
+    std::vector<cd> W, Vh;
+    jacobi_svd(rows, cols, At, W, f.sigma, Vh);
+    int r = 0;
+    hsf_status st = count_rank(p, f.sigma, r);
+    if (st != HSF_OK) return st;
+    f.rank = r;
+    pieces_from_svd(blk, r, f.sigma, W, rows, Vh, cols, f);
+    return HSF_OK;
+}
+
+hsf_status factor_block_rank(const Plan& p, const Block& blk, int64_t gate_id, double param, int rank, Factors& f) {
+    const int ka = (int)blk.sa.size(), kb = (int)blk.sb.size();
+    const int rows = 1 << (2 * kb), cols = 1 << (2 * ka);
+    if (ka > p.max_side || kb > p.max_side || rank <= 0 || rank >= std::min(rows, cols))
+        return factor_block(p, blk, gate_id, param, f);
+    f = Factors();
+    bool taken = false;
+    hsf_status ps = try_product(p, blk, gate_id, param, f, taken);
+    if (ps != HSF_OK || taken) return ps;
+    std::vector<cd> At;
+    reshaped_block(p, blk, gate_id, param, At);
+    double nrm = 0;
+    for (const cd& v : At) nrm += std::norm(v);
+    nrm = std::sqrt(nrm);
+    // range of At from `rank` fixed probe vectors (a fixed integer hash gives
+    // entries in [-1, 1]; any probes in general position serve), columns of
+    // Q orthonormalised twice by modified Gram-Schmidt
+    const int r = rank;
+    std::vector<cd> Q((size_t)r * rows, cd(0));            // column m at Q[m * rows]
+    for (int m = 0; m < r; ++m)
+        for (int c = 0; c < cols; ++c) {
+            uint32_t h = (uint32_t)(m * 7919 + c) * 2654435761u;
+            h ^= h >> 15;
+            h *= 2246822519u;
+            h ^= h >> 13;
+            const cd w((double)(h & 0xffff) / 32768.0 - 1.0, (double)(h >> 16) / 32768.0 - 1.0);
+            for (int i = 0; i < rows; ++i) Q[(size_t)m * rows + i] += At[(size_t)i * cols + c] * w;
+        }
+    for (int m = 0; m < r; ++m) {
+        cd* qm = &Q[(size_t)m * rows];
+        for (int pass = 0; pass < 2; ++pass)
+            for (int k = 0; k < m; ++k) {
+                const cd* qk = &Q[(size_t)k * rows];
+                cd dot = 0;
+                for (int i = 0; i < rows; ++i) dot += std::conj(qk[i]) * qm[i];
+                for (int i = 0; i < rows; ++i) qm[i] -= dot * qk[i];
+            }
+        double n2 = 0;
+        for (int i = 0; i < rows; ++i) n2 += std::norm(qm[i]);
+        // a lower rank than the plan's: the full decomposition finds it
+        if (std::sqrt(n2) <= 1e-10 * nrm) return factor_block(p, blk, gate_id, param, f);
+        const double inv = 1.0 / std::sqrt(n2);
+        for (int i = 0; i < rows; ++i) qm[i] *= inv;
+    }
+    // B = Q^H At (r x cols), then At = Q B checked element by element
+    std::vector<cd> B((size_t)r * cols, cd(0));
+    for (int m = 0; m < r; ++m)
+        for (int i = 0; i < rows; ++i) {
+            const cd qc = std::conj(Q[(size_t)m * rows + i]);
+            for (int c = 0; c < cols; ++c) B[(size_t)m * cols + c] += qc * At[(size_t)i * cols + c];
+        }
+    double res = 0;
+    for (int i = 0; i < rows; ++i)
+        for (int c = 0; c < cols; ++c) {
+            cd v = At[(size_t)i * cols + c];
+            for (int m = 0; m < r; ++m) v -= Q[(size_t)m * rows + i] * B[(size_t)m * cols + c];
+            res += std::norm(v);
+        }
+    if (std::sqrt(res) > 1e-11 * nrm) return factor_block(p, blk, gate_id, param, f);
+    // B = Wb diag(s) Vbh (r x r, r x cols): At = (Q Wb) diag(s) Vbh
+    std::vector<cd> Wb, Vbh;
+    jacobi_svd(r, cols, B, Wb, f.sigma, Vbh);
+    int rr = 0;
+    hsf_status st = count_rank(p, f.sigma, rr);
+    if (st != HSF_OK) return st;
+    f.rank = rr;
+    std::vector<cd> W((size_t)r * rows, cd(0));             // column m of Q Wb at W[m * rows]
+    for (int m = 0; m < r; ++m)
+        for (int k = 0; k < r; ++k) {
+            const cd w = Wb[(size_t)m * r + k];
+            for (int i = 0; i < rows; ++i) W[(size_t)m * rows + i] += Q[(size_t)k * rows + i] * w;
+        }
+    pieces_from_svd(blk, rr, f.sigma, W, rows, Vbh, cols, f);
     return HSF_OK;
 }
 

@@ -96,6 +96,12 @@ struct SideArgs {
     const void* src;
     int64_t src_ld, src_lo, S_par;
     int32_t mode;
+    // Replicas of one run that differ only in their factor pools and buffers
+    // (0: n_blocks, one run): workgroup b belongs to copy r = b / rep_blocks,
+    // which reads pool + r pool_rs, writes psi + r dst_rs and (ROW_PARENT)
+    // reads src + r src_rs (strides in complex elements).
+    uint32_t rep_blocks;
+    int64_t pool_rs, dst_rs, src_rs;
 };
 
 // LDS position of tile element e: the low four index bits are XORed with the
@@ -377,22 +383,27 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideA
     const bool sd = blockIdx.x >= s0.n_blocks;
 #define HSF_SEL(f) (sd ? s1.f : s0.f)
     const uint32_t n_tiles = HSF_SEL(n_tiles);
-    const uint32_t blk = sd ? blockIdx.x - s0.n_blocks : blockIdx.x;
+    uint32_t blk = sd ? blockIdx.x - s0.n_blocks : blockIdx.x;
+    const uint32_t rb = HSF_SEL(rep_blocks);
+    const uint32_t r = rb ? blk / rb : 0u;
+    blk -= r * rb;
     const uint32_t pl = blk / n_tiles;
     const uint32_t t = blk - pl * n_tiles;
     const int64_t i = HSF_SEL(i_lo) + (int64_t)pl;
     const int64_t S = HSF_SEL(S);
     const int64_t path = max(i * S, HSF_SEL(p0));
-    V* st = reinterpret_cast<V*>(HSF_SEL(psi)) + (i - HSF_SEL(dst_lo)) * HSF_SEL(ld);
+    V* st = reinterpret_cast<V*>(HSF_SEL(psi)) + (int64_t)r * HSF_SEL(dst_rs) + (i - HSF_SEL(dst_lo)) * HSF_SEL(ld);
     const V* src = st;
     const int32_t mode = HSF_SEL(mode);
     if (mode == ROW_SHARED)
         src = reinterpret_cast<const V*>(HSF_SEL(src));
     else if (mode == ROW_PARENT)
-        src = reinterpret_cast<const V*>(HSF_SEL(src)) + ((i * S) / HSF_SEL(S_par) - HSF_SEL(src_lo)) * HSF_SEL(src_ld);
+        src = reinterpret_cast<const V*>(HSF_SEL(src)) + (int64_t)r * HSF_SEL(src_rs) +
+              ((i * S) / HSF_SEL(S_par) - HSF_SEL(src_lo)) * HSF_SEL(src_ld);
     sweep_tile<T, KG, S1>(as_table(HSF_SEL(pass)), as_table(HSF_SEL(ops)),
                           as_table(reinterpret_cast<const DSub<T>*>(HSF_SEL(subs))),
-                          reinterpret_cast<const V*>(HSF_SEL(pool)), st, src, t, path, reinterpret_cast<V*>(smem_raw));
+                          reinterpret_cast<const V*>(HSF_SEL(pool)) + (int64_t)r * HSF_SEL(pool_rs), st, src, t,
+                          path, reinterpret_cast<V*>(smem_raw));
 #undef HSF_SEL
 }
 
@@ -761,9 +772,13 @@ size_t tree_workspace(const Plan& p, int64_t n_paths) {
 }
 
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
-                     void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream) {
+                     void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream,
+                     const SweepReplicas* reps) {
     const bool dbl = p.dtype == HSF_C128;
     const size_t esz = dbl ? 16 : 8;
+    const int64_t R = reps ? std::max(1, reps->R) : 1;
+    if (R > 1 && (reps->ws_rs % esz != 0 || reps->ws_rs % 256 != 0))
+        return fail(HSF_E_ARG, "internal: replica workspace stride not a multiple of 256 bytes");
     // the path tree when it pays and the caller's workspace holds its levels
     SweepChoice ch = choose_sweep(p, n_paths);
     TreeScratch tsc;
@@ -797,7 +812,7 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
     int64_t tiles_max = 1;
     for (int s = 0; s < 2; ++s)
         for (const SweepItem& it : items[s]) tiles_max = std::max<int64_t>(tiles_max, int64_t(1) << sc[s]->passes[it.k].n_nonlocal);
-    const int64_t max_rows = std::max<int64_t>(1, (int64_t(1) << 29) / tiles_max);
+    const int64_t max_rows = std::max<int64_t>(1, (int64_t(1) << 29) / (tiles_max * R));
     for (size_t j = 0; j < rounds; ++j) {
         SideArgs a[2];
         std::memset(a, 0, sizeof(a));
@@ -825,6 +840,13 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
             a[s].src_lo = m.src_lo;
             a[s].S_par = m.S_par;
             a[s].mode = m.mode;
+            if (R > 1) {
+                // the last level writes the caller's rows, the others a copy's tree levels
+                const int64_t lvl_rs = (int64_t)(reps->ws_rs / esz);
+                a[s].pool_rs = reps->pool_rs;
+                a[s].dst_rs = m.dst == psi[s] ? reps->psi_rs[s] : lvl_rs;
+                a[s].src_rs = m.mode == ROW_PARENT ? lvl_rs : 0;
+            }
             emax = std::max(emax, 1u << ps.n_local);
             rows_max = std::max(rows_max, m.rows);
         }
@@ -843,7 +865,8 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
                 if (!b[s].pass) continue;
                 const int64_t nr = std::max<int64_t>(0, std::min(max_rows, it[s]->rows - r0));
                 b[s].i_lo = it[s]->i_lo + r0;
-                b[s].n_blocks = (uint32_t)(nr * b[s].n_tiles);
+                b[s].rep_blocks = (uint32_t)(nr * b[s].n_tiles);
+                b[s].n_blocks = (uint32_t)(nr * b[s].n_tiles * R);
                 if (nr == 0) b[s].pass = nullptr;
             }
             // a side with no pass this round contributes no workgroups

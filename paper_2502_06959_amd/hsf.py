@@ -321,18 +321,27 @@ class Plan:
         hsf_amplitudes_bitstrings(self.handle, psiA, psiB, n_paths, x, out, accumulate)
         return out
 
-    def backward(self, x, chunk=None, grad=None, dl_dpsi=None):
+    def backward(self, x, chunk=None, grad=None, dl_dpsi=None, ws=None):
         """dL/dt for every parameter id (float64 tensor of n_params entries).
         x: device tensor of basis-state indices.  dl_dpsi: None for L =
         sum_j |psi(x_j)|^2, else complex128 cotangents dL/dRe psi(x_j) +
-        i dL/dIm psi(x_j)."""
+        i dL/dIm psi(x_j).  ws: a uint8 device workspace of at least
+        workspace_backward(..., minimal=True) bytes (default: the preferred
+        size)."""
         chunk = min(self.P, 256) if chunk is None else chunk
-        nbytes = hsf_workspace_size(self.handle, 2, chunk, x.numel())
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        if ws is None:
+            ws = torch.empty(self.workspace_backward(x.numel(), chunk), dtype=torch.uint8, device=x.device)
         if grad is None:
             grad = torch.zeros(max(self.n_params, 1), dtype=torch.float64, device=x.device)
         hsf_backward(self.handle, x, grad, chunk, ws, dl_dpsi)
         return grad[:self.n_params]
+
+    def workspace_backward(self, n_x, chunk=None, minimal=False):
+        """Bytes of hsf_backward's workspace for n_x bitstrings: the preferred
+        size, or the least it accepts (the shifted forward runs then go one
+        copy per batch)."""
+        chunk = min(self.P, 256) if chunk is None else chunk
+        return hsf_workspace_size(self.handle, 4 if minimal else 2, chunk, n_x)
 
     def loss_device(self, x, chunk=None, amps=None):
         """L = sum_j |psi(x_j)|^2 as a one-entry float64 device tensor, from

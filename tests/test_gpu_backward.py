@@ -53,6 +53,27 @@ def test_variational_chunks_and_determinism():
     assert np.max(np.abs(g1 - g3)) <= 1e-5 * np.max(np.abs(g1))
 
 
+@pytest.mark.parametrize("chunk", [None, 5])
+def test_shifted_runs_in_batches_of_any_size(chunk):
+    """The shifted forward runs go as copies of one run, as many per batch as
+    the workspace holds: the least workspace (one copy per batch), one of
+    three copies and the preferred one give the same gradient bit for bit."""
+    c = cg.c3(seed=5, n=10, layers=6)
+    xs = cg.c3_bitstrings(n=10, count=40, seed=11)
+    plan = Plan(c)
+    x = torch.from_numpy(np.asarray(xs, dtype=np.int64)).cuda()
+    n_min = plan.workspace_backward(x.numel(), chunk, minimal=True)
+    n_pref = plan.workspace_backward(x.numel(), chunk)
+    assert n_pref > n_min
+    g = plan.backward(x, chunk).cpu().numpy()
+    for nbytes in (n_min, (2 * n_min + n_pref) // 3):
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        assert np.array_equal(plan.backward(x, chunk, ws=ws).cpu().numpy(), g), nbytes
+    from paper_2502_06959_amd import HsfError
+    with pytest.raises(HsfError):
+        plan.backward(x, chunk, ws=torch.empty(n_min - 256, dtype=torch.uint8, device="cuda"))
+
+
 def test_qaoa_shared_parameters():
     c = cg.qaoa_sbm(4, sizes=(5, 5), p_intra=0.6, p_inter=0.3)
     xs = np.arange(0, 1 << 10, 7, dtype=np.uint64)
