@@ -225,6 +225,8 @@ def main():
     ap.add_argument("--no-standard", action="store_true",
                     help="--workload qaoa: skip the standard-cutting comparison runs")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="c2p / c2: also time the whole step replayed from a HIP graph")
     ap.add_argument("--tree", default="auto", choices=["auto", "on", "off"],
                     help="path-tree sweeps (one state per distinct leading-digit prefix)")
     args = ap.parse_args()
@@ -327,6 +329,31 @@ def bench_full(args):
              "sweeps_ms": _stats([e[0].elapsed_time(e[1]) for e in evs]),
              "split_ms": _stats([e[1].elapsed_time(e[2]) for e in evs]),
              "path_sum_ms": _stats([e[2].elapsed_time(e[3]) for e in evs])}
+        if args.graph:
+            # the same step captured once and replayed: no host enqueue, the
+            # launches back to back on the device
+            g = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream()
+            cs.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cs):
+                step()
+                torch.cuda.synchronize()
+                with torch.cuda.graph(g, stream=cs):
+                    step()
+            torch.cuda.synchronize()
+            for _ in range(warmup):
+                g.replay()
+            torch.cuda.synchronize()
+            ge = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+            t0 = time.perf_counter()
+            for i in range(steps):
+                ge[i][0].record()
+                g.replay()
+                ge[i][1].record()
+            torch.cuda.synchronize()
+            r["graph"] = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / steps,
+                          "step_ms": _stats([e[0].elapsed_time(e[1]) for e in ge])}
+            del g
         if not args.no_check:
             from oracle import hsf as ohsf
             if "oracle" not in cache:
@@ -378,6 +405,7 @@ def bench_full(args):
         "path_sum_tflops_fp32_equiv": flops / (sum_ms * 1e-3) / 1e12,
         "sweep_executed_updates_per_s": executed / (res_m["sweeps_ms"]["mean"] * 1e-3),
         "rel_l2_sampled_rows": res_m.get("rel_l2_sampled_rows"),
+        "graph_replay": res_m.get("graph"),
         "plain_c64_hsf": None if plain is None else {
             "path_sum": "f32", "ms_per_step": plain["ms_per_step"], "step_ms": plain["step_ms"],
             "path_sum_ms": plain["path_sum_ms"], "rel_l2_sampled_rows": plain.get("rel_l2_sampled_rows"),

@@ -260,10 +260,13 @@ hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* 
  * adds into `out` (path chunks, resume).  ws: hsf_workspace_size(plan, 1,
  * n_paths, mode) bytes (HSF_SUM_BF16X3 uses it as scratch; with
  * HSF_SUM_BF16X3_SPLIT it holds the planes of hsf_split_operands, psiA and
- * psiB are not read and may be NULL).  n_paths = 0 is the
- * empty sum: the rows are set to zero (left as they are with accumulate = 1)
- * and psiA / psiB are not read (they may be NULL).  An empty row range
- * writes nothing and `out` may then be NULL.                                */
+ * psiB are not read and may be NULL).  A range of at most 32 rows (the
+ * first amplitudes of a large state) is bound by reading psiB once: there
+ * HSF_SUM_F32 and HSF_SUM_BF16X3 both run FP32 MFMA products straight from
+ * the half-states (no split, the workspace is not touched).  n_paths = 0 is
+ * the empty sum: the rows are set to zero (left as they are with
+ * accumulate = 1) and psiA / psiB are not read (they may be NULL).  An empty
+ * row range writes nothing and `out` may then be NULL.                      */
 hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA,
                                const void* psiB, int64_t ldB, int64_t n_paths,
                                int64_t row_begin, int64_t row_end, void* out, int64_t ldo,

@@ -109,6 +109,63 @@ __global__ __launch_bounds__(256) void pathsum_f32_batch(const GemmDesc* __restr
     }
 }
 
+// Row panels: at most 32 output rows (the first amplitudes of a large state)
+// against every column.  The sum is then bound by reading PsiB once (each of
+// its entries meets only the panel's rows), so the operands go straight from
+// global memory into FP32 MFMAs, with no split planes and no LDS: each wave
+// owns the panel x 32 columns as one 32x32x2 block per product (rows past M
+// read as zero), its operands prefetched R_DEPTH path pairs ahead.
+constexpr int R_COLS = 128;   // columns per workgroup (4 waves)
+constexpr int R_DEPTH = 8;
+
+__global__ __launch_bounds__(256) void pathsum_f32_rows(const float2* __restrict__ A, int64_t ldA,
+                                                        const float2* __restrict__ B, int64_t ldB, int64_t K,
+                                                        int64_t M, int64_t N, float2* __restrict__ out, int64_t ldo,
+                                                        int accumulate) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 31, lk = lane >> 5;
+    const int64_t n0 = (int64_t)blockIdx.x * R_COLS + w * 32;
+    if (n0 >= N) return;
+    const bool mok = li < M, nok = n0 + li < N;
+    f32x16 cr = (f32x16)0.0f, ci = (f32x16)0.0f;
+    float2 av[R_DEPTH], bv[R_DEPTH];
+    const float2 zero = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int d = 0; d < R_DEPTH; ++d) {
+        const int64_t k = 2 * d + lk;
+        av[d] = (k < K && mok) ? A[k * ldA + li] : zero;
+        bv[d] = (k < K && nok) ? B[k * ldB + n0 + li] : zero;
+    }
+    for (int64_t k0 = 0; k0 < K; k0 += 2 * R_DEPTH) {
+#pragma unroll
+        for (int d = 0; d < R_DEPTH; ++d) {
+            const float2 a = av[d], b = bv[d];
+            const int64_t kn = k0 + 2 * (d + R_DEPTH) + lk;
+            av[d] = (kn < K && mok) ? A[kn * ldA + li] : zero;
+            bv[d] = (kn < K && nok) ? B[kn * ldB + n0 + li] : zero;
+            cr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, -b.y, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, ci, 0, 0, 0);
+        }
+    }
+    if (!nok) return;
+    // accumulator r sits at row (r/4)*8 + (lane/32)*4 + r%4, column lane%32
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = (r >> 2) * 8 + lk * 4 + (r & 3);
+        if (row >= M) continue;
+        float2 v = make_float2(cr[r], ci[r]);
+        float2* o = out + row * ldo + n0 + li;
+        if (accumulate) {
+            const float2 old = *o;
+            v.x += old.x;
+            v.y += old.y;
+        }
+        *o = v;
+    }
+}
+
 // ---------------------------------------------------------------- FP64 ----
 // Same structure on the 16x16x4 FP64 MFMA: wave 32 x 32 outputs (2 x 2
 // blocks), workgroup 64 x 64.  Inputs are c128, or c64 widened on load.
@@ -358,6 +415,14 @@ hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void*
         const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(4096, (M * N * words + 255) / 256));
         hipLaunchKernelGGL(zero_rows, dim3((uint32_t)blocks), dim3(256), 0, st, (uint2*)out, ldo * words, M, N * words);
         return hip_check(hipGetLastError(), "zero_rows launch");
+    }
+    if (dtype == HSF_C64 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3) && M <= 32) {
+        // a row panel: FP32 products straight from the half-states (no split)
+        const int64_t grid = (N + R_COLS - 1) / R_COLS;
+        if (grid > 0x7fffffff) return fail(HSF_E_ARG, "too many output columns in one call");
+        hipLaunchKernelGGL(pathsum_f32_rows, dim3((uint32_t)grid), dim3(256), 0, st, (const float2*)A + row0, ldA,
+                           (const float2*)B, ldB, K, M, N, (float2*)out, ldo, accumulate);
+        return hip_check(hipGetLastError(), "pathsum_f32_rows launch");
     }
     if (dtype == HSF_C64 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3) &&
         path_sum_lds_fits(mode, (const float2*)A + row0, ldA, B, ldB, K, M, N)) {

@@ -187,3 +187,31 @@ def test_presplit_needs_the_split_workspace_and_path_count():
         plan.amplitudes_full(Ad[:K - 1], Bd[:K - 1], n_paths=K - 1, mode="bf16x3_split", out=out, ws=ws)
     assert e.value.code == "HSF_E_ARG"
     assert torch.count_nonzero(out).item() == 0
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+@pytest.mark.parametrize("rows,K,nb", [((0, 1), 1, 5), ((3, 10), 17, 7), ((0, 16), 33, 9), ((100, 131), 100, 8),
+                                       ((64, 96), 1000, 11), ((5, 37), 2, 4), ((0, 32), 4099, 10)])
+def test_row_panels(mode, rows, K, nb):
+    """Row ranges of at most 32 rows take the FP32 row-panel kernel in both
+    modes (prefetch ring deeper than K for small K, ragged K and N, a
+    column count below one workgroup's 128), with accumulation over two path
+    chunks and an odd output leading dimension."""
+    na = 9
+    rng = np.random.default_rng(rows[0] * 7 + K + nb)
+    A = _rand(rng, K, 1 << na, np.complex64)
+    B = _rand(rng, K, 1 << nb, np.complex64)
+    ref = A.astype(np.complex128).T @ B.astype(np.complex128)
+    plan = _shape_plan(na, nb)
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    r0, r1 = rows
+    out = torch.full((r1 - r0, (1 << nb) + 1), 7.0, dtype=torch.complex64, device="cuda")
+    h = K // 2
+    if h:
+        plan.amplitudes_full(Ad[:h], Bd[:h], n_paths=h, rows=rows, mode=mode, out=out)
+        plan.amplitudes_full(Ad[h:], Bd[h:], n_paths=K - h, rows=rows, mode=mode, out=out, accumulate=True)
+    else:
+        plan.amplitudes_full(Ad, Bd, n_paths=K, rows=rows, mode=mode, out=out)
+    got = out.cpu().numpy()
+    assert ohsf.rel_l2(got[:, :1 << nb], ref[r0:r1]) < 1e-5
+    assert np.all(got[:, 1 << nb:] == 7.0)
