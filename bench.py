@@ -693,7 +693,8 @@ def _first_amplitudes(plan, chunk, rows, mode, out):
     e0.record()
     for p0 in range(0, plan.P, chunk):
         n = min(chunk, plan.P - p0)
-        plan.run_paths(p0, p0 + n, A[:n], B[:n], ws=ws)
+        # side a only where the first `rows` rows are: its last pass runs only their tiles
+        plan.run_paths(p0, p0 + n, A[:n], B[:n], ws=ws, rows=(0, rows))
         plan.amplitudes_full(A[:n], B[:n], n_paths=n, rows=(0, rows), mode=mode, out=out, accumulate=p0 > 0)
     e1.record()
     torch.cuda.synchronize()

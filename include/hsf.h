@@ -253,6 +253,18 @@ hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* 
                          int64_t ldA, void* psiB, int64_t ldB, void* ws, size_t ws_bytes,
                          hsf_stream_t stream);
 
+/* hsf_run_paths for callers that need only the amplitudes [row_begin,
+ * row_end) of side a (at most 2^20), such as the first amplitudes of the
+ * state (Sec. V computes the first 10^6): the last LDS pass of side a runs
+ * only the tiles that hold those rows, so the rest of each psiA row is left
+ * unspecified (psiA is required and keeps its full layout, ldA >= 2^n_a).
+ * Side b (psiB, may be NULL) is computed in full.  The wanted rows equal
+ * hsf_run_paths' bit for bit.  Other arguments, errors and ownership as in
+ * hsf_run_paths.                                                            */
+hsf_status hsf_run_paths_rows(hsf_plan_t plan, int64_t p_begin, int64_t p_end, int64_t row_begin,
+                              int64_t row_end, void* psiA, int64_t ldA, void* psiB, int64_t ldB,
+                              void* ws, size_t ws_bytes, hsf_stream_t stream);
+
 /* Path sum (Sec. II-B), output rows [row_begin, row_end) of C = PsiA^T PsiB:
  * out[(r - row_begin) * ldo + c] = sum_{j < n_paths} psiA[j][r] psiB[j][c],
  * c < 2^n_b.  Input type: the plan's dtype.  Output type: c64 for HSF_SUM_F32

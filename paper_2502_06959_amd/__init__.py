@@ -8,10 +8,10 @@ current stream.  Functions keep the C names (hsf_plan, hsf_run_paths, ...);
 """
 from .hsf import (Amplitudes, Batch, Plan, ProbabilityMass, hsf_amplitudes_bitstrings, hsf_amplitudes_full, hsf_amplitudes_full_noalloc,
                   hsf_backward, hsf_loss,
-                  hsf_find_blocks, hsf_norm2, hsf_plan, hsf_run_paths, hsf_split_operands, hsf_workspace_size,
+                  hsf_find_blocks, hsf_norm2, hsf_plan, hsf_run_paths, hsf_run_paths_rows, hsf_split_operands, hsf_workspace_size,
                   joint_blocked)
 from ._lib import HsfError
 
 __all__ = ["Amplitudes", "Batch", "Plan", "ProbabilityMass", "HsfError", "hsf_plan", "hsf_find_blocks", "joint_blocked",
-           "hsf_run_paths", "hsf_amplitudes_full", "hsf_amplitudes_full_noalloc", "hsf_split_operands", "hsf_amplitudes_bitstrings", "hsf_norm2", "hsf_backward", "hsf_loss",
+           "hsf_run_paths", "hsf_run_paths_rows", "hsf_amplitudes_full", "hsf_amplitudes_full_noalloc", "hsf_split_operands", "hsf_amplitudes_bitstrings", "hsf_norm2", "hsf_backward", "hsf_loss",
            "hsf_workspace_size"]

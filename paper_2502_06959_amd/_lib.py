@@ -65,6 +65,8 @@ SIGNATURES = {
     "hsf_workspace_size": (c_size_t, [c_void_p, c_int32, c_int64, c_int32]),
     "hsf_run_paths": (c_int32, [c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                 c_size_t, c_void_p]),
+    "hsf_run_paths_rows": (c_int32, [c_void_p, c_int64, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p,
+                                     c_int64, c_void_p, c_size_t, c_void_p]),
     "hsf_amplitudes_full": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64, c_int64,
                                       c_void_p, c_int64, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "hsf_amplitudes_full_noalloc": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64,

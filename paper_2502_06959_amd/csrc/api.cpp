@@ -246,6 +246,27 @@ hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* 
     HSF_GUARD_END
 }
 
+hsf_status hsf_run_paths_rows(hsf_plan_t plan, int64_t p_begin, int64_t p_end, int64_t row_begin, int64_t row_end,
+                              void* psiA, int64_t ldA, void* psiB, int64_t ldB, void* ws, size_t ws_bytes,
+                              hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    if (!plan || !psiA) return fail(HSF_E_ARG, "null argument");
+    Plan* p = P_(plan);
+    if (p_begin < 0 || p_end > p->P || p_begin > p_end) return fail(HSF_E_ARG, "path range outside [0, P)");
+    if (row_begin < 0 || row_end > (int64_t(1) << p->na) || row_begin > row_end)
+        return fail(HSF_E_ARG, "row range outside [0, 2^n_a)");
+    if (row_end - row_begin > (int64_t(1) << 20)) return fail(HSF_E_ARG, "more than 2^20 rows: use hsf_run_paths");
+    if (ldA < (int64_t(1) << p->na)) return fail(HSF_E_ARG, "ldA smaller than 2^n_a");
+    if (psiB && ldB < (int64_t(1) << p->nb)) return fail(HSF_E_ARG, "ldB smaller than 2^n_b");
+    if (p_begin == p_end) return HSF_OK;
+    DeviceCopy* d = nullptr;
+    hsf_status s = ensure_device(*p, &d);
+    if (s != HSF_OK) return s;
+    return run_sides(*p, *d, p_begin, p_end - p_begin, psiA, ldA, psiB, ldB, ws, ws_bytes, (hipStream_t)stream,
+                     nullptr, row_begin, row_end);
+    HSF_GUARD_END
+}
+
 hsf_status hsf_amplitudes_full(hsf_plan_t plan, const void* psiA, int64_t ldA, const void* psiB,
                                int64_t ldB, int64_t n_paths, int64_t row_begin, int64_t row_end,
                                void* out, int64_t ldo, int32_t mode, int32_t accumulate, void* ws,

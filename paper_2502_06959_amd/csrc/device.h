@@ -26,10 +26,13 @@ struct SweepReplicas {
 // Half-states of paths [p_begin, p_begin + n_paths) into psiA / psiB (either
 // may be null).  ws: tree_workspace(p, n_paths) bytes for the path-tree
 // levels; with less (or null) every path runs every per-path op.  reps: the
-// run's copies (null: one).
+// run's copies (null: one).  a_row_end >= 0: only side a's amplitudes
+// [a_row_begin, a_row_end) are wanted (at most 2^20 of them): its last pass
+// runs only the tiles that hold them, so the rest of each side-a row is left
+// unspecified.
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
                      void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream,
-                     const SweepReplicas* reps = nullptr);
+                     const SweepReplicas* reps = nullptr, int64_t a_row_begin = 0, int64_t a_row_end = -1);
 size_t tree_workspace(const Plan& p, int64_t n_paths);
 
 // How a sweep launch row finds its input.  ROW_INPLACE: its own row.

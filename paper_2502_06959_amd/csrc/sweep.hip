@@ -102,6 +102,8 @@ struct SideArgs {
     // reads src + r src_rs (strides in complex elements).
     uint32_t rep_blocks;
     int64_t pool_rs, dst_rs, src_rs;
+    // the launch covers tiles [tile0, tile0 + n_tiles) of each row
+    uint32_t tile0;
 };
 
 // LDS position of tile element e: the low four index bits are XORed with the
@@ -388,7 +390,7 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideA
     const uint32_t r = rb ? blk / rb : 0u;
     blk -= r * rb;
     const uint32_t pl = blk / n_tiles;
-    const uint32_t t = blk - pl * n_tiles;
+    const uint32_t t = HSF_SEL(tile0) + (blk - pl * n_tiles);
     const int64_t i = HSF_SEL(i_lo) + (int64_t)pl;
     const int64_t S = HSF_SEL(S);
     const int64_t path = max(i * S, HSF_SEL(p0));
@@ -773,7 +775,7 @@ size_t tree_workspace(const Plan& p, int64_t n_paths) {
 
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
                      void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream,
-                     const SweepReplicas* reps) {
+                     const SweepReplicas* reps, int64_t a_row_begin, int64_t a_row_end) {
     const bool dbl = p.dtype == HSF_C128;
     const size_t esz = dbl ? 16 : 8;
     const int64_t R = reps ? std::max(1, reps->R) : 1;
@@ -840,6 +842,20 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
             a[s].src_lo = m.src_lo;
             a[s].S_par = m.S_par;
             a[s].mode = m.mode;
+            if (s == 0 && j + 1 == items[0].size() && a_row_end >= 0) {
+                // side a's last pass: only the tiles that hold rows [a_row_begin, a_row_end)
+                uint32_t lo = a[s].n_tiles - 1, hi = 0;
+                for (int64_t x = a_row_begin; x < a_row_end; ++x) {
+                    uint32_t t = 0;
+                    for (int b = 0; b < ps.n_nonlocal; ++b) t |= (uint32_t)((x >> ps.nonlocal_q[b]) & 1) << b;
+                    lo = std::min(lo, t);
+                    hi = std::max(hi, t);
+                }
+                if (a_row_end > a_row_begin) {
+                    a[s].tile0 = lo;
+                    a[s].n_tiles = hi - lo + 1;
+                }
+            }
             if (R > 1) {
                 // the last level writes the caller's rows, the others a copy's tree levels
                 const int64_t lvl_rs = (int64_t)(reps->ws_rs / esz);

@@ -122,6 +122,19 @@ def hsf_run_paths(plan, p_begin, p_end, psiA, psiB, ws=None):
                                   ws.numel() * ws.element_size() if ws is not None else 0, _stream(ref)))
 
 
+def hsf_run_paths_rows(plan, p_begin, p_end, row_begin, row_end, psiA, psiB, ws=None):
+    """hsf_run_paths keeping only side a's amplitudes [row_begin, row_end)
+    of each psiA row (the rest is left unspecified)."""
+    if ws is None and p_end > p_begin:
+        nbytes = hsf_workspace_size(plan, 0, p_end - p_begin, 0)
+        if nbytes > 0:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=psiA.device)
+    L.check(L.lib().hsf_run_paths_rows(ctypes.c_void_p(plan), p_begin, p_end, row_begin, row_end, _ptr(psiA),
+                                       psiA.stride(0), _ptr(psiB), psiB.stride(0) if psiB is not None else 0,
+                                       _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0,
+                                       _stream(psiA)))
+
+
 def hsf_amplitudes_full(plan, psiA, psiB, n_paths, row_begin, row_end, out, mode="f32", accumulate=False,
                         ws=None):
     L.check(L.lib().hsf_amplitudes_full(ctypes.c_void_p(plan), _ptr(psiA), psiA.stride(0), _ptr(psiB),
@@ -278,11 +291,16 @@ class Plan:
         B = torch.empty((n_paths, 1 << self.nb), dtype=self.torch_dtype, device=device)
         return A, B
 
-    def run_paths(self, p_begin=0, p_end=None, psiA=None, psiB=None, ws=None):
+    def run_paths(self, p_begin=0, p_end=None, psiA=None, psiB=None, ws=None, rows=None):
+        """Half-states of paths [p_begin, p_end).  rows = (r0, r1): only side
+        a's amplitudes r0 .. r1 - 1 are wanted (hsf_run_paths_rows)."""
         p_end = self.P if p_end is None else p_end
         if psiA is None and psiB is None:
             psiA, psiB = self.alloc_halves(p_end - p_begin)
-        hsf_run_paths(self.handle, p_begin, p_end, psiA, psiB, ws)
+        if rows is None:
+            hsf_run_paths(self.handle, p_begin, p_end, psiA, psiB, ws)
+        else:
+            hsf_run_paths_rows(self.handle, p_begin, p_end, rows[0], rows[1], psiA, psiB, ws)
         return psiA, psiB
 
     def amplitudes_full(self, psiA, psiB, n_paths=None, rows=None, mode=None, out=None, accumulate=False,

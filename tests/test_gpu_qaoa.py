@@ -106,3 +106,41 @@ def test_q30_first_million_amplitudes_and_norm():
         plan.amplitudes_full(A, B, rows=(r0, r0 + (1 << 12)), mode="bf16x3", out=tile)
         total += float(hsf_norm2(tile.reshape(-1)).cpu().numpy()[0])
     assert abs(total - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("tree", ["on", "off"])
+@pytest.mark.parametrize("kind", ["qaoa", "brick"])
+def test_run_paths_rows_equals_full_rows(tree, kind):
+    """hsf_run_paths_rows (side a's last pass only on the tiles that hold the
+    wanted rows): those rows bit for bit hsf_run_paths', side b in full, on
+    product-form QAOA blocks and dense brickwork blocks, path tree and flat,
+    with two path chunks; row ranges inside one tile, across tiles, at the
+    end and the whole side."""
+    # 8-qubit tiles on sides of 12-13 qubits: 16-32 tiles per row
+    if kind == "qaoa":
+        plan = Plan(joint_blocked(cg.qaoa_sbm(41, (13, 12), 0.8, 0.15)), tree=tree, tile_qubits=8)
+    else:
+        plan = Plan(cg.c3(seed=6, n=24, layers=6), tree=tree, tile_qubits=8)
+    assert plan.side_stats(0)["tile_qubits"] == 8 and plan.na >= 12
+    ref_A, ref_B = plan.run_paths()
+    M = 1 << plan.na
+    for r0, r1 in ((0, 16), (0, 1), (37, 60), (M - 40, M - 8), (0, M)):
+        A, B = plan.alloc_halves(plan.P)
+        A.fill_(float("nan"))
+        h = plan.P // 2
+        plan.run_paths(0, h, A[:h], B[:h], rows=(r0, r1))
+        plan.run_paths(h, plan.P, A[h:], B[h:], rows=(r0, r1))
+        assert torch.equal(A[:, r0:r1], ref_A[:, r0:r1]), (r0, r1)
+        assert torch.equal(B, ref_B), (r0, r1)
+
+
+def test_q30_first_million_amplitudes_rows_only():
+    """The first 10^6 amplitudes of q30-1 from side a's first 31 rows only
+    (hsf_run_paths_rows) and the row-panel path sum, against the oracle."""
+    g = np.load(os.path.join(GOLDEN, "qaoa_q30.npz"))
+    plan = Plan(joint_blocked(cg.qaoa_sbm(100, (15, 15), 0.8, 0.1)))
+    rows = (10 ** 6 + (1 << plan.nb) - 1) >> plan.nb
+    A, B = plan.run_paths(rows=(0, rows))
+    first = plan.amplitudes_full(A, B, rows=(0, rows), mode="bf16x3").reshape(-1)
+    xs = torch.from_numpy(np.asarray(g["x"], dtype=np.uint64).astype(np.int64)).cuda()
+    assert ohsf.rel_l2(first[xs].cpu().numpy(), g["psi"]) < 1e-5
