@@ -166,6 +166,75 @@ __global__ __launch_bounds__(256) void pathsum_f32_rows(const float2* __restrict
     }
 }
 
+// Panels of at most 16 rows on the 16x16x4 FP32 MFMA (16 rows x 16 columns,
+// four paths per instruction: half the MFMA work of a 32-row block): each
+// wave owns 32 columns as two blocks, path quads prefetched R16_DEPTH ahead.
+// Lane l supplies A row l%16 and B column l%16 of path l/16; accumulator r
+// of a block sits at row 4 (l/16) + r, column l%16.
+constexpr int R16_DEPTH = 8;
+using f32x4 = float __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void pathsum_f32_rows16(const float2* __restrict__ A, int64_t ldA,
+                                                          const float2* __restrict__ B, int64_t ldB, int64_t K,
+                                                          int64_t M, int64_t N, float2* __restrict__ out,
+                                                          int64_t ldo, int accumulate) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lq = lane >> 4;
+    const int64_t n0 = (int64_t)blockIdx.x * R_COLS + w * 32;
+    if (n0 >= N) return;
+    const bool mok = li < M;
+    bool nok[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) nok[b] = n0 + b * 16 + li < N;
+    f32x4 cr[2], ci[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) cr[b] = ci[b] = (f32x4)0.0f;
+    float2 av[R16_DEPTH], bv[R16_DEPTH][2];
+    const float2 zero = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int d = 0; d < R16_DEPTH; ++d) {
+        const int64_t k = 4 * d + lq;
+        av[d] = (k < K && mok) ? A[k * ldA + li] : zero;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[d][b] = (k < K && nok[b]) ? B[k * ldB + n0 + b * 16 + li] : zero;
+    }
+    for (int64_t k0 = 0; k0 < K; k0 += 4 * R16_DEPTH) {
+#pragma unroll
+        for (int d = 0; d < R16_DEPTH; ++d) {
+            const float2 a = av[d], b0 = bv[d][0], b1 = bv[d][1];
+            const int64_t kn = k0 + 4 * (d + R16_DEPTH) + lq;
+            av[d] = (kn < K && mok) ? A[kn * ldA + li] : zero;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[d][b] = (kn < K && nok[b]) ? B[kn * ldB + n0 + b * 16 + li] : zero;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const float2 bb = b ? b1 : b0;
+                cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, cr[b], 0, 0, 0);
+                cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, -bb.y, cr[b], 0, 0, 0);
+                ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.y, ci[b], 0, 0, 0);
+                ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, ci[b], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        if (!nok[b]) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = 4 * lq + r;
+            if (row >= M) continue;
+            float2 v = make_float2(cr[b][r], ci[b][r]);
+            float2* o = out + row * ldo + n0 + b * 16 + li;
+            if (accumulate) {
+                const float2 old = *o;
+                v.x += old.x;
+                v.y += old.y;
+            }
+            *o = v;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- FP64 ----
 // Same structure on the 16x16x4 FP64 MFMA: wave 32 x 32 outputs (2 x 2
 // blocks), workgroup 64 x 64.  Inputs are c128, or c64 widened on load.
@@ -420,8 +489,12 @@ hsf_status path_sum(int dtype, int mode, const void* A, int64_t ldA, const void*
         // a row panel: FP32 products straight from the half-states (no split)
         const int64_t grid = (N + R_COLS - 1) / R_COLS;
         if (grid > 0x7fffffff) return fail(HSF_E_ARG, "too many output columns in one call");
-        hipLaunchKernelGGL(pathsum_f32_rows, dim3((uint32_t)grid), dim3(256), 0, st, (const float2*)A + row0, ldA,
-                           (const float2*)B, ldB, K, M, N, (float2*)out, ldo, accumulate);
+        if (M <= 16)
+            hipLaunchKernelGGL(pathsum_f32_rows16, dim3((uint32_t)grid), dim3(256), 0, st, (const float2*)A + row0,
+                               ldA, (const float2*)B, ldB, K, M, N, (float2*)out, ldo, accumulate);
+        else
+            hipLaunchKernelGGL(pathsum_f32_rows, dim3((uint32_t)grid), dim3(256), 0, st, (const float2*)A + row0,
+                               ldA, (const float2*)B, ldB, K, M, N, (float2*)out, ldo, accumulate);
         return hip_check(hipGetLastError(), "pathsum_f32_rows launch");
     }
     if (dtype == HSF_C64 && (mode == HSF_SUM_F32 || mode == HSF_SUM_BF16X3) &&
