@@ -11,6 +11,9 @@ c3_grad.npz     C3: dL/dt for all 708 parameter ids by the full-state FP64
                 adjoint (two 2^30 states; about two hours on 8 cores), and
                 central differences (h = 1e-4) of the oracle HSF loss for 24
                 seeded ids
+c3_medium_grad.npz  a C3-recipe circuit at n=26 (seed 7, 6 layers; 13-qubit
+                sides): L over 256 seeded bitstrings and dL/dt for all its
+                parameter ids by the full-state FP64 adjoint
 c4.npz          C4 (P=4096): psi at 4096 seeded basis states
 c5.npz          C5 (64 circuits): psi at 64 seeded basis states of each circuit
 c5_rows.npz     C5: four whole output rows of each circuit (row 0, the last
@@ -95,6 +98,18 @@ def main(which):
         ids = np.arange(c["meta"]["n_params"])
         np.savez(os.path.join(OUT, "c3_grad.npz"), grad=np.array([adj[i] for i in ids]),
                  fd_ids=np.array(fd_ids), fd=np.array([fd[i] for i in fd_ids]), fd_h=1e-4)
+    if "c3med" in which:
+        # a medium C3-recipe circuit (n=26: 13-qubit sides, more than one
+        # adjoint tile per row in complex64 and complex128), every angle
+        c = cg.c3(seed=7, n=26, layers=6)
+        xs = cg.c3_bitstrings(n=26, count=256, seed=8)
+        t = time.time()
+        log = lambda m: print(f"{m} ({time.time() - t:.0f}s)", flush=True)  # noqa: E731
+        adj = OG.loss_grad_adjoint(c, xs, log=log)
+        log("c3med adjoint")
+        ids = np.arange(c["meta"]["n_params"])
+        np.savez(os.path.join(OUT, "c3_medium_grad.npz"), x=xs, grad=np.array([adj[i] for i in ids]),
+                 loss=OG.loss(c, xs, False))
     if "c4" in which:
         xs, amp = sampled_psi(cg.c4(), 4096, 44)
         np.savez(os.path.join(OUT, "c4.npz"), x=xs, psi=amp)

@@ -257,3 +257,24 @@ def test_amplitudes_autograd_nonlinear_loss():
     got = theta.grad.cpu().numpy()
     assert theta.grad.device.type == "cuda"
     assert np.max(np.abs(got - ref)) < 1e-6 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_medium_c3_every_angle_multipass_tree(dtype):
+    """A C3-recipe circuit at n=26 (13-qubit sides): forced path-tree sweeps on
+    8-qubit tiles (several passes per level) and 13-qubit adjoint rows (two
+    adjoint tiles per row in complex64, four in complex128), against the
+    oracle's full-state adjoint gradient for every angle
+    (tests/golden/c3_medium_grad.npz)."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_medium_grad.npz"))
+    c = cg.c3(seed=7, n=26, layers=6)
+    plan = Plan(c, dtype=dtype, tree="on", tile_qubits=8)
+    assert plan.na == 13 and plan.side_stats(0)["tile_qubits"] == 8 and plan.uses_tree(plan.P)
+    x = torch.from_numpy(np.asarray(g["x"], dtype=np.int64)).cuda()
+    got = plan.backward(x).cpu().numpy()
+    ref = g["grad"]
+    tol = 1e-9 if dtype == "c128" else 1e-4
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    assert err < tol, err
+    assert abs(plan.loss(x) - float(g["loss"])) < (1e-12 if dtype == "c128" else 1e-6) * float(g["loss"])
