@@ -76,6 +76,20 @@ __device__ __forceinline__ V cmulf(V m, V x) {
     return r;
 }
 
+// m x and acc += m x for a real coefficient m.x (m.y = 0)
+template <typename V>
+__device__ __forceinline__ V rmul(V m, V x) {
+    V r;
+    r.x = m.x * x.x;
+    r.y = m.x * x.y;
+    return r;
+}
+template <typename V>
+__device__ __forceinline__ void rfma(V& acc, V m, V x) {
+    acc.x = fmad(m.x, x.x, acc.x);
+    acc.y = fmad(m.x, x.y, acc.y);
+}
+
 // (ar, ai) += l t (no conjugate)
 template <typename V, typename A>
 __device__ __forceinline__ void cdot(A& ar, A& ai, V l, V t) {
@@ -321,7 +335,7 @@ constexpr size_t kTileMatBytes = 12 << 10;
 struct AdjTileOp {
     int32_t k, rb0, rb1, ang;      // register bits of the op's qubits (q[0] first); pass-local angle or -1
     int32_t inv, tr, dg;           // element offsets of M^dagger, M^T, D in the pass's matrix block (dg: ang >= 0)
-    int32_t diag;                  // M and D diagonal: only their diagonal entries are read
+    int32_t form;                  // FORM_*: which entries of M^dagger, M^T and D are read
 };
 struct AdjTileUnit {
     int32_t K, op_begin, op_end;
@@ -348,15 +362,32 @@ __device__ __forceinline__ double wave_sum(double v) {
 // and an angle's term (l, D s) is accumulated first in A (FP32 for complex64
 // rows: each thread sums a few dozen terms, the waves and tiles then in FP64).
 // DG: M and D diagonal (RZ, RZZ, PHASE, CP), only their diagonal entries read.
-template <int K, int RB, typename V, typename A, bool DG>
+// Matrix forms of a tile op (AdjTileOp::form).  One-qubit forms: REAL1, M
+// real (RY), D zero on its diagonal and real (with an angle); ANTI1, D zero
+// on its diagonal (RX).
+enum : int32_t { FORM_DENSE = 0, FORM_DIAG = 1, FORM_REAL1 = 2, FORM_ANTI1 = 3 };
+
+template <int K, int RB, typename V, typename A, int F>
 __device__ __forceinline__ void tadj1(V (&vs)[1 << K], V (&vl)[1 << K], const V* mi, const V* mt, const V* md,
                                       A& ar, A& ai) {
+    constexpr bool DG = F == FORM_DIAG;
 #pragma unroll
     for (int b = 0; b < (1 << K); ++b) {
         if (b & (1 << RB)) continue;
         const int i0 = b, i1 = b | (1 << RB);
         const V s0 = vs[i0], s1 = vs[i1], l0 = vl[i0], l1 = vl[i1];
-        if constexpr (DG) {
+        if constexpr (F == FORM_REAL1) {
+            if (md) {
+                cdot(ar, ai, l0, rmul(md[1], s1));
+                cdot(ar, ai, l1, rmul(md[2], s0));
+            }
+            V a0 = rmul(mi[0], s0), a1 = rmul(mi[2], s0), c0 = rmul(mt[0], l0), c1 = rmul(mt[2], l0);
+            rfma(a0, mi[1], s1);
+            rfma(a1, mi[3], s1);
+            rfma(c0, mt[1], l1);
+            rfma(c1, mt[3], l1);
+            vs[i0] = a0; vs[i1] = a1; vl[i0] = c0; vl[i1] = c1;
+        } else if constexpr (DG) {
             if (md) {
                 cdot(ar, ai, l0, cmulf(md[0], s0));
                 cdot(ar, ai, l1, cmulf(md[3], s1));
@@ -367,11 +398,16 @@ __device__ __forceinline__ void tadj1(V (&vs)[1 << K], V (&vl)[1 << K], const V*
             vl[i1] = cmulf(mt[3], l1);
         } else {
             if (md) {
-                V t0 = cmulf(md[0], s0), t1 = cmulf(md[2], s0);
-                cfma(t0, md[1], s1);
-                cfma(t1, md[3], s1);
-                cdot(ar, ai, l0, t0);
-                cdot(ar, ai, l1, t1);
+                if constexpr (F == FORM_ANTI1) {
+                    cdot(ar, ai, l0, cmulf(md[1], s1));
+                    cdot(ar, ai, l1, cmulf(md[2], s0));
+                } else {
+                    V t0 = cmulf(md[0], s0), t1 = cmulf(md[2], s0);
+                    cfma(t0, md[1], s1);
+                    cfma(t1, md[3], s1);
+                    cdot(ar, ai, l0, t0);
+                    cdot(ar, ai, l1, t1);
+                }
             }
             V a0 = cmulf(mi[0], s0), a1 = cmulf(mi[2], s0), c0 = cmulf(mt[0], l0), c1 = cmulf(mt[2], l0);
             cfma(a0, mi[1], s1);
@@ -433,18 +469,19 @@ __device__ __forceinline__ void tadj2(V (&vs)[1 << K], V (&vl)[1 << K], const V*
     }
 }
 
-template <int K, typename V, typename A, bool DG>
+template <int K, typename V, typename A, int F>
 __device__ __forceinline__ void tadj_op(V (&vs)[1 << K], V (&vl)[1 << K], int k, int r0, int r1, const V* mi,
                                         const V* mt, const V* md, A& ar, A& ai) {
+    constexpr bool DG = F == FORM_DIAG;
     if (k == 1) {
         switch (r0) {
-            case 0: tadj1<K, 0, V, A, DG>(vs, vl, mi, mt, md, ar, ai); break;
-            case 1: if constexpr (K > 1) tadj1<K, 1, V, A, DG>(vs, vl, mi, mt, md, ar, ai); break;
-            default: if constexpr (K > 2) tadj1<K, 2, V, A, DG>(vs, vl, mi, mt, md, ar, ai); break;
+            case 0: tadj1<K, 0, V, A, F>(vs, vl, mi, mt, md, ar, ai); break;
+            case 1: if constexpr (K > 1) tadj1<K, 1, V, A, F>(vs, vl, mi, mt, md, ar, ai); break;
+            default: if constexpr (K > 2) tadj1<K, 2, V, A, F>(vs, vl, mi, mt, md, ar, ai); break;
         }
         return;
     }
-    if constexpr (K >= 2) {
+    if constexpr (K >= 2 && F <= FORM_DIAG) {
 #define HSF_TADJ2(A0, B0) \
     if (r0 == A0 && r1 == B0) { if constexpr (A0 < K && B0 < K) tadj2<K, A0, B0, V, A, DG>(vs, vl, mi, mt, md, ar, ai); return; }
         HSF_TADJ2(0, 1) HSF_TADJ2(1, 0) HSF_TADJ2(0, 2) HSF_TADJ2(2, 0) HSF_TADJ2(1, 2) HSF_TADJ2(2, 1)
@@ -504,10 +541,24 @@ __device__ __forceinline__ void adj_tile_unit(typename Cx<T>::v* ts, typename Cx
             if (j >= n_ops) break;
             const AdjTileOp op = ops[u.op_begin + j];
             const V* md = op.ang >= 0 ? mats + op.dg : nullptr;
-            if (op.diag)
-                tadj_op<K, V, T, true>(vs, vl, op.k, op.rb0, op.rb1, mats + op.inv, mats + op.tr, md, ar[j], ai[j]);
-            else
-                tadj_op<K, V, T, false>(vs, vl, op.k, op.rb0, op.rb1, mats + op.inv, mats + op.tr, md, ar[j], ai[j]);
+            switch (op.form) {
+                case FORM_DIAG:
+                    tadj_op<K, V, T, FORM_DIAG>(vs, vl, op.k, op.rb0, op.rb1, mats + op.inv, mats + op.tr, md, ar[j],
+                                                ai[j]);
+                    break;
+                case FORM_REAL1:
+                    tadj_op<K, V, T, FORM_REAL1>(vs, vl, op.k, op.rb0, op.rb1, mats + op.inv, mats + op.tr, md, ar[j],
+                                                 ai[j]);
+                    break;
+                case FORM_ANTI1:
+                    tadj_op<K, V, T, FORM_ANTI1>(vs, vl, op.k, op.rb0, op.rb1, mats + op.inv, mats + op.tr, md, ar[j],
+                                                 ai[j]);
+                    break;
+                default:
+                    tadj_op<K, V, T, FORM_DENSE>(vs, vl, op.k, op.rb0, op.rb1, mats + op.inv, mats + op.tr, md, ar[j],
+                                                 ai[j]);
+                    break;
+            }
         }
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -889,6 +940,21 @@ bool adj_diagonal(const SideOp& o) {
         for (int c = 0; c < d; ++c)
             if (r != c && o.dgen[(size_t)r * d + c] != cd(0)) return false;
     return true;
+}
+
+// Which entries of a raw op's matrices the tile pass reads (FORM_*): M is
+// `fwd` (2^k x 2^k); with an angle, D is the op's dgen.
+int32_t adj_form(const SideOp& o, const cd* fwd) {
+    if (adj_diagonal(o)) return FORM_DIAG;
+    if (o.k != 1) return FORM_DENSE;
+    const bool anti = o.param_id < 0 || (o.dgen[0] == cd(0) && o.dgen[3] == cd(0));
+    bool real = true;
+    for (int e = 0; e < 4; ++e) real = real && fwd[e].imag() == 0.0;
+    if (o.param_id >= 0)
+        for (int e = 0; e < 4; ++e) real = real && o.dgen[(size_t)e].imag() == 0.0;
+    if (real && anti) return FORM_REAL1;
+    if (anti && o.param_id >= 0) return FORM_ANTI1;
+    return FORM_DENSE;
 }
 
 // The adjoint pass's units of one side, in the order it takes them: a factor
@@ -1432,13 +1498,7 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
                         }
                         op.inv = stage(om[side][ri].inv, gop.k);
                         op.tr = stage(om[side][ri].tr, gop.k);
-                        op.diag = gop.kind == SideOp::DIAG ? 1 : 0;
-                        if (op.diag && gop.param_id >= 0) {
-                            const int dd2 = 1 << gop.k;
-                            for (int r = 0; r < dd2; ++r)
-                                for (int c = 0; c < dd2; ++c)
-                                    if (r != c && gop.dgen[(size_t)r * dd2 + c] != cd(0)) op.diag = 0;
-                        }
+                        op.form = adj_form(gop, hm.data() + om[side][ri].fwd);
                         op.ang = -1;
                         if (gop.param_id >= 0) {
                             op.dg = stage(om[side][ri].dg, gop.k);
