@@ -766,6 +766,7 @@ struct Layout {
     size_t shift_t;                      // parameter id of each shifted run
     size_t vA, vB, lA, lB, ckA, ckB, psi_x, loss, partial, tables, mats, pools, tree, tree_bytes, total;
     size_t repA, repB, rep_psi, rep_tree, rep_tree_bytes;   // copies of the shifted forward run
+    size_t keep, keep_off[2];            // the unshifted forward's path-tree levels below the last
     int64_t reps;          // copies per batch of shifted forward runs
     int64_t dimA, dimB;
     int ka, kb;            // checkpoints per side
@@ -887,8 +888,18 @@ Layout layout(const Plan& p, int64_t chunk, int64_t nx, int64_t reps_cap = 0) {
     }
     L.repA = take((size_t)L.reps * chunk * L.dimA * esz);
     L.repB = take((size_t)L.reps * chunk * L.dimB * esz);
-    L.rep_psi = take((size_t)L.reps * nx * 16);
+    L.rep_psi = take((size_t)std::max<int64_t>(1, L.n_shift) * nx * 16);
     L.rep_tree = take((size_t)L.reps * L.rep_tree_bytes);
+    // every level below the last of the unshifted forward, kept for the
+    // shifted runs to start from (path trees only)
+    {
+        size_t kb = 0;
+        for (int s = 0; s < 2; ++s) {
+            L.keep_off[s] = kb;
+            if (L.n_shift > 0) kb += level_keep_offset(p, chunk, s, 1 << 30);
+        }
+        L.keep = take(kb);
+    }
     const size_t n_raw = p.side[0].raw.size() + p.side[1].raw.size();
     size_t tile_mats = 0;
     for (int s = 0; s < 2; ++s)
@@ -1729,30 +1740,62 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
             return s;
         V* repS[2] = {(V*)(base + Lo.repA), (V*)(base + Lo.repB)};
         double2* rpsi = (double2*)(base + Lo.rep_psi);
+        unsigned char* keep[2] = {base + Lo.keep + Lo.keep_off[0], base + Lo.keep + Lo.keep_off[1]};
         DeviceCopy dd = d;
-        for (size_t i0 = 0; i0 < ns; i0 += (size_t)Lo.reps) {
-            // shifts i0 .. i0 + R - 1: copy r reads the pools of shift i0 + r
-            const int R = (int)std::min<size_t>((size_t)Lo.reps, ns - i0);
-            for (int side = 0; side < 2; ++side)
-                for (int tr = 0; tr < 2; ++tr) {
-                    std::vector<DeviceSchedule>& dv = tr ? dd.tree[side] : dd.side[side];
-                    for (size_t q = 0; q < dv.size(); ++q)
-                        if (used_sched[2 * side + tr][q])
-                            dv[q].pool = pools + i0 * Lo.pool_elems + pool_at[2 * side + tr][q];
+        // batches: runs of shifts of one block, at most Lo.reps each
+        std::vector<std::pair<size_t, int>> batches;
+        for (size_t i0 = 0; i0 < ns;) {
+            size_t i1 = i0 + 1;
+            while (i1 < ns && i1 - i0 < (size_t)Lo.reps && shifts[i1].k == shifts[i0].k) ++i1;
+            batches.push_back({i0, (int)(i1 - i0)});
+            i0 = i1;
+        }
+        for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
+            const int64_t np = std::min(chunk, p.P - p0);
+            // the unshifted forward of this chunk, its levels below the last kept
+            SweepLevels kl;
+            kl.keep[0] = keep[0];
+            kl.keep[1] = keep[1];
+            if ((s = run_sides(p, d, p0, np, repS[0], dim[0], repS[1], dim[1], base + Lo.rep_tree, Lo.tree_bytes,
+                               ss.st, nullptr, 0, -1, &kl)) != HSF_OK)
+                return s;
+            for (const auto& bt : batches) {
+                // shifts i0 .. i0 + R - 1 of block k: copy r reads the pools of shift i0 + r
+                const size_t i0 = bt.first;
+                const int R = bt.second;
+                for (int side = 0; side < 2; ++side)
+                    for (int tr = 0; tr < 2; ++tr) {
+                        std::vector<DeviceSchedule>& dv = tr ? dd.tree[side] : dd.side[side];
+                        for (size_t q = 0; q < dv.size(); ++q)
+                            if (used_sched[2 * side + tr][q])
+                                dv[q].pool = pools + i0 * Lo.pool_elems + pool_at[2 * side + tr][q];
+                    }
+                // the copies start at each side's first level whose states
+                // depend on block k's digit (S <= its stride), from the kept
+                // level before it: the earlier levels do not see the shift
+                SweepLevels rl;
+                const int64_t stride = p.blocks[shifts[i0].k].stride;
+                for (int side = 0; side < 2; ++side) {
+                    if (p.side[side].tree.empty()) continue;
+                    const std::vector<TreeLevel>& lv = p.side[side].tree[0].levels;
+                    int st0 = 0;
+                    while (st0 + 1 < (int)lv.size() && lv[(size_t)st0].S > stride) ++st0;
+                    rl.start[side] = st0;
+                    rl.parent[side] = st0 > 0 ? keep[side] + level_keep_offset(p, np, side, st0 - 1) : nullptr;
                 }
-            const SweepReplicas rp{R, (int64_t)Lo.pool_elems, {chunk * dim[0], chunk * dim[1]}, Lo.rep_tree_bytes};
-            for (int64_t p0 = 0; p0 < p.P; p0 += chunk) {
-                const int64_t np = std::min(chunk, p.P - p0);
-                if ((s = run_sides(p, dd, p0, np, repS[0], dim[0], repS[1], dim[1], base + Lo.rep_tree, Lo.tree_bytes,
-                                   ss.st, &rp)) != HSF_OK ||
-                    (s = gather_dot(p.dtype, repS[0], dim[0], repS[1], dim[1], np, p.nb, p.n, x, nx, rpsi,
-                                    p0 > 0 ? 1 : 0, ss.st, R, chunk * dim[0], chunk * dim[1])) != HSF_OK)
+                const SweepReplicas rp{R, (int64_t)Lo.pool_elems, {chunk * dim[0], chunk * dim[1]},
+                                       Lo.rep_tree_bytes};
+                if ((s = run_sides(p, dd, p0, np, repS[0], dim[0], repS[1], dim[1], base + Lo.rep_tree,
+                                   Lo.tree_bytes, ss.st, &rp, 0, -1, &rl)) != HSF_OK ||
+                    (s = gather_dot(p.dtype, repS[0], dim[0], repS[1], dim[1], np, p.nb, p.n, x, nx,
+                                    rpsi + i0 * (size_t)nx, p0 > 0 ? 1 : 0, ss.st, R, chunk * dim[0],
+                                    chunk * dim[1])) != HSF_OK)
                     return s;
             }
-            hipLaunchKernelGGL(bw_shift_dot, dim3((uint32_t)R), dim3(256), 0, ss.st, (const double2*)psi_x,
-                               (const double2*)rpsi, nx, lossb + i0);
-            if ((s = hip_check(hipGetLastError(), "bw_shift_dot launch")) != HSF_OK) return s;
         }
+        hipLaunchKernelGGL(bw_shift_dot, dim3((uint32_t)ns), dim3(256), 0, ss.st, (const double2*)psi_x,
+                           (const double2*)rpsi, nx, lossb);
+        if ((s = hip_check(hipGetLastError(), "bw_shift_dot launch")) != HSF_OK) return s;
         // the caller's stream waits for the shifted runs, then dL/dt +=
         // Re sum_j conj(c_j) psi_j(t + pi) per occurrence, in plan order
         hipEvent_t done = nullptr;

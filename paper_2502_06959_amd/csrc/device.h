@@ -9,6 +9,21 @@ namespace hsf {
 
 constexpr size_t kNormWsDoubles = 8192;
 
+// Path-tree levels kept or resumed (hsf_backward's shifted forward runs):
+// keep[s] non-null: side s's levels below the last each go to a buffer of
+// their own, level l at keep[s] + level_keep_offset(p, n_paths, s, l); so a
+// later run over the same paths can start at level start[s] > 0, its first
+// pass reading level start[s] - 1 from parent[s] (laid out as kept; shared by
+// every copy of a replicated run).
+struct SweepLevels {
+    unsigned char* keep[2] = {nullptr, nullptr};
+    int start[2] = {0, 0};
+    const unsigned char* parent[2] = {nullptr, nullptr};
+};
+// Bytes from the start of a side's kept levels to level l's rows for a chunk
+// of n_paths paths (l = the number of levels below the last: the total).
+size_t level_keep_offset(const Plan& p, int64_t n_paths, int side, int l);
+
 // R copies of one forward run in the same launches, which differ only in
 // their factor pools and buffers: copy r reads every schedule's pool at
 // pool + r pool_rs, writes its half-states at psi + r psi_rs[side] (strides
@@ -32,7 +47,8 @@ struct SweepReplicas {
 // unspecified.
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
                      void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream,
-                     const SweepReplicas* reps = nullptr, int64_t a_row_begin = 0, int64_t a_row_end = -1);
+                     const SweepReplicas* reps = nullptr, int64_t a_row_begin = 0, int64_t a_row_end = -1,
+                     const SweepLevels* levels = nullptr);
 size_t tree_workspace(const Plan& p, int64_t n_paths);
 
 // How a sweep launch row finds its input.  ROW_INPLACE: its own row.
@@ -52,6 +68,7 @@ struct SweepItem {
     int64_t dst_ld;
     const void* src;
     int64_t src_ld, src_lo, S_par;
+    int32_t src_shared = 0;   // src is one buffer for every copy of a replicated run
 };
 
 // Scratch of the path-tree levels below the last for a chunk of n_paths
@@ -66,7 +83,8 @@ TreeScratch tree_scratch(const Plan& p, int64_t n_paths);
 // it is non-null) or level by level (buf0 / buf1: the side's tree scratch).
 std::vector<SweepItem> side_items(const Schedule& sc, bool tree, const void* prefix, int64_t p_begin,
                                   int64_t n_paths, void* psi, int64_t ld, unsigned char* buf0, unsigned char* buf1,
-                                  int64_t dim);
+                                  int64_t dim, const unsigned char* const* keep = nullptr, int start = 0,
+                                  const unsigned char* parent = nullptr);
 // The passes of one flat schedule without factor slots over rows 0 .. rows-1
 // of psi (ld elements apart), in place.
 hsf_status run_segment(const Plan& p, const DeviceSchedule& ds, const Schedule& sc, void* psi, int64_t ld, int64_t rows,

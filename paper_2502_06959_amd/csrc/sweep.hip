@@ -733,31 +733,40 @@ TreeScratch tree_scratch(const Plan& p, int64_t n_paths) {
 // rows written to its scratch buffer (the last level to psi), its first pass
 // reading the prefix state or the previous level.
 std::vector<SweepItem> side_items(const Schedule& sc, bool tree, const void* prefix, int64_t p_begin, int64_t n_paths,
-                             void* psi, int64_t ld, unsigned char* buf0, unsigned char* buf1, int64_t dim) {
+                             void* psi, int64_t ld, unsigned char* buf0, unsigned char* buf1, int64_t dim,
+                             const unsigned char* const* keep, int start, const unsigned char* parent) {
     std::vector<SweepItem> v;
     const size_t first = prefix ? (size_t)sc.n_prefix_passes : 0;
     if (!tree) {
         for (size_t k = first; k < sc.passes.size(); ++k) {
             const bool sh = k == first && prefix;
-            v.push_back({k, sh ? ROW_SHARED : ROW_INPLACE, 1, p_begin, n_paths, psi, ld, sh ? prefix : nullptr, 0, 0, 1});
+            SweepItem it{k, sh ? ROW_SHARED : ROW_INPLACE, 1, p_begin, n_paths, psi, ld, sh ? prefix : nullptr, 0, 0, 1};
+            it.src_shared = sh ? 1 : 0;
+            v.push_back(it);
         }
         return v;
     }
     unsigned char* buf[2] = {buf0, buf1};
     const size_t nl = sc.levels.size();
-    for (size_t l = 0; l < nl; ++l) {
+    // level l's rows below the last: its own kept buffer, else one of two
+    auto level_buf = [&](size_t l) -> unsigned char* { return keep ? (unsigned char*)keep[l] : buf[l % 2]; };
+    for (size_t l = (size_t)std::max(start, 0); l < nl; ++l) {
         const TreeLevel& tl = sc.levels[l];
         const int64_t lo = p_begin / tl.S, rows = level_rows(p_begin, n_paths, tl.S);
-        void* dst = l + 1 == nl ? psi : (void*)buf[l % 2];
+        void* dst = l + 1 == nl ? psi : (void*)level_buf(l);
         const int64_t dld = l + 1 == nl ? ld : dim;
         for (size_t k = (size_t)tl.pass_begin; k < (size_t)tl.pass_end; ++k) {
             SweepItem it{k, ROW_INPLACE, tl.S, lo, rows, dst, dld, nullptr, 0, 0, 1};
             if (k == (size_t)tl.pass_begin && l == 0 && prefix) {
                 it.mode = ROW_SHARED;
                 it.src = prefix;
+                it.src_shared = 1;
             } else if (k == (size_t)tl.pass_begin && l > 0) {
                 it.mode = ROW_PARENT;
-                it.src = buf[(l - 1) % 2];
+                // a resumed run's first level reads the given parent level
+                const bool resumed = (int)l == start && parent;
+                it.src = resumed ? (const void*)parent : (const void*)level_buf(l - 1);
+                it.src_shared = resumed ? 1 : 0;
                 it.src_ld = dim;
                 it.S_par = sc.levels[l - 1].S;
                 it.src_lo = p_begin / it.S_par;
@@ -768,6 +777,17 @@ std::vector<SweepItem> side_items(const Schedule& sc, bool tree, const void* pre
     return v;
 }
 
+size_t level_keep_offset(const Plan& p, int64_t n_paths, int side, int l) {
+    const size_t esz = p.dtype == HSF_C128 ? 16 : 8;
+    if (p.side[side].tree.empty()) return 0;
+    const std::vector<TreeLevel>& lv = p.side[side].tree[0].levels;
+    size_t o = 0;
+    for (int i = 0; i < l && i + 1 < (int)lv.size(); ++i)
+        o += ((size_t)level_rows_max(n_paths, lv[(size_t)i].S) * ((size_t)1 << p.side[side].nq) * esz + 255) &
+             ~size_t(255);
+    return o;
+}
+
 size_t tree_workspace(const Plan& p, int64_t n_paths) {
     if (n_paths <= 0 || !choose_sweep(p, n_paths).tree) return 0;
     return tree_scratch(p, n_paths).total;
@@ -775,7 +795,7 @@ size_t tree_workspace(const Plan& p, int64_t n_paths) {
 
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
                      void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream,
-                     const SweepReplicas* reps, int64_t a_row_begin, int64_t a_row_end) {
+                     const SweepReplicas* reps, int64_t a_row_begin, int64_t a_row_end, const SweepLevels* levels) {
     const bool dbl = p.dtype == HSF_C128;
     const size_t esz = dbl ? 16 : 8;
     const int64_t R = reps ? std::max(1, reps->R) : 1;
@@ -805,9 +825,16 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
         dsc[s] = &dv[si];
         if (!psi[s]) continue;
         // a side with a shared prefix state starts after its prefix passes
+        std::vector<unsigned char*> keep;
+        if (tree && levels && levels->keep[s]) {
+            const size_t nlv = sc[s]->levels.size();
+            for (size_t l = 0; l + 1 < nlv; ++l)
+                keep.push_back(levels->keep[s] + level_keep_offset(p, n_paths, s, (int)l));
+        }
         items[s] = side_items(*sc[s], tree, dsc[s]->prefix, p_begin, n_paths, psi[s], ld[s],
                               tree ? base + tsc.off[s][0] : nullptr, tree ? base + tsc.off[s][1] : nullptr,
-                              int64_t(1) << p.side[s].nq);
+                              int64_t(1) << p.side[s].nq, keep.empty() ? nullptr : keep.data(),
+                              tree && levels ? levels->start[s] : 0, tree && levels ? levels->parent[s] : nullptr);
         rounds = std::max(rounds, items[s].size());
     }
     // rows per launch bounded so the grid stays below 2^31 workgroups
@@ -861,7 +888,7 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
                 const int64_t lvl_rs = (int64_t)(reps->ws_rs / esz);
                 a[s].pool_rs = reps->pool_rs;
                 a[s].dst_rs = m.dst == psi[s] ? reps->psi_rs[s] : lvl_rs;
-                a[s].src_rs = m.mode == ROW_PARENT ? lvl_rs : 0;
+                a[s].src_rs = m.mode == ROW_PARENT && !m.src_shared ? lvl_rs : 0;
             }
             emax = std::max(emax, 1u << ps.n_local);
             rows_max = std::max(rows_max, m.rows);
