@@ -256,3 +256,24 @@ def test_shared_prefix_hoists_commuting_ops():
         st = p3.side_stats(s)
         assert 0 <= st["ops_shared"] <= st["ops_fused"]
         assert st["passes"] >= 1
+
+
+def test_run_paths_rows_argument_checks():
+    """hsf_run_paths_rows rejects a null psiA, row ranges outside [0, 2^n_a)
+    or wider than 2^20, a short ldA and bad path ranges before any device
+    work; an empty path range returns at once."""
+    lib = L.lib()
+    p = Plan(cg.c1())
+    h, ma, mb = ctypes.c_void_p(p.handle), 1 << p.na, 1 << p.nb
+    dummy = ctypes.c_void_p(0x1000)      # never dereferenced: every call below fails its checks first
+    assert lib.hsf_run_paths_rows(None, 0, 1, 0, 1, dummy, ma, None, 0, None, 0, None) == 1
+    assert lib.hsf_run_paths_rows(h, 0, 1, 0, 1, None, ma, None, 0, None, 0, None) == 1
+    assert "null" in lib.hsf_last_error().decode()
+    assert lib.hsf_run_paths_rows(h, 0, 1, 2, 1, dummy, ma, None, 0, None, 0, None) == 1
+    assert lib.hsf_run_paths_rows(h, 0, 1, 0, ma + 1, dummy, ma, None, 0, None, 0, None) == 1
+    assert "row range" in lib.hsf_last_error().decode()
+    assert lib.hsf_run_paths_rows(h, 0, 1, 0, 1, dummy, ma - 1, None, 0, None, 0, None) == 1
+    assert lib.hsf_run_paths_rows(h, 0, 1, 0, 1, dummy, ma, dummy, mb - 1, None, 0, None) == 1
+    assert lib.hsf_run_paths_rows(h, 0, p.P + 1, 0, 1, dummy, ma, None, 0, None, 0, None) == 1
+    assert "path range" in lib.hsf_last_error().decode()
+    assert lib.hsf_run_paths_rows(h, 2, 2, 0, 1, dummy, ma, None, 0, None, 0, None) == 0
