@@ -1275,21 +1275,38 @@ hsf_status backward_t(Plan& p, DeviceCopy& d, const uint64_t* x, int64_t nx, con
                 if (!used_sched[2 * side + tr][q]) continue;
                 const Schedule& sc = (tr ? p.side[side].tree : p.side[side].sched)[q];
                 std::vector<cd> pl = sc.pool;
+                // rank m's matrix of a patched piece, with the gates the
+                // plan folded into that piece (post * f_m)
+                auto patched = [&](const std::vector<cd>& f, int m, size_t d2, const std::vector<cd>& post) {
+                    std::vector<cd> fm(f.begin() + (size_t)m * d2, f.begin() + (size_t)(m + 1) * d2);
+                    if (post.empty()) return fm;
+                    std::vector<cd> out(4, cd(0));
+                    for (int i = 0; i < 2; ++i)
+                        for (int j = 0; j < 2; ++j)
+                            for (int l = 0; l < 2; ++l) out[(size_t)i * 2 + j] += post[(size_t)i * 2 + l] * fm[(size_t)l * 2 + j];
+                    return out;
+                };
                 for (const DevOp& op : sc.devops)
                     if (op.type == DOP_SLOT && op.block == (int)sh.k) {
                         const std::vector<cd>& f = pcs[op.piece].m;
                         const size_t d2 = (size_t)1 << (2 * op.k);
-                        for (int m = 0; m < b.rank; ++m)
-                            for (size_t e2 = 0; e2 < d2; ++e2)
-                                pl[op.mat + m * d2 + e2] = m < r ? f[m * d2 + e2] : cd(0);
+                        static const std::vector<cd> none;
+                        const std::vector<cd>* post = &none;
+                        for (const SideOp& so : p.side[side].ops)
+                            if (so.kind == SideOp::SLOT && so.block == op.block && so.piece == op.piece) post = &so.post;
+                        for (int m = 0; m < b.rank; ++m) {
+                            const std::vector<cd> fm = m < r ? patched(f, m, d2, *post) : std::vector<cd>(d2, cd(0));
+                            for (size_t e2 = 0; e2 < d2; ++e2) pl[op.mat + m * d2 + e2] = fm[e2];
+                        }
                     }
                 // one-qubit factor pieces applied inside register groups
                 for (const SubOp& so : sc.subs)
                     if (so.type == SUB_SLOT1 && so.block == (int)sh.k) {
                         const std::vector<cd>& f = pcs[so.piece].m;
-                        for (int m = 0; m < b.rank; ++m)
-                            for (size_t e2 = 0; e2 < 4; ++e2)
-                                pl[so.mat + m * 4 + e2] = m < r ? f[m * 4 + e2] : cd(0);
+                        for (int m = 0; m < b.rank; ++m) {
+                            const std::vector<cd> fm = m < r ? patched(f, m, 4, so.post) : std::vector<cd>(4, cd(0));
+                            for (size_t e2 = 0; e2 < 4; ++e2) pl[so.mat + m * 4 + e2] = fm[e2];
+                        }
                     }
                 if (pl.empty()) pl.push_back(cd(0));
                 all.insert(all.end(), pl.begin(), pl.end());

@@ -94,7 +94,15 @@ struct SideOp {
     int64_t logical = 1;     // circuit gates represented by this op
     int param_id = -1;       // rotation angle of a single gate (before fusion), -1 if none
     std::vector<cd> dgen;    // D with dU/dparam = D U on the op's qubits (param_id >= 0)
+    // SLOT on one qubit: the one-qubit gates that followed the piece on its
+    // qubit, folded into it (2x2, applied after each rank's matrix); empty:
+    // none
+    std::vector<cd> post;
 };
+
+// Rank r's 2^k x 2^k matrix of a factor slot with its folded gates applied
+// (post * m_r for a one-qubit piece).
+std::vector<cd> slot_matrix(const SideOp& o, int r);
 
 // Device op (plain data, read by the sweep kernels).
 // A register group whose bits all lie below 6 + k ("wave-private") maps the
@@ -140,6 +148,7 @@ struct SubOp {
     int32_t rank = 1;
     int64_t stride = 1;
     int32_t block = -1, piece = 0;
+    std::vector<cd> post;  // SLOT1: the slot's folded gates (empty: none)
 };
 
 struct Pass {

@@ -663,12 +663,23 @@ std::vector<cd> as_dense1(const SideOp& o) {
 }
 
 // Merge runs of one-qubit ops on the same qubit (exact in real arithmetic),
-// then fold diagonal ops into the diagonal op placed before them when their
-// union stays within kMaxOpQubits qubits and nothing in between touches them.
+// fold one-qubit ops that directly follow a one-qubit factor piece on its
+// qubit into the piece (its `post`: the path's digit still picks the piece,
+// the folded gates are the same for every digit), then fold diagonal ops
+// into the diagonal op placed before them when their union stays within
+// kMaxOpQubits qubits and nothing in between touches them.
 void fuse_ops(std::vector<SideOp>& ops, int nq) {
     std::vector<SideOp> out;
     std::vector<int> pend(nq, -1);  // index in `out` of a one-qubit op still open on q
+    std::vector<int> spend(nq, -1); // index in `out` of a one-qubit factor piece still open on q
     for (SideOp& o : ops) {
+        if (o.kind != SideOp::SLOT && o.k == 1 && spend[o.q[0]] >= 0) {
+            SideOp& t = out[spend[o.q[0]]];
+            const std::vector<cd> prev = t.post.empty() ? std::vector<cd>{1, 0, 0, 1} : t.post;
+            t.post = mat_mul(as_dense1(o), prev, 2);
+            t.logical += o.logical;
+            continue;
+        }
         if (o.kind != SideOp::SLOT && o.k == 1 && pend[o.q[0]] >= 0) {
             SideOp& t = out[pend[o.q[0]]];
             if (t.kind == SideOp::DIAG && o.kind == SideOp::DIAG) {
@@ -681,9 +692,10 @@ void fuse_ops(std::vector<SideOp>& ops, int nq) {
             t.logical += o.logical;
             continue;
         }
-        for (int j = 0; j < o.k; ++j) pend[o.q[j]] = -1;
+        for (int j = 0; j < o.k; ++j) pend[o.q[j]] = spend[o.q[j]] = -1;
         out.push_back(std::move(o));
         if (out.back().kind != SideOp::SLOT && out.back().k == 1) pend[out.back().q[0]] = (int)out.size() - 1;
+        if (out.back().kind == SideOp::SLOT && out.back().k == 1) spend[out.back().q[0]] = (int)out.size() - 1;
     }
     // diagonal folding
     std::vector<SideOp> res;
@@ -757,9 +769,16 @@ void fuse_side(Plan& p, int s) {
 // An op that is diagonal.  A factor slot counts only in the product form,
 // which is diagonal for every angle of its block: the backward pass
 // re-factors blocks at shifted angles and reuses this plan's op order.
+std::vector<cd> slot_matrix(const SideOp& o, int r) {
+    const size_t d2 = (size_t)1 << (2 * o.k);
+    std::vector<cd> m(o.m.begin() + (size_t)r * d2, o.m.begin() + (size_t)(r + 1) * d2);
+    if (o.post.empty()) return m;
+    return mat_mul(o.post, m, 2);
+}
+
 bool op_is_diagonal(const SideOp& o) {
     if (o.kind == SideOp::DIAG) return true;
-    if (o.kind == SideOp::SLOT) return o.product;
+    if (o.kind == SideOp::SLOT) return o.product && (o.post.empty() || (o.post[1] == cd(0) && o.post[2] == cd(0)));
     const int d = 1 << o.k;
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j)
@@ -938,9 +957,13 @@ void emit_pass(const std::vector<SideOp>& sops, Schedule& sc, const Pass& ps, co
             if (o.kind == SideOp::SLOT) {
                 so.type = SUB_SLOT1;
                 so.g = pos_in(bits, tbit(o.q[0]));
-                so.qb[0] = op_is_diagonal(o) ? 1 : 0;   // bit 0: diagonal; bit 1: chained (below)
+                so.qb[0] = op_is_diagonal(o) ? 1 : 0;   // bit 0: diagonal; bits 1, 2: chains (below)
                 so.mat = (int32_t)sc.pool.size();
-                sc.pool.insert(sc.pool.end(), o.m.begin(), o.m.end());
+                for (int r = 0; r < o.rank; ++r) {
+                    const std::vector<cd> f = slot_matrix(o, r);
+                    sc.pool.insert(sc.pool.end(), f.begin(), f.end());
+                }
+                so.post = o.post;
                 so.rank = o.rank;
                 so.stride = o.stride;
                 so.block = o.block;
@@ -996,12 +1019,16 @@ void emit_pass(const std::vector<SideOp>& sops, Schedule& sc, const Pass& ps, co
             sc.subs.push_back(so);
         }
         // a diagonal piece followed by another on the same register bit only
-        // multiplies into the chain; the last of the chain applies it
+        // multiplies into the chain; the last of the chain (diagonal, or a
+        // piece with folded gates) applies it
         for (int j = d.mat; j + 1 < d.mat + d.rank; ++j) {
             SubOp& x = sc.subs[j];
             const SubOp& y = sc.subs[j + 1];
-            if (x.type == SUB_SLOT1 && y.type == SUB_SLOT1 && (x.qb[0] & 1) && (y.qb[0] & 1) && x.g == y.g)
-                x.qb[0] |= 2;
+            SubOp& y2 = sc.subs[j + 1];
+            if (x.type == SUB_SLOT1 && y.type == SUB_SLOT1 && (x.qb[0] & 1) && x.g == y.g) {
+                x.qb[0] |= 2;    // bit 1: chained into the next
+                y2.qb[0] |= 4;   // bit 2: ends (or continues) a chain
+            }
         }
         sc.devops.push_back(d);
         grp.clear();
@@ -1030,7 +1057,14 @@ void emit_pass(const std::vector<SideOp>& sops, Schedule& sc, const Pass& ps, co
             d.stride = o.stride;
             d.block = o.block;
             d.piece = o.piece;
-            sc.pool.insert(sc.pool.end(), o.m.begin(), o.m.end());
+            if (o.kind == SideOp::SLOT) {
+                for (int r = 0; r < o.rank; ++r) {
+                    const std::vector<cd> f = slot_matrix(o, r);
+                    sc.pool.insert(sc.pool.end(), f.begin(), f.end());
+                }
+            } else {
+                sc.pool.insert(sc.pool.end(), o.m.begin(), o.m.end());
+            }
             sc.devops.push_back(d);
         }
     }

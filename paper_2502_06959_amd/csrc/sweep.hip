@@ -183,6 +183,15 @@ __device__ __forceinline__ void d1g(V (&v)[1 << K], V m00, V m01, V m10, V m11) 
     }
 }
 
+// Diagonal 2x2 (f00, f11) on register position G: one product per amplitude.
+template <int K, int G, typename V>
+__device__ __forceinline__ void d1diag(V (&v)[1 << K], V f00, V f11) {
+    if constexpr (G < K) {
+#pragma unroll
+        for (int j = 0; j < (1 << K); ++j) v[j] = cmul((j & (1 << G)) ? f11 : f00, v[j]);
+    }
+}
+
 // S1: the group may hold one-qubit factor pieces (SUB_SLOT1); instantiated
 // separately so the kernels of passes without them keep their code.
 template <int K, typename T, bool S1>
@@ -250,10 +259,23 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
                 /* diagonal piece followed by another on this bit: multiply into the chain */           \
                 ch0 = cmul(f00, ch0);                                                                    \
                 ch1 = cmul(f11, ch1);                                                                    \
+            } else if (fl & 1) {                                                                         \
+                /* last diagonal piece of a chain: apply the product, one product per amplitude */      \
+                f00 = cmul(f00, ch0);                                                                    \
+                f11 = cmul(f11, ch1);                                                                    \
+                ch0.x = T(1); ch0.y = T(0); ch1 = ch0;                                                   \
+                switch ((so).g) {                                                                        \
+                    case 0: d1diag<K, 0>(v, f00, f11); break;                                            \
+                    case 1: d1diag<K, 1>(v, f00, f11); break;                                            \
+                    case 2: d1diag<K, 2>(v, f00, f11); break;                                            \
+                    default: d1diag<K, 3>(v, f00, f11); break;                                           \
+                }                                                                                        \
             } else {                                                                                     \
-                if (fl & 1) {                                                                            \
-                    /* last diagonal piece of a chain: apply the product */                             \
+                if (fl & 4) {                                                                            \
+                    /* a piece with folded gates ends a chain: the chain's diagonal comes first */        \
                     f00 = cmul(f00, ch0);                                                                \
+                    f10 = cmul(f10, ch0);                                                                \
+                    f01 = cmul(f01, ch1);                                                                \
                     f11 = cmul(f11, ch1);                                                                \
                     ch0.x = T(1); ch0.y = T(0); ch1 = ch0;                                               \
                 }                                                                                        \

@@ -239,13 +239,14 @@ def test_shared_prefix_hoists_commuting_ops():
              g("H", (2,)),             # a: dense on the slot's qubit -> per path
              g("H", (3,)),             # a: disjoint from everything left behind -> shared
              g("H", (0,)),             # b: disjoint from the slot on 1 -> shared
-             g("H", (1,))]             # b: dense on the slot's qubit -> per path
+             g("H", (1,))]             # b: right after the slot on its qubit -> folded into its pieces
     p = Plan(cg.circuit("prefix", 4, gates, 1, [[0]]))
     a, b = p.side_stats(0), p.side_stats(1)
     # side a: slot, H(3), RZZ, H(2), H(3) (the RZZ keeps the two H(3) apart);
     # shared: H(3), RZZ, H(3)
     assert a["ops_shared"] == 3 and a["ops_fused"] == 5
-    assert b["ops_shared"] == 1 and b["ops_fused"] == 3
+    # side b: the slot (with H(1) folded in, per path) and H(0) (shared)
+    assert b["ops_shared"] == 1 and b["ops_fused"] == 2
     # a dense op on the qubit of a dense factor slot stays per path
     gates2 = [g("CX", (1, 2)), g("H", (2,)), g("H", (3,))]
     p2 = Plan(cg.circuit("prefix2", 4, gates2, 1, [[0]]))
