@@ -160,6 +160,10 @@ struct Pass {
     int32_t nonlocal_q[kMaxTileBits] = {};
     int32_t has_slot1 = 0;             // some group applies a one-qubit factor piece (SUB_SLOT1)
     int32_t prefix = 0;                // applies ops of the path-independent prefix only
+    // one register group is the whole pass: each thread takes its group's
+    // amplitudes straight from the source row and stores them to the
+    // destination (no LDS tile, no barriers); its filler bits are high tile bits
+    int32_t direct = 0;
 };
 
 // One level of a path-tree schedule: passes [pass_begin, pass_end) apply

@@ -1156,6 +1156,50 @@ Schedule schedule_side(const Plan& p, int s, int L, const std::vector<SideOp>& o
             ps.op_begin = (int32_t)sc.devops.size();
             emit_pass(ops, sc, ps, ids, group_slots);
             ps.op_end = (int32_t)sc.devops.size();
+            // a pass that is one register group runs without the LDS tile; the
+            // group's filler bits (positions no sub-op reads) move to the
+            // highest free tile bits, so the lanes of a wave, which vary the
+            // low bits, read and write runs of contiguous amplitudes
+            if (ps.op_end == ps.op_begin + 1 && sc.devops[(size_t)ps.op_begin].type == DOP_GROUP) {
+                DevOp& d = sc.devops[(size_t)ps.op_begin];
+                std::vector<char> used_pos((size_t)d.k, 0), taken((size_t)ps.n_local, 0);
+                for (int j = d.mat; j < d.mat + d.rank; ++j) {
+                    const SubOp& so = sc.subs[(size_t)j];
+                    if (so.type == SUB_D1 || so.type == SUB_SLOT1) {
+                        used_pos[(size_t)so.g] = 1;
+                    } else {
+                        // a diagonal op's table depends on every register position; its
+                        // controls outside the group must stay outside it
+                        for (int g = 0; g < d.k; ++g) used_pos[(size_t)g] = 1;
+                        for (int i = 0; i < so.nc; ++i)
+                            if (so.qb[i] >= 0) taken[(size_t)so.qb[i]] = 1;
+                    }
+                }
+                for (int g = 0; g < d.k; ++g)
+                    if (used_pos[(size_t)g]) taken[(size_t)d.bit[g]] = 1;
+                int nb[kMaxTileBits];
+                for (int g = 0; g < d.k; ++g) nb[g] = d.bit[g];
+                int hi = ps.n_local - 1;
+                bool ok = true;
+                for (int g = 0; g < d.k && ok; ++g) {
+                    if (used_pos[(size_t)g]) continue;
+                    while (hi >= 0 && taken[(size_t)hi]) --hi;
+                    if (hi < 0) ok = false;
+                    else {
+                        nb[g] = hi;
+                        taken[(size_t)hi] = 1;
+                    }
+                }
+                for (int g = 0; g < d.k && ok; ++g)
+                    for (int h = g + 1; h < d.k; ++h) ok = ok && nb[g] != nb[h];
+                // a group on the three lowest tile bits would read eight
+                // scattered amplitudes per lane: keep the LDS tile there
+                for (int g = 0; g < d.k && ok; ++g) ok = nb[g] >= 3;
+                if (ok) {
+                    for (int g = 0; g < d.k; ++g) d.bit[g] = nb[g];
+                    ps.direct = 1;
+                }
+            }
             // barriers: only between ops that are not both wave-private (a wave
             // holds 64 lanes x 2^k amplitudes of a group, tile bits 0 .. 5+k)
             auto wave_private = [&](const DevOp& d) {

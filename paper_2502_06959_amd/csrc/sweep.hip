@@ -194,10 +194,15 @@ __device__ __forceinline__ void d1diag(V (&v)[1 << K], V f00, V f11) {
 
 // S1: the group may hold one-qubit factor pieces (SUB_SLOT1); instantiated
 // separately so the kernels of passes without them keep their code.
-template <int K, typename T, bool S1>
+// DIRECT: the pass is this one group (Pass::direct): amplitudes come from
+// src and go to st at their row indices (gmap maps tile bits to side
+// qubits), no LDS tile; init: the first pass, from |0...0>.
+template <int K, typename T, bool S1, bool DIRECT = false>
 __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E, const DevOp& op,
                                             ctab<DSub<T>> subs, const typename Cx<T>::v* __restrict__ pool,
-                                            uint64_t gbase, int64_t path, int tid, int nt) {
+                                            uint64_t gbase, int64_t path, int tid, int nt,
+                                            ctab<Pass> ps = nullptr, typename Cx<T>::v* st = nullptr,
+                                            const typename Cx<T>::v* src = nullptr, int init = 0) {
     const ctab<T> pool_s = as_table(reinterpret_cast<const T*>(pool));   // uniform reads of factor pieces
     using V = typename Cx<T>::v;
     constexpr int D = 1 << K;
@@ -206,14 +211,23 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
     // the swizzle is linear over XOR and a group's base and register bits
     // are disjoint: slot(base | off_j) = swz(base) ^ swz(off_j)
     uint32_t soff[D];
+    uint64_t goff[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         uint32_t o = 0;
+        uint64_t go = 0;
 #pragma unroll
         for (int g = 0; g < K; ++g)
-            if ((j >> g) & 1) o |= 1u << op.bit[g];
+            if ((j >> g) & 1) {
+                o |= 1u << op.bit[g];
+                if constexpr (DIRECT) go |= uint64_t(1) << ps->local_q[op.bit[g]];
+            }
         soff[j] = swz(o);
+        goff[j] = go;
     }
+    int nc = 0;
+    if constexpr (DIRECT)
+        while (nc < ps->n_local && ps->local_q[nc] == nc) ++nc;
     const int s0 = op.mat, ns = op.rank;
     const uint32_t groups = E >> K;
     for (uint32_t gi = tid; gi < groups; gi += nt) {
@@ -222,8 +236,24 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
         for (int i = 0; i < K; ++i) base = ins0(base, sb[i]);
         const uint32_t sbase = swz(base);
         V v[D];
+        uint64_t gb = 0;
+        if constexpr (DIRECT) {
+            // the group's row index: the tile's non-local bits, then its local bits
+            gb = gbase | (base & ((1u << nc) - 1u));
+            for (int i = nc; i < ps->n_local; ++i) gb |= (uint64_t)((base >> i) & 1u) << ps->local_q[i];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = tile[sbase ^ soff[j]];
+            for (int j = 0; j < D; ++j) {
+                if (init) {
+                    v[j].x = (gb | goff[j]) == 0 ? T(1) : T(0);
+                    v[j].y = T(0);
+                } else {
+                    v[j] = src[gb | goff[j]];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < D; ++j) v[j] = tile[sbase ^ soff[j]];
+        }
         // Records alternate between two register sets (unrolled by two, the
         // next index clamped so the loads are unconditional): the next
         // record's scalar loads are issued before the current one is applied,
@@ -322,8 +352,13 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
             HSF_APPLY_SUB(rb);
         }
 #undef HSF_APPLY_SUB
+        if constexpr (DIRECT) {
 #pragma unroll
-        for (int j = 0; j < D; ++j) tile[sbase ^ soff[j]] = v[j];
+            for (int j = 0; j < D; ++j) st[gb | goff[j]] = v[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < D; ++j) tile[sbase ^ soff[j]] = v[j];
+        }
     }
 }
 
@@ -355,6 +390,13 @@ __device__ __forceinline__ void sweep_tile(ctab<Pass> ps, ctab<DevOp> ops, ctab<
         for (int i = nc; i < L; ++i) g |= (uint64_t)((e >> i) & 1u) << ps->local_q[i];
         return g;
     };
+
+    if (ps->direct) {
+        // the pass is one register group: row to row, no LDS tile
+        const DevOp op = ops[ps->op_begin];
+        apply_group<KG, T, S1, true>(tile, E, op, subs, pool, base, path, tid, nt, ps, st, src, ps->init_zero);
+        return;
+    }
 
     if (ps->init_zero) {
         for (uint32_t e = tid; e < E; e += nt) {
