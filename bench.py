@@ -781,8 +781,8 @@ class _PathWindow:
     def handle(self):
         return self.plan.handle
 
-    def run_paths(self, p0, p1, A, B, ws=None):
-        return self.plan.run_paths(p0, p1, A, B, ws=ws)
+    def run_paths(self, p0, p1, A, B, ws=None, rows=None):
+        return self.plan.run_paths(p0, p1, A, B, ws=ws, rows=rows)
 
     def amplitudes_full(self, *a, **k):
         return self.plan.amplitudes_full(*a, **k)
