@@ -414,6 +414,15 @@ hsf_status hsf_batch_run(hsf_batch_t batch, void* const* outs, int32_t mode, int
  * returns it in *policy.  Synchronises `stream`.                             */
 hsf_status hsf_batch_tune(hsf_batch_t batch, void* const* outs, int32_t mode, void* ws, size_t ws_bytes,
                           hsf_stream_t stream, int32_t* policy);
+/* Tuner cache: every successful hsf_batch_tune records its choice in a
+ * process-wide table keyed by the path-sum mode and, circuit by circuit in
+ * batch order, n_a, n_b, the path count and each side's fused op count.
+ * hsf_batch_tune_cached looks `batch` up there: on a hit it applies the
+ * recorded policy to the batch (as hsf_batch_tune would) and returns it in
+ * *policy; otherwise *policy = -1 and the batch is unchanged.  Host only (no
+ * device work, no timing); HSF_E_ARG for a null batch or policy or a mode
+ * other than HSF_SUM_F32 / HSF_SUM_BF16X3.  Thread-safe.                     */
+hsf_status hsf_batch_tune_cached(hsf_batch_t batch, int32_t mode, int32_t* policy);
 
 /* Thread-local message for the last non-OK status on this thread.            */
 const char* hsf_last_error(void);

@@ -85,6 +85,7 @@ SIGNATURES = {
     "hsf_batch_workspace_size": (c_size_t, [c_void_p, c_int32]),
     "hsf_batch_run": (c_int32, [c_void_p, P(c_void_p), c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "hsf_batch_tune": (c_int32, [c_void_p, P(c_void_p), c_int32, c_void_p, c_size_t, c_void_p, P(c_int32)]),
+    "hsf_batch_tune_cached": (c_int32, [c_void_p, c_int32, P(c_int32)]),
     "hsf_last_error": (ctypes.c_char_p, []),
     "hsf_version": (ctypes.c_char_p, []),
 }

@@ -411,4 +411,13 @@ hsf_status hsf_batch_tune(hsf_batch_t batch, void* const* outs, int32_t mode, vo
     HSF_GUARD_END
 }
 
+hsf_status hsf_batch_tune_cached(hsf_batch_t batch, int32_t mode, int32_t* policy) {
+    HSF_GUARD_BEGIN
+    if (!batch || !policy) return fail(HSF_E_ARG, "null batch or policy");
+    if (mode != HSF_SUM_F32 && mode != HSF_SUM_BF16X3) return fail(HSF_E_ARG, "batches use HSF_SUM_F32 or HSF_SUM_BF16X3");
+    *policy = batch_tune_cached(*reinterpret_cast<Batch*>(batch), mode);
+    return HSF_OK;
+    HSF_GUARD_END
+}
+
 }  // extern "C"

@@ -5,6 +5,8 @@
 // an autotuner picks the tile policy by timing the candidates on the device.
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -364,6 +366,37 @@ hsf_status batch_run(Batch& b, void* const* outs, int mode, int use_graph, void*
     return hip_check(hipGraphLaunch(b.exec, st), "hipGraphLaunch");
 }
 
+namespace {
+
+// Tuned policies by batch shape, shared by the process: the path-sum mode
+// and, circuit by circuit in batch order, n_a, n_b, P and the fused op count
+// of each side.
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, int> g_tune_cache;
+
+std::vector<int64_t> tune_key(const Batch& b, int mode) {
+    std::vector<int64_t> k{mode, (int64_t)b.plans.size()};
+    for (const Plan* p : b.plans) {
+        k.push_back(p->na);
+        k.push_back(p->nb);
+        k.push_back(p->P);
+        k.push_back((int64_t)p->side[0].ops.size());
+        k.push_back((int64_t)p->side[1].ops.size());
+    }
+    return k;
+}
+
+}  // namespace
+
+int batch_tune_cached(Batch& b, int mode) {
+    const std::vector<int64_t> k = tune_key(b, mode);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune_cache.find(k);
+    if (it == g_tune_cache.end()) return -1;
+    b.policy = it->second;
+    return it->second;
+}
+
 hsf_status batch_tune(Batch& b, void* const* outs, int mode, void* ws, hipStream_t st, int* chosen) {
     hipEvent_t e0, e1;
     hsf_status s;
@@ -394,6 +427,10 @@ hsf_status batch_tune(Batch& b, void* const* outs, int mode, void* ws, hipStream
     (void)hipEventDestroy(e1);
     b.policy = best_p;
     if (chosen) *chosen = best_p;
+    if (s == HSF_OK) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[tune_key(b, mode)] = best_p;
+    }
     return s;
 }
 

@@ -350,6 +350,9 @@ void batch_destroy(Batch* b);
 size_t batch_workspace(const Batch& b, int mode);
 hsf_status batch_run(Batch& b, void* const* outs, int mode, int use_graph, void* ws, hipStream_t st);
 hsf_status batch_tune(Batch& b, void* const* outs, int mode, void* ws, hipStream_t st, int* chosen);
+// The policy an earlier batch_tune in this process chose for a batch of the
+// same shapes and mode, applied to b; -1 (b unchanged) if there is none.
+int batch_tune_cached(Batch& b, int mode);
 
 // Device side (sweep.hip / pathsum.hip).
 hsf_status ensure_device(Plan& p, DeviceCopy** out);

@@ -474,9 +474,23 @@ class Batch:
                                       1 if graph else 0, _ptr(ws), ws.numel(), _stream(outs[0])))
         return outs
 
-    def tune(self, outs, mode="bf16x3"):
+    def tune(self, outs, mode="bf16x3", cached=False):
+        """Times the sweep policies and keeps the fastest (hsf_batch_tune);
+        with cached=True a policy recorded for a batch of the same shapes in
+        this process is applied instead when there is one."""
+        if cached:
+            pol = self.tuned_policy(mode)
+            if pol >= 0:
+                return pol
         ws = self.workspace(mode, outs[0].device)
         pol = ctypes.c_int32()
         L.check(L.lib().hsf_batch_tune(ctypes.c_void_p(self.handle), self._outs(outs), L.SUM_MODE[mode], _ptr(ws),
                                        ws.numel(), _stream(outs[0]), ctypes.byref(pol)))
+        return pol.value
+
+    def tuned_policy(self, mode="bf16x3"):
+        """The policy recorded for this batch's shapes (applied to it), or -1
+        (hsf_batch_tune_cached; host only)."""
+        pol = ctypes.c_int32()
+        L.check(L.lib().hsf_batch_tune_cached(ctypes.c_void_p(self.handle), L.SUM_MODE[mode], ctypes.byref(pol)))
         return pol.value

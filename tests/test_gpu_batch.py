@@ -76,3 +76,18 @@ def test_autotune_keeps_results(small_batch):
     torch.cuda.synchronize()
     for c, o in zip(cs, outs):
         assert ohsf.rel_l2(o.cpu().numpy().reshape(-1), sv.run(c)) < 1e-5
+    # the choice is recorded for this batch shape: a second batch of the same
+    # plans takes it without timing and gives the same amplitudes
+    b2 = Batch(plans)
+    assert b2.tuned_policy("bf16x3") == pol
+    assert b2.tune(b2.alloc_outputs(), mode="bf16x3", cached=True) == pol
+    outs2 = b2.alloc_outputs()
+    b2.run(outs2, mode="bf16x3", graph=False)
+    torch.cuda.synchronize()
+    for o, o2 in zip(outs, outs2):
+        assert torch.equal(o, o2)
+    # another shape (one circuit fewer) has no record
+    b3 = Batch(plans[:-1])
+    assert b3.tuned_policy("bf16x3") == -1
+    for x in (b2, b3):
+        x.close()

@@ -278,3 +278,21 @@ def test_run_paths_rows_argument_checks():
     assert lib.hsf_run_paths_rows(h, 0, p.P + 1, 0, 1, dummy, ma, None, 0, None, 0, None) == 1
     assert "path range" in lib.hsf_last_error().decode()
     assert lib.hsf_run_paths_rows(h, 2, 2, 0, 1, dummy, ma, None, 0, None, 0, None) == 0
+
+
+def test_batch_tune_cache_lookup_on_the_host():
+    """hsf_batch_tune_cached: no recorded policy for a fresh batch shape (-1,
+    host only, no device work), argument checks through the C ABI."""
+    from paper_2502_06959_amd.hsf import Batch
+    plans = [Plan(c, dtype="c64") for c in cg.c5(count=2)]
+    b = Batch(plans)
+    try:
+        assert b.tuned_policy("bf16x3") == -1
+        assert b.tuned_policy("f32") == -1
+        pol = ctypes.c_int32(7)
+        assert L.lib().hsf_batch_tune_cached(ctypes.c_void_p(b.handle), L.SUM_MODE["f64"], ctypes.byref(pol)) != 0
+        assert L.lib().hsf_batch_tune_cached(None, L.SUM_MODE["bf16x3"], ctypes.byref(pol)) != 0
+        assert L.lib().hsf_batch_tune_cached(ctypes.c_void_p(b.handle), L.SUM_MODE["bf16x3"], None) != 0
+        assert pol.value == 7
+    finally:
+        b.close()
