@@ -56,7 +56,7 @@ typedef enum {
     HSF_E_RANK_AMBIGUOUS = 7,   /* a singular-value ratio lies in (1e-13, 1e-7]      */
     HSF_E_PATHS_OVERFLOW = 8,   /* more than 2^62 paths                              */
     HSF_E_DEVICE = 9,           /* HIP error (allocation, launch, copy)              */
-    HSF_E_UNSUPPORTED = 10      /* valid request this build does not implement       */
+    HSF_E_UNSUPPORTED = 10      /* valid request the library does not implement      */
 } hsf_status;
 
 typedef enum {
