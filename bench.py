@@ -222,6 +222,9 @@ def main():
                     help="timed steps of the plain FP32 leg (default: all steps, at most 2 on c4)")
     ap.add_argument("--qaoa-instances", default=None,
                     help="comma-separated Table II names (q30-1, ...) to run with --workload qaoa (default: all 12)")
+    ap.add_argument("--no-defer", action="store_true",
+                    help="qaoa: keep side b's gates after its last factor slot in every path's half-state "
+                         "instead of applying them once to the output rows")
     ap.add_argument("--no-standard", action="store_true",
                     help="--workload qaoa: skip the standard-cutting comparison runs")
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -696,6 +699,8 @@ def _first_amplitudes(plan, chunk, rows, mode, out):
         # side a only where the first `rows` rows are: its last pass runs only their tiles
         plan.run_paths(p0, p0 + n, A[:n], B[:n], ws=ws, rows=(0, rows))
         plan.amplitudes_full(A[:n], B[:n], n_paths=n, rows=(0, rows), mode=mode, out=out, accumulate=p0 > 0)
+    # side b's deferred gates, once on the summed rows (no-op without deferral)
+    plan.apply_b_suffix(out, rows)
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
@@ -722,7 +727,7 @@ def bench_qaoa(args):
         c = cg.qaoa_sbm(100 + i, sizes, 0.8, pout)
         t0 = time.perf_counter()
         r = joint_blocked(c)
-        pj = Plan(r, tree=args.tree)
+        pj = Plan(r, tree=args.tree, defer_b_suffix=not args.no_defer)
         host_ms = (time.perf_counter() - t0) * 1e3
         rows = (10 ** 6 + (1 << pj.nb) - 1) >> pj.nb
         out = torch.empty((rows, 1 << pj.nb), dtype=torch.complex64, device="cuda")
@@ -733,7 +738,7 @@ def bench_qaoa(args):
         std = dict(c)
         std["blocks"] = [[k] for k, g in enumerate(c["gates"])
                          if 0 < sum(q <= c["cut"] for q in g["q"]) < len(g["q"])]
-        ps = Plan(std, tree=args.tree)
+        ps = Plan(std, tree=args.tree, defer_b_suffix=not args.no_defer)
         if args.no_standard:
             t_ms, t_kind = float("nan"), "skipped"
         elif ps.P <= (1 << 16):
@@ -760,7 +765,8 @@ def bench_qaoa(args):
            "ms_per_step": total_j, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": f"c64 (f32 sweeps, {mode} path sum)", "data": "synthetic",
            "config": {"workload": "qaoa: single-layer QAOA MaxCut on seeded SBM graphs, Table II sizes, "
-                                  "p_intra 0.8, first 10^6 amplitudes"},
+                                  "p_intra 0.8, first 10^6 amplitudes",
+                      "defer_b_suffix": not args.no_defer},
            "instances": rows_out,
            "geomean_standard_over_joint": (float(np.exp(np.mean([np.log(x["standard_over_joint"]) for x in rows_out])))
                                            if not args.no_standard else None)}
@@ -783,6 +789,9 @@ class _PathWindow:
 
     def run_paths(self, p0, p1, A, B, ws=None, rows=None):
         return self.plan.run_paths(p0, p1, A, B, ws=ws, rows=rows)
+
+    def apply_b_suffix(self, out, rows=None):
+        return self.plan.apply_b_suffix(out, rows)
 
     def amplitudes_full(self, *a, **k):
         return self.plan.amplitudes_full(*a, **k)

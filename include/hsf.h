@@ -115,6 +115,9 @@ typedef struct {
     int32_t tree;            /* path-tree sweeps (hsf_side_levels): 0 = where the
                                 planner's cost estimate favours them (default),
                                 1 = never, 2 = always                               */
+    int32_t defer_b_suffix;  /* 1 = side b's ops after its last factor slot are
+                                left out of the half-states and applied to output
+                                rows by hsf_apply_b_suffix (default 0)             */
 } hsf_plan_options;
 
 /* ---------------------------------------------------------------- plan ---- */
@@ -146,6 +149,27 @@ hsf_status hsf_plan(const hsf_circuit* circuit, int32_t cut, const int64_t* bloc
                     const int64_t* block_offsets, int32_t n_blocks,
                     const hsf_plan_options* opts, hsf_plan_t* out);
 void hsf_plan_destroy(hsf_plan_t plan);
+
+/* Deferred side-b suffix (Sec. II-B, by linearity of the path sum).  With
+ * hsf_plan_options.defer_b_suffix = 1, side b's program stops at its last
+ * factor slot: the gates after it act on every path's side-b state alike, so
+ * for each output row (x >> n_b fixed) they can be applied once to the row's
+ * 2^{n_b} amplitudes after the sum over paths instead of to every path's
+ * half-state.  This pays when few rows are wanted (the first amplitudes of
+ * Sec. V: a few rows of 2^{n_b} amplitudes against P half-states).  Such a
+ * plan's half-states (hsf_run_paths) and path sums (hsf_amplitudes_full,
+ * hsf_amplitudes_full_noalloc) lack those gates until hsf_apply_b_suffix
+ * runs on the output rows; hsf_amplitudes_bitstrings, hsf_loss,
+ * hsf_backward and hsf_batch_create reject the plan (HSF_E_UNSUPPORTED).
+ *   out    device, `rows` rows of 2^{n_b} amplitudes (c64 or c128 as the
+ *          plan), row r at out + r * ldo elements; updated in place.
+ *   ldo    >= 2^{n_b}.
+ * Call it once per row, after every path has been summed into it (the ops
+ * are linear, so rows summed in several accumulating calls take it once at
+ * the end).  A plan without a deferred suffix returns HSF_OK and leaves
+ * `out` unchanged.  Asynchronous on `stream`; HSF_E_ARG for null arguments,
+ * rows < 0 or ldo < 2^{n_b}.                                                 */
+hsf_status hsf_apply_b_suffix(hsf_plan_t plan, void* out, int64_t ldo, int64_t rows, hsf_stream_t stream);
 
 /* Joint blocks for a cut (host only), Sec. III-A and Sec. V: the gates of
  * every maximal run of consecutive diagonal gates commute, so the run's

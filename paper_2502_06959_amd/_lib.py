@@ -33,7 +33,7 @@ class HsfCircuit(ctypes.Structure):
 
 class HsfPlanOptions(ctypes.Structure):
     _fields_ = [("rank_tol", c_double), ("max_side_qubits", c_int32), ("dtype", c_int32),
-                ("tile_qubits", c_int32), ("fuse", c_int32), ("tree", c_int32)]
+                ("tile_qubits", c_int32), ("fuse", c_int32), ("tree", c_int32), ("defer_b_suffix", c_int32)]
 
 
 class HsfError(RuntimeError):
@@ -86,6 +86,7 @@ SIGNATURES = {
     "hsf_batch_run": (c_int32, [c_void_p, P(c_void_p), c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "hsf_batch_tune": (c_int32, [c_void_p, P(c_void_p), c_int32, c_void_p, c_size_t, c_void_p, P(c_int32)]),
     "hsf_batch_tune_cached": (c_int32, [c_void_p, c_int32, P(c_int32)]),
+    "hsf_apply_b_suffix": (c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_void_p]),
     "hsf_last_error": (ctypes.c_char_p, []),
     "hsf_version": (ctypes.c_char_p, []),
 }

@@ -307,6 +307,8 @@ hsf_status hsf_amplitudes_bitstrings(hsf_plan_t plan, const void* psiA, int64_t 
     if (!plan || (n_x > 0 && (!x || !out)) || (n_x > 0 && n_paths > 0 && (!psiA || !psiB)))
         return fail(HSF_E_ARG, "null argument");
     const Plan* p = P_(plan);
+    if (!p->side[1].post.empty())
+        return fail(HSF_E_UNSUPPORTED, "the plan defers side b's suffix to output rows (hsf_apply_b_suffix)");
     if (n_paths < 0 || n_x < 0) return fail(HSF_E_ARG, "negative size");
     if (ldA < (int64_t(1) << p->na) || ldB < (int64_t(1) << p->nb)) return fail(HSF_E_ARG, "leading dimension too small");
     if (n_x == 0) return HSF_OK;
@@ -332,6 +334,8 @@ hsf_status hsf_backward(hsf_plan_t plan, const uint64_t* x, int64_t n_x, const v
     HSF_GUARD_BEGIN
     if (!plan || !grad || (n_x > 0 && !x)) return fail(HSF_E_ARG, "null argument");
     Plan* p = P_(plan);
+    if (!p->side[1].post.empty())
+        return fail(HSF_E_UNSUPPORTED, "the plan defers side b's suffix to output rows (hsf_apply_b_suffix)");
     if (n_params < p->n_params) return fail(HSF_E_ARG, "grad has fewer slots than the circuit's parameter ids");
     if (chunk <= 0) return fail(HSF_E_ARG, "chunk must be positive");
     if (n_x < 0) return fail(HSF_E_ARG, "negative bitstring count");
@@ -349,6 +353,8 @@ hsf_status hsf_loss(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* los
     HSF_GUARD_BEGIN
     if (!plan || !loss || (n_x > 0 && !x) || !ws) return fail(HSF_E_ARG, "null argument");
     Plan* p = P_(plan);
+    if (!p->side[1].post.empty())
+        return fail(HSF_E_UNSUPPORTED, "the plan defers side b's suffix to output rows (hsf_apply_b_suffix)");
     if (chunk <= 0) return fail(HSF_E_ARG, "chunk must be positive");
     if (n_x < 0) return fail(HSF_E_ARG, "negative bitstring count");
     if (ws_bytes < loss_workspace(*p, chunk, n_x)) return fail(HSF_E_ARG, "workspace too small");
@@ -356,6 +362,20 @@ hsf_status hsf_loss(hsf_plan_t plan, const uint64_t* x, int64_t n_x, double* los
     hsf_status s = ensure_device(*p, &d);
     if (s != HSF_OK) return s;
     return prob_mass(*p, *d, x, n_x, loss, amps, chunk, ws, ws_bytes, (hipStream_t)stream);
+    HSF_GUARD_END
+}
+
+hsf_status hsf_apply_b_suffix(hsf_plan_t plan, void* out, int64_t ldo, int64_t rows, hsf_stream_t stream) {
+    HSF_GUARD_BEGIN
+    if (!plan || (rows > 0 && !out)) return fail(HSF_E_ARG, "null argument");
+    Plan* p = P_(plan);
+    if (rows < 0) return fail(HSF_E_ARG, "negative row count");
+    if (ldo < (int64_t(1) << p->nb)) return fail(HSF_E_ARG, "leading dimension too small");
+    if (p->side[1].post.empty() || rows == 0) return HSF_OK;
+    DeviceCopy* d = nullptr;
+    hsf_status s = ensure_device(*p, &d);
+    if (s != HSF_OK) return s;
+    return run_segment(*p, d->post[1][0], p->side[1].post[0], out, ldo, rows, (hipStream_t)stream);
     HSF_GUARD_END
 }
 
@@ -367,6 +387,8 @@ hsf_status hsf_batch_create(const hsf_plan_t* plans, int32_t n_plans, hsf_batch_
     for (int i = 0; i < n_plans; ++i) {
         if (!plans[i]) return fail(HSF_E_ARG, "null plan in batch");
         ps[i] = P_(plans[i]);
+        if (!ps[i]->side[1].post.empty())
+            return fail(HSF_E_UNSUPPORTED, "a plan in the batch defers side b's suffix (hsf_apply_b_suffix)");
     }
     Batch* b = nullptr;
     hsf_status s = batch_create(ps.data(), n_plans, &b);

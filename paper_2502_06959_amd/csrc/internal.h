@@ -207,6 +207,11 @@ struct SideProgram {
     // angles only)
     std::vector<Schedule> seg;
     std::vector<int> seg_lo, seg_hi;
+    // side b's ops after its last factor slot when the plan defers them to
+    // the output rows (hsf_apply_b_suffix): their count before fusion and
+    // one flat schedule (empty otherwise)
+    int64_t post_ops = 0;
+    std::vector<Schedule> post;
 };
 
 // One (circuit, side) segment of a batched sweep launch (device table).
@@ -260,6 +265,7 @@ struct DeviceCopy {
     std::vector<DeviceSchedule> side[2];
     std::vector<DeviceSchedule> tree[2];   // the sides' path-tree schedules
     std::vector<DeviceSchedule> seg[2];    // the gradient's replay segments
+    std::vector<DeviceSchedule> post[2];   // a deferred side-b suffix
 };
 
 struct Plan {
@@ -270,6 +276,7 @@ struct Plan {
     int fuse = 1;
     int tile_req = 0;
     int tree_mode = 0;                // path-tree sweeps: 0 = by cost estimate, 1 = never, 2 = always
+    int defer_b = 0;                  // side b's suffix deferred to the output rows (hsf_apply_b_suffix)
     std::vector<Gate> gates;
     std::vector<Block> blocks;
     int64_t P = 1;
@@ -321,6 +328,8 @@ bool gate_generator(int kind, int nq, std::vector<cd>& d);
 
 // Side-program fusion and pass scheduling (plan.cpp).
 void fuse_side(Plan& p, int side);
+// The same fusion on an op list of an nq-qubit side (the deferred suffix).
+void fuse_list(const Plan& p, std::vector<SideOp>& ops, int nq);
 // Commutes diagonal gates ahead of diagonal factor pieces and sets n_prefix.
 void order_prefix(SideProgram& sp);
 // Fused ops of a side in path-tree order (stable by level) and the bounds

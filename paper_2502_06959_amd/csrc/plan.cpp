@@ -425,6 +425,8 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
         p->fuse = opts->fuse;
         if (opts->tree < 0 || opts->tree > 2) return fail(HSF_E_ARG, "tree must be 0, 1 or 2");
         p->tree_mode = opts->tree;
+            if (opts->defer_b_suffix != 0 && opts->defer_b_suffix != 1) return fail(HSF_E_ARG, "defer_b_suffix must be 0 or 1");
+        p->defer_b = opts->defer_b_suffix;
     }
     if (p->tile_req < 0 || p->tile_req > max_tile_bits(p->dtype))
         return fail(HSF_E_ARG, "tile_qubits out of range");
@@ -600,6 +602,20 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
             }
         }
     }
+    // side b's ops after its last factor slot, deferred to the output rows:
+    // the same gates act on every path's side-b state, and the path sum is
+    // linear in that state
+    std::vector<SideOp> b_post;
+    if (p->defer_b) {
+        std::vector<SideOp>& v = p->side[1].ops;
+        int last = -1;
+        for (int i = 0; i < (int)v.size(); ++i)
+            if (v[i].kind == SideOp::SLOT) last = i;
+        if (last >= 0 && last + 1 < (int)v.size()) {
+            b_post.assign(v.begin() + last + 1, v.end());
+            v.resize((size_t)last + 1);
+        }
+    }
     for (int s = 0; s < 2; ++s) {
         p->side[s].ops_logical = (int64_t)p->side[s].ops.size();
         p->side[s].raw = p->side[s].ops;
@@ -630,6 +646,15 @@ hsf_status build_plan(const hsf_circuit* c, int32_t cut, const int64_t* ids, con
                 p->side[s].seg_hi.push_back(hi);
                 lo = hi;
             }
+        }
+        if (s == 1 && !b_post.empty()) {
+            p->side[1].post_ops = (int64_t)b_post.size();
+            fuse_list(*p, b_post, nq);
+            const int n_post = (int)b_post.size();
+            Schedule sc = schedule_side(*p, 1, std::min(std::min(12, tmax), nq), b_post, {0, 0, n_post}, {}, false);
+            // the rows hold the summed state: no pass starts from |0...0>
+            for (Pass& q : sc.passes) q.init_zero = 0;
+            p->side[1].post.push_back(std::move(sc));
         }
         if (!p->blocks.empty()) {
             std::vector<int> cuts, levels;
@@ -761,6 +786,10 @@ void fuse_ops(std::vector<SideOp>& ops, int nq) {
 }  // namespace
 
 // ------------------------------------------------------- pass scheduling --
+
+void fuse_list(const Plan& p, std::vector<SideOp>& ops, int nq) {
+    if (p.fuse) fuse_ops(ops, std::max(nq, 1));
+}
 
 void fuse_side(Plan& p, int s) {
     if (p.fuse) fuse_ops(p.side[s].ops, std::max(p.side[s].nq, 1));
@@ -958,6 +987,10 @@ void emit_pass(const std::vector<SideOp>& sops, Schedule& sc, const Pass& ps, co
                 so.type = SUB_SLOT1;
                 so.g = pos_in(bits, tbit(o.q[0]));
                 so.qb[0] = op_is_diagonal(o) ? 1 : 0;   // bit 0: diagonal; bits 1, 2: chains (below)
+                // a diagonal piece off the register bits (g < 0) scales every
+                // amplitude by the entry its qubit's bit selects (tile bit
+                // qb[1] >= 0, or non-local qubit -1 - qb[1])
+                so.qb[1] = tbit(o.q[0]);
                 so.mat = (int32_t)sc.pool.size();
                 for (int r = 0; r < o.rank; ++r) {
                     const std::vector<cd> f = slot_matrix(o, r);
@@ -1025,7 +1058,7 @@ void emit_pass(const std::vector<SideOp>& sops, Schedule& sc, const Pass& ps, co
             SubOp& x = sc.subs[j];
             const SubOp& y = sc.subs[j + 1];
             SubOp& y2 = sc.subs[j + 1];
-            if (x.type == SUB_SLOT1 && y.type == SUB_SLOT1 && (x.qb[0] & 1) && x.g == y.g) {
+            if (x.type == SUB_SLOT1 && y.type == SUB_SLOT1 && (x.qb[0] & 1) && x.g >= 0 && x.g == y.g) {
                 x.qb[0] |= 2;    // bit 1: chained into the next
                 y2.qb[0] |= 4;   // bit 2: ends (or continues) a chain
             }
@@ -1036,8 +1069,14 @@ void emit_pass(const std::vector<SideOp>& sops, Schedule& sc, const Pass& ps, co
     };
     for (int id : ids) {
         const SideOp& o = sops[id];
-        // one-qubit gates and one-qubit factor pieces join register groups
-        if ((o.kind == SideOp::DENSE || (o.kind == SideOp::SLOT && group_slots)) && o.k == 1) {
+        // one-qubit gates and one-qubit factor pieces join register groups;
+        // a diagonal piece on a bit the group does not hold joins as is
+        // (like a diagonal gate, it needs no register bit)
+        if (o.kind == SideOp::SLOT && group_slots && o.k == 1 && op_is_diagonal(o) &&
+            pos_in(gbits, tbit(o.q[0])) < 0 && (int)gbits.size() >= KG) {
+            grp.push_back(id);
+            if (grp.size() >= 24) close();
+        } else if ((o.kind == SideOp::DENSE || (o.kind == SideOp::SLOT && group_slots)) && o.k == 1) {
             const int b = tbit(o.q[0]);
             if (pos_in(gbits, b) < 0 && (int)gbits.size() >= KG) close();
             if (pos_in(gbits, b) < 0) gbits.push_back(b);
@@ -1165,7 +1204,11 @@ Schedule schedule_side(const Plan& p, int s, int L, const std::vector<SideOp>& o
                 std::vector<char> used_pos((size_t)d.k, 0), taken((size_t)ps.n_local, 0);
                 for (int j = d.mat; j < d.mat + d.rank; ++j) {
                     const SubOp& so = sc.subs[(size_t)j];
-                    if (so.type == SUB_D1 || so.type == SUB_SLOT1) {
+                    if (so.type == SUB_SLOT1 && so.g < 0) {
+                        // a diagonal piece off the register bits: its tile bit
+                        // must stay outside the group
+                        if (so.qb[1] >= 0) taken[(size_t)so.qb[1]] = 1;
+                    } else if (so.type == SUB_D1 || so.type == SUB_SLOT1) {
                         used_pos[(size_t)so.g] = 1;
                     } else {
                         // a diagonal op's table depends on every register position; its

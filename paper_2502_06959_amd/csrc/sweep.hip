@@ -294,11 +294,19 @@ __device__ __forceinline__ void apply_group(typename Cx<T>::v* tile, uint32_t E,
                 f00 = cmul(f00, ch0);                                                                    \
                 f11 = cmul(f11, ch1);                                                                    \
                 ch0.x = T(1); ch0.y = T(0); ch1 = ch0;                                                   \
-                switch ((so).g) {                                                                        \
-                    case 0: d1diag<K, 0>(v, f00, f11); break;                                            \
-                    case 1: d1diag<K, 1>(v, f00, f11); break;                                            \
-                    case 2: d1diag<K, 2>(v, f00, f11); break;                                            \
-                    default: d1diag<K, 3>(v, f00, f11); break;                                           \
+                if ((so).g < 0) {                                                                        \
+                    /* a piece off the register bits: its qubit's bit is the group's own */             \
+                    const int b = (so).qb[1];                                                            \
+                    const uint32_t bit = b >= 0 ? (base >> b) & 1u : (uint32_t)((gbase >> (-1 - b)) & 1u); \
+                    const V f = bit ? f11 : f00;                                                         \
+                    _Pragma("unroll") for (int j = 0; j < D; ++j) v[j] = cmul(f, v[j]);                  \
+                } else {                                                                                 \
+                    switch ((so).g) {                                                                    \
+                        case 0: d1diag<K, 0>(v, f00, f11); break;                                        \
+                        case 1: d1diag<K, 1>(v, f00, f11); break;                                        \
+                        case 2: d1diag<K, 2>(v, f00, f11); break;                                        \
+                        default: d1diag<K, 3>(v, f00, f11); break;                                       \
+                    }                                                                                    \
                 }                                                                                        \
             } else {                                                                                     \
                 if (fl & 4) {                                                                            \
@@ -617,9 +625,12 @@ hsf_status ensure_device(Plan& p, DeviceCopy** out) {
     DeviceCopy& d = p.dev.back();
     d.device = dev;
     for (int side = 0; side < 2; ++side)
-        for (int tr = 0; tr < 3; ++tr)
-            for (const Schedule& sc : tr == 2 ? p.side[side].seg : tr ? p.side[side].tree : p.side[side].sched) {
-                std::vector<DeviceSchedule>& v = tr == 2 ? d.seg[side] : tr ? d.tree[side] : d.side[side];
+        for (int tr = 0; tr < 4; ++tr)
+            for (const Schedule& sc : tr == 3   ? p.side[side].post
+                                      : tr == 2 ? p.side[side].seg
+                                      : tr      ? p.side[side].tree
+                                                : p.side[side].sched) {
+                std::vector<DeviceSchedule>& v = tr == 3 ? d.post[side] : tr == 2 ? d.seg[side] : tr ? d.tree[side] : d.side[side];
                 v.emplace_back();
                 s = p.dtype == HSF_C128 ? upload_schedule<double>(sc, v.back()) : upload_schedule<float>(sc, v.back());
                 if (s != HSF_OK) {
@@ -670,8 +681,8 @@ void release_device(Plan& p) {
     for (DeviceCopy& d : p.dev) {
         (void)hipSetDevice(d.device);
         for (int side = 0; side < 2; ++side)
-            for (int tr = 0; tr < 3; ++tr)
-                for (DeviceSchedule& ds : tr == 2 ? d.seg[side] : tr ? d.tree[side] : d.side[side])
+            for (int tr = 0; tr < 4; ++tr)
+                for (DeviceSchedule& ds : tr == 3 ? d.post[side] : tr == 2 ? d.seg[side] : tr ? d.tree[side] : d.side[side])
                     for (void* q : {ds.passes, ds.ops, ds.subs, ds.pool, ds.prefix})
                         if (q) (void)hipFree(q);
     }

@@ -82,11 +82,12 @@ _TREE = {"auto": 0, "off": 1, "on": 2}
 
 
 def hsf_plan(circuit, cut=None, blocks=None, dtype="c64", rank_tol=1e-10, max_side_qubits=4, tile_qubits=0,
-             fuse=True, tree="auto"):
+             fuse=True, tree="auto", defer_b_suffix=False):
     """Plan for `circuit` (a dict with n, gates[, cut, blocks]); returns the
     opaque handle (int).  tree: path-tree sweeps "auto" (by the planner's
-    cost estimate), "off" or "on".  Raises HsfError with the library's
-    status."""
+    cost estimate), "off" or "on".  defer_b_suffix: side b's gates after its
+    last factor slot are applied to output rows by Plan.apply_b_suffix
+    instead of to every path.  Raises HsfError with the library's status."""
     lib = L.lib()
     cut = circuit["cut"] if cut is None else cut
     blocks = circuit.get("blocks", []) if blocks is None else blocks
@@ -95,7 +96,8 @@ def hsf_plan(circuit, cut=None, blocks=None, dtype="c64", rank_tol=1e-10, max_si
     offs = np.zeros(len(blocks) + 1, dtype=np.int64)
     offs[1:] = np.cumsum([len(b) for b in blocks]) if blocks else []
     opts = L.HsfPlanOptions(rank_tol=rank_tol, max_side_qubits=max_side_qubits, dtype=_DT[dtype],
-                            tile_qubits=tile_qubits, fuse=1 if fuse else 0, tree=_TREE[tree])
+                            tile_qubits=tile_qubits, fuse=1 if fuse else 0, tree=_TREE[tree],
+                            defer_b_suffix=1 if defer_b_suffix else 0)
     h = ctypes.c_void_p()
     L.check(lib.hsf_plan(ctypes.byref(c), int(cut), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                          offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(blocks), ctypes.byref(opts),
@@ -223,6 +225,17 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def apply_b_suffix(self, out, rows=None):
+        """Side b's deferred gates on the first `rows` rows of `out` (rows x
+        2^n_b, the plan's dtype, on the device), in place
+        (hsf_apply_b_suffix); a no-op for a plan without a deferred suffix."""
+        rows = out.shape[0] if rows is None else rows
+        if out.dtype != self.torch_dtype:
+            raise ValueError(f"rows must be {self.torch_dtype} like the plan's half-states")
+        L.check(L.lib().hsf_apply_b_suffix(ctypes.c_void_p(self.handle), _ptr(out), out.stride(0), rows,
+                                           _stream(out)))
+        return out
 
     # ---------------------------------------------------------- tables ----
     def block_info(self, k):

@@ -296,3 +296,36 @@ def test_batch_tune_cache_lookup_on_the_host():
         assert pol.value == 7
     finally:
         b.close()
+
+
+def test_deferred_b_suffix_planning_and_argument_checks():
+    """defer_b_suffix: side b's gates after its last factor slot leave its
+    program (QAOA: the mixer's RX on every side-b qubit); option and
+    hsf_apply_b_suffix argument checks on the host."""
+    from paper_2502_06959_amd import joint_blocked
+    c = joint_blocked(cg.qaoa_sbm(3, sizes=(6, 7), p_intra=0.5, p_inter=0.3))
+    base, plan = Plan(c), Plan(c, defer_b_suffix=True)
+    nb = plan.nb
+    assert base.side_stats(1)["ops_logical"] - plan.side_stats(1)["ops_logical"] == nb
+    assert base.side_stats(0) == plan.side_stats(0) and base.P == plan.P
+    from paper_2502_06959_amd.hsf import _circuit_struct
+    lib = L.lib()
+    cs, keep = _circuit_struct(c)
+    ids = np.array([int(i) for b in c["blocks"] for i in b], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum([len(b) for b in c["blocks"]])]).astype(np.int64)
+    opts = L.HsfPlanOptions(rank_tol=1e-10, max_side_qubits=4, dtype=0, tile_qubits=0, fuse=1, tree=0,
+                            defer_b_suffix=2)
+    h = ctypes.c_void_p()
+    st = lib.hsf_plan(ctypes.byref(cs), int(c["cut"]), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                      offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(c["blocks"]), ctypes.byref(opts),
+                      ctypes.byref(h))
+    assert st != 0 and not h.value
+    del keep
+    dummy = ctypes.c_void_p(16)
+    assert lib.hsf_apply_b_suffix(None, dummy, 1 << nb, 1, None) != 0
+    assert lib.hsf_apply_b_suffix(ctypes.c_void_p(plan.handle), None, 1 << nb, 1, None) != 0
+    assert lib.hsf_apply_b_suffix(ctypes.c_void_p(plan.handle), dummy, 1 << nb, -1, None) != 0
+    assert lib.hsf_apply_b_suffix(ctypes.c_void_p(plan.handle), dummy, (1 << nb) - 1, 1, None) != 0
+    # no rows, or no deferred gates: nothing to do, no device call
+    assert lib.hsf_apply_b_suffix(ctypes.c_void_p(plan.handle), dummy, 1 << nb, 0, None) == 0
+    assert lib.hsf_apply_b_suffix(ctypes.c_void_p(base.handle), dummy, 1 << nb, 4, None) == 0
