@@ -279,9 +279,12 @@ hsf_status hsf_run_paths(hsf_plan_t plan, int64_t p_begin, int64_t p_end, void* 
 
 /* hsf_run_paths for callers that need only the amplitudes [row_begin,
  * row_end) of side a (at most 2^20), such as the first amplitudes of the
- * state (Sec. V computes the first 10^6): the last LDS pass of side a runs
- * only the tiles that hold those rows, so the rest of each psiA row is left
- * unspecified (psiA is required and keeps its full layout, ldA >= 2^n_a).
+ * state (Sec. V computes the first 10^6): side a's passes, from its last
+ * back, run only the tiles those rows depend on (a pass's tile reads the
+ * same tile of its input, so the needed amplitudes widen by each pass's tile
+ * qubits; the walk stops at the first pass that needs every tile), so the
+ * rest of each psiA row is left unspecified (psiA is required and keeps its
+ * full layout, ldA >= 2^n_a).
  * Side b (psiB, may be NULL) is computed in full.  The wanted rows equal
  * hsf_run_paths' bit for bit.  Other arguments, errors and ownership as in
  * hsf_run_paths.                                                            */

@@ -42,9 +42,9 @@ struct SweepReplicas {
 // may be null).  ws: tree_workspace(p, n_paths) bytes for the path-tree
 // levels; with less (or null) every path runs every per-path op.  reps: the
 // run's copies (null: one).  a_row_end >= 0: only side a's amplitudes
-// [a_row_begin, a_row_end) are wanted (at most 2^20 of them): its last pass
-// runs only the tiles that hold them, so the rest of each side-a row is left
-// unspecified.
+// [a_row_begin, a_row_end) are wanted (at most 2^20 of them): side a's
+// passes, from its last back, run only the tiles they depend on, so the rest
+// of each side-a row (and of its tree levels) is left unspecified.
 hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, void* psiA, int64_t ldA,
                      void* psiB, int64_t ldB, void* ws, size_t ws_bytes, hipStream_t stream,
                      const SweepReplicas* reps = nullptr, int64_t a_row_begin = 0, int64_t a_row_end = -1,

@@ -102,8 +102,11 @@ struct SideArgs {
     // reads src + r src_rs (strides in complex elements).
     uint32_t rep_blocks;
     int64_t pool_rs, dst_rs, src_rs;
-    // the launch covers tiles [tile0, tile0 + n_tiles) of each row
+    // the launch covers tiles [tile0, tile0 + n_tiles) of each row, or with
+    // tile_free != 0 the n_tiles = 2^popcount(tile_free) tiles tile0 | s, s
+    // a subset of tile_free's bits
     uint32_t tile0;
+    uint32_t tile_free;
 };
 
 // LDS position of tile element e: the low four index bits are XORed with the
@@ -462,7 +465,17 @@ __global__ __launch_bounds__(Threads<T>::max) void sweep_pass(SideArgs s0, SideA
     const uint32_t r = rb ? blk / rb : 0u;
     blk -= r * rb;
     const uint32_t pl = blk / n_tiles;
-    const uint32_t t = HSF_SEL(tile0) + (blk - pl * n_tiles);
+    const uint32_t ti = blk - pl * n_tiles;
+    uint32_t t = HSF_SEL(tile0);
+    const uint32_t tfree = HSF_SEL(tile_free);
+    if (tfree) {
+        // the ti-th subset of tile_free's bits, in order
+        uint32_t i = ti;
+        for (uint32_t m = tfree; m; m &= m - 1, i >>= 1)
+            if (i & 1u) t |= m & (~m + 1u);
+    } else {
+        t += ti;
+    }
     const int64_t i = HSF_SEL(i_lo) + (int64_t)pl;
     const int64_t S = HSF_SEL(S);
     const int64_t path = max(i * S, HSF_SEL(p0));
@@ -912,6 +925,35 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
                               tree && levels ? levels->start[s] : 0, tree && levels ? levels->parent[s] : nullptr);
         rounds = std::max(rounds, items[s].size());
     }
+    // Rows [a_row_begin, a_row_end) of side a only: walking side a's passes
+    // from the last, the side-a indices still needed form a cube (free bits
+    // F, the others fixed to V; first the rows, then widened by each pass's
+    // tile bits, since a tile's outputs read its whole input tile).  A pass
+    // need only run the tiles whose non-local bits agree with the cube (the
+    // fixed ones from V, the free ones in every combination); the walk stops
+    // at the first pass that needs all of its tiles.
+    std::vector<uint32_t> a_tile0(items[0].size(), 0), a_ntiles(items[0].size(), 0), a_free(items[0].size(), 0);
+    if (a_row_end > a_row_begin && a_row_begin >= 0 && !items[0].empty()) {
+        const uint64_t diff = (uint64_t)a_row_begin ^ (uint64_t)(a_row_end - 1);
+        uint64_t F = 0;
+        while ((F & diff) != diff) F = (F << 1) | 1u;
+        const uint64_t V = (uint64_t)a_row_begin & ~F;
+        for (size_t j = items[0].size(); j-- > 0;) {
+            const Pass& ps = sc[0]->passes[items[0][j].k];
+            const uint64_t fixed = V & ~F;    // bits freed by later passes are no longer fixed
+            uint32_t t0 = 0, tf = 0;
+            for (int b = 0; b < ps.n_nonlocal; ++b) {
+                t0 |= (uint32_t)((fixed >> ps.nonlocal_q[b]) & 1u) << b;
+                tf |= (uint32_t)((F >> ps.nonlocal_q[b]) & 1u) << b;
+            }
+            const int nf = __builtin_popcount(tf);
+            if (nf >= ps.n_nonlocal) break;
+            a_tile0[j] = t0;
+            a_ntiles[j] = 1u << nf;
+            a_free[j] = tf;
+            for (int i = 0; i < ps.n_local; ++i) F |= uint64_t(1) << ps.local_q[i];
+        }
+    }
     // rows per launch bounded so the grid stays below 2^31 workgroups
     int64_t tiles_max = 1;
     for (int s = 0; s < 2; ++s)
@@ -944,19 +986,11 @@ hsf_status run_sides(Plan& p, DeviceCopy& d, int64_t p_begin, int64_t n_paths, v
             a[s].src_lo = m.src_lo;
             a[s].S_par = m.S_par;
             a[s].mode = m.mode;
-            if (s == 0 && j + 1 == items[0].size() && a_row_end >= 0) {
-                // side a's last pass: only the tiles that hold rows [a_row_begin, a_row_end)
-                uint32_t lo = a[s].n_tiles - 1, hi = 0;
-                for (int64_t x = a_row_begin; x < a_row_end; ++x) {
-                    uint32_t t = 0;
-                    for (int b = 0; b < ps.n_nonlocal; ++b) t |= (uint32_t)((x >> ps.nonlocal_q[b]) & 1) << b;
-                    lo = std::min(lo, t);
-                    hi = std::max(hi, t);
-                }
-                if (a_row_end > a_row_begin) {
-                    a[s].tile0 = lo;
-                    a[s].n_tiles = hi - lo + 1;
-                }
+            if (s == 0 && a_ntiles[j] > 0) {
+                // only the tiles the wanted rows depend on (the cube above)
+                a[s].tile0 = a_tile0[j];
+                a[s].n_tiles = a_ntiles[j];
+                a[s].tile_free = a_free[j];
             }
             if (R > 1) {
                 // the last level writes the caller's rows, the others a copy's tree levels
