@@ -111,8 +111,9 @@ def test_q30_first_million_amplitudes_and_norm():
 @pytest.mark.parametrize("tree", ["on", "off"])
 @pytest.mark.parametrize("kind", ["qaoa", "brick"])
 def test_run_paths_rows_equals_full_rows(tree, kind):
-    """hsf_run_paths_rows (side a's last pass only on the tiles that hold the
-    wanted rows): those rows bit for bit hsf_run_paths', side b in full, on
+    """hsf_run_paths_rows (side a's passes, from the last back, only on the
+    tiles the wanted rows depend on): those rows bit for bit hsf_run_paths',
+    side b in full, on
     product-form QAOA blocks and dense brickwork blocks, path tree and flat,
     with two path chunks; row ranges inside one tile, across tiles, at the
     end and the whole side."""
@@ -124,7 +125,7 @@ def test_run_paths_rows_equals_full_rows(tree, kind):
     assert plan.side_stats(0)["tile_qubits"] == 8 and plan.na >= 12
     ref_A, ref_B = plan.run_paths()
     M = 1 << plan.na
-    for r0, r1 in ((0, 16), (0, 1), (37, 60), (M - 40, M - 8), (0, M)):
+    for r0, r1 in ((0, 16), (0, 1), (37, 60), (M - 40, M - 8), (M // 2 - 5, M // 2 + 7), (1, 3), (0, M)):
         A, B = plan.alloc_halves(plan.P)
         A.fill_(float("nan"))
         h = plan.P // 2
