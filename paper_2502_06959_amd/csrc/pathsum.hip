@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void pathsum_f32_batch(const GemmDesc* __restr
 // owns the panel x 32 columns as one 32x32x2 block per product (rows past M
 // read as zero), its operands prefetched R_DEPTH path pairs ahead.
 constexpr int R_COLS = 128;   // columns per workgroup (4 waves)
-constexpr int R_DEPTH = 8;
+constexpr int R_DEPTH = 16;
 
 __global__ __launch_bounds__(256) void pathsum_f32_rows(const float2* __restrict__ A, int64_t ldA,
                                                         const float2* __restrict__ B, int64_t ldB, int64_t K,
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void pathsum_f32_rows(const float2* __restrict
 // wave owns 32 columns as two blocks, path quads prefetched R16_DEPTH ahead.
 // Lane l supplies A row l%16 and B column l%16 of path l/16; accumulator r
 // of a block sits at row 4 (l/16) + r, column l%16.
-constexpr int R16_DEPTH = 8;
+constexpr int R16_DEPTH = 16;
 using f32x4 = float __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void pathsum_f32_rows16(const float2* __restrict__ A, int64_t ldA,
