@@ -227,6 +227,8 @@ def main():
                          "instead of applying them once to the output rows")
     ap.add_argument("--no-standard", action="store_true",
                     help="--workload qaoa: skip the standard-cutting comparison runs")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="--workload qaoa: keep the planner's sweep tile choice (no timing of 9/10/11-qubit tiles)")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="c2p / c2: also time the whole step replayed from a HIP graph")
@@ -732,6 +734,21 @@ def bench_qaoa(args):
         rows = (10 ** 6 + (1 << pj.nb) - 1) >> pj.nb
         out = torch.empty((rows, 1 << pj.nb), dtype=torch.complex64, device="cuda")
         chunk = min(pj.P, 1 << 14)
+        tile_choice, tune_ms = 0, 0.0
+        if not args.no_tune:
+            # tuner: the planner's own sweep tile choice (0) against tiles
+            # forced to 9, 10 and 11 qubits, one warm and one timed run each,
+            # outside the measured runs below
+            t0 = time.perf_counter()
+            best = None
+            for tq in (0, 9, 10, 11):
+                cand = pj if tq == 0 else Plan(r, tree=args.tree, defer_b_suffix=not args.no_defer, tile_qubits=tq)
+                _first_amplitudes(cand, chunk, rows, mode, out)
+                t_c = _first_amplitudes(cand, chunk, rows, mode, out)
+                if best is None or t_c < best[0]:
+                    best = (t_c, tq, cand)
+            pj, tile_choice = best[2], best[1]
+            tune_ms = (time.perf_counter() - t0) * 1e3
         _first_amplitudes(pj, chunk, rows, mode, out)            # warm-up
         j_ms = min(_first_amplitudes(pj, chunk, rows, mode, out) for _ in range(max(1, args.steps // 5)))
         total_j += j_ms
@@ -755,6 +772,7 @@ def bench_qaoa(args):
                          "log2_paths_joint": int(pj.P).bit_length() - 1,
                          "log2_paths_standard": int(ps.P).bit_length() - 1,
                          "joint_ms": j_ms, "joint_host_plan_ms": host_ms,
+                         "sweep_tile_qubits": tile_choice or "planner", "tune_ms": tune_ms,
                          "standard_ms": None if args.no_standard else t_ms, "standard_timing": t_kind,
                          "standard_over_joint": None if args.no_standard else t_ms / j_ms,
                          "paper_joint_cpu_s": paper_j, "paper_log2_paths_joint": paper_log2p})
@@ -766,7 +784,10 @@ def bench_qaoa(args):
            "dtype": f"c64 (f32 sweeps, {mode} path sum)", "data": "synthetic",
            "config": {"workload": "qaoa: single-layer QAOA MaxCut on seeded SBM graphs, Table II sizes, "
                                   "p_intra 0.8, first 10^6 amplitudes",
-                      "defer_b_suffix": not args.no_defer},
+                      "defer_b_suffix": not args.no_defer,
+                      "sweep_tiles": "untuned (planner's estimate)" if args.no_tune else
+                                     "tuned per instance: planner's estimate or 9/10/11-qubit tiles, "
+                                     "timed before the measured runs; standard cutting untuned"},
            "instances": rows_out,
            "geomean_standard_over_joint": (float(np.exp(np.mean([np.log(x["standard_over_joint"]) for x in rows_out])))
                                            if not args.no_standard else None)}
